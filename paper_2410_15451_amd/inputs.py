@@ -1,0 +1,205 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle checks.
+
+This module builds graphs and edge-update batches only.  It contains none of the
+community-detection method: no modularity, no local moving, no refinement, no
+aggregation.  Both the HIP path and the CPU oracle receive exactly the arrays made
+here, so the two sides never disagree about their inputs.
+
+Graph format (host, numpy):
+  ``Csr(n, offs, cols, w)`` - an undirected graph stored with both directions of
+  every edge (the paper's convention of adding reverse edges, Section 4.1.4),
+  ``offs`` int64[n+1], ``cols`` uint32[nnz] sorted inside each row, ``w`` uint32[nnz]
+  with w > 0, no duplicate entries.
+
+Batch format: deletions ``uint32[nd, 2]`` (each undirected pair once) and insertions
+``uint32[ni, 3]`` as (u, v, w) (each undirected pair once, w > 0), following the
+batch update definition of Section 2.4 (deletions are existing edges, insertions
+are absent pairs, no vertex is added or removed).
+
+Workload recipes (the paper's SuiteSparse and SNAP graphs are not available; these
+stand in for them):
+  * planted partition: n vertices in equal blocks, each pair is an edge with
+    probability p_in (same block) or p_out (different blocks), unit weights;
+  * R-MAT: 2^scale vertices, edge_factor * 2^scale samples with quadrant
+    probabilities (a, b, c, d), self-loops and duplicates dropped, a seeded vertex
+    permutation, unit weights;
+  * random batch (Section 4.1.3): a fraction of |E| undirected updates, 80%
+    insertions of uniform absent pairs and 20% deletions of uniform existing edges.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+BASE_SEED = 2410154510
+
+
+@dataclass
+class Csr:
+    n: int
+    offs: np.ndarray  # int64[n+1]
+    cols: np.ndarray  # uint32[nnz]
+    w: np.ndarray  # uint32[nnz]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.cols.shape[0])
+
+    def degrees(self) -> np.ndarray:
+        return np.diff(self.offs)
+
+    def undirected_keys(self) -> np.ndarray:
+        """Sorted uint64 keys u*2^32+v of the undirected edges with u < v."""
+        src = np.repeat(np.arange(self.n, dtype=np.uint64), np.diff(self.offs))
+        dst = self.cols.astype(np.uint64)
+        m = src < dst
+        return np.sort((src[m] << np.uint64(32)) | dst[m])
+
+
+def rng_for(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def csr_from_undirected(n: int, u, v, w=None) -> Csr:
+    """Build the symmetric CSR of an undirected edge list (each pair given once).
+
+    Pairs must be distinct and free of self-loops; rows come out sorted.
+    """
+    u = np.asarray(u, dtype=np.uint64)
+    v = np.asarray(v, dtype=np.uint64)
+    if w is None:
+        w = np.ones(u.shape[0], dtype=np.uint32)
+    w = np.asarray(w, dtype=np.uint32)
+    src = np.concatenate([u, v])
+    dst = np.concatenate([v, u])
+    ww = np.concatenate([w, w])
+    key = (src << np.uint64(32)) | dst
+    order = np.argsort(key, kind="stable")
+    src = src[order]
+    dst = dst[order].astype(np.uint32)
+    ww = ww[order]
+    counts = np.bincount(src.astype(np.int64), minlength=n) if n > 0 else np.zeros(0, np.int64)
+    offs = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=offs[1:])
+    return Csr(n, offs, dst, ww)
+
+
+def csr_from_edges(n: int, edges) -> Csr:
+    """Small helper for hand-written test graphs: ``edges`` is [(u, v)] or [(u, v, w)]."""
+    if len(edges) == 0:
+        return Csr(n, np.zeros(n + 1, np.int64), np.zeros(0, np.uint32), np.zeros(0, np.uint32))
+    arr = np.asarray(edges, dtype=np.int64)
+    u, v = arr[:, 0], arr[:, 1]
+    w = arr[:, 2] if arr.shape[1] > 2 else np.ones(len(arr), np.int64)
+    return csr_from_undirected(n, u, v, w)
+
+
+def planted_partition(n: int = 1000, blocks: int = 10, p_in: float = 0.1, p_out: float = 0.005,
+                      seed: int = BASE_SEED + 1) -> Csr:
+    """Planted-partition graph: block(v) = floor(v / (n / blocks))."""
+    rng = rng_for(seed)
+    iu, ju = np.triu_indices(n, k=1)
+    bs = n // blocks
+    same = (iu // bs) == (ju // bs)
+    p = np.where(same, p_in, p_out)
+    keep = rng.random(iu.shape[0]) < p
+    return csr_from_undirected(n, iu[keep], ju[keep])
+
+
+def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c: float = 0.19,
+         seed: int = BASE_SEED + 2, permute: bool = True) -> Csr:
+    """R-MAT graph with 2^scale vertices and edge_factor * 2^scale samples.
+
+    Each sample picks one quadrant per level with probabilities (a, b, c, 1-a-b-c);
+    self-loops and duplicate pairs are dropped, the result is symmetrised and the
+    vertex IDs are shuffled by a seeded permutation; unit weights.
+    """
+    rng = rng_for(seed)
+    n = 1 << scale
+    m = edge_factor * n
+    src = np.zeros(m, dtype=np.uint32)
+    dst = np.zeros(m, dtype=np.uint32)
+    ab, abc = a + b, a + b + c
+    for lvl in range(scale):
+        r = rng.random(m, dtype=np.float32)
+        bit = np.uint32(1 << (scale - 1 - lvl))
+        sb = r >= ab
+        db = ((r >= a) & (r < ab)) | (r >= abc)
+        src |= sb.astype(np.uint32) * bit
+        dst |= db.astype(np.uint32) * bit
+        del r, sb, db
+    keep = src != dst
+    src, dst = src[keep], dst[keep]
+    lo = np.minimum(src, dst).astype(np.uint64)
+    hi = np.maximum(src, dst).astype(np.uint64)
+    del src, dst, keep
+    key = np.unique((lo << np.uint64(32)) | hi)
+    del lo, hi
+    u = (key >> np.uint64(32)).astype(np.uint32)
+    v = (key & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    del key
+    if permute:
+        perm = rng.permutation(n).astype(np.uint32)
+        u, v = perm[u], perm[v]
+    return csr_from_undirected(n, u, v)
+
+
+def random_batch(n: int, existing_keys: np.ndarray, n_updates: int, seed: int,
+                 ins_frac: float = 0.8, w_range=(1, 1)):
+    """Random batch update of ``n_updates`` undirected updates (Section 4.1.3).
+
+    ``existing_keys`` are the sorted u*2^32+v keys (u < v) of the current graph.
+    Returns (deletions uint32[nd,2], insertions uint32[ni,3]); deletions are distinct
+    existing edges, insertions are distinct absent pairs without self-loops.
+    """
+    rng = rng_for(seed)
+    n_ins = int(round(n_updates * ins_frac))
+    n_del = int(n_updates) - n_ins
+    n_del = min(n_del, existing_keys.shape[0])
+    if n_del > 0:
+        pick = rng.choice(existing_keys.shape[0], size=n_del, replace=False)
+        dk = existing_keys[np.sort(pick)]
+    else:
+        dk = np.zeros(0, np.uint64)
+    dels = np.stack([(dk >> np.uint64(32)).astype(np.uint32),
+                     (dk & np.uint64(0xFFFFFFFF)).astype(np.uint32)], axis=1)
+    got = np.zeros(0, np.uint64)
+    max_pairs = n * (n - 1) // 2 - existing_keys.shape[0]
+    n_ins = min(n_ins, max_pairs)
+    while got.shape[0] < n_ins:
+        want = (n_ins - got.shape[0]) * 2 + 16
+        u = rng.integers(0, n, size=want, dtype=np.uint64)
+        v = rng.integers(0, n, size=want, dtype=np.uint64)
+        ok = u != v
+        u, v = u[ok], v[ok]
+        k = (np.minimum(u, v) << np.uint64(32)) | np.maximum(u, v)
+        # keep the first occurrence of each new key, in draw order
+        _, first = np.unique(k, return_index=True)
+        k = k[np.sort(first)]
+        pos = np.searchsorted(existing_keys, k)
+        pos = np.minimum(pos, max(existing_keys.shape[0] - 1, 0))
+        present = existing_keys[pos] == k if existing_keys.shape[0] else np.zeros(k.shape, bool)
+        k = k[~present]
+        k = k[~np.isin(k, got)]
+        got = np.concatenate([got, k])[:n_ins]
+    lo, hi = w_range
+    ww = rng.integers(lo, hi + 1, size=got.shape[0], dtype=np.int64).astype(np.uint32)
+    ins = np.stack([(got >> np.uint64(32)).astype(np.uint32),
+                    (got & np.uint64(0xFFFFFFFF)).astype(np.uint32), ww], axis=1)
+    return dels.astype(np.uint32).reshape(-1, 2), ins.astype(np.uint32).reshape(-1, 3)
+
+
+def keys_after_batch(existing_keys: np.ndarray, dels: np.ndarray, ins: np.ndarray) -> np.ndarray:
+    """Edge-key bookkeeping for generating a stream of batches (sorted result)."""
+    dk = (np.minimum(dels[:, 0], dels[:, 1]).astype(np.uint64) << np.uint64(32)) | \
+        np.maximum(dels[:, 0], dels[:, 1]).astype(np.uint64)
+    ik = (np.minimum(ins[:, 0], ins[:, 1]).astype(np.uint64) << np.uint64(32)) | \
+        np.maximum(ins[:, 0], ins[:, 1]).astype(np.uint64)
+    keep = ~np.isin(existing_keys, dk, assume_unique=True)
+    return np.sort(np.concatenate([existing_keys[keep], ik]))
+
+
+def batch_size_for(nnz_directed: int, frac: float) -> int:
+    """Number of undirected updates for a batch of ``frac * |E|`` (|E| counts directed entries)."""
+    return max(1, int(round(frac * nnz_directed)))

@@ -1,0 +1,643 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+Every check here is independent of the oracle's own code: hand-computed
+closed forms of Eq. 1 (tests/golden), Eq. 2 against an exact-rational
+difference of Eq. 1, brute-force optimal modularity on tiny graphs, and the
+invariants the paper states (refined and final communities are connected,
+aggregation keeps the total weight and the modularity of a partition, moves of
+the sequential local-moving phase never lower modularity, an empty batch leaves
+DF / DS memberships unchanged).
+
+The blocked synchronous (JACOBI) schedule's class and colour rules are readings
+of this project: parity unpinned against the paper, checked here only through
+invariants and closeness to the sequential schedule.
+"""
+import itertools
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2410_15451_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------
+# helpers written from the definitions (not from the oracle)
+# --------------------------------------------------------------------------
+def directed_entries(g):
+    src = np.repeat(np.arange(g.n), np.diff(g.offs))
+    return src, g.cols.astype(np.int64), g.w.astype(np.int64)
+
+
+def q_exact(g, C):
+    """Eq. 1 as an exact fraction: sum_c sigma_c/2m - (Sigma_c/2m)^2."""
+    src, dst, w = directed_entries(g)
+    M2 = int(w.sum())
+    if M2 == 0:
+        return Fraction(0)
+    sigma = {}
+    Sig = {}
+    for i, j, x in zip(src.tolist(), dst.tolist(), w.tolist()):
+        Sig[C[i]] = Sig.get(C[i], 0) + x
+        if C[i] == C[j]:
+            sigma[C[i]] = sigma.get(C[i], 0) + x
+    q = Fraction(0)
+    for c in Sig:
+        q += Fraction(sigma.get(c, 0), M2) - Fraction(Sig[c], M2) ** 2
+    return q
+
+
+def components_connected(g, C):
+    """True when every community induces a connected subgraph (BFS)."""
+    C = np.asarray(C)
+    src, dst, _ = directed_entries(g)
+    adj = [[] for _ in range(g.n)]
+    for i, j in zip(src.tolist(), dst.tolist()):
+        if C[i] == C[j] and i != j:
+            adj[i].append(j)
+    seen = np.zeros(g.n, bool)
+    comm_roots = {}
+    for s in range(g.n):
+        if seen[s]:
+            continue
+        c = int(C[s])
+        if c in comm_roots:
+            return False  # second component of the same community
+        comm_roots[c] = s
+        stack = [s]
+        seen[s] = True
+        while stack:
+            u = stack.pop()
+            for v in adj[u]:
+                if not seen[v]:
+                    seen[v] = True
+                    stack.append(v)
+    return True
+
+
+def set_partitions(n):
+    """All set partitions of range(n) as restricted growth strings."""
+    a = [0] * n
+
+    def rec(i, m):
+        if i == n:
+            yield list(a)
+            return
+        for v in range(m + 2):
+            a[i] = v
+            yield from rec(i + 1, max(m, v))
+    if n == 0:
+        yield []
+        return
+    a[0] = 0
+    yield from rec(1, 0)
+
+
+def brute_force_opt(g):
+    A = np.zeros((g.n, g.n))
+    src, dst, w = directed_entries(g)
+    np.add.at(A, (src, dst), w)
+    k = A.sum(1)
+    M2 = k.sum()
+    B = A - np.outer(k, k) / M2
+    best = -1.0
+    for p in set_partitions(g.n):
+        p = np.asarray(p)
+        q = B[p[:, None] == p[None, :]].sum() / M2
+        best = max(best, q)
+    return best
+
+
+def random_graph(n, p, seed, wmax=1):
+    rng = np.random.default_rng(seed)
+    iu, ju = np.triu_indices(n, 1)
+    keep = rng.random(iu.shape[0]) < p
+    w = rng.integers(1, wmax + 1, size=int(keep.sum()))
+    return inputs.csr_from_undirected(n, iu[keep], ju[keep], w)
+
+
+def read_golden_eq1():
+    cases = []
+    with open(os.path.join(GOLDEN, "eq1_closed_forms.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            name, n, edges, part, frac = [x.strip() for x in line.split("|")]
+            es = []
+            for tok in edges.split():
+                uv, _, ww = tok.partition(":")
+                u, v = uv.split("-")
+                es.append((int(u), int(v), int(ww) if ww else 1))
+            cases.append((name, int(n), es, [int(x) for x in part.split()], Fraction(frac)))
+    return cases
+
+
+# --------------------------------------------------------------------------
+# Eq. 1
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("case", read_golden_eq1(), ids=lambda c: c[0])
+def test_eq1_closed_forms(orc, case):
+    name, n, es, part, expect = case
+    g = inputs.csr_from_edges(n, es)
+    q = orc.modularity(g, np.asarray(part, np.uint32))
+    assert abs(q - float(expect)) <= 1e-15, (name, q, expect)
+
+
+def test_eq1_cliques_and_singletons(orc):
+    for k in (2, 3, 5, 8):
+        edges = []
+        for b in range(k):
+            base = 4 * b
+            edges += [(base + a, base + c) for a in range(4) for c in range(a + 1, 4)]
+        g = inputs.csr_from_edges(4 * k, edges)
+        part = np.repeat(np.arange(k), 4).astype(np.uint32)
+        assert abs(orc.modularity(g, part) - (1 - 1 / k)) <= 1e-15
+        assert orc.modularity(g, np.zeros(4 * k, np.uint32)) == 0.0
+    g = random_graph(12, 0.4, seed=3, wmax=5)
+    K = np.diff(g.offs) * 0
+    np.add.at(K, np.repeat(np.arange(g.n), np.diff(g.offs)), g.w.astype(np.int64))
+    expect = -float(sum(Fraction(int(x), int(K.sum())) ** 2 for x in K))
+    assert abs(orc.modularity(g, np.arange(g.n, dtype=np.uint32)) - expect) <= 1e-15
+
+
+def test_eq1_range_and_exact_rational(orc):
+    rng = np.random.default_rng(7)
+    for s in range(20):
+        g = random_graph(10, 0.35, seed=s, wmax=6)
+        if g.nnz == 0:
+            continue
+        C = rng.integers(0, 4, size=g.n).astype(np.uint32)
+        q = orc.modularity(g, C)
+        assert -0.5 <= q <= 1.0
+        assert abs(q - float(q_exact(g, C.tolist()))) <= 1e-15
+
+
+# --------------------------------------------------------------------------
+# Eq. 2: the closed form equals the exact difference of Eq. 1
+# --------------------------------------------------------------------------
+def test_eq2_equals_exact_difference(orc):
+    rng = np.random.default_rng(11)
+    checked = 0
+    for s in range(40):
+        n = 9
+        g = random_graph(n, 0.4, seed=100 + s, wmax=7)
+        if s % 3 == 0:  # add self-loops: Eq. 2 must exclude them from K_{i->c}
+            src, dst, w = directed_entries(g)
+            loops = rng.choice(n, size=2, replace=False)
+            src = np.concatenate([src, loops])
+            dst = np.concatenate([dst, loops])
+            w = np.concatenate([w, rng.integers(1, 5, size=2)])
+            order = np.lexsort((dst, src))
+            offs = np.zeros(n + 1, np.int64)
+            np.cumsum(np.bincount(src, minlength=n), out=offs[1:])
+            g = inputs.Csr(n, offs, dst[order].astype(np.uint32), w[order].astype(np.uint32))
+        src, dst, w = directed_entries(g)
+        M2 = int(w.sum())
+        if M2 == 0:
+            continue
+        C = rng.integers(0, 4, size=n).tolist()
+        K = np.zeros(n, np.int64)
+        np.add.at(K, src, w)
+        S = {}
+        for v in range(n):
+            S[C[v]] = S.get(C[v], 0) + int(K[v])
+        for _ in range(6):
+            i = int(rng.integers(0, n))
+            d = C[i]
+            c = int(rng.integers(0, 5))
+            if c == d:
+                continue
+            Kic = sum(int(x) for a, b, x in zip(src, dst, w) if a == i and b != i and C[b] == c)
+            Kid = sum(int(x) for a, b, x in zip(src, dst, w) if a == i and b != i and C[b] == d)
+            dq = orc.delta_modularity(Kic, Kid, int(K[i]), S.get(c, 0), S[d], M2)
+            C2 = list(C)
+            C2[i] = c
+            exact = q_exact(g, C2) - q_exact(g, C)
+            assert abs(dq - float(exact)) <= 1e-14, (s, i, d, c, dq, float(exact))
+            checked += 1
+    assert checked > 100
+
+
+# --------------------------------------------------------------------------
+# Whole static runs against brute force on tiny graphs
+# --------------------------------------------------------------------------
+DESIGNED = {
+    "three_triangles": (9, [(0, 1), (1, 2), (0, 2), (3, 4), (4, 5), (3, 5), (6, 7), (7, 8), (6, 8)]),
+    "barbell_k4": (8, [(a, b) for a in range(4) for b in range(a + 1, 4)] +
+                   [(a, b) for a in range(4, 8) for b in range(a + 1, 8)] + [(3, 4)]),
+    "ring_of_triangles": (9, [(0, 1), (1, 2), (0, 2), (3, 4), (4, 5), (3, 5), (6, 7), (7, 8), (6, 8),
+                              (2, 3), (5, 6), (8, 0)]),
+    "two_triangles": (6, [(0, 1), (1, 2), (0, 2), (3, 4), (4, 5), (3, 5), (2, 3)]),
+}
+
+
+@pytest.mark.parametrize("schedule", [0, 1], ids=["seq", "jacobi"])
+@pytest.mark.parametrize("name", sorted(DESIGNED))
+def test_static_reaches_optimum_on_designed_graphs(orc, name, schedule):
+    n, es = DESIGNED[name]
+    g = inputs.csr_from_edges(n, es)
+    C, q, _ = orc.static(g, schedule=schedule)
+    opt = brute_force_opt(g)
+    assert abs(q - opt) <= 1e-12, (name, q, opt)
+    assert abs(q - float(q_exact(g, C.tolist()))) <= 1e-15
+
+
+@pytest.mark.parametrize("schedule", [0, 1], ids=["seq", "jacobi"])
+def test_static_never_beats_brute_force(orc, schedule):
+    for s in range(12):
+        g = random_graph(8, 0.4, seed=300 + s, wmax=3)
+        if g.nnz == 0:
+            continue
+        C, q, _ = orc.static(g, schedule=schedule)
+        opt = brute_force_opt(g)
+        assert q <= opt + 1e-12
+        assert abs(q - float(q_exact(g, C.tolist()))) <= 1e-15
+        assert q >= opt - 0.15  # heuristic, but never far off on these graphs
+        assert components_connected(g, C)
+
+
+def test_static_labels_dense_by_min_vertex(orc):
+    g = inputs.planted_partition()
+    for schedule in (0, 1):
+        C, _, _ = orc.static(g, schedule=schedule)
+        first = {}
+        for v, c in enumerate(C.tolist()):
+            first.setdefault(c, v)
+        order = sorted(first, key=first.get)
+        assert order == list(range(len(order)))
+
+
+def test_edgeless_and_empty_graphs(orc):
+    g = inputs.csr_from_edges(5, [])
+    C, q, st = orc.static(g)
+    assert C.tolist() == [0, 1, 2, 3, 4] and q == 0.0
+    g0 = inputs.csr_from_edges(0, [])
+    C, q, _ = orc.static(g0)
+    assert C.shape == (0,) and q == 0.0
+
+
+# --------------------------------------------------------------------------
+# Planted partition (the 1,000-vertex workload)
+# --------------------------------------------------------------------------
+def test_planted_partition_quality(orc):
+    g = inputs.planted_partition()
+    planted = (np.arange(g.n) // 100).astype(np.uint32)
+    qp = orc.modularity(g, planted)
+    # about 2*4950*0.1/|E| - 10*(1/10)^2 for p_in = 0.1, p_out = 0.005
+    assert 0.55 < qp < 0.62
+    res = {}
+    for schedule in (0, 1):
+        C, q, st = orc.static(g, schedule=schedule)
+        assert q >= qp - 0.01
+        assert len(np.unique(C)) == 10
+        assert components_connected(g, C)
+        res[schedule] = q
+    assert abs(res[0] - res[1]) <= 1e-2
+
+
+# --------------------------------------------------------------------------
+# Sequential local moving never lowers modularity; each move gains exactly dq
+# --------------------------------------------------------------------------
+def test_seq_moves_raise_q_by_their_gain(orc):
+    for seed in (1, 2):
+        g = random_graph(14, 0.3, seed=seed, wmax=4)
+        C0 = np.arange(g.n, dtype=np.uint32)
+        _, moves = orc.move_trace(g, C0)
+        assert moves
+        C = C0.tolist()
+        q = q_exact(g, C)
+        for v, frm, to, dq in moves:
+            assert C[v] == frm and dq > 0
+            C[v] = to
+            q2 = q_exact(g, C)
+            assert abs(float(q2 - q) - dq) <= 1e-14
+            assert q2 > q
+            q = q2
+
+
+# --------------------------------------------------------------------------
+# Split: plain connected-component definition
+# --------------------------------------------------------------------------
+def test_split_matches_component_definition(orc):
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+    rng = np.random.default_rng(5)
+    for s in range(10):
+        g = random_graph(30, 0.08, seed=500 + s)
+        C = rng.integers(0, 5, size=g.n).astype(np.uint32)
+        split = np.zeros(g.n, np.uint8)
+        refine = np.zeros(g.n, np.uint8)
+        split[[0, 1, 2, 3]] = 1
+        refine[[3]] = 1
+        out = orc.split(g, C, split, refine)
+        src, dst, _ = directed_entries(g)
+        for c in range(5):
+            members = np.flatnonzero(C == c)
+            if split[c] and not refine[c]:
+                idx = {v: k for k, v in enumerate(members)}
+                rows, cols = [], []
+                for a, b in zip(src, dst):
+                    if a in idx and b in idx:
+                        rows.append(idx[a])
+                        cols.append(idx[b])
+                m = csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(len(members), len(members)))
+                ncomp, lab = connected_components(m, directed=False)
+                for comp in range(ncomp):
+                    vs = members[lab == comp]
+                    assert set(out[vs].tolist()) == {int(vs.min())}
+            else:
+                assert (out[members] == c).all()
+
+
+# --------------------------------------------------------------------------
+# Aggregation keeps total weight and partition modularity
+# --------------------------------------------------------------------------
+def test_aggregation_invariants(orc):
+    rng = np.random.default_rng(9)
+    for s in range(6):
+        g = random_graph(40, 0.12, seed=700 + s, wmax=5)
+        nc = 7
+        C = rng.integers(0, nc, size=g.n).astype(np.uint32)
+        C = np.unique(C, return_inverse=True)[1].astype(np.uint32)
+        nc = int(C.max()) + 1
+        w64 = g.w.astype(np.int64)
+        o2, c2, w2 = orc.aggregate(g.n, g.offs, g.cols, w64, C, nc)
+        assert int(w2.sum()) == int(w64.sum())
+        K = np.zeros(g.n, np.int64)
+        np.add.at(K, np.repeat(np.arange(g.n), np.diff(g.offs)), w64)
+        Sig = np.zeros(nc, np.int64)
+        np.add.at(Sig, C, K)
+        Ksup = np.zeros(nc, np.int64)
+        np.add.at(Ksup, np.repeat(np.arange(nc), np.diff(o2)), w2)
+        assert (Ksup == Sig).all()
+        for _ in range(4):
+            P = rng.integers(0, 3, size=nc).astype(np.uint32)
+            a = orc.modularity64(g.n, g.offs, g.cols, w64, P[C])
+            b = orc.modularity64(nc, o2, c2, w2, P)
+            assert a[1:] == b[1:]  # sigma, 2m and T identical integers
+            assert a[0] == b[0]
+
+
+# --------------------------------------------------------------------------
+# Dynamic front-end and special cases
+# --------------------------------------------------------------------------
+def _setup_dynamic(orc, g, nb, seed, schedule=1):
+    C0, _, _ = orc.static(g, schedule=schedule)
+    st = orc.initial_state(g, C0)
+    dels, ins = inputs.random_batch(g.n, g.undirected_keys(), nb, seed=seed)
+    gt, dw = orc.apply_batch(g, dels, ins)
+    return C0, st, dels, ins, gt, dw
+
+
+def test_aux_update_equals_recompute(orc):
+    g = inputs.planted_partition()
+    C0, st, dels, ins, gt, dw = _setup_dynamic(orc, g, 300, seed=21)
+    for mode in ("nd", "ds", "df"):
+        p = orc.prepare(gt, dw, ins, st, mode)
+        K = np.zeros(g.n, np.int64)
+        np.add.at(K, np.repeat(np.arange(gt.n), np.diff(gt.offs)), gt.w.astype(np.int64))
+        assert (p["K"] == K).all()
+        S = np.zeros(g.n, np.int64)
+        np.add.at(S, C0, K)
+        assert (p["S"] == S).all()
+        C1, st1, q1, _ = orc.update(gt, dw, ins, st, mode)
+        assert (st1.K == K).all()
+        S1 = np.zeros(g.n, np.int64)
+        np.add.at(S1, C1, K)
+        assert (st1.S == S1).all()
+        assert abs(q1 - orc.modularity(gt, C1)) == 0.0
+
+
+def test_batch_application_set_semantics(orc):
+    g = inputs.planted_partition()
+    keys = g.undirected_keys()
+    dels, ins = inputs.random_batch(g.n, keys, 200, seed=4)
+    gt, dw = orc.apply_batch(g, dels, ins)
+    assert np.array_equal(gt.undirected_keys(), inputs.keys_after_batch(keys, dels, ins))
+    assert (dw[:, 2] == 1).all()
+    for bad_dels, bad_ins in [
+        (np.array([[0, 0]]), np.zeros((0, 3))),                       # self-loop deletion
+        (np.zeros((0, 2)), np.array([[5, 5, 1]])),                    # self-loop insertion
+        (np.zeros((0, 2)), np.array([[0, 1000, 1]])),                 # ID out of range
+        (dels[:1], np.zeros((0, 3))),                                 # deleted twice (absent now)
+        (np.zeros((0, 2)), ins[:1]),                                  # present pair inserted
+        (np.zeros((0, 2)), np.array([[2, 3, 0]])),                    # zero weight
+    ]:
+        with pytest.raises(ValueError):
+            orc.apply_batch(gt, np.asarray(bad_dels, np.uint32), np.asarray(bad_ins, np.uint32))
+    u, v = int(keys[0] >> 32), int(keys[0] & 0xFFFFFFFF)
+    with pytest.raises(ValueError):  # same pair twice in one batch
+        orc.apply_batch(g, np.array([[u, v], [v, u]], np.uint32), np.zeros((0, 3), np.uint32))
+
+
+@pytest.mark.parametrize("schedule", [0, 1], ids=["seq", "jacobi"])
+def test_empty_batch_keeps_memberships(orc, schedule):
+    g = inputs.planted_partition()
+    C0, _, _ = orc.static(g, schedule=schedule)
+    st = orc.initial_state(g, C0)
+    e2, e3 = np.zeros((0, 3), np.uint32), np.zeros((0, 3), np.uint32)
+    for mode in ("ds", "df"):
+        C1, st1, _, stats = orc.update(g, e2, e3, st, mode, schedule=schedule)
+        assert (C1 == C0).all()
+        assert stats["passes"] == 1 and stats["iters"] == [1]
+        assert (st1.dS == 0).all()
+
+
+def test_df_ignores_inter_deletions_and_intra_insertions(orc):
+    g = inputs.planted_partition()
+    C0, _, _ = orc.static(g)
+    st = orc.initial_state(g, C0)
+    keys = g.undirected_keys()
+    u = (keys >> np.uint64(32)).astype(np.int64)
+    v = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    inter = np.flatnonzero(C0[u] != C0[v])[:10]
+    dels = np.stack([u[inter], v[inter]], 1).astype(np.uint32)
+    rng = np.random.default_rng(2)
+    present = set(keys.tolist())
+    ins = []
+    while len(ins) < 10:
+        a, b = sorted(rng.integers(0, g.n, 2).tolist())
+        if a != b and C0[a] == C0[b] and ((a << 32) | b) not in present and (a, b, 1) not in ins:
+            ins.append((a, b, 1))
+    ins = np.asarray(ins, np.uint32)
+    gt, dw = orc.apply_batch(g, dels, ins)
+    p = orc.prepare(gt, dw, ins, st, "df")
+    assert p["affected"].sum() == 0 and p["refine"].sum() == 0
+    C1, _, _, stats = orc.update(gt, dw, ins, st, "df")
+    assert (C1 == C0).all()
+
+
+def test_dynamic_results_connected_and_close_to_static(orc):
+    g = inputs.planted_partition()
+    for schedule in (0, 1):
+        C0, st, dels, ins, gt, dw = _setup_dynamic(orc, g, 100, seed=8, schedule=schedule)
+        Cs, qs, _ = orc.static(gt, schedule=schedule)
+        for mode in ("nd", "ds", "df"):
+            C1, st1, q1, _ = orc.update(gt, dw, ins, st, mode, schedule=schedule)
+            assert components_connected(gt, C1)
+            assert q1 >= qs - 0.01
+            assert (np.unique(C1) < g.n).all()
+
+
+def test_refine_threshold_marks_and_resets(orc):
+    g = inputs.planted_partition()
+    C0, _, _ = orc.static(g)
+    st = orc.initial_state(g, C0)
+    # a heavy intra-community insertion: DeltaSigma/Sigma > 3/5 marks the community
+    c = int(C0[0])
+    members = np.flatnonzero(C0 == c)
+    keys = set(g.undirected_keys().tolist())
+    pair = next((int(a), int(b)) for a, b in itertools.combinations(members, 2) if ((int(a) << 32) | int(b)) not in keys)
+    Sc = int(st.S[c])
+    ins = np.array([[pair[0], pair[1], Sc]], np.uint32)  # 2*Sc added, 5*2Sc > 3*(Sc+2Sc)
+    gt, dw = orc.apply_batch(g, np.zeros((0, 2), np.uint32), ins)
+    p = orc.prepare(gt, dw, ins, st, "df")
+    assert p["refine"][c] == 1 and p["refine"].sum() == 1
+    assert p["dS"][c] == 0
+    ins2 = np.array([[pair[0], pair[1], 1]], np.uint32)
+    gt2, dw2 = orc.apply_batch(g, np.zeros((0, 2), np.uint32), ins2)
+    p2 = orc.prepare(gt2, dw2, ins2, st, "df")
+    assert p2["refine"].sum() == 0 and p2["dS"][c] == 2
+
+
+# --------------------------------------------------------------------------
+# Tracking (Alg. 12)
+# --------------------------------------------------------------------------
+def boyer_moore_candidates(C_cur, C_prev, K):
+    """The paper's weighted majority vote per old community, run sequentially."""
+    H = {}
+    for c, cp, w in zip(C_prev, C_cur, K):
+        if c in H and H[c][0] == cp:
+            H[c][1] += w
+        elif c in H and H[c][1] > w:
+            H[c][1] -= w
+        else:
+            H[c] = [cp, w]
+    return {b: v[0] for b, v in H.items()}
+
+
+def test_tracking_identity_and_permutation(orc):
+    rng = np.random.default_rng(4)
+    n = 200
+    prev = rng.integers(0, 30, size=n).astype(np.uint32)
+    K = rng.integers(1, 9, size=n).astype(np.int64)
+    perm = rng.permutation(n).astype(np.uint32)
+    assert (orc.track(perm[prev], prev, K) == prev).all()
+    cur = rng.integers(0, 25, size=n).astype(np.uint32)
+    a = orc.track(cur, prev, K)
+    b = orc.track(perm[cur], prev, K)
+    assert (a == b).all()
+    # the same partition comes out, relabelled
+    assert len(np.unique(a)) == len(np.unique(cur))
+    pairs = set(zip(a.tolist(), cur.tolist()))
+    assert len(pairs) == len(np.unique(cur))
+
+
+def test_tracking_agrees_with_boyer_moore_majority(orc):
+    rng = np.random.default_rng(6)
+    n = 300
+    for s in range(20):
+        prev = rng.integers(0, 20, size=n).astype(np.uint32)
+        K = rng.integers(1, 6, size=n).astype(np.int64)
+        # each old community keeps a strict weighted majority in one new community
+        target = rng.permutation(40)[:20]
+        cur = target[prev].astype(np.uint32)
+        flip = rng.random(n) < 0.15
+        cur[flip] = rng.integers(0, 40, size=int(flip.sum()))
+        out = orc.track(cur, prev, K)
+        bm = boyer_moore_candidates(cur.tolist(), prev.tolist(), K.tolist())
+        for b in np.unique(prev):
+            m = prev == b
+            tot = K[m].sum()
+            ov = {}
+            for c, w in zip(cur[m], K[m]):
+                ov[int(c)] = ov.get(int(c), 0) + int(w)
+            best = max(ov.items(), key=lambda kv: (kv[1], -kv[0]))
+            if 2 * best[1] > tot:
+                assert bm[int(b)] == best[0]
+                # the community that b picked now carries a label of an old community
+                assert out[cur == best[0]][0] in set(prev.tolist())
+    # fresh labels are the smallest IDs that were not old labels
+    prev = np.array([0, 0, 1, 1, 2, 2], np.uint32)
+    cur = np.array([5, 5, 5, 7, 8, 9], np.uint32)
+    K = np.ones(6, np.int64)
+    out = orc.track(cur, prev, K)
+    assert out.tolist() == [0, 0, 0, 3, 2, 4]
+
+
+# --------------------------------------------------------------------------
+# Readings pinned by hand-derived cases
+# --------------------------------------------------------------------------
+def test_equal_gains_go_to_lowest_label(orc):
+    # star with centre 0 and leaves 1, 2 (unit weights): the sequential sweep
+    # reaches 0 first; joining {1} or {2} gains the same, so 0 joins community 1.
+    g = inputs.csr_from_edges(3, [(0, 1), (0, 2)])
+    _, moves = orc.move_trace(g)
+    assert moves[0][:3] == (0, 0, 1)
+    # dq = (1 - 0)/m - K0 (K0 + S1 - S0)/(2 m^2) with m = 2, K0 = S0 = 2, S1 = 1
+    assert moves[0][3] == 1 / 2 - 2 * (2 + 1 - 2) / (2 * 4)
+
+
+def test_subset_renumber_uses_minimum_member(orc):
+    rng = np.random.default_rng(12)
+    n = 60
+    C = rng.integers(0, n, size=n).astype(np.uint32)
+    S = rng.integers(0, 100, size=n).astype(np.int64)
+    sp = (rng.random(n) < 0.5).astype(np.uint8)
+    rf = (rng.random(n) < 0.5).astype(np.uint8)
+    C2, S2, sp2, rf2 = orc.subset_renumber(C, S, sp, rf)
+    for c in np.unique(C):
+        members = np.flatnonzero(C == c)
+        r = int(members.min())
+        assert (C2[members] == r).all()
+        assert S2[r] == S[c] and sp2[r] == sp[c] and rf2[r] == rf[c]
+    used = set(np.unique(C2).tolist())
+    for x in range(n):
+        if x not in used:
+            assert S2[x] == 0 and sp2[x] == 0 and rf2[x] == 0
+
+
+def test_ds_marking_follows_its_definition(orc):
+    g = inputs.planted_partition()
+    C0, _, _ = orc.static(g)
+    st = orc.initial_state(g, C0)
+    keys = g.undirected_keys()
+    u = (keys >> np.uint64(32)).astype(np.int64)
+    v = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    k = int(np.flatnonzero(C0[u] == C0[v])[0])
+    a, b = int(u[k]), int(v[k])
+    dels = np.array([[a, b]], np.uint32)
+    gt, dw = orc.apply_batch(g, dels, np.zeros((0, 3), np.uint32))
+    p = orc.prepare(gt, dw, np.zeros((0, 3), np.uint32), st, "ds")
+    # intra-community deletion: both endpoints, their neighbours in G^t and the
+    # whole community are affected
+    expect = set(np.flatnonzero(C0 == C0[a]).tolist()) | {a, b}
+    for x in (a, b):
+        expect |= set(gt.cols[gt.offs[x]:gt.offs[x + 1]].tolist())
+    assert set(np.flatnonzero(p["affected"]).tolist()) == expect
+    assert (p["in_range"] == p["affected"]).all()
+    assert p["split"][C0[a]] == 1 and p["split"].sum() == 1
+    # inter-community insertion (i, j): i, j, their neighbours, and the whole
+    # community of the other endpoint (the only candidate) are affected
+    present = set(keys.tolist())
+    rng = np.random.default_rng(1)
+    while True:
+        i, j = sorted(rng.integers(0, g.n, 2).tolist())
+        if i != j and C0[i] != C0[j] and ((i << 32) | j) not in present:
+            break
+    ins = np.array([[i, j, 1]], np.uint32)
+    gt, dw = orc.apply_batch(g, np.zeros((0, 2), np.uint32), ins)
+    p = orc.prepare(gt, dw, ins, st, "ds")
+    expect = set(np.flatnonzero(C0 == C0[j]).tolist()) | set(np.flatnonzero(C0 == C0[i]).tolist())
+    for x in (i, j):
+        expect |= set(gt.cols[gt.offs[x]:gt.offs[x + 1]].tolist()) | {x}
+    assert set(np.flatnonzero(p["affected"]).tolist()) == expect
+    pdf = orc.prepare(gt, dw, ins, st, "df")
+    assert set(np.flatnonzero(pdf["affected"]).tolist()) == {i, j}
+    assert pdf["in_range"].all()
+    pnd = orc.prepare(gt, dw, ins, st, "nd")
+    assert pnd["affected"].all() and pnd["in_range"].all()
