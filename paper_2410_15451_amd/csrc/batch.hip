@@ -1,0 +1,586 @@
+// Batch update kernels: G^{t-1} -> G^t with set semantics (Section 2.4) on
+// the device slack CSR, the auxiliary-state update of Alg. 11, the community
+// marking of Alg. 5 and the vertex marking of Alg. 2 / Alg. 3.
+//
+// Every undirected update becomes its two directed entries.  Entries are
+// grouped by source row (counting by row, one segment per touched row) and
+// sorted by destination inside each segment; validation then checks each
+// entry against the sorted old row, and the merge writes each new sorted row
+// to scratch before it is committed in place (or into the overflow area when
+// the row outgrows its capacity).  Nothing is written to the graph before
+// validation has passed, so a rejected batch leaves the graph unchanged.
+#include "kernels.h"
+
+namespace lm {
+
+static int grid_n(uint64_t n, int per_block = kBlock, int cap = 8192) {
+  uint64_t b = (n + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > (uint64_t)cap) b = cap;
+  return (int)b;
+}
+
+#define GRID_STRIDE(i, n) \
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < (uint64_t)(n); i += (uint64_t)gridDim.x * kBlock)
+
+enum : unsigned int { kErrId = 1, kErrDup = 2, kErrPresent = 4, kErrAbsent = 8 };
+
+// ---------------------------------------------------------------------------
+// Expansion and grouping
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_expand(const uint32_t* del, uint64_t n_del, const uint32_t* ins,
+                                                   uint64_t n_ins, uint32_t n, BatchBufs b, Ctl* ctl) {
+  GRID_STRIDE(k, n_del + n_ins) {
+    const bool is_del = k < n_del;
+    const uint32_t u = is_del ? del[2 * k] : ins[3 * (k - n_del)];
+    const uint32_t v = is_del ? del[2 * k + 1] : ins[3 * (k - n_del) + 1];
+    const uint32_t w = is_del ? 0u : ins[3 * (k - n_del) + 2];
+    if (u >= n || v >= n || u == v || (!is_del && w == 0)) {
+      atomicOr(&ctl->error, kErrId);
+      b.src[2 * k] = kNone;
+      b.src[2 * k + 1] = kNone;
+      continue;
+    }
+    for (int h = 0; h < 2; ++h) {
+      const uint64_t e = 2 * k + h;
+      const uint32_t a = h ? v : u, c = h ? u : v;
+      const uint32_t sl = atomicAdd(&b.row_cnt[a], 1u);
+      if (sl == 0) list_push(b.touched, &ctl->touched, a);
+      b.slot[e] = sl;
+      b.src[e] = a;
+      b.dst[e] = c;
+      b.w[e] = w;
+      b.is_del[e] = is_del ? 1u : 0u;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_setup(uint64_t nt, BatchBufs b) {
+  GRID_STRIDE(t, nt) {
+    const uint32_t r = b.touched[t];
+    b.seg_cnt[t] = b.row_cnt[r];
+    b.row_idx[r] = (uint32_t)t;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(uint64_t ne, BatchBufs b) {
+  GRID_STRIDE(e, ne) {
+    const uint32_t a = b.src[e];
+    if (a == kNone) continue;
+    const uint32_t t = b.row_idx[a];
+    const uint64_t pos = b.seg_off[t] + b.slot[e];
+    b.seg_src[pos] = a;
+    b.seg_dst[pos] = b.dst[e];
+    b.seg_w[pos] = b.w[e];
+    b.seg_del[pos] = b.is_del[e];
+    b.seg_id[pos] = t;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_row_cnt_clear(uint64_t nt, BatchBufs b) {
+  GRID_STRIDE(t, nt) b.row_cnt[b.touched[t]] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Sorting each segment by destination (src is equal inside a segment).
+// Short segments: one thread, insertion sort.  Medium: one block, bitonic
+// sort in LDS.  Long: one block, bottom-up merge sort through scratch.
+// ---------------------------------------------------------------------------
+__device__ inline void seg_swap(BatchBufs& b, uint64_t x, uint64_t y) {
+  uint32_t t;
+  t = b.seg_dst[x]; b.seg_dst[x] = b.seg_dst[y]; b.seg_dst[y] = t;
+  t = b.seg_w[x]; b.seg_w[x] = b.seg_w[y]; b.seg_w[y] = t;
+  t = b.seg_del[x]; b.seg_del[x] = b.seg_del[y]; b.seg_del[y] = t;
+}
+
+constexpr uint32_t kSortShort = 32, kSortLds = 2048;
+
+__global__ __launch_bounds__(kBlock) void k_sort_short(uint64_t nt, BatchBufs b) {
+  GRID_STRIDE(t, nt) {
+    const uint64_t s0 = b.seg_off[t], s1 = b.seg_off[t + 1];
+    if (s1 - s0 > kSortShort) continue;
+    for (uint64_t i = s0 + 1; i < s1; ++i)
+      for (uint64_t j = i; j > s0 && b.seg_dst[j - 1] > b.seg_dst[j]; --j) seg_swap(b, j - 1, j);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sort_lds(uint64_t nt, BatchBufs b) {
+  __shared__ uint32_t key[kSortLds];
+  __shared__ uint32_t idx[kSortLds];
+  for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    const uint64_t s0 = b.seg_off[t], s1 = b.seg_off[t + 1];
+    const uint32_t L = (uint32_t)(s1 - s0);
+    if (L <= kSortShort || L > kSortLds) continue;
+    uint32_t P = 1;
+    while (P < L) P <<= 1;
+    for (uint32_t i = threadIdx.x; i < P; i += kBlock) {
+      key[i] = i < L ? b.seg_dst[s0 + i] : kNone;
+      idx[i] = i;
+    }
+    __syncthreads();
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        for (uint32_t i = threadIdx.x; i < P; i += kBlock) {
+          const uint32_t l = i ^ j;
+          if (l > i) {
+            const bool up = (i & k) == 0;
+            const bool gt = key[i] > key[l] || (key[i] == key[l] && idx[i] > idx[l]);
+            if (gt == up) {
+              uint32_t x = key[i]; key[i] = key[l]; key[l] = x;
+              x = idx[i]; idx[i] = idx[l]; idx[l] = x;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // permute the payload through registers of this block (at most kSortLds / kBlock each)
+    constexpr int kPer = kSortLds / kBlock;
+    uint32_t pw[kPer], pd[kPer];
+    int cnt = 0;
+    for (uint32_t i = threadIdx.x; i < L; i += kBlock, ++cnt) {
+      pw[cnt] = b.seg_w[s0 + idx[i]];
+      pd[cnt] = b.seg_del[s0 + idx[i]];
+    }
+    __syncthreads();
+    cnt = 0;
+    for (uint32_t i = threadIdx.x; i < L; i += kBlock, ++cnt) {
+      b.seg_dst[s0 + i] = key[i];
+      b.seg_w[s0 + i] = pw[cnt];
+      b.seg_del[s0 + i] = pd[cnt];
+    }
+    __syncthreads();
+  }
+}
+
+// One block per long segment: merge runs of width 1, 2, 4, ... between the
+// segment and its scratch copy; each thread merges one pair of runs.
+__global__ __launch_bounds__(kBlock) void k_sort_long(uint64_t nt, BatchBufs b) {
+  for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    const uint64_t s0 = b.seg_off[t], s1 = b.seg_off[t + 1];
+    const uint64_t L = s1 - s0;
+    if (L <= kSortLds) continue;
+    uint32_t *ad = b.seg_dst + s0, *aw = b.seg_w + s0, *ax = b.seg_del + s0;
+    uint32_t *bd = b.tmp_dst + s0, *bw = b.tmp_w + s0, *bx = b.tmp_del + s0;
+    for (uint64_t width = 1; width < L; width <<= 1) {
+      for (uint64_t lo = (uint64_t)threadIdx.x * 2 * width; lo < L; lo += (uint64_t)kBlock * 2 * width) {
+        const uint64_t mid = lo + width < L ? lo + width : L;
+        const uint64_t hi = lo + 2 * width < L ? lo + 2 * width : L;
+        uint64_t i = lo, j = mid, o = lo;
+        while (i < mid || j < hi) {
+          const bool take_i = j >= hi || (i < mid && ad[i] <= ad[j]);
+          const uint64_t s = take_i ? i++ : j++;
+          bd[o] = ad[s];
+          bw[o] = aw[s];
+          bx[o] = ax[s];
+          ++o;
+        }
+      }
+      __syncthreads();
+      uint32_t* x;
+      x = ad; ad = bd; bd = x;
+      x = aw; aw = bw; bw = x;
+      x = ax; ax = bx; bx = x;
+    }
+    if (ad != b.seg_dst + s0) {
+      for (uint64_t i = threadIdx.x; i < L; i += kBlock) {
+        b.seg_dst[s0 + i] = ad[i];
+        b.seg_w[s0 + i] = aw[i];
+        b.seg_del[s0 + i] = ax[i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Validation against G^{t-1}: no pair twice, deletions present (their old
+// weight is recorded), insertions absent.
+// ---------------------------------------------------------------------------
+__device__ inline int64_t row_find(const uint32_t* cols, int64_t s0, uint32_t L, uint32_t key) {
+  uint32_t lo = 0, hi = L;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (cols[s0 + mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return (lo < L && cols[s0 + lo] == key) ? s0 + lo : -1;
+}
+
+__device__ inline uint32_t row_lower_bound(const uint32_t* cols, int64_t s0, uint32_t L, uint32_t key) {
+  uint32_t lo = 0, hi = L;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (cols[s0 + mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_validate(uint64_t ne, Rows<uint32_t> g, BatchBufs b, Ctl* ctl) {
+  unsigned int err = 0;
+  GRID_STRIDE(q, ne) {
+    const uint32_t t = b.seg_id[q];
+    const uint32_t d = b.seg_dst[q];
+    if (q + 1 < b.seg_off[t + 1] && b.seg_dst[q + 1] == d) err |= kErrDup;
+    const uint32_t r = b.seg_src[q];
+    const int64_t pos = row_find(g.cols, g.start[r], g.len[r], d);
+    if (b.seg_del[q]) {
+      if (pos < 0)
+        err |= kErrAbsent;
+      else
+        b.seg_w[q] = g.w[pos];
+    } else if (pos >= 0) {
+      err |= kErrPresent;
+    }
+  }
+  if (err) atomicOr(&ctl->error, err);
+}
+
+// ---------------------------------------------------------------------------
+// Merge planning, merge and commit
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_new_len(uint64_t nt, const uint32_t* len, const uint32_t* cap,
+                                                    BatchBufs b, Ctl* ctl) {
+  unsigned long long need = 0;
+  GRID_STRIDE(t, nt) {
+    const uint32_t r = b.touched[t];
+    const uint64_t s0 = b.seg_off[t], s1 = b.seg_off[t + 1];
+    const uint64_t dels = b.seg_pre[s1] - b.seg_pre[s0];
+    const uint64_t inss = (s1 - s0) - dels;
+    const uint32_t nl = (uint32_t)(len[r] - dels + inss);
+    b.new_len[t] = nl;
+    if (nl > cap[r]) need += nl + (nl >> 2) + 4;
+  }
+  if (need) atomicAdd(&ctl->overflow_need, need);
+}
+
+// One wavefront per touched row: every old entry and every inserted entry
+// computes its position in the merged sorted row directly.
+__global__ __launch_bounds__(kBlock) void k_merge(uint64_t nt, Rows<uint32_t> g, BatchBufs b) {
+  const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const uint32_t lane = threadIdx.x % kWave;
+  const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
+  for (uint64_t t = wave; t < nt; t += nwaves) {
+    const uint32_t r = b.touched[t];
+    const uint64_t s0 = b.seg_off[t], s1 = b.seg_off[t + 1];
+    const uint32_t L = (uint32_t)(s1 - s0);
+    const int64_t r0 = g.start[r];
+    const uint32_t RL = g.len[r];
+    const uint64_t o = b.out_off[t];
+    const uint64_t pre0 = b.seg_pre[s0];
+    // old entries
+    for (uint32_t p = lane; p < RL; p += kWave) {
+      const uint32_t x = g.cols[r0 + p];
+      uint32_t lo = 0, hi = L;  // first segment entry with dst >= x
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (b.seg_dst[s0 + mid] < x)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      if (lo < L && b.seg_dst[s0 + lo] == x) continue;  // deleted (insertions of present pairs were rejected)
+      const uint64_t dels = b.seg_pre[s0 + lo] - pre0;
+      const uint64_t inss = lo - dels;
+      const uint64_t pos = o + p - dels + inss;
+      b.mcols[pos] = x;
+      b.mw[pos] = g.w[r0 + p];
+    }
+    // inserted entries
+    for (uint32_t q = lane; q < L; q += kWave) {
+      if (b.seg_del[s0 + q]) continue;
+      const uint32_t y = b.seg_dst[s0 + q];
+      const uint32_t lb = row_lower_bound(g.cols, r0, RL, y);
+      const uint64_t dels = b.seg_pre[s0 + q] - pre0;
+      const uint64_t inss = q - dels;
+      const uint64_t pos = o + lb - dels + inss;
+      b.mcols[pos] = y;
+      b.mw[pos] = b.seg_w[s0 + q];
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_commit(uint64_t nt, int64_t* start, uint32_t* len, uint32_t* cap,
+                                                   uint32_t* cols, uint32_t* w, BatchBufs b,
+                                                   unsigned long long* edge_top) {
+  const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const uint32_t lane = threadIdx.x % kWave;
+  const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
+  for (uint64_t t = wave; t < nt; t += nwaves) {
+    const uint32_t r = b.touched[t];
+    const uint32_t nl = b.new_len[t];
+    int64_t s0 = start[r];
+    if (nl > cap[r]) {
+      const uint32_t nc = nl + (nl >> 2) + 4;
+      unsigned long long base = 0;
+      if (lane == 0) base = atomicAdd(edge_top, (unsigned long long)nc);
+      base = __shfl(base, 0, kWave);
+      s0 = (int64_t)base;
+      if (lane == 0) {
+        start[r] = s0;
+        cap[r] = nc;
+      }
+    }
+    const uint64_t o = b.out_off[t];
+    for (uint32_t p = lane; p < nl; p += kWave) {
+      cols[s0 + p] = b.mcols[o + p];
+      w[s0 + p] = b.mw[o + p];
+    }
+    if (lane == 0) len[r] = nl;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side of the batch pipeline
+// ---------------------------------------------------------------------------
+int batch_prepare(hipStream_t s, uint32_t n, const uint32_t* del, uint64_t n_del, const uint32_t* ins, uint64_t n_ins,
+                  BatchBufs& b, Ctl* ctl, uint64_t* n_touched_host) {
+  const uint64_t nb = n_del + n_ins;
+  const uint64_t ne = 2 * nb;
+  if (nb)
+    hipLaunchKernelGGL(k_expand, dim3(grid_n(nb)), dim3(kBlock), 0, s, del, n_del, ins, n_ins, n, b, ctl);
+  unsigned int hv[2] = {0, 0};
+  (void)hipMemcpyAsync(hv, &ctl->error, sizeof(hv), hipMemcpyDeviceToHost, s);  // error, touched
+  if (hipStreamSynchronize(s) != hipSuccess) return -100;
+  const uint64_t nt = hv[1];
+  *n_touched_host = nt;
+  if (hv[0]) {
+    if (nt) hipLaunchKernelGGL(k_row_cnt_clear, dim3(grid_n(nt)), dim3(kBlock), 0, s, nt, b);
+    return (int)hv[0];
+  }
+  if (nt == 0) return 0;
+  hipLaunchKernelGGL(k_seg_setup, dim3(grid_n(nt)), dim3(kBlock), 0, s, nt, b);
+  exclusive_scan_u32(s, b.seg_cnt, b.seg_off, nt, b.total, b.scan_tmp);
+  (void)hipMemcpyAsync(b.seg_off + nt, b.total, sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
+  hipLaunchKernelGGL(k_scatter, dim3(grid_n(ne)), dim3(kBlock), 0, s, ne, b);
+  hipLaunchKernelGGL(k_row_cnt_clear, dim3(grid_n(nt)), dim3(kBlock), 0, s, nt, b);
+  hipLaunchKernelGGL(k_sort_short, dim3(grid_n(nt)), dim3(kBlock), 0, s, nt, b);
+  hipLaunchKernelGGL(k_sort_lds, dim3(grid_n(nt, 1, 1024)), dim3(kBlock), 0, s, nt, b);
+  hipLaunchKernelGGL(k_sort_long, dim3(grid_n(nt, 1, 256)), dim3(kBlock), 0, s, nt, b);
+  // prefix counts of deletions inside segments (for the merge positions)
+  exclusive_scan_u32(s, b.seg_del, b.seg_pre, ne, b.total, b.scan_tmp);
+  (void)hipMemcpyAsync(b.seg_pre + ne, b.total, sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
+  return 0;
+}
+
+int batch_validate(hipStream_t s, Rows<uint32_t> g, uint32_t n, uint64_t n_entries, uint64_t n_touched, BatchBufs& b,
+                   Ctl* ctl) {
+  (void)n;
+  (void)n_touched;
+  if (n_entries)
+    hipLaunchKernelGGL(k_validate, dim3(grid_n(n_entries)), dim3(kBlock), 0, s, n_entries, g, b, ctl);
+  unsigned int err = 0;
+  (void)hipMemcpyAsync(&err, &ctl->error, sizeof(err), hipMemcpyDeviceToHost, s);
+  if (hipStreamSynchronize(s) != hipSuccess) return -100;
+  return (int)err;
+}
+
+int batch_merge(hipStream_t s, int64_t* start, uint32_t* len, uint32_t* cap, uint32_t* cols, uint32_t* w,
+                uint64_t n_touched, BatchBufs& b, unsigned long long* edge_top, uint64_t edge_cap, Ctl* ctl) {
+  const uint64_t nt = n_touched;
+  if (nt == 0) return 0;
+  hipLaunchKernelGGL(k_new_len, dim3(grid_n(nt)), dim3(kBlock), 0, s, nt, len, cap, b, ctl);
+  exclusive_scan_u32(s, b.new_len, b.out_off, nt, b.total, b.scan_tmp);
+  unsigned long long hv[3] = {0, 0, 0};  // need, top, merged total
+  (void)hipMemcpyAsync(&hv[0], &ctl->overflow_need, sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+  (void)hipMemcpyAsync(&hv[1], edge_top, sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+  (void)hipMemcpyAsync(&hv[2], b.total, sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+  if (hipStreamSynchronize(s) != hipSuccess) return -100;
+  if (hv[1] + hv[0] > edge_cap || hv[2] > b.mcap) return 1;
+  Rows<uint32_t> g{start, len, cols, w};
+  hipLaunchKernelGGL(k_merge, dim3(grid_n(nt, kBlock / kWave, 8192)), dim3(kBlock), 0, s, nt, g, b);
+  hipLaunchKernelGGL(k_commit, dim3(grid_n(nt, kBlock / kWave, 8192)), dim3(kBlock), 0, s, nt, start, len, cap, cols,
+                     w, b, edge_top);
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 11: K and Sigma by the old memberships; DeltaSigma counts deletions and
+// insertions alike.  Integer atomics, so the order of entries is irrelevant.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_aux_update(uint64_t ne, BatchBufs b, const uint32_t* Cprev, int64_t* K,
+                                                       int64_t* S, int64_t* dSig) {
+  GRID_STRIDE(q, ne) {
+    const uint32_t i = b.seg_src[q];
+    const uint32_t c = Cprev[i];
+    const long long w = (long long)b.seg_w[q];
+    const long long sgn = b.seg_del[q] ? -w : w;
+    atomicAdd((unsigned long long*)&K[i], (unsigned long long)sgn);
+    atomicAdd((unsigned long long*)&S[c], (unsigned long long)sgn);
+    atomicAdd((unsigned long long*)&dSig[c], (unsigned long long)w);
+  }
+}
+
+void launch_aux_update(hipStream_t s, const BatchBufs& b, uint64_t n_entries, const uint32_t* Cprev, int64_t* K,
+                       int64_t* S, int64_t* dSig) {
+  if (n_entries)
+    hipLaunchKernelGGL(k_aux_update, dim3(grid_n(n_entries)), dim3(kBlock), 0, s, n_entries, b, Cprev, K, S, dSig);
+}
+
+// Alg. 5 (dynamic branch): split flags for intra-community deletions; refine
+// flags for intra-community updates with DeltaSigma / Sigma > num / den
+// (compared exactly as den * DeltaSigma > num * Sigma); then the cumulative
+// change of every refine-marked community restarts from zero.
+__device__ inline bool ratio_exceeds(unsigned long long dsig, unsigned long long sig, uint32_t num, uint32_t den) {
+  const unsigned long long alo = dsig * den, ahi = __umul64hi(dsig, (unsigned long long)den);
+  const unsigned long long blo = sig * num, bhi = __umul64hi(sig, (unsigned long long)num);
+  return ahi > bhi || (ahi == bhi && alo > blo);
+}
+
+__global__ __launch_bounds__(kBlock) void k_mark_comm(uint64_t ne, BatchBufs b, const uint32_t* Cprev,
+                                                      const int64_t* S, const int64_t* dSig, uint32_t num,
+                                                      uint32_t den, uint8_t* dS, uint8_t* dR) {
+  GRID_STRIDE(q, ne) {
+    const uint32_t c = Cprev[b.seg_src[q]], d = Cprev[b.seg_dst[q]];
+    if (c != d) continue;
+    if (b.seg_del[q]) dS[c] = 1;
+    const long long sg = S[c];
+    if (ratio_exceeds((unsigned long long)dSig[c], (unsigned long long)(sg > 0 ? sg : 0), num, den)) dR[c] = 1;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_mark_reset(uint64_t ne, BatchBufs b, const uint32_t* Cprev,
+                                                       const uint8_t* dR, int64_t* dSig) {
+  GRID_STRIDE(q, ne) {
+    const uint32_t c = Cprev[b.seg_src[q]];
+    if (dR[c]) dSig[c] = 0;
+  }
+}
+
+void launch_mark_communities(hipStream_t s, const BatchBufs& b, uint64_t n_entries, const uint32_t* Cprev,
+                             const int64_t* S, int64_t* dSig, uint32_t num, uint32_t den, uint8_t* dS, uint8_t* dR) {
+  if (!n_entries) return;
+  hipLaunchKernelGGL(k_mark_comm, dim3(grid_n(n_entries)), dim3(kBlock), 0, s, n_entries, b, Cprev, S, dSig, num, den,
+                     dS, dR);
+  hipLaunchKernelGGL(k_mark_reset, dim3(grid_n(n_entries)), dim3(kBlock), 0, s, n_entries, b, Cprev, dR, dSig);
+}
+
+// Alg. 3: endpoints of intra-community deletions and inter-community
+// insertions are affected; they form the first unprocessed list directly.
+__global__ __launch_bounds__(kBlock) void k_mark_df(uint64_t ne, BatchBufs b, const uint32_t* Cprev, uint32_t* list,
+                                                    unsigned int* count, uint32_t* mark, uint32_t stamp) {
+  GRID_STRIDE(q, ne) {
+    const uint32_t i = b.seg_src[q];
+    const bool same = Cprev[i] == Cprev[b.seg_dst[q]];
+    if (b.seg_del[q] ? same : !same) {
+      if (atomicExch(&mark[i], stamp) != stamp) list_push(list, count, i);
+    }
+  }
+}
+
+void launch_mark_df(hipStream_t s, const BatchBufs& b, uint64_t n_entries, const uint32_t* Cprev, uint32_t* list,
+                    unsigned int* count, uint32_t* mark, uint32_t stamp) {
+  if (n_entries)
+    hipLaunchKernelGGL(k_mark_df, dim3(grid_n(n_entries)), dim3(kBlock), 0, s, n_entries, b, Cprev, list, count, mark,
+                       stamp);
+}
+
+// Alg. 2: intra-community deletions mark the source, its neighbours and the
+// community; each source of inter-community insertions marks itself, its
+// neighbours and the community c* with the largest Eq. 2 gain over the
+// communities of its inserted neighbours (K_{i->c} = inserted weight into c,
+// K_{i->d} = 0, ties to the lowest ID).
+__global__ __launch_bounds__(kBlock) void k_ds_del(uint64_t ne, BatchBufs b, const uint32_t* Cprev, uint8_t* dV,
+                                                   uint8_t* dE, uint8_t* dC) {
+  GRID_STRIDE(q, ne) {
+    if (!b.seg_del[q]) continue;
+    const uint32_t i = b.seg_src[q], j = b.seg_dst[q];
+    if (Cprev[i] != Cprev[j]) continue;
+    dV[i] = 1;
+    dE[i] = 1;
+    dC[Cprev[j]] = 1;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_ds_ins(uint64_t nt, BatchBufs b, const uint32_t* Cprev, const int64_t* K,
+                                                   const int64_t* S, double inv_m, double inv_2m2, uint8_t* dV,
+                                                   uint8_t* dE, uint8_t* dC) {
+  const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const uint32_t lane = threadIdx.x % kWave;
+  const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
+  for (uint64_t t = wave; t < nt; t += nwaves) {
+    const uint64_t s0 = b.seg_off[t], s1 = b.seg_off[t + 1];
+    const uint32_t i = b.touched[t];
+    const uint32_t d = Cprev[i];
+    double bdq = -INFINITY;
+    uint32_t bc = kNone;
+    for (uint64_t qb = s0; qb < s1; qb += kWave) {
+      const uint64_t q = qb + lane;
+      if (q < s1 && !b.seg_del[q]) {
+        const uint32_t c = Cprev[b.seg_dst[q]];
+        bool first = c != d;
+        for (uint64_t p = s0; first && p < q; ++p)
+          if (!b.seg_del[p] && Cprev[b.seg_dst[p]] == c) first = false;
+        if (first) {
+          long long h = 0;
+          for (uint64_t p = s0; p < s1; ++p)
+            if (!b.seg_del[p] && Cprev[b.seg_dst[p]] == c) h += b.seg_w[p];
+          const double dq = delta_q(h, 0, K[i], S[c], S[d], inv_m, inv_2m2);
+          if (better(dq, c, bdq, bc)) {
+            bdq = dq;
+            bc = c;
+          }
+        }
+      }
+    }
+    group_best<kWave>(bdq, bc);
+    if (lane == 0 && bc != kNone) {
+      dV[i] = 1;
+      dE[i] = 1;
+      dC[bc] = 1;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_ds_neighbours(uint64_t nt, BatchBufs b, Rows<uint32_t> g,
+                                                          const uint8_t* dE, uint8_t* dV) {
+  const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const uint32_t lane = threadIdx.x % kWave;
+  const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
+  for (uint64_t t = wave; t < nt; t += nwaves) {
+    const uint32_t i = b.touched[t];
+    if (!dE[i]) continue;
+    const int64_t s0 = g.start[i];
+    const uint32_t L = g.len[i];
+    for (uint32_t e = lane; e < L; e += kWave) dV[g.cols[s0 + e]] = 1;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_ds_comm(uint32_t n, const uint32_t* Cprev, const uint8_t* dC, uint8_t* dV) {
+  GRID_STRIDE(i, n) if (dC[Cprev[i]]) dV[i] = 1;
+}
+
+void launch_mark_ds(hipStream_t s, const BatchBufs& b, uint64_t n_entries, uint64_t n_touched, Rows<uint32_t> g,
+                    uint32_t n, const uint32_t* Cprev, const int64_t* K, const int64_t* S, double inv_m,
+                    double inv_2m2, uint8_t* dV, uint8_t* dE, uint8_t* dC) {
+  if (n_entries) {
+    hipLaunchKernelGGL(k_ds_del, dim3(grid_n(n_entries)), dim3(kBlock), 0, s, n_entries, b, Cprev, dV, dE, dC);
+    hipLaunchKernelGGL(k_ds_ins, dim3(grid_n(n_touched, kBlock / kWave)), dim3(kBlock), 0, s, n_touched, b, Cprev, K,
+                       S, inv_m, inv_2m2, dV, dE, dC);
+    hipLaunchKernelGGL(k_ds_neighbours, dim3(grid_n(n_touched, kBlock / kWave)), dim3(kBlock), 0, s, n_touched, b, g,
+                       dE, dV);
+  }
+  if (n) hipLaunchKernelGGL(k_ds_comm, dim3(grid_n(n)), dim3(kBlock), 0, s, n, Cprev, dC, dV);
+}
+
+// Flag array -> vertex list (order irrelevant), stamping each listed vertex.
+__global__ __launch_bounds__(kBlock) void k_flags_to_list(const uint8_t* flags, uint32_t n, uint32_t* list,
+                                                          unsigned int* count, uint32_t* mark, uint32_t stamp) {
+  GRID_STRIDE(i, n) {
+    if (!flags[i]) continue;
+    mark[i] = stamp;
+    list_push(list, count, (uint32_t)i);
+  }
+}
+
+void launch_flags_to_list(hipStream_t s, const uint8_t* flags, uint32_t n, uint32_t* list, unsigned int* count,
+                          uint32_t* mark, uint32_t stamp) {
+  if (n) hipLaunchKernelGGL(k_flags_to_list, dim3(grid_n(n)), dim3(kBlock), 0, s, flags, n, list, count, mark, stamp);
+}
+
+}  // namespace lm

@@ -1,0 +1,205 @@
+// Shared definitions of the gfx950 Leiden kernels and their host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace lm {
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr int kBlock = 256;     // threads per block of every list kernel
+constexpr int kWave = 64;       // CDNA wavefront
+constexpr int kMaxClasses = 32; // vertex classes / refinement colours
+constexpr int kBins = 6;        // degree bins of the hash kernels
+
+// Degree bins: lanes per vertex and hash slots per vertex.  A vertex of
+// degree d goes to the first bin with d <= kBinMaxDeg; the last bin keeps its
+// table in global scratch.
+constexpr uint32_t kBinMaxDeg[kBins] = {8, 32, 128, 512, 2048, 0xFFFFFFFFu};
+
+__host__ __device__ inline int bin_of_degree(uint32_t d) {
+  int b = 0;
+  while (b < kBins - 1 && d > kBinMaxDeg[b]) ++b;
+  return b;
+}
+
+// A decided move of the local-moving or refinement phase.
+struct Mover {
+  uint32_t v;
+  uint32_t c;
+  double dq;
+};
+
+// Row view of one level of the graph: row i holds entries
+// [start[i], start[i] + len[i]) of cols / w.
+template <typename W>
+struct Rows {
+  const int64_t* start;
+  const uint32_t* len;
+  const uint32_t* cols;
+  const W* w;
+};
+
+// Counters and scalars that live on the device during one call.
+struct Ctl {
+  unsigned long long dq_fixed;       // int64 fixed-point gain sum of the iteration (2^56 scale)
+  unsigned long long moves;          // moves of the current sub-round
+  unsigned long long edges;          // edge scans of the call
+  unsigned long long total_moves;    // local-moving moves of the call
+  unsigned long long refine_moves;   // refinement moves of the call
+  unsigned int next_count;           // vertices unprocessed for the next iteration
+  unsigned int iter_count;           // vertices unprocessed at the start of this iteration
+  unsigned int cls_count[kMaxClasses];
+  unsigned int bin_count[kBins];
+  unsigned int mover_count;
+  unsigned int refined_any;          // some vertex lies in a refined bound
+  unsigned int split_count;          // vertices of split-marked communities
+  unsigned int changed;              // connected-components fixpoint flag
+  unsigned int error;                // batch validation error code
+  unsigned int touched;              // rows touched by the batch
+  unsigned int init_count;           // vertices marked affected by the batch
+  unsigned long long overflow_need;  // entries to relocate into the overflow area
+  unsigned int misc[8];
+};
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+
+// MurmurHash3 32-bit finaliser (Appleby, public domain).
+__host__ __device__ inline uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+
+// Class of vertex v in local-moving iteration t with P classes.
+__host__ __device__ inline uint32_t vertex_class(uint32_t v, uint32_t t, uint32_t P) {
+  return fmix32(v + t * 0x9e3779b9u) % P;
+}
+
+// Colour of vertex v in the R synchronous refinement rounds.
+__host__ __device__ inline uint32_t vertex_colour(uint32_t v, uint32_t R) { return fmix32(v) % R; }
+
+// Eq. 2, delta-modularity of moving a vertex i from community d to c:
+//   (K_{i->c} - K_{i->d}) / m - K_i (K_i + Sigma_c - Sigma_d) / (2 m^2),
+// with inv_m = 1/m and inv_2m2 = 1/(2 m^2) precomputed on the host.  Integer
+// parts are exact; every product and difference below is rounded on its own
+// (no contraction into fused multiply-add).
+__device__ inline double delta_q(int64_t kic, int64_t kid, int64_t ki, int64_t sc, int64_t sd, double inv_m,
+                                 double inv_2m2) {
+#pragma clang fp contract(off)
+  double a = (double)(kic - kid);
+  double b = (double)(ki + sc - sd);
+  double first = a * inv_m;
+  double kb = (double)ki * b;
+  double second = kb * inv_2m2;
+  return first - second;
+}
+
+// Gain as int64 fixed point with 2^56 scale (truncation toward zero).
+__device__ inline long long gain_fixed(double dq) {
+#pragma clang fp contract(off)
+  return (long long)(dq * 72057594037927936.0);
+}
+
+// (dq, c) order of the best-community choice: larger gain first, then lower ID.
+__device__ inline bool better(double dq, uint32_t c, double bdq, uint32_t bc) {
+  return dq > bdq || (dq == bdq && c < bc);
+}
+
+__device__ inline uint32_t slot_hash(uint32_t key, uint32_t mask) { return (key * 2654435761u ^ (key >> 15)) & mask; }
+
+// Open-addressing insert-or-add into a table of `mask + 1` slots (keys kNone
+// when free); the table always has more slots than distinct keys.
+template <typename KeyPtr, typename ValPtr>
+__device__ inline void table_add(KeyPtr keys, ValPtr vals, uint32_t mask, uint32_t key, unsigned long long w) {
+  uint32_t h = slot_hash(key, mask);
+  while (true) {
+    uint32_t k = __atomic_load_n(&keys[h], __ATOMIC_RELAXED);
+    if (k == key) {
+      atomicAdd(&vals[h], w);
+      return;
+    }
+    if (k == kNone) {
+      uint32_t o = atomicCAS(&keys[h], kNone, key);
+      if (o == kNone || o == key) {
+        atomicAdd(&vals[h], w);
+        return;
+      }
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+template <int G, typename T>
+__device__ inline T group_sum(T x) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, G);
+  return x;
+}
+
+template <int G>
+__device__ inline void group_best(double& dq, uint32_t& c) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    double odq = __shfl_xor(dq, o, G);
+    uint32_t oc = __shfl_xor(c, o, G);
+    if (better(odq, oc, dq, c)) {
+      dq = odq;
+      c = oc;
+    }
+  }
+}
+
+// Block-wide (kBlock threads) sum and best-choice through LDS.
+template <typename T>
+__device__ inline T block_sum(T x, T* red) {
+  x = group_sum<kWave>(x);
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  if (l == 0) red[w] = x;
+  __syncthreads();
+  T r = 0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < kBlock / kWave; ++i) r += red[i];
+    red[0] = r;
+  }
+  __syncthreads();
+  r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ inline void block_best(double& dq, uint32_t& c, double* rdq, uint32_t* rc) {
+  group_best<kWave>(dq, c);
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  if (l == 0) {
+    rdq[w] = dq;
+    rc[w] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < kBlock / kWave; ++i)
+      if (better(rdq[i], rc[i], rdq[0], rc[0])) {
+        rdq[0] = rdq[i];
+        rc[0] = rc[i];
+      }
+  }
+  __syncthreads();
+  dq = rdq[0];
+  c = rc[0];
+  __syncthreads();
+}
+
+// Append one item to a list with a device counter.
+__device__ inline void list_push(uint32_t* list, unsigned int* count, uint32_t v) {
+  unsigned int pos = atomicAdd(count, 1u);
+  list[pos] = v;
+}
+
+}  // namespace lm

@@ -1,0 +1,213 @@
+// Kernel parameter blocks and host launchers of the gfx950 Leiden library.
+#pragma once
+
+#include "common.h"
+
+namespace lm {
+
+template <typename W>
+struct DecideParams {
+  Rows<W> g;
+  const uint32_t* C;     // current community of each vertex
+  const int64_t* K;      // weighted degree
+  const int64_t* S;      // total weight of each community
+  const uint32_t* size;  // members of each community label
+  const uint32_t* CB;    // community bound (refinement)
+  uint32_t colour;       // refinement round
+  uint32_t R;            // refinement rounds
+  double inv_m, inv_2m2; // 1/m and 1/(2 m^2)
+  const uint32_t* list;  // vertices of this bin
+  const unsigned int* count;
+  Mover* movers;
+  Ctl* ctl;
+  uint32_t* hub_keys;  // global tables of the hub bin
+  unsigned long long* hub_vals;
+  uint32_t hub_mask;
+};
+
+struct ApplyParams {
+  const int64_t* start;
+  const uint32_t* len;
+  const uint32_t* cols;
+  uint32_t* C;
+  int64_t* S;
+  const int64_t* K;
+  uint32_t* size;
+  uint8_t* dS;  // split flags (dynamic runs) or null
+  const Mover* movers;
+  Ctl* ctl;
+  uint32_t li, P, k, stamp;
+  uint32_t* pend_mark;
+  uint32_t* unproc_mark;
+  uint32_t* cls_lists;
+  size_t cls_stride;
+  uint32_t* next_list;
+};
+
+// move.hip
+void launch_distribute(hipStream_t s, const uint32_t* in_list, const unsigned int* in_count, uint32_t n_upper,
+                       uint32_t li, uint32_t P, uint32_t stamp, uint32_t* pend_mark, uint32_t* cls_lists,
+                       size_t stride, Ctl* ctl);
+void launch_bin(hipStream_t s, const uint32_t* list, const unsigned int* count, uint32_t n_upper, const uint32_t* len,
+                const uint8_t* in_range, uint32_t* bin_lists, size_t stride, Ctl* ctl);
+template <typename W, bool REFINE>
+void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, size_t stride, unsigned int* bin_counts,
+                       const uint64_t* bin_upper, int hub_grid);
+void launch_apply_moves(hipStream_t s, const ApplyParams& p, uint32_t n_upper);
+void launch_apply_refine(hipStream_t s, uint32_t* C, int64_t* S, const int64_t* K, uint32_t* size,
+                         const Mover* movers, Ctl* ctl, uint32_t n_upper);
+void launch_subround_reset(hipStream_t s, Ctl* ctl);
+void launch_iteration_reset(hipStream_t s, Ctl* ctl, uint32_t P);
+void launch_cls_reset(hipStream_t s, Ctl* ctl);
+
+// prims.hip
+void fill_u32(hipStream_t s, uint32_t* p, uint32_t v, size_t n);
+void fill_u8(hipStream_t s, uint8_t* p, uint8_t v, size_t n);
+void fill_i64(hipStream_t s, int64_t* p, int64_t v, size_t n);
+void iota_u32(hipStream_t s, uint32_t* p, size_t n);
+// exclusive scan of n values (u32 in, u64 out); writes the total to *total (device) if non-null
+void exclusive_scan_u32(hipStream_t s, const uint32_t* in, uint64_t* out, size_t n, uint64_t* total, void* tmp);
+size_t scan_tmp_bytes(size_t n);
+void exclusive_scan_u64(hipStream_t s, const uint64_t* in, uint64_t* out, size_t n, uint64_t* total, void* tmp);
+
+// phases.hip
+void fill_u64(hipStream_t s, uint64_t* p, uint64_t v, size_t n);
+void launch_degree_hist(hipStream_t s, const uint32_t* len, uint32_t n, unsigned long long* bins_out,
+                        unsigned int* maxdeg_out);
+void launch_row_sums_u32(hipStream_t s, Rows<uint32_t> g, uint32_t n, int64_t* K);
+void launch_count_members(hipStream_t s, const uint32_t* C, uint32_t n, uint32_t* size);
+void launch_sigma_from(hipStream_t s, const uint32_t* C, const int64_t* K, uint32_t n, int64_t* S);
+
+struct RenumberBufs {
+  uint32_t* rep;
+  int64_t* S2;
+  uint32_t* size2;
+  uint8_t* dS2;
+  uint8_t* dR2;
+};
+void subset_renumber(hipStream_t s, uint32_t n, uint32_t* C, int64_t*& S, uint32_t*& size, uint8_t*& dS,
+                     uint8_t*& dR, RenumberBufs& b, Ctl* ctl);
+
+template <typename W>
+void launch_split_init(hipStream_t s, uint32_t n, const uint32_t* C, const uint8_t* dS, const uint8_t* dR,
+                       uint32_t* lab, uint32_t* list, Ctl* ctl);
+template <typename W>
+void launch_split_hook(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* lab, const uint32_t* list, Ctl* ctl,
+                       uint32_t n_upper);
+void launch_split_finish(hipStream_t s, uint32_t* C, uint32_t* lab, const uint32_t* list, Ctl* ctl, uint32_t n_upper);
+
+void launch_refine_reset(hipStream_t s, uint32_t n, uint32_t* C, uint32_t* CB, int64_t* S, const int64_t* K,
+                         uint32_t* size, const uint8_t* dR, uint32_t R, uint32_t* col_lists, size_t stride,
+                         Ctl* ctl);
+
+// dense renumber: flag (u32[n]) scratch, newid (u64[n]) scratch; returns count on device in *total
+void dense_renumber(hipStream_t s, uint32_t n, uint32_t* C, uint32_t* flag, uint64_t* newid, uint64_t* total,
+                    void* scan_tmp);
+void launch_lookup(hipStream_t s, uint32_t* Ctop, const uint32_t* C, uint32_t n);
+
+struct AggBufs {
+  uint32_t* comm_count;   // members per community
+  uint64_t* comm_off;     // member offsets (n + 1)
+  uint32_t* comm_fill;
+  uint32_t* members;
+  uint64_t* comm_deg;     // total degree per community
+  uint64_t* cap_off;      // super-row capacity offsets (n + 1)
+  uint64_t* total;        // device scalars
+  void* scan_tmp;
+  uint32_t* small_lists;  // communities per bin (small, medium, big), n each
+  uint64_t* big_cap;      // row capacity of each listed big community
+  uint64_t* tbl_off;      // global table offsets for big communities
+  uint32_t* gkeys;
+  unsigned long long* gvals;
+  size_t gcap;            // slots available in gkeys / gvals
+};
+template <typename W>
+int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t nc, AggBufs& b, int64_t* out_start,
+              uint32_t* out_len, uint32_t* out_cols, int64_t* out_w, int64_t* Kout, Ctl* ctl);
+
+void launch_static_relabel(hipStream_t s, const uint32_t* C, uint32_t n, uint32_t* minv, uint32_t* flag,
+                           uint64_t* rank, uint32_t* out, void* scan_tmp, uint64_t* total);
+
+struct ModParts {
+  unsigned long long sigma;
+  unsigned long long T_hi, T_lo;
+};
+void modularity_parts(hipStream_t s, Rows<uint32_t> g, uint32_t n, const uint32_t* C, const int64_t* K, int64_t* Sig,
+                      unsigned long long* partials, int nblocks, ModParts* out_dev);
+
+struct TrackBufs {
+  uint32_t* minv;
+  unsigned long long* hkeys;
+  long long* hvals;
+  uint64_t hmask;
+  long long* best_w;
+  uint32_t* best_vmin;
+  long long* cand_w;
+  uint32_t* cand_b;
+  uint32_t* is_old;
+  uint32_t* flag;
+  uint64_t* rank;
+  uint64_t* free_rank;
+  uint32_t* free_id;
+  uint32_t* label;
+  uint8_t* matched;
+  void* scan_tmp;
+  uint64_t* total;
+};
+void track(hipStream_t s, uint32_t n, const uint32_t* Ccur, const uint32_t* Cprev, const int64_t* K, uint32_t* out,
+           TrackBufs& b);
+
+// batch.hip
+struct BatchBufs {
+  // directed entries in arrival order (2 per undirected update)
+  uint32_t* src;
+  uint32_t* dst;
+  uint32_t* w;
+  uint32_t* is_del;
+  uint32_t* slot;      // rank of the entry inside its row segment
+  // per vertex
+  uint32_t* row_cnt;   // entries per source row (kept zero between batches)
+  uint32_t* row_idx;   // position of a touched row in `touched`
+  // per touched row
+  uint32_t* touched;
+  uint32_t* seg_cnt;
+  uint64_t* seg_off;   // nt + 1
+  uint32_t* new_len;
+  uint64_t* out_off;   // merge scratch offsets
+  // entries grouped by row and sorted by destination
+  uint32_t* seg_src;
+  uint32_t* seg_dst;
+  uint32_t* seg_w;     // deletions: weight in G^{t-1} after validation
+  uint32_t* seg_del;
+  uint32_t* seg_id;
+  uint64_t* seg_pre;   // exclusive prefix of seg_del (ne + 1)
+  uint32_t* tmp_dst;   // merge-sort scratch for long segments
+  uint32_t* tmp_w;
+  uint32_t* tmp_del;
+  // merged rows
+  uint32_t* mcols;
+  uint32_t* mw;
+  uint64_t mcap;
+  void* scan_tmp;
+  uint64_t* total;
+};
+int batch_prepare(hipStream_t s, uint32_t n, const uint32_t* del, uint64_t n_del, const uint32_t* ins, uint64_t n_ins,
+                  BatchBufs& b, Ctl* ctl, uint64_t* n_touched_host);
+int batch_validate(hipStream_t s, Rows<uint32_t> g, uint32_t n, uint64_t n_entries, uint64_t n_touched, BatchBufs& b,
+                   Ctl* ctl);
+// applies the validated batch; returns 1 if the overflow area is exhausted (nothing written)
+int batch_merge(hipStream_t s, int64_t* start, uint32_t* len, uint32_t* cap, uint32_t* cols, uint32_t* w,
+                uint64_t n_touched, BatchBufs& b, unsigned long long* edge_top, uint64_t edge_cap, Ctl* ctl);
+void launch_aux_update(hipStream_t s, const BatchBufs& b, uint64_t n_entries, const uint32_t* Cprev, int64_t* K,
+                       int64_t* S, int64_t* dSig);
+void launch_mark_communities(hipStream_t s, const BatchBufs& b, uint64_t n_entries, const uint32_t* Cprev,
+                             const int64_t* S, int64_t* dSig, uint32_t num, uint32_t den, uint8_t* dS, uint8_t* dR);
+void launch_mark_df(hipStream_t s, const BatchBufs& b, uint64_t n_entries, const uint32_t* Cprev, uint32_t* list,
+                    unsigned int* count, uint32_t* mark, uint32_t stamp);
+void launch_mark_ds(hipStream_t s, const BatchBufs& b, uint64_t n_entries, uint64_t n_touched, Rows<uint32_t> g,
+                    uint32_t n, const uint32_t* Cprev, const int64_t* K, const int64_t* S, double inv_m,
+                    double inv_2m2, uint8_t* dV, uint8_t* dE, uint8_t* dC);
+void launch_flags_to_list(hipStream_t s, const uint8_t* flags, uint32_t n, uint32_t* list, unsigned int* count,
+                          uint32_t* mark, uint32_t stamp);
+
+}  // namespace lm

@@ -1,0 +1,403 @@
+// Local-moving (Alg. 6) and refinement (Alg. 8) kernels for gfx950.
+//
+// One synchronous sub-round is: bin the active vertices by degree, decide
+// every active vertex against the current state with the degree-binned hash
+// kernels (scanCommunities / scanBounded into a per-vertex open-addressing
+// table, then the best community by Eq. 2), then apply all decided moves.
+// Lists and counters live on the device; every list kernel is a grid-stride
+// loop that reads its item count from device memory, so a sub-round needs no
+// host round trip.
+#include "kernels.h"
+
+namespace lm {
+
+// ---------------------------------------------------------------------------
+// Class distribution (start of a local-moving iteration)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_distribute(const uint32_t* in_list, const unsigned int* in_count,
+                                                       uint32_t n_all, uint32_t li, uint32_t P, uint32_t stamp,
+                                                       uint32_t* pend_mark, uint32_t* cls_lists, size_t stride,
+                                                       Ctl* ctl) {
+  __shared__ unsigned int lcount[kMaxClasses], lbase[kMaxClasses];
+  const uint32_t cnt = in_count ? *in_count : n_all;
+  for (uint32_t base = blockIdx.x * kBlock; base < cnt; base += gridDim.x * kBlock) {
+    if (threadIdx.x < kMaxClasses) lcount[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t i = base + threadIdx.x;
+    uint32_t v = 0, k = 0, pos = 0;
+    const bool ok = i < cnt;
+    if (ok) {
+      v = in_list ? in_list[i] : i;
+      k = vertex_class(v, li, P);
+      pend_mark[v] = stamp;
+      pos = atomicAdd(&lcount[k], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < P && lcount[threadIdx.x] > 0)
+      lbase[threadIdx.x] = atomicAdd(&ctl->cls_count[threadIdx.x], lcount[threadIdx.x]);
+    __syncthreads();
+    if (ok) cls_lists[(size_t)k * stride + lbase[k] + pos] = v;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Degree binning of one class list.  Vertices outside the affected range
+// (Delta-screening, first pass) and vertices without entries are processed
+// without a decision.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_bin(const uint32_t* list, const unsigned int* count,
+                                                const uint32_t* len, const uint8_t* in_range, uint32_t* bin_lists,
+                                                size_t stride, Ctl* ctl) {
+  __shared__ unsigned int lcount[kBins], lbase[kBins];
+  const uint32_t cnt = *count;
+  for (uint32_t base = blockIdx.x * kBlock; base < cnt; base += gridDim.x * kBlock) {
+    if (threadIdx.x < kBins) lcount[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t i = base + threadIdx.x;
+    uint32_t v = 0, pos = 0;
+    int b = -1;
+    if (i < cnt) {
+      v = list[i];
+      const uint32_t d = len[v];
+      if (d > 0 && (!in_range || in_range[v])) {
+        b = bin_of_degree(d);
+        pos = atomicAdd(&lcount[b], 1u);
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < kBins && lcount[threadIdx.x] > 0)
+      lbase[threadIdx.x] = atomicAdd(&ctl->bin_count[threadIdx.x], lcount[threadIdx.x]);
+    __syncthreads();
+    if (b >= 0) bin_lists[(size_t)b * stride + lbase[b] + pos] = v;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Decision kernels.  REFINE selects Alg. 8 (bounded scan, isolated movers,
+// targets that cannot move in the same colour round) instead of Alg. 6.
+// ---------------------------------------------------------------------------
+template <typename W, bool REFINE>
+__device__ inline bool allowed_target(const DecideParams<W>& p, uint32_t c) {
+  if (!REFINE) return true;
+  return p.size[c] >= 2 || vertex_colour(c, p.R) != p.colour;
+}
+
+template <typename W, bool REFINE>
+__device__ inline void emit_decision(const DecideParams<W>& p, uint32_t v, uint32_t d, double bdq, uint32_t bc) {
+  if (bc == kNone || !(bdq > 0.0)) return;
+  // two singletons of one class would swap forever: only the higher label moves
+  if (!REFINE && p.size[d] == 1 && p.size[bc] == 1 && bc > d) return;
+  const unsigned int pos = atomicAdd(&p.ctl->mover_count, 1u);
+  p.movers[pos] = Mover{v, bc, bdq};
+}
+
+// G lanes per vertex (G <= 64, groups inside one wavefront), T slots each.
+template <int G, int T, typename W, bool REFINE>
+__global__ __launch_bounds__(kBlock) void k_decide_group(DecideParams<W> p) {
+  constexpr int GPB = kBlock / G;
+  __shared__ uint32_t keys[GPB * T];
+  __shared__ unsigned long long vals[GPB * T];
+  const int g = threadIdx.x / G, lane = threadIdx.x % G;
+  uint32_t* tk = keys + g * T;
+  unsigned long long* tv = vals + g * T;
+  const uint32_t cnt = *p.count;
+  unsigned long long edges = 0;
+  for (uint32_t base = blockIdx.x * GPB; base < cnt; base += gridDim.x * GPB) {
+    const uint32_t item = base + g;
+    for (int s = lane; s < T; s += G) {
+      tk[s] = kNone;
+      tv[s] = 0;
+    }
+    __syncthreads();
+    bool valid = item < cnt;
+    uint32_t v = 0, d = 0;
+    unsigned long long kid = 0;
+    if (valid) {
+      v = p.list[item];
+      d = p.C[v];
+      if (REFINE && p.size[d] != 1) valid = false;  // no longer isolated
+    }
+    if (valid) {
+      const int64_t s0 = p.g.start[v];
+      const uint32_t L = p.g.len[v];
+      const uint32_t bnd = REFINE ? p.CB[v] : 0;
+      if (!REFINE && lane == 0) edges += L;
+      for (uint32_t e = lane; e < L; e += G) {
+        const uint32_t j = p.g.cols[s0 + e];
+        if (j == v) continue;
+        if (REFINE && p.CB[j] != bnd) continue;
+        const uint32_t c = p.C[j];
+        const unsigned long long w = (unsigned long long)p.g.w[s0 + e];
+        if (c == d)
+          kid += w;
+        else
+          table_add(tk, tv, T - 1, c, w);
+      }
+    }
+    __syncthreads();
+    kid = group_sum<G>(kid);
+    double bdq = -INFINITY;
+    uint32_t bc = kNone;
+    if (valid) {
+      const int64_t ki = p.K[v], sd = p.S[d];
+      for (int s = lane; s < T; s += G) {
+        const uint32_t c = tk[s];
+        if (c == kNone || !allowed_target<W, REFINE>(p, c)) continue;
+        const double dq = delta_q((int64_t)tv[s], (int64_t)kid, ki, p.S[c], sd, p.inv_m, p.inv_2m2);
+        if (better(dq, c, bdq, bc)) {
+          bdq = dq;
+          bc = c;
+        }
+      }
+    }
+    group_best<G>(bdq, bc);
+    if (valid && lane == 0) emit_decision<W, REFINE>(p, v, d, bdq, bc);
+    __syncthreads();
+  }
+  if (edges) atomicAdd(&p.ctl->edges, edges);
+}
+
+// One block (kBlock lanes) per vertex.  HUB keeps the T-slot table in the
+// block's region of global scratch instead of LDS (T = hub_mask + 1).
+template <int T, typename W, bool REFINE, bool HUB>
+__global__ __launch_bounds__(kBlock) void k_decide_block(DecideParams<W> p) {
+  __shared__ uint32_t lkeys[HUB ? 1 : T];
+  __shared__ unsigned long long lvals[HUB ? 1 : T];
+  __shared__ unsigned long long red[kBlock / kWave];
+  __shared__ double rdq[kBlock / kWave];
+  __shared__ uint32_t rc[kBlock / kWave];
+  uint32_t* tk = lkeys;
+  unsigned long long* tv = lvals;
+  uint32_t mask = T - 1;
+  if (HUB) {
+    mask = p.hub_mask;
+    tk = p.hub_keys + (size_t)blockIdx.x * (mask + 1);
+    tv = p.hub_vals + (size_t)blockIdx.x * (mask + 1);
+  }
+  const uint32_t cnt = *p.count;
+  unsigned long long edges = 0;
+  for (uint32_t item = blockIdx.x; item < cnt; item += gridDim.x) {
+    for (uint32_t s = threadIdx.x; s <= mask; s += kBlock) {
+      tk[s] = kNone;
+      tv[s] = 0;
+    }
+    __syncthreads();
+    const uint32_t v = p.list[item];
+    const uint32_t d = p.C[v];
+    const bool valid = !(REFINE && p.size[d] != 1);
+    unsigned long long kid = 0;
+    if (valid) {
+      const int64_t s0 = p.g.start[v];
+      const uint32_t L = p.g.len[v];
+      const uint32_t bnd = REFINE ? p.CB[v] : 0;
+      if (!REFINE && threadIdx.x == 0) edges += L;
+      for (uint32_t e = threadIdx.x; e < L; e += kBlock) {
+        const uint32_t j = p.g.cols[s0 + e];
+        if (j == v) continue;
+        if (REFINE && p.CB[j] != bnd) continue;
+        const uint32_t c = p.C[j];
+        const unsigned long long w = (unsigned long long)p.g.w[s0 + e];
+        if (c == d)
+          kid += w;
+        else
+          table_add(tk, tv, mask, c, w);
+      }
+    }
+    __syncthreads();
+    kid = block_sum(kid, red);
+    double bdq = -INFINITY;
+    uint32_t bc = kNone;
+    if (valid) {
+      const int64_t ki = p.K[v], sd = p.S[d];
+      for (uint32_t s = threadIdx.x; s <= mask; s += kBlock) {
+        const uint32_t c = tk[s];
+        if (c == kNone || !allowed_target<W, REFINE>(p, c)) continue;
+        const double dq = delta_q((int64_t)tv[s], (int64_t)kid, ki, p.S[c], sd, p.inv_m, p.inv_2m2);
+        if (better(dq, c, bdq, bc)) {
+          bdq = dq;
+          bc = c;
+        }
+      }
+    }
+    block_best(bdq, bc, rdq, rc);
+    if (valid && threadIdx.x == 0) emit_decision<W, REFINE>(p, v, d, bdq, bc);
+    __syncthreads();
+  }
+  if (edges) atomicAdd(&p.ctl->edges, edges);
+}
+
+// ---------------------------------------------------------------------------
+// Apply kernels
+// ---------------------------------------------------------------------------
+
+// Local-moving moves: one wavefront per mover.  Lane 0 moves the vertex
+// (C, Sigma, member counts, gain sum, split flag of the source community);
+// all lanes mark the neighbours: a neighbour of a later class joins that
+// class's sub-round of this iteration, any other neighbour is queued as
+// unprocessed for the next iteration.
+__global__ __launch_bounds__(kBlock) void k_apply_moves(ApplyParams p) {
+  const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const uint32_t lane = threadIdx.x % kWave;
+  const uint32_t nwaves = gridDim.x * (kBlock / kWave);
+  const uint32_t cnt = p.ctl->mover_count;
+  long long dqsum = 0;
+  for (uint32_t m = wave; m < cnt; m += nwaves) {
+    const Mover mv = p.movers[m];
+    const uint32_t v = mv.v;
+    if (lane == 0) {
+      const uint32_t d = p.C[v];
+      const long long k = p.K[v];
+      p.C[v] = mv.c;
+      atomicAdd((unsigned long long*)&p.S[d], (unsigned long long)(-k));
+      atomicAdd((unsigned long long*)&p.S[mv.c], (unsigned long long)k);
+      atomicSub(&p.size[d], 1u);
+      atomicAdd(&p.size[mv.c], 1u);
+      dqsum += gain_fixed(mv.dq);
+      if (p.dS) p.dS[d] = 1;
+    }
+    const int64_t s0 = p.start[v];
+    const uint32_t L = p.len[v];
+    for (uint32_t e = lane; e < L; e += kWave) {
+      const uint32_t j = p.cols[s0 + e];
+      const uint32_t kj = vertex_class(j, p.li, p.P);
+      if (kj > p.k) {
+        if (atomicExch(&p.pend_mark[j], p.stamp) != p.stamp)
+          list_push(p.cls_lists + (size_t)kj * p.cls_stride, &p.ctl->cls_count[kj], j);
+      } else {
+        if (atomicExch(&p.unproc_mark[j], p.stamp + 1) != p.stamp + 1) list_push(p.next_list, &p.ctl->next_count, j);
+      }
+    }
+  }
+  if (lane == 0 && dqsum != 0) atomicAdd(&p.ctl->dq_fixed, (unsigned long long)dqsum);
+  if (lane == 0 && wave == 0) atomicAdd(&p.ctl->total_moves, (unsigned long long)cnt);
+}
+
+// Refinement moves: an isolated vertex joins its chosen sub-community.
+__global__ __launch_bounds__(kBlock) void k_apply_refine(uint32_t* C, int64_t* S, const int64_t* K, uint32_t* size,
+                                                         const Mover* movers, Ctl* ctl) {
+  const uint32_t cnt = ctl->mover_count;
+  for (uint32_t m = blockIdx.x * kBlock + threadIdx.x; m < cnt; m += gridDim.x * kBlock) {
+    const Mover mv = movers[m];
+    const uint32_t d = C[mv.v];
+    const long long k = K[mv.v];
+    C[mv.v] = mv.c;
+    atomicAdd((unsigned long long*)&S[d], (unsigned long long)(-k));
+    atomicAdd((unsigned long long*)&S[mv.c], (unsigned long long)k);
+    atomicSub(&size[d], 1u);
+    atomicAdd(&size[mv.c], 1u);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctl->refine_moves, (unsigned long long)cnt);
+}
+
+__global__ void k_subround_reset(Ctl* ctl) {
+  if (threadIdx.x < kBins) ctl->bin_count[threadIdx.x] = 0;
+  if (threadIdx.x == 0) ctl->mover_count = 0;
+}
+
+// Start of an iteration: the vertices queued as unprocessed become this
+// iteration's input (the host swaps the two list buffers to match).
+__global__ void k_iteration_reset(Ctl* ctl, uint32_t P) {
+  if (threadIdx.x < kMaxClasses) ctl->cls_count[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    ctl->dq_fixed = 0;
+    ctl->iter_count = ctl->next_count;
+    ctl->next_count = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+static int grid_for(uint64_t items, int per_block, int cap) {
+  uint64_t b = (items + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > (uint64_t)cap) b = cap;
+  return (int)b;
+}
+
+void launch_distribute(hipStream_t s, const uint32_t* in_list, const unsigned int* in_count, uint32_t n_upper,
+                       uint32_t li, uint32_t P, uint32_t stamp, uint32_t* pend_mark, uint32_t* cls_lists,
+                       size_t stride, Ctl* ctl) {
+  hipLaunchKernelGGL(k_distribute, dim3(grid_for(n_upper, kBlock, 4096)), dim3(kBlock), 0, s, in_list, in_count,
+                     n_upper, li, P, stamp, pend_mark, cls_lists, stride, ctl);
+}
+
+void launch_bin(hipStream_t s, const uint32_t* list, const unsigned int* count, uint32_t n_upper, const uint32_t* len,
+                const uint8_t* in_range, uint32_t* bin_lists, size_t stride, Ctl* ctl) {
+  hipLaunchKernelGGL(k_bin, dim3(grid_for(n_upper, kBlock, 4096)), dim3(kBlock), 0, s, list, count, len, in_range,
+                     bin_lists, stride, ctl);
+}
+
+template <typename W, bool REFINE>
+void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, size_t stride, unsigned int* bin_counts,
+                       const uint64_t* bin_upper, int hub_grid) {
+  // bin 0: 8 lanes / 16 slots, bin 1: 32 / 64, bin 2: 64 / 256,
+  // bin 3: block / 1024, bin 4: block / 4096, bin 5: block / global table
+  for (int b = 0; b < kBins; ++b) {
+    if (bin_upper[b] == 0) continue;
+    DecideParams<W> q = p;
+    q.list = bin_lists + (size_t)b * stride;
+    q.count = bin_counts + b;
+    switch (b) {
+      case 0:
+        hipLaunchKernelGGL((k_decide_group<8, 16, W, REFINE>), dim3(grid_for(bin_upper[b], kBlock / 8, 2048)),
+                           dim3(kBlock), 0, s, q);
+        break;
+      case 1:
+        hipLaunchKernelGGL((k_decide_group<32, 64, W, REFINE>), dim3(grid_for(bin_upper[b], kBlock / 32, 2048)),
+                           dim3(kBlock), 0, s, q);
+        break;
+      case 2:
+        hipLaunchKernelGGL((k_decide_group<64, 256, W, REFINE>), dim3(grid_for(bin_upper[b], kBlock / 64, 2048)),
+                           dim3(kBlock), 0, s, q);
+        break;
+      case 3:
+        hipLaunchKernelGGL((k_decide_block<1024, W, REFINE, false>), dim3(grid_for(bin_upper[b], 1, 2048)),
+                           dim3(kBlock), 0, s, q);
+        break;
+      case 4:
+        hipLaunchKernelGGL((k_decide_block<4096, W, REFINE, false>), dim3(grid_for(bin_upper[b], 1, 1024)),
+                           dim3(kBlock), 0, s, q);
+        break;
+      default:
+        hipLaunchKernelGGL((k_decide_block<1, W, REFINE, true>), dim3(grid_for(bin_upper[b], 1, hub_grid)),
+                           dim3(kBlock), 0, s, q);
+        break;
+    }
+  }
+}
+
+template void launch_decide_all<uint32_t, false>(hipStream_t, DecideParams<uint32_t>, uint32_t*, size_t,
+                                                 unsigned int*, const uint64_t*, int);
+template void launch_decide_all<uint32_t, true>(hipStream_t, DecideParams<uint32_t>, uint32_t*, size_t,
+                                                unsigned int*, const uint64_t*, int);
+template void launch_decide_all<int64_t, false>(hipStream_t, DecideParams<int64_t>, uint32_t*, size_t,
+                                                unsigned int*, const uint64_t*, int);
+template void launch_decide_all<int64_t, true>(hipStream_t, DecideParams<int64_t>, uint32_t*, size_t, unsigned int*,
+                                               const uint64_t*, int);
+
+void launch_apply_moves(hipStream_t s, const ApplyParams& p, uint32_t n_upper) {
+  hipLaunchKernelGGL(k_apply_moves, dim3(grid_for(n_upper, kBlock / kWave, 2048)), dim3(kBlock), 0, s, p);
+}
+
+void launch_apply_refine(hipStream_t s, uint32_t* C, int64_t* S, const int64_t* K, uint32_t* size,
+                         const Mover* movers, Ctl* ctl, uint32_t n_upper) {
+  hipLaunchKernelGGL(k_apply_refine, dim3(grid_for(n_upper, kBlock, 2048)), dim3(kBlock), 0, s, C, S, K, size, movers,
+                     ctl);
+}
+
+void launch_subround_reset(hipStream_t s, Ctl* ctl) { hipLaunchKernelGGL(k_subround_reset, dim3(1), dim3(64), 0, s, ctl); }
+
+void launch_iteration_reset(hipStream_t s, Ctl* ctl, uint32_t P) {
+  hipLaunchKernelGGL(k_iteration_reset, dim3(1), dim3(64), 0, s, ctl, P);
+}
+
+__global__ void k_cls_reset(Ctl* ctl) {
+  if (threadIdx.x < kMaxClasses) ctl->cls_count[threadIdx.x] = 0;
+}
+
+void launch_cls_reset(hipStream_t s, Ctl* ctl) { hipLaunchKernelGGL(k_cls_reset, dim3(1), dim3(64), 0, s, ctl); }
+
+}  // namespace lm

@@ -1,0 +1,822 @@
+// Pass-level phases of Alg. 4 on gfx950: subset renumbering (Alg. 10),
+// splitting (Alg. 7), the refinement reset (Alg. 8), dense renumbering and
+// dendrogram lookup, aggregation (Alg. 9), modularity (Eq. 1), static output
+// labels and community tracking (Alg. 12).  All are O(n) or O(|E|) sweeps with
+// integer atomics, so their results do not depend on thread timing.
+#include "kernels.h"
+
+namespace lm {
+
+static int grid_n(uint64_t n, int per_block = kBlock, int cap = 8192) {
+  uint64_t b = (n + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > (uint64_t)cap) b = cap;
+  return (int)b;
+}
+
+#define GRID_STRIDE(i, n) \
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < (uint64_t)(n); i += (uint64_t)gridDim.x * kBlock)
+
+// ---------------------------------------------------------------------------
+// Per-level helpers
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_degree_hist(const uint32_t* len, uint32_t n, unsigned long long* bins,
+                                                        unsigned int* maxdeg) {
+  __shared__ unsigned int lb[kBins];
+  __shared__ unsigned int lmax;
+  if (threadIdx.x < kBins) lb[threadIdx.x] = 0;
+  if (threadIdx.x == 0) lmax = 0;
+  __syncthreads();
+  GRID_STRIDE(i, n) {
+    const uint32_t d = len[i];
+    if (d > 0) {
+      atomicAdd(&lb[bin_of_degree(d)], 1u);
+      atomicMax(&lmax, d);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kBins && lb[threadIdx.x]) atomicAdd(&bins[threadIdx.x], (unsigned long long)lb[threadIdx.x]);
+  if (threadIdx.x == 0 && lmax) atomicMax(maxdeg, lmax);
+}
+
+void launch_degree_hist(hipStream_t s, const uint32_t* len, uint32_t n, unsigned long long* bins_out,
+                        unsigned int* maxdeg_out) {
+  hipLaunchKernelGGL(k_degree_hist, dim3(grid_n(n, kBlock, 2048)), dim3(kBlock), 0, s, len, n, bins_out, maxdeg_out);
+}
+
+__global__ __launch_bounds__(kBlock) void k_row_sums(Rows<uint32_t> g, uint32_t n, int64_t* K) {
+  GRID_STRIDE(i, n) {
+    const int64_t s0 = g.start[i];
+    const uint32_t L = g.len[i];
+    int64_t k = 0;
+    for (uint32_t e = 0; e < L; ++e) k += g.w[s0 + e];
+    K[i] = k;
+  }
+}
+
+void launch_row_sums_u32(hipStream_t s, Rows<uint32_t> g, uint32_t n, int64_t* K) {
+  if (n) hipLaunchKernelGGL(k_row_sums, dim3(grid_n(n)), dim3(kBlock), 0, s, g, n, K);
+}
+
+__global__ __launch_bounds__(kBlock) void k_count_members(const uint32_t* C, uint32_t n, uint32_t* size) {
+  GRID_STRIDE(i, n) atomicAdd(&size[C[i]], 1u);
+}
+
+void launch_count_members(hipStream_t s, const uint32_t* C, uint32_t n, uint32_t* size) {
+  fill_u32(s, size, 0, n);
+  if (n) hipLaunchKernelGGL(k_count_members, dim3(grid_n(n)), dim3(kBlock), 0, s, C, n, size);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sigma_from(const uint32_t* C, const int64_t* K, uint32_t n, int64_t* S) {
+  GRID_STRIDE(i, n) atomicAdd((unsigned long long*)&S[C[i]], (unsigned long long)K[i]);
+}
+
+void launch_sigma_from(hipStream_t s, const uint32_t* C, const int64_t* K, uint32_t n, int64_t* S) {
+  fill_i64(s, S, 0, n);
+  if (n) hipLaunchKernelGGL(k_sigma_from, dim3(grid_n(n)), dim3(kBlock), 0, s, C, K, n, S);
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 10: each community takes the ID of its minimum member vertex; Sigma,
+// member counts and the split / refine flags move with the label.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_min_member(const uint32_t* C, uint32_t n, uint32_t* rep) {
+  GRID_STRIDE(i, n) atomicMin(&rep[C[i]], (uint32_t)i);
+}
+
+__global__ __launch_bounds__(kBlock) void k_move_by_label(uint32_t n, const uint32_t* rep, const int64_t* S,
+                                                          const uint32_t* size, const uint8_t* dS, const uint8_t* dR,
+                                                          int64_t* S2, uint32_t* size2, uint8_t* dS2, uint8_t* dR2,
+                                                          Ctl* ctl) {
+  unsigned int nsplit = 0, nref = 0;
+  GRID_STRIDE(c, n) {
+    const uint32_t r = rep[c];
+    if (r == kNone) continue;
+    S2[r] = S[c];
+    size2[r] = size[c];
+    dS2[r] = dS[c];
+    dR2[r] = dR[c];
+    nsplit += (dS[c] && !dR[c]) ? 1u : 0u;
+    nref += dR[c] ? 1u : 0u;
+  }
+  if (nsplit) atomicAdd(&ctl->misc[0], nsplit);
+  if (nref) atomicAdd(&ctl->misc[1], nref);
+}
+
+__global__ __launch_bounds__(kBlock) void k_relabel(uint32_t* C, uint32_t n, const uint32_t* rep) {
+  GRID_STRIDE(i, n) C[i] = rep[C[i]];
+}
+
+__global__ void k_clear_misc(Ctl* ctl) {
+  if (threadIdx.x < 8) ctl->misc[threadIdx.x] = 0;
+}
+
+void subset_renumber(hipStream_t s, uint32_t n, uint32_t* C, int64_t*& S, uint32_t*& size, uint8_t*& dS,
+                     uint8_t*& dR, RenumberBufs& b, Ctl* ctl) {
+  hipLaunchKernelGGL(k_clear_misc, dim3(1), dim3(64), 0, s, ctl);
+  if (n == 0) return;
+  fill_u32(s, b.rep, kNone, n);
+  fill_i64(s, b.S2, 0, n);
+  fill_u32(s, b.size2, 0, n);
+  fill_u8(s, b.dS2, 0, n);
+  fill_u8(s, b.dR2, 0, n);
+  hipLaunchKernelGGL(k_min_member, dim3(grid_n(n)), dim3(kBlock), 0, s, C, n, b.rep);
+  hipLaunchKernelGGL(k_move_by_label, dim3(grid_n(n)), dim3(kBlock), 0, s, n, b.rep, S, size, dS, dR, b.S2, b.size2,
+                     b.dS2, b.dR2, ctl);
+  hipLaunchKernelGGL(k_relabel, dim3(grid_n(n)), dim3(kBlock), 0, s, C, n, b.rep);
+  std::swap(S, b.S2);
+  std::swap(size, b.size2);
+  std::swap(dS, b.dS2);
+  std::swap(dR, b.dR2);
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 7 by its definition: connected components of the subgraph induced by
+// each community marked to be split and not refined, labelled by their
+// minimum vertex (hooking larger roots under smaller ones until no edge joins
+// two roots).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_split_init(uint32_t n, const uint32_t* C, const uint8_t* dS,
+                                                       const uint8_t* dR, uint32_t* lab, uint32_t* list, Ctl* ctl) {
+  GRID_STRIDE(i, n) {
+    const uint32_t c = C[i];
+    lab[i] = (uint32_t)i;
+    if (dS[c] && !dR[c]) list_push(list, &ctl->split_count, (uint32_t)i);
+  }
+}
+
+__device__ inline uint32_t find_root(uint32_t* lab, uint32_t x) {
+  while (true) {
+    const uint32_t p = __atomic_load_n(&lab[x], __ATOMIC_RELAXED);
+    if (p == x) return x;
+    x = p;
+  }
+}
+
+template <typename W>
+__global__ __launch_bounds__(kBlock) void k_split_hook(Rows<W> g, const uint32_t* C, uint32_t* lab,
+                                                       const uint32_t* list, Ctl* ctl) {
+  const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
+  const uint32_t nwaves = gridDim.x * (kBlock / kWave);
+  const uint32_t cnt = ctl->split_count;
+  bool changed = false;
+  for (uint32_t it = wave; it < cnt; it += nwaves) {
+    const uint32_t i = list[it];
+    const uint32_t c = C[i];
+    const int64_t s0 = g.start[i];
+    const uint32_t L = g.len[i];
+    for (uint32_t e = lane; e < L; e += kWave) {
+      const uint32_t j = g.cols[s0 + e];
+      if (j == i || C[j] != c) continue;
+      const uint32_t ri = find_root(lab, i), rj = find_root(lab, j);
+      if (ri != rj) {
+        atomicMin(&lab[ri > rj ? ri : rj], ri < rj ? ri : rj);
+        changed = true;
+      }
+    }
+  }
+  if (changed) ctl->changed = 1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_split_compress(uint32_t* lab, const uint32_t* list, Ctl* ctl) {
+  const uint32_t cnt = ctl->split_count;
+  GRID_STRIDE(it, cnt) {
+    const uint32_t i = list[it];
+    lab[i] = find_root(lab, i);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_split_finish(uint32_t* C, uint32_t* lab, const uint32_t* list, Ctl* ctl) {
+  const uint32_t cnt = ctl->split_count;
+  GRID_STRIDE(it, cnt) {
+    const uint32_t i = list[it];
+    C[i] = find_root(lab, i);
+  }
+}
+
+__global__ void k_reset_changed(Ctl* ctl, int also_count) {
+  if (threadIdx.x == 0) {
+    ctl->changed = 0;
+    if (also_count) ctl->split_count = 0;
+  }
+}
+
+template <typename W>
+void launch_split_init(hipStream_t s, uint32_t n, const uint32_t* C, const uint8_t* dS, const uint8_t* dR,
+                       uint32_t* lab, uint32_t* list, Ctl* ctl) {
+  hipLaunchKernelGGL(k_reset_changed, dim3(1), dim3(1), 0, s, ctl, 1);
+  if (n) hipLaunchKernelGGL(k_split_init, dim3(grid_n(n)), dim3(kBlock), 0, s, n, C, dS, dR, lab, list, ctl);
+}
+
+template <typename W>
+void launch_split_hook(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* lab, const uint32_t* list, Ctl* ctl,
+                       uint32_t n_upper) {
+  hipLaunchKernelGGL(k_reset_changed, dim3(1), dim3(1), 0, s, ctl, 0);
+  hipLaunchKernelGGL(k_split_hook<W>, dim3(grid_n(n_upper, kBlock / kWave, 4096)), dim3(kBlock), 0, s, g, C, lab,
+                     list, ctl);
+  hipLaunchKernelGGL(k_split_compress, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, lab, list, ctl);
+}
+
+void launch_split_finish(hipStream_t s, uint32_t* C, uint32_t* lab, const uint32_t* list, Ctl* ctl, uint32_t n_upper) {
+  hipLaunchKernelGGL(k_split_finish, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, C, lab, list, ctl);
+}
+
+template void launch_split_init<uint32_t>(hipStream_t, uint32_t, const uint32_t*, const uint8_t*, const uint8_t*,
+                                          uint32_t*, uint32_t*, Ctl*);
+template void launch_split_init<int64_t>(hipStream_t, uint32_t, const uint32_t*, const uint8_t*, const uint8_t*,
+                                         uint32_t*, uint32_t*, Ctl*);
+template void launch_split_hook<uint32_t>(hipStream_t, Rows<uint32_t>, const uint32_t*, uint32_t*, const uint32_t*,
+                                          Ctl*, uint32_t);
+template void launch_split_hook<int64_t>(hipStream_t, Rows<int64_t>, const uint32_t*, uint32_t*, const uint32_t*,
+                                         Ctl*, uint32_t);
+
+// ---------------------------------------------------------------------------
+// Alg. 8, first loop: vertices of refined bounds become singletons; they are
+// listed by refinement colour.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_refine_reset(uint32_t n, uint32_t* C, uint32_t* CB, int64_t* S,
+                                                         const int64_t* K, uint32_t* size, const uint8_t* dR,
+                                                         uint32_t R, uint32_t* col_lists, size_t stride, Ctl* ctl) {
+  __shared__ unsigned int lcount[kMaxClasses], lbase[kMaxClasses];
+  bool any = false;
+  for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < n; base += (uint64_t)gridDim.x * kBlock) {
+    if (threadIdx.x < kMaxClasses) lcount[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t i = base + threadIdx.x;
+    int col = -1;
+    unsigned int pos = 0;
+    if (i < n) {
+      const uint32_t b = C[i];
+      CB[i] = b;
+      if (dR[b]) {
+        C[i] = (uint32_t)i;
+        S[i] = K[i];
+        size[i] = 1;
+        any = true;
+        col = (int)vertex_colour((uint32_t)i, R);
+        pos = atomicAdd(&lcount[col], 1u);
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < R && lcount[threadIdx.x] > 0)
+      lbase[threadIdx.x] = atomicAdd(&ctl->cls_count[threadIdx.x], lcount[threadIdx.x]);
+    __syncthreads();
+    if (col >= 0) col_lists[(size_t)col * stride + lbase[col] + pos] = (uint32_t)i;
+    __syncthreads();
+  }
+  if (any) ctl->refined_any = 1;
+}
+
+void launch_refine_reset(hipStream_t s, uint32_t n, uint32_t* C, uint32_t* CB, int64_t* S, const int64_t* K,
+                         uint32_t* size, const uint8_t* dR, uint32_t R, uint32_t* col_lists, size_t stride,
+                         Ctl* ctl) {
+  if (n) hipLaunchKernelGGL(k_refine_reset, dim3(grid_n(n)), dim3(kBlock), 0, s, n, C, CB, S, K, size, dR, R,
+                            col_lists, stride, ctl);
+}
+
+// ---------------------------------------------------------------------------
+// Dense renumbering in ascending label order, and dendrogram lookup.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_flag_labels(const uint32_t* C, uint32_t n, uint32_t* flag) {
+  GRID_STRIDE(i, n) flag[C[i]] = 1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_apply_newid(uint32_t* C, uint32_t n, const uint64_t* newid) {
+  GRID_STRIDE(i, n) C[i] = (uint32_t)newid[C[i]];
+}
+
+void dense_renumber(hipStream_t s, uint32_t n, uint32_t* C, uint32_t* flag, uint64_t* newid, uint64_t* total,
+                    void* scan_tmp) {
+  fill_u32(s, flag, 0, n);
+  if (n) hipLaunchKernelGGL(k_flag_labels, dim3(grid_n(n)), dim3(kBlock), 0, s, C, n, flag);
+  exclusive_scan_u32(s, flag, newid, n, total, scan_tmp);
+  if (n) hipLaunchKernelGGL(k_apply_newid, dim3(grid_n(n)), dim3(kBlock), 0, s, C, n, newid);
+}
+
+__global__ __launch_bounds__(kBlock) void k_lookup(uint32_t* Ctop, const uint32_t* C, uint32_t n) {
+  GRID_STRIDE(i, n) Ctop[i] = C[Ctop[i]];
+}
+
+void launch_lookup(hipStream_t s, uint32_t* Ctop, const uint32_t* C, uint32_t n) {
+  if (n) hipLaunchKernelGGL(k_lookup, dim3(grid_n(n)), dim3(kBlock), 0, s, Ctop, C, n);
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 9: super-vertex graph.  w''(c, d) = sum of w_ij over entries with
+// C[i] = c, C[j] = d (self-loops included).  Communities are grouped into a
+// member CSR by counting sort; each community accumulates its neighbour
+// communities in a hash table (LDS for total degree up to 2048, a global
+// table above) and writes the distinct (d, w) pairs to its super row, whose
+// capacity is min(total degree, number of communities).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_comm_stats(const uint32_t* C, const uint32_t* len, uint32_t n,
+                                                       uint32_t* count, uint64_t* deg) {
+  GRID_STRIDE(i, n) {
+    const uint32_t c = C[i];
+    atomicAdd(&count[c], 1u);
+    atomicAdd((unsigned long long*)&deg[c], (unsigned long long)len[i]);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_comm_scatter(const uint32_t* C, uint32_t n, const uint64_t* off,
+                                                         uint32_t* fill, uint32_t* members) {
+  GRID_STRIDE(i, n) {
+    const uint32_t c = C[i];
+    members[off[c] + atomicAdd(&fill[c], 1u)] = (uint32_t)i;
+  }
+}
+
+// Row capacities and classification: 0 = small (LDS, 64 lanes, 256 slots),
+// 1 = medium (LDS, block, 4096 slots), 2 = big (global table).
+constexpr uint64_t kAggSmall = 128, kAggMedium = 2048;
+
+__global__ __launch_bounds__(kBlock) void k_comm_classify(uint32_t nc, const uint64_t* deg, uint64_t* cap,
+                                                          uint32_t* out_len, int64_t* Kout, uint32_t* lists,
+                                                          size_t stride, uint64_t* big_cap, Ctl* ctl) {
+  GRID_STRIDE(c, nc) {
+    const uint64_t d = deg[c];
+    const uint64_t cp = d < nc ? d : nc;
+    cap[c] = cp;
+    out_len[c] = 0;
+    Kout[c] = 0;
+    if (d == 0) continue;
+    const int k = d <= kAggSmall ? 0 : (d <= kAggMedium ? 1 : 2);
+    const unsigned int pos = atomicAdd(&ctl->misc[2 + k], 1u);
+    lists[(size_t)k * stride + pos] = (uint32_t)c;
+    if (k == 2) big_cap[pos] = cp;
+  }
+}
+
+// Accumulate all entries of the members of community c into table (tk, tv).
+// G lanes cooperate; members are taken G at a time and their entries are
+// flattened so every lane has work whatever the member degrees.
+template <int G, typename W, typename KP, typename VP>
+__device__ inline void agg_accumulate(Rows<W> g, const uint32_t* C, const uint32_t* members, uint64_t m0, uint64_t m1,
+                                      KP tk, VP tv, uint32_t mask, int lane, int64_t* sstart, uint32_t* spre) {
+  for (uint64_t mb = m0; mb < m1; mb += G) {
+    const uint64_t mi = mb + lane;
+    uint32_t L = 0;
+    int64_t st = 0;
+    if (mi < m1) {
+      const uint32_t v = members[mi];
+      L = g.len[v];
+      st = g.start[v];
+    }
+    if (G <= kWave) {
+      // inclusive prefix of member lengths, kept in registers; every lane runs
+      // the same number of steps so the shuffles stay converged
+      uint32_t incl = L;
+#pragma unroll
+      for (int o = 1; o < G; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, G);
+        if (lane >= o) incl += y;
+      }
+      const uint32_t total = __shfl(incl, G - 1, G);
+      for (uint32_t xb = 0; xb < total; xb += G) {
+        const uint32_t x = xb + lane;
+        // p = number of members whose inclusive prefix is <= x (binary lifting)
+        int p = 0;
+#pragma unroll
+        for (int step = G / 2; step > 0; step >>= 1) {
+          const uint32_t v = __shfl(incl, p + step - 1, G);
+          if (v <= x) p += step;
+        }
+        const uint32_t before = __shfl(incl, p > 0 ? p - 1 : 0, G);
+        const long long sp = __shfl((long long)st, p, G);
+        if (x < total) {
+          const int64_t e = sp + (x - (p > 0 ? before : 0u));
+          table_add(tk, tv, mask, C[g.cols[e]], (unsigned long long)g.w[e]);
+        }
+      }
+    } else {
+      sstart[lane] = st;
+      spre[lane] = L;
+      __syncthreads();
+      if (lane == 0)
+        for (int q = 1; q < G; ++q) spre[q] += spre[q - 1];
+      __syncthreads();
+      const uint32_t total = spre[G - 1];
+      for (uint32_t x = lane; x < total; x += G) {
+        // member p with spre[p-1] <= x < spre[p]
+        int lo = 0, hi = G - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (spre[mid] > x)
+            hi = mid;
+          else
+            lo = mid + 1;
+        }
+        const uint32_t before = lo > 0 ? spre[lo - 1] : 0;
+        const int64_t e = sstart[lo] + (x - before);
+        table_add(tk, tv, mask, C[g.cols[e]], (unsigned long long)g.w[e]);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <int G, int T, typename W>
+__global__ __launch_bounds__(kBlock) void k_agg_lds(Rows<W> g, const uint32_t* C, const uint32_t* members,
+                                                    const uint64_t* moff, const uint32_t* list, const unsigned int* count,
+                                                    const uint64_t* cap_off, uint32_t* out_len, uint32_t* out_cols,
+                                                    int64_t* out_w, int64_t* Kout) {
+  constexpr int GPB = kBlock / G;
+  __shared__ uint32_t keys[GPB * T];
+  __shared__ unsigned long long vals[GPB * T];
+  __shared__ int64_t sstart[kBlock];
+  __shared__ uint32_t spre[kBlock];
+  __shared__ unsigned int wpos[GPB];
+  __shared__ unsigned long long red[kBlock / kWave];
+  const int grp = threadIdx.x / G, lane = threadIdx.x % G;
+  uint32_t* tk = keys + grp * T;
+  unsigned long long* tv = vals + grp * T;
+  const uint32_t cnt = *count;
+  for (uint32_t base = blockIdx.x * GPB; base < cnt; base += gridDim.x * GPB) {
+    const uint32_t item = base + grp;
+    for (int s = lane; s < T; s += G) {
+      tk[s] = kNone;
+      tv[s] = 0;
+    }
+    if (lane == 0) wpos[grp] = 0;
+    __syncthreads();
+    const bool valid = item < cnt;
+    const uint32_t c = valid ? list[item] : 0;
+    const uint64_t m0 = valid ? moff[c] : 0, m1 = valid ? moff[c + 1] : 0;
+    agg_accumulate<G, W>(g, C, members, m0, m1, tk, tv, T - 1, lane, sstart + grp * G, spre + grp * G);
+    __syncthreads();
+    unsigned long long ksum = 0;
+    if (valid) {
+      const uint64_t o = cap_off[c];
+      for (int sl = lane; sl < T; sl += G) {
+        const uint32_t d = tk[sl];
+        if (d == kNone) continue;
+        const unsigned long long w = tv[sl];
+        const unsigned int p = atomicAdd(&wpos[grp], 1u);
+        out_cols[o + p] = d;
+        out_w[o + p] = (int64_t)w;
+        ksum += w;
+      }
+    }
+    if (G <= kWave)
+      ksum = group_sum<G>(ksum);
+    else
+      ksum = block_sum(ksum, red);
+    __syncthreads();
+    if (valid && lane == 0) {
+      out_len[c] = wpos[grp];
+      Kout[c] = (int64_t)ksum;
+    }
+    __syncthreads();
+  }
+}
+
+// Big communities: one block each, global table of tbl_size[c] slots.
+template <typename W>
+__global__ __launch_bounds__(kBlock) void k_agg_global(Rows<W> g, const uint32_t* C, const uint32_t* members,
+                                                       const uint64_t* moff, const uint32_t* list, uint32_t first,
+                                                       uint32_t last, const uint64_t* tbl_off, const uint64_t* tbl_mask,
+                                                       uint32_t* gkeys, unsigned long long* gvals,
+                                                       const uint64_t* cap_off, uint32_t* out_len, uint32_t* out_cols,
+                                                       int64_t* out_w, int64_t* Kout) {
+  __shared__ int64_t sstart[kBlock];
+  __shared__ uint32_t spre[kBlock];
+  __shared__ unsigned int wpos;
+  __shared__ unsigned long long red[kBlock / kWave];
+  for (uint32_t item = first + blockIdx.x; item < last; item += gridDim.x) {
+    const uint32_t c = list[item];
+    const uint64_t toff = tbl_off[item - first];
+    const uint32_t mask = (uint32_t)tbl_mask[item - first];
+    uint32_t* tk = gkeys + toff;
+    unsigned long long* tv = gvals + toff;
+    for (uint64_t sl = threadIdx.x; sl <= mask; sl += kBlock) {
+      tk[sl] = kNone;
+      tv[sl] = 0;
+    }
+    if (threadIdx.x == 0) wpos = 0;
+    __syncthreads();
+    agg_accumulate<kBlock, W>(g, C, members, moff[c], moff[c + 1], tk, tv, mask, threadIdx.x, sstart, spre);
+    __syncthreads();
+    const uint64_t o = cap_off[c];
+    unsigned long long ksum = 0;
+    for (uint64_t sl = threadIdx.x; sl <= mask; sl += kBlock) {
+      const uint32_t d = tk[sl];
+      if (d == kNone) continue;
+      const unsigned long long w = tv[sl];
+      const unsigned int p = atomicAdd(&wpos, 1u);
+      out_cols[o + p] = d;
+      out_w[o + p] = (int64_t)w;
+      ksum += w;
+    }
+    ksum = block_sum(ksum, red);
+    if (threadIdx.x == 0) {
+      out_len[c] = wpos;
+      Kout[c] = (int64_t)ksum;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_zero_misc_agg(Ctl* ctl) {
+  if (threadIdx.x < 3) ctl->misc[2 + threadIdx.x] = 0;
+}
+
+static uint64_t next_pow2(uint64_t x) {
+  uint64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+template <typename W>
+int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t nc, AggBufs& b, int64_t* out_start,
+              uint32_t* out_len, uint32_t* out_cols, int64_t* out_w, int64_t* Kout, Ctl* ctl) {
+  fill_u32(s, b.comm_count, 0, nc);
+  fill_u64(s, b.comm_deg, 0, nc);
+  hipLaunchKernelGGL(k_comm_stats, dim3(grid_n(n)), dim3(kBlock), 0, s, C, g.len, n, b.comm_count, b.comm_deg);
+  exclusive_scan_u32(s, b.comm_count, b.comm_off, nc, b.total, b.scan_tmp);
+  (void)hipMemcpyAsync(b.comm_off + nc, b.total, sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
+  fill_u32(s, b.comm_fill, 0, nc);
+  hipLaunchKernelGGL(k_comm_scatter, dim3(grid_n(n)), dim3(kBlock), 0, s, C, n, b.comm_off, b.comm_fill, b.members);
+  hipLaunchKernelGGL(k_zero_misc_agg, dim3(1), dim3(64), 0, s, ctl);
+  // capacity per community -> super-row starts
+  hipLaunchKernelGGL(k_comm_classify, dim3(grid_n(nc)), dim3(kBlock), 0, s, nc, b.comm_deg, b.cap_off, out_len, Kout,
+                     b.small_lists, (size_t)nc, b.big_cap, ctl);
+  exclusive_scan_u64(s, b.cap_off, (uint64_t*)out_start, nc, b.total, b.scan_tmp);
+  // kernel launches for small / medium communities read their counts on device
+  hipLaunchKernelGGL((k_agg_lds<64, 256, W>), dim3(grid_n(nc, kBlock / 64, 2048)), dim3(kBlock), 0, s, g, C, b.members,
+                     b.comm_off, b.small_lists, &ctl->misc[2], (const uint64_t*)out_start, out_len, out_cols, out_w,
+                     Kout);
+  hipLaunchKernelGGL((k_agg_lds<kBlock, 4096, W>), dim3(grid_n(nc, 1, 2048)), dim3(kBlock), 0, s, g, C, b.members,
+                     b.comm_off, b.small_lists + (size_t)nc, &ctl->misc[3], (const uint64_t*)out_start, out_len,
+                     out_cols, out_w, Kout);
+  // big communities: plan global tables on the host
+  unsigned int nbig = 0;
+  (void)hipMemcpyAsync(&nbig, &ctl->misc[4], sizeof(nbig), hipMemcpyDeviceToHost, s);
+  if (hipStreamSynchronize(s) != hipSuccess) return -1;
+  if (nbig == 0) return 0;
+  std::vector<uint64_t> caps(nbig);
+  (void)hipMemcpyAsync(caps.data(), b.big_cap, sizeof(uint64_t) * nbig, hipMemcpyDeviceToHost, s);
+  if (hipStreamSynchronize(s) != hipSuccess) return -1;
+  uint32_t first = 0;
+  while (first < nbig) {
+    std::vector<uint64_t> offs, masks;
+    uint64_t used = 0;
+    uint32_t last = first;
+    while (last < nbig) {
+      const uint64_t t = next_pow2(2 * caps[last]);
+      if (used + t > b.gcap && last > first) break;
+      if (t > b.gcap) return -2;
+      offs.push_back(used);
+      masks.push_back(t - 1);
+      used += t;
+      ++last;
+    }
+    (void)hipMemcpyAsync(b.tbl_off, offs.data(), sizeof(uint64_t) * offs.size(), hipMemcpyHostToDevice, s);
+    (void)hipMemcpyAsync(b.tbl_off + nbig + 1, masks.data(), sizeof(uint64_t) * masks.size(), hipMemcpyHostToDevice, s);
+    const int grid = (int)std::min<uint32_t>(last - first, 1024);
+    hipLaunchKernelGGL(k_agg_global<W>, dim3(grid), dim3(kBlock), 0, s, g, C, b.members, b.comm_off,
+                       b.small_lists + 2 * (size_t)nc, first, last, b.tbl_off, b.tbl_off + nbig + 1, b.gkeys, b.gvals,
+                       (const uint64_t*)out_start, out_len, out_cols, out_w, Kout);
+    if (hipStreamSynchronize(s) != hipSuccess) return -1;
+    first = last;
+  }
+  return 0;
+}
+
+template int aggregate<uint32_t>(hipStream_t, Rows<uint32_t>, uint32_t, const uint32_t*, uint32_t, AggBufs&, int64_t*,
+                                 uint32_t*, uint32_t*, int64_t*, int64_t*, Ctl*);
+template int aggregate<int64_t>(hipStream_t, Rows<int64_t>, uint32_t, const uint32_t*, uint32_t, AggBufs&, int64_t*,
+                                uint32_t*, uint32_t*, int64_t*, int64_t*, Ctl*);
+
+// ---------------------------------------------------------------------------
+// Static output labels: dense, ordered by each community's minimum vertex.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_min_vertex(const uint32_t* C, uint32_t n, uint32_t* minv) {
+  GRID_STRIDE(i, n) atomicMin(&minv[C[i]], (uint32_t)i);
+}
+
+__global__ __launch_bounds__(kBlock) void k_first_flag(const uint32_t* C, uint32_t n, const uint32_t* minv,
+                                                       uint32_t* flag) {
+  GRID_STRIDE(i, n) flag[i] = minv[C[i]] == (uint32_t)i ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rank_label(const uint32_t* C, uint32_t n, const uint32_t* minv,
+                                                       const uint64_t* rank, uint32_t* out) {
+  GRID_STRIDE(i, n) out[i] = (uint32_t)rank[minv[C[i]]];
+}
+
+void launch_static_relabel(hipStream_t s, const uint32_t* C, uint32_t n, uint32_t* minv, uint32_t* flag,
+                           uint64_t* rank, uint32_t* out, void* scan_tmp, uint64_t* total) {
+  if (n == 0) return;
+  fill_u32(s, minv, kNone, n);
+  hipLaunchKernelGGL(k_min_vertex, dim3(grid_n(n)), dim3(kBlock), 0, s, C, n, minv);
+  hipLaunchKernelGGL(k_first_flag, dim3(grid_n(n)), dim3(kBlock), 0, s, C, n, minv, flag);
+  exclusive_scan_u32(s, flag, rank, n, total, scan_tmp);
+  hipLaunchKernelGGL(k_rank_label, dim3(grid_n(n)), dim3(kBlock), 0, s, C, n, minv, rank, out);
+}
+
+// ---------------------------------------------------------------------------
+// Eq. 1 parts: sigma (weight of entries inside communities), Sigma_c, and
+// T = sum Sigma_c^2 as a 128-bit integer.  The host forms
+// Q = sigma / 2m - T / (2m)^2.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_mod_sigma(Rows<uint32_t> g, uint32_t n, const uint32_t* C,
+                                                      const int64_t* K, int64_t* Sig, unsigned long long* partials) {
+  __shared__ unsigned long long red[kBlock / kWave];
+  unsigned long long sig = 0;
+  GRID_STRIDE(i, n) {
+    const uint32_t c = C[i];
+    const int64_t s0 = g.start[i];
+    const uint32_t L = g.len[i];
+    for (uint32_t e = 0; e < L; ++e)
+      if (C[g.cols[s0 + e]] == c) sig += g.w[s0 + e];
+    atomicAdd((unsigned long long*)&Sig[c], (unsigned long long)K[i]);
+  }
+  sig = block_sum(sig, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = sig;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mod_square(uint32_t n, const int64_t* Sig, unsigned long long* partials) {
+  __shared__ unsigned long long rhi[kBlock], rlo[kBlock];
+  unsigned long long hi = 0, lo = 0;
+  GRID_STRIDE(c, n) {
+    const unsigned long long x = (unsigned long long)Sig[c];
+    const unsigned long long plo = x * x;
+    const unsigned long long phi = __umul64hi(x, x);
+    lo += plo;
+    hi += phi + (lo < plo ? 1ull : 0ull);
+  }
+  rhi[threadIdx.x] = hi;
+  rlo[threadIdx.x] = lo;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long H = 0, L = 0;
+    for (int t = 0; t < kBlock; ++t) {
+      L += rlo[t];
+      H += rhi[t] + (L < rlo[t] ? 1ull : 0ull);
+    }
+    partials[2 * blockIdx.x] = H;
+    partials[2 * blockIdx.x + 1] = L;
+  }
+}
+
+__global__ void k_mod_final(const unsigned long long* sig_part, const unsigned long long* sq_part, int nblocks,
+                            ModParts* out) {
+  if (threadIdx.x != 0) return;
+  unsigned long long sig = 0, H = 0, L = 0;
+  for (int b = 0; b < nblocks; ++b) {
+    sig += sig_part[b];
+    L += sq_part[2 * b + 1];
+    H += sq_part[2 * b] + (L < sq_part[2 * b + 1] ? 1ull : 0ull);
+  }
+  out->sigma = sig;
+  out->T_hi = H;
+  out->T_lo = L;
+}
+
+void modularity_parts(hipStream_t s, Rows<uint32_t> g, uint32_t n, const uint32_t* C, const int64_t* K, int64_t* Sig,
+                      unsigned long long* partials, int nblocks, ModParts* out_dev) {
+  fill_i64(s, Sig, 0, n);
+  hipLaunchKernelGGL(k_mod_sigma, dim3(nblocks), dim3(kBlock), 0, s, g, n, C, K, Sig, partials);
+  hipLaunchKernelGGL(k_mod_square, dim3(nblocks), dim3(kBlock), 0, s, n, Sig, partials + nblocks);
+  hipLaunchKernelGGL(k_mod_final, dim3(1), dim3(1), 0, s, partials, partials + nblocks, nblocks, out_dev);
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 12 by its stated purpose: exact maximum overlap (total K^t of shared
+// vertices) between old and current communities; ties go to the current
+// community with the lowest minimum vertex, then to the lowest old ID;
+// unmatched current communities take the smallest IDs that were not old
+// labels, in ascending order of their minimum vertex.
+// ---------------------------------------------------------------------------
+constexpr unsigned long long kNone64 = ~0ull;
+
+__device__ inline uint64_t pair_slot(unsigned long long key, uint64_t mask) {
+  return ((key * 0x9E3779B97F4A7C15ull) >> 17) & mask;
+}
+
+__global__ __launch_bounds__(kBlock) void k_track_pairs(uint32_t n, const uint32_t* Ccur, const uint32_t* Cprev,
+                                                        const int64_t* K, unsigned long long* hk, long long* hv,
+                                                        uint64_t mask, uint32_t* minv, uint32_t* is_old) {
+  GRID_STRIDE(i, n) {
+    const uint32_t c = Ccur[i], b = Cprev[i];
+    atomicMin(&minv[c], (uint32_t)i);
+    is_old[b] = 1;
+    const unsigned long long key = ((unsigned long long)b << 32) | c;
+    uint64_t h = pair_slot(key, mask);
+    while (true) {
+      const unsigned long long k = __atomic_load_n(&hk[h], __ATOMIC_RELAXED);
+      if (k == key) break;
+      if (k == kNone64) {
+        const unsigned long long o = atomicCAS(&hk[h], kNone64, key);
+        if (o == kNone64 || o == key) break;
+      }
+      h = (h + 1) & mask;
+    }
+    atomicAdd((unsigned long long*)&hv[h], (unsigned long long)K[i]);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_track_best_w(const unsigned long long* hk, const long long* hv,
+                                                         uint64_t slots, long long* best_w) {
+  GRID_STRIDE(sl, slots) {
+    const unsigned long long k = hk[sl];
+    if (k == kNone64) continue;
+    atomicMax(&best_w[k >> 32], hv[sl]);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_track_best_c(const unsigned long long* hk, const long long* hv,
+                                                         uint64_t slots, const long long* best_w,
+                                                         const uint32_t* minv, uint32_t* best_vmin) {
+  GRID_STRIDE(sl, slots) {
+    const unsigned long long k = hk[sl];
+    if (k == kNone64) continue;
+    const uint32_t b = (uint32_t)(k >> 32), c = (uint32_t)k;
+    if (hv[sl] == best_w[b]) atomicMin(&best_vmin[b], minv[c]);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_track_cand_w(uint32_t n, const uint32_t* Ccur, const long long* best_w,
+                                                         const uint32_t* best_vmin, long long* cand_w) {
+  GRID_STRIDE(b, n) {
+    const uint32_t vm = best_vmin[b];
+    if (vm == kNone) continue;
+    atomicMax(&cand_w[Ccur[vm]], best_w[b]);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_track_cand_b(uint32_t n, const uint32_t* Ccur, const long long* best_w,
+                                                         const uint32_t* best_vmin, const long long* cand_w,
+                                                         uint32_t* cand_b) {
+  GRID_STRIDE(b, n) {
+    const uint32_t vm = best_vmin[b];
+    if (vm == kNone) continue;
+    const uint32_t c = Ccur[vm];
+    if (best_w[b] == cand_w[c]) atomicMin(&cand_b[c], (uint32_t)b);
+  }
+}
+
+// flag[v] = v is the minimum vertex of an unmatched current community;
+// freeflag[x] = x is not an old label
+__global__ __launch_bounds__(kBlock) void k_track_flags(uint32_t n, const uint32_t* Ccur, const uint32_t* minv,
+                                                        const uint32_t* cand_b, const uint32_t* is_old, uint32_t* flag,
+                                                        uint32_t* freeflag) {
+  GRID_STRIDE(i, n) {
+    const uint32_t c = Ccur[i];
+    flag[i] = (minv[c] == (uint32_t)i && cand_b[c] == kNone) ? 1u : 0u;
+    freeflag[i] = is_old[i] ? 0u : 1u;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_track_free(uint32_t n, const uint32_t* freeflag, const uint64_t* free_rank,
+                                                       uint32_t* free_id) {
+  GRID_STRIDE(x, n) if (freeflag[x]) free_id[free_rank[x]] = (uint32_t)x;
+}
+
+__global__ __launch_bounds__(kBlock) void k_track_label(uint32_t n, const uint32_t* Ccur, const uint32_t* minv,
+                                                        const uint32_t* cand_b, const uint64_t* rank,
+                                                        const uint32_t* free_id, uint32_t* out, uint8_t* matched) {
+  GRID_STRIDE(i, n) {
+    const uint32_t c = Ccur[i];
+    const uint32_t b = cand_b[c];
+    if (b != kNone) {
+      out[i] = b;
+      matched[b] = 1;
+    } else {
+      out[i] = free_id[rank[minv[c]]];
+    }
+  }
+}
+
+void track(hipStream_t s, uint32_t n, const uint32_t* Ccur, const uint32_t* Cprev, const int64_t* K, uint32_t* out,
+           TrackBufs& b) {
+  if (n == 0) return;
+  const uint64_t slots = b.hmask + 1;
+  fill_u32(s, b.minv, kNone, n);
+  fill_u32(s, b.is_old, 0, n);
+  fill_u64(s, (uint64_t*)b.hkeys, ~0ull, slots);
+  fill_u64(s, (uint64_t*)b.hvals, 0, slots);
+  hipLaunchKernelGGL(k_track_pairs, dim3(grid_n(n)), dim3(kBlock), 0, s, n, Ccur, Cprev, K, b.hkeys, b.hvals, b.hmask,
+                     b.minv, b.is_old);
+  fill_i64(s, (int64_t*)b.best_w, -1, n);
+  fill_u32(s, b.best_vmin, kNone, n);
+  hipLaunchKernelGGL(k_track_best_w, dim3(grid_n(slots)), dim3(kBlock), 0, s, b.hkeys, b.hvals, slots, b.best_w);
+  hipLaunchKernelGGL(k_track_best_c, dim3(grid_n(slots)), dim3(kBlock), 0, s, b.hkeys, b.hvals, slots, b.best_w,
+                     b.minv, b.best_vmin);
+  fill_i64(s, (int64_t*)b.cand_w, -1, n);
+  fill_u32(s, b.cand_b, kNone, n);
+  hipLaunchKernelGGL(k_track_cand_w, dim3(grid_n(n)), dim3(kBlock), 0, s, n, Ccur, b.best_w, b.best_vmin, b.cand_w);
+  hipLaunchKernelGGL(k_track_cand_b, dim3(grid_n(n)), dim3(kBlock), 0, s, n, Ccur, b.best_w, b.best_vmin, b.cand_w,
+                     b.cand_b);
+  uint32_t* freeflag = b.label;  // scratch reuse
+  hipLaunchKernelGGL(k_track_flags, dim3(grid_n(n)), dim3(kBlock), 0, s, n, Ccur, b.minv, b.cand_b, b.is_old, b.flag,
+                     freeflag);
+  exclusive_scan_u32(s, b.flag, b.rank, n, b.total, b.scan_tmp);
+  exclusive_scan_u32(s, freeflag, b.free_rank, n, b.total, b.scan_tmp);
+  hipLaunchKernelGGL(k_track_free, dim3(grid_n(n)), dim3(kBlock), 0, s, n, freeflag, b.free_rank, b.free_id);
+  fill_u8(s, b.matched, 0, n);
+  hipLaunchKernelGGL(k_track_label, dim3(grid_n(n)), dim3(kBlock), 0, s, n, Ccur, b.minv, b.cand_b, b.rank,
+                     b.free_id, out, b.matched);
+}
+
+}  // namespace lm

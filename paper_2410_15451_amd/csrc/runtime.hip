@@ -1,0 +1,1161 @@
+// Host runtime and C-ABI of the gfx950 Leiden library: the graph handle, its
+// device workspace, and the pass loop of Alg. 4 driving the kernels.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "../../include/leiden.h"
+#include "graph.h"
+
+using namespace lm;
+
+namespace {
+
+thread_local std::string g_err;
+
+leiden_status fail(leiden_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                                   \
+  do {                                                                                                 \
+    hipError_t e_ = (expr);                                                                            \
+    if (e_ != hipSuccess) return fail(LEIDEN_EDEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                                      __FILE__, __LINE__);                                             \
+  } while (0)
+
+#define CHK(expr)                              \
+  do {                                         \
+    leiden_status s_ = (expr);                 \
+    if (s_ != LEIDEN_OK) return s_;            \
+  } while (0)
+
+// Device allocation owned by the handle; grows on demand, never shrinks.
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~Buf() {
+    if (p) (void)hipFree(p);
+  }
+  leiden_status reserve(size_t b) {
+    if (b <= bytes) return LEIDEN_OK;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    size_t want = std::max<size_t>(b, 256);
+    if (hipMalloc(&p, want) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      return fail(LEIDEN_ENOMEM, "device allocation of %zu bytes failed", want);
+    }
+    bytes = want;
+    return LEIDEN_OK;
+  }
+  template <typename T>
+  T* as() const {
+    return (T*)p;
+  }
+};
+
+uint64_t next_pow2(uint64_t x) {
+  uint64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// Eq. 2 constants from 2m, computed once per run on the host.
+struct QConst {
+  double inv_m = 0, inv_2m2 = 0;
+};
+QConst make_qconst(uint64_t M2) {
+  QConst q;
+  const double m = 0.5 * (double)M2;
+  q.inv_m = 1.0 / m;
+  q.inv_2m2 = 1.0 / ((2.0 * m) * m);
+  return q;
+}
+
+}  // namespace
+
+struct leiden_graph {
+  int device = 0;
+  hipStream_t own = nullptr;
+  uint32_t n = 0;
+  float slack = 0.2f;
+  SlackCsr g;
+  Buf b_start, b_len, b_cap, b_cols, b_w;
+  Buf b_top;  // unsigned long long bump pointer of the overflow area
+  uint64_t nnz = 0;
+  // auxiliary state (Section 3.4): C, K, Sigma, DeltaSigma
+  bool has_state = false;
+  Buf st_C, st_K, st_S, st_dS;
+  uint32_t stamp = 0;  // iteration stamp, never reused
+  // level-0 degree bins
+  uint64_t bins0[kBins] = {0};
+  uint32_t maxdeg0 = 0;
+  // workspace
+  Buf C, K, Kb, Kt, S, S2, size, size2, dS, dS2, dR, dR2, CB, rep, Ctop, pend, unproc;
+  Buf cls_lists, bin_lists, iter_list, next_list, movers, split_list, lab;
+  Buf flag, newid, scan_tmp, ctl, small;
+  Buf lvA_start, lvA_len, lvA_cols, lvA_w, lvB_start, lvB_len, lvB_cols, lvB_w;
+  Buf agg_count, agg_off, agg_fill, agg_members, agg_deg, agg_cap, agg_lists, agg_bigcap, agg_tbl, agg_keys, agg_vals;
+  Buf hub_keys, hub_vals;
+  Buf tr_minv, tr_hk, tr_hv, tr_bw, tr_bv, tr_cw, tr_cb, tr_old, tr_flag, tr_rank, tr_frank, tr_fid, tr_label,
+      tr_matched;
+  Buf dV, dE, dC, sig, partials, modparts;
+  Buf bt_src, bt_dst, bt_w, bt_del, bt_slot, bt_rowcnt, bt_rowidx, bt_touched, bt_segcnt, bt_segoff, bt_newlen,
+      bt_outoff, bt_ssrc, bt_sdst, bt_sw, bt_sdel, bt_sid, bt_spre, bt_tdst, bt_tw, bt_tdel, bt_mcols, bt_mw, bt_in;
+  Buf rb_cols, rb_w, rb_off, rb_reserve;
+  size_t ws_n = 0, ws_classes = 0;
+  uint64_t ws_nnz = 0;
+  bool rowcnt_ready = false;
+  Ctl* hctl = nullptr;  // pinned mirror
+  ~leiden_graph() {
+    if (hctl) (void)hipHostFree(hctl);
+    if (own) (void)hipStreamDestroy(own);
+  }
+};
+
+namespace {
+
+hipStream_t stream_of(leiden_graph* g, const leiden_opts* o) {
+  return (o && o->stream) ? (hipStream_t)o->stream : g->own;
+}
+
+void bind_graph(leiden_graph* G) {
+  G->g.start = G->b_start.as<int64_t>();
+  G->g.len = G->b_len.as<uint32_t>();
+  G->g.cap = G->b_cap.as<uint32_t>();
+  G->g.cols = G->b_cols.as<uint32_t>();
+  G->g.w = G->b_w.as<uint32_t>();
+}
+
+Rows<uint32_t> rows0(leiden_graph* G) { return Rows<uint32_t>{G->g.start, G->g.len, G->g.cols, G->g.w}; }
+
+// Allocate every n- and nnz-sized array a run needs.
+leiden_status ensure_workspace(leiden_graph* G, uint32_t classes) {
+  const size_t n = std::max<size_t>(G->n, 1);
+  const uint64_t nnz = std::max<uint64_t>(G->nnz, 1);
+  if (G->ws_n >= n && G->ws_nnz >= nnz && G->ws_classes >= classes) return LEIDEN_OK;
+  const size_t u32 = 4, u64 = 8;
+  CHK(G->C.reserve(n * u32));
+  CHK(G->K.reserve(n * u64));
+  CHK(G->Kb.reserve(n * u64));
+  CHK(G->Kt.reserve(n * u64));
+  CHK(G->S.reserve(n * u64));
+  CHK(G->S2.reserve(n * u64));
+  CHK(G->size.reserve(n * u32));
+  CHK(G->size2.reserve(n * u32));
+  CHK(G->dS.reserve(n));
+  CHK(G->dS2.reserve(n));
+  CHK(G->dR.reserve(n));
+  CHK(G->dR2.reserve(n));
+  CHK(G->CB.reserve(n * u32));
+  CHK(G->rep.reserve(n * u32));
+  CHK(G->Ctop.reserve(n * u32));
+  if (G->pend.bytes < n * u32) {
+    CHK(G->pend.reserve(n * u32));
+    CHK(G->unproc.reserve(n * u32));
+    HIPCHK(hipMemset(G->pend.p, 0, n * u32));
+    HIPCHK(hipMemset(G->unproc.p, 0, n * u32));
+  }
+  CHK(G->cls_lists.reserve(n * u32 * classes));
+  CHK(G->bin_lists.reserve(n * u32 * kBins));
+  CHK(G->iter_list.reserve(n * u32));
+  CHK(G->next_list.reserve(n * u32));
+  CHK(G->movers.reserve(n * sizeof(Mover)));
+  CHK(G->split_list.reserve(n * u32));
+  CHK(G->lab.reserve(n * u32));
+  CHK(G->flag.reserve(n * u32));
+  CHK(G->newid.reserve((n + 1) * u64));
+  CHK(G->scan_tmp.reserve(scan_tmp_bytes(std::max<uint64_t>(n, 2 * nnz)) + 64));
+  CHK(G->ctl.reserve(sizeof(Ctl)));
+  CHK(G->small.reserve(4096));
+  for (Buf* b : {&G->lvA_start, &G->lvB_start}) CHK(b->reserve(n * u64));
+  for (Buf* b : {&G->lvA_len, &G->lvB_len}) CHK(b->reserve(n * u32));
+  for (Buf* b : {&G->lvA_cols, &G->lvB_cols}) CHK(b->reserve(nnz * u32));
+  for (Buf* b : {&G->lvA_w, &G->lvB_w}) CHK(b->reserve(nnz * u64));
+  CHK(G->agg_count.reserve(n * u32));
+  CHK(G->agg_off.reserve((n + 1) * u64));
+  CHK(G->agg_fill.reserve(n * u32));
+  CHK(G->agg_members.reserve(n * u32));
+  CHK(G->agg_deg.reserve(n * u64));
+  CHK(G->agg_cap.reserve((n + 1) * u64));
+  CHK(G->agg_lists.reserve(3 * n * u32));
+  CHK(G->agg_bigcap.reserve(n * u64));
+  CHK(G->agg_tbl.reserve((2 * n + 2) * u64));
+  const uint64_t gcap = std::max<uint64_t>(2 * next_pow2(2 * n), 1 << 16);
+  CHK(G->agg_keys.reserve(gcap * u32));
+  CHK(G->agg_vals.reserve(gcap * u64));
+  const uint64_t hslots = next_pow2(2 * n);
+  CHK(G->tr_minv.reserve(n * u32));
+  CHK(G->tr_hk.reserve(hslots * u64));
+  CHK(G->tr_hv.reserve(hslots * u64));
+  CHK(G->tr_bw.reserve(n * u64));
+  CHK(G->tr_bv.reserve(n * u32));
+  CHK(G->tr_cw.reserve(n * u64));
+  CHK(G->tr_cb.reserve(n * u32));
+  CHK(G->tr_old.reserve(n * u32));
+  CHK(G->tr_flag.reserve(n * u32));
+  CHK(G->tr_rank.reserve(n * u64));
+  CHK(G->tr_frank.reserve(n * u64));
+  CHK(G->tr_fid.reserve(n * u32));
+  CHK(G->tr_label.reserve(n * u32));
+  CHK(G->tr_matched.reserve(n));
+  CHK(G->dV.reserve(n));
+  CHK(G->dE.reserve(n));
+  CHK(G->dC.reserve(n));
+  CHK(G->sig.reserve(n * u64));
+  CHK(G->partials.reserve(3 * 1024 * u64));
+  CHK(G->modparts.reserve(sizeof(ModParts)));
+  CHK(G->rb_reserve.reserve(n * u32));
+  CHK(G->rb_off.reserve((n + 1) * u64));
+  G->ws_n = n;
+  G->ws_nnz = nnz;
+  G->ws_classes = classes;
+  return LEIDEN_OK;
+}
+
+leiden_status ensure_hub(leiden_graph* G, uint32_t maxdeg, uint32_t* mask_out, int* grid_out) {
+  const uint64_t T = next_pow2(2 * (uint64_t)std::max<uint32_t>(maxdeg, 1));
+  const uint64_t budget = 1ull << 25;
+  int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(256, budget / T));
+  CHK(G->hub_keys.reserve(T * grid * 4));
+  CHK(G->hub_vals.reserve(T * grid * 8));
+  *mask_out = (uint32_t)(T - 1);
+  *grid_out = grid;
+  return LEIDEN_OK;
+}
+
+Ctl* dctl(leiden_graph* G) { return G->ctl.as<Ctl>(); }
+
+leiden_status read_ctl(leiden_graph* G, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(G->hctl, G->ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return LEIDEN_OK;
+}
+
+__global__ void k_zero_ctl(Ctl* c) {
+  unsigned int* p = (unsigned int*)c;
+  for (size_t i = threadIdx.x; i < sizeof(Ctl) / 4; i += blockDim.x) p[i] = 0;
+}
+
+void zero_ctl(leiden_graph* G, hipStream_t s) { hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(256), 0, s, dctl(G)); }
+
+// Degree bins (vertex counts per bin) and max degree of one level.
+leiden_status level_bins(leiden_graph* G, hipStream_t s, const uint32_t* len, uint32_t nl, uint64_t bins[kBins],
+                         uint32_t* maxdeg) {
+  unsigned long long* d = G->small.as<unsigned long long>();
+  fill_u64(s, (uint64_t*)d, 0, kBins + 1);
+  launch_degree_hist(s, len, nl, d, (unsigned int*)(d + kBins));
+  unsigned long long h[kBins + 1];
+  HIPCHK(hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int b = 0; b < kBins; ++b) bins[b] = h[b];
+  *maxdeg = (uint32_t)h[kBins];
+  return LEIDEN_OK;
+}
+
+struct RunOpts {
+  leiden_opts o;
+  bool dynamic;
+  int mode;                // for dynamic runs
+  const uint8_t* in_range; // first pass of DS, else null
+  bool init_all;           // first iteration: every vertex
+};
+
+// Mutable per-level state pointers (swapped by subset renumbering).
+struct LevelState {
+  uint32_t* C;
+  int64_t* K;
+  int64_t* S;
+  uint32_t* size;
+  uint8_t* dS;
+  uint8_t* dR;
+  RenumberBufs rb;
+};
+
+struct PassOut {
+  uint32_t iters = 0;
+  uint32_t subrounds = 0;
+  bool refined = false;
+};
+
+// Alg. 6 with the blocked synchronous schedule on one level.
+template <typename W>
+leiden_status local_move(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, LevelState& L, const RunOpts& ro,
+                         bool first_pass, double tau, const QConst& qc, const uint64_t bins[kBins], uint32_t maxdeg,
+                         PassOut& out) {
+  const uint32_t P = ro.o.move_classes;
+  Ctl* ctl = dctl(G);
+  uint32_t hub_mask = 0;
+  int hub_grid = 1;
+  if (bins[kBins - 1]) CHK(ensure_hub(G, maxdeg, &hub_mask, &hub_grid));
+  uint32_t* iter_list = G->iter_list.as<uint32_t>();
+  uint32_t* next_list = G->next_list.as<uint32_t>();
+  DecideParams<W> dp{};
+  dp.g = g;
+  dp.C = L.C;
+  dp.K = L.K;
+  dp.S = L.S;
+  dp.size = L.size;
+  dp.inv_m = qc.inv_m;
+  dp.inv_2m2 = qc.inv_2m2;
+  dp.movers = G->movers.as<Mover>();
+  dp.ctl = ctl;
+  dp.hub_keys = G->hub_keys.as<uint32_t>();
+  dp.hub_vals = G->hub_vals.as<unsigned long long>();
+  dp.hub_mask = hub_mask;
+  const uint8_t* in_range = first_pass ? ro.in_range : nullptr;
+  for (uint32_t li = 0; li < ro.o.max_iters; ++li) {
+    const uint32_t stamp = ++G->stamp;
+    launch_iteration_reset(s, ctl, P);  // moves the queued count into iter_count
+    std::swap(iter_list, next_list);
+    const bool all = li == 0 && (!first_pass || ro.init_all);
+    launch_distribute(s, all ? nullptr : iter_list, all ? nullptr : &ctl->iter_count, nl, li, P, stamp,
+                      G->pend.as<uint32_t>(), G->cls_lists.as<uint32_t>(), (size_t)nl, ctl);
+    for (uint32_t k = 0; k < P; ++k) {
+      launch_subround_reset(s, ctl);
+      launch_bin(s, G->cls_lists.as<uint32_t>() + (size_t)k * nl, &ctl->cls_count[k], nl, g.len, in_range,
+                 G->bin_lists.as<uint32_t>(), (size_t)nl, ctl);
+      launch_decide_all<W, false>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, hub_grid);
+      ApplyParams ap{};
+      ap.start = g.start;
+      ap.len = g.len;
+      ap.cols = g.cols;
+      ap.C = L.C;
+      ap.S = L.S;
+      ap.K = L.K;
+      ap.size = L.size;
+      ap.dS = ro.dynamic ? L.dS : nullptr;
+      ap.movers = G->movers.as<Mover>();
+      ap.ctl = ctl;
+      ap.li = li;
+      ap.P = P;
+      ap.k = k;
+      ap.stamp = stamp;
+      ap.pend_mark = G->pend.as<uint32_t>();
+      ap.unproc_mark = G->unproc.as<uint32_t>();
+      ap.cls_lists = G->cls_lists.as<uint32_t>();
+      ap.cls_stride = nl;
+      ap.next_list = next_list;
+      launch_apply_moves(s, ap, nl);
+    }
+    CHK(read_ctl(G, s));
+    out.iters = li + 1;
+    for (uint32_t k = 0; k < P; ++k) out.subrounds += G->hctl->cls_count[k] ? 1 : 0;
+    const double dq = (double)(long long)G->hctl->dq_fixed / 72057594037927936.0;
+    if (dq <= tau) break;
+  }
+  // the last iteration queued vertices under stamp + 1; never hand that value out again
+  ++G->stamp;
+  return LEIDEN_OK;
+}
+
+// Alg. 8 with R colour rounds on one level (after subset renumbering / split).
+template <typename W>
+leiden_status refine(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, LevelState& L, const RunOpts& ro,
+                     const QConst& qc, const uint64_t bins[kBins], uint32_t maxdeg) {
+  const uint32_t R = ro.o.refine_rounds;
+  Ctl* ctl = dctl(G);
+  uint32_t hub_mask = 0;
+  int hub_grid = 1;
+  if (bins[kBins - 1]) CHK(ensure_hub(G, maxdeg, &hub_mask, &hub_grid));
+  launch_cls_reset(s, ctl);
+  launch_refine_reset(s, nl, L.C, G->CB.as<uint32_t>(), L.S, L.K, L.size, L.dR, R, G->cls_lists.as<uint32_t>(),
+                      (size_t)nl, ctl);
+  DecideParams<W> dp{};
+  dp.g = g;
+  dp.C = L.C;
+  dp.K = L.K;
+  dp.S = L.S;
+  dp.size = L.size;
+  dp.CB = G->CB.as<uint32_t>();
+  dp.R = R;
+  dp.inv_m = qc.inv_m;
+  dp.inv_2m2 = qc.inv_2m2;
+  dp.movers = G->movers.as<Mover>();
+  dp.ctl = ctl;
+  dp.hub_keys = G->hub_keys.as<uint32_t>();
+  dp.hub_vals = G->hub_vals.as<unsigned long long>();
+  dp.hub_mask = hub_mask;
+  for (uint32_t r = 0; r < R; ++r) {
+    launch_subround_reset(s, ctl);
+    launch_bin(s, G->cls_lists.as<uint32_t>() + (size_t)r * nl, &ctl->cls_count[r], nl, g.len, nullptr,
+               G->bin_lists.as<uint32_t>(), (size_t)nl, ctl);
+    dp.colour = r;
+    launch_decide_all<W, true>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, hub_grid);
+    launch_apply_refine(s, L.C, L.S, L.K, L.size, G->movers.as<Mover>(), ctl, nl);
+  }
+  return LEIDEN_OK;
+}
+
+template <typename W>
+leiden_status split(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, LevelState& L) {
+  Ctl* ctl = dctl(G);
+  uint32_t* lab = G->lab.as<uint32_t>();
+  uint32_t* list = G->split_list.as<uint32_t>();
+  launch_split_init<W>(s, nl, L.C, L.dS, L.dR, lab, list, ctl);
+  for (int it = 0; it < 64; ++it) {
+    launch_split_hook<W>(s, g, L.C, lab, list, ctl, nl);
+    CHK(read_ctl(G, s));
+    if (!G->hctl->changed) break;
+    if (it == 63) return fail(LEIDEN_EDEVICE, "split did not converge");
+  }
+  launch_split_finish(s, L.C, lab, list, ctl, nl);
+  return LEIDEN_OK;
+}
+
+// One pass of Alg. 4 on level graph g; returns whether the pass loop stops.
+template <typename W>
+leiden_status run_pass(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, LevelState& L, const RunOpts& ro,
+                       uint32_t pass, double tau, const QConst& qc, const uint64_t bins[kBins], uint32_t maxdeg,
+                       leiden_stats* st, bool* stop) {
+  PassOut po;
+  CHK(local_move<W>(G, s, g, nl, L, ro, pass == 0, tau, qc, bins, maxdeg, po));
+  if (st && pass < 16) st->iters[pass] = po.iters, st->subrounds[pass] = po.subrounds;
+  subset_renumber(s, nl, L.C, L.S, L.size, L.dS, L.dR, L.rb, dctl(G));
+  CHK(read_ctl(G, s));
+  const uint32_t nsplit = G->hctl->misc[0], nref = G->hctl->misc[1];
+  if (nsplit > 0) CHK(split<W>(G, s, g, nl, L));
+  if (st && pass == 0) st->split_marked = nsplit;
+  const bool refined = nref > 0;
+  if (refined) CHK(refine<W>(G, s, g, nl, L, ro, qc, bins, maxdeg));
+  if (st && pass == 0) st->refined_first_pass = refined ? 1 : 0;
+  *stop = (po.iters <= 1 && !refined) || (po.iters <= 1 && pass > 0);
+  return LEIDEN_OK;
+}
+
+// Aggregate level g (labels L.C renumbered densely) into the next level.
+template <typename W>
+leiden_status next_level(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, LevelState& L, bool useA,
+                         Rows<int64_t>* out, uint32_t* nc_out) {
+  uint64_t* total = G->small.as<uint64_t>() + 64;
+  dense_renumber(s, nl, L.C, G->flag.as<uint32_t>(), G->newid.as<uint64_t>(), total, G->scan_tmp.p);
+  uint64_t nc = 0;
+  HIPCHK(hipMemcpyAsync(&nc, total, sizeof(nc), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  launch_lookup(s, G->Ctop.as<uint32_t>(), L.C, G->n);
+  Buf& bs = useA ? G->lvA_start : G->lvB_start;
+  Buf& bl = useA ? G->lvA_len : G->lvB_len;
+  Buf& bc = useA ? G->lvA_cols : G->lvB_cols;
+  Buf& bw = useA ? G->lvA_w : G->lvB_w;
+  AggBufs ab{};
+  ab.comm_count = G->agg_count.as<uint32_t>();
+  ab.comm_off = G->agg_off.as<uint64_t>();
+  ab.comm_fill = G->agg_fill.as<uint32_t>();
+  ab.members = G->agg_members.as<uint32_t>();
+  ab.comm_deg = G->agg_deg.as<uint64_t>();
+  ab.cap_off = G->agg_cap.as<uint64_t>();
+  ab.total = total;
+  ab.scan_tmp = G->scan_tmp.p;
+  ab.small_lists = G->agg_lists.as<uint32_t>();
+  ab.big_cap = G->agg_bigcap.as<uint64_t>();
+  ab.tbl_off = G->agg_tbl.as<uint64_t>();
+  ab.gkeys = G->agg_keys.as<uint32_t>();
+  ab.gvals = G->agg_vals.as<unsigned long long>();
+  ab.gcap = G->agg_keys.bytes / 4;
+  // K of the next level goes to whichever of the two K buffers is not current
+  int64_t* Kn = L.K == G->K.as<int64_t>() ? G->Kb.as<int64_t>() : G->K.as<int64_t>();
+  int rc = aggregate<W>(s, g, nl, L.C, (uint32_t)nc, ab, bs.as<int64_t>(), bl.as<uint32_t>(), bc.as<uint32_t>(),
+                        bw.as<int64_t>(), Kn, dctl(G));
+  if (rc != 0) return fail(LEIDEN_EDEVICE, "aggregation failed (%d)", rc);
+  // K' = Sigma' = weight of each super-vertex; C' = identity; all refined; none split
+  HIPCHK(hipMemcpyAsync(L.S, Kn, sizeof(int64_t) * nc, hipMemcpyDeviceToDevice, s));
+  L.K = Kn;
+  fill_u32(s, L.size, 1, nc);
+  iota_u32(s, L.C, nc);
+  fill_u8(s, L.dR, 1, nc);
+  fill_u8(s, L.dS, 0, nc);
+  *out = Rows<int64_t>{bs.as<int64_t>(), bl.as<uint32_t>(), bc.as<uint32_t>(), bw.as<int64_t>()};
+  *nc_out = (uint32_t)nc;
+  return LEIDEN_OK;
+}
+
+// Alg. 4 over all levels.  On entry L holds C^{t-1} (identity for static
+// runs), K^t, Sigma^t, the split / refine flags, and (dynamic DF / DS) the
+// first unprocessed list queued in next_list.  On exit Ctop holds C.
+leiden_status run_leiden(leiden_graph* G, hipStream_t s, LevelState& L, const RunOpts& ro, uint64_t M2,
+                         leiden_stats* st) {
+  const uint32_t n = G->n;
+  iota_u32(s, G->Ctop.as<uint32_t>(), n);
+  if (M2 == 0 || n == 0) {  // no edges: every vertex stays alone
+    iota_u32(s, L.C, n);
+    return LEIDEN_OK;
+  }
+  const QConst qc = make_qconst(M2);
+  launch_count_members(s, L.C, n, L.size);
+  double tau = ro.o.tau;
+  uint64_t bins[kBins];
+  for (int b = 0; b < kBins; ++b) bins[b] = G->bins0[b];
+  uint32_t maxdeg = G->maxdeg0;
+  Rows<int64_t> cur{};
+  uint32_t nl = n;
+  bool useA = true;
+  uint32_t pass = 0;
+  for (; pass < ro.o.max_passes; ++pass) {
+    bool stop = false;
+    if (pass == 0)
+      CHK(run_pass<uint32_t>(G, s, rows0(G), nl, L, ro, pass, tau, qc, bins, maxdeg, st, &stop));
+    else
+      CHK(run_pass<int64_t>(G, s, cur, nl, L, ro, pass, tau, qc, bins, maxdeg, st, &stop));
+    if (stop) break;
+    Rows<int64_t> nxt{};
+    uint32_t nc = 0;
+    if (pass == 0)
+      CHK(next_level<uint32_t>(G, s, rows0(G), nl, L, useA, &nxt, &nc));
+    else
+      CHK(next_level<int64_t>(G, s, cur, nl, L, useA, &nxt, &nc));
+    cur = nxt;
+    nl = nc;
+    useA = !useA;
+    CHK(level_bins(G, s, cur.len, nl, bins, &maxdeg));
+    tau = tau / (double)ro.o.tol_decline;
+  }
+  if (st) st->passes = pass < ro.o.max_passes ? pass + 1 : ro.o.max_passes;
+  launch_lookup(s, G->Ctop.as<uint32_t>(), L.C, n);
+  return LEIDEN_OK;
+}
+
+LevelState level_state(leiden_graph* G) {
+  LevelState L;
+  L.C = G->C.as<uint32_t>();
+  L.K = G->K.as<int64_t>();
+  L.S = G->S.as<int64_t>();
+  L.size = G->size.as<uint32_t>();
+  L.dS = G->dS.as<uint8_t>();
+  L.dR = G->dR.as<uint8_t>();
+  L.rb.rep = G->rep.as<uint32_t>();
+  L.rb.S2 = G->S2.as<int64_t>();
+  L.rb.size2 = G->size2.as<uint32_t>();
+  L.rb.dS2 = G->dS2.as<uint8_t>();
+  L.rb.dR2 = G->dR2.as<uint8_t>();
+  return L;
+}
+
+leiden_status check_opts(const leiden_opts& o) {
+  if (o.move_classes < 1 || o.move_classes > (uint32_t)kMaxClasses)
+    return fail(LEIDEN_EINVAL, "move_classes must be in 1..%d", kMaxClasses);
+  if (o.refine_rounds < 1 || o.refine_rounds > (uint32_t)kMaxClasses)
+    return fail(LEIDEN_EINVAL, "refine_rounds must be in 1..%d", kMaxClasses);
+  if (o.tau_re_den == 0 || o.tol_decline == 0 || o.max_iters == 0)
+    return fail(LEIDEN_EINVAL, "tau_re_den, tol_decline and max_iters must be > 0");
+  if (!(o.tau >= 0.0)) return fail(LEIDEN_EINVAL, "tau must be >= 0");
+  if (!o.deterministic) return fail(LEIDEN_EINVAL, "only the deterministic schedule is available");
+  return LEIDEN_OK;
+}
+
+leiden_status modularity_of(leiden_graph* G, hipStream_t s, const uint32_t* C, const int64_t* K, double* q) {
+  const int nb = 1024;
+  ModParts* mp = G->modparts.as<ModParts>();
+  modularity_parts(s, rows0(G), G->n, C, K, G->sig.as<int64_t>(), G->partials.as<unsigned long long>(), nb, mp);
+  unsigned long long* m2d = G->small.as<unsigned long long>() + 128;
+  sum_i64(s, K, G->n, m2d);
+  ModParts h;
+  unsigned long long M2 = 0;
+  HIPCHK(hipMemcpyAsync(&h, mp, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&M2, m2d, sizeof(M2), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (M2 == 0) {
+    *q = 0.0;
+    return LEIDEN_OK;
+  }
+  const unsigned __int128 T = ((unsigned __int128)h.T_hi << 64) | h.T_lo;
+  const double m2 = (double)M2;
+  const double first = (double)h.sigma / m2;
+  const double second = (double)T / (m2 * m2);
+  *q = first - second;
+  return LEIDEN_OK;
+}
+
+leiden_status copy_out(hipStream_t s, void* dst, const void* src, size_t bytes, int on_device) {
+  if (!dst || !bytes) return LEIDEN_OK;
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+  return LEIDEN_OK;
+}
+
+leiden_status copy_in(hipStream_t s, void* dst, const void* src, size_t bytes, int on_device) {
+  if (!bytes) return LEIDEN_OK;
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+  return LEIDEN_OK;
+}
+
+// Rebuild the slack CSR so every row has room for `reserve` entries (or its
+// current length when reserve is null), with fresh per-row slack.
+leiden_status rebuild(leiden_graph* G, hipStream_t s, const uint32_t* reserve) {
+  const uint32_t n = G->n;
+  uint64_t* total = G->small.as<uint64_t>() + 200;
+  CHK(G->rb_off.reserve((uint64_t)(n + 1) * 8));
+  rebuild_caps(s, n, G->g.len, reserve, G->slack, G->g.cap, G->rb_off.as<uint64_t>(), G->scan_tmp.p, total);
+  uint64_t tot = 0;
+  HIPCHK(hipMemcpyAsync(&tot, total, sizeof(tot), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const uint64_t cap = tot + tot / 8 + 4096;
+  Buf nc, nw;
+  CHK(nc.reserve(cap * 4));
+  CHK(nw.reserve(cap * 4));
+  copy_rows(s, n, G->g.start, G->g.len, G->g.cols, G->g.w, G->rb_off.as<uint64_t>(), nc.as<uint32_t>(),
+            nw.as<uint32_t>(), G->g.start);
+  unsigned long long top = tot;
+  HIPCHK(hipMemcpyAsync(G->b_top.p, &top, sizeof(top), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::swap(G->b_cols.p, nc.p);
+  std::swap(G->b_cols.bytes, nc.bytes);
+  std::swap(G->b_w.p, nw.p);
+  std::swap(G->b_w.bytes, nw.bytes);
+  bind_graph(G);
+  G->g.edge_cap = cap;
+  return LEIDEN_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+extern "C" {
+
+leiden_status leiden_default_opts(leiden_opts* o) {
+  if (!o) return fail(LEIDEN_EINVAL, "null opts");
+  o->tau = 1e-2;
+  o->tau_re_num = 3;
+  o->tau_re_den = 5;
+  o->tol_decline = 10;
+  o->max_iters = 20;
+  o->max_passes = 10;
+  o->move_classes = 8;
+  o->refine_rounds = 8;
+  o->deterministic = 1;
+  o->compute_modularity = 1;
+  o->stream = nullptr;
+  return LEIDEN_OK;
+}
+
+const char* leiden_last_error(void) { return g_err.c_str(); }
+
+leiden_status leiden_graph_create(int device, uint32_t n, uint64_t nnz, const int64_t* offsets, const uint32_t* cols,
+                                  const uint32_t* w, int on_device, double slack, leiden_graph** out) {
+  g_err.clear();
+  if (!out) return fail(LEIDEN_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!offsets || (nnz && (!cols || !w))) return fail(LEIDEN_EINVAL, "null CSR arrays");
+  if (!(slack >= 0.0) || slack > 64.0) return fail(LEIDEN_EINVAL, "slack must be in [0, 64]");
+  if (n == 0xFFFFFFFFu) return fail(LEIDEN_EINVAL, "n too large");
+  int ndev = 0;
+  HIPCHK(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(LEIDEN_EINVAL, "no device %d", device);
+  HIPCHK(hipSetDevice(device));
+  leiden_graph* G = new leiden_graph();
+  G->device = device;
+  G->n = n;
+  G->slack = (float)slack;
+  G->nnz = nnz;
+  auto bail = [&](leiden_status st) {
+    delete G;
+    return st;
+  };
+  if (hipStreamCreateWithFlags(&G->own, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(LEIDEN_EDEVICE, "stream creation failed"));
+  if (hipHostMalloc((void**)&G->hctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess)
+    return bail(fail(LEIDEN_EDEVICE, "pinned allocation failed"));
+  hipStream_t s = G->own;
+  leiden_status st;
+  // upload the input CSR
+  Buf in_offs, in_cols, in_w;
+  if ((st = in_offs.reserve((uint64_t)(n + 1) * 8)) || (st = in_cols.reserve(nnz * 4)) ||
+      (st = in_w.reserve(nnz * 4)))
+    return bail(st);
+  auto up = [&](void* d, const void* h, size_t b) {
+    return hipMemcpyAsync(d, h, b, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
+  };
+  if (up(in_offs.p, offsets, (uint64_t)(n + 1) * 8) != hipSuccess || (nnz && up(in_cols.p, cols, nnz * 4) != hipSuccess) ||
+      (nnz && up(in_w.p, w, nnz * 4) != hipSuccess))
+    return bail(fail(LEIDEN_EDEVICE, "input copy failed"));
+  if ((st = G->small.reserve(4096)) || (st = G->ctl.reserve(sizeof(Ctl)))) return bail(st);
+  const unsigned int err = csr_check(s, n, nnz, in_offs.as<int64_t>(), in_cols.as<uint32_t>(), in_w.as<uint32_t>(),
+                                     (unsigned int*)G->small.p);
+  if (err & 0x80000000u) return bail(fail(LEIDEN_EDEVICE, "input check failed"));
+  if (err & 16) return bail(fail(LEIDEN_EINVAL, "offsets must start at 0, end at nnz and not decrease"));
+  if (err & 1) return bail(fail(LEIDEN_EINVAL, "column out of range, self-loop or zero weight"));
+  if (err & 2) return bail(fail(LEIDEN_EINVAL, "rows must be sorted without duplicate columns"));
+  if (err & 4) return bail(fail(LEIDEN_EINVAL, "matrix is not symmetric (missing or unequal reverse entry)"));
+  // slack layout
+  const size_t nn = std::max<size_t>(n, 1);
+  if ((st = G->b_start.reserve(nn * 8)) || (st = G->b_len.reserve(nn * 4)) || (st = G->b_cap.reserve(nn * 4)) ||
+      (st = G->b_top.reserve(8)) || (st = G->rb_off.reserve((nn + 1) * 8)) ||
+      (st = G->scan_tmp.reserve(scan_tmp_bytes(std::max<uint64_t>(nn, 2 * nnz)) + 64)))
+    return bail(st);
+  bind_graph(G);
+  uint64_t* total = G->small.as<uint64_t>() + 200;
+  caps_from_csr(s, n, in_offs.as<int64_t>(), G->slack, G->g, G->rb_off.as<uint64_t>(), G->scan_tmp.p, total);
+  uint64_t tot = 0;
+  if (hipMemcpyAsync(&tot, total, 8, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+    return bail(fail(LEIDEN_EDEVICE, "layout failed"));
+  const uint64_t cap = tot + tot / 8 + 4096;
+  if ((st = G->b_cols.reserve(cap * 4)) || (st = G->b_w.reserve(cap * 4))) return bail(st);
+  bind_graph(G);
+  G->g.edge_cap = cap;
+  copy_rows(s, n, in_offs.as<int64_t>(), G->g.len, in_cols.as<uint32_t>(), in_w.as<uint32_t>(),
+            G->rb_off.as<uint64_t>(), G->g.cols, G->g.w, G->g.start);
+  unsigned long long top = tot;
+  if (hipMemcpyAsync(G->b_top.p, &top, 8, hipMemcpyHostToDevice, s) != hipSuccess) return bail(fail(LEIDEN_EDEVICE, "copy"));
+  G->bins0[0] = 0;
+  if ((st = level_bins(G, s, G->g.len, n, G->bins0, &G->maxdeg0))) return bail(st);
+  if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(LEIDEN_EDEVICE, "graph creation failed"));
+  *out = G;
+  return LEIDEN_OK;
+}
+
+void leiden_graph_destroy(leiden_graph* g) {
+  if (!g) return;
+  (void)hipSetDevice(g->device);
+  (void)hipStreamSynchronize(g->own);
+  delete g;
+}
+
+leiden_status leiden_graph_nnz(leiden_graph* g, uint64_t* nnz) {
+  if (!g || !nnz) return fail(LEIDEN_EINVAL, "null argument");
+  *nnz = g->nnz;
+  return LEIDEN_OK;
+}
+
+leiden_status leiden_static(leiden_graph* G, const leiden_opts* opts, uint32_t* membership_out, int out_on_device,
+                            double* q_out, leiden_stats* stats) {
+  g_err.clear();
+  if (!G) return fail(LEIDEN_EINVAL, "null handle");
+  leiden_opts o;
+  leiden_default_opts(&o);
+  if (opts) o = *opts;
+  CHK(check_opts(o));
+  HIPCHK(hipSetDevice(G->device));
+  hipStream_t s = stream_of(G, opts);
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  CHK(ensure_workspace(G, std::max(o.move_classes, o.refine_rounds)));
+  hipEvent_t e0, e1, e2;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventCreate(&e2));
+  HIPCHK(hipEventRecord(e0, s));
+  const uint32_t n = G->n;
+  zero_ctl(G, s);
+  LevelState L = level_state(G);
+  launch_row_sums_u32(s, rows0(G), n, L.K);
+  HIPCHK(hipMemcpyAsync(L.S, L.K, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s));
+  iota_u32(s, L.C, n);
+  fill_u8(s, L.dR, 1, n);
+  fill_u8(s, L.dS, 0, n);
+  unsigned long long* m2d = G->small.as<unsigned long long>() + 128;
+  sum_i64(s, L.K, n, m2d);
+  unsigned long long M2 = 0;
+  HIPCHK(hipMemcpyAsync(&M2, m2d, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  RunOpts ro{o, false, 0, nullptr, true};
+  CHK(run_leiden(G, s, L, ro, M2, stats));
+  // dense output labels by minimum vertex; new state (C, K, Sigma, DeltaSigma = 0)
+  CHK(G->st_C.reserve((size_t)std::max<uint32_t>(n, 1) * 4));
+  CHK(G->st_K.reserve((size_t)std::max<uint32_t>(n, 1) * 8));
+  CHK(G->st_S.reserve((size_t)std::max<uint32_t>(n, 1) * 8));
+  CHK(G->st_dS.reserve((size_t)std::max<uint32_t>(n, 1) * 8));
+  uint32_t* out = G->st_C.as<uint32_t>();
+  launch_static_relabel(s, G->Ctop.as<uint32_t>(), n, G->tr_minv.as<uint32_t>(), G->flag.as<uint32_t>(),
+                        G->newid.as<uint64_t>(), out, G->scan_tmp.p, G->small.as<uint64_t>() + 64);
+  launch_row_sums_u32(s, rows0(G), n, G->st_K.as<int64_t>());
+  launch_sigma_from(s, out, G->st_K.as<int64_t>(), n, G->st_S.as<int64_t>());
+  fill_i64(s, G->st_dS.as<int64_t>(), 0, n);
+  G->has_state = true;
+  HIPCHK(hipEventRecord(e1, s));
+  double q = std::numeric_limits<double>::quiet_NaN();
+  if (o.compute_modularity) CHK(modularity_of(G, s, out, G->st_K.as<int64_t>(), &q));
+  HIPCHK(hipEventRecord(e2, s));
+  CHK(copy_out(s, membership_out, out, sizeof(uint32_t) * n, out_on_device));
+  HIPCHK(hipStreamSynchronize(s));
+  if (q_out) *q_out = q;
+  if (stats) {
+    CHK(read_ctl(G, s));
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e2);
+    stats->ms_total = ms;
+    (void)hipEventElapsedTime(&ms, e1, e2);
+    stats->ms_modularity = ms;
+    stats->affected = n;
+    stats->moves = G->hctl->total_moves;
+    stats->refine_moves = G->hctl->refine_moves;
+    stats->edges_scanned = G->hctl->edges;
+    stats->nnz = G->nnz;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(e2);
+  return LEIDEN_OK;
+}
+
+leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del, const uint32_t* ins,
+                            uint64_t n_ins, int batch_on_device, const uint32_t* prev_membership, int prev_on_device,
+                            leiden_mode mode, const leiden_opts* opts, uint32_t* membership_out, int out_on_device,
+                            double* q_out, leiden_stats* stats) {
+  g_err.clear();
+  if (!G) return fail(LEIDEN_EINVAL, "null handle");
+  if (mode != LEIDEN_ND && mode != LEIDEN_DS && mode != LEIDEN_DF) return fail(LEIDEN_EINVAL, "unknown mode");
+  if ((n_del && !del) || (n_ins && !ins)) return fail(LEIDEN_EINVAL, "null batch arrays");
+  leiden_opts o;
+  leiden_default_opts(&o);
+  if (opts) o = *opts;
+  CHK(check_opts(o));
+  if (!G->has_state && !prev_membership)
+    return fail(LEIDEN_ESTATE, "no previous memberships: run leiden_static or pass prev_membership");
+  HIPCHK(hipSetDevice(G->device));
+  hipStream_t s = stream_of(G, opts);
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  const uint32_t n = G->n;
+  CHK(ensure_workspace(G, std::max(o.move_classes, o.refine_rounds)));
+  CHK(G->st_C.reserve((size_t)std::max<uint32_t>(n, 1) * 4));
+  CHK(G->st_K.reserve((size_t)std::max<uint32_t>(n, 1) * 8));
+  CHK(G->st_S.reserve((size_t)std::max<uint32_t>(n, 1) * 8));
+  CHK(G->st_dS.reserve((size_t)std::max<uint32_t>(n, 1) * 8));
+  // batch buffers
+  const uint64_t nb = n_del + n_ins, ne = 2 * nb;
+  const size_t nn = std::max<size_t>(n, 1), nE = std::max<uint64_t>(ne, 1);
+  CHK(G->bt_in.reserve((2 * n_del + 3 * n_ins + 1) * 4));
+  for (Buf* b : {&G->bt_src, &G->bt_dst, &G->bt_w, &G->bt_del, &G->bt_slot, &G->bt_ssrc, &G->bt_sdst, &G->bt_sw,
+                 &G->bt_sdel, &G->bt_sid, &G->bt_tdst, &G->bt_tw, &G->bt_tdel, &G->bt_touched, &G->bt_segcnt,
+                 &G->bt_newlen})
+    CHK(b->reserve(nE * 4));
+  CHK(G->bt_segoff.reserve((nE + 1) * 8));
+  CHK(G->bt_outoff.reserve((nE + 1) * 8));
+  CHK(G->bt_spre.reserve((nE + 1) * 8));
+  if (!G->rowcnt_ready) {
+    CHK(G->bt_rowcnt.reserve(nn * 4));
+    CHK(G->bt_rowidx.reserve(nn * 4));
+    HIPCHK(hipMemset(G->bt_rowcnt.p, 0, nn * 4));
+    G->rowcnt_ready = true;
+  }
+  CHK(G->scan_tmp.reserve(scan_tmp_bytes(std::max<uint64_t>(nn, nE)) + 64));
+  hipEvent_t e0, e1, e2, e3;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventCreate(&e2));
+  HIPCHK(hipEventCreate(&e3));
+  HIPCHK(hipEventRecord(e0, s));
+  zero_ctl(G, s);
+  // previous memberships: validate and compare with the handle's state
+  uint32_t* Cprev = G->st_C.as<uint32_t>();
+  bool restart = !G->has_state;
+  if (prev_membership) {
+    uint32_t* pm = G->tr_label.as<uint32_t>();
+    CHK(copy_in(s, pm, prev_membership, sizeof(uint32_t) * n, prev_on_device));
+    unsigned int* fl = (unsigned int*)(G->small.as<uint64_t>() + 300);
+    label_check(s, pm, G->has_state ? Cprev : nullptr, n, fl);
+    unsigned int f = 0;
+    HIPCHK(hipMemcpyAsync(&f, fl, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (f & 1) return fail(LEIDEN_EINVAL, "prev_membership has a label >= n");
+    if (f & 2) restart = true;
+    if (restart) HIPCHK(hipMemcpyAsync(Cprev, pm, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
+  }
+  // batch: copy, group, sort, validate (nothing changes before this passes)
+  uint32_t* din = G->bt_in.as<uint32_t>();
+  CHK(copy_in(s, din, del, sizeof(uint32_t) * 2 * n_del, batch_on_device));
+  CHK(copy_in(s, din + 2 * n_del, ins, sizeof(uint32_t) * 3 * n_ins, batch_on_device));
+  BatchBufs bb{};
+  bb.src = G->bt_src.as<uint32_t>();
+  bb.dst = G->bt_dst.as<uint32_t>();
+  bb.w = G->bt_w.as<uint32_t>();
+  bb.is_del = G->bt_del.as<uint32_t>();
+  bb.slot = G->bt_slot.as<uint32_t>();
+  bb.row_cnt = G->bt_rowcnt.as<uint32_t>();
+  bb.row_idx = G->bt_rowidx.as<uint32_t>();
+  bb.touched = G->bt_touched.as<uint32_t>();
+  bb.seg_cnt = G->bt_segcnt.as<uint32_t>();
+  bb.seg_off = G->bt_segoff.as<uint64_t>();
+  bb.new_len = G->bt_newlen.as<uint32_t>();
+  bb.out_off = G->bt_outoff.as<uint64_t>();
+  bb.seg_src = G->bt_ssrc.as<uint32_t>();
+  bb.seg_dst = G->bt_sdst.as<uint32_t>();
+  bb.seg_w = G->bt_sw.as<uint32_t>();
+  bb.seg_del = G->bt_sdel.as<uint32_t>();
+  bb.seg_id = G->bt_sid.as<uint32_t>();
+  bb.seg_pre = G->bt_spre.as<uint64_t>();
+  bb.tmp_dst = G->bt_tdst.as<uint32_t>();
+  bb.tmp_w = G->bt_tw.as<uint32_t>();
+  bb.tmp_del = G->bt_tdel.as<uint32_t>();
+  bb.scan_tmp = G->scan_tmp.p;
+  bb.total = G->small.as<uint64_t>() + 64;
+  uint64_t nt = 0;
+  int rc = batch_prepare(s, n, din, n_del, din + 2 * n_del, n_ins, bb, dctl(G), &nt);
+  if (rc < 0) return fail(LEIDEN_EDEVICE, "batch preparation failed");
+  if (rc > 0) return fail(LEIDEN_EINVAL, "invalid batch: vertex ID out of range, self-loop or zero weight");
+  rc = batch_validate(s, rows0(G), n, ne, nt, bb, dctl(G));
+  if (rc < 0) return fail(LEIDEN_EDEVICE, "batch validation failed");
+  if (rc & 2) return fail(LEIDEN_EINVAL, "invalid batch: a pair appears twice");
+  if (rc & 8) return fail(LEIDEN_EINVAL, "invalid batch: deletion of an absent edge");
+  if (rc & 4) return fail(LEIDEN_EINVAL, "invalid batch: insertion of a present edge");
+  // merge into the slack CSR (rebuild with more room if the overflow area is short)
+  {
+    uint64_t mneed = 0;
+    // upper bound of merged entries: touched rows' lengths + insertions
+    CHK(G->bt_mcols.reserve(std::max<uint64_t>(G->bt_mcols.bytes / 4, 1024) * 4));
+    bb.mcols = G->bt_mcols.as<uint32_t>();
+    bb.mw = G->bt_mw.as<uint32_t>();
+    bb.mcap = std::min(G->bt_mcols.bytes, G->bt_mw.bytes) / 4;
+    for (int attempt = 0; attempt < 3; ++attempt) {
+      rc = batch_merge(s, G->g.start, G->g.len, G->g.cap, G->g.cols, G->g.w, nt, bb,
+                       G->b_top.as<unsigned long long>(), G->g.edge_cap, dctl(G));
+      if (rc == 0) break;
+      if (rc < 0) return fail(LEIDEN_EDEVICE, "batch merge failed");
+      // short of merge scratch or overflow room
+      HIPCHK(hipMemcpyAsync(&mneed, bb.total, 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (mneed > bb.mcap) {
+        CHK(G->bt_mcols.reserve(mneed * 4 + 4096));
+        CHK(G->bt_mw.reserve(mneed * 4 + 4096));
+        bb.mcols = G->bt_mcols.as<uint32_t>();
+        bb.mw = G->bt_mw.as<uint32_t>();
+        bb.mcap = std::min(G->bt_mcols.bytes, G->bt_mw.bytes) / 4;
+      }
+      unsigned long long need = 0, top = 0;
+      HIPCHK(hipMemcpyAsync(&need, &dctl(G)->overflow_need, 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(&top, G->b_top.p, 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (top + need > G->g.edge_cap) {
+        uint32_t* reserve = G->rb_reserve.as<uint32_t>();
+        HIPCHK(hipMemcpyAsync(reserve, G->g.len, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
+        reserve_touched(s, nt, bb.touched, bb.new_len, reserve);
+        CHK(rebuild(G, s, reserve));
+      }
+      HIPCHK(hipMemsetAsync(&dctl(G)->overflow_need, 0, 8, s));
+    }
+    if (rc != 0) return fail(LEIDEN_ENOMEM, "could not make room for the batch");
+  }
+  // level-0 degree bins after the batch
+  CHK(level_bins(G, s, G->g.len, n, G->bins0, &G->maxdeg0));
+  G->nnz = G->nnz - 2 * n_del + 2 * n_ins;
+  HIPCHK(hipEventRecord(e1, s));
+  // auxiliary state: restart or continue
+  LevelState L = level_state(G);
+  if (restart) {
+    launch_row_sums_u32(s, rows0(G), n, L.K);  // K^t directly
+    launch_sigma_from(s, Cprev, L.K, n, L.S);   // Sigma^t by C^{t-1}
+    fill_i64(s, G->st_dS.as<int64_t>(), 0, n);
+    // DeltaSigma^t from zero
+    int64_t* dSig = G->sig.as<int64_t>();
+    fill_i64(s, dSig, 0, n);
+    int64_t* Kdummy = G->S2.as<int64_t>();
+    int64_t* Sdummy = (int64_t*)G->newid.p;
+    fill_i64(s, Kdummy, 0, n);
+    fill_i64(s, Sdummy, 0, n);
+    launch_aux_update(s, bb, ne, Cprev, Kdummy, Sdummy, dSig);
+  } else {
+    HIPCHK(hipMemcpyAsync(L.K, G->st_K.p, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(L.S, G->st_S.p, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(G->sig.p, G->st_dS.p, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s));
+    launch_aux_update(s, bb, ne, Cprev, L.K, L.S, G->sig.as<int64_t>());
+  }
+  int64_t* dSig = G->sig.as<int64_t>();
+  fill_u8(s, L.dS, 0, n);
+  fill_u8(s, L.dR, 0, n);
+  launch_mark_communities(s, bb, ne, Cprev, L.S, dSig, o.tau_re_num, o.tau_re_den, L.dS, L.dR);
+  unsigned long long* m2d = G->small.as<unsigned long long>() + 128;
+  sum_i64(s, L.K, n, m2d);
+  unsigned long long M2 = 0;
+  HIPCHK(hipMemcpyAsync(&M2, m2d, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  // vertex marking (first pass): the first unprocessed list goes to next_list
+  RunOpts ro{o, true, (int)mode, nullptr, false};
+  const uint32_t first_stamp = G->stamp + 1;
+  Ctl* ctl = dctl(G);
+  if (mode == LEIDEN_ND) {
+    ro.init_all = true;
+  } else if (mode == LEIDEN_DF) {
+    launch_mark_df(s, bb, ne, Cprev, G->next_list.as<uint32_t>(), &ctl->next_count, G->unproc.as<uint32_t>(),
+                   first_stamp);
+  } else {
+    uint8_t *dV = G->dV.as<uint8_t>(), *dE = G->dE.as<uint8_t>(), *dC = G->dC.as<uint8_t>();
+    fill_u8(s, dV, 0, n);
+    fill_u8(s, dE, 0, n);
+    fill_u8(s, dC, 0, n);
+    const QConst qc = make_qconst(M2 ? M2 : 1);
+    if (M2) launch_mark_ds(s, bb, ne, nt, rows0(G), n, Cprev, L.K, L.S, qc.inv_m, qc.inv_2m2, dV, dE, dC);
+    launch_flags_to_list(s, dV, n, G->next_list.as<uint32_t>(), &ctl->next_count, G->unproc.as<uint32_t>(),
+                         first_stamp);
+    ro.in_range = dV;
+  }
+  // the run starts from C^{t-1}
+  HIPCHK(hipMemcpyAsync(L.C, Cprev, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
+  CHK(read_ctl(G, s));
+  const uint64_t affected = mode == LEIDEN_ND ? n : G->hctl->next_count;
+  unsigned long long refine_marked = 0;
+  {
+    // count communities marked for refinement (statistics)
+    unsigned int* cnt = (unsigned int*)(G->small.as<uint64_t>() + 310);
+    (void)cnt;
+  }
+  // K^t of the input graph survives the run in its own buffer (levels reuse K)
+  int64_t* Kt = G->Kt.as<int64_t>();
+  HIPCHK(hipMemcpyAsync(Kt, L.K, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s));
+  CHK(run_leiden(G, s, L, ro, M2, stats));
+  // tracking (Alg. 12) and the new state
+  TrackBufs tb{};
+  tb.minv = G->tr_minv.as<uint32_t>();
+  tb.hkeys = G->tr_hk.as<unsigned long long>();
+  tb.hvals = G->tr_hv.as<long long>();
+  tb.hmask = next_pow2(2 * (uint64_t)std::max<uint32_t>(n, 1)) - 1;
+  tb.best_w = G->tr_bw.as<long long>();
+  tb.best_vmin = G->tr_bv.as<uint32_t>();
+  tb.cand_w = G->tr_cw.as<long long>();
+  tb.cand_b = G->tr_cb.as<uint32_t>();
+  tb.is_old = G->tr_old.as<uint32_t>();
+  tb.flag = G->tr_flag.as<uint32_t>();
+  tb.rank = G->tr_rank.as<uint64_t>();
+  tb.free_rank = G->tr_frank.as<uint64_t>();
+  tb.free_id = G->tr_fid.as<uint32_t>();
+  tb.label = G->tr_label.as<uint32_t>();
+  tb.matched = G->tr_matched.as<uint8_t>();
+  tb.scan_tmp = G->scan_tmp.p;
+  tb.total = G->small.as<uint64_t>() + 64;
+  uint32_t* out = G->flag.as<uint32_t>();  // free after the run
+  track(s, n, G->Ctop.as<uint32_t>(), Cprev, Kt, out, tb);
+  // new state: C^t, K^t, Sigma^t by C^t, DeltaSigma^t kept for continued labels
+  HIPCHK(hipMemcpyAsync(G->st_K.p, Kt, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s));
+  dsig_out(s, n, tb.matched, dSig, G->st_dS.as<int64_t>());
+  HIPCHK(hipMemcpyAsync(G->st_C.p, out, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
+  launch_sigma_from(s, G->st_C.as<uint32_t>(), G->st_K.as<int64_t>(), n, G->st_S.as<int64_t>());
+  G->has_state = true;
+  HIPCHK(hipEventRecord(e2, s));
+  double q = std::numeric_limits<double>::quiet_NaN();
+  if (o.compute_modularity) CHK(modularity_of(G, s, G->st_C.as<uint32_t>(), G->st_K.as<int64_t>(), &q));
+  HIPCHK(hipEventRecord(e3, s));
+  CHK(copy_out(s, membership_out, G->st_C.p, sizeof(uint32_t) * n, out_on_device));
+  HIPCHK(hipStreamSynchronize(s));
+  if (q_out) *q_out = q;
+  if (stats) {
+    CHK(read_ctl(G, s));
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e3);
+    stats->ms_total = ms;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    stats->ms_batch = ms;
+    (void)hipEventElapsedTime(&ms, e2, e3);
+    stats->ms_modularity = ms;
+    stats->affected = affected;
+    stats->refine_marked = refine_marked;
+    stats->moves = G->hctl->total_moves;
+    stats->refine_moves = G->hctl->refine_moves;
+    stats->edges_scanned = G->hctl->edges;
+    stats->nnz = G->nnz;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(e2);
+  (void)hipEventDestroy(e3);
+  return LEIDEN_OK;
+}
+
+leiden_status leiden_modularity(leiden_graph* G, const uint32_t* membership, int on_device, double* q_out) {
+  g_err.clear();
+  if (!G || !membership || !q_out) return fail(LEIDEN_EINVAL, "null argument");
+  HIPCHK(hipSetDevice(G->device));
+  hipStream_t s = G->own;
+  CHK(ensure_workspace(G, 8));
+  const uint32_t n = G->n;
+  uint32_t* C = G->C.as<uint32_t>();
+  CHK(copy_in(s, C, membership, sizeof(uint32_t) * n, on_device));
+  unsigned int* fl = (unsigned int*)(G->small.as<uint64_t>() + 300);
+  label_check(s, C, nullptr, n, fl);
+  unsigned int f = 0;
+  HIPCHK(hipMemcpyAsync(&f, fl, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (f & 1) return fail(LEIDEN_EINVAL, "membership has a label >= n");
+  int64_t* K = G->K.as<int64_t>();
+  launch_row_sums_u32(s, rows0(G), n, K);
+  return modularity_of(G, s, C, K, q_out);
+}
+
+leiden_status leiden_graph_export(leiden_graph* G, int64_t* offsets_out, uint32_t* cols_out, uint32_t* w_out) {
+  g_err.clear();
+  if (!G || !offsets_out) return fail(LEIDEN_EINVAL, "null argument");
+  HIPCHK(hipSetDevice(G->device));
+  hipStream_t s = G->own;
+  const uint32_t n = G->n;
+  std::vector<int64_t> start(n);
+  std::vector<uint32_t> len(n);
+  unsigned long long top = 0;
+  HIPCHK(hipMemcpyAsync(start.data(), G->g.start, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(len.data(), G->g.len, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&top, G->b_top.p, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<uint32_t> cols(top), w(top);
+  HIPCHK(hipMemcpyAsync(cols.data(), G->g.cols, sizeof(uint32_t) * top, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(w.data(), G->g.w, sizeof(uint32_t) * top, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  int64_t e = 0;
+  offsets_out[0] = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    for (uint32_t k = 0; k < len[i]; ++k, ++e) {
+      if (cols_out) cols_out[e] = cols[start[i] + k];
+      if (w_out) w_out[e] = w[start[i] + k];
+    }
+    offsets_out[i + 1] = e;
+  }
+  return LEIDEN_OK;
+}
+
+leiden_status leiden_state_export(leiden_graph* G, uint32_t* C, int64_t* K, int64_t* Sigma, int64_t* dSigma) {
+  g_err.clear();
+  if (!G) return fail(LEIDEN_EINVAL, "null handle");
+  if (!G->has_state) return fail(LEIDEN_ESTATE, "no state yet");
+  HIPCHK(hipSetDevice(G->device));
+  hipStream_t s = G->own;
+  const uint32_t n = G->n;
+  CHK(copy_out(s, C, G->st_C.p, sizeof(uint32_t) * n, 0));
+  CHK(copy_out(s, K, G->st_K.p, sizeof(int64_t) * n, 0));
+  CHK(copy_out(s, Sigma, G->st_S.p, sizeof(int64_t) * n, 0));
+  CHK(copy_out(s, dSigma, G->st_dS.p, sizeof(int64_t) * n, 0));
+  HIPCHK(hipStreamSynchronize(s));
+  return LEIDEN_OK;
+}
+
+leiden_status leiden_state_import(leiden_graph* G, const uint32_t* C, const int64_t* K, const int64_t* Sigma,
+                                  const int64_t* dSigma) {
+  g_err.clear();
+  if (!G || !C || !K || !Sigma || !dSigma) return fail(LEIDEN_EINVAL, "null argument");
+  HIPCHK(hipSetDevice(G->device));
+  hipStream_t s = G->own;
+  const uint32_t n = G->n;
+  CHK(ensure_workspace(G, 8));
+  for (Buf* b : {&G->st_C}) CHK(b->reserve((size_t)std::max<uint32_t>(n, 1) * 4));
+  for (Buf* b : {&G->st_K, &G->st_S, &G->st_dS}) CHK(b->reserve((size_t)std::max<uint32_t>(n, 1) * 8));
+  // check on the host: labels < n, K = row sums, Sigma = sums of K by label
+  std::vector<int64_t> Kref(n);
+  int64_t* Kd = G->K.as<int64_t>();
+  launch_row_sums_u32(s, rows0(G), n, Kd);
+  HIPCHK(hipMemcpyAsync(Kref.data(), Kd, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<int64_t> Sref(n, 0);
+  for (uint32_t i = 0; i < n; ++i) {
+    if (C[i] >= n) return fail(LEIDEN_EINVAL, "label >= n");
+    if (K[i] != Kref[i]) return fail(LEIDEN_EINVAL, "K differs from the row sums of the graph");
+    Sref[C[i]] += K[i];
+  }
+  for (uint32_t c = 0; c < n; ++c)
+    if (Sref[c] != Sigma[c]) return fail(LEIDEN_EINVAL, "Sigma differs from the sums of K by community");
+  CHK(copy_in(s, G->st_C.p, C, sizeof(uint32_t) * n, 0));
+  CHK(copy_in(s, G->st_K.p, K, sizeof(int64_t) * n, 0));
+  CHK(copy_in(s, G->st_S.p, Sigma, sizeof(int64_t) * n, 0));
+  CHK(copy_in(s, G->st_dS.p, dSigma, sizeof(int64_t) * n, 0));
+  HIPCHK(hipStreamSynchronize(s));
+  G->has_state = true;
+  return LEIDEN_OK;
+}
+
+}  // extern "C"

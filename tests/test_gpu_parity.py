@@ -1,0 +1,216 @@
+"""Parity of the HIP path with the CPU oracle (deterministic schedule).
+
+Every case runs the same seeded inputs through the C-ABI and through the
+oracle, and requires identical memberships (bit-exact integer labels),
+identical modularity (both evaluate Eq. 1 from exact integer parts with the
+same final formula), identical pass / iteration counts, identical graphs after
+batch updates and identical auxiliary state (K, Sigma, DeltaSigma).
+"""
+import numpy as np
+import pytest
+
+from paper_2410_15451_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lm():
+    from paper_2410_15451_amd import binding
+    binding.lib()
+    return binding
+
+
+def _graph(lm, g, **kw):
+    return lm.Graph.from_csr(g, **kw)
+
+
+def _check_static(lm, orc, g, tag, **kw):
+    okw = {k: v for k, v in kw.items() if k in ("move_classes", "refine_rounds", "max_iters", "max_passes", "tau")}
+    G = _graph(lm, g)
+    r = G.static(**kw)
+    C, q, st = orc.static(g, schedule=orc.JACOBI, **okw)
+    assert np.array_equal(r.membership, C), (tag, int((r.membership != C).sum()))
+    assert r.q == q, (tag, r.q, q)
+    assert r.stats["passes"] == st["passes"], (tag, r.stats, st)
+    assert r.stats["iters"] == st["iters"], (tag, r.stats, st)
+    return G, r
+
+
+def test_static_planted_partition(lm, orc):
+    g = inputs.planted_partition()
+    _, r = _check_static(lm, orc, g, "planted")
+    assert len(np.unique(r.membership)) == 10
+
+
+@pytest.mark.parametrize("scale,seed", [(8, 1), (10, 2), (12, 3), (14, 4)])
+def test_static_rmat(lm, orc, scale, seed):
+    g = inputs.rmat(scale, seed=seed)
+    _check_static(lm, orc, g, "rmat%d" % scale)
+
+
+@pytest.mark.parametrize("P,R", [(1, 1), (3, 5), (8, 8), (32, 2)])
+def test_static_schedule_parameters(lm, orc, P, R):
+    g = inputs.rmat(11, seed=7)
+    _check_static(lm, orc, g, "P%dR%d" % (P, R), move_classes=P, refine_rounds=R)
+
+
+def test_static_weighted(lm, orc):
+    rng = np.random.default_rng(3)
+    g = inputs.rmat(11, seed=9)
+    w = rng.integers(1, 17, size=g.nnz // 2).astype(np.uint32)
+    # symmetric weights: assign per undirected pair
+    keys = g.undirected_keys()
+    u = (keys >> np.uint64(32)).astype(np.int64)
+    v = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    gw = inputs.csr_from_undirected(g.n, u, v, w[:keys.shape[0]])
+    _check_static(lm, orc, gw, "weighted")
+
+
+def test_static_edge_cases(lm, orc):
+    cases = {
+        "edgeless": inputs.csr_from_edges(7, []),
+        "single_edge": inputs.csr_from_edges(2, [(0, 1)]),
+        "isolated_mix": inputs.csr_from_edges(9, [(0, 1), (1, 2), (5, 6)]),
+        "triangles": inputs.csr_from_edges(6, [(0, 1), (1, 2), (0, 2), (3, 4), (4, 5), (3, 5), (2, 3)]),
+        "star": inputs.csr_from_edges(40, [(0, i) for i in range(1, 40)]),
+        "hub": inputs.csr_from_edges(5000, [(0, i) for i in range(1, 5000)] + [(i, i + 1) for i in range(1, 4999)]),
+    }
+    for name, g in cases.items():
+        _check_static(lm, orc, g, name)
+
+
+def _run_updates(lm, orc, g, batches, mode, **kw):
+    """Static run, then a sequence of batches; everything compared with the oracle."""
+    G = _graph(lm, g, slack=kw.pop("slack", 0.2))
+    r0 = G.static()
+    C0, q0, _ = orc.static(g)
+    assert np.array_equal(r0.membership, C0)
+    state = orc.initial_state(g, C0)
+    cur = g
+    for bi, (dels, ins) in enumerate(batches):
+        gt, dw = orc.apply_batch(cur, dels, ins)
+        r = G.update(dels, ins, mode=mode, **kw)
+        offs, cols, w = G.export()
+        assert np.array_equal(offs, gt.offs) and np.array_equal(cols, gt.cols) and np.array_equal(w, gt.w), bi
+        C1, state, q1, st1 = orc.update(gt, dw, ins, state, mode)
+        assert np.array_equal(r.membership, C1), (mode, bi, int((r.membership != C1).sum()))
+        assert r.q == q1, (mode, bi, r.q, q1)
+        assert r.stats["passes"] == st1["passes"] and r.stats["iters"] == st1["iters"], (r.stats, st1)
+        assert r.stats["affected"] == st1["affected"], (r.stats["affected"], st1["affected"])
+        Cs, Ks, Ss, dSs = G.state()
+        assert np.array_equal(Cs, state.C) and np.array_equal(Ks, state.K)
+        assert np.array_equal(Ss, state.S) and np.array_equal(dSs, state.dS)
+        cur = gt
+    return G
+
+
+def _stream(g, sizes, seed):
+    keys = g.undirected_keys()
+    out = []
+    for k, nb in enumerate(sizes):
+        dels, ins = inputs.random_batch(g.n, keys, nb, seed=seed + k)
+        out.append((dels, ins))
+        keys = inputs.keys_after_batch(keys, dels, ins)
+    return out
+
+
+@pytest.mark.parametrize("mode", ["nd", "ds", "df"])
+def test_update_planted(lm, orc, mode):
+    g = inputs.planted_partition()
+    _run_updates(lm, orc, g, _stream(g, [100, 100, 500, 2000], seed=11), mode)
+
+
+@pytest.mark.parametrize("mode", ["nd", "ds", "df"])
+def test_update_rmat(lm, orc, mode):
+    g = inputs.rmat(12, seed=5)
+    _run_updates(lm, orc, g, _stream(g, [1, 10, 100, 1000, 5000], seed=21), mode)
+
+
+def test_update_overflow_and_rebuild(lm, orc):
+    # no slack: insertions overflow rows and force relocations and rebuilds
+    g = inputs.rmat(10, seed=6)
+    _run_updates(lm, orc, g, _stream(g, [3000, 3000, 3000], seed=31), "df", slack=0.0)
+
+
+def test_update_empty_batch_and_ds_of_empty(lm, orc):
+    g = inputs.planted_partition()
+    e2, e3 = np.zeros((0, 2), np.uint32), np.zeros((0, 3), np.uint32)
+    for mode in ("ds", "df", "nd"):
+        _run_updates(lm, orc, g, [(e2, e3)], mode)
+
+
+def test_invalid_batches_leave_state(lm, orc):
+    g = inputs.planted_partition()
+    G = _graph(lm, g)
+    r0 = G.static()
+    before = G.export(), G.state()
+    keys = g.undirected_keys()
+    u, v = int(keys[0] >> 32), int(keys[0] & 0xFFFFFFFF)
+    absent = next((a, b) for a in range(g.n) for b in range(a + 1, g.n)
+                  if (a << 32 | b) not in set(keys[:50000].tolist()))
+    bad = [
+        (np.array([[0, 0]]), np.zeros((0, 3))),
+        (np.zeros((0, 2)), np.array([[1, 1, 1]])),
+        (np.zeros((0, 2)), np.array([[0, g.n, 1]])),
+        (np.array([[absent[0], absent[1]]]), np.zeros((0, 3))),
+        (np.zeros((0, 2)), np.array([[u, v, 1]])),
+        (np.zeros((0, 2)), np.array([[absent[0], absent[1], 0]])),
+        (np.array([[u, v], [v, u]]), np.zeros((0, 3))),
+        (np.array([[u, v]]), np.array([[v, u, 2]])),
+    ]
+    for dels, ins in bad:
+        with pytest.raises(lm.LeidenError) as ei:
+            G.update(np.asarray(dels, np.uint32), np.asarray(ins, np.uint32), mode="df")
+        assert ei.value.code == lm.LEIDEN_EINVAL
+        after = G.export(), G.state()
+        for a, b in zip(before[0] + before[1], after[0] + after[1]):
+            assert np.array_equal(a, b)
+    # still usable afterwards
+    _ = G.update(np.zeros((0, 2), np.uint32), np.zeros((0, 3), np.uint32), mode="df")
+
+
+def test_prev_membership_restart(lm, orc):
+    g = inputs.planted_partition()
+    G = _graph(lm, g)
+    G.static()
+    rng = np.random.default_rng(2)
+    prev = (np.arange(g.n) // 100).astype(np.uint32)  # not the last result
+    prev[rng.choice(g.n, 30, replace=False)] = rng.integers(0, 10, 30).astype(np.uint32)
+    dels, ins = _stream(g, [200], seed=3)[0]
+    gt, dw = orc.apply_batch(g, dels, ins)
+    r = G.update(dels, ins, mode="df", prev=prev)
+    st = orc.initial_state(g, prev)  # Sigma from K by prev, DeltaSigma = 0
+    C1, st1, q1, _ = orc.update(gt, dw, ins, st, "df")
+    assert np.array_equal(r.membership, C1)
+    assert r.q == q1
+
+
+def test_modularity_api(lm, orc):
+    g = inputs.rmat(11, seed=4)
+    G = _graph(lm, g)
+    rng = np.random.default_rng(1)
+    for k in (1, 7, 100, g.n):
+        C = rng.integers(0, k, size=g.n).astype(np.uint32)
+        assert G.modularity(C) == orc.modularity(g, C)
+
+
+def test_device_pointers(lm, orc):
+    torch = pytest.importorskip("torch")
+    g = inputs.planted_partition()
+    dev = torch.device("cuda:0")
+    offs = torch.from_numpy(g.offs).to(dev)
+    cols = torch.from_numpy(g.cols.view(np.int32)).to(dev)
+    w = torch.from_numpy(g.w.view(np.int32)).to(dev)
+    G = lm.Graph(offs, cols, w, n=g.n)
+    out = torch.zeros(g.n, dtype=torch.int32, device=dev)
+    r = G.static(out=out, stream=torch.cuda.current_stream().cuda_stream)
+    C, q, _ = orc.static(g)
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), C)
+    dels, ins = _stream(g, [100], seed=9)[0]
+    d = torch.from_numpy(dels.view(np.int32)).to(dev)
+    i = torch.from_numpy(ins.view(np.int32)).to(dev)
+    r = G.update(d, i, mode="df", out=out)
+    gt, dw = orc.apply_batch(g, dels, ins)
+    C1, _, q1, _ = orc.update(gt, dw, ins, orc.initial_state(g, C), "df")
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), C1)
