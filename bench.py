@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X Leiden path on one GPU.
+
+Workload (the 4M-vertex R-MAT configuration): R-MAT with 2^22 vertices and
+2^26 samples, (a, b, c, d) = (0.57, 0.19, 0.19, 0.05), self-loops and
+duplicates removed, seeded vertex permutation, unit weights.  After a static
+run, a stream of Dynamic Frontier (DF) updates of 1e-3 |E| undirected updates
+each (80% insertions of absent pairs, 20% deletions of existing edges).
+
+A step is one DF-Leiden update through the C-ABI with its batch already in
+HBM: batch validation and merge into the device CSR, the auxiliary-state
+update, community and vertex marking, every pass of local moving, splitting,
+refinement and aggregation, and tracking.  value = |E^t| / step time
+(directed entries of the updated graph per second, the paper's "runtime on
+the entire updated graph").  Modularity is computed once outside the timed
+steps.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "edges/s static & DF-Leiden update (1 GPU, % HBM roofline); p50/p99 update latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def percentile(xs, p):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * p / 100.0
+    lo = int(k)
+    hi = min(lo + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def cpu_baseline(scale, frac, reps, seed):
+    """The oracle (single-threaded CPU) on a bounded sample: R-MAT at `scale`
+    with the same recipe, its own static run (untimed), then `reps` DF updates
+    of frac*|E| timed around the algorithm only."""
+    import numpy as np
+
+    import oracle
+    from paper_2410_15451_amd import inputs
+    g = inputs.rmat(scale, seed=seed)
+    C0, _, _ = oracle.static(g)
+    st = oracle.initial_state(g, C0)
+    keys = g.undirected_keys()
+    batches = inputs.random_batch_stream(g.n, keys, inputs.batch_size_for(g.nnz, frac), reps, seed=seed + 1000)
+    edges = 0
+    tsum = 0.0
+    cur_keys = keys
+    for dels, ins in batches:
+        cur_keys = inputs.keys_after_batch(cur_keys, dels, ins)
+        gt = inputs.csr_from_undirected(g.n, cur_keys >> np.uint64(32), cur_keys & np.uint64(0xFFFFFFFF))
+        dw = np.concatenate([dels, np.ones((dels.shape[0], 1), np.uint32)], 1)
+        t = time.perf_counter()
+        _, st, _, _ = oracle.update(gt, dw, ins, st, "df")
+        tsum += time.perf_counter() - t
+        edges += gt.nnz
+    return {"value": edges / tsum, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": "R-MAT scale %d (same recipe, |E|=%d), %d DF updates of %g|E| after an untimed oracle static "
+                      "run; single-threaded C++ oracle, %.1f s timed" % (scale, g.nnz, reps, frac, tsum)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--scale", type=int, default=22)
+    ap.add_argument("--frac", type=float, default=1e-3)
+    ap.add_argument("--mode", default="df", choices=["nd", "ds", "df"])
+    ap.add_argument("--context-steps", type=int, default=3, help="ND / DS / static steps for the ratio context")
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--cpu-scale", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2410_15451_amd import binding, inputs
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+
+    t0 = time.time()
+    g = inputs.rmat(args.scale, seed=inputs.BASE_SEED + 2)
+    log("graph: n=%d nnz=%d maxdeg=%d (%.1f s)" % (g.n, g.nnz, int(g.degrees().max()), time.time() - t0))
+    nb = inputs.batch_size_for(g.nnz, args.frac)
+    ctx = args.context_steps
+    total_batches = args.warmup + args.steps + 2 * ctx
+    batches = inputs.random_batch_stream(g.n, g.undirected_keys(), nb, total_batches,
+                                         seed=inputs.BASE_SEED + 2 + 1000)
+    dev_batches = [(torch.from_numpy(d.view(np.int32)).to(dev), torch.from_numpy(i.view(np.int32)).to(dev))
+                   for d, i in batches]
+    G = binding.Graph.from_csr(g)
+    out = torch.zeros(g.n, dtype=torch.int32, device=dev)
+    opts = dict(stream=sp, compute_modularity=0)
+
+    # static Leiden (twice: the first run also allocates the workspace)
+    G.static(out=out, **opts)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rs = G.static(out=out, **opts)
+    torch.cuda.synchronize()
+    t_static = time.perf_counter() - t
+    q_static = G.modularity(out)
+    log("static: %.2f ms, passes %d, iters %s, q=%.5f" % (t_static * 1e3, rs.stats["passes"], rs.stats["iters"],
+                                                          q_static))
+    bi = 0
+
+    def run_update(mode):
+        nonlocal bi
+        d, i = dev_batches[bi]
+        bi += 1
+        ta = time.perf_counter()
+        r = G.update(d, i, mode=mode, out=out, **opts)
+        return time.perf_counter() - ta, r
+
+    for _ in range(args.warmup):
+        run_update(args.mode)
+    torch.cuda.synchronize()
+    lat, edges, stats = [], 0, []
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    tw = time.perf_counter()
+    for _ in range(args.steps):
+        dt, r = run_update(args.mode)
+        lat.append(dt)
+        edges += r.stats["nnz"]
+        stats.append(r.stats)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - tw
+    dev_ms = ev0.elapsed_time(ev1)
+    T = max(wall, dev_ms / 1e3)
+    value = edges / T
+    q_dyn = G.modularity(out)
+    log("%s: %d steps, %.3f ms/step, p50 %.3f ms, p99 %.3f ms, q=%.5f" % (
+        args.mode, args.steps, T / args.steps * 1e3, percentile(lat, 50) * 1e3, percentile(lat, 99) * 1e3, q_dyn))
+
+    # context: ND / DS updates and a static recompute on the evolving graph
+    context = {}
+    for mode in [m for m in ("nd", "ds") if m != args.mode]:
+        ts = [run_update(mode)[0] for _ in range(ctx)]
+        context[mode + "_ms"] = 1e3 * sum(ts) / len(ts)
+    ts = []
+    for _ in range(ctx):
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        G.static(out=out, **opts)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - ta)
+    context["static_ms"] = 1e3 * sum(ts) / len(ts)
+    context[args.mode + "_ms"] = T / args.steps * 1e3
+    for m in ("nd", "ds", "df"):
+        if m + "_ms" in context:
+            context["speedup_%s_vs_static" % m] = context["static_ms"] / context[m + "_ms"]
+    context["paper_speedup_vs_static_64core_epyc"] = {"nd": 3.9, "ds": 4.4, "df": 6.1}
+
+    mean = {k: sum(s[k] for s in stats) / len(stats) for k in ("ms_total", "ms_batch", "edges_scanned", "moves",
+                                                                 "affected", "passes")}
+    line = {
+        "metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": T / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64+f64", "data": "synthetic",
+        "config": {"workload": "rmat%d_%s_update_%g" % (args.scale, args.mode, args.frac), "n": g.n, "nnz": g.nnz,
+                   "batch_undirected_updates": nb, "mode": args.mode, "deterministic": True},
+        "p50_ms": percentile(lat, 50) * 1e3, "p99_ms": percentile(lat, 99) * 1e3,
+        "static_edges_per_s": g.nnz / t_static, "static_ms": t_static * 1e3,
+        "batch_edges_per_s": 2 * nb * args.steps / T,
+        "modularity": {"static": q_static, "after_updates": q_dyn},
+        "step_stats_mean": mean, "context": context,
+    }
+    if args.cpu_baseline:
+        t = time.time()
+        line["cpu_baseline"] = cpu_baseline(args.cpu_scale, args.frac, 3, inputs.BASE_SEED + 2)
+        log("cpu baseline: %.3g edges/s (%.1f s)" % (line["cpu_baseline"]["value"], time.time() - t))
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

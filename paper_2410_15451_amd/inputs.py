@@ -190,6 +190,21 @@ def random_batch(n: int, existing_keys: np.ndarray, n_updates: int, seed: int,
     return dels.astype(np.uint32).reshape(-1, 2), ins.astype(np.uint32).reshape(-1, 3)
 
 
+def random_batch_stream(n: int, existing_keys: np.ndarray, n_updates: int, count: int, seed: int,
+                        ins_frac: float = 0.8, w_range=(1, 1)):
+    """``count`` consecutive batches of ``n_updates`` each, valid when applied in order.
+
+    All deletions are distinct edges of the starting graph and all insertions
+    distinct pairs absent from it, so no batch touches a pair an earlier batch
+    changed.  Returns a list of (deletions, insertions)."""
+    dels, ins = random_batch(n, existing_keys, n_updates * count, seed, ins_frac, w_range)
+    rng = rng_for(seed + 7)
+    dels = dels[rng.permutation(dels.shape[0])]
+    ins = ins[rng.permutation(ins.shape[0])]
+    nd, ni = dels.shape[0] // count, ins.shape[0] // count
+    return [(dels[k * nd:(k + 1) * nd], ins[k * ni:(k + 1) * ni]) for k in range(count)]
+
+
 def keys_after_batch(existing_keys: np.ndarray, dels: np.ndarray, ins: np.ndarray) -> np.ndarray:
     """Edge-key bookkeeping for generating a stream of batches (sorted result)."""
     dk = (np.minimum(dels[:, 0], dels[:, 1]).astype(np.uint64) << np.uint64(32)) | \
