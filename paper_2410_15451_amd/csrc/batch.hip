@@ -571,10 +571,12 @@ void launch_mark_ds(hipStream_t s, const BatchBufs& b, uint64_t n_entries, uint6
 // Flag array -> vertex list (order irrelevant), stamping each listed vertex.
 __global__ __launch_bounds__(kBlock) void k_flags_to_list(const uint8_t* flags, uint32_t n, uint32_t* list,
                                                           unsigned int* count, uint32_t* mark, uint32_t stamp) {
-  GRID_STRIDE(i, n) {
-    if (!flags[i]) continue;
-    mark[i] = stamp;
-    list_push(list, count, (uint32_t)i);
+  __shared__ unsigned int s2[2];
+  for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < n; base += (uint64_t)gridDim.x * kBlock) {
+    const uint64_t i = base + threadIdx.x;
+    const bool on = i < n && flags[i];
+    if (on) mark[i] = stamp;
+    block_append(list, count, on, (uint32_t)i, s2);
   }
 }
 

@@ -13,6 +13,7 @@ constexpr int kBlock = 256;     // threads per block of every list kernel
 constexpr int kWave = 64;       // CDNA wavefront
 constexpr int kMaxClasses = 32; // vertex classes / refinement colours
 constexpr int kBins = 6;        // degree bins of the hash kernels
+constexpr uint32_t kBigRow = 4096; // movers with longer rows are marked block-parallel
 
 // Degree bins: lanes per vertex and hash slots per vertex.  A vertex of
 // degree d goes to the first bin with d <= kBinMaxDeg; the last bin keeps its
@@ -61,6 +62,7 @@ struct Ctl {
   unsigned int touched;              // rows touched by the batch
   unsigned int init_count;           // vertices marked affected by the batch
   unsigned long long overflow_need;  // entries to relocate into the overflow area
+  unsigned int big_count;            // movers whose rows are marked by the block-parallel kernel
   unsigned int misc[8];
 };
 
@@ -200,6 +202,27 @@ __device__ inline void block_best(double& dq, uint32_t& c, double* rdq, uint32_t
 __device__ inline void list_push(uint32_t* list, unsigned int* count, uint32_t v) {
   unsigned int pos = atomicAdd(count, 1u);
   list[pos] = v;
+}
+
+// Block-wide append: every thread of the block calls this (block-uniform
+// control flow); threads with `pred` append `v`.  One global atomic per block.
+// `s2` is two words of shared memory.
+__device__ inline void block_append(uint32_t* list, unsigned int* count, bool pred, uint32_t v, unsigned int* s2) {
+  if (threadIdx.x == 0) s2[0] = 0;
+  __syncthreads();
+  unsigned int pos = 0;
+  if (pred) pos = atomicAdd(&s2[0], 1u);
+  __syncthreads();
+  if (threadIdx.x == 0 && s2[0]) s2[1] = atomicAdd(count, s2[0]);
+  __syncthreads();
+  if (pred) list[s2[1] + pos] = v;
+  __syncthreads();
+}
+
+__host__ __device__ inline uint32_t pow2_at_least(uint32_t x) {
+  uint32_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
 }
 
 }  // namespace lm

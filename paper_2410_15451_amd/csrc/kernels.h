@@ -42,6 +42,7 @@ struct ApplyParams {
   uint32_t* cls_lists;
   size_t cls_stride;
   uint32_t* next_list;
+  uint32_t* big_list;  // movers with long rows (marked by the block-parallel kernel)
 };
 
 // move.hip
@@ -53,7 +54,8 @@ void launch_bin(hipStream_t s, const uint32_t* list, const unsigned int* count, 
 template <typename W, bool REFINE>
 void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, size_t stride, unsigned int* bin_counts,
                        const uint64_t* bin_upper, int hub_grid);
-void launch_apply_moves(hipStream_t s, const ApplyParams& p, uint32_t n_upper);
+// long_rows: the level has rows longer than the wavefront path handles
+void launch_apply_moves(hipStream_t s, const ApplyParams& p, uint32_t n_upper, bool long_rows);
 void launch_apply_refine(hipStream_t s, uint32_t* C, int64_t* S, const int64_t* K, uint32_t* size,
                          const Mover* movers, Ctl* ctl, uint32_t n_upper);
 void launch_subround_reset(hipStream_t s, Ctl* ctl);
@@ -69,6 +71,12 @@ void iota_u32(hipStream_t s, uint32_t* p, size_t n);
 void exclusive_scan_u32(hipStream_t s, const uint32_t* in, uint64_t* out, size_t n, uint64_t* total, void* tmp);
 size_t scan_tmp_bytes(size_t n);
 void exclusive_scan_u64(hipStream_t s, const uint64_t* in, uint64_t* out, size_t n, uint64_t* total, void* tmp);
+
+// scatter.hip: block-privatised scatter reductions over i < n
+void scatter_add_i64(hipStream_t s, const uint32_t* key, const int64_t* val, uint64_t n, int64_t* out);
+void scatter_add_u32_to_u64(hipStream_t s, const uint32_t* key, const uint32_t* val, uint64_t n, uint64_t* out);
+void scatter_count(hipStream_t s, const uint32_t* key, uint64_t n, uint32_t* out);
+void scatter_min_index(hipStream_t s, const uint32_t* key, uint64_t n, uint32_t* out);
 
 // phases.hip
 void fill_u64(hipStream_t s, uint64_t* p, uint64_t v, size_t n);
@@ -115,8 +123,10 @@ struct AggBufs {
   uint64_t* total;        // device scalars
   void* scan_tmp;
   uint32_t* small_lists;  // communities per bin (small, medium, big), n each
-  uint64_t* big_cap;      // row capacity of each listed big community
-  uint64_t* tbl_off;      // global table offsets for big communities
+  uint64_t* big_info;     // (member begin, member end, capacity) of each big community, 3 n
+  void* bigc;             // per-round table descriptors of big communities (16 B each, n)
+  void* items;            // per-round work items (24 B each, item_cap)
+  uint64_t item_cap;
   uint32_t* gkeys;
   unsigned long long* gvals;
   size_t gcap;            // slots available in gkeys / gvals

@@ -172,20 +172,21 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(DecideParams<W> p) {
   unsigned long long* tv = lvals;
   uint32_t mask = T - 1;
   if (HUB) {
-    mask = p.hub_mask;
-    tk = p.hub_keys + (size_t)blockIdx.x * (mask + 1);
-    tv = p.hub_vals + (size_t)blockIdx.x * (mask + 1);
+    tk = p.hub_keys + (size_t)blockIdx.x * (p.hub_mask + 1);
+    tv = p.hub_vals + (size_t)blockIdx.x * (p.hub_mask + 1);
   }
   const uint32_t cnt = *p.count;
   unsigned long long edges = 0;
   for (uint32_t item = blockIdx.x; item < cnt; item += gridDim.x) {
+    const uint32_t v = p.list[item];
+    const uint32_t d = p.C[v];
+    // a hub's table holds at least twice its degree (never more than the region)
+    if (HUB) mask = min(p.hub_mask, pow2_at_least(2 * p.g.len[v]) - 1);
     for (uint32_t s = threadIdx.x; s <= mask; s += kBlock) {
       tk[s] = kNone;
       tv[s] = 0;
     }
     __syncthreads();
-    const uint32_t v = p.list[item];
-    const uint32_t d = p.C[v];
     const bool valid = !(REFINE && p.size[d] != 1);
     unsigned long long kid = 0;
     if (valid) {
@@ -232,6 +233,19 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(DecideParams<W> p) {
 // Apply kernels
 // ---------------------------------------------------------------------------
 
+// A neighbour j of a mover in class k: if j's class comes later it joins
+// that class's sub-round of this iteration, otherwise it is queued as
+// unprocessed for the next iteration (each vertex at most once per list).
+__device__ inline void mark_neighbour(const ApplyParams& p, uint32_t j) {
+  const uint32_t kj = vertex_class(j, p.li, p.P);
+  if (kj > p.k) {
+    if (atomicExch(&p.pend_mark[j], p.stamp) != p.stamp)
+      list_push(p.cls_lists + (size_t)kj * p.cls_stride, &p.ctl->cls_count[kj], j);
+  } else {
+    if (atomicExch(&p.unproc_mark[j], p.stamp + 1) != p.stamp + 1) list_push(p.next_list, &p.ctl->next_count, j);
+  }
+}
+
 // Local-moving moves: one wavefront per mover.  Lane 0 moves the vertex
 // (C, Sigma, member counts, gain sum, split flag of the source community);
 // all lanes mark the neighbours: a neighbour of a later class joins that
@@ -257,21 +271,28 @@ __global__ __launch_bounds__(kBlock) void k_apply_moves(ApplyParams p) {
       dqsum += gain_fixed(mv.dq);
       if (p.dS) p.dS[d] = 1;
     }
-    const int64_t s0 = p.start[v];
     const uint32_t L = p.len[v];
-    for (uint32_t e = lane; e < L; e += kWave) {
-      const uint32_t j = p.cols[s0 + e];
-      const uint32_t kj = vertex_class(j, p.li, p.P);
-      if (kj > p.k) {
-        if (atomicExch(&p.pend_mark[j], p.stamp) != p.stamp)
-          list_push(p.cls_lists + (size_t)kj * p.cls_stride, &p.ctl->cls_count[kj], j);
-      } else {
-        if (atomicExch(&p.unproc_mark[j], p.stamp + 1) != p.stamp + 1) list_push(p.next_list, &p.ctl->next_count, j);
-      }
+    if (L > kBigRow) {
+      if (lane == 0) list_push(p.big_list, &p.ctl->big_count, v);
+      continue;
     }
+    const int64_t s0 = p.start[v];
+    for (uint32_t e = lane; e < L; e += kWave) mark_neighbour(p, p.cols[s0 + e]);
   }
   if (lane == 0 && dqsum != 0) atomicAdd(&p.ctl->dq_fixed, (unsigned long long)dqsum);
   if (lane == 0 && wave == 0) atomicAdd(&p.ctl->total_moves, (unsigned long long)cnt);
+}
+
+// Neighbour marking of movers with long rows: every block takes a share of
+// each such row.
+__global__ __launch_bounds__(kBlock) void k_mark_big(ApplyParams p) {
+  const uint32_t nbig = p.ctl->big_count;
+  for (uint32_t m = 0; m < nbig; ++m) {
+    const uint32_t v = p.big_list[m];
+    const int64_t s0 = p.start[v];
+    const uint32_t L = p.len[v];
+    for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < L; e += gridDim.x * kBlock) mark_neighbour(p, p.cols[s0 + e]);
+  }
 }
 
 // Refinement moves: an isolated vertex joins its chosen sub-community.
@@ -293,7 +314,10 @@ __global__ __launch_bounds__(kBlock) void k_apply_refine(uint32_t* C, int64_t* S
 
 __global__ void k_subround_reset(Ctl* ctl) {
   if (threadIdx.x < kBins) ctl->bin_count[threadIdx.x] = 0;
-  if (threadIdx.x == 0) ctl->mover_count = 0;
+  if (threadIdx.x == 0) {
+    ctl->mover_count = 0;
+    ctl->big_count = 0;
+  }
 }
 
 // Start of an iteration: the vertices queued as unprocessed become this
@@ -378,8 +402,9 @@ template void launch_decide_all<int64_t, false>(hipStream_t, DecideParams<int64_
 template void launch_decide_all<int64_t, true>(hipStream_t, DecideParams<int64_t>, uint32_t*, size_t, unsigned int*,
                                                const uint64_t*, int);
 
-void launch_apply_moves(hipStream_t s, const ApplyParams& p, uint32_t n_upper) {
+void launch_apply_moves(hipStream_t s, const ApplyParams& p, uint32_t n_upper, bool long_rows) {
   hipLaunchKernelGGL(k_apply_moves, dim3(grid_for(n_upper, kBlock / kWave, 2048)), dim3(kBlock), 0, s, p);
+  if (long_rows) hipLaunchKernelGGL(k_mark_big, dim3(512), dim3(kBlock), 0, s, p);
 }
 
 void launch_apply_refine(hipStream_t s, uint32_t* C, int64_t* S, const int64_t* K, uint32_t* size,

@@ -44,46 +44,39 @@ void launch_degree_hist(hipStream_t s, const uint32_t* len, uint32_t n, unsigned
   hipLaunchKernelGGL(k_degree_hist, dim3(grid_n(n, kBlock, 2048)), dim3(kBlock), 0, s, len, n, bins_out, maxdeg_out);
 }
 
+// Weighted degree of every row, one wavefront per row.
 __global__ __launch_bounds__(kBlock) void k_row_sums(Rows<uint32_t> g, uint32_t n, int64_t* K) {
-  GRID_STRIDE(i, n) {
+  const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const uint32_t lane = threadIdx.x % kWave;
+  const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
+  for (uint64_t i = wave; i < n; i += nwaves) {
     const int64_t s0 = g.start[i];
     const uint32_t L = g.len[i];
-    int64_t k = 0;
-    for (uint32_t e = 0; e < L; ++e) k += g.w[s0 + e];
-    K[i] = k;
+    unsigned long long k = 0;
+    for (uint32_t e = lane; e < L; e += kWave) k += g.w[s0 + e];
+    k = group_sum<kWave>(k);
+    if (lane == 0) K[i] = (int64_t)k;
   }
 }
 
 void launch_row_sums_u32(hipStream_t s, Rows<uint32_t> g, uint32_t n, int64_t* K) {
-  if (n) hipLaunchKernelGGL(k_row_sums, dim3(grid_n(n)), dim3(kBlock), 0, s, g, n, K);
-}
-
-__global__ __launch_bounds__(kBlock) void k_count_members(const uint32_t* C, uint32_t n, uint32_t* size) {
-  GRID_STRIDE(i, n) atomicAdd(&size[C[i]], 1u);
+  if (n) hipLaunchKernelGGL(k_row_sums, dim3(grid_n(n, kBlock / kWave, 16384)), dim3(kBlock), 0, s, g, n, K);
 }
 
 void launch_count_members(hipStream_t s, const uint32_t* C, uint32_t n, uint32_t* size) {
   fill_u32(s, size, 0, n);
-  if (n) hipLaunchKernelGGL(k_count_members, dim3(grid_n(n)), dim3(kBlock), 0, s, C, n, size);
-}
-
-__global__ __launch_bounds__(kBlock) void k_sigma_from(const uint32_t* C, const int64_t* K, uint32_t n, int64_t* S) {
-  GRID_STRIDE(i, n) atomicAdd((unsigned long long*)&S[C[i]], (unsigned long long)K[i]);
+  scatter_count(s, C, n, size);
 }
 
 void launch_sigma_from(hipStream_t s, const uint32_t* C, const int64_t* K, uint32_t n, int64_t* S) {
   fill_i64(s, S, 0, n);
-  if (n) hipLaunchKernelGGL(k_sigma_from, dim3(grid_n(n)), dim3(kBlock), 0, s, C, K, n, S);
+  scatter_add_i64(s, C, K, n, S);
 }
 
 // ---------------------------------------------------------------------------
 // Alg. 10: each community takes the ID of its minimum member vertex; Sigma,
 // member counts and the split / refine flags move with the label.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_min_member(const uint32_t* C, uint32_t n, uint32_t* rep) {
-  GRID_STRIDE(i, n) atomicMin(&rep[C[i]], (uint32_t)i);
-}
-
 __global__ __launch_bounds__(kBlock) void k_move_by_label(uint32_t n, const uint32_t* rep, const int64_t* S,
                                                           const uint32_t* size, const uint8_t* dS, const uint8_t* dR,
                                                           int64_t* S2, uint32_t* size2, uint8_t* dS2, uint8_t* dR2,
@@ -120,7 +113,7 @@ void subset_renumber(hipStream_t s, uint32_t n, uint32_t* C, int64_t*& S, uint32
   fill_u32(s, b.size2, 0, n);
   fill_u8(s, b.dS2, 0, n);
   fill_u8(s, b.dR2, 0, n);
-  hipLaunchKernelGGL(k_min_member, dim3(grid_n(n)), dim3(kBlock), 0, s, C, n, b.rep);
+  scatter_min_index(s, C, n, b.rep);
   hipLaunchKernelGGL(k_move_by_label, dim3(grid_n(n)), dim3(kBlock), 0, s, n, b.rep, S, size, dS, dR, b.S2, b.size2,
                      b.dS2, b.dR2, ctl);
   hipLaunchKernelGGL(k_relabel, dim3(grid_n(n)), dim3(kBlock), 0, s, C, n, b.rep);
@@ -138,10 +131,16 @@ void subset_renumber(hipStream_t s, uint32_t n, uint32_t* C, int64_t*& S, uint32
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_split_init(uint32_t n, const uint32_t* C, const uint8_t* dS,
                                                        const uint8_t* dR, uint32_t* lab, uint32_t* list, Ctl* ctl) {
-  GRID_STRIDE(i, n) {
-    const uint32_t c = C[i];
-    lab[i] = (uint32_t)i;
-    if (dS[c] && !dR[c]) list_push(list, &ctl->split_count, (uint32_t)i);
+  __shared__ unsigned int s2[2];
+  for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < n; base += (uint64_t)gridDim.x * kBlock) {
+    const uint64_t i = base + threadIdx.x;
+    bool in = false;
+    if (i < n) {
+      const uint32_t c = C[i];
+      lab[i] = (uint32_t)i;
+      in = dS[c] && !dR[c];
+    }
+    block_append(list, &ctl->split_count, in, (uint32_t)i, s2);
   }
 }
 
@@ -309,20 +308,48 @@ void launch_lookup(hipStream_t s, uint32_t* Ctop, const uint32_t* C, uint32_t n)
 // table above) and writes the distinct (d, w) pairs to its super row, whose
 // capacity is min(total degree, number of communities).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_comm_stats(const uint32_t* C, const uint32_t* len, uint32_t n,
-                                                       uint32_t* count, uint64_t* deg) {
-  GRID_STRIDE(i, n) {
-    const uint32_t c = C[i];
-    atomicAdd(&count[c], 1u);
-    atomicAdd((unsigned long long*)&deg[c], (unsigned long long)len[i]);
-  }
-}
-
+// Counting-sort scatter of vertices into the member CSR.  Per tile, the
+// vertices of one community reserve their range with a single atomic (ranks
+// inside the tile come from the LDS counter), so large communities do not
+// serialise on one global counter.
 __global__ __launch_bounds__(kBlock) void k_comm_scatter(const uint32_t* C, uint32_t n, const uint64_t* off,
                                                          uint32_t* fill, uint32_t* members) {
-  GRID_STRIDE(i, n) {
-    const uint32_t c = C[i];
-    members[off[c] + atomicAdd(&fill[c], 1u)] = (uint32_t)i;
+  constexpr int kTile = 1024, kSlots = 2048, kPer = kTile / kBlock;
+  __shared__ uint32_t hk[kSlots];
+  __shared__ uint32_t hc[kSlots];
+  __shared__ uint32_t hb[kSlots];
+  for (uint64_t base = (uint64_t)blockIdx.x * kTile; base < n; base += (uint64_t)gridDim.x * kTile) {
+    for (int s = threadIdx.x; s < kSlots; s += kBlock) {
+      hk[s] = kNone;
+      hc[s] = 0;
+    }
+    __syncthreads();
+    uint32_t slot[kPer], rank[kPer], key[kPer];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const uint64_t i = base + t * kBlock + threadIdx.x;
+      if (i >= n) continue;
+      const uint32_t c = C[i];
+      uint32_t h = slot_hash(c, kSlots - 1);
+      while (true) {
+        const uint32_t o = atomicCAS(&hk[h], kNone, c);
+        if (o == kNone || o == c) break;
+        h = (h + 1) & (kSlots - 1);
+      }
+      key[t] = c;
+      slot[t] = h;
+      rank[t] = atomicAdd(&hc[h], 1u);
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < kSlots; s += kBlock)
+      if (hk[s] != kNone) hb[s] = atomicAdd(&fill[hk[s]], hc[s]);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const uint64_t i = base + t * kBlock + threadIdx.x;
+      if (i < n) members[off[key[t]] + hb[slot[t]] + rank[t]] = (uint32_t)i;
+    }
+    __syncthreads();
   }
 }
 
@@ -332,18 +359,31 @@ constexpr uint64_t kAggSmall = 128, kAggMedium = 2048;
 
 __global__ __launch_bounds__(kBlock) void k_comm_classify(uint32_t nc, const uint64_t* deg, uint64_t* cap,
                                                           uint32_t* out_len, int64_t* Kout, uint32_t* lists,
-                                                          size_t stride, uint64_t* big_cap, Ctl* ctl) {
-  GRID_STRIDE(c, nc) {
-    const uint64_t d = deg[c];
-    const uint64_t cp = d < nc ? d : nc;
-    cap[c] = cp;
-    out_len[c] = 0;
-    Kout[c] = 0;
-    if (d == 0) continue;
-    const int k = d <= kAggSmall ? 0 : (d <= kAggMedium ? 1 : 2);
-    const unsigned int pos = atomicAdd(&ctl->misc[2 + k], 1u);
-    lists[(size_t)k * stride + pos] = (uint32_t)c;
-    if (k == 2) big_cap[pos] = cp;
+                                                          size_t stride, Ctl* ctl) {
+  __shared__ unsigned int s2[2];
+  for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < nc; base += (uint64_t)gridDim.x * kBlock) {
+    const uint64_t c = base + threadIdx.x;
+    int k = -1;
+    if (c < nc) {
+      const uint64_t d = deg[c];
+      cap[c] = d < nc ? d : nc;
+      out_len[c] = 0;
+      Kout[c] = 0;
+      if (d > 0) k = d <= kAggSmall ? 0 : (d <= kAggMedium ? 1 : 2);
+    }
+    for (int b = 0; b < 3; ++b) block_append(lists + (size_t)b * stride, &ctl->misc[2 + b], k == b, (uint32_t)c, s2);
+  }
+}
+
+// Member ranges and row capacities of the big communities (for host planning).
+__global__ __launch_bounds__(kBlock) void k_big_info(const uint32_t* big, const unsigned int* nbig,
+                                                     const uint64_t* moff, const uint64_t* cap, uint64_t* info) {
+  const uint32_t cnt = *nbig;
+  GRID_STRIDE(k, cnt) {
+    const uint32_t c = big[k];
+    info[3 * k] = moff[c];
+    info[3 * k + 1] = moff[c + 1];
+    info[3 * k + 2] = cap[c];
   }
 }
 
@@ -470,49 +510,70 @@ __global__ __launch_bounds__(kBlock) void k_agg_lds(Rows<W> g, const uint32_t* C
   }
 }
 
-// Big communities: one block each, global table of tbl_size[c] slots.
+// Big communities: every community of a round owns a global table; blocks
+// take work items (a chunk of one community's members) and insert into that
+// table, then other items (a chunk of one table's slots) compact it into the
+// super row.
+struct BigComm {
+  uint32_t c;
+  uint32_t mask;
+  uint64_t toff;
+};
+struct AggItem {
+  uint32_t big;
+  uint32_t pad;
+  uint64_t a, b;
+};
+
 template <typename W>
-__global__ __launch_bounds__(kBlock) void k_agg_global(Rows<W> g, const uint32_t* C, const uint32_t* members,
-                                                       const uint64_t* moff, const uint32_t* list, uint32_t first,
-                                                       uint32_t last, const uint64_t* tbl_off, const uint64_t* tbl_mask,
-                                                       uint32_t* gkeys, unsigned long long* gvals,
-                                                       const uint64_t* cap_off, uint32_t* out_len, uint32_t* out_cols,
-                                                       int64_t* out_w, int64_t* Kout) {
+__global__ __launch_bounds__(kBlock) void k_agg_big_insert(Rows<W> g, const uint32_t* C, const uint32_t* members,
+                                                           const BigComm* bc, const AggItem* items, uint32_t nitems,
+                                                           uint32_t* gkeys, unsigned long long* gvals) {
   __shared__ int64_t sstart[kBlock];
   __shared__ uint32_t spre[kBlock];
-  __shared__ unsigned int wpos;
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const AggItem x = items[it];
+    const BigComm b = bc[x.big];
+    agg_accumulate<kBlock, W>(g, C, members, x.a, x.b, gkeys + b.toff, gvals + b.toff, b.mask, threadIdx.x, sstart,
+                              spre);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_agg_big_compact(const BigComm* bc, const AggItem* items, uint32_t nitems,
+                                                            const uint32_t* gkeys, const unsigned long long* gvals,
+                                                            const uint64_t* cap_off, uint32_t* out_len,
+                                                            uint32_t* out_cols, int64_t* out_w, int64_t* Kout) {
+  __shared__ unsigned int s_cnt, s_base;
   __shared__ unsigned long long red[kBlock / kWave];
-  for (uint32_t item = first + blockIdx.x; item < last; item += gridDim.x) {
-    const uint32_t c = list[item];
-    const uint64_t toff = tbl_off[item - first];
-    const uint32_t mask = (uint32_t)tbl_mask[item - first];
-    uint32_t* tk = gkeys + toff;
-    unsigned long long* tv = gvals + toff;
-    for (uint64_t sl = threadIdx.x; sl <= mask; sl += kBlock) {
-      tk[sl] = kNone;
-      tv[sl] = 0;
-    }
-    if (threadIdx.x == 0) wpos = 0;
-    __syncthreads();
-    agg_accumulate<kBlock, W>(g, C, members, moff[c], moff[c + 1], tk, tv, mask, threadIdx.x, sstart, spre);
-    __syncthreads();
-    const uint64_t o = cap_off[c];
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const AggItem x = items[it];
+    const BigComm b = bc[x.big];
+    const uint64_t o = cap_off[b.c];
     unsigned long long ksum = 0;
-    for (uint64_t sl = threadIdx.x; sl <= mask; sl += kBlock) {
-      const uint32_t d = tk[sl];
-      if (d == kNone) continue;
-      const unsigned long long w = tv[sl];
-      const unsigned int p = atomicAdd(&wpos, 1u);
-      out_cols[o + p] = d;
-      out_w[o + p] = (int64_t)w;
-      ksum += w;
+    for (uint64_t sb = x.a; sb < x.b; sb += kBlock) {
+      const uint64_t sl = sb + threadIdx.x;
+      uint32_t d = kNone;
+      unsigned long long w = 0;
+      if (sl < x.b) {
+        d = gkeys[b.toff + sl];
+        w = gvals[b.toff + sl];
+      }
+      if (threadIdx.x == 0) s_cnt = 0;
+      __syncthreads();
+      unsigned int pos = 0;
+      if (d != kNone) pos = atomicAdd(&s_cnt, 1u);
+      __syncthreads();
+      if (threadIdx.x == 0 && s_cnt) s_base = atomicAdd(&out_len[b.c], s_cnt);
+      __syncthreads();
+      if (d != kNone) {
+        out_cols[o + s_base + pos] = d;
+        out_w[o + s_base + pos] = (int64_t)w;
+        ksum += w;
+      }
+      __syncthreads();
     }
     ksum = block_sum(ksum, red);
-    if (threadIdx.x == 0) {
-      out_len[c] = wpos;
-      Kout[c] = (int64_t)ksum;
-    }
-    __syncthreads();
+    if (threadIdx.x == 0 && ksum) atomicAdd((unsigned long long*)&Kout[b.c], ksum);
   }
 }
 
@@ -531,15 +592,17 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
               uint32_t* out_len, uint32_t* out_cols, int64_t* out_w, int64_t* Kout, Ctl* ctl) {
   fill_u32(s, b.comm_count, 0, nc);
   fill_u64(s, b.comm_deg, 0, nc);
-  hipLaunchKernelGGL(k_comm_stats, dim3(grid_n(n)), dim3(kBlock), 0, s, C, g.len, n, b.comm_count, b.comm_deg);
+  scatter_count(s, C, n, b.comm_count);
+  scatter_add_u32_to_u64(s, C, g.len, n, b.comm_deg);
   exclusive_scan_u32(s, b.comm_count, b.comm_off, nc, b.total, b.scan_tmp);
   (void)hipMemcpyAsync(b.comm_off + nc, b.total, sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
   fill_u32(s, b.comm_fill, 0, nc);
-  hipLaunchKernelGGL(k_comm_scatter, dim3(grid_n(n)), dim3(kBlock), 0, s, C, n, b.comm_off, b.comm_fill, b.members);
+  hipLaunchKernelGGL(k_comm_scatter, dim3(grid_n(n, 1024, 4096)), dim3(kBlock), 0, s, C, n, b.comm_off, b.comm_fill,
+                     b.members);
   hipLaunchKernelGGL(k_zero_misc_agg, dim3(1), dim3(64), 0, s, ctl);
   // capacity per community -> super-row starts
   hipLaunchKernelGGL(k_comm_classify, dim3(grid_n(nc)), dim3(kBlock), 0, s, nc, b.comm_deg, b.cap_off, out_len, Kout,
-                     b.small_lists, (size_t)nc, b.big_cap, ctl);
+                     b.small_lists, (size_t)nc, ctl);
   exclusive_scan_u64(s, b.cap_off, (uint64_t*)out_start, nc, b.total, b.scan_tmp);
   // kernel launches for small / medium communities read their counts on device
   hipLaunchKernelGGL((k_agg_lds<64, 256, W>), dim3(grid_n(nc, kBlock / 64, 2048)), dim3(kBlock), 0, s, g, C, b.members,
@@ -553,30 +616,48 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
   (void)hipMemcpyAsync(&nbig, &ctl->misc[4], sizeof(nbig), hipMemcpyDeviceToHost, s);
   if (hipStreamSynchronize(s) != hipSuccess) return -1;
   if (nbig == 0) return 0;
-  std::vector<uint64_t> caps(nbig);
-  (void)hipMemcpyAsync(caps.data(), b.big_cap, sizeof(uint64_t) * nbig, hipMemcpyDeviceToHost, s);
+  const uint32_t* big = b.small_lists + 2 * (size_t)nc;
+  hipLaunchKernelGGL(k_big_info, dim3(grid_n(nbig)), dim3(kBlock), 0, s, big, &ctl->misc[4], b.comm_off, b.cap_off,
+                     b.big_info);
+  std::vector<uint64_t> info(3 * (size_t)nbig);
+  std::vector<uint32_t> ids(nbig);
+  (void)hipMemcpyAsync(info.data(), b.big_info, sizeof(uint64_t) * 3 * nbig, hipMemcpyDeviceToHost, s);
+  (void)hipMemcpyAsync(ids.data(), big, sizeof(uint32_t) * nbig, hipMemcpyDeviceToHost, s);
   if (hipStreamSynchronize(s) != hipSuccess) return -1;
+  constexpr uint64_t kMemChunk = 256, kSlotChunk = 4096;
+  const uint64_t item_cap = b.item_cap;
   uint32_t first = 0;
   while (first < nbig) {
-    std::vector<uint64_t> offs, masks;
+    // a round: as many communities as their tables (and work items) fit
+    std::vector<BigComm> rc;
+    std::vector<AggItem> ins, cmp;
     uint64_t used = 0;
     uint32_t last = first;
     while (last < nbig) {
-      const uint64_t t = next_pow2(2 * caps[last]);
-      if (used + t > b.gcap && last > first) break;
-      if (t > b.gcap) return -2;
-      offs.push_back(used);
-      masks.push_back(t - 1);
+      const uint64_t m0 = info[3 * last], m1 = info[3 * last + 1], cap = info[3 * last + 2];
+      const uint64_t t = next_pow2(2 * cap);
+      const uint64_t nitems = (m1 - m0 + kMemChunk - 1) / kMemChunk + (t + kSlotChunk - 1) / kSlotChunk;
+      if (t > b.gcap || nitems > item_cap) return -2;
+      if (last > first && (used + t > b.gcap || ins.size() + cmp.size() + nitems > item_cap)) break;
+      const uint32_t r = (uint32_t)rc.size();
+      rc.push_back(BigComm{ids[last], (uint32_t)(t - 1), used});
+      for (uint64_t a = m0; a < m1; a += kMemChunk) ins.push_back(AggItem{r, 0, a, std::min(m1, a + kMemChunk)});
+      for (uint64_t a = 0; a < t; a += kSlotChunk) cmp.push_back(AggItem{r, 0, a, std::min(t, a + kSlotChunk)});
       used += t;
       ++last;
     }
-    (void)hipMemcpyAsync(b.tbl_off, offs.data(), sizeof(uint64_t) * offs.size(), hipMemcpyHostToDevice, s);
-    (void)hipMemcpyAsync(b.tbl_off + nbig + 1, masks.data(), sizeof(uint64_t) * masks.size(), hipMemcpyHostToDevice, s);
-    const int grid = (int)std::min<uint32_t>(last - first, 1024);
-    hipLaunchKernelGGL(k_agg_global<W>, dim3(grid), dim3(kBlock), 0, s, g, C, b.members, b.comm_off,
-                       b.small_lists + 2 * (size_t)nc, first, last, b.tbl_off, b.tbl_off + nbig + 1, b.gkeys, b.gvals,
+    AggItem* di = (AggItem*)b.items;
+    (void)hipMemcpyAsync(b.bigc, rc.data(), sizeof(BigComm) * rc.size(), hipMemcpyHostToDevice, s);
+    (void)hipMemcpyAsync(di, ins.data(), sizeof(AggItem) * ins.size(), hipMemcpyHostToDevice, s);
+    (void)hipMemcpyAsync(di + ins.size(), cmp.data(), sizeof(AggItem) * cmp.size(), hipMemcpyHostToDevice, s);
+    fill_u32(s, b.gkeys, kNone, used);
+    fill_u64(s, (uint64_t*)b.gvals, 0, used);
+    hipLaunchKernelGGL(k_agg_big_insert<W>, dim3(std::min<size_t>(ins.size(), 4096)), dim3(kBlock), 0, s, g, C,
+                       b.members, (const BigComm*)b.bigc, di, (uint32_t)ins.size(), b.gkeys, b.gvals);
+    hipLaunchKernelGGL(k_agg_big_compact, dim3(std::min<size_t>(cmp.size(), 4096)), dim3(kBlock), 0, s,
+                       (const BigComm*)b.bigc, di + ins.size(), (uint32_t)cmp.size(), b.gkeys, b.gvals,
                        (const uint64_t*)out_start, out_len, out_cols, out_w, Kout);
-    if (hipStreamSynchronize(s) != hipSuccess) return -1;
+    if (hipStreamSynchronize(s) != hipSuccess) return -1;  // host vectors must outlive the copies
     first = last;
   }
   return 0;
@@ -590,10 +671,6 @@ template int aggregate<int64_t>(hipStream_t, Rows<int64_t>, uint32_t, const uint
 // ---------------------------------------------------------------------------
 // Static output labels: dense, ordered by each community's minimum vertex.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_min_vertex(const uint32_t* C, uint32_t n, uint32_t* minv) {
-  GRID_STRIDE(i, n) atomicMin(&minv[C[i]], (uint32_t)i);
-}
-
 __global__ __launch_bounds__(kBlock) void k_first_flag(const uint32_t* C, uint32_t n, const uint32_t* minv,
                                                        uint32_t* flag) {
   GRID_STRIDE(i, n) flag[i] = minv[C[i]] == (uint32_t)i ? 1u : 0u;
@@ -608,7 +685,7 @@ void launch_static_relabel(hipStream_t s, const uint32_t* C, uint32_t n, uint32_
                            uint64_t* rank, uint32_t* out, void* scan_tmp, uint64_t* total) {
   if (n == 0) return;
   fill_u32(s, minv, kNone, n);
-  hipLaunchKernelGGL(k_min_vertex, dim3(grid_n(n)), dim3(kBlock), 0, s, C, n, minv);
+  scatter_min_index(s, C, n, minv);
   hipLaunchKernelGGL(k_first_flag, dim3(grid_n(n)), dim3(kBlock), 0, s, C, n, minv, flag);
   exclusive_scan_u32(s, flag, rank, n, total, scan_tmp);
   hipLaunchKernelGGL(k_rank_label, dim3(grid_n(n)), dim3(kBlock), 0, s, C, n, minv, rank, out);
@@ -619,17 +696,20 @@ void launch_static_relabel(hipStream_t s, const uint32_t* C, uint32_t n, uint32_
 // T = sum Sigma_c^2 as a 128-bit integer.  The host forms
 // Q = sigma / 2m - T / (2m)^2.
 // ---------------------------------------------------------------------------
+// sigma partial sums, one wavefront per row
 __global__ __launch_bounds__(kBlock) void k_mod_sigma(Rows<uint32_t> g, uint32_t n, const uint32_t* C,
-                                                      const int64_t* K, int64_t* Sig, unsigned long long* partials) {
+                                                      unsigned long long* partials) {
   __shared__ unsigned long long red[kBlock / kWave];
+  const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const uint32_t lane = threadIdx.x % kWave;
+  const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
   unsigned long long sig = 0;
-  GRID_STRIDE(i, n) {
+  for (uint64_t i = wave; i < n; i += nwaves) {
     const uint32_t c = C[i];
     const int64_t s0 = g.start[i];
     const uint32_t L = g.len[i];
-    for (uint32_t e = 0; e < L; ++e)
+    for (uint32_t e = lane; e < L; e += kWave)
       if (C[g.cols[s0 + e]] == c) sig += g.w[s0 + e];
-    atomicAdd((unsigned long long*)&Sig[c], (unsigned long long)K[i]);
   }
   sig = block_sum(sig, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = sig;
@@ -676,7 +756,8 @@ __global__ void k_mod_final(const unsigned long long* sig_part, const unsigned l
 void modularity_parts(hipStream_t s, Rows<uint32_t> g, uint32_t n, const uint32_t* C, const int64_t* K, int64_t* Sig,
                       unsigned long long* partials, int nblocks, ModParts* out_dev) {
   fill_i64(s, Sig, 0, n);
-  hipLaunchKernelGGL(k_mod_sigma, dim3(nblocks), dim3(kBlock), 0, s, g, n, C, K, Sig, partials);
+  scatter_add_i64(s, C, K, n, Sig);
+  hipLaunchKernelGGL(k_mod_sigma, dim3(nblocks), dim3(kBlock), 0, s, g, n, C, partials);
   hipLaunchKernelGGL(k_mod_square, dim3(nblocks), dim3(kBlock), 0, s, n, Sig, partials + nblocks);
   hipLaunchKernelGGL(k_mod_final, dim3(1), dim3(1), 0, s, partials, partials + nblocks, nblocks, out_dev);
 }
@@ -694,25 +775,56 @@ __device__ inline uint64_t pair_slot(unsigned long long key, uint64_t mask) {
   return ((key * 0x9E3779B97F4A7C15ull) >> 17) & mask;
 }
 
+__device__ inline uint64_t pair_insert(unsigned long long* hk, uint64_t mask, unsigned long long key) {
+  uint64_t h = pair_slot(key, mask);
+  while (true) {
+    const unsigned long long k = __atomic_load_n(&hk[h], __ATOMIC_RELAXED);
+    if (k == key) return h;
+    if (k == kNone64) {
+      const unsigned long long o = atomicCAS(&hk[h], kNone64, key);
+      if (o == kNone64 || o == key) return h;
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+// Overlap weights of (old, current) community pairs.  Each tile of 1024
+// vertices first sums its pairs in LDS (unchanged communities make a few
+// pairs very hot), then adds each distinct pair once to the global table.
 __global__ __launch_bounds__(kBlock) void k_track_pairs(uint32_t n, const uint32_t* Ccur, const uint32_t* Cprev,
                                                         const int64_t* K, unsigned long long* hk, long long* hv,
-                                                        uint64_t mask, uint32_t* minv, uint32_t* is_old) {
-  GRID_STRIDE(i, n) {
-    const uint32_t c = Ccur[i], b = Cprev[i];
-    atomicMin(&minv[c], (uint32_t)i);
-    is_old[b] = 1;
-    const unsigned long long key = ((unsigned long long)b << 32) | c;
-    uint64_t h = pair_slot(key, mask);
-    while (true) {
-      const unsigned long long k = __atomic_load_n(&hk[h], __ATOMIC_RELAXED);
-      if (k == key) break;
-      if (k == kNone64) {
-        const unsigned long long o = atomicCAS(&hk[h], kNone64, key);
-        if (o == kNone64 || o == key) break;
-      }
-      h = (h + 1) & mask;
+                                                        uint64_t mask, uint32_t* is_old) {
+  constexpr int kTile = 1024, kSlots = 2048;
+  __shared__ unsigned long long lk[kSlots];
+  __shared__ unsigned long long lv[kSlots];
+  for (uint64_t base = (uint64_t)blockIdx.x * kTile; base < n; base += (uint64_t)gridDim.x * kTile) {
+    for (int s = threadIdx.x; s < kSlots; s += kBlock) {
+      lk[s] = kNone64;
+      lv[s] = 0;
     }
-    atomicAdd((unsigned long long*)&hv[h], (unsigned long long)K[i]);
+    __syncthreads();
+    for (int t = threadIdx.x; t < kTile; t += kBlock) {
+      const uint64_t i = base + t;
+      if (i >= n) continue;
+      const uint32_t b = Cprev[i];
+      is_old[b] = 1;
+      const unsigned long long key = ((unsigned long long)b << 32) | Ccur[i];
+      uint32_t h = (uint32_t)pair_slot(key, kSlots - 1);
+      while (true) {
+        const unsigned long long o = atomicCAS(&lk[h], kNone64, key);
+        if (o == kNone64 || o == key) break;
+        h = (h + 1) & (kSlots - 1);
+      }
+      atomicAdd(&lv[h], (unsigned long long)K[i]);
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < kSlots; s += kBlock) {
+      const unsigned long long key = lk[s];
+      if (key == kNone64) continue;
+      const uint64_t h = pair_insert(hk, mask, key);
+      atomicAdd((unsigned long long*)&hv[h], lv[s]);
+    }
+    __syncthreads();
   }
 }
 
@@ -796,8 +908,9 @@ void track(hipStream_t s, uint32_t n, const uint32_t* Ccur, const uint32_t* Cpre
   fill_u32(s, b.is_old, 0, n);
   fill_u64(s, (uint64_t*)b.hkeys, ~0ull, slots);
   fill_u64(s, (uint64_t*)b.hvals, 0, slots);
-  hipLaunchKernelGGL(k_track_pairs, dim3(grid_n(n)), dim3(kBlock), 0, s, n, Ccur, Cprev, K, b.hkeys, b.hvals, b.hmask,
-                     b.minv, b.is_old);
+  scatter_min_index(s, Ccur, n, b.minv);
+  hipLaunchKernelGGL(k_track_pairs, dim3(grid_n(n, 1024, 4096)), dim3(kBlock), 0, s, n, Ccur, Cprev, K, b.hkeys,
+                     b.hvals, b.hmask, b.is_old);
   fill_i64(s, (int64_t*)b.best_w, -1, n);
   fill_u32(s, b.best_vmin, kNone, n);
   hipLaunchKernelGGL(k_track_best_w, dim3(grid_n(slots)), dim3(kBlock), 0, s, b.hkeys, b.hvals, slots, b.best_w);

@@ -68,6 +68,8 @@ struct Buf {
   }
 };
 
+constexpr uint64_t kAggItems = 1 << 20;  // aggregation work items per round of big communities
+
 uint64_t next_pow2(uint64_t x) {
   uint64_t p = 1;
   while (p < x) p <<= 1;
@@ -109,7 +111,8 @@ struct leiden_graph {
   Buf cls_lists, bin_lists, iter_list, next_list, movers, split_list, lab;
   Buf flag, newid, scan_tmp, ctl, small;
   Buf lvA_start, lvA_len, lvA_cols, lvA_w, lvB_start, lvB_len, lvB_cols, lvB_w;
-  Buf agg_count, agg_off, agg_fill, agg_members, agg_deg, agg_cap, agg_lists, agg_bigcap, agg_tbl, agg_keys, agg_vals;
+  Buf agg_count, agg_off, agg_fill, agg_members, agg_deg, agg_cap, agg_lists, agg_bigcap, agg_tbl, agg_keys, agg_vals,
+      agg_items, big_list;
   Buf hub_keys, hub_vals;
   Buf tr_minv, tr_hk, tr_hv, tr_bw, tr_bv, tr_cw, tr_cb, tr_old, tr_flag, tr_rank, tr_frank, tr_fid, tr_label,
       tr_matched;
@@ -193,8 +196,10 @@ leiden_status ensure_workspace(leiden_graph* G, uint32_t classes) {
   CHK(G->agg_deg.reserve(n * u64));
   CHK(G->agg_cap.reserve((n + 1) * u64));
   CHK(G->agg_lists.reserve(3 * n * u32));
-  CHK(G->agg_bigcap.reserve(n * u64));
-  CHK(G->agg_tbl.reserve((2 * n + 2) * u64));
+  CHK(G->agg_bigcap.reserve(3 * n * u64));
+  CHK(G->agg_tbl.reserve(n * 16));
+  CHK(G->agg_items.reserve(kAggItems * 24));
+  CHK(G->big_list.reserve(n * u32));
   const uint64_t gcap = std::max<uint64_t>(2 * next_pow2(2 * n), 1 << 16);
   CHK(G->agg_keys.reserve(gcap * u32));
   CHK(G->agg_vals.reserve(gcap * u64));
@@ -350,7 +355,8 @@ leiden_status local_move(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
       ap.cls_lists = G->cls_lists.as<uint32_t>();
       ap.cls_stride = nl;
       ap.next_list = next_list;
-      launch_apply_moves(s, ap, nl);
+      ap.big_list = G->big_list.as<uint32_t>();
+      launch_apply_moves(s, ap, nl, maxdeg > kBigRow);
     }
     CHK(read_ctl(G, s));
     out.iters = li + 1;
@@ -461,8 +467,10 @@ leiden_status next_level(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
   ab.total = total;
   ab.scan_tmp = G->scan_tmp.p;
   ab.small_lists = G->agg_lists.as<uint32_t>();
-  ab.big_cap = G->agg_bigcap.as<uint64_t>();
-  ab.tbl_off = G->agg_tbl.as<uint64_t>();
+  ab.big_info = G->agg_bigcap.as<uint64_t>();
+  ab.bigc = G->agg_tbl.p;
+  ab.items = G->agg_items.p;
+  ab.item_cap = kAggItems;
   ab.gkeys = G->agg_keys.as<uint32_t>();
   ab.gvals = G->agg_vals.as<unsigned long long>();
   ab.gcap = G->agg_keys.bytes / 4;
