@@ -20,10 +20,28 @@ struct DecideParams {
   const unsigned int* count;
   Mover* movers;
   Ctl* ctl;
-  uint32_t* hub_keys;  // global tables of the hub bin
+  // hub bin: every hub of the level owns a clean table in the arena
+  const uint32_t* hub_idx;   // vertex -> hub index (hubs only)
+  const uint64_t* hub_off;   // hub index -> first slot in the arena
+  const uint32_t* hub_mask;  // hub index -> slots - 1
+  unsigned long long* hub_kid;  // hub index -> K_{i->d} accumulator (kept zero between uses)
+  uint32_t* hub_keys;
   unsigned long long* hub_vals;
-  uint32_t hub_mask;
 };
+
+// Hub layout of one level: hubs (degree above the last LDS bin) get table
+// regions of pow2(2 * degree) slots in one arena.
+struct HubLayout {
+  uint32_t* list;       // hubs of the level
+  uint32_t* idx;        // vertex -> hub index (valid for hubs)
+  uint64_t* off;        // hub index -> arena offset (count + 1)
+  uint32_t* mask;       // hub index -> slots - 1
+  uint64_t* size_tmp;   // scratch (count)
+  unsigned long long* kid;
+};
+// fills list / idx / off / mask for the level; returns the arena slots needed in *slots
+int hub_layout(hipStream_t s, const uint32_t* len, uint32_t nl, HubLayout& h, Ctl* ctl, void* scan_tmp,
+               uint64_t* total_dev, uint32_t* count_out, uint64_t* slots_out);
 
 struct ApplyParams {
   const int64_t* start;
@@ -51,9 +69,10 @@ void launch_distribute(hipStream_t s, const uint32_t* in_list, const unsigned in
                        size_t stride, Ctl* ctl);
 void launch_bin(hipStream_t s, const uint32_t* list, const unsigned int* count, uint32_t n_upper, const uint32_t* len,
                 const uint8_t* in_range, uint32_t* bin_lists, size_t stride, Ctl* ctl);
+// maxdeg: largest degree of the level (sizes the hub kernels)
 template <typename W, bool REFINE>
 void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, size_t stride, unsigned int* bin_counts,
-                       const uint64_t* bin_upper, int hub_grid);
+                       const uint64_t* bin_upper, uint32_t maxdeg);
 // long_rows: the level has rows longer than the wavefront path handles
 void launch_apply_moves(hipStream_t s, const ApplyParams& p, uint32_t n_upper, bool long_rows);
 void launch_apply_refine(hipStream_t s, uint32_t* C, int64_t* S, const int64_t* K, uint32_t* size,

@@ -11,6 +11,10 @@
 
 namespace lm {
 
+static int grid_for(uint64_t items, int per_block, int cap);
+
+__global__ void k_clear_misc6(Ctl* ctl) { ctl->misc[6] = 0; }
+
 // ---------------------------------------------------------------------------
 // Class distribution (start of a local-moving iteration)
 // ---------------------------------------------------------------------------
@@ -159,29 +163,20 @@ __global__ __launch_bounds__(kBlock) void k_decide_group(DecideParams<W> p) {
   if (edges) atomicAdd(&p.ctl->edges, edges);
 }
 
-// One block (kBlock lanes) per vertex.  HUB keeps the T-slot table in the
-// block's region of global scratch instead of LDS (T = hub_mask + 1).
-template <int T, typename W, bool REFINE, bool HUB>
+// One block (kBlock lanes) per vertex, T-slot table in LDS.
+template <int T, typename W, bool REFINE>
 __global__ __launch_bounds__(kBlock) void k_decide_block(DecideParams<W> p) {
-  __shared__ uint32_t lkeys[HUB ? 1 : T];
-  __shared__ unsigned long long lvals[HUB ? 1 : T];
+  __shared__ uint32_t tk[T];
+  __shared__ unsigned long long tv[T];
   __shared__ unsigned long long red[kBlock / kWave];
   __shared__ double rdq[kBlock / kWave];
   __shared__ uint32_t rc[kBlock / kWave];
-  uint32_t* tk = lkeys;
-  unsigned long long* tv = lvals;
-  uint32_t mask = T - 1;
-  if (HUB) {
-    tk = p.hub_keys + (size_t)blockIdx.x * (p.hub_mask + 1);
-    tv = p.hub_vals + (size_t)blockIdx.x * (p.hub_mask + 1);
-  }
+  constexpr uint32_t mask = T - 1;
   const uint32_t cnt = *p.count;
   unsigned long long edges = 0;
   for (uint32_t item = blockIdx.x; item < cnt; item += gridDim.x) {
     const uint32_t v = p.list[item];
     const uint32_t d = p.C[v];
-    // a hub's table holds at least twice its degree (never more than the region)
-    if (HUB) mask = min(p.hub_mask, pow2_at_least(2 * p.g.len[v]) - 1);
     for (uint32_t s = threadIdx.x; s <= mask; s += kBlock) {
       tk[s] = kNone;
       tv[s] = 0;
@@ -227,6 +222,150 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(DecideParams<W> p) {
     __syncthreads();
   }
   if (edges) atomicAdd(&p.ctl->edges, edges);
+}
+
+// ---------------------------------------------------------------------------
+// Hub bin: all blocks share every hub's row.  Each block sums a chunk of
+// 2048 entries by community in LDS and adds each distinct community once to
+// the hub's global table (and K_{i->d} to its accumulator); then one block per
+// hub picks the best community from the table and clears it for the next use.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kHubChunk = 2048, kHubSlots = 4096;
+
+template <typename W, bool REFINE>
+__global__ __launch_bounds__(kBlock) void k_hub_insert(DecideParams<W> p) {
+  __shared__ uint32_t lk[kHubSlots];
+  __shared__ unsigned long long lv[kHubSlots];
+  __shared__ unsigned long long red[kBlock / kWave];
+  for (int s = threadIdx.x; s < (int)kHubSlots; s += kBlock) {
+    lk[s] = kNone;
+    lv[s] = 0;
+  }
+  __syncthreads();
+  const uint32_t cnt = *p.count;
+  unsigned long long edges = 0;
+  for (uint32_t h = 0; h < cnt; ++h) {
+    const uint32_t v = p.list[h];
+    const uint32_t d = p.C[v];
+    if (REFINE && p.size[d] != 1) continue;  // block-uniform
+    const uint32_t hi = p.hub_idx[v];
+    uint32_t* tk = p.hub_keys + p.hub_off[hi];
+    unsigned long long* tv = p.hub_vals + p.hub_off[hi];
+    const uint32_t mask = p.hub_mask[hi];
+    const int64_t s0 = p.g.start[v];
+    const uint32_t L = p.g.len[v];
+    const uint32_t bnd = REFINE ? p.CB[v] : 0;
+    // chunk c of hub h goes to block (c + 97 h) mod grid, spreading the first
+    // chunks of consecutive hubs over different blocks
+    const uint32_t rot = (uint32_t)(((uint64_t)h * 97u) % gridDim.x);
+    const uint32_t first = (blockIdx.x + gridDim.x - rot) % gridDim.x;
+    for (uint32_t cb = first * kHubChunk; cb < L; cb += gridDim.x * kHubChunk) {
+      const uint32_t ce = min(L, cb + kHubChunk);
+      unsigned long long kid = 0;
+      for (uint32_t e = cb + threadIdx.x; e < ce; e += kBlock) {
+        const uint32_t j = p.g.cols[s0 + e];
+        if (j == v) continue;
+        if (REFINE && p.CB[j] != bnd) continue;
+        const uint32_t c = p.C[j];
+        const unsigned long long w = (unsigned long long)p.g.w[s0 + e];
+        if (c == d)
+          kid += w;
+        else
+          table_add(lk, lv, kHubSlots - 1, c, w);
+      }
+      if (!REFINE && threadIdx.x == 0) edges += ce - cb;
+      kid = block_sum(kid, red);
+      if (threadIdx.x == 0 && kid) atomicAdd(&p.hub_kid[hi], kid);
+      for (int s = threadIdx.x; s < (int)kHubSlots; s += kBlock) {
+        const uint32_t k = lk[s];
+        if (k == kNone) continue;
+        table_add(tk, tv, mask, k, lv[s]);
+        lk[s] = kNone;
+        lv[s] = 0;
+      }
+      __syncthreads();
+    }
+  }
+  if (edges) atomicAdd(&p.ctl->edges, edges);
+}
+
+template <typename W, bool REFINE>
+__global__ __launch_bounds__(kBlock) void k_hub_select(DecideParams<W> p) {
+  __shared__ double rdq[kBlock / kWave];
+  __shared__ uint32_t rc[kBlock / kWave];
+  const uint32_t cnt = *p.count;
+  for (uint32_t h = blockIdx.x; h < cnt; h += gridDim.x) {
+    const uint32_t v = p.list[h];
+    const uint32_t d = p.C[v];
+    const bool valid = !(REFINE && p.size[d] != 1);
+    const uint32_t hi = p.hub_idx[v];
+    uint32_t* tk = p.hub_keys + p.hub_off[hi];
+    unsigned long long* tv = p.hub_vals + p.hub_off[hi];
+    const uint32_t mask = p.hub_mask[hi];
+    const int64_t kid = (int64_t)p.hub_kid[hi];
+    const int64_t ki = p.K[v], sd = p.S[d];
+    double bdq = -INFINITY;
+    uint32_t bc = kNone;
+    for (uint32_t s = threadIdx.x; s <= mask; s += kBlock) {
+      const uint32_t c = tk[s];
+      if (c == kNone) continue;
+      const int64_t kic = (int64_t)tv[s];
+      tk[s] = kNone;
+      tv[s] = 0;
+      if (!valid || !allowed_target<W, REFINE>(p, c)) continue;
+      const double dq = delta_q(kic, kid, ki, p.S[c], sd, p.inv_m, p.inv_2m2);
+      if (better(dq, c, bdq, bc)) {
+        bdq = dq;
+        bc = c;
+      }
+    }
+    block_best(bdq, bc, rdq, rc);
+    if (threadIdx.x == 0) {
+      p.hub_kid[hi] = 0;
+      if (valid) emit_decision<W, REFINE>(p, v, d, bdq, bc);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_hub_list(const uint32_t* len, uint32_t nl, uint32_t* list, Ctl* ctl) {
+  __shared__ unsigned int s2[2];
+  for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < nl; base += (uint64_t)gridDim.x * kBlock) {
+    const uint64_t i = base + threadIdx.x;
+    const bool hub = i < nl && len[i] > kBinMaxDeg[kBins - 2];
+    block_append(list, &ctl->misc[6], hub, (uint32_t)i, s2);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_hub_sizes(const uint32_t* len, uint32_t cnt, HubLayout h) {
+  for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < cnt; k += gridDim.x * kBlock) {
+    const uint32_t v = h.list[k];
+    const uint32_t t = pow2_at_least(2 * len[v]);
+    h.size_tmp[k] = t;
+    h.mask[k] = t - 1;
+    h.idx[v] = k;
+  }
+}
+
+int hub_layout(hipStream_t s, const uint32_t* len, uint32_t nl, HubLayout& h, Ctl* ctl, void* scan_tmp,
+               uint64_t* total_dev, uint32_t* count_out, uint64_t* slots_out) {
+  hipLaunchKernelGGL(k_clear_misc6, dim3(1), dim3(1), 0, s, ctl);
+  hipLaunchKernelGGL(k_hub_list, dim3(grid_for(nl, kBlock, 4096)), dim3(kBlock), 0, s, len, nl, h.list, ctl);
+  unsigned int cnt = 0;
+  if (hipMemcpyAsync(&cnt, &ctl->misc[6], sizeof(cnt), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return -1;
+  *count_out = cnt;
+  *slots_out = 0;
+  if (cnt == 0) return 0;
+  hipLaunchKernelGGL(k_hub_sizes, dim3(grid_for(cnt, kBlock, 1024)), dim3(kBlock), 0, s, len, cnt, h);
+  exclusive_scan_u64(s, h.size_tmp, h.off, cnt, total_dev, scan_tmp);
+  uint64_t slots = 0;
+  if (hipMemcpyAsync(&slots, total_dev, sizeof(slots), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return -1;
+  *slots_out = slots;
+  return 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -356,9 +495,9 @@ void launch_bin(hipStream_t s, const uint32_t* list, const unsigned int* count, 
 
 template <typename W, bool REFINE>
 void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, size_t stride, unsigned int* bin_counts,
-                       const uint64_t* bin_upper, int hub_grid) {
+                       const uint64_t* bin_upper, uint32_t maxdeg) {
   // bin 0: 8 lanes / 16 slots, bin 1: 32 / 64, bin 2: 64 / 256,
-  // bin 3: block / 1024, bin 4: block / 4096, bin 5: block / global table
+  // bin 3: block / 1024, bin 4: block / 4096, bin 5: hubs (all blocks per hub)
   for (int b = 0; b < kBins; ++b) {
     if (bin_upper[b] == 0) continue;
     DecideParams<W> q = p;
@@ -378,29 +517,30 @@ void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, si
                            dim3(kBlock), 0, s, q);
         break;
       case 3:
-        hipLaunchKernelGGL((k_decide_block<1024, W, REFINE, false>), dim3(grid_for(bin_upper[b], 1, 2048)),
-                           dim3(kBlock), 0, s, q);
+        hipLaunchKernelGGL((k_decide_block<1024, W, REFINE>), dim3(grid_for(bin_upper[b], 1, 2048)), dim3(kBlock), 0,
+                           s, q);
         break;
       case 4:
-        hipLaunchKernelGGL((k_decide_block<4096, W, REFINE, false>), dim3(grid_for(bin_upper[b], 1, 1024)),
-                           dim3(kBlock), 0, s, q);
+        hipLaunchKernelGGL((k_decide_block<4096, W, REFINE>), dim3(grid_for(bin_upper[b], 1, 1024)), dim3(kBlock), 0,
+                           s, q);
         break;
       default:
-        hipLaunchKernelGGL((k_decide_block<1, W, REFINE, true>), dim3(grid_for(bin_upper[b], 1, hub_grid)),
+        hipLaunchKernelGGL((k_hub_insert<W, REFINE>), dim3(grid_for(bin_upper[b] * (maxdeg / kHubChunk + 1), 1, 1024)),
                            dim3(kBlock), 0, s, q);
+        hipLaunchKernelGGL((k_hub_select<W, REFINE>), dim3(grid_for(bin_upper[b], 1, 1024)), dim3(kBlock), 0, s, q);
         break;
     }
   }
 }
 
 template void launch_decide_all<uint32_t, false>(hipStream_t, DecideParams<uint32_t>, uint32_t*, size_t,
-                                                 unsigned int*, const uint64_t*, int);
+                                                 unsigned int*, const uint64_t*, uint32_t);
 template void launch_decide_all<uint32_t, true>(hipStream_t, DecideParams<uint32_t>, uint32_t*, size_t,
-                                                unsigned int*, const uint64_t*, int);
+                                                unsigned int*, const uint64_t*, uint32_t);
 template void launch_decide_all<int64_t, false>(hipStream_t, DecideParams<int64_t>, uint32_t*, size_t,
-                                                unsigned int*, const uint64_t*, int);
+                                                unsigned int*, const uint64_t*, uint32_t);
 template void launch_decide_all<int64_t, true>(hipStream_t, DecideParams<int64_t>, uint32_t*, size_t, unsigned int*,
-                                               const uint64_t*, int);
+                                               const uint64_t*, uint32_t);
 
 void launch_apply_moves(hipStream_t s, const ApplyParams& p, uint32_t n_upper, bool long_rows) {
   hipLaunchKernelGGL(k_apply_moves, dim3(grid_for(n_upper, kBlock / kWave, 2048)), dim3(kBlock), 0, s, p);

@@ -152,6 +152,11 @@ __device__ inline uint32_t find_root(uint32_t* lab, uint32_t x) {
   }
 }
 
+// One round of minimum-label propagation: each vertex takes the smallest
+// label among itself and its same-community neighbours (a wavefront
+// reduction, no per-edge atomics) and hooks its current parent to it.  Labels
+// only decrease and always name a vertex of the same component, so the
+// fixpoint labels every component by its minimum vertex.
 template <typename W>
 __global__ __launch_bounds__(kBlock) void k_split_hook(Rows<W> g, const uint32_t* C, uint32_t* lab,
                                                        const uint32_t* list, Ctl* ctl) {
@@ -164,12 +169,19 @@ __global__ __launch_bounds__(kBlock) void k_split_hook(Rows<W> g, const uint32_t
     const uint32_t c = C[i];
     const int64_t s0 = g.start[i];
     const uint32_t L = g.len[i];
+    uint32_t m = __atomic_load_n(&lab[i], __ATOMIC_RELAXED);
     for (uint32_t e = lane; e < L; e += kWave) {
       const uint32_t j = g.cols[s0 + e];
       if (j == i || C[j] != c) continue;
-      const uint32_t ri = find_root(lab, i), rj = find_root(lab, j);
-      if (ri != rj) {
-        atomicMin(&lab[ri > rj ? ri : rj], ri < rj ? ri : rj);
+      m = min(m, __atomic_load_n(&lab[j], __ATOMIC_RELAXED));
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) m = min(m, (uint32_t)__shfl_xor(m, o, kWave));
+    if (lane == 0) {
+      const uint32_t li = __atomic_load_n(&lab[i], __ATOMIC_RELAXED);
+      if (m < li) {
+        atomicMin(&lab[i], m);
+        atomicMin(&lab[li], m);
         changed = true;
       }
     }
@@ -525,17 +537,71 @@ struct AggItem {
   uint64_t a, b;
 };
 
+// Each item's entries are summed by key in an LDS table, 2048 entries at a
+// time, and each distinct key is then added once to the community's global
+// table: a community's internal edges all carry the same key, and adding them
+// one by one would serialise on one global slot.
 template <typename W>
 __global__ __launch_bounds__(kBlock) void k_agg_big_insert(Rows<W> g, const uint32_t* C, const uint32_t* members,
                                                            const BigComm* bc, const AggItem* items, uint32_t nitems,
                                                            uint32_t* gkeys, unsigned long long* gvals) {
+  constexpr uint32_t kStage = 2048, kSlots = 4096;
   __shared__ int64_t sstart[kBlock];
   __shared__ uint32_t spre[kBlock];
+  __shared__ uint32_t lk[kSlots];
+  __shared__ unsigned long long lv[kSlots];
+  for (int s = threadIdx.x; s < (int)kSlots; s += kBlock) {
+    lk[s] = kNone;
+    lv[s] = 0;
+  }
+  __syncthreads();
   for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const AggItem x = items[it];
     const BigComm b = bc[x.big];
-    agg_accumulate<kBlock, W>(g, C, members, x.a, x.b, gkeys + b.toff, gvals + b.toff, b.mask, threadIdx.x, sstart,
-                              spre);
+    uint32_t* tk = gkeys + b.toff;
+    unsigned long long* tv = gvals + b.toff;
+    for (uint64_t mb = x.a; mb < x.b; mb += kBlock) {
+      const uint64_t mi = mb + threadIdx.x;
+      uint32_t L = 0;
+      int64_t st = 0;
+      if (mi < x.b) {
+        const uint32_t v = members[mi];
+        L = g.len[v];
+        st = g.start[v];
+      }
+      sstart[threadIdx.x] = st;
+      spre[threadIdx.x] = L;
+      __syncthreads();
+      if (threadIdx.x == 0)
+        for (int q = 1; q < kBlock; ++q) spre[q] += spre[q - 1];
+      __syncthreads();
+      const uint32_t total = spre[kBlock - 1];
+      for (uint32_t xb = 0; xb < total; xb += kStage) {
+        const uint32_t xe = min(total, xb + kStage);
+        for (uint32_t xx = xb + threadIdx.x; xx < xe; xx += kBlock) {
+          int lo = 0, hi = kBlock - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (spre[mid] > xx)
+              hi = mid;
+            else
+              lo = mid + 1;
+          }
+          const uint32_t before = lo > 0 ? spre[lo - 1] : 0;
+          const int64_t e = sstart[lo] + (xx - before);
+          table_add(lk, lv, kSlots - 1, C[g.cols[e]], (unsigned long long)g.w[e]);
+        }
+        __syncthreads();
+        for (int s = threadIdx.x; s < (int)kSlots; s += kBlock) {
+          const uint32_t k = lk[s];
+          if (k == kNone) continue;
+          table_add(tk, tv, b.mask, k, lv[s]);
+          lk[s] = kNone;
+          lv[s] = 0;
+        }
+        __syncthreads();
+      }
+    }
   }
 }
 

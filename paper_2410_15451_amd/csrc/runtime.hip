@@ -113,7 +113,7 @@ struct leiden_graph {
   Buf lvA_start, lvA_len, lvA_cols, lvA_w, lvB_start, lvB_len, lvB_cols, lvB_w;
   Buf agg_count, agg_off, agg_fill, agg_members, agg_deg, agg_cap, agg_lists, agg_bigcap, agg_tbl, agg_keys, agg_vals,
       agg_items, big_list;
-  Buf hub_keys, hub_vals;
+  Buf hub_keys, hub_vals, hub_list, hub_idx, hub_off, hub_mask, hub_size, hub_kid;
   Buf tr_minv, tr_hk, tr_hv, tr_bw, tr_bv, tr_cw, tr_cb, tr_old, tr_flag, tr_rank, tr_frank, tr_fid, tr_label,
       tr_matched;
   Buf dV, dE, dC, sig, partials, modparts;
@@ -232,18 +232,46 @@ leiden_status ensure_workspace(leiden_graph* G, uint32_t classes) {
   return LEIDEN_OK;
 }
 
-leiden_status ensure_hub(leiden_graph* G, uint32_t maxdeg, uint32_t* mask_out, int* grid_out) {
-  const uint64_t T = next_pow2(2 * (uint64_t)std::max<uint32_t>(maxdeg, 1));
-  const uint64_t budget = 1ull << 25;
-  int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(256, budget / T));
-  CHK(G->hub_keys.reserve(T * grid * 4));
-  CHK(G->hub_vals.reserve(T * grid * 8));
-  *mask_out = (uint32_t)(T - 1);
-  *grid_out = grid;
+Ctl* dctl(leiden_graph* G) { return G->ctl.as<Ctl>(); }
+
+// Hub tables of the current level: every hub gets a clean region of the
+// arena (the select kernel clears what it reads, so the arena stays clean).
+leiden_status setup_hubs(leiden_graph* G, hipStream_t s, const uint32_t* len, uint32_t nl) {
+  const size_t n = std::max<size_t>(G->n, 1);
+  CHK(G->hub_list.reserve(n * 4));
+  CHK(G->hub_idx.reserve(n * 4));
+  CHK(G->hub_off.reserve((n + 1) * 8));
+  CHK(G->hub_mask.reserve(n * 4));
+  CHK(G->hub_size.reserve(n * 8));
+  if (G->hub_kid.bytes < n * 8) {
+    CHK(G->hub_kid.reserve(n * 8));
+    HIPCHK(hipMemsetAsync(G->hub_kid.p, 0, n * 8, s));
+  }
+  HubLayout h{G->hub_list.as<uint32_t>(), G->hub_idx.as<uint32_t>(), G->hub_off.as<uint64_t>(),
+              G->hub_mask.as<uint32_t>(), G->hub_size.as<uint64_t>(), G->hub_kid.as<unsigned long long>()};
+  uint32_t cnt = 0;
+  uint64_t slots = 0;
+  if (hub_layout(s, len, nl, h, dctl(G), G->scan_tmp.p, G->small.as<uint64_t>() + 64, &cnt, &slots) != 0)
+    return fail(LEIDEN_EDEVICE, "hub layout failed");
+  if (slots * 4 > G->hub_keys.bytes || slots * 8 > G->hub_vals.bytes) {
+    const uint64_t want = slots + slots / 4 + 4096;
+    CHK(G->hub_keys.reserve(want * 4));
+    CHK(G->hub_vals.reserve(want * 8));
+    fill_u32(s, G->hub_keys.as<uint32_t>(), kNone, G->hub_keys.bytes / 4);
+    fill_u64(s, G->hub_vals.as<uint64_t>(), 0, G->hub_vals.bytes / 8);
+  }
   return LEIDEN_OK;
 }
 
-Ctl* dctl(leiden_graph* G) { return G->ctl.as<Ctl>(); }
+template <typename W>
+void bind_hubs(leiden_graph* G, DecideParams<W>& dp) {
+  dp.hub_idx = G->hub_idx.as<uint32_t>();
+  dp.hub_off = G->hub_off.as<uint64_t>();
+  dp.hub_mask = G->hub_mask.as<uint32_t>();
+  dp.hub_kid = G->hub_kid.as<unsigned long long>();
+  dp.hub_keys = G->hub_keys.as<uint32_t>();
+  dp.hub_vals = G->hub_vals.as<unsigned long long>();
+}
 
 leiden_status read_ctl(leiden_graph* G, hipStream_t s) {
   HIPCHK(hipMemcpyAsync(G->hctl, G->ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -304,9 +332,6 @@ leiden_status local_move(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
                          PassOut& out) {
   const uint32_t P = ro.o.move_classes;
   Ctl* ctl = dctl(G);
-  uint32_t hub_mask = 0;
-  int hub_grid = 1;
-  if (bins[kBins - 1]) CHK(ensure_hub(G, maxdeg, &hub_mask, &hub_grid));
   uint32_t* iter_list = G->iter_list.as<uint32_t>();
   uint32_t* next_list = G->next_list.as<uint32_t>();
   DecideParams<W> dp{};
@@ -319,9 +344,7 @@ leiden_status local_move(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
   dp.inv_2m2 = qc.inv_2m2;
   dp.movers = G->movers.as<Mover>();
   dp.ctl = ctl;
-  dp.hub_keys = G->hub_keys.as<uint32_t>();
-  dp.hub_vals = G->hub_vals.as<unsigned long long>();
-  dp.hub_mask = hub_mask;
+  bind_hubs(G, dp);
   const uint8_t* in_range = first_pass ? ro.in_range : nullptr;
   for (uint32_t li = 0; li < ro.o.max_iters; ++li) {
     const uint32_t stamp = ++G->stamp;
@@ -334,7 +357,7 @@ leiden_status local_move(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
       launch_subround_reset(s, ctl);
       launch_bin(s, G->cls_lists.as<uint32_t>() + (size_t)k * nl, &ctl->cls_count[k], nl, g.len, in_range,
                  G->bin_lists.as<uint32_t>(), (size_t)nl, ctl);
-      launch_decide_all<W, false>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, hub_grid);
+      launch_decide_all<W, false>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, maxdeg);
       ApplyParams ap{};
       ap.start = g.start;
       ap.len = g.len;
@@ -375,9 +398,6 @@ leiden_status refine(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, Lev
                      const QConst& qc, const uint64_t bins[kBins], uint32_t maxdeg) {
   const uint32_t R = ro.o.refine_rounds;
   Ctl* ctl = dctl(G);
-  uint32_t hub_mask = 0;
-  int hub_grid = 1;
-  if (bins[kBins - 1]) CHK(ensure_hub(G, maxdeg, &hub_mask, &hub_grid));
   launch_cls_reset(s, ctl);
   launch_refine_reset(s, nl, L.C, G->CB.as<uint32_t>(), L.S, L.K, L.size, L.dR, R, G->cls_lists.as<uint32_t>(),
                       (size_t)nl, ctl);
@@ -393,15 +413,13 @@ leiden_status refine(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, Lev
   dp.inv_2m2 = qc.inv_2m2;
   dp.movers = G->movers.as<Mover>();
   dp.ctl = ctl;
-  dp.hub_keys = G->hub_keys.as<uint32_t>();
-  dp.hub_vals = G->hub_vals.as<unsigned long long>();
-  dp.hub_mask = hub_mask;
+  bind_hubs(G, dp);
   for (uint32_t r = 0; r < R; ++r) {
     launch_subround_reset(s, ctl);
     launch_bin(s, G->cls_lists.as<uint32_t>() + (size_t)r * nl, &ctl->cls_count[r], nl, g.len, nullptr,
                G->bin_lists.as<uint32_t>(), (size_t)nl, ctl);
     dp.colour = r;
-    launch_decide_all<W, true>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, hub_grid);
+    launch_decide_all<W, true>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, maxdeg);
     launch_apply_refine(s, L.C, L.S, L.K, L.size, G->movers.as<Mover>(), ctl, nl);
   }
   return LEIDEN_OK;
@@ -413,11 +431,13 @@ leiden_status split(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, Leve
   uint32_t* lab = G->lab.as<uint32_t>();
   uint32_t* list = G->split_list.as<uint32_t>();
   launch_split_init<W>(s, nl, L.C, L.dS, L.dR, lab, list, ctl);
-  for (int it = 0; it < 64; ++it) {
+  // labels strictly decrease while anything changes, so the loop ends; the
+  // cap only guards against a defect
+  for (int it = 0;; ++it) {
     launch_split_hook<W>(s, g, L.C, lab, list, ctl, nl);
     CHK(read_ctl(G, s));
     if (!G->hctl->changed) break;
-    if (it == 63) return fail(LEIDEN_EDEVICE, "split did not converge");
+    if (it == 4096) return fail(LEIDEN_EDEVICE, "split did not converge");
   }
   launch_split_finish(s, L.C, lab, list, ctl, nl);
   return LEIDEN_OK;
@@ -429,6 +449,7 @@ leiden_status run_pass(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, L
                        uint32_t pass, double tau, const QConst& qc, const uint64_t bins[kBins], uint32_t maxdeg,
                        leiden_stats* st, bool* stop) {
   PassOut po;
+  if (bins[kBins - 1]) CHK(setup_hubs(G, s, g.len, nl));
   CHK(local_move<W>(G, s, g, nl, L, ro, pass == 0, tau, qc, bins, maxdeg, po));
   if (st && pass < 16) st->iters[pass] = po.iters, st->subrounds[pass] = po.subrounds;
   subset_renumber(s, nl, L.C, L.S, L.size, L.dS, L.dR, L.rb, dctl(G));
