@@ -259,79 +259,95 @@ __global__ __launch_bounds__(kBlock) void k_new_len(uint64_t nt, const uint32_t*
   if (need) atomicAdd(&ctl->overflow_need, need);
 }
 
-// One wavefront per touched row: every old entry and every inserted entry
-// computes its position in the merged sorted row directly.
-__global__ __launch_bounds__(kBlock) void k_merge(uint64_t nt, Rows<uint32_t> g, BatchBufs b) {
-  const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
-  const uint32_t lane = threadIdx.x % kWave;
-  const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
-  for (uint64_t t = wave; t < nt; t += nwaves) {
+// Merge, one thread per entry: every old entry and every inserted entry
+// computes its position in the merged sorted row directly.  Rows are found by
+// binary search over per-row offsets, so long rows spread over all threads.
+__device__ inline uint64_t row_of(const uint64_t* off, uint64_t nt, uint64_t x) {
+  // largest t < nt with off[t] <= x
+  uint64_t lo = 0, hi = nt;
+  while (hi - lo > 1) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (off[mid] <= x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_old_len(uint64_t nt, const uint32_t* len, BatchBufs b) {
+  GRID_STRIDE(t, nt) b.old_len[t] = len[b.touched[t]];
+}
+
+__global__ __launch_bounds__(kBlock) void k_merge_old(uint64_t nt, const uint64_t* total_old, Rows<uint32_t> g,
+                                                      BatchBufs b) {
+  const uint64_t tot = *total_old;
+  GRID_STRIDE(x, tot) {
+    const uint64_t t = row_of(b.old_off, nt, x);
     const uint32_t r = b.touched[t];
-    const uint64_t s0 = b.seg_off[t], s1 = b.seg_off[t + 1];
-    const uint32_t L = (uint32_t)(s1 - s0);
+    const uint32_t p = (uint32_t)(x - b.old_off[t]);
+    const uint64_t s0 = b.seg_off[t];
+    const uint32_t L = (uint32_t)(b.seg_off[t + 1] - s0);
     const int64_t r0 = g.start[r];
-    const uint32_t RL = g.len[r];
-    const uint64_t o = b.out_off[t];
-    const uint64_t pre0 = b.seg_pre[s0];
-    // old entries
-    for (uint32_t p = lane; p < RL; p += kWave) {
-      const uint32_t x = g.cols[r0 + p];
-      uint32_t lo = 0, hi = L;  // first segment entry with dst >= x
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (b.seg_dst[s0 + mid] < x)
-          lo = mid + 1;
-        else
-          hi = mid;
-      }
-      if (lo < L && b.seg_dst[s0 + lo] == x) continue;  // deleted (insertions of present pairs were rejected)
-      const uint64_t dels = b.seg_pre[s0 + lo] - pre0;
-      const uint64_t inss = lo - dels;
-      const uint64_t pos = o + p - dels + inss;
-      b.mcols[pos] = x;
-      b.mw[pos] = g.w[r0 + p];
+    const uint32_t y = g.cols[r0 + p];
+    uint32_t lo = 0, hi = L;  // first segment entry with dst >= y
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (b.seg_dst[s0 + mid] < y)
+        lo = mid + 1;
+      else
+        hi = mid;
     }
-    // inserted entries
-    for (uint32_t q = lane; q < L; q += kWave) {
-      if (b.seg_del[s0 + q]) continue;
-      const uint32_t y = b.seg_dst[s0 + q];
-      const uint32_t lb = row_lower_bound(g.cols, r0, RL, y);
-      const uint64_t dels = b.seg_pre[s0 + q] - pre0;
-      const uint64_t inss = q - dels;
-      const uint64_t pos = o + lb - dels + inss;
-      b.mcols[pos] = y;
-      b.mw[pos] = b.seg_w[s0 + q];
-    }
+    if (lo < L && b.seg_dst[s0 + lo] == y) continue;  // deleted (insertions of present pairs were rejected)
+    const uint64_t dels = b.seg_pre[s0 + lo] - b.seg_pre[s0];
+    const uint64_t inss = lo - dels;
+    const uint64_t pos = b.out_off[t] + p - dels + inss;
+    b.mcols[pos] = y;
+    b.mw[pos] = g.w[r0 + p];
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_commit(uint64_t nt, int64_t* start, uint32_t* len, uint32_t* cap,
-                                                   uint32_t* cols, uint32_t* w, BatchBufs b,
-                                                   unsigned long long* edge_top) {
-  const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
-  const uint32_t lane = threadIdx.x % kWave;
-  const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
-  for (uint64_t t = wave; t < nt; t += nwaves) {
+__global__ __launch_bounds__(kBlock) void k_merge_ins(uint64_t ne, Rows<uint32_t> g, BatchBufs b) {
+  GRID_STRIDE(q, ne) {
+    if (b.seg_del[q]) continue;
+    const uint32_t t = b.seg_id[q];
+    const uint32_t r = b.touched[t];
+    const uint64_t s0 = b.seg_off[t];
+    const uint32_t y = b.seg_dst[q];
+    const uint32_t lb = row_lower_bound(g.cols, g.start[r], g.len[r], y);
+    const uint64_t dels = b.seg_pre[q] - b.seg_pre[s0];
+    const uint64_t inss = (q - s0) - dels;
+    const uint64_t pos = b.out_off[t] + lb - dels + inss;
+    b.mcols[pos] = y;
+    b.mw[pos] = b.seg_w[q];
+  }
+}
+
+// Per touched row: destination of the merged row (in place, or a new span in
+// the overflow area when it outgrew its capacity) and the new length.
+__global__ __launch_bounds__(kBlock) void k_commit_rows(uint64_t nt, int64_t* start, uint32_t* len, uint32_t* cap,
+                                                        BatchBufs b, unsigned long long* edge_top) {
+  GRID_STRIDE(t, nt) {
     const uint32_t r = b.touched[t];
     const uint32_t nl = b.new_len[t];
-    int64_t s0 = start[r];
     if (nl > cap[r]) {
       const uint32_t nc = nl + (nl >> 2) + 4;
-      unsigned long long base = 0;
-      if (lane == 0) base = atomicAdd(edge_top, (unsigned long long)nc);
-      base = __shfl(base, 0, kWave);
-      s0 = (int64_t)base;
-      if (lane == 0) {
-        start[r] = s0;
-        cap[r] = nc;
-      }
+      start[r] = (int64_t)atomicAdd(edge_top, (unsigned long long)nc);
+      cap[r] = nc;
     }
-    const uint64_t o = b.out_off[t];
-    for (uint32_t p = lane; p < nl; p += kWave) {
-      cols[s0 + p] = b.mcols[o + p];
-      w[s0 + p] = b.mw[o + p];
-    }
-    if (lane == 0) len[r] = nl;
+    b.dest[t] = (uint64_t)start[r];
+    len[r] = nl;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_commit_copy(uint64_t nt, const uint64_t* total_new, uint32_t* cols,
+                                                        uint32_t* w, BatchBufs b) {
+  const uint64_t tot = *total_new;
+  GRID_STRIDE(x, tot) {
+    const uint64_t t = row_of(b.out_off, nt, x);
+    const uint64_t d = b.dest[t] + (x - b.out_off[t]);
+    cols[d] = b.mcols[x];
+    w[d] = b.mw[x];
   }
 }
 
@@ -386,16 +402,20 @@ int batch_merge(hipStream_t s, int64_t* start, uint32_t* len, uint32_t* cap, uin
   if (nt == 0) return 0;
   hipLaunchKernelGGL(k_new_len, dim3(grid_n(nt)), dim3(kBlock), 0, s, nt, len, cap, b, ctl);
   exclusive_scan_u32(s, b.new_len, b.out_off, nt, b.total, b.scan_tmp);
-  unsigned long long hv[3] = {0, 0, 0};  // need, top, merged total
+  hipLaunchKernelGGL(k_old_len, dim3(grid_n(nt)), dim3(kBlock), 0, s, nt, len, b);
+  exclusive_scan_u32(s, b.old_len, b.old_off, nt, b.total + 1, b.scan_tmp);
+  unsigned long long hv[4] = {0, 0, 0, 0};  // need, top, merged total, old total
   (void)hipMemcpyAsync(&hv[0], &ctl->overflow_need, sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
   (void)hipMemcpyAsync(&hv[1], edge_top, sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
-  (void)hipMemcpyAsync(&hv[2], b.total, sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+  (void)hipMemcpyAsync(&hv[2], b.total, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
   if (hipStreamSynchronize(s) != hipSuccess) return -100;
   if (hv[1] + hv[0] > edge_cap || hv[2] > b.mcap) return 1;
   Rows<uint32_t> g{start, len, cols, w};
-  hipLaunchKernelGGL(k_merge, dim3(grid_n(nt, kBlock / kWave, 8192)), dim3(kBlock), 0, s, nt, g, b);
-  hipLaunchKernelGGL(k_commit, dim3(grid_n(nt, kBlock / kWave, 8192)), dim3(kBlock), 0, s, nt, start, len, cap, cols,
-                     w, b, edge_top);
+  if (hv[3]) hipLaunchKernelGGL(k_merge_old, dim3(grid_n(hv[3])), dim3(kBlock), 0, s, nt, b.total + 1, g, b);
+  const uint64_t nent = b.n_entries;
+  if (nent) hipLaunchKernelGGL(k_merge_ins, dim3(grid_n(nent)), dim3(kBlock), 0, s, nent, g, b);
+  hipLaunchKernelGGL(k_commit_rows, dim3(grid_n(nt)), dim3(kBlock), 0, s, nt, start, len, cap, b, edge_top);
+  if (hv[2]) hipLaunchKernelGGL(k_commit_copy, dim3(grid_n(hv[2])), dim3(kBlock), 0, s, nt, b.total, cols, w, b);
   return 0;
 }
 

@@ -119,8 +119,9 @@ template <typename W>
 void launch_split_init(hipStream_t s, uint32_t n, const uint32_t* C, const uint8_t* dS, const uint8_t* dR,
                        uint32_t* lab, uint32_t* list, Ctl* ctl);
 template <typename W>
-void launch_split_hook(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* lab, const uint32_t* list, Ctl* ctl,
-                       uint32_t n_upper);
+void launch_split_hook(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* lab, const uint32_t* list,
+                       const uint32_t* bin_lists, size_t stride, const unsigned int* bin_counts,
+                       const uint64_t* bin_upper, Ctl* ctl, uint32_t n_upper);
 void launch_split_finish(hipStream_t s, uint32_t* C, uint32_t* lab, const uint32_t* list, Ctl* ctl, uint32_t n_upper);
 
 void launch_refine_reset(hipStream_t s, uint32_t n, uint32_t* C, uint32_t* CB, int64_t* S, const int64_t* K,
@@ -202,7 +203,11 @@ struct BatchBufs {
   uint32_t* seg_cnt;
   uint64_t* seg_off;   // nt + 1
   uint32_t* new_len;
-  uint64_t* out_off;   // merge scratch offsets
+  uint64_t* out_off;   // merged-row offsets (nt + 1)
+  uint32_t* old_len;   // length of the row before the batch
+  uint64_t* old_off;   // exclusive prefix of old_len (nt + 1)
+  uint64_t* dest;      // where the merged row is written in the slack CSR
+  uint64_t n_entries;  // directed entries (2 per update)
   // entries grouped by row and sorted by destination
   uint32_t* seg_src;
   uint32_t* seg_dst;

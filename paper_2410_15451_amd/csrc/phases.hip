@@ -157,27 +157,43 @@ __device__ inline uint32_t find_root(uint32_t* lab, uint32_t x) {
 // reduction, no per-edge atomics) and hooks its current parent to it.  Labels
 // only decrease and always name a vertex of the same component, so the
 // fixpoint labels every component by its minimum vertex.
-template <typename W>
+// G lanes per vertex (G <= 64 inside a wavefront, G = kBlock for a block);
+// the vertices come from the degree bin lists of the split vertices.
+template <int G, typename W>
 __global__ __launch_bounds__(kBlock) void k_split_hook(Rows<W> g, const uint32_t* C, uint32_t* lab,
-                                                       const uint32_t* list, Ctl* ctl) {
-  const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
-  const uint32_t nwaves = gridDim.x * (kBlock / kWave);
-  const uint32_t cnt = ctl->split_count;
+                                                       const uint32_t* list, const unsigned int* count, Ctl* ctl) {
+  __shared__ uint32_t red[kBlock / kWave];
+  const uint32_t grp = threadIdx.x / G, lane = threadIdx.x % G;
+  constexpr uint32_t GPB = kBlock / G;
+  const uint32_t cnt = *count;
   bool changed = false;
-  for (uint32_t it = wave; it < cnt; it += nwaves) {
-    const uint32_t i = list[it];
-    const uint32_t c = C[i];
-    const int64_t s0 = g.start[i];
-    const uint32_t L = g.len[i];
-    uint32_t m = __atomic_load_n(&lab[i], __ATOMIC_RELAXED);
-    for (uint32_t e = lane; e < L; e += kWave) {
-      const uint32_t j = g.cols[s0 + e];
-      if (j == i || C[j] != c) continue;
-      m = min(m, __atomic_load_n(&lab[j], __ATOMIC_RELAXED));
+  for (uint32_t base = blockIdx.x * GPB; base < cnt; base += gridDim.x * GPB) {
+    const uint32_t it = base + grp;
+    uint32_t m = kNone, i = 0;
+    if (it < cnt) {
+      i = list[it];
+      const uint32_t c = C[i];
+      const int64_t s0 = g.start[i];
+      const uint32_t L = g.len[i];
+      m = __atomic_load_n(&lab[i], __ATOMIC_RELAXED);
+      for (uint32_t e = lane; e < L; e += G) {
+        const uint32_t j = g.cols[s0 + e];
+        if (j == i || C[j] != c) continue;
+        m = min(m, __atomic_load_n(&lab[j], __ATOMIC_RELAXED));
+      }
     }
+    if (G <= kWave) {
 #pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) m = min(m, (uint32_t)__shfl_xor(m, o, kWave));
-    if (lane == 0) {
+      for (int o = G / 2; o > 0; o >>= 1) m = min(m, (uint32_t)__shfl_xor(m, o, G));
+    } else {
+#pragma unroll
+      for (int o = kWave / 2; o > 0; o >>= 1) m = min(m, (uint32_t)__shfl_xor(m, o, kWave));
+      if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = m;
+      __syncthreads();
+      m = min(min(red[0], red[1]), min(red[2], red[3]));
+      __syncthreads();
+    }
+    if (it < cnt && lane == 0) {
       const uint32_t li = __atomic_load_n(&lab[i], __ATOMIC_RELAXED);
       if (m < li) {
         atomicMin(&lab[i], m);
@@ -219,12 +235,30 @@ void launch_split_init(hipStream_t s, uint32_t n, const uint32_t* C, const uint8
   if (n) hipLaunchKernelGGL(k_split_init, dim3(grid_n(n)), dim3(kBlock), 0, s, n, C, dS, dR, lab, list, ctl);
 }
 
+// One propagation round over the degree-binned split vertices (bins as in
+// the local-moving kernels), then full path compression.
 template <typename W>
-void launch_split_hook(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* lab, const uint32_t* list, Ctl* ctl,
-                       uint32_t n_upper) {
+void launch_split_hook(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* lab, const uint32_t* list,
+                       const uint32_t* bin_lists, size_t stride, const unsigned int* bin_counts,
+                       const uint64_t* bin_upper, Ctl* ctl, uint32_t n_upper) {
   hipLaunchKernelGGL(k_reset_changed, dim3(1), dim3(1), 0, s, ctl, 0);
-  hipLaunchKernelGGL(k_split_hook<W>, dim3(grid_n(n_upper, kBlock / kWave, 4096)), dim3(kBlock), 0, s, g, C, lab,
-                     list, ctl);
+  for (int b = 0; b < kBins; ++b) {
+    if (!bin_upper[b]) continue;
+    const uint32_t* bl = bin_lists + (size_t)b * stride;
+    const unsigned int* bc = bin_counts + b;
+    if (b == 0)
+      hipLaunchKernelGGL((k_split_hook<8, W>), dim3(grid_n(bin_upper[b], kBlock / 8, 4096)), dim3(kBlock), 0, s, g, C,
+                         lab, bl, bc, ctl);
+    else if (b == 1)
+      hipLaunchKernelGGL((k_split_hook<32, W>), dim3(grid_n(bin_upper[b], kBlock / 32, 4096)), dim3(kBlock), 0, s, g,
+                         C, lab, bl, bc, ctl);
+    else if (b == 2)
+      hipLaunchKernelGGL((k_split_hook<64, W>), dim3(grid_n(bin_upper[b], kBlock / 64, 4096)), dim3(kBlock), 0, s, g,
+                         C, lab, bl, bc, ctl);
+    else
+      hipLaunchKernelGGL((k_split_hook<kBlock, W>), dim3(grid_n(bin_upper[b], 1, 4096)), dim3(kBlock), 0, s, g, C,
+                         lab, bl, bc, ctl);
+  }
   hipLaunchKernelGGL(k_split_compress, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, lab, list, ctl);
 }
 
@@ -237,9 +271,11 @@ template void launch_split_init<uint32_t>(hipStream_t, uint32_t, const uint32_t*
 template void launch_split_init<int64_t>(hipStream_t, uint32_t, const uint32_t*, const uint8_t*, const uint8_t*,
                                          uint32_t*, uint32_t*, Ctl*);
 template void launch_split_hook<uint32_t>(hipStream_t, Rows<uint32_t>, const uint32_t*, uint32_t*, const uint32_t*,
-                                          Ctl*, uint32_t);
+                                          const uint32_t*, size_t, const unsigned int*, const uint64_t*, Ctl*,
+                                          uint32_t);
 template void launch_split_hook<int64_t>(hipStream_t, Rows<int64_t>, const uint32_t*, uint32_t*, const uint32_t*,
-                                         Ctl*, uint32_t);
+                                         const uint32_t*, size_t, const unsigned int*, const uint64_t*, Ctl*,
+                                         uint32_t);
 
 // ---------------------------------------------------------------------------
 // Alg. 8, first loop: vertices of refined bounds become singletons; they are

@@ -118,7 +118,7 @@ struct leiden_graph {
       tr_matched;
   Buf dV, dE, dC, sig, partials, modparts;
   Buf bt_src, bt_dst, bt_w, bt_del, bt_slot, bt_rowcnt, bt_rowidx, bt_touched, bt_segcnt, bt_segoff, bt_newlen,
-      bt_outoff, bt_ssrc, bt_sdst, bt_sw, bt_sdel, bt_sid, bt_spre, bt_tdst, bt_tw, bt_tdel, bt_mcols, bt_mw, bt_in;
+      bt_outoff, bt_ssrc, bt_sdst, bt_sw, bt_sdel, bt_sid, bt_spre, bt_tdst, bt_tw, bt_tdel, bt_mcols, bt_mw, bt_in, bt_oldlen, bt_oldoff, bt_dest;
   Buf rb_cols, rb_w, rb_off, rb_reserve;
   size_t ws_n = 0, ws_classes = 0;
   uint64_t ws_nnz = 0;
@@ -426,15 +426,20 @@ leiden_status refine(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, Lev
 }
 
 template <typename W>
-leiden_status split(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, LevelState& L) {
+leiden_status split(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, LevelState& L,
+                    const uint64_t bins[kBins]) {
   Ctl* ctl = dctl(G);
   uint32_t* lab = G->lab.as<uint32_t>();
   uint32_t* list = G->split_list.as<uint32_t>();
   launch_split_init<W>(s, nl, L.C, L.dS, L.dR, lab, list, ctl);
+  // split vertices by degree, for the group sizes of the propagation kernels
+  launch_subround_reset(s, ctl);
+  launch_bin(s, list, &ctl->split_count, nl, g.len, nullptr, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl);
   // labels strictly decrease while anything changes, so the loop ends; the
   // cap only guards against a defect
   for (int it = 0;; ++it) {
-    launch_split_hook<W>(s, g, L.C, lab, list, ctl, nl);
+    launch_split_hook<W>(s, g, L.C, lab, list, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, ctl,
+                         nl);
     CHK(read_ctl(G, s));
     if (!G->hctl->changed) break;
     if (it == 4096) return fail(LEIDEN_EDEVICE, "split did not converge");
@@ -455,7 +460,7 @@ leiden_status run_pass(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, L
   subset_renumber(s, nl, L.C, L.S, L.size, L.dS, L.dR, L.rb, dctl(G));
   CHK(read_ctl(G, s));
   const uint32_t nsplit = G->hctl->misc[0], nref = G->hctl->misc[1];
-  if (nsplit > 0) CHK(split<W>(G, s, g, nl, L));
+  if (nsplit > 0) CHK(split<W>(G, s, g, nl, L, bins));
   if (st && pass == 0) st->split_marked = nsplit;
   const bool refined = nref > 0;
   if (refined) CHK(refine<W>(G, s, g, nl, L, ro, qc, bins, maxdeg));
@@ -858,8 +863,10 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   CHK(G->bt_in.reserve((2 * n_del + 3 * n_ins + 1) * 4));
   for (Buf* b : {&G->bt_src, &G->bt_dst, &G->bt_w, &G->bt_del, &G->bt_slot, &G->bt_ssrc, &G->bt_sdst, &G->bt_sw,
                  &G->bt_sdel, &G->bt_sid, &G->bt_tdst, &G->bt_tw, &G->bt_tdel, &G->bt_touched, &G->bt_segcnt,
-                 &G->bt_newlen})
+                 &G->bt_newlen, &G->bt_oldlen})
     CHK(b->reserve(nE * 4));
+  CHK(G->bt_oldoff.reserve((nE + 1) * 8));
+  CHK(G->bt_dest.reserve(nE * 8));
   CHK(G->bt_segoff.reserve((nE + 1) * 8));
   CHK(G->bt_outoff.reserve((nE + 1) * 8));
   CHK(G->bt_spre.reserve((nE + 1) * 8));
@@ -909,6 +916,10 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   bb.seg_off = G->bt_segoff.as<uint64_t>();
   bb.new_len = G->bt_newlen.as<uint32_t>();
   bb.out_off = G->bt_outoff.as<uint64_t>();
+  bb.old_len = G->bt_oldlen.as<uint32_t>();
+  bb.old_off = G->bt_oldoff.as<uint64_t>();
+  bb.dest = G->bt_dest.as<uint64_t>();
+  bb.n_entries = ne;
   bb.seg_src = G->bt_ssrc.as<uint32_t>();
   bb.seg_dst = G->bt_sdst.as<uint32_t>();
   bb.seg_w = G->bt_sw.as<uint32_t>();
