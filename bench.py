@@ -70,7 +70,53 @@ def cpu_baseline(scale, frac, reps, seed):
         edges += gt.nnz
     return {"value": edges / tsum, "unit": "edges/s", "cores": 1, "kind": "oracle",
             "sample": "R-MAT scale %d (same recipe, |E|=%d), %d DF updates of %g|E| after an untimed oracle static "
-                      "run; single-threaded C++ oracle, %.1f s timed" % (scale, g.nnz, reps, frac, tsum)}
+                      "run; single-threaded C++ oracle, %.1f s timed" % (scale, g.nnz, reps, frac, tsum),
+            "host": host_info()}
+
+
+def host_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    mem = 0
+    try:
+        mem = os.sysconf("SC_PAGE_SIZE") * os.sysconf("SC_PHYS_PAGES") / 2**30
+    except (ValueError, OSError):
+        pass
+    return {"cpu": model, "logical_cpus": os.cpu_count(), "ram_gib": round(mem, 1)}
+
+
+def kernel_source_digest():
+    """Digest of the sources the timed kernel is built from: a stored counter
+    reading is only reported while it still describes the same code."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("common.h", "kernels.h", "move.hip"):
+        with open(os.path.join(ROOT, "paper_2410_15451_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel factor), or
+    None when there is none for the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    r = rec.get(kernel, {}).get(workload)
+    if not r or r.get("source_digest") != kernel_source_digest():
+        return None
+    return r.get("hbm_bytes_per_launch")
 
 
 def main():
@@ -84,6 +130,12 @@ def main():
     ap.add_argument("--context-steps", type=int, default=3, help="ND / DS / static steps for the ratio context")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-scale", type=int, default=20)
+    ap.add_argument("--cpu-reps", type=int, default=24)
+    ap.add_argument("--timed-kernel", default="hub_insert", help="kernel timed with HIP events for the roofline")
+    ap.add_argument("--marker", type=int, default=0,
+                    help="launch a spin kernel right before and after the timed steps (profile windowing)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device copy of this size first (reference for rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus,
@@ -97,6 +149,14 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     sp = stream.cuda_stream
+    if args.calib_copy_mib:
+        x = torch.ones(args.calib_copy_mib << 18, dtype=torch.int32, device=dev)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log("calibration copy: %d MiB" % args.calib_copy_mib)
+        del x, y
 
     t0 = time.time()
     g = inputs.rmat(args.scale, seed=inputs.BASE_SEED + 2)
@@ -124,12 +184,12 @@ def main():
                                                           q_static))
     bi = 0
 
-    def run_update(mode):
+    def run_update(mode, **kw):
         nonlocal bi
         d, i = dev_batches[bi]
         bi += 1
         ta = time.perf_counter()
-        r = G.update(d, i, mode=mode, out=out, **opts)
+        r = G.update(d, i, mode=mode, out=out, **opts, **kw)
         return time.perf_counter() - ta, r
 
     for _ in range(args.warmup):
@@ -137,14 +197,18 @@ def main():
     torch.cuda.synchronize()
     lat, edges, stats = [], 0, []
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    if args.marker:
+        torch.cuda._sleep(1000)
     ev0.record(stream)
     tw = time.perf_counter()
     for _ in range(args.steps):
-        dt, r = run_update(args.mode)
+        dt, r = run_update(args.mode, timed_kernel=args.timed_kernel)
         lat.append(dt)
         edges += r.stats["nnz"]
         stats.append(r.stats)
     ev1.record(stream)
+    if args.marker:
+        torch.cuda._sleep(1000)
     torch.cuda.synchronize()
     wall = time.perf_counter() - tw
     dev_ms = ev0.elapsed_time(ev1)
@@ -156,7 +220,7 @@ def main():
 
     # context: ND / DS updates and a static recompute on the evolving graph
     context = {}
-    for mode in [m for m in ("nd", "ds") if m != args.mode]:
+    for mode in [m for m in ("nd", "ds") if m != args.mode and ctx]:
         ts = [run_update(mode)[0] for _ in range(ctx)]
         context[mode + "_ms"] = 1e3 * sum(ts) / len(ts)
     ts = []
@@ -166,7 +230,7 @@ def main():
         G.static(out=out, **opts)
         torch.cuda.synchronize()
         ts.append(time.perf_counter() - ta)
-    context["static_ms"] = 1e3 * sum(ts) / len(ts)
+    context["static_ms"] = 1e3 * sum(ts) / len(ts) if ts else t_static * 1e3
     context[args.mode + "_ms"] = T / args.steps * 1e3
     for m in ("nd", "ds", "df"):
         if m + "_ms" in context:
@@ -175,21 +239,36 @@ def main():
 
     mean = {k: sum(s[k] for s in stats) / len(stats) for k in ("ms_total", "ms_batch", "edges_scanned", "moves",
                                                                  "affected", "passes")}
+    # roofline of the timed kernel: algorithmic bytes per launch over its
+    # average launch time (HIP events on the call's stream)
+    launches = sum(s["kt_launches"] for s in stats)
+    kt_ms = sum(s["kt_ms"] for s in stats)
+    kt_bytes = sum(s["kt_bytes"] for s in stats)
+    workload = "rmat%d_%s_update_%g" % (args.scale, args.mode, args.frac)
+    kname = binding.kernel_name(args.timed_kernel)
+    roof = None
+    if launches and kt_ms > 0:
+        achieved = kt_bytes / (kt_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(kname, workload), "kernel": kname,
+                "launches": launches, "avg_launch_ms": kt_ms / launches, "bytes_per_launch": kt_bytes / launches,
+                "units_per_launch": sum(s["kt_units"] for s in stats) / launches,
+                "share_of_step": kt_ms / (T * 1e3)}
     line = {
         "metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": T / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int64+f64", "data": "synthetic",
-        "config": {"workload": "rmat%d_%s_update_%g" % (args.scale, args.mode, args.frac), "n": g.n, "nnz": g.nnz,
+        "config": {"workload": workload, "n": g.n, "nnz": g.nnz,
                    "batch_undirected_updates": nb, "mode": args.mode, "deterministic": True},
         "p50_ms": percentile(lat, 50) * 1e3, "p99_ms": percentile(lat, 99) * 1e3,
         "static_edges_per_s": g.nnz / t_static, "static_ms": t_static * 1e3,
         "batch_edges_per_s": 2 * nb * args.steps / T,
         "modularity": {"static": q_static, "after_updates": q_dyn},
-        "step_stats_mean": mean, "context": context,
+        "step_stats_mean": mean, "context": context, "roofline": roof,
     }
     if args.cpu_baseline:
         t = time.time()
-        line["cpu_baseline"] = cpu_baseline(args.cpu_scale, args.frac, 3, inputs.BASE_SEED + 2)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_scale, args.frac, args.cpu_reps, inputs.BASE_SEED + 2)
         log("cpu baseline: %.3g edges/s (%.1f s)" % (line["cpu_baseline"]["value"], time.time() - t))
     print(json.dumps(line), flush=True)
 

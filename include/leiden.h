@@ -48,6 +48,17 @@ typedef enum {
   LEIDEN_DF = 2  /* Dynamic Frontier (Alg. 3) */
 } leiden_mode;
 
+/* Kernels that a call can time (leiden_opts.timed_kernel), with the unit of
+ * work each one counts and the algorithmic bytes per unit: the data the
+ * method has to touch, not what the kernel actually moves. */
+typedef enum {
+  LEIDEN_KT_NONE = 0,
+  /* Local moving (Alg. 6) of the hub-degree bin on the input graph: one unit
+   * per scanned row entry, 12 bytes (neighbour ID, edge weight and the
+   * neighbour's community, 4 bytes each). */
+  LEIDEN_KT_HUB_INSERT = 1
+} leiden_kernel;
+
 /* Parameters (defaults from Section 4.1.2). */
 typedef struct {
   double tau;             /* initial iteration tolerance, 1e-2 */
@@ -56,11 +67,13 @@ typedef struct {
   uint32_t tol_decline;   /* TOLERANCE_DECLINE_FACTOR, 10 */
   uint32_t max_iters;     /* MAX_ITERATIONS per pass, 20 */
   uint32_t max_passes;    /* MAX_PASSES, 10 */
-  uint32_t move_classes;  /* vertex classes of the synchronous local-moving sub-rounds, 8 (1..64) */
-  uint32_t refine_rounds; /* colour rounds of the synchronous refinement, 8 (1..64) */
+  uint32_t move_classes;  /* vertex classes of the synchronous local-moving sub-rounds, 8 (1..32) */
+  uint32_t refine_rounds; /* colour rounds of the synchronous refinement, 8 (1..32) */
   int32_t deterministic;  /* 1: synchronous schedule, bit-exact and reproducible */
   int32_t compute_modularity; /* 1: fill *q_out with Eq. 1 of the result; 0: NaN */
   void* stream;           /* hipStream_t or NULL */
+  int32_t timed_kernel;   /* a leiden_kernel to time with HIP events on the stream, or LEIDEN_KT_NONE */
+  int32_t pad_;
 } leiden_opts;
 
 /* Per-call statistics. */
@@ -80,16 +93,27 @@ typedef struct {
   double ms_batch;           /* batch validation and graph update */
   double ms_modularity;      /* final modularity */
   uint64_t nnz;              /* directed entries of the graph after the call */
+  /* the kernel named by leiden_opts.timed_kernel: each launch is bracketed by
+   * two events recorded on the call's stream */
+  uint32_t kt_launches;      /* launches of that kernel in the call */
+  uint32_t kt_pad_;
+  double kt_ms;              /* their summed device time */
+  uint64_t kt_units;         /* work units they processed (see leiden_kernel) */
+  double kt_bytes;           /* algorithmic bytes of those units */
 } leiden_stats;
 
 typedef struct leiden_graph leiden_graph;
+
+/* Symbol of a leiden_kernel as profilers list it (NULL for an unknown value). */
+const char* leiden_kernel_name(int32_t kernel);
 
 /* Fill *opts with the defaults above. */
 leiden_status leiden_default_opts(leiden_opts* opts);
 
 /* Create a handle on GPU `device` holding the undirected graph given as a CSR
  * with both directions of every edge: offsets int64[n+1], cols uint32[nnz],
- * w uint32[nnz].  Rows need not be sorted; duplicate entries, self-loops,
+ * w uint32[nnz] (the graph of Section 3.1 with integer weights).  Each row
+ * must be sorted by column; unsorted rows, duplicate entries, self-loops,
  * zero weights, IDs >= n or an asymmetric matrix give LEIDEN_EINVAL.  `slack`
  * >= 0 reserves room per row for future insertions (fraction of the row
  * length).  *out receives the handle. */

@@ -21,7 +21,22 @@ MODES = {"nd": 0, "ds": 1, "df": 2}
 # Every symbol include/leiden.h declares.
 EXPORTS = ("leiden_default_opts", "leiden_graph_create", "leiden_graph_destroy", "leiden_graph_nnz", "leiden_static",
            "leiden_update", "leiden_modularity", "leiden_graph_export", "leiden_state_export",
-           "leiden_state_import", "leiden_last_error")
+           "leiden_state_import", "leiden_last_error", "leiden_kernel_name")
+
+
+# leiden_kernel values (timed kernels)
+KERNELS = {"none": 0, "hub_insert": 1}
+
+
+def kernel_name(kernel):
+    """Symbol of a timed kernel as profilers list it."""
+    k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    f = lib().leiden_kernel_name
+    f.restype = ctypes.c_char_p
+    r = f(ctypes.c_int32(k))
+    if r is None:
+        raise ValueError("unknown kernel %r" % (kernel,))
+    return r.decode()
 
 
 class LeidenOpts(ctypes.Structure):
@@ -29,7 +44,7 @@ class LeidenOpts(ctypes.Structure):
                 ("tol_decline", ctypes.c_uint32), ("max_iters", ctypes.c_uint32), ("max_passes", ctypes.c_uint32),
                 ("move_classes", ctypes.c_uint32), ("refine_rounds", ctypes.c_uint32),
                 ("deterministic", ctypes.c_int32), ("compute_modularity", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("timed_kernel", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class LeidenStats(ctypes.Structure):
@@ -38,7 +53,9 @@ class LeidenStats(ctypes.Structure):
                 ("refine_marked", ctypes.c_uint64), ("moves", ctypes.c_uint64), ("refine_moves", ctypes.c_uint64),
                 ("edges_scanned", ctypes.c_uint64), ("refined_first_pass", ctypes.c_int32),
                 ("pad_", ctypes.c_int32), ("ms_total", ctypes.c_double), ("ms_batch", ctypes.c_double),
-                ("ms_modularity", ctypes.c_double), ("nnz", ctypes.c_uint64)]
+                ("ms_modularity", ctypes.c_double), ("nnz", ctypes.c_uint64),
+                ("kt_launches", ctypes.c_uint32), ("kt_pad_", ctypes.c_uint32), ("kt_ms", ctypes.c_double),
+                ("kt_units", ctypes.c_uint64), ("kt_bytes", ctypes.c_double)]
 
     def as_dict(self):
         p = self.passes
@@ -46,7 +63,9 @@ class LeidenStats(ctypes.Structure):
                 "affected": self.affected, "split_marked": self.split_marked, "moves": self.moves,
                 "refine_moves": self.refine_moves, "edges_scanned": self.edges_scanned,
                 "refined_first_pass": self.refined_first_pass, "ms_total": self.ms_total,
-                "ms_batch": self.ms_batch, "ms_modularity": self.ms_modularity, "nnz": self.nnz}
+                "ms_batch": self.ms_batch, "ms_modularity": self.ms_modularity, "nnz": self.nnz,
+                "kt_launches": self.kt_launches, "kt_ms": self.kt_ms, "kt_units": self.kt_units,
+                "kt_bytes": self.kt_bytes}
 
 
 class LeidenError(RuntimeError):
@@ -121,6 +140,8 @@ def default_opts(**kw) -> LeidenOpts:
             o.tau_re_num, o.tau_re_den = v
         elif k == "stream":
             o.stream = ctypes.c_void_p(v)
+        elif k == "timed_kernel" and isinstance(v, str):
+            o.timed_kernel = KERNELS[v]
         else:
             setattr(o, k, v)
     return o

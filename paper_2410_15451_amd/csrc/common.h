@@ -64,6 +64,7 @@ struct Ctl {
   unsigned long long overflow_need;  // entries to relocate into the overflow area
   unsigned int big_count;            // movers whose rows are marked by the block-parallel kernel
   unsigned int misc[8];
+  unsigned long long kt_units[4];    // work units of the timed kernels (indexed by leiden_kernel)
 };
 
 // ---------------------------------------------------------------------------

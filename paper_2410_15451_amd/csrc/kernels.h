@@ -2,6 +2,7 @@
 #pragma once
 
 #include "common.h"
+#include "leiden.h"
 
 namespace lm {
 
@@ -186,6 +187,22 @@ struct TrackBufs {
 };
 void track(hipStream_t s, uint32_t n, const uint32_t* Ccur, const uint32_t* Cprev, const int64_t* K, uint32_t* out,
            TrackBufs& b);
+
+// Per-launch timing of one kernel with HIP events on the launch stream.  The
+// runtime points tl_ktimer at the handle's timer for the duration of a call
+// that asks for it; launch sites bracket the kernel with kt_mark.
+constexpr int kKtMaxLaunches = 1024;
+struct KTimer {
+  int which = 0;  // leiden_kernel being timed
+  int n = 0;      // events recorded (two per launch)
+  bool ready = false;
+  hipEvent_t ev[2 * kKtMaxLaunches];
+};
+extern thread_local KTimer* tl_ktimer;
+inline void kt_mark(int which, hipStream_t s) {
+  KTimer* t = tl_ktimer;
+  if (t && t->which == which && t->n < 2 * kKtMaxLaunches) (void)hipEventRecord(t->ev[t->n++], s);
+}
 
 // batch.hip
 struct BatchBufs {

@@ -286,7 +286,10 @@ __global__ __launch_bounds__(kBlock) void k_hub_insert(DecideParams<W> p) {
       __syncthreads();
     }
   }
-  if (edges) atomicAdd(&p.ctl->edges, edges);
+  if (edges) {
+    atomicAdd(&p.ctl->edges, edges);
+    if (sizeof(W) == 4) atomicAdd(&p.ctl->kt_units[LEIDEN_KT_HUB_INSERT], edges);
+  }
 }
 
 template <typename W, bool REFINE>
@@ -525,8 +528,10 @@ void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, si
                            s, q);
         break;
       default:
+        if (sizeof(W) == 4 && !REFINE) kt_mark(LEIDEN_KT_HUB_INSERT, s);
         hipLaunchKernelGGL((k_hub_insert<W, REFINE>), dim3(grid_for(bin_upper[b] * (maxdeg / kHubChunk + 1), 1, 1024)),
                            dim3(kBlock), 0, s, q);
+        if (sizeof(W) == 4 && !REFINE) kt_mark(LEIDEN_KT_HUB_INSERT, s);
         hipLaunchKernelGGL((k_hub_select<W, REFINE>), dim3(grid_for(bin_upper[b], 1, 1024)), dim3(kBlock), 0, s, q);
         break;
     }

@@ -124,13 +124,52 @@ struct leiden_graph {
   uint64_t ws_nnz = 0;
   bool rowcnt_ready = false;
   Ctl* hctl = nullptr;  // pinned mirror
+  KTimer kt;
   ~leiden_graph() {
+    if (kt.ready)
+      for (hipEvent_t& e : kt.ev) (void)hipEventDestroy(e);
     if (hctl) (void)hipHostFree(hctl);
     if (own) (void)hipStreamDestroy(own);
   }
 };
 
+namespace lm {
+thread_local KTimer* tl_ktimer = nullptr;
+}
+
 namespace {
+
+// Points the launch sites at the handle's timer for one call.
+struct KtScope {
+  explicit KtScope(leiden_graph* G, int which) {
+    if (!which) return;
+    if (!G->kt.ready) {
+      for (hipEvent_t& e : G->kt.ev)
+        if (hipEventCreate(&e) != hipSuccess) return;
+      G->kt.ready = true;
+    }
+    G->kt.which = which;
+    G->kt.n = 0;
+    tl_ktimer = &G->kt;
+  }
+  ~KtScope() { tl_ktimer = nullptr; }
+};
+
+double kt_unit_bytes(int which) { return which == LEIDEN_KT_HUB_INSERT ? 12.0 : 0.0; }
+
+// After the call's final synchronisation: launches, device time, units, bytes.
+void kt_collect(leiden_graph* G, int which, leiden_stats* st) {
+  if (!which || tl_ktimer != &G->kt) return;
+  double ms = 0;
+  for (int k = 0; k + 1 < G->kt.n; k += 2) {
+    float m = 0;
+    if (hipEventElapsedTime(&m, G->kt.ev[k], G->kt.ev[k + 1]) == hipSuccess) ms += m;
+  }
+  st->kt_launches = (uint32_t)(G->kt.n / 2);
+  st->kt_ms = ms;
+  st->kt_units = G->hctl->kt_units[which];
+  st->kt_bytes = (double)st->kt_units * kt_unit_bytes(which);
+}
 
 hipStream_t stream_of(leiden_graph* g, const leiden_opts* o) {
   return (o && o->stream) ? (hipStream_t)o->stream : g->own;
@@ -587,6 +626,8 @@ leiden_status check_opts(const leiden_opts& o) {
     return fail(LEIDEN_EINVAL, "tau_re_den, tol_decline and max_iters must be > 0");
   if (!(o.tau >= 0.0)) return fail(LEIDEN_EINVAL, "tau must be >= 0");
   if (!o.deterministic) return fail(LEIDEN_EINVAL, "only the deterministic schedule is available");
+  if (o.timed_kernel < LEIDEN_KT_NONE || o.timed_kernel > LEIDEN_KT_HUB_INSERT)
+    return fail(LEIDEN_EINVAL, "unknown timed_kernel");
   return LEIDEN_OK;
 }
 
@@ -673,7 +714,20 @@ leiden_status leiden_default_opts(leiden_opts* o) {
   o->deterministic = 1;
   o->compute_modularity = 1;
   o->stream = nullptr;
+  o->timed_kernel = LEIDEN_KT_NONE;
+  o->pad_ = 0;
   return LEIDEN_OK;
+}
+
+const char* leiden_kernel_name(int32_t kernel) {
+  switch (kernel) {
+    case LEIDEN_KT_NONE:
+      return "";
+    case LEIDEN_KT_HUB_INSERT:
+      return "lm::k_hub_insert<unsigned int, false>";
+    default:
+      return nullptr;
+  }
 }
 
 const char* leiden_last_error(void) { return g_err.c_str(); }
@@ -775,6 +829,7 @@ leiden_status leiden_static(leiden_graph* G, const leiden_opts* opts, uint32_t* 
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = stream_of(G, opts);
   if (stats) std::memset(stats, 0, sizeof(*stats));
+  KtScope kts(G, o.timed_kernel);
   CHK(ensure_workspace(G, std::max(o.move_classes, o.refine_rounds)));
   hipEvent_t e0, e1, e2;
   HIPCHK(hipEventCreate(&e0));
@@ -822,6 +877,7 @@ leiden_status leiden_static(leiden_graph* G, const leiden_opts* opts, uint32_t* 
     stats->ms_total = ms;
     (void)hipEventElapsedTime(&ms, e1, e2);
     stats->ms_modularity = ms;
+    kt_collect(G, o.timed_kernel, stats);
     stats->affected = n;
     stats->moves = G->hctl->total_moves;
     stats->refine_moves = G->hctl->refine_moves;
@@ -851,6 +907,7 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = stream_of(G, opts);
   if (stats) std::memset(stats, 0, sizeof(*stats));
+  KtScope kts(G, o.timed_kernel);
   const uint32_t n = G->n;
   CHK(ensure_workspace(G, std::max(o.move_classes, o.refine_rounds)));
   CHK(G->st_C.reserve((size_t)std::max<uint32_t>(n, 1) * 4));
@@ -1087,6 +1144,7 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
     stats->ms_batch = ms;
     (void)hipEventElapsedTime(&ms, e2, e3);
     stats->ms_modularity = ms;
+    kt_collect(G, o.timed_kernel, stats);
     stats->affected = affected;
     stats->refine_marked = refine_marked;
     stats->moves = G->hctl->total_moves;
