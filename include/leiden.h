@@ -3,13 +3,13 @@
  *
  * The calls follow the problem statement of "Heuristic-based Dynamic Leiden
  * Algorithm for Efficient Tracking of Communities on Evolving Graphs" (Sahu):
- * Static Leiden takes a graph G (Section 4.1.5); the dynamic ND, DS and DF
+ * Static Leiden takes a graph G (Section 5.1.5); the dynamic ND, DS and DF
  * algorithms (Alg. 1, 2, 3) take the updated graph G^t, the batch update
- * (deletions Delta^{t-} and insertions Delta^{t+}, Section 2.4), the previous
+ * (deletions Delta^{t-} and insertions Delta^{t+}, Section 3.5), the previous
  * memberships C^{t-1} and the auxiliary state K^{t-1}, Sigma^{t-1} and
  * DeltaSigma^{t-1}, and return C^t with the new auxiliary state.  Here the
  * graph handle owns G^t on the device together with that auxiliary state
- * (Section 3.4), and applies each batch to its own copy of the graph.
+ * (Section 4.4), and applies each batch to its own copy of the graph.
  *
  * Conventions
  *   - Vertex IDs are uint32 in [0, n); edge weights are uint32 > 0; the graph
@@ -59,7 +59,7 @@ typedef enum {
   LEIDEN_KT_HUB_INSERT = 1
 } leiden_kernel;
 
-/* Parameters (defaults from Section 4.1.2). */
+/* Parameters (defaults from Section 5.1.2). */
 typedef struct {
   double tau;             /* initial iteration tolerance, 1e-2 */
   uint32_t tau_re_num;    /* refinement tolerance tau_re = num / den, 3 / 5 */
@@ -112,7 +112,7 @@ leiden_status leiden_default_opts(leiden_opts* opts);
 
 /* Create a handle on GPU `device` holding the undirected graph given as a CSR
  * with both directions of every edge: offsets int64[n+1], cols uint32[nnz],
- * w uint32[nnz] (the graph of Section 3.1 with integer weights).  Each row
+ * w uint32[nnz] (the graph of Section 3 with integer weights).  Each row
  * must be sorted by column; unsorted rows, duplicate entries, self-loops,
  * zero weights, IDs >= n or an asymmetric matrix give LEIDEN_EINVAL.  `slack`
  * >= 0 reserves room per row for future insertions (fraction of the row

@@ -68,7 +68,7 @@ const u32 kEmpty = 0xFFFFFFFFu;
 extern "C" {
 
 typedef struct {
-  double tau;           /* initial iteration tolerance (Section 4.1.2: 1e-2) */
+  double tau;           /* initial iteration tolerance (Section 5.1.2: 1e-2) */
   uint32_t tau_re_num;  /* refinement tolerance as num/den (0.6 = 3/5) */
   uint32_t tau_re_den;
   uint32_t tol_decline; /* TOLERANCE_DECLINE_FACTOR (10) */
@@ -893,7 +893,7 @@ int oracle_static(uint32_t n, const int64_t* offs, const uint32_t* cols, const u
   return ORACLE_OK;
 }
 
-/* Batch application G^{t-1} -> G^t with set semantics (Section 2.4): the
+/* Batch application G^{t-1} -> G^t with set semantics (Section 3.5): the
  * deleted pairs must exist, the inserted pairs must be absent, no self-loops,
  * IDs < n, no pair twice in the batch.  Also returns each deleted edge's
  * weight in G^{t-1}.  The caller sizes the outputs for

@@ -1,4 +1,4 @@
-// Batch update kernels: G^{t-1} -> G^t with set semantics (Section 2.4) on
+// Batch update kernels: G^{t-1} -> G^t with set semantics (Section 3.5) on
 // the device slack CSR, the auxiliary-state update of Alg. 11, the community
 // marking of Alg. 5 and the vertex marking of Alg. 2 / Alg. 3.
 //

@@ -99,7 +99,7 @@ struct leiden_graph {
   Buf b_start, b_len, b_cap, b_cols, b_w;
   Buf b_top;  // unsigned long long bump pointer of the overflow area
   uint64_t nnz = 0;
-  // auxiliary state (Section 3.4): C, K, Sigma, DeltaSigma
+  // auxiliary state (Section 4.4): C, K, Sigma, DeltaSigma
   bool has_state = false;
   Buf st_C, st_K, st_S, st_dS;
   uint32_t stamp = 0;  // iteration stamp, never reused

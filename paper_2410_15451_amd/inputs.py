@@ -7,13 +7,13 @@ here, so the two sides never disagree about their inputs.
 
 Graph format (host, numpy):
   ``Csr(n, offs, cols, w)`` - an undirected graph stored with both directions of
-  every edge (the paper's convention of adding reverse edges, Section 4.1.4),
+  every edge (the paper's convention of adding reverse edges, Section 5.1.4),
   ``offs`` int64[n+1], ``cols`` uint32[nnz] sorted inside each row, ``w`` uint32[nnz]
   with w > 0, no duplicate entries.
 
 Batch format: deletions ``uint32[nd, 2]`` (each undirected pair once) and insertions
 ``uint32[ni, 3]`` as (u, v, w) (each undirected pair once, w > 0), following the
-batch update definition of Section 2.4 (deletions are existing edges, insertions
+batch update definition of Section 3.5 (deletions are existing edges, insertions
 are absent pairs, no vertex is added or removed).
 
 Workload recipes (the paper's SuiteSparse and SNAP graphs are not available; these
@@ -23,7 +23,7 @@ stand in for them):
   * R-MAT: 2^scale vertices, edge_factor * 2^scale samples with quadrant
     probabilities (a, b, c, d), self-loops and duplicates dropped, a seeded vertex
     permutation, unit weights;
-  * random batch (Section 4.1.3): a fraction of |E| undirected updates, 80%
+  * random batch (Section 5.1.4): a fraction of |E| undirected updates, 80%
     insertions of uniform absent pairs and 20% deletions of uniform existing edges.
 """
 from __future__ import annotations
@@ -147,7 +147,7 @@ def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c:
 
 def random_batch(n: int, existing_keys: np.ndarray, n_updates: int, seed: int,
                  ins_frac: float = 0.8, w_range=(1, 1)):
-    """Random batch update of ``n_updates`` undirected updates (Section 4.1.3).
+    """Random batch update of ``n_updates`` undirected updates (Section 5.1.4).
 
     ``existing_keys`` are the sorted u*2^32+v keys (u < v) of the current graph.
     Returns (deletions uint32[nd,2], insertions uint32[ni,3]); deletions are distinct
