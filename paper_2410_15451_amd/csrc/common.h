@@ -57,7 +57,10 @@ struct Ctl {
   unsigned int mover_count;
   unsigned int refined_any;          // some vertex lies in a refined bound
   unsigned int split_count;          // vertices of split-marked communities
-  unsigned int changed;              // connected-components fixpoint flag
+  unsigned int changed;              // unused
+  unsigned int split_rest;           // split vertices outside their community's main tree
+  unsigned int hub_items;            // (hub, partition) work items of the current sub-round
+  unsigned int hub_over;             // hubs whose LDS tables overflowed in the current sub-round
   unsigned int error;                // batch validation error code
   unsigned int touched;              // rows touched by the batch
   unsigned int init_count;           // vertices marked affected by the batch

@@ -28,6 +28,16 @@ struct DecideParams {
   unsigned long long* hub_kid;  // hub index -> K_{i->d} accumulator (kept zero between uses)
   uint32_t* hub_keys;
   unsigned long long* hub_vals;
+  // LDS-resident hub kernel: work items (hub, key partition), per-hub
+  // partial results and completion counters, overflow list for the tables
+  // above, and the distinct-key estimate of each hub from its last use
+  unsigned long long* hub_items;
+  double* hub_pdq;             // hub index * kHubMaxParts + partition
+  uint32_t* hub_pc;
+  uint32_t* hub_pkeys;         // distinct keys seen by each partition
+  unsigned int* hub_done;      // hub index -> finished partitions (kept zero between uses)
+  uint32_t* hub_over_list;
+  uint32_t* hub_est;           // vertex -> distinct neighbour communities at the last use (0: unknown)
 };
 
 // Hub layout of one level: hubs (degree above the last LDS bin) get table
@@ -71,6 +81,7 @@ void launch_distribute(hipStream_t s, const uint32_t* in_list, const unsigned in
 void launch_bin(hipStream_t s, const uint32_t* list, const unsigned int* count, uint32_t n_upper, const uint32_t* len,
                 const uint8_t* in_range, uint32_t* bin_lists, size_t stride, Ctl* ctl);
 // maxdeg: largest degree of the level (sizes the hub kernels)
+constexpr uint32_t kHubMaxParts = 16;
 template <typename W, bool REFINE>
 void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, size_t stride, unsigned int* bin_counts,
                        const uint64_t* bin_upper, uint32_t maxdeg);
@@ -118,11 +129,13 @@ void subset_renumber(hipStream_t s, uint32_t n, uint32_t* C, int64_t*& S, uint32
 
 template <typename W>
 void launch_split_init(hipStream_t s, uint32_t n, const uint32_t* C, const uint8_t* dS, const uint8_t* dR,
-                       uint32_t* lab, uint32_t* list, Ctl* ctl);
+                       uint32_t* lab, uint32_t* list, unsigned long long* main_key, Ctl* ctl);
 template <typename W>
-void launch_split_hook(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* lab, const uint32_t* list,
-                       const uint32_t* bin_lists, size_t stride, const unsigned int* bin_counts,
-                       const uint64_t* bin_upper, Ctl* ctl, uint32_t n_upper);
+void launch_split_sample(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* lab, const uint32_t* list,
+                         unsigned long long* main_key, uint32_t* rest, Ctl* ctl, uint32_t n_upper);
+template <typename W>
+void launch_split_union(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* lab, const uint32_t* bin_lists,
+                        size_t stride, const unsigned int* bin_counts, const uint64_t* bin_upper);
 void launch_split_finish(hipStream_t s, uint32_t* C, uint32_t* lab, const uint32_t* list, Ctl* ctl, uint32_t n_upper);
 
 void launch_refine_reset(hipStream_t s, uint32_t n, uint32_t* C, uint32_t* CB, int64_t* S, const int64_t* K,

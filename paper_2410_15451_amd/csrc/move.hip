@@ -286,10 +286,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_insert(DecideParams<W> p) {
       __syncthreads();
     }
   }
-  if (edges) {
-    atomicAdd(&p.ctl->edges, edges);
-    if (sizeof(W) == 4) atomicAdd(&p.ctl->kt_units[LEIDEN_KT_HUB_INSERT], edges);
-  }
+  if (edges) atomicAdd(&p.ctl->edges, edges);
 }
 
 template <typename W, bool REFINE>
@@ -328,6 +325,211 @@ __global__ __launch_bounds__(kBlock) void k_hub_select(DecideParams<W> p) {
       if (valid) emit_decision<W, REFINE>(p, v, d, bdq, bc);
     }
     __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Hub bin, LDS-resident form.  The neighbour communities of a hub are split
+// into P key partitions (P from the hub's distinct-community count at its
+// last use, else from its degree); one 1024-thread block per (hub, partition)
+// scans the whole row, sums the weights of its partition's communities in a
+// 16384-slot LDS table and picks its best candidate.  The last block of a hub
+// combines the partial results.  A table that reaches its capacity sends the
+// hub to the global-table kernels above instead (no decision is emitted
+// here), so the result never depends on the estimate.
+// ---------------------------------------------------------------------------
+constexpr int kHubThreads = 1024;
+constexpr uint32_t kHubLdsSlots = 16384, kHubLdsCap = 12288;
+
+__device__ inline uint32_t hub_parts(uint32_t est, uint32_t len) {
+  const uint32_t d = est ? est + est / 4 : len;
+  const uint32_t p = (d + kHubLdsCap - 1) / kHubLdsCap;
+  return p < 1 ? 1 : (p > kHubMaxParts ? kHubMaxParts : p);
+}
+
+__device__ inline uint32_t key_part(uint32_t c, uint32_t P) { return P == 1 ? 0 : (fmix32(c) >> 4) % P; }
+
+template <typename W>
+__global__ __launch_bounds__(kBlock) void k_hub_items(DecideParams<W> p) {
+  const uint32_t cnt = *p.count;
+  for (uint32_t h = blockIdx.x * kBlock + threadIdx.x; h < cnt; h += gridDim.x * kBlock) {
+    const uint32_t v = p.list[h];
+    const uint32_t P = hub_parts(p.hub_est[v], p.g.len[v]);
+    const unsigned int base = atomicAdd(&p.ctl->hub_items, P);
+    for (uint32_t q = 0; q < P; ++q)
+      p.hub_items[base + q] = ((unsigned long long)v << 32) | ((unsigned long long)P << 8) | q;
+  }
+}
+
+template <typename T>
+__device__ inline T hub_block_sum(T x, T* red) {
+  x = group_sum<kWave>(x);
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = x;
+  __syncthreads();
+  T r = 0;
+#pragma unroll
+  for (int i = 0; i < kHubThreads / kWave; ++i) r += red[i];
+  __syncthreads();
+  return r;
+}
+
+__device__ inline void hub_block_best(double& dq, uint32_t& c, double* rdq, uint32_t* rc) {
+  group_best<kWave>(dq, c);
+  if (threadIdx.x % kWave == 0) {
+    rdq[threadIdx.x / kWave] = dq;
+    rc[threadIdx.x / kWave] = c;
+  }
+  __syncthreads();
+  dq = -INFINITY;
+  c = kNone;
+#pragma unroll
+  for (int i = 0; i < kHubThreads / kWave; ++i)
+    if (better(rdq[i], rc[i], dq, c)) {
+      dq = rdq[i];
+      c = rc[i];
+    }
+  __syncthreads();
+}
+
+template <typename W, bool REFINE>
+__global__ __launch_bounds__(kHubThreads) void k_hub_lds(DecideParams<W> p) {
+  __shared__ uint32_t tk[kHubLdsSlots];
+  __shared__ uint32_t tv[kHubLdsSlots];
+  __shared__ unsigned long long red[kHubThreads / kWave];
+  __shared__ double rdq[kHubThreads / kWave];
+  __shared__ uint32_t rc[kHubThreads / kWave];
+  __shared__ unsigned int used, over, last;
+  constexpr uint32_t mask = kHubLdsSlots - 1;
+  const uint32_t items = p.ctl->hub_items;
+  unsigned long long edges = 0;
+  for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const unsigned long long item = p.hub_items[it];
+    const uint32_t v = (uint32_t)(item >> 32), P = (uint32_t)(item >> 8) & 0xFFu, q = (uint32_t)item & 0xFFu;
+    const uint32_t d = p.C[v];
+    const uint32_t hi = p.hub_idx[v];
+    const bool valid = !(REFINE && p.size[d] != 1);  // block-uniform
+    for (uint32_t sl = threadIdx.x; sl < kHubLdsSlots; sl += kHubThreads) {
+      tk[sl] = kNone;
+      tv[sl] = 0;
+    }
+    if (threadIdx.x == 0) {
+      used = 0;
+      // 32-bit sums need K_i < 2^32; a heavier hub takes the global tables
+      over = p.K[v] >= (int64_t)0xFFFFFFFFll ? 1u : 0u;
+    }
+    __syncthreads();
+    unsigned long long kid = 0;
+    if (valid && !over) {
+      const int64_t s0 = p.g.start[v];
+      const uint32_t L = p.g.len[v];
+      const uint32_t bnd = REFINE ? p.CB[v] : 0;
+      for (uint32_t e = threadIdx.x; e < L; e += kHubThreads) {
+        const uint32_t j = p.g.cols[s0 + e];
+        if (j == v) continue;
+        if (REFINE && p.CB[j] != bnd) continue;
+        const uint32_t c = p.C[j];
+        const uint32_t w = (uint32_t)p.g.w[s0 + e];
+        if (c == d) {
+          kid += w;
+          continue;
+        }
+        if (key_part(c, P) != q || __atomic_load_n(&over, __ATOMIC_RELAXED)) continue;
+        uint32_t h = slot_hash(c, mask);
+        while (true) {
+          const uint32_t k = tk[h];
+          if (k == c) {
+            atomicAdd(&tv[h], w);
+            break;
+          }
+          if (k == kNone) {
+            const uint32_t o = atomicCAS(&tk[h], kNone, c);
+            if (o == kNone) {
+              atomicAdd(&tv[h], w);
+              // at most kHubLdsCap + 2 * kHubThreads slots are ever claimed
+              if (atomicAdd(&used, 1u) + 1 >= kHubLdsCap) atomicExch(&over, 1u);
+              break;
+            }
+            if (o == c) {
+              atomicAdd(&tv[h], w);
+              break;
+            }
+          }
+          h = (h + 1) & mask;
+        }
+      }
+    }
+    kid = hub_block_sum(kid, red);
+    double bdq = -INFINITY;
+    uint32_t bc = kNone;
+    const bool ok = valid && !over;
+    if (ok) {
+      const int64_t ki = p.K[v], sd = p.S[d];
+      for (uint32_t sl = threadIdx.x; sl < kHubLdsSlots; sl += kHubThreads) {
+        const uint32_t c = tk[sl];
+        if (c == kNone || !allowed_target<W, REFINE>(p, c)) continue;
+        const double dq = delta_q((int64_t)tv[sl], (int64_t)kid, ki, p.S[c], sd, p.inv_m, p.inv_2m2);
+        if (better(dq, c, bdq, bc)) {
+          bdq = dq;
+          bc = c;
+        }
+      }
+    }
+    hub_block_best(bdq, bc, rdq, rc);
+    if (threadIdx.x == 0) {
+      if (P == 1) {
+        if (ok) {
+          emit_decision<W, REFINE>(p, v, d, bdq, bc);
+          p.hub_est[v] = used;
+          if (!REFINE) edges += p.g.len[v];
+        } else if (valid) {
+          p.hub_over_list[atomicAdd(&p.ctl->hub_over, 1u)] = v;
+        }
+        last = 0;
+      } else {
+        const size_t slot = (size_t)hi * kHubMaxParts + q;
+        p.hub_pdq[slot] = ok ? bdq : NAN;  // NaN marks an overflowed partition
+        p.hub_pc[slot] = bc;
+        p.hub_pkeys[slot] = used;
+        __threadfence();
+        last = atomicAdd(&p.hub_done[hi], 1u) == P - 1 ? 1u : 0u;
+      }
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+      // every partition of this hub has finished: combine in partition order
+      __threadfence();
+      bool all_ok = true;
+      double cdq = -INFINITY;
+      uint32_t cc = kNone, keys = 0;
+      const size_t base = (size_t)hi * kHubMaxParts;
+      for (uint32_t r = 0; r < P; ++r) {
+        const double x = __longlong_as_double((long long)__atomic_load_n(
+            reinterpret_cast<unsigned long long*>(&p.hub_pdq[base + r]), __ATOMIC_RELAXED));
+        const uint32_t xc = __atomic_load_n(&p.hub_pc[base + r], __ATOMIC_RELAXED);
+        keys += __atomic_load_n(&p.hub_pkeys[base + r], __ATOMIC_RELAXED);
+        if (x != x) {
+          all_ok = false;
+          continue;
+        }
+        if (better(x, xc, cdq, cc)) {
+          cdq = x;
+          cc = xc;
+        }
+      }
+      p.hub_done[hi] = 0;
+      if (all_ok) {
+        emit_decision<W, REFINE>(p, v, d, cdq, cc);
+        p.hub_est[v] = keys;
+        if (!REFINE) edges += p.g.len[v];
+      } else if (valid) {
+        p.hub_over_list[atomicAdd(&p.ctl->hub_over, 1u)] = v;
+      }
+    }
+    __syncthreads();
+  }
+  if (edges) {
+    atomicAdd(&p.ctl->edges, edges);
+    if (sizeof(W) == 4 && !REFINE) atomicAdd(&p.ctl->kt_units[LEIDEN_KT_HUB_INSERT], edges);
   }
 }
 
@@ -459,6 +661,8 @@ __global__ void k_subround_reset(Ctl* ctl) {
   if (threadIdx.x == 0) {
     ctl->mover_count = 0;
     ctl->big_count = 0;
+    ctl->hub_items = 0;
+    ctl->hub_over = 0;
   }
 }
 
@@ -527,13 +731,21 @@ void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, si
         hipLaunchKernelGGL((k_decide_block<4096, W, REFINE>), dim3(grid_for(bin_upper[b], 1, 1024)), dim3(kBlock), 0,
                            s, q);
         break;
-      default:
+      default: {
+        hipLaunchKernelGGL((k_hub_items<W>), dim3(grid_for(bin_upper[b], kBlock, 64)), dim3(kBlock), 0, s, q);
         if (sizeof(W) == 4 && !REFINE) kt_mark(LEIDEN_KT_HUB_INSERT, s);
+        hipLaunchKernelGGL((k_hub_lds<W, REFINE>), dim3(grid_for(bin_upper[b] * kHubMaxParts, 1, 4096)),
+                           dim3(kHubThreads), 0, s, q);
+        if (sizeof(W) == 4 && !REFINE) kt_mark(LEIDEN_KT_HUB_INSERT, s);
+        // hubs whose LDS tables overflowed (usually none)
+        DecideParams<W> o = q;
+        o.list = p.hub_over_list;
+        o.count = &p.ctl->hub_over;
         hipLaunchKernelGGL((k_hub_insert<W, REFINE>), dim3(grid_for(bin_upper[b] * (maxdeg / kHubChunk + 1), 1, 1024)),
-                           dim3(kBlock), 0, s, q);
-        if (sizeof(W) == 4 && !REFINE) kt_mark(LEIDEN_KT_HUB_INSERT, s);
-        hipLaunchKernelGGL((k_hub_select<W, REFINE>), dim3(grid_for(bin_upper[b], 1, 1024)), dim3(kBlock), 0, s, q);
+                           dim3(kBlock), 0, s, o);
+        hipLaunchKernelGGL((k_hub_select<W, REFINE>), dim3(grid_for(bin_upper[b], 1, 1024)), dim3(kBlock), 0, s, o);
         break;
+      }
     }
   }
 }

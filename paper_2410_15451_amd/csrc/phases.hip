@@ -126,11 +126,25 @@ void subset_renumber(hipStream_t s, uint32_t n, uint32_t* C, int64_t*& S, uint32
 // ---------------------------------------------------------------------------
 // Alg. 7 by its definition: connected components of the subgraph induced by
 // each community marked to be split and not refined, labelled by their
-// minimum vertex (hooking larger roots under smaller ones until no edge joins
-// two roots).
+// minimum vertex.
+//
+// Concurrent union-find in which a union always hangs the larger root under
+// the smaller one (so parent[x] <= x and every root is the minimum vertex of
+// its tree), in the sampled form of Sutton et al., "Optimizing Parallel Graph
+// Connectivity Computation via Subgraph Sampling" (IPDPS 2018):
+//   1. union each split vertex with the same-community neighbours among the
+//      first kSplitSample entries of its row, then compress;
+//   2. per community, take the tree of its highest-degree member as the main
+//      tree; a vertex already in it skips its row (each of its edges is either
+//      inside the main tree or seen from the other endpoint);
+//   3. every other split vertex unions all its same-community neighbours;
+//   4. compress: the root of each vertex is its component's minimum vertex.
 // ---------------------------------------------------------------------------
+constexpr uint32_t kSplitSample = 4;
+
 __global__ __launch_bounds__(kBlock) void k_split_init(uint32_t n, const uint32_t* C, const uint8_t* dS,
-                                                       const uint8_t* dR, uint32_t* lab, uint32_t* list, Ctl* ctl) {
+                                                       const uint8_t* dR, uint32_t* lab, uint32_t* list,
+                                                       unsigned long long* main_key, Ctl* ctl) {
   __shared__ unsigned int s2[2];
   for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < n; base += (uint64_t)gridDim.x * kBlock) {
     const uint64_t i = base + threadIdx.x;
@@ -139,77 +153,108 @@ __global__ __launch_bounds__(kBlock) void k_split_init(uint32_t n, const uint32_
       const uint32_t c = C[i];
       lab[i] = (uint32_t)i;
       in = dS[c] && !dR[c];
+      if (in) main_key[c] = 0;
     }
     block_append(list, &ctl->split_count, in, (uint32_t)i, s2);
   }
 }
 
-__device__ inline uint32_t find_root(uint32_t* lab, uint32_t x) {
+__device__ inline uint32_t uf_find(uint32_t* p, uint32_t x) {
+  // path halving: every pointer written is an ancestor of the node
+  uint32_t px = __atomic_load_n(&p[x], __ATOMIC_RELAXED);
+  while (px != x) {
+    const uint32_t gp = __atomic_load_n(&p[px], __ATOMIC_RELAXED);
+    if (gp != px) __atomic_store_n(&p[x], gp, __ATOMIC_RELAXED);
+    x = gp;
+    px = __atomic_load_n(&p[x], __ATOMIC_RELAXED);
+  }
+  return x;
+}
+
+__device__ inline void uf_union(uint32_t* p, uint32_t a, uint32_t b) {
   while (true) {
-    const uint32_t p = __atomic_load_n(&lab[x], __ATOMIC_RELAXED);
-    if (p == x) return x;
-    x = p;
+    a = uf_find(p, a);
+    b = uf_find(p, b);
+    if (a == b) return;
+    if (a > b) {
+      const uint32_t t = a;
+      a = b;
+      b = t;
+    }
+    // hang root b under the smaller root a; retry if b stopped being a root
+    if (atomicCAS(&p[b], b, a) == b) return;
   }
 }
 
-// One round of minimum-label propagation: each vertex takes the smallest
-// label among itself and its same-community neighbours (a wavefront
-// reduction, no per-edge atomics) and hooks its current parent to it.  Labels
-// only decrease and always name a vertex of the same component, so the
-// fixpoint labels every component by its minimum vertex.
-// G lanes per vertex (G <= 64 inside a wavefront, G = kBlock for a block);
-// the vertices come from the degree bin lists of the split vertices.
-template <int G, typename W>
-__global__ __launch_bounds__(kBlock) void k_split_hook(Rows<W> g, const uint32_t* C, uint32_t* lab,
-                                                       const uint32_t* list, const unsigned int* count, Ctl* ctl) {
-  __shared__ uint32_t red[kBlock / kWave];
-  const uint32_t grp = threadIdx.x / G, lane = threadIdx.x % G;
-  constexpr uint32_t GPB = kBlock / G;
-  const uint32_t cnt = *count;
-  bool changed = false;
-  for (uint32_t base = blockIdx.x * GPB; base < cnt; base += gridDim.x * GPB) {
-    const uint32_t it = base + grp;
-    uint32_t m = kNone, i = 0;
-    if (it < cnt) {
-      i = list[it];
-      const uint32_t c = C[i];
-      const int64_t s0 = g.start[i];
-      const uint32_t L = g.len[i];
-      m = __atomic_load_n(&lab[i], __ATOMIC_RELAXED);
-      for (uint32_t e = lane; e < L; e += G) {
-        const uint32_t j = g.cols[s0 + e];
-        if (j == i || C[j] != c) continue;
-        m = min(m, __atomic_load_n(&lab[j], __ATOMIC_RELAXED));
-      }
-    }
-    if (G <= kWave) {
-#pragma unroll
-      for (int o = G / 2; o > 0; o >>= 1) m = min(m, (uint32_t)__shfl_xor(m, o, G));
-    } else {
-#pragma unroll
-      for (int o = kWave / 2; o > 0; o >>= 1) m = min(m, (uint32_t)__shfl_xor(m, o, kWave));
-      if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = m;
-      __syncthreads();
-      m = min(min(red[0], red[1]), min(red[2], red[3]));
-      __syncthreads();
-    }
-    if (it < cnt && lane == 0) {
-      const uint32_t li = __atomic_load_n(&lab[i], __ATOMIC_RELAXED);
-      if (m < li) {
-        atomicMin(&lab[i], m);
-        atomicMin(&lab[li], m);
-        changed = true;
-      }
+template <typename W>
+__global__ __launch_bounds__(kBlock) void k_split_sample(Rows<W> g, const uint32_t* C, uint32_t* lab,
+                                                         const uint32_t* list, const Ctl* ctl) {
+  const uint32_t cnt = ctl->split_count;
+  GRID_STRIDE(it, cnt) {
+    const uint32_t u = list[it];
+    const uint32_t c = C[u];
+    const int64_t s0 = g.start[u];
+    const uint32_t L = min(g.len[u], kSplitSample);
+    for (uint32_t e = 0; e < L; ++e) {
+      const uint32_t j = g.cols[s0 + e];
+      if (j != u && C[j] == c) uf_union(lab, u, j);
     }
   }
-  if (changed) ctl->changed = 1;
 }
 
-__global__ __launch_bounds__(kBlock) void k_split_compress(uint32_t* lab, const uint32_t* list, Ctl* ctl) {
+__global__ __launch_bounds__(kBlock) void k_split_compress(uint32_t* lab, const uint32_t* list, const Ctl* ctl) {
   const uint32_t cnt = ctl->split_count;
   GRID_STRIDE(it, cnt) {
     const uint32_t i = list[it];
-    lab[i] = find_root(lab, i);
+    lab[i] = uf_find(lab, i);
+  }
+}
+
+// main tree of each community: its member of highest degree (lowest ID on ties)
+__global__ __launch_bounds__(kBlock) void k_split_main(const uint32_t* len, const uint32_t* C, const uint32_t* list,
+                                                       unsigned long long* main_key, const Ctl* ctl) {
+  const uint32_t cnt = ctl->split_count;
+  GRID_STRIDE(it, cnt) {
+    const uint32_t u = list[it];
+    atomicMax(&main_key[C[u]], ((unsigned long long)len[u] << 32) | (unsigned long long)(0xFFFFFFFFu - u));
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_split_rest(const uint32_t* C, const uint32_t* lab, const uint32_t* list,
+                                                       const unsigned long long* main_key, uint32_t* rest, Ctl* ctl) {
+  __shared__ unsigned int s2[2];
+  const uint32_t cnt = ctl->split_count;
+  for (uint32_t base = blockIdx.x * kBlock; base < cnt; base += gridDim.x * kBlock) {
+    const uint32_t it = base + threadIdx.x;
+    bool out = false;
+    uint32_t u = 0;
+    if (it < cnt) {
+      u = list[it];
+      const uint32_t m = 0xFFFFFFFFu - (uint32_t)(main_key[C[u]] & 0xFFFFFFFFull);
+      out = lab[u] != lab[m];  // both are roots after compression
+    }
+    block_append(rest, &ctl->split_rest, out, u, s2);
+  }
+}
+
+// G lanes per vertex (G <= 64 inside a wavefront, G = kBlock for a block)
+template <int G, typename W>
+__global__ __launch_bounds__(kBlock) void k_split_union(Rows<W> g, const uint32_t* C, uint32_t* lab,
+                                                        const uint32_t* list, const unsigned int* count) {
+  const uint32_t grp = threadIdx.x / G, lane = threadIdx.x % G;
+  constexpr uint32_t GPB = kBlock / G;
+  const uint32_t cnt = *count;
+  for (uint32_t base = blockIdx.x * GPB; base < cnt; base += gridDim.x * GPB) {
+    const uint32_t it = base + grp;
+    if (it >= cnt) continue;
+    const uint32_t u = list[it];
+    const uint32_t c = C[u];
+    const int64_t s0 = g.start[u];
+    const uint32_t L = g.len[u];
+    for (uint32_t e = lane; e < L; e += G) {
+      const uint32_t j = g.cols[s0 + e];
+      if (j != u && C[j] == c) uf_union(lab, u, j);
+    }
   }
 }
 
@@ -217,49 +262,56 @@ __global__ __launch_bounds__(kBlock) void k_split_finish(uint32_t* C, uint32_t* 
   const uint32_t cnt = ctl->split_count;
   GRID_STRIDE(it, cnt) {
     const uint32_t i = list[it];
-    C[i] = find_root(lab, i);
+    C[i] = uf_find(lab, i);
   }
 }
 
-__global__ void k_reset_changed(Ctl* ctl, int also_count) {
+__global__ void k_split_reset(Ctl* ctl) {
   if (threadIdx.x == 0) {
-    ctl->changed = 0;
-    if (also_count) ctl->split_count = 0;
+    ctl->split_count = 0;
+    ctl->split_rest = 0;
   }
 }
 
 template <typename W>
 void launch_split_init(hipStream_t s, uint32_t n, const uint32_t* C, const uint8_t* dS, const uint8_t* dR,
-                       uint32_t* lab, uint32_t* list, Ctl* ctl) {
-  hipLaunchKernelGGL(k_reset_changed, dim3(1), dim3(1), 0, s, ctl, 1);
-  if (n) hipLaunchKernelGGL(k_split_init, dim3(grid_n(n)), dim3(kBlock), 0, s, n, C, dS, dR, lab, list, ctl);
+                       uint32_t* lab, uint32_t* list, unsigned long long* main_key, Ctl* ctl) {
+  hipLaunchKernelGGL(k_split_reset, dim3(1), dim3(1), 0, s, ctl);
+  if (n)
+    hipLaunchKernelGGL(k_split_init, dim3(grid_n(n)), dim3(kBlock), 0, s, n, C, dS, dR, lab, list, main_key, ctl);
 }
 
-// One propagation round over the degree-binned split vertices (bins as in
-// the local-moving kernels), then full path compression.
 template <typename W>
-void launch_split_hook(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* lab, const uint32_t* list,
-                       const uint32_t* bin_lists, size_t stride, const unsigned int* bin_counts,
-                       const uint64_t* bin_upper, Ctl* ctl, uint32_t n_upper) {
-  hipLaunchKernelGGL(k_reset_changed, dim3(1), dim3(1), 0, s, ctl, 0);
+void launch_split_sample(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* lab, const uint32_t* list,
+                         unsigned long long* main_key, uint32_t* rest, Ctl* ctl, uint32_t n_upper) {
+  hipLaunchKernelGGL((k_split_sample<W>), dim3(grid_n(n_upper)), dim3(kBlock), 0, s, g, C, lab, list, ctl);
+  hipLaunchKernelGGL(k_split_compress, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, lab, list, ctl);
+  hipLaunchKernelGGL(k_split_main, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, g.len, C, list, main_key, ctl);
+  hipLaunchKernelGGL(k_split_rest, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, C, lab, list, main_key, rest, ctl);
+}
+
+// Full rows of the vertices outside their community's main tree, by degree
+// bin (bins as in the local-moving kernels).
+template <typename W>
+void launch_split_union(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* lab, const uint32_t* bin_lists,
+                        size_t stride, const unsigned int* bin_counts, const uint64_t* bin_upper) {
   for (int b = 0; b < kBins; ++b) {
     if (!bin_upper[b]) continue;
     const uint32_t* bl = bin_lists + (size_t)b * stride;
     const unsigned int* bc = bin_counts + b;
     if (b == 0)
-      hipLaunchKernelGGL((k_split_hook<8, W>), dim3(grid_n(bin_upper[b], kBlock / 8, 4096)), dim3(kBlock), 0, s, g, C,
-                         lab, bl, bc, ctl);
+      hipLaunchKernelGGL((k_split_union<8, W>), dim3(grid_n(bin_upper[b], kBlock / 8, 4096)), dim3(kBlock), 0, s,
+                         g, C, lab, bl, bc);
     else if (b == 1)
-      hipLaunchKernelGGL((k_split_hook<32, W>), dim3(grid_n(bin_upper[b], kBlock / 32, 4096)), dim3(kBlock), 0, s, g,
-                         C, lab, bl, bc, ctl);
+      hipLaunchKernelGGL((k_split_union<32, W>), dim3(grid_n(bin_upper[b], kBlock / 32, 4096)), dim3(kBlock), 0, s,
+                         g, C, lab, bl, bc);
     else if (b == 2)
-      hipLaunchKernelGGL((k_split_hook<64, W>), dim3(grid_n(bin_upper[b], kBlock / 64, 4096)), dim3(kBlock), 0, s, g,
-                         C, lab, bl, bc, ctl);
+      hipLaunchKernelGGL((k_split_union<64, W>), dim3(grid_n(bin_upper[b], kBlock / 64, 4096)), dim3(kBlock), 0, s,
+                         g, C, lab, bl, bc);
     else
-      hipLaunchKernelGGL((k_split_hook<kBlock, W>), dim3(grid_n(bin_upper[b], 1, 4096)), dim3(kBlock), 0, s, g, C,
-                         lab, bl, bc, ctl);
+      hipLaunchKernelGGL((k_split_union<kBlock, W>), dim3(grid_n(bin_upper[b], 1, 4096)), dim3(kBlock), 0, s, g, C,
+                         lab, bl, bc);
   }
-  hipLaunchKernelGGL(k_split_compress, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, lab, list, ctl);
 }
 
 void launch_split_finish(hipStream_t s, uint32_t* C, uint32_t* lab, const uint32_t* list, Ctl* ctl, uint32_t n_upper) {
@@ -267,15 +319,17 @@ void launch_split_finish(hipStream_t s, uint32_t* C, uint32_t* lab, const uint32
 }
 
 template void launch_split_init<uint32_t>(hipStream_t, uint32_t, const uint32_t*, const uint8_t*, const uint8_t*,
-                                          uint32_t*, uint32_t*, Ctl*);
+                                          uint32_t*, uint32_t*, unsigned long long*, Ctl*);
 template void launch_split_init<int64_t>(hipStream_t, uint32_t, const uint32_t*, const uint8_t*, const uint8_t*,
-                                         uint32_t*, uint32_t*, Ctl*);
-template void launch_split_hook<uint32_t>(hipStream_t, Rows<uint32_t>, const uint32_t*, uint32_t*, const uint32_t*,
-                                          const uint32_t*, size_t, const unsigned int*, const uint64_t*, Ctl*,
-                                          uint32_t);
-template void launch_split_hook<int64_t>(hipStream_t, Rows<int64_t>, const uint32_t*, uint32_t*, const uint32_t*,
-                                         const uint32_t*, size_t, const unsigned int*, const uint64_t*, Ctl*,
-                                         uint32_t);
+                                         uint32_t*, uint32_t*, unsigned long long*, Ctl*);
+template void launch_split_sample<uint32_t>(hipStream_t, Rows<uint32_t>, const uint32_t*, uint32_t*,
+                                            const uint32_t*, unsigned long long*, uint32_t*, Ctl*, uint32_t);
+template void launch_split_sample<int64_t>(hipStream_t, Rows<int64_t>, const uint32_t*, uint32_t*, const uint32_t*,
+                                           unsigned long long*, uint32_t*, Ctl*, uint32_t);
+template void launch_split_union<uint32_t>(hipStream_t, Rows<uint32_t>, const uint32_t*, uint32_t*, const uint32_t*,
+                                           size_t, const unsigned int*, const uint64_t*);
+template void launch_split_union<int64_t>(hipStream_t, Rows<int64_t>, const uint32_t*, uint32_t*, const uint32_t*,
+                                          size_t, const unsigned int*, const uint64_t*);
 
 // ---------------------------------------------------------------------------
 // Alg. 8, first loop: vertices of refined bounds become singletons; they are

@@ -108,12 +108,13 @@ struct leiden_graph {
   uint32_t maxdeg0 = 0;
   // workspace
   Buf C, K, Kb, Kt, S, S2, size, size2, dS, dS2, dR, dR2, CB, rep, Ctop, pend, unproc;
-  Buf cls_lists, bin_lists, iter_list, next_list, movers, split_list, lab;
+  Buf cls_lists, bin_lists, iter_list, next_list, movers, split_list, split_rest, split_key, lab;
   Buf flag, newid, scan_tmp, ctl, small;
   Buf lvA_start, lvA_len, lvA_cols, lvA_w, lvB_start, lvB_len, lvB_cols, lvB_w;
   Buf agg_count, agg_off, agg_fill, agg_members, agg_deg, agg_cap, agg_lists, agg_bigcap, agg_tbl, agg_keys, agg_vals,
       agg_items, big_list;
   Buf hub_keys, hub_vals, hub_list, hub_idx, hub_off, hub_mask, hub_size, hub_kid;
+  Buf hub_items, hub_pdq, hub_pc, hub_pkeys, hub_done, hub_over_list, hub_est0, hub_estL;
   Buf tr_minv, tr_hk, tr_hv, tr_bw, tr_bv, tr_cw, tr_cb, tr_old, tr_flag, tr_rank, tr_frank, tr_fid, tr_label,
       tr_matched;
   Buf dV, dE, dC, sig, partials, modparts;
@@ -218,6 +219,8 @@ leiden_status ensure_workspace(leiden_graph* G, uint32_t classes) {
   CHK(G->next_list.reserve(n * u32));
   CHK(G->movers.reserve(n * sizeof(Mover)));
   CHK(G->split_list.reserve(n * u32));
+  CHK(G->split_rest.reserve(n * u32));
+  CHK(G->split_key.reserve(n * u64));
   CHK(G->lab.reserve(n * u32));
   CHK(G->flag.reserve(n * u32));
   CHK(G->newid.reserve((n + 1) * u64));
@@ -292,6 +295,22 @@ leiden_status setup_hubs(leiden_graph* G, hipStream_t s, const uint32_t* len, ui
   uint64_t slots = 0;
   if (hub_layout(s, len, nl, h, dctl(G), G->scan_tmp.p, G->small.as<uint64_t>() + 64, &cnt, &slots) != 0)
     return fail(LEIDEN_EDEVICE, "hub layout failed");
+  // LDS-resident hub kernel: items, partial results, counters, estimates
+  const size_t hc = std::max<uint32_t>(cnt, 1);
+  CHK(G->hub_items.reserve(hc * kHubMaxParts * 8));
+  CHK(G->hub_pdq.reserve(hc * kHubMaxParts * 8));
+  CHK(G->hub_pc.reserve(hc * kHubMaxParts * 4));
+  CHK(G->hub_pkeys.reserve(hc * kHubMaxParts * 4));
+  CHK(G->hub_over_list.reserve(hc * 4));
+  if (G->hub_done.bytes < hc * 4) {
+    CHK(G->hub_done.reserve(hc * 4));
+    fill_u32(s, G->hub_done.as<uint32_t>(), 0, G->hub_done.bytes / 4);
+  }
+  for (Buf* b : {&G->hub_est0, &G->hub_estL})
+    if (b->bytes < n * 4) {
+      CHK(b->reserve(n * 4));
+      fill_u32(s, b->as<uint32_t>(), 0, b->bytes / 4);
+    }
   if (slots * 4 > G->hub_keys.bytes || slots * 8 > G->hub_vals.bytes) {
     const uint64_t want = slots + slots / 4 + 4096;
     CHK(G->hub_keys.reserve(want * 4));
@@ -310,6 +329,13 @@ void bind_hubs(leiden_graph* G, DecideParams<W>& dp) {
   dp.hub_kid = G->hub_kid.as<unsigned long long>();
   dp.hub_keys = G->hub_keys.as<uint32_t>();
   dp.hub_vals = G->hub_vals.as<unsigned long long>();
+  dp.hub_items = G->hub_items.as<unsigned long long>();
+  dp.hub_pdq = G->hub_pdq.as<double>();
+  dp.hub_pc = G->hub_pc.as<uint32_t>();
+  dp.hub_pkeys = G->hub_pkeys.as<uint32_t>();
+  dp.hub_done = G->hub_done.as<unsigned int>();
+  dp.hub_over_list = G->hub_over_list.as<uint32_t>();
+  dp.hub_est = sizeof(W) == 4 ? G->hub_est0.as<uint32_t>() : G->hub_estL.as<uint32_t>();
 }
 
 leiden_status read_ctl(leiden_graph* G, hipStream_t s) {
@@ -470,19 +496,14 @@ leiden_status split(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, Leve
   Ctl* ctl = dctl(G);
   uint32_t* lab = G->lab.as<uint32_t>();
   uint32_t* list = G->split_list.as<uint32_t>();
-  launch_split_init<W>(s, nl, L.C, L.dS, L.dR, lab, list, ctl);
-  // split vertices by degree, for the group sizes of the propagation kernels
+  uint32_t* rest = G->split_rest.as<uint32_t>();
+  unsigned long long* key = G->split_key.as<unsigned long long>();
+  launch_split_init<W>(s, nl, L.C, L.dS, L.dR, lab, list, key, ctl);
+  launch_split_sample<W>(s, g, L.C, lab, list, key, rest, ctl, nl);
+  // vertices outside their community's main tree, by degree
   launch_subround_reset(s, ctl);
-  launch_bin(s, list, &ctl->split_count, nl, g.len, nullptr, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl);
-  // labels strictly decrease while anything changes, so the loop ends; the
-  // cap only guards against a defect
-  for (int it = 0;; ++it) {
-    launch_split_hook<W>(s, g, L.C, lab, list, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, ctl,
-                         nl);
-    CHK(read_ctl(G, s));
-    if (!G->hctl->changed) break;
-    if (it == 4096) return fail(LEIDEN_EDEVICE, "split did not converge");
-  }
+  launch_bin(s, rest, &ctl->split_rest, nl, g.len, nullptr, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl);
+  launch_split_union<W>(s, g, L.C, lab, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins);
   launch_split_finish(s, L.C, lab, list, ctl, nl);
   return LEIDEN_OK;
 }
@@ -724,7 +745,7 @@ const char* leiden_kernel_name(int32_t kernel) {
     case LEIDEN_KT_NONE:
       return "";
     case LEIDEN_KT_HUB_INSERT:
-      return "lm::k_hub_insert<unsigned int, false>";
+      return "lm::k_hub_lds<unsigned int, false>";
     default:
       return nullptr;
   }
