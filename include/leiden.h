@@ -58,8 +58,8 @@ typedef enum {
    * neighbour's community, 4 bytes each). */
   LEIDEN_KT_HUB_INSERT = 1
 } leiden_kernel;
-/* (LEIDEN_KT_HUB_INSERT names the hub kernel that sums the rows in LDS; its
- * units are the entries of the hubs it decides, counted once per hub.) */
+/* (LEIDEN_KT_HUB_INSERT is the kernel that sums chunks of hub rows by
+ * community in LDS and merges them into per-hub tables.) */
 
 /* Parameters (defaults from Section 5.1.2). */
 typedef struct {

@@ -275,36 +275,97 @@ __device__ inline uint64_t row_of(const uint64_t* off, uint64_t nt, uint64_t x) 
   return lo;
 }
 
+// Entry-parallel walk over rows: the entries [0, tot) of consecutive rows
+// (row t owns [off[t], off[t + 1])) are cut into one contiguous range per
+// block.  A block finds the row of its first entry by binary search, then
+// stages kRowWin row offsets at a time in LDS; each thread finds its row in
+// that window, and the next tile starts from the row of the tile's last
+// entry.  Rows beyond the window (only when a tile spans more rows than the
+// window holds) are found by binary search.  f(t, x) runs once per entry x.
+constexpr uint32_t kRowWin = 512;
+
+__device__ inline uint64_t row_in(const uint64_t* off, uint64_t lo, uint64_t hi, uint64_t x) {
+  // largest t in [lo, hi) with off[t] <= x, given off[lo] <= x
+  while (hi - lo > 1) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (off[mid] <= x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <typename F>
+__device__ inline void block_rows_for_each(const uint64_t* off, uint64_t nt, uint64_t tot, F f) {
+  __shared__ uint64_t woff[kRowWin];
+  __shared__ uint64_t t0s, tnext;
+  const uint64_t per = (tot + gridDim.x - 1) / gridDim.x;
+  const uint64_t xb = (uint64_t)blockIdx.x * per, xe = min(tot, xb + per);
+  if (xb >= xe) return;  // block-uniform
+  if (threadIdx.x == 0) t0s = row_in(off, 0, nt, xb);
+  __syncthreads();
+  for (uint64_t x0 = xb; x0 < xe; x0 += kBlock) {
+    const uint64_t t0 = t0s;
+    const uint64_t w = min((uint64_t)kRowWin, nt - t0);
+    for (uint32_t k = threadIdx.x; k < w; k += kBlock) woff[k] = off[t0 + k];
+    __syncthreads();
+    const uint64_t x = x0 + threadIdx.x;
+    const uint64_t xl = min(x0 + kBlock, xe) - 1;
+    if (x <= xl) {
+      uint64_t t;
+      if (w == kRowWin && x >= woff[w - 1]) {
+        t = row_in(off, t0 + w - 1, nt, x);
+      } else {
+        uint64_t lo = 0, hi = w;
+        while (hi - lo > 1) {
+          const uint64_t mid = (lo + hi) >> 1;
+          if (woff[mid] <= x)
+            lo = mid;
+          else
+            hi = mid;
+        }
+        t = t0 + lo;
+      }
+      f(t, x);
+      if (x == xl) tnext = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) t0s = tnext;
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_old_len(uint64_t nt, const uint32_t* len, BatchBufs b) {
   GRID_STRIDE(t, nt) b.old_len[t] = len[b.touched[t]];
 }
 
+__device__ inline void merge_old_entry(uint64_t t, uint64_t x, const Rows<uint32_t>& g, const BatchBufs& b) {
+  const uint32_t r = b.touched[t];
+  const uint32_t p = (uint32_t)(x - b.old_off[t]);
+  const uint64_t s0 = b.seg_off[t];
+  const uint32_t L = (uint32_t)(b.seg_off[t + 1] - s0);
+  const int64_t r0 = g.start[r];
+  const uint32_t y = g.cols[r0 + p];
+  uint32_t lo = 0, hi = L;  // first segment entry with dst >= y
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (b.seg_dst[s0 + mid] < y)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  if (lo < L && b.seg_dst[s0 + lo] == y) return;  // deleted (insertions of present pairs were rejected)
+  const uint64_t dels = b.seg_pre[s0 + lo] - b.seg_pre[s0];
+  const uint64_t inss = lo - dels;
+  const uint64_t pos = b.out_off[t] + p - dels + inss;
+  b.mcols[pos] = y;
+  b.mw[pos] = g.w[r0 + p];
+}
+
 __global__ __launch_bounds__(kBlock) void k_merge_old(uint64_t nt, const uint64_t* total_old, Rows<uint32_t> g,
                                                       BatchBufs b) {
-  const uint64_t tot = *total_old;
-  GRID_STRIDE(x, tot) {
-    const uint64_t t = row_of(b.old_off, nt, x);
-    const uint32_t r = b.touched[t];
-    const uint32_t p = (uint32_t)(x - b.old_off[t]);
-    const uint64_t s0 = b.seg_off[t];
-    const uint32_t L = (uint32_t)(b.seg_off[t + 1] - s0);
-    const int64_t r0 = g.start[r];
-    const uint32_t y = g.cols[r0 + p];
-    uint32_t lo = 0, hi = L;  // first segment entry with dst >= y
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (b.seg_dst[s0 + mid] < y)
-        lo = mid + 1;
-      else
-        hi = mid;
-    }
-    if (lo < L && b.seg_dst[s0 + lo] == y) continue;  // deleted (insertions of present pairs were rejected)
-    const uint64_t dels = b.seg_pre[s0 + lo] - b.seg_pre[s0];
-    const uint64_t inss = lo - dels;
-    const uint64_t pos = b.out_off[t] + p - dels + inss;
-    b.mcols[pos] = y;
-    b.mw[pos] = g.w[r0 + p];
-  }
+  block_rows_for_each(b.old_off, nt, *total_old, [&](uint64_t t, uint64_t x) { merge_old_entry(t, x, g, b); });
 }
 
 __global__ __launch_bounds__(kBlock) void k_merge_ins(uint64_t ne, Rows<uint32_t> g, BatchBufs b) {
@@ -342,13 +403,11 @@ __global__ __launch_bounds__(kBlock) void k_commit_rows(uint64_t nt, int64_t* st
 
 __global__ __launch_bounds__(kBlock) void k_commit_copy(uint64_t nt, const uint64_t* total_new, uint32_t* cols,
                                                         uint32_t* w, BatchBufs b) {
-  const uint64_t tot = *total_new;
-  GRID_STRIDE(x, tot) {
-    const uint64_t t = row_of(b.out_off, nt, x);
+  block_rows_for_each(b.out_off, nt, *total_new, [&](uint64_t t, uint64_t x) {
     const uint64_t d = b.dest[t] + (x - b.out_off[t]);
     cols[d] = b.mcols[x];
     w[d] = b.mw[x];
-  }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -431,8 +490,8 @@ __global__ __launch_bounds__(kBlock) void k_aux_update(uint64_t ne, BatchBufs b,
     const long long w = (long long)b.seg_w[q];
     const long long sgn = b.seg_del[q] ? -w : w;
     atomicAdd((unsigned long long*)&K[i], (unsigned long long)sgn);
-    atomicAdd((unsigned long long*)&S[c], (unsigned long long)sgn);
-    atomicAdd((unsigned long long*)&dSig[c], (unsigned long long)w);
+    // large communities collect many entries: one atomic per community and wavefront
+    wave_add2_by_key(c, sgn, w, (long long*)S, (long long*)dSig);
   }
 }
 
@@ -487,9 +546,11 @@ __global__ __launch_bounds__(kBlock) void k_mark_df(uint64_t ne, BatchBufs b, co
   GRID_STRIDE(q, ne) {
     const uint32_t i = b.seg_src[q];
     const bool same = Cprev[i] == Cprev[b.seg_dst[q]];
-    if (b.seg_del[q] ? same : !same) {
-      if (atomicExch(&mark[i], stamp) != stamp) list_push(list, count, i);
-    }
+    const bool push = (b.seg_del[q] ? same : !same) && atomicExch(&mark[i], stamp) != stamp;
+    wave_append(push ? 0u : kNone, i, [&](uint32_t, uint32_t*& l, unsigned int*& c) {
+      l = list;
+      c = count;
+    });
   }
 }
 

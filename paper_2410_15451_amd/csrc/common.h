@@ -13,7 +13,6 @@ constexpr int kBlock = 256;     // threads per block of every list kernel
 constexpr int kWave = 64;       // CDNA wavefront
 constexpr int kMaxClasses = 32; // vertex classes / refinement colours
 constexpr int kBins = 6;        // degree bins of the hash kernels
-constexpr uint32_t kBigRow = 4096; // movers with longer rows are marked block-parallel
 
 // Degree bins: lanes per vertex and hash slots per vertex.  A vertex of
 // degree d goes to the first bin with d <= kBinMaxDeg; the last bin keeps its
@@ -59,13 +58,12 @@ struct Ctl {
   unsigned int split_count;          // vertices of split-marked communities
   unsigned int changed;              // unused
   unsigned int split_rest;           // split vertices outside their community's main tree
-  unsigned int hub_items;            // (hub, partition) work items of the current sub-round
-  unsigned int hub_over;             // hubs whose LDS tables overflowed in the current sub-round
+  unsigned int hub_items;            // (hub, chunk) work items of the current sub-round
   unsigned int error;                // batch validation error code
   unsigned int touched;              // rows touched by the batch
   unsigned int init_count;           // vertices marked affected by the batch
   unsigned long long overflow_need;  // entries to relocate into the overflow area
-  unsigned int big_count;            // movers whose rows are marked by the block-parallel kernel
+  unsigned int mark_items;           // neighbour-marking work items of the current sub-round
   unsigned int misc[8];
   unsigned long long kt_units[4];    // work units of the timed kernels (indexed by leiden_kernel)
 };
@@ -206,6 +204,54 @@ __device__ inline void block_best(double& dq, uint32_t& c, double* rdq, uint32_t
 __device__ inline void list_push(uint32_t* list, unsigned int* count, uint32_t v) {
   unsigned int pos = atomicAdd(count, 1u);
   list[pos] = v;
+}
+
+// Wavefront-aggregated append to one of several lists: every active lane
+// calls this together; a lane with key != kNone appends v to list `key`
+// (list_of(key) gives the list base and its counter).  One atomic per
+// distinct key in the wavefront instead of one per lane.
+template <typename ListOf>
+__device__ inline void wave_append(uint32_t key, uint32_t v, ListOf list_of) {
+  const uint32_t lane = threadIdx.x % kWave;
+  unsigned long long pending = __ballot(key != kNone);
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const uint32_t lk = __shfl(key, leader);
+    const unsigned long long mask = __ballot(key == lk) & pending;
+    uint32_t* list;
+    unsigned int* count;
+    list_of(lk, list, count);
+    unsigned int base = 0;
+    if ((int)lane == leader) base = atomicAdd(count, (unsigned int)__popcll(mask));
+    base = __shfl(base, leader);
+    if ((mask >> lane) & 1ull) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = v;
+    pending &= ~mask;
+  }
+}
+
+// Wavefront-aggregated atomic adds keyed by address index: every active lane
+// calls this together; the lanes sharing a key are summed and one of them
+// adds the sums to a[key] and b[key].  Lanes with key == kNone add nothing.
+__device__ inline void wave_add2_by_key(uint32_t key, long long va, long long vb, long long* a, long long* b) {
+  const uint32_t lane = threadIdx.x % kWave;
+  unsigned long long pending = __ballot(key != kNone);
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const uint32_t lk = __shfl(key, leader);
+    const unsigned long long mask = __ballot(key == lk) & pending;
+    const bool mine = (mask >> lane) & 1ull;
+    long long sa = mine ? va : 0, sb = mine ? vb : 0;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+      sa += __shfl_xor(sa, o);
+      sb += __shfl_xor(sb, o);
+    }
+    if ((int)lane == leader) {
+      atomicAdd((unsigned long long*)&a[lk], (unsigned long long)sa);
+      atomicAdd((unsigned long long*)&b[lk], (unsigned long long)sb);
+    }
+    pending &= ~mask;
+  }
 }
 
 // Block-wide append: every thread of the block calls this (block-uniform

@@ -28,16 +28,9 @@ struct DecideParams {
   unsigned long long* hub_kid;  // hub index -> K_{i->d} accumulator (kept zero between uses)
   uint32_t* hub_keys;
   unsigned long long* hub_vals;
-  // LDS-resident hub kernel: work items (hub, key partition), per-hub
-  // partial results and completion counters, overflow list for the tables
-  // above, and the distinct-key estimate of each hub from its last use
-  unsigned long long* hub_items;
-  double* hub_pdq;             // hub index * kHubMaxParts + partition
-  uint32_t* hub_pc;
-  uint32_t* hub_pkeys;         // distinct keys seen by each partition
-  unsigned int* hub_done;      // hub index -> finished partitions (kept zero between uses)
-  uint32_t* hub_over_list;
-  uint32_t* hub_est;           // vertex -> distinct neighbour communities at the last use (0: unknown)
+  uint32_t* hub_occ;           // per hub (same offsets as the table): claimed slots
+  unsigned int* hub_nocc;      // hub index -> claimed slots (kept zero between uses)
+  unsigned long long* hub_items;  // (hub vertex, chunk) work items of the current sub-round
 };
 
 // Hub layout of one level: hubs (degree above the last LDS bin) get table
@@ -71,7 +64,7 @@ struct ApplyParams {
   uint32_t* cls_lists;
   size_t cls_stride;
   uint32_t* next_list;
-  uint32_t* big_list;  // movers with long rows (marked by the block-parallel kernel)
+  unsigned long long* mark_items;  // (mover, chunk) marking work items of the sub-round
 };
 
 // move.hip
@@ -81,12 +74,12 @@ void launch_distribute(hipStream_t s, const uint32_t* in_list, const unsigned in
 void launch_bin(hipStream_t s, const uint32_t* list, const unsigned int* count, uint32_t n_upper, const uint32_t* len,
                 const uint8_t* in_range, uint32_t* bin_lists, size_t stride, Ctl* ctl);
 // maxdeg: largest degree of the level (sizes the hub kernels)
-constexpr uint32_t kHubMaxParts = 16;
 template <typename W, bool REFINE>
 void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, size_t stride, unsigned int* bin_counts,
                        const uint64_t* bin_upper, uint32_t maxdeg);
 // long_rows: the level has rows longer than the wavefront path handles
-void launch_apply_moves(hipStream_t s, const ApplyParams& p, uint32_t n_upper, bool long_rows);
+// items_upper: upper bound of the marking work items (entries / 64 + vertices)
+void launch_apply_moves(hipStream_t s, const ApplyParams& p, uint32_t n_upper, uint64_t items_upper);
 void launch_apply_refine(hipStream_t s, uint32_t* C, int64_t* S, const int64_t* K, uint32_t* size,
                          const Mover* movers, Ctl* ctl, uint32_t n_upper);
 void launch_subround_reset(hipStream_t s, Ctl* ctl);

@@ -225,94 +225,135 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(DecideParams<W> p) {
 }
 
 // ---------------------------------------------------------------------------
-// Hub bin: all blocks share every hub's row.  Each block sums a chunk of
-// 2048 entries by community in LDS and adds each distinct community once to
-// the hub's global table (and K_{i->d} to its accumulator); then one block per
-// hub picks the best community from the table and clears it for the next use.
+// Hub bin (degree above the last LDS bin).  Rows are cut into chunks of
+// kHubChunk entries and every (hub, chunk) pair is a work item of one block.
+// The block sums its chunk by community in an LDS table, adds its K_{i->d}
+// share to the hub's accumulator, and adds each distinct community once to
+// the hub's table in global memory (at least 2 * degree slots, so it never
+// fills), noting newly claimed slots in the hub's occupancy list.  Then one
+// block per hub evaluates only the occupied slots, picks the best community
+// and clears what it used.  Hubs usually see few distinct communities, so
+// the global atomics per chunk are few.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kHubChunk = 2048, kHubSlots = 4096;
 
 template <typename W, bool REFINE>
-__global__ __launch_bounds__(kBlock) void k_hub_insert(DecideParams<W> p) {
-  __shared__ uint32_t lk[kHubSlots];
-  __shared__ unsigned long long lv[kHubSlots];
-  __shared__ unsigned long long red[kBlock / kWave];
-  for (int s = threadIdx.x; s < (int)kHubSlots; s += kBlock) {
-    lk[s] = kNone;
-    lv[s] = 0;
-  }
-  __syncthreads();
+__global__ __launch_bounds__(kBlock) void k_hub_items(DecideParams<W> p) {
   const uint32_t cnt = *p.count;
-  unsigned long long edges = 0;
-  for (uint32_t h = 0; h < cnt; ++h) {
+  for (uint32_t h = blockIdx.x * kBlock + threadIdx.x; h < cnt; h += gridDim.x * kBlock) {
     const uint32_t v = p.list[h];
-    const uint32_t d = p.C[v];
-    if (REFINE && p.size[d] != 1) continue;  // block-uniform
-    const uint32_t hi = p.hub_idx[v];
-    uint32_t* tk = p.hub_keys + p.hub_off[hi];
-    unsigned long long* tv = p.hub_vals + p.hub_off[hi];
-    const uint32_t mask = p.hub_mask[hi];
-    const int64_t s0 = p.g.start[v];
-    const uint32_t L = p.g.len[v];
-    const uint32_t bnd = REFINE ? p.CB[v] : 0;
-    // chunk c of hub h goes to block (c + 97 h) mod grid, spreading the first
-    // chunks of consecutive hubs over different blocks
-    const uint32_t rot = (uint32_t)(((uint64_t)h * 97u) % gridDim.x);
-    const uint32_t first = (blockIdx.x + gridDim.x - rot) % gridDim.x;
-    for (uint32_t cb = first * kHubChunk; cb < L; cb += gridDim.x * kHubChunk) {
-      const uint32_t ce = min(L, cb + kHubChunk);
-      unsigned long long kid = 0;
-      for (uint32_t e = cb + threadIdx.x; e < ce; e += kBlock) {
-        const uint32_t j = p.g.cols[s0 + e];
-        if (j == v) continue;
-        if (REFINE && p.CB[j] != bnd) continue;
-        const uint32_t c = p.C[j];
-        const unsigned long long w = (unsigned long long)p.g.w[s0 + e];
-        if (c == d)
-          kid += w;
-        else
-          table_add(lk, lv, kHubSlots - 1, c, w);
-      }
-      if (!REFINE && threadIdx.x == 0) edges += ce - cb;
-      kid = block_sum(kid, red);
-      if (threadIdx.x == 0 && kid) atomicAdd(&p.hub_kid[hi], kid);
-      for (int s = threadIdx.x; s < (int)kHubSlots; s += kBlock) {
-        const uint32_t k = lk[s];
-        if (k == kNone) continue;
-        table_add(tk, tv, mask, k, lv[s]);
-        lk[s] = kNone;
-        lv[s] = 0;
-      }
-      __syncthreads();
-    }
+    if (REFINE && p.size[p.C[v]] != 1) continue;  // only isolated vertices are refined
+    const uint32_t nch = (p.g.len[v] + kHubChunk - 1) / kHubChunk;
+    const unsigned int base = atomicAdd(&p.ctl->hub_items, nch);
+    for (uint32_t k = 0; k < nch; ++k) p.hub_items[base + k] = ((unsigned long long)v << 32) | k;
   }
-  if (edges) atomicAdd(&p.ctl->edges, edges);
 }
 
 template <typename W, bool REFINE>
-__global__ __launch_bounds__(kBlock) void k_hub_select(DecideParams<W> p) {
+__global__ __launch_bounds__(kBlock) void k_hub_chunk(DecideParams<W> p) {
+  __shared__ uint32_t lk[kHubSlots];
+  __shared__ unsigned long long lv[kHubSlots];
+  __shared__ unsigned long long red[kBlock / kWave];
+  for (uint32_t sl = threadIdx.x; sl < kHubSlots; sl += kBlock) {
+    lk[sl] = kNone;
+    lv[sl] = 0;
+  }
+  __syncthreads();
+  const uint32_t items = p.ctl->hub_items;
+  unsigned long long edges = 0;
+  for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const unsigned long long item = p.hub_items[it];
+    const uint32_t v = (uint32_t)(item >> 32), k = (uint32_t)item;
+    const uint32_t d = p.C[v];
+    const uint32_t hi = p.hub_idx[v];
+    const int64_t s0 = p.g.start[v];
+    const uint32_t L = p.g.len[v];
+    const uint32_t cb = k * kHubChunk, ce = min(L, cb + kHubChunk);
+    const uint32_t bnd = REFINE ? p.CB[v] : 0;
+    unsigned long long kid = 0;
+    for (uint32_t e = cb + threadIdx.x; e < ce; e += kBlock) {
+      const uint32_t j = p.g.cols[s0 + e];
+      if (j == v) continue;
+      if (REFINE && p.CB[j] != bnd) continue;
+      const uint32_t c = p.C[j];
+      const unsigned long long w = (unsigned long long)p.g.w[s0 + e];
+      if (c == d)
+        kid += w;
+      else
+        table_add(lk, lv, kHubSlots - 1, c, w);
+    }
+    kid = block_sum(kid, red);
+    if (threadIdx.x == 0) {
+      if (kid) atomicAdd(&p.hub_kid[hi], kid);
+      if (!REFINE) edges += ce - cb;
+    }
+    const uint64_t off = p.hub_off[hi];
+    uint32_t* tk = p.hub_keys + off;
+    unsigned long long* tv = p.hub_vals + off;
+    uint32_t* occ = p.hub_occ + off;
+    const uint32_t mask = p.hub_mask[hi];
+    for (uint32_t sl = threadIdx.x; sl < kHubSlots; sl += kBlock) {
+      const uint32_t c = lk[sl];
+      if (c == kNone) continue;
+      const unsigned long long w = lv[sl];
+      lk[sl] = kNone;
+      lv[sl] = 0;
+      uint32_t h = slot_hash(c, mask);
+      while (true) {
+        const uint32_t o0 = __atomic_load_n(&tk[h], __ATOMIC_RELAXED);
+        if (o0 == c) {
+          atomicAdd(&tv[h], w);
+          break;
+        }
+        if (o0 == kNone) {
+          const uint32_t o = atomicCAS(&tk[h], kNone, c);
+          if (o == kNone) {
+            atomicAdd(&tv[h], w);
+            occ[atomicAdd(&p.hub_nocc[hi], 1u)] = h;
+            break;
+          }
+          if (o == c) {
+            atomicAdd(&tv[h], w);
+            break;
+          }
+        }
+        h = (h + 1) & mask;
+      }
+    }
+    __syncthreads();
+  }
+  if (edges) {
+    atomicAdd(&p.ctl->edges, edges);
+    if (sizeof(W) == 4 && !REFINE) atomicAdd(&p.ctl->kt_units[LEIDEN_KT_HUB_INSERT], edges);
+  }
+}
+
+template <typename W, bool REFINE>
+__global__ __launch_bounds__(kBlock) void k_hub_pick(DecideParams<W> p) {
   __shared__ double rdq[kBlock / kWave];
   __shared__ uint32_t rc[kBlock / kWave];
   const uint32_t cnt = *p.count;
   for (uint32_t h = blockIdx.x; h < cnt; h += gridDim.x) {
     const uint32_t v = p.list[h];
     const uint32_t d = p.C[v];
-    const bool valid = !(REFINE && p.size[d] != 1);
+    if (REFINE && p.size[d] != 1) continue;  // block-uniform; nothing was summed
     const uint32_t hi = p.hub_idx[v];
-    uint32_t* tk = p.hub_keys + p.hub_off[hi];
-    unsigned long long* tv = p.hub_vals + p.hub_off[hi];
-    const uint32_t mask = p.hub_mask[hi];
+    const uint64_t off = p.hub_off[hi];
+    uint32_t* tk = p.hub_keys + off;
+    unsigned long long* tv = p.hub_vals + off;
+    const uint32_t* occ = p.hub_occ + off;
+    const uint32_t nocc = p.hub_nocc[hi];
     const int64_t kid = (int64_t)p.hub_kid[hi];
     const int64_t ki = p.K[v], sd = p.S[d];
     double bdq = -INFINITY;
     uint32_t bc = kNone;
-    for (uint32_t s = threadIdx.x; s <= mask; s += kBlock) {
-      const uint32_t c = tk[s];
-      if (c == kNone) continue;
-      const int64_t kic = (int64_t)tv[s];
-      tk[s] = kNone;
-      tv[s] = 0;
-      if (!valid || !allowed_target<W, REFINE>(p, c)) continue;
+    for (uint32_t q = threadIdx.x; q < nocc; q += kBlock) {
+      const uint32_t sl = occ[q];
+      const uint32_t c = tk[sl];
+      const int64_t kic = (int64_t)tv[sl];
+      tk[sl] = kNone;
+      tv[sl] = 0;
+      if (!allowed_target<W, REFINE>(p, c)) continue;
       const double dq = delta_q(kic, kid, ki, p.S[c], sd, p.inv_m, p.inv_2m2);
       if (better(dq, c, bdq, bc)) {
         bdq = dq;
@@ -322,214 +363,10 @@ __global__ __launch_bounds__(kBlock) void k_hub_select(DecideParams<W> p) {
     block_best(bdq, bc, rdq, rc);
     if (threadIdx.x == 0) {
       p.hub_kid[hi] = 0;
-      if (valid) emit_decision<W, REFINE>(p, v, d, bdq, bc);
+      p.hub_nocc[hi] = 0;
+      emit_decision<W, REFINE>(p, v, d, bdq, bc);
     }
     __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Hub bin, LDS-resident form.  The neighbour communities of a hub are split
-// into P key partitions (P from the hub's distinct-community count at its
-// last use, else from its degree); one 1024-thread block per (hub, partition)
-// scans the whole row, sums the weights of its partition's communities in a
-// 16384-slot LDS table and picks its best candidate.  The last block of a hub
-// combines the partial results.  A table that reaches its capacity sends the
-// hub to the global-table kernels above instead (no decision is emitted
-// here), so the result never depends on the estimate.
-// ---------------------------------------------------------------------------
-constexpr int kHubThreads = 1024;
-constexpr uint32_t kHubLdsSlots = 16384, kHubLdsCap = 12288;
-
-__device__ inline uint32_t hub_parts(uint32_t est, uint32_t len) {
-  const uint32_t d = est ? est + est / 4 : len;
-  const uint32_t p = (d + kHubLdsCap - 1) / kHubLdsCap;
-  return p < 1 ? 1 : (p > kHubMaxParts ? kHubMaxParts : p);
-}
-
-__device__ inline uint32_t key_part(uint32_t c, uint32_t P) { return P == 1 ? 0 : (fmix32(c) >> 4) % P; }
-
-template <typename W>
-__global__ __launch_bounds__(kBlock) void k_hub_items(DecideParams<W> p) {
-  const uint32_t cnt = *p.count;
-  for (uint32_t h = blockIdx.x * kBlock + threadIdx.x; h < cnt; h += gridDim.x * kBlock) {
-    const uint32_t v = p.list[h];
-    const uint32_t P = hub_parts(p.hub_est[v], p.g.len[v]);
-    const unsigned int base = atomicAdd(&p.ctl->hub_items, P);
-    for (uint32_t q = 0; q < P; ++q)
-      p.hub_items[base + q] = ((unsigned long long)v << 32) | ((unsigned long long)P << 8) | q;
-  }
-}
-
-template <typename T>
-__device__ inline T hub_block_sum(T x, T* red) {
-  x = group_sum<kWave>(x);
-  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = x;
-  __syncthreads();
-  T r = 0;
-#pragma unroll
-  for (int i = 0; i < kHubThreads / kWave; ++i) r += red[i];
-  __syncthreads();
-  return r;
-}
-
-__device__ inline void hub_block_best(double& dq, uint32_t& c, double* rdq, uint32_t* rc) {
-  group_best<kWave>(dq, c);
-  if (threadIdx.x % kWave == 0) {
-    rdq[threadIdx.x / kWave] = dq;
-    rc[threadIdx.x / kWave] = c;
-  }
-  __syncthreads();
-  dq = -INFINITY;
-  c = kNone;
-#pragma unroll
-  for (int i = 0; i < kHubThreads / kWave; ++i)
-    if (better(rdq[i], rc[i], dq, c)) {
-      dq = rdq[i];
-      c = rc[i];
-    }
-  __syncthreads();
-}
-
-template <typename W, bool REFINE>
-__global__ __launch_bounds__(kHubThreads) void k_hub_lds(DecideParams<W> p) {
-  __shared__ uint32_t tk[kHubLdsSlots];
-  __shared__ uint32_t tv[kHubLdsSlots];
-  __shared__ unsigned long long red[kHubThreads / kWave];
-  __shared__ double rdq[kHubThreads / kWave];
-  __shared__ uint32_t rc[kHubThreads / kWave];
-  __shared__ unsigned int used, over, last;
-  constexpr uint32_t mask = kHubLdsSlots - 1;
-  const uint32_t items = p.ctl->hub_items;
-  unsigned long long edges = 0;
-  for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
-    const unsigned long long item = p.hub_items[it];
-    const uint32_t v = (uint32_t)(item >> 32), P = (uint32_t)(item >> 8) & 0xFFu, q = (uint32_t)item & 0xFFu;
-    const uint32_t d = p.C[v];
-    const uint32_t hi = p.hub_idx[v];
-    const bool valid = !(REFINE && p.size[d] != 1);  // block-uniform
-    for (uint32_t sl = threadIdx.x; sl < kHubLdsSlots; sl += kHubThreads) {
-      tk[sl] = kNone;
-      tv[sl] = 0;
-    }
-    if (threadIdx.x == 0) {
-      used = 0;
-      // 32-bit sums need K_i < 2^32; a heavier hub takes the global tables
-      over = p.K[v] >= (int64_t)0xFFFFFFFFll ? 1u : 0u;
-    }
-    __syncthreads();
-    unsigned long long kid = 0;
-    if (valid && !over) {
-      const int64_t s0 = p.g.start[v];
-      const uint32_t L = p.g.len[v];
-      const uint32_t bnd = REFINE ? p.CB[v] : 0;
-      for (uint32_t e = threadIdx.x; e < L; e += kHubThreads) {
-        const uint32_t j = p.g.cols[s0 + e];
-        if (j == v) continue;
-        if (REFINE && p.CB[j] != bnd) continue;
-        const uint32_t c = p.C[j];
-        const uint32_t w = (uint32_t)p.g.w[s0 + e];
-        if (c == d) {
-          kid += w;
-          continue;
-        }
-        if (key_part(c, P) != q || __atomic_load_n(&over, __ATOMIC_RELAXED)) continue;
-        uint32_t h = slot_hash(c, mask);
-        while (true) {
-          const uint32_t k = tk[h];
-          if (k == c) {
-            atomicAdd(&tv[h], w);
-            break;
-          }
-          if (k == kNone) {
-            const uint32_t o = atomicCAS(&tk[h], kNone, c);
-            if (o == kNone) {
-              atomicAdd(&tv[h], w);
-              // at most kHubLdsCap + 2 * kHubThreads slots are ever claimed
-              if (atomicAdd(&used, 1u) + 1 >= kHubLdsCap) atomicExch(&over, 1u);
-              break;
-            }
-            if (o == c) {
-              atomicAdd(&tv[h], w);
-              break;
-            }
-          }
-          h = (h + 1) & mask;
-        }
-      }
-    }
-    kid = hub_block_sum(kid, red);
-    double bdq = -INFINITY;
-    uint32_t bc = kNone;
-    const bool ok = valid && !over;
-    if (ok) {
-      const int64_t ki = p.K[v], sd = p.S[d];
-      for (uint32_t sl = threadIdx.x; sl < kHubLdsSlots; sl += kHubThreads) {
-        const uint32_t c = tk[sl];
-        if (c == kNone || !allowed_target<W, REFINE>(p, c)) continue;
-        const double dq = delta_q((int64_t)tv[sl], (int64_t)kid, ki, p.S[c], sd, p.inv_m, p.inv_2m2);
-        if (better(dq, c, bdq, bc)) {
-          bdq = dq;
-          bc = c;
-        }
-      }
-    }
-    hub_block_best(bdq, bc, rdq, rc);
-    if (threadIdx.x == 0) {
-      if (P == 1) {
-        if (ok) {
-          emit_decision<W, REFINE>(p, v, d, bdq, bc);
-          p.hub_est[v] = used;
-          if (!REFINE) edges += p.g.len[v];
-        } else if (valid) {
-          p.hub_over_list[atomicAdd(&p.ctl->hub_over, 1u)] = v;
-        }
-        last = 0;
-      } else {
-        const size_t slot = (size_t)hi * kHubMaxParts + q;
-        p.hub_pdq[slot] = ok ? bdq : NAN;  // NaN marks an overflowed partition
-        p.hub_pc[slot] = bc;
-        p.hub_pkeys[slot] = used;
-        __threadfence();
-        last = atomicAdd(&p.hub_done[hi], 1u) == P - 1 ? 1u : 0u;
-      }
-    }
-    __syncthreads();
-    if (last && threadIdx.x == 0) {
-      // every partition of this hub has finished: combine in partition order
-      __threadfence();
-      bool all_ok = true;
-      double cdq = -INFINITY;
-      uint32_t cc = kNone, keys = 0;
-      const size_t base = (size_t)hi * kHubMaxParts;
-      for (uint32_t r = 0; r < P; ++r) {
-        const double x = __longlong_as_double((long long)__atomic_load_n(
-            reinterpret_cast<unsigned long long*>(&p.hub_pdq[base + r]), __ATOMIC_RELAXED));
-        const uint32_t xc = __atomic_load_n(&p.hub_pc[base + r], __ATOMIC_RELAXED);
-        keys += __atomic_load_n(&p.hub_pkeys[base + r], __ATOMIC_RELAXED);
-        if (x != x) {
-          all_ok = false;
-          continue;
-        }
-        if (better(x, xc, cdq, cc)) {
-          cdq = x;
-          cc = xc;
-        }
-      }
-      p.hub_done[hi] = 0;
-      if (all_ok) {
-        emit_decision<W, REFINE>(p, v, d, cdq, cc);
-        p.hub_est[v] = keys;
-        if (!REFINE) edges += p.g.len[v];
-      } else if (valid) {
-        p.hub_over_list[atomicAdd(&p.ctl->hub_over, 1u)] = v;
-      }
-    }
-    __syncthreads();
-  }
-  if (edges) {
-    atomicAdd(&p.ctl->edges, edges);
-    if (sizeof(W) == 4 && !REFINE) atomicAdd(&p.ctl->kt_units[LEIDEN_KT_HUB_INSERT], edges);
   }
 }
 
@@ -579,32 +416,56 @@ int hub_layout(hipStream_t s, const uint32_t* len, uint32_t nl, HubLayout& h, Ct
 
 // A neighbour j of a mover in class k: if j's class comes later it joins
 // that class's sub-round of this iteration, otherwise it is queued as
-// unprocessed for the next iteration (each vertex at most once per list).
+// unprocessed for the next iteration (each vertex at most once per list: the
+// stamp is read first and claimed by exchange only when it is not set).
+// Every active lane of the wavefront calls this together; lanes without a
+// neighbour pass kNone.
 __device__ inline void mark_neighbour(const ApplyParams& p, uint32_t j) {
-  const uint32_t kj = vertex_class(j, p.li, p.P);
-  if (kj > p.k) {
-    if (atomicExch(&p.pend_mark[j], p.stamp) != p.stamp)
-      list_push(p.cls_lists + (size_t)kj * p.cls_stride, &p.ctl->cls_count[kj], j);
-  } else {
-    if (atomicExch(&p.unproc_mark[j], p.stamp + 1) != p.stamp + 1) list_push(p.next_list, &p.ctl->next_count, j);
+  uint32_t key = kNone;
+  if (j != kNone) {
+    const uint32_t kj = vertex_class(j, p.li, p.P);
+    if (kj > p.k) {
+      if (__atomic_load_n(&p.pend_mark[j], __ATOMIC_RELAXED) != p.stamp &&
+          atomicExch(&p.pend_mark[j], p.stamp) != p.stamp)
+        key = kj;
+    } else {
+      if (__atomic_load_n(&p.unproc_mark[j], __ATOMIC_RELAXED) != p.stamp + 1 &&
+          atomicExch(&p.unproc_mark[j], p.stamp + 1) != p.stamp + 1)
+        key = p.P;
+    }
   }
+  wave_append(key, j, [&](uint32_t k, uint32_t*& list, unsigned int*& count) {
+    if (k < p.P) {
+      list = p.cls_lists + (size_t)k * p.cls_stride;
+      count = &p.ctl->cls_count[k];
+    } else {
+      list = p.next_list;
+      count = &p.ctl->next_count;
+    }
+  });
 }
 
-// Local-moving moves: one wavefront per mover.  Lane 0 moves the vertex
-// (C, Sigma, member counts, gain sum, split flag of the source community);
-// all lanes mark the neighbours: a neighbour of a later class joins that
-// class's sub-round of this iteration, any other neighbour is queued as
-// unprocessed for the next iteration.
+// Local-moving moves: one thread per mover moves the vertex (C, Sigma, member
+// counts, gain sum, split flag of the source community) and cuts its row into
+// chunks of kMarkChunk entries, queued as marking work items; then one
+// wavefront per item marks the neighbours (a neighbour of a later class joins
+// that class's sub-round of this iteration, any other neighbour is queued as
+// unprocessed for the next iteration).  Long and short rows thus spread evenly
+// over the machine.
+constexpr uint32_t kMarkChunk = kWave;
+
 __global__ __launch_bounds__(kBlock) void k_apply_moves(ApplyParams p) {
-  const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
   const uint32_t lane = threadIdx.x % kWave;
-  const uint32_t nwaves = gridDim.x * (kBlock / kWave);
   const uint32_t cnt = p.ctl->mover_count;
   long long dqsum = 0;
-  for (uint32_t m = wave; m < cnt; m += nwaves) {
-    const Mover mv = p.movers[m];
-    const uint32_t v = mv.v;
-    if (lane == 0) {
+  const uint32_t stride = gridDim.x * kBlock;
+  // every lane runs every iteration (wavefront-uniform loop)
+  for (uint32_t base = blockIdx.x * kBlock + (threadIdx.x - lane); base < cnt; base += stride) {
+    const uint32_t m = base + lane;
+    uint32_t nch = 0, v = 0;
+    if (m < cnt) {
+      const Mover mv = p.movers[m];
+      v = mv.v;
       const uint32_t d = p.C[v];
       const long long k = p.K[v];
       p.C[v] = mv.c;
@@ -614,28 +475,37 @@ __global__ __launch_bounds__(kBlock) void k_apply_moves(ApplyParams p) {
       atomicAdd(&p.size[mv.c], 1u);
       dqsum += gain_fixed(mv.dq);
       if (p.dS) p.dS[d] = 1;
+      nch = (p.len[v] + kMarkChunk - 1) / kMarkChunk;
     }
-    const uint32_t L = p.len[v];
-    if (L > kBigRow) {
-      if (lane == 0) list_push(p.big_list, &p.ctl->big_count, v);
-      continue;
+    // wavefront prefix of the chunk counts, one atomic per wavefront
+    uint32_t incl = nch;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o);
+      if ((int)lane >= o) incl += y;
     }
-    const int64_t s0 = p.start[v];
-    for (uint32_t e = lane; e < L; e += kWave) mark_neighbour(p, p.cols[s0 + e]);
+    const uint32_t total = __shfl(incl, kWave - 1);
+    unsigned int first = 0;
+    if (lane == kWave - 1 && total) first = atomicAdd(&p.ctl->mark_items, total);
+    first = __shfl(first, kWave - 1);
+    for (uint32_t k = 0; k < nch; ++k) p.mark_items[first + incl - nch + k] = ((unsigned long long)v << 32) | k;
   }
+  dqsum = group_sum<kWave>(dqsum);
   if (lane == 0 && dqsum != 0) atomicAdd(&p.ctl->dq_fixed, (unsigned long long)dqsum);
-  if (lane == 0 && wave == 0) atomicAdd(&p.ctl->total_moves, (unsigned long long)cnt);
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&p.ctl->total_moves, (unsigned long long)cnt);
 }
 
-// Neighbour marking of movers with long rows: every block takes a share of
-// each such row.
-__global__ __launch_bounds__(kBlock) void k_mark_big(ApplyParams p) {
-  const uint32_t nbig = p.ctl->big_count;
-  for (uint32_t m = 0; m < nbig; ++m) {
-    const uint32_t v = p.big_list[m];
-    const int64_t s0 = p.start[v];
+__global__ __launch_bounds__(kBlock) void k_mark_items(ApplyParams p) {
+  const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const uint32_t lane = threadIdx.x % kWave;
+  const uint32_t nwaves = gridDim.x * (kBlock / kWave);
+  const uint32_t items = p.ctl->mark_items;
+  for (uint32_t it = wave; it < items; it += nwaves) {
+    const unsigned long long item = p.mark_items[it];
+    const uint32_t v = (uint32_t)(item >> 32), k = (uint32_t)item;
     const uint32_t L = p.len[v];
-    for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < L; e += gridDim.x * kBlock) mark_neighbour(p, p.cols[s0 + e]);
+    const uint32_t e = k * kMarkChunk + lane;
+    mark_neighbour(p, e < L ? p.cols[p.start[v] + e] : kNone);
   }
 }
 
@@ -660,9 +530,8 @@ __global__ void k_subround_reset(Ctl* ctl) {
   if (threadIdx.x < kBins) ctl->bin_count[threadIdx.x] = 0;
   if (threadIdx.x == 0) {
     ctl->mover_count = 0;
-    ctl->big_count = 0;
+    ctl->mark_items = 0;
     ctl->hub_items = 0;
-    ctl->hub_over = 0;
   }
 }
 
@@ -732,18 +601,12 @@ void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, si
                            s, q);
         break;
       default: {
-        hipLaunchKernelGGL((k_hub_items<W>), dim3(grid_for(bin_upper[b], kBlock, 64)), dim3(kBlock), 0, s, q);
+        hipLaunchKernelGGL((k_hub_items<W, REFINE>), dim3(grid_for(bin_upper[b], kBlock, 64)), dim3(kBlock), 0, s, q);
         if (sizeof(W) == 4 && !REFINE) kt_mark(LEIDEN_KT_HUB_INSERT, s);
-        hipLaunchKernelGGL((k_hub_lds<W, REFINE>), dim3(grid_for(bin_upper[b] * kHubMaxParts, 1, 4096)),
-                           dim3(kHubThreads), 0, s, q);
+        hipLaunchKernelGGL((k_hub_chunk<W, REFINE>), dim3(grid_for(bin_upper[b] * (maxdeg / kHubChunk + 1), 1, 1536)),
+                           dim3(kBlock), 0, s, q);
         if (sizeof(W) == 4 && !REFINE) kt_mark(LEIDEN_KT_HUB_INSERT, s);
-        // hubs whose LDS tables overflowed (usually none)
-        DecideParams<W> o = q;
-        o.list = p.hub_over_list;
-        o.count = &p.ctl->hub_over;
-        hipLaunchKernelGGL((k_hub_insert<W, REFINE>), dim3(grid_for(bin_upper[b] * (maxdeg / kHubChunk + 1), 1, 1024)),
-                           dim3(kBlock), 0, s, o);
-        hipLaunchKernelGGL((k_hub_select<W, REFINE>), dim3(grid_for(bin_upper[b], 1, 1024)), dim3(kBlock), 0, s, o);
+        hipLaunchKernelGGL((k_hub_pick<W, REFINE>), dim3(grid_for(bin_upper[b], 1, 1024)), dim3(kBlock), 0, s, q);
         break;
       }
     }
@@ -759,9 +622,9 @@ template void launch_decide_all<int64_t, false>(hipStream_t, DecideParams<int64_
 template void launch_decide_all<int64_t, true>(hipStream_t, DecideParams<int64_t>, uint32_t*, size_t, unsigned int*,
                                                const uint64_t*, uint32_t);
 
-void launch_apply_moves(hipStream_t s, const ApplyParams& p, uint32_t n_upper, bool long_rows) {
-  hipLaunchKernelGGL(k_apply_moves, dim3(grid_for(n_upper, kBlock / kWave, 2048)), dim3(kBlock), 0, s, p);
-  if (long_rows) hipLaunchKernelGGL(k_mark_big, dim3(512), dim3(kBlock), 0, s, p);
+void launch_apply_moves(hipStream_t s, const ApplyParams& p, uint32_t n_upper, uint64_t items_upper) {
+  hipLaunchKernelGGL(k_apply_moves, dim3(grid_for(n_upper, kBlock, 1024)), dim3(kBlock), 0, s, p);
+  hipLaunchKernelGGL(k_mark_items, dim3(grid_for(items_upper, kBlock / kWave, 2048)), dim3(kBlock), 0, s, p);
 }
 
 void launch_apply_refine(hipStream_t s, uint32_t* C, int64_t* S, const int64_t* K, uint32_t* size,

@@ -134,9 +134,10 @@ void subset_renumber(hipStream_t s, uint32_t n, uint32_t* C, int64_t*& S, uint32
 // Connectivity Computation via Subgraph Sampling" (IPDPS 2018):
 //   1. union each split vertex with the same-community neighbours among the
 //      first kSplitSample entries of its row, then compress;
-//   2. per community, take the tree of its highest-degree member as the main
-//      tree; a vertex already in it skips its row (each of its edges is either
-//      inside the main tree or seen from the other endpoint);
+//   2. per community one main tree (that of its highest-degree member, or of
+//      its label vertex, the minimum member after subset renumbering); a
+//      vertex already in it skips its row (each of its edges is either inside
+//      the main tree or seen from the other endpoint);
 //   3. every other split vertex unions all its same-community neighbours;
 //   4. compress: the root of each vertex is its component's minimum vertex.
 // ---------------------------------------------------------------------------
@@ -153,7 +154,8 @@ __global__ __launch_bounds__(kBlock) void k_split_init(uint32_t n, const uint32_
       const uint32_t c = C[i];
       lab[i] = (uint32_t)i;
       in = dS[c] && !dR[c];
-      if (in) main_key[c] = 0;
+      // the label of a community is its minimum member: one writer per community
+      if (in && c == (uint32_t)i) main_key[c] = 0;
     }
     block_append(list, &ctl->split_count, in, (uint32_t)i, s2);
   }
@@ -210,18 +212,26 @@ __global__ __launch_bounds__(kBlock) void k_split_compress(uint32_t* lab, const 
   }
 }
 
-// main tree of each community: its member of highest degree (lowest ID on ties)
+// main tree of a community: that of its highest-degree member among those
+// with more than kSplitMainDeg entries (lowest ID on ties), else that of its
+// label vertex
+constexpr uint32_t kSplitMainDeg = 128;
 __global__ __launch_bounds__(kBlock) void k_split_main(const uint32_t* len, const uint32_t* C, const uint32_t* list,
                                                        unsigned long long* main_key, const Ctl* ctl) {
   const uint32_t cnt = ctl->split_count;
   GRID_STRIDE(it, cnt) {
     const uint32_t u = list[it];
-    atomicMax(&main_key[C[u]], ((unsigned long long)len[u] << 32) | (unsigned long long)(0xFFFFFFFFu - u));
+    const uint32_t L = len[u];
+    if (L <= kSplitMainDeg) continue;
+    const unsigned long long key = ((unsigned long long)L << 32) | (unsigned long long)(0xFFFFFFFFu - u);
+    unsigned long long* slot = &main_key[C[u]];
+    if (__atomic_load_n(slot, __ATOMIC_RELAXED) < key) atomicMax(slot, key);
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_split_rest(const uint32_t* C, const uint32_t* lab, const uint32_t* list,
-                                                       const unsigned long long* main_key, uint32_t* rest, Ctl* ctl) {
+__global__ __launch_bounds__(kBlock) void k_split_rest(uint32_t n, const uint32_t* C, const uint32_t* lab,
+                                                       const uint32_t* list, const unsigned long long* main_key,
+                                                       uint32_t* rest, Ctl* ctl) {
   __shared__ unsigned int s2[2];
   const uint32_t cnt = ctl->split_count;
   for (uint32_t base = blockIdx.x * kBlock; base < cnt; base += gridDim.x * kBlock) {
@@ -230,7 +240,10 @@ __global__ __launch_bounds__(kBlock) void k_split_rest(const uint32_t* C, const 
     uint32_t u = 0;
     if (it < cnt) {
       u = list[it];
-      const uint32_t m = 0xFFFFFFFFu - (uint32_t)(main_key[C[u]] & 0xFFFFFFFFull);
+      const uint32_t c = C[u];
+      const unsigned long long key = main_key[c];
+      uint32_t m = key ? 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull) : c;
+      if (m >= n || C[m] != c) m = c;  // any choice is correct; this one is always in range
       out = lab[u] != lab[m];  // both are roots after compression
     }
     block_append(rest, &ctl->split_rest, out, u, s2);
@@ -287,7 +300,8 @@ void launch_split_sample(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* 
   hipLaunchKernelGGL((k_split_sample<W>), dim3(grid_n(n_upper)), dim3(kBlock), 0, s, g, C, lab, list, ctl);
   hipLaunchKernelGGL(k_split_compress, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, lab, list, ctl);
   hipLaunchKernelGGL(k_split_main, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, g.len, C, list, main_key, ctl);
-  hipLaunchKernelGGL(k_split_rest, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, C, lab, list, main_key, rest, ctl);
+  hipLaunchKernelGGL(k_split_rest, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, n_upper, C, lab, list, main_key, rest,
+                     ctl);
 }
 
 // Full rows of the vertices outside their community's main tree, by degree

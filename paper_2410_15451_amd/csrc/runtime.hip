@@ -112,9 +112,9 @@ struct leiden_graph {
   Buf flag, newid, scan_tmp, ctl, small;
   Buf lvA_start, lvA_len, lvA_cols, lvA_w, lvB_start, lvB_len, lvB_cols, lvB_w;
   Buf agg_count, agg_off, agg_fill, agg_members, agg_deg, agg_cap, agg_lists, agg_bigcap, agg_tbl, agg_keys, agg_vals,
-      agg_items, big_list;
+      agg_items, mark_items;
   Buf hub_keys, hub_vals, hub_list, hub_idx, hub_off, hub_mask, hub_size, hub_kid;
-  Buf hub_items, hub_pdq, hub_pc, hub_pkeys, hub_done, hub_over_list, hub_est0, hub_estL;
+  Buf hub_items, hub_occ, hub_nocc;
   Buf tr_minv, tr_hk, tr_hv, tr_bw, tr_bv, tr_cw, tr_cb, tr_old, tr_flag, tr_rank, tr_frank, tr_fid, tr_label,
       tr_matched;
   Buf dV, dE, dC, sig, partials, modparts;
@@ -189,8 +189,9 @@ Rows<uint32_t> rows0(leiden_graph* G) { return Rows<uint32_t>{G->g.start, G->g.l
 // Allocate every n- and nnz-sized array a run needs.
 leiden_status ensure_workspace(leiden_graph* G, uint32_t classes) {
   const size_t n = std::max<size_t>(G->n, 1);
-  const uint64_t nnz = std::max<uint64_t>(G->nnz, 1);
+  uint64_t nnz = std::max<uint64_t>(G->nnz, 1);
   if (G->ws_n >= n && G->ws_nnz >= nnz && G->ws_classes >= classes) return LEIDEN_OK;
+  if (G->ws_nnz) nnz += nnz / 4;  // the graph grew: leave room for further growth
   const size_t u32 = 4, u64 = 8;
   CHK(G->C.reserve(n * u32));
   CHK(G->K.reserve(n * u64));
@@ -241,7 +242,7 @@ leiden_status ensure_workspace(leiden_graph* G, uint32_t classes) {
   CHK(G->agg_bigcap.reserve(3 * n * u64));
   CHK(G->agg_tbl.reserve(n * 16));
   CHK(G->agg_items.reserve(kAggItems * 24));
-  CHK(G->big_list.reserve(n * u32));
+  CHK(G->mark_items.reserve((nnz / 64 + n + 1) * 8));
   const uint64_t gcap = std::max<uint64_t>(2 * next_pow2(2 * n), 1 << 16);
   CHK(G->agg_keys.reserve(gcap * u32));
   CHK(G->agg_vals.reserve(gcap * u64));
@@ -295,22 +296,14 @@ leiden_status setup_hubs(leiden_graph* G, hipStream_t s, const uint32_t* len, ui
   uint64_t slots = 0;
   if (hub_layout(s, len, nl, h, dctl(G), G->scan_tmp.p, G->small.as<uint64_t>() + 64, &cnt, &slots) != 0)
     return fail(LEIDEN_EDEVICE, "hub layout failed");
-  // LDS-resident hub kernel: items, partial results, counters, estimates
+  // work items (at most one per 2048 entries plus one per hub), claim counters
   const size_t hc = std::max<uint32_t>(cnt, 1);
-  CHK(G->hub_items.reserve(hc * kHubMaxParts * 8));
-  CHK(G->hub_pdq.reserve(hc * kHubMaxParts * 8));
-  CHK(G->hub_pc.reserve(hc * kHubMaxParts * 4));
-  CHK(G->hub_pkeys.reserve(hc * kHubMaxParts * 4));
-  CHK(G->hub_over_list.reserve(hc * 4));
-  if (G->hub_done.bytes < hc * 4) {
-    CHK(G->hub_done.reserve(hc * 4));
-    fill_u32(s, G->hub_done.as<uint32_t>(), 0, G->hub_done.bytes / 4);
+  CHK(G->hub_items.reserve((slots / 4096 + hc + 1) * 8));
+  if (G->hub_nocc.bytes < hc * 4) {
+    CHK(G->hub_nocc.reserve(hc * 4));
+    fill_u32(s, G->hub_nocc.as<uint32_t>(), 0, G->hub_nocc.bytes / 4);
   }
-  for (Buf* b : {&G->hub_est0, &G->hub_estL})
-    if (b->bytes < n * 4) {
-      CHK(b->reserve(n * 4));
-      fill_u32(s, b->as<uint32_t>(), 0, b->bytes / 4);
-    }
+  CHK(G->hub_occ.reserve(std::max<uint64_t>(slots, 1) * 4));
   if (slots * 4 > G->hub_keys.bytes || slots * 8 > G->hub_vals.bytes) {
     const uint64_t want = slots + slots / 4 + 4096;
     CHK(G->hub_keys.reserve(want * 4));
@@ -330,12 +323,8 @@ void bind_hubs(leiden_graph* G, DecideParams<W>& dp) {
   dp.hub_keys = G->hub_keys.as<uint32_t>();
   dp.hub_vals = G->hub_vals.as<unsigned long long>();
   dp.hub_items = G->hub_items.as<unsigned long long>();
-  dp.hub_pdq = G->hub_pdq.as<double>();
-  dp.hub_pc = G->hub_pc.as<uint32_t>();
-  dp.hub_pkeys = G->hub_pkeys.as<uint32_t>();
-  dp.hub_done = G->hub_done.as<unsigned int>();
-  dp.hub_over_list = G->hub_over_list.as<uint32_t>();
-  dp.hub_est = sizeof(W) == 4 ? G->hub_est0.as<uint32_t>() : G->hub_estL.as<uint32_t>();
+  dp.hub_occ = G->hub_occ.as<uint32_t>();
+  dp.hub_nocc = G->hub_nocc.as<unsigned int>();
 }
 
 leiden_status read_ctl(leiden_graph* G, hipStream_t s) {
@@ -443,8 +432,8 @@ leiden_status local_move(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
       ap.cls_lists = G->cls_lists.as<uint32_t>();
       ap.cls_stride = nl;
       ap.next_list = next_list;
-      ap.big_list = G->big_list.as<uint32_t>();
-      launch_apply_moves(s, ap, nl, maxdeg > kBigRow);
+      ap.mark_items = G->mark_items.as<unsigned long long>();
+      launch_apply_moves(s, ap, nl, G->mark_items.bytes / 8);
     }
     CHK(read_ctl(G, s));
     out.iters = li + 1;
@@ -745,7 +734,7 @@ const char* leiden_kernel_name(int32_t kernel) {
     case LEIDEN_KT_NONE:
       return "";
     case LEIDEN_KT_HUB_INSERT:
-      return "lm::k_hub_lds<unsigned int, false>";
+      return "lm::k_hub_chunk<unsigned int, false>";
     default:
       return nullptr;
   }
@@ -1058,6 +1047,7 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   // level-0 degree bins after the batch
   CHK(level_bins(G, s, G->g.len, n, G->bins0, &G->maxdeg0));
   G->nnz = G->nnz - 2 * n_del + 2 * n_ins;
+  CHK(ensure_workspace(G, std::max(o.move_classes, o.refine_rounds)));  // nnz-sized scratch
   HIPCHK(hipEventRecord(e1, s));
   // auxiliary state: restart or continue
   LevelState L = level_state(G);
