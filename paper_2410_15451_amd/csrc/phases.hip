@@ -659,11 +659,15 @@ __global__ __launch_bounds__(kBlock) void k_agg_big_insert(Rows<W> g, const uint
     lv[s] = 0;
   }
   __syncthreads();
+  __shared__ unsigned long long red[kBlock / kWave];
   for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const AggItem x = items[it];
     const BigComm b = bc[x.big];
     uint32_t* tk = gkeys + b.toff;
     unsigned long long* tv = gvals + b.toff;
+    // most entries of a large community stay inside it: that key is summed in
+    // registers instead of one LDS slot shared by every lane
+    unsigned long long self = 0;
     for (uint64_t mb = x.a; mb < x.b; mb += kBlock) {
       const uint64_t mi = mb + threadIdx.x;
       uint32_t L = 0;
@@ -674,10 +678,20 @@ __global__ __launch_bounds__(kBlock) void k_agg_big_insert(Rows<W> g, const uint
         st = g.start[v];
       }
       sstart[threadIdx.x] = st;
-      spre[threadIdx.x] = L;
+      // inclusive block scan of the row lengths (wavefront scans, then wavefront totals)
+      uint32_t inc = L;
+      const uint32_t lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o);
+        if ((int)lane >= o) inc += y;
+      }
+      if (lane == kWave - 1) spre[wv] = inc;
       __syncthreads();
-      if (threadIdx.x == 0)
-        for (int q = 1; q < kBlock; ++q) spre[q] += spre[q - 1];
+      uint32_t add = 0;
+      for (uint32_t q = 0; q < wv; ++q) add += spre[q];
+      __syncthreads();
+      spre[threadIdx.x] = inc + add;
       __syncthreads();
       const uint32_t total = spre[kBlock - 1];
       for (uint32_t xb = 0; xb < total; xb += kStage) {
@@ -693,7 +707,12 @@ __global__ __launch_bounds__(kBlock) void k_agg_big_insert(Rows<W> g, const uint
           }
           const uint32_t before = lo > 0 ? spre[lo - 1] : 0;
           const int64_t e = sstart[lo] + (xx - before);
-          table_add(lk, lv, kSlots - 1, C[g.cols[e]], (unsigned long long)g.w[e]);
+          const uint32_t c = C[g.cols[e]];
+          const unsigned long long w = (unsigned long long)g.w[e];
+          if (c == b.c)
+            self += w;
+          else
+            table_add(lk, lv, kSlots - 1, c, w);
         }
         __syncthreads();
         for (int s = threadIdx.x; s < (int)kSlots; s += kBlock) {
@@ -706,6 +725,8 @@ __global__ __launch_bounds__(kBlock) void k_agg_big_insert(Rows<W> g, const uint
         __syncthreads();
       }
     }
+    self = block_sum(self, red);
+    if (threadIdx.x == 0 && self) table_add(tk, tv, b.mask, b.c, self);
   }
 }
 

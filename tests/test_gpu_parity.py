@@ -214,3 +214,65 @@ def test_device_pointers(lm, orc):
     gt, dw = orc.apply_batch(g, dels, ins)
     C1, _, q1, _ = orc.update(gt, dw, ins, orc.initial_state(g, C), "df")
     assert np.array_equal(out.cpu().numpy().view(np.uint32), C1)
+
+
+# ---------------------------------------------------------------------------
+# Larger sizes.  R-MAT 2^18: static plus a stream of DF updates of 1e-5, 1e-4
+# and 1e-3 |E|, every result against the oracle.  R-MAT 2^22 in the benchmark's
+# configuration (device-resident batches): the oracle's results are stored in
+# tests/golden/rmat22_df.json by tests/golden/make_rmat22_golden.py; the
+# updated graph and the auxiliary state are checked entry by entry.
+# ---------------------------------------------------------------------------
+def test_update_rmat18_batch_sizes(lm, orc):
+    g = inputs.rmat(18, seed=inputs.BASE_SEED + 2)
+    sizes = [inputs.batch_size_for(g.nnz, f) for f in (1e-5, 1e-4, 1e-3)]
+    _run_updates(lm, orc, g, _stream(g, sizes, seed=41), "df")
+
+
+def _digest(C):
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(C, dtype="<u4").tobytes()).hexdigest()
+
+
+def test_rmat22_benchmark_configuration(lm, orc):
+    import json
+    import os
+
+    import torch
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rmat22_df.json")
+    with open(path) as f:
+        gold = json.load(f)
+    g = inputs.rmat(22, seed=inputs.BASE_SEED + 2)
+    assert (g.n, g.nnz) == (gold["n"], gold["nnz"])
+    G = _graph(lm, g)
+    dev = torch.device("cuda:0")
+    out = torch.zeros(g.n, dtype=torch.int32, device=dev)
+    r0 = G.static(out=out)
+    C0 = out.cpu().numpy().view(np.uint32)
+    assert _digest(C0) == gold["static"]["membership_sha256"]
+    assert r0.q == gold["static"]["q"]
+    assert r0.stats["passes"] == gold["static"]["passes"] and r0.stats["iters"] == gold["static"]["iters"]
+    nb = inputs.batch_size_for(g.nnz, 1e-3)
+    assert nb == gold["batch_undirected_updates"]
+    (dels, ins), _ = inputs.random_batch_stream(g.n, g.undirected_keys(), nb, 2, seed=inputs.BASE_SEED + 2 + 1000)
+    d_dev = torch.from_numpy(dels.view(np.int32)).to(dev)
+    i_dev = torch.from_numpy(ins.view(np.int32)).to(dev)
+    r1 = G.update(d_dev, i_dev, mode="df", out=out)
+    C1 = out.cpu().numpy().view(np.uint32)
+    assert _digest(C1) == gold["df"]["membership_sha256"]
+    assert r1.q == gold["df"]["q"]
+    assert r1.stats["passes"] == gold["df"]["passes"] and r1.stats["iters"] == gold["df"]["iters"]
+    assert r1.stats["affected"] == gold["df"]["affected"]
+    # the updated graph, entry by entry
+    gt, _ = orc.apply_batch(g, dels, ins)
+    offs, cols, w = G.export()
+    assert gt.nnz == gold["df"]["nnz"]
+    assert np.array_equal(offs, gt.offs) and np.array_equal(cols, gt.cols) and np.array_equal(w, gt.w)
+    # auxiliary state by its definition: K = row sums, Sigma = sums of K per community
+    Cs, Ks, Ss, _ = G.state()
+    assert np.array_equal(Cs, C1)
+    cs = np.concatenate([[0], np.cumsum(gt.w, dtype=np.int64)])
+    K = cs[gt.offs[1:]] - cs[gt.offs[:-1]]
+    assert np.array_equal(Ks, K)
+    S = np.bincount(C1, weights=K.astype(np.float64), minlength=g.n).astype(np.int64)  # exact below 2^53
+    assert np.array_equal(Ss, S)
