@@ -97,7 +97,7 @@ def kernel_source_digest():
     reading is only reported while it still describes the same code."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("common.h", "kernels.h", "move.hip"):
+    for f in ("common.h", "kernels.h", "move.hip", "phases.hip"):
         with open(os.path.join(ROOT, "paper_2410_15451_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -131,7 +131,7 @@ def main():
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-scale", type=int, default=20)
     ap.add_argument("--cpu-reps", type=int, default=24)
-    ap.add_argument("--timed-kernel", default="hub_insert", help="kernel timed with HIP events for the roofline")
+    ap.add_argument("--timed-kernel", default="agg_big", help="kernel timed with HIP events for the roofline")
     ap.add_argument("--marker", type=int, default=0,
                     help="launch a spin kernel right before and after the timed steps (profile windowing)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,

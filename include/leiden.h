@@ -56,7 +56,11 @@ typedef enum {
   /* Local moving (Alg. 6) of the hub-degree bin on the input graph: one unit
    * per scanned row entry, 12 bytes (neighbour ID, edge weight and the
    * neighbour's community, 4 bytes each). */
-  LEIDEN_KT_HUB_INSERT = 1
+  LEIDEN_KT_HUB_INSERT = 1,
+  /* Aggregation (Alg. 9) of the large communities of the input graph: one
+   * unit per member row entry read, 12 bytes (neighbour ID, edge weight and
+   * the neighbour's community). */
+  LEIDEN_KT_AGG_BIG = 2
 } leiden_kernel;
 /* (LEIDEN_KT_HUB_INSERT is the kernel that sums chunks of hub rows by
  * community in LDS and merges them into per-hub tables.) */
@@ -105,6 +109,32 @@ typedef struct {
 } leiden_stats;
 
 typedef struct leiden_graph leiden_graph;
+
+/* Degree-bin thresholds of a handle.  Local moving and refinement decide a
+ * vertex of degree d in the first bin b with d <= bin_max_degree[b] (bins:
+ * 8 lanes and 16 table slots per vertex, 32 / 64, 64 / 256, a block with 1024
+ * slots, a block with 4096 slots); longer rows are hubs, split into chunks.
+ * The thresholds must increase and stay within 15, 63, 255, 1023 and 4095 (a
+ * bin's table must hold every distinct community of its rows).  They decide
+ * only which kernel evaluates a vertex, never the result (memberships are
+ * identical for every valid setting).  Defaults 8, 32, 128,
+ * 512, 2048. */
+typedef struct {
+  uint32_t bin_max_degree[5];
+  uint32_t pad_;
+  double probe_ms; /* time of the autotuning probe with these thresholds (0 if never tuned) */
+} leiden_tuning;
+
+leiden_status leiden_get_tuning(leiden_graph* g, leiden_tuning* out);
+/* LEIDEN_EINVAL if the thresholds are not increasing or exceed the limits. */
+leiden_status leiden_set_tuning(leiden_graph* g, const leiden_tuning* t);
+/* Choose the thresholds for this graph by measurement: coordinate descent
+ * over each threshold at 1/2, 3/4, 3/2 and 2 times its value, timing one
+ * decide-only local-moving iteration over every vertex from singleton
+ * communities (on opts->stream); keeps the fastest setting in the handle and
+ * returns it in *out (may be NULL).  The handle's graph and state are
+ * unchanged. */
+leiden_status leiden_autotune(leiden_graph* g, const leiden_opts* opts, leiden_tuning* out);
 
 /* Symbol of a leiden_kernel as profilers list it (NULL for an unknown value). */
 const char* leiden_kernel_name(int32_t kernel);
@@ -172,6 +202,75 @@ leiden_status leiden_state_import(leiden_graph* g, const uint32_t* C, const int6
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* leiden_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Batched form: many independent graphs at once.  `streams` worker threads,
+ * each with its own HIP stream, take the handles in order and run the
+ * single-graph call on them, so each result equals the one the graph gets
+ * alone.  items == NULL: leiden_static on every handle; otherwise
+ * leiden_update with items[i] (host batch arrays as for leiden_update, same
+ * mode and opts for all).  memberships_out[i]: host uint32[n_i] (entries may
+ * be NULL); q_out (may be NULL): double[count]; status_out (may be NULL):
+ * per-graph status.  Returns the first failure's status, else LEIDEN_OK.
+ * opts->stream is ignored.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  const uint32_t* del; /* uint32[n_del][2] */
+  uint64_t n_del;
+  const uint32_t* ins; /* uint32[n_ins][3] */
+  uint64_t n_ins;
+} leiden_batch_item;
+
+leiden_status leiden_batch_run(leiden_graph* const* graphs, uint32_t count, const leiden_batch_item* items,
+                               leiden_mode mode, const leiden_opts* opts, uint32_t streams,
+                               uint32_t* const* memberships_out, double* q_out, leiden_status* status_out);
+
+/* ---------------------------------------------------------------------------
+ * Serving form: device-resident tenant graphs receiving streams of update
+ * batches.  A server owns `workers` threads with one HIP stream each.
+ * Requests wait in arrival order and start as soon as a worker is free,
+ * except that one graph never runs two requests at once (per-graph order is
+ * kept).  Each request is a DF / DS / ND update (leiden_update) whose result
+ * equals the one its graph gets alone.
+ * ------------------------------------------------------------------------- */
+typedef struct leiden_server leiden_server;
+
+typedef struct {
+  uint64_t completed, failed, waiting;
+  uint32_t graphs, pad_;
+  uint64_t hbm_reserved;      /* admitted graphs' estimated device bytes */
+  double latency_p50_ms;      /* completion minus arrival */
+  double latency_p99_ms;
+  double service_p50_ms;      /* completion minus start */
+  double service_p99_ms;
+  double updated_edges_per_s; /* undirected updates of completed requests over first arrival to last completion */
+} leiden_server_stats;
+
+/* workers: 1..64.  hbm_budget_bytes bounds the admitted graphs' estimated
+ * device footprint. */
+leiden_status leiden_server_create(int device, uint64_t hbm_budget_bytes, uint32_t workers, leiden_server** out);
+/* Waits for running requests, then frees every graph and the server. */
+void leiden_server_destroy(leiden_server* s);
+/* Admit a graph (arguments as leiden_graph_create) and run leiden_static on
+ * it (opts may be NULL).  LEIDEN_ENOMEM when its estimated footprint does not
+ * fit in what is left of the budget; *graph_id receives its ID. */
+leiden_status leiden_server_add_graph(leiden_server* s, uint32_t n, uint64_t nnz, const int64_t* offsets,
+                                      const uint32_t* cols, const uint32_t* w, int on_device, double slack,
+                                      const leiden_opts* opts, uint32_t* graph_id);
+/* Free a graph with no waiting requests (LEIDEN_ESTATE otherwise) and return
+ * its share of the budget. */
+leiden_status leiden_server_remove_graph(leiden_server* s, uint32_t graph_id);
+/* Queue an update of graph_id (host batch arrays, copied before returning).
+ * *ticket identifies the request. */
+leiden_status leiden_server_submit(leiden_server* s, uint32_t graph_id, const uint32_t* del, uint64_t n_del,
+                                   const uint32_t* ins, uint64_t n_ins, leiden_mode mode, const leiden_opts* opts,
+                                   uint64_t* ticket);
+/* Block until the request is done; returns its status and fills the outputs
+ * (membership_out: host uint32[n] of its graph; any output may be NULL).
+ * Each ticket can be waited for once. */
+leiden_status leiden_server_wait(leiden_server* s, uint64_t ticket, uint32_t* membership_out, double* q_out,
+                                 leiden_stats* stats_out, double* latency_ms, double* service_ms);
+leiden_status leiden_server_get_stats(leiden_server* s, leiden_server_stats* out);
 
 #ifdef __cplusplus
 }

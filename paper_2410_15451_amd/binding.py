@@ -21,19 +21,20 @@ MODES = {"nd": 0, "ds": 1, "df": 2}
 # Every symbol include/leiden.h declares.
 EXPORTS = ("leiden_default_opts", "leiden_graph_create", "leiden_graph_destroy", "leiden_graph_nnz", "leiden_static",
            "leiden_update", "leiden_modularity", "leiden_graph_export", "leiden_state_export",
-           "leiden_state_import", "leiden_last_error", "leiden_kernel_name")
+           "leiden_state_import", "leiden_last_error", "leiden_kernel_name", "leiden_get_tuning",
+           "leiden_set_tuning", "leiden_autotune", "leiden_batch_run", "leiden_server_create",
+           "leiden_server_destroy", "leiden_server_add_graph", "leiden_server_remove_graph", "leiden_server_submit",
+           "leiden_server_wait", "leiden_server_get_stats")
 
 
 # leiden_kernel values (timed kernels)
-KERNELS = {"none": 0, "hub_insert": 1}
+KERNELS = {"none": 0, "hub_insert": 1, "agg_big": 2}
 
 
 def kernel_name(kernel):
     """Symbol of a timed kernel as profilers list it."""
     k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
-    f = lib().leiden_kernel_name
-    f.restype = ctypes.c_char_p
-    r = f(ctypes.c_int32(k))
+    r = lib().leiden_kernel_name(k)
     if r is None:
         raise ValueError("unknown kernel %r" % (kernel,))
     return r.decode()
@@ -66,6 +67,29 @@ class LeidenStats(ctypes.Structure):
                 "ms_batch": self.ms_batch, "ms_modularity": self.ms_modularity, "nnz": self.nnz,
                 "kt_launches": self.kt_launches, "kt_ms": self.kt_ms, "kt_units": self.kt_units,
                 "kt_bytes": self.kt_bytes}
+
+
+class LeidenTuning(ctypes.Structure):
+    _fields_ = [("bin_max_degree", ctypes.c_uint32 * 5), ("pad_", ctypes.c_uint32), ("probe_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"bin_max_degree": list(self.bin_max_degree), "probe_ms": self.probe_ms}
+
+
+class LeidenBatchItem(ctypes.Structure):
+    _fields_ = [("dels", ctypes.c_void_p), ("n_del", ctypes.c_uint64), ("ins", ctypes.c_void_p),
+                ("n_ins", ctypes.c_uint64)]
+
+
+class LeidenServerStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64), ("waiting", ctypes.c_uint64),
+                ("graphs", ctypes.c_uint32), ("pad_", ctypes.c_uint32), ("hbm_reserved", ctypes.c_uint64),
+                ("latency_p50_ms", ctypes.c_double), ("latency_p99_ms", ctypes.c_double),
+                ("service_p50_ms", ctypes.c_double), ("service_p99_ms", ctypes.c_double),
+                ("updated_edges_per_s", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
 
 
 class LeidenError(RuntimeError):
@@ -114,6 +138,21 @@ def lib():
         L.leiden_state_import.restype = i32
         L.leiden_last_error.argtypes = []
         L.leiden_last_error.restype = ctypes.c_char_p
+        L.leiden_kernel_name.argtypes = [i32]
+        L.leiden_kernel_name.restype = ctypes.c_char_p
+        for name, args in (("leiden_get_tuning", [P, P]), ("leiden_set_tuning", [P, P]),
+                           ("leiden_autotune", [P, P, P]),
+                           ("leiden_batch_run", [P, u32, P, i32, P, u32, P, P, P]),
+                           ("leiden_server_create", [i32, u64, u32, ctypes.POINTER(P)]),
+                           ("leiden_server_add_graph", [P, u32, u64, P, P, P, i32, dbl, P, ctypes.POINTER(u32)]),
+                           ("leiden_server_remove_graph", [P, u32]),
+                           ("leiden_server_submit", [P, u32, P, u64, P, u64, i32, P, ctypes.POINTER(u64)]),
+                           ("leiden_server_wait", [P, u64, P, P, P, P, P]),
+                           ("leiden_server_get_stats", [P, P])):
+            getattr(L, name).argtypes = args
+            getattr(L, name).restype = i32
+        L.leiden_server_destroy.argtypes = [P]
+        L.leiden_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -259,6 +298,117 @@ class Graph:
         _check(lib().leiden_state_export(self._h, _ptr(C)[0], _ptr(K)[0], _ptr(S)[0], _ptr(dS)[0]))
         return C, K, S, dS
 
+    def tuning(self) -> dict:
+        t = LeidenTuning()
+        _check(lib().leiden_get_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, bin_max_degree):
+        t = LeidenTuning()
+        for i, x in enumerate(bin_max_degree):
+            t.bin_max_degree[i] = int(x)
+        _check(lib().leiden_set_tuning(self._h, ctypes.byref(t)))
+
+    def autotune(self, **opts) -> dict:
+        """Pick the degree-bin thresholds for this graph by measurement."""
+        o = default_opts(**opts)
+        t = LeidenTuning()
+        _check(lib().leiden_autotune(self._h, ctypes.byref(o), ctypes.byref(t)))
+        return t.as_dict()
+
     def set_state(self, C, K, S, dS):
         arrs = [np.ascontiguousarray(C, np.uint32)] + [np.ascontiguousarray(x, np.int64) for x in (K, S, dS)]
         _check(lib().leiden_state_import(self._h, *[_ptr(a)[0] for a in arrs]))
+
+
+def _batch_arrays(dels, ins):
+    d = np.ascontiguousarray(dels, np.uint32).reshape(-1, 2)
+    i = np.ascontiguousarray(ins, np.uint32).reshape(-1, 3)
+    return d, i
+
+
+def batch_run(graphs, batches=None, mode="df", streams=8, **opts):
+    """Batched form: leiden_static (batches None) or leiden_update on every
+    handle, `streams` graphs at a time.  Returns (memberships, q values)."""
+    count = len(graphs)
+    o = default_opts(**opts)
+    hs = (ctypes.c_void_p * count)(*[g._h.value for g in graphs])
+    outs = [np.zeros(g.n, np.uint32) for g in graphs]
+    po = (ctypes.c_void_p * count)(*[o_.ctypes.data for o_ in outs])
+    q = np.zeros(count, np.float64)
+    st = (ctypes.c_int * count)()
+    items = None
+    keep = []
+    if batches is not None:
+        items = (LeidenBatchItem * count)()
+        for k, (d, i) in enumerate(batches):
+            d, i = _batch_arrays(d, i)
+            keep += [d, i]
+            items[k] = LeidenBatchItem(d.ctypes.data if d.shape[0] else None, d.shape[0],
+                                       i.ctypes.data if i.shape[0] else None, i.shape[0])
+    rc = lib().leiden_batch_run(hs, count, items, MODES.get(mode, mode), ctypes.byref(o), streams, po,
+                                q.ctypes.data_as(ctypes.c_void_p), st)
+    _check(rc)
+    return outs, q
+
+
+class Server:
+    """Serving form: tenant graphs under an HBM budget, update requests served
+    by `workers` streams in arrival order (one request per graph at a time)."""
+
+    def __init__(self, hbm_budget_bytes, workers=4, device=0):
+        h = ctypes.c_void_p()
+        _check(lib().leiden_server_create(device, ctypes.c_uint64(int(hbm_budget_bytes)), workers, ctypes.byref(h)))
+        self._h = h
+        self._n = {}
+
+    def add_graph(self, csr, slack=0.2, **opts):
+        o = default_opts(**opts)
+        offs = np.ascontiguousarray(csr.offs, np.int64)
+        cols = np.ascontiguousarray(csr.cols, np.uint32)
+        w = np.ascontiguousarray(csr.w, np.uint32)
+        gid = ctypes.c_uint32()
+        _check(lib().leiden_server_add_graph(self._h, csr.n, ctypes.c_uint64(cols.shape[0]), _ptr(offs)[0],
+                                             _ptr(cols)[0], _ptr(w)[0], 0, ctypes.c_double(slack), ctypes.byref(o),
+                                             ctypes.byref(gid)))
+        self._n[gid.value] = csr.n
+        return gid.value
+
+    def remove_graph(self, gid):
+        _check(lib().leiden_server_remove_graph(self._h, gid))
+        self._n.pop(gid, None)
+
+    def submit(self, gid, dels, ins, mode="df", **opts):
+        o = default_opts(**opts)
+        d, i = _batch_arrays(dels, ins)
+        t = ctypes.c_uint64()
+        _check(lib().leiden_server_submit(self._h, gid, d.ctypes.data if d.shape[0] else None,
+                                          ctypes.c_uint64(d.shape[0]), i.ctypes.data if i.shape[0] else None,
+                                          ctypes.c_uint64(i.shape[0]), MODES.get(mode, mode), ctypes.byref(o),
+                                          ctypes.byref(t)))
+        return (gid, t.value)
+
+    def wait(self, ticket):
+        gid, t = ticket
+        out = np.zeros(self._n[gid], np.uint32)
+        q, lat, svc = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        st = LeidenStats()
+        _check(lib().leiden_server_wait(self._h, ctypes.c_uint64(t), out.ctypes.data_as(ctypes.c_void_p),
+                                        ctypes.byref(q), ctypes.byref(st), ctypes.byref(lat), ctypes.byref(svc)))
+        return Result(out, q.value, st.as_dict()), lat.value, svc.value
+
+    def stats(self):
+        s = LeidenServerStats()
+        _check(lib().leiden_server_get_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().leiden_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

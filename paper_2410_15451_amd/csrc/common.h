@@ -15,13 +15,19 @@ constexpr int kMaxClasses = 32; // vertex classes / refinement colours
 constexpr int kBins = 6;        // degree bins of the hash kernels
 
 // Degree bins: lanes per vertex and hash slots per vertex.  A vertex of
-// degree d goes to the first bin with d <= kBinMaxDeg; the last bin keeps its
-// table in global scratch.
-constexpr uint32_t kBinMaxDeg[kBins] = {8, 32, 128, 512, 2048, 0xFFFFFFFFu};
+// degree d goes to the first bin b with d <= max_deg[b]; the last bin (hubs)
+// keeps its tables in global memory.  The thresholds are tunable up to the
+// capacity of each bin's table (kBinCap: slots - 1, so a table never fills);
+// they change where a vertex is decided, never the decision.
+struct BinCfg {
+  uint32_t max_deg[kBins];
+};
+constexpr BinCfg kDefaultBins = {{8, 32, 128, 512, 2048, 0xFFFFFFFFu}};
+constexpr uint32_t kBinCap[kBins - 1] = {15, 63, 255, 1023, 4095};
 
-__host__ __device__ inline int bin_of_degree(uint32_t d) {
+__host__ __device__ inline int bin_of_degree(uint32_t d, const BinCfg& cfg) {
   int b = 0;
-  while (b < kBins - 1 && d > kBinMaxDeg[b]) ++b;
+  while (b < kBins - 1 && d > cfg.max_deg[b]) ++b;
   return b;
 }
 

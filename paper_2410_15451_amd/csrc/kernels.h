@@ -21,6 +21,8 @@ struct DecideParams {
   const unsigned int* count;
   Mover* movers;
   Ctl* ctl;
+  int async;             // 1: moves are applied at once against the live state
+  uint8_t* dS;           // split flags for asynchronous local moves (dynamic runs) or null
   // hub bin: every hub of the level owns a clean table in the arena
   const uint32_t* hub_idx;   // vertex -> hub index (hubs only)
   const uint64_t* hub_off;   // hub index -> first slot in the arena
@@ -44,7 +46,8 @@ struct HubLayout {
   unsigned long long* kid;
 };
 // fills list / idx / off / mask for the level; returns the arena slots needed in *slots
-int hub_layout(hipStream_t s, const uint32_t* len, uint32_t nl, HubLayout& h, Ctl* ctl, void* scan_tmp,
+int hub_layout(hipStream_t s, const uint32_t* len, uint32_t nl, uint32_t hub_above, HubLayout& h, Ctl* ctl,
+               void* scan_tmp,
                uint64_t* total_dev, uint32_t* count_out, uint64_t* slots_out);
 
 struct ApplyParams {
@@ -65,6 +68,7 @@ struct ApplyParams {
   size_t cls_stride;
   uint32_t* next_list;
   unsigned long long* mark_items;  // (mover, chunk) marking work items of the sub-round
+  int applied;         // 1: the decide kernels already moved the vertices (asynchronous mode)
 };
 
 // move.hip
@@ -72,7 +76,7 @@ void launch_distribute(hipStream_t s, const uint32_t* in_list, const unsigned in
                        uint32_t li, uint32_t P, uint32_t stamp, uint32_t* pend_mark, uint32_t* cls_lists,
                        size_t stride, Ctl* ctl);
 void launch_bin(hipStream_t s, const uint32_t* list, const unsigned int* count, uint32_t n_upper, const uint32_t* len,
-                const uint8_t* in_range, uint32_t* bin_lists, size_t stride, Ctl* ctl);
+                const uint8_t* in_range, uint32_t* bin_lists, size_t stride, const BinCfg& cfg, Ctl* ctl);
 // maxdeg: largest degree of the level (sizes the hub kernels)
 template <typename W, bool REFINE>
 void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, size_t stride, unsigned int* bin_counts,
@@ -104,7 +108,7 @@ void scatter_min_index(hipStream_t s, const uint32_t* key, uint64_t n, uint32_t*
 
 // phases.hip
 void fill_u64(hipStream_t s, uint64_t* p, uint64_t v, size_t n);
-void launch_degree_hist(hipStream_t s, const uint32_t* len, uint32_t n, unsigned long long* bins_out,
+void launch_degree_hist(hipStream_t s, const uint32_t* len, uint32_t n, const BinCfg& cfg, unsigned long long* bins_out,
                         unsigned int* maxdeg_out);
 void launch_row_sums_u32(hipStream_t s, Rows<uint32_t> g, uint32_t n, int64_t* K);
 void launch_count_members(hipStream_t s, const uint32_t* C, uint32_t n, uint32_t* size);

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(kBlock) void k_distribute(const uint32_t* in_list, 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_bin(const uint32_t* list, const unsigned int* count,
                                                 const uint32_t* len, const uint8_t* in_range, uint32_t* bin_lists,
-                                                size_t stride, Ctl* ctl) {
+                                                size_t stride, BinCfg cfg, Ctl* ctl) {
   __shared__ unsigned int lcount[kBins], lbase[kBins];
   const uint32_t cnt = *count;
   for (uint32_t base = blockIdx.x * kBlock; base < cnt; base += gridDim.x * kBlock) {
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kBlock) void k_bin(const uint32_t* list, const unsi
       v = list[i];
       const uint32_t d = len[v];
       if (d > 0 && (!in_range || in_range[v])) {
-        b = bin_of_degree(d);
+        b = bin_of_degree(d, cfg);
         pos = atomicAdd(&lcount[b], 1u);
       }
     }
@@ -84,8 +84,51 @@ __global__ __launch_bounds__(kBlock) void k_bin(const uint32_t* list, const unsi
 // ---------------------------------------------------------------------------
 template <typename W, bool REFINE>
 __device__ inline bool allowed_target(const DecideParams<W>& p, uint32_t c) {
-  if (!REFINE) return true;
+  if (!REFINE || p.async) return true;
   return p.size[c] >= 2 || vertex_colour(c, p.R) != p.colour;
+}
+
+// Asynchronous refinement move of isolated vertex v from its singleton d into
+// c (Alg. 8 with the paper's compare-and-swap guard): v first empties its own
+// community (only while nobody has joined it), then joins c unless c has been
+// emptied meanwhile, in which case v takes its community back.  Members of
+// communities with two or more vertices never move in this phase, so every
+// community stays connected.
+template <typename W>
+__device__ inline void refine_move_async(const DecideParams<W>& p, uint32_t v, uint32_t d, uint32_t c) {
+  uint32_t* size = const_cast<uint32_t*>(p.size);
+  if (atomicCAS(&size[d], 1u, 0u) != 1u) return;
+  uint32_t s = __atomic_load_n(&size[c], __ATOMIC_RELAXED);
+  while (s != 0) {
+    const uint32_t o = atomicCAS(&size[c], s, s + 1);
+    if (o == s) break;
+    s = o;
+  }
+  if (s == 0) {
+    atomicExch(&size[d], 1u);
+    return;
+  }
+  const long long k = p.K[v];
+  __atomic_store_n(const_cast<uint32_t*>(&p.C[v]), c, __ATOMIC_RELAXED);
+  atomicAdd((unsigned long long*)const_cast<int64_t*>(&p.S[d]), (unsigned long long)(-k));
+  atomicAdd((unsigned long long*)const_cast<int64_t*>(&p.S[c]), (unsigned long long)k);
+  atomicAdd(&p.ctl->refine_moves, 1ull);
+}
+
+// Asynchronous local move: applied at once against the live state; the mover
+// is queued only for marking its neighbours.
+template <typename W>
+__device__ inline void local_move_async(const DecideParams<W>& p, uint32_t v, uint32_t d, double dq, uint32_t c) {
+  const long long k = p.K[v];
+  __atomic_store_n(const_cast<uint32_t*>(&p.C[v]), c, __ATOMIC_RELAXED);
+  atomicAdd((unsigned long long*)const_cast<int64_t*>(&p.S[d]), (unsigned long long)(-k));
+  atomicAdd((unsigned long long*)const_cast<int64_t*>(&p.S[c]), (unsigned long long)k);
+  atomicSub(const_cast<uint32_t*>(&p.size[d]), 1u);
+  atomicAdd(const_cast<uint32_t*>(&p.size[c]), 1u);
+  if (p.dS) p.dS[d] = 1;
+  atomicAdd(&p.ctl->dq_fixed, (unsigned long long)gain_fixed(dq));
+  const unsigned int pos = atomicAdd(&p.ctl->mover_count, 1u);
+  p.movers[pos] = Mover{v, c, dq};
 }
 
 template <typename W, bool REFINE>
@@ -93,6 +136,13 @@ __device__ inline void emit_decision(const DecideParams<W>& p, uint32_t v, uint3
   if (bc == kNone || !(bdq > 0.0)) return;
   // two singletons of one class would swap forever: only the higher label moves
   if (!REFINE && p.size[d] == 1 && p.size[bc] == 1 && bc > d) return;
+  if (p.async) {
+    if (REFINE)
+      refine_move_async(p, v, d, bc);
+    else
+      local_move_async(p, v, d, bdq, bc);
+    return;
+  }
   const unsigned int pos = atomicAdd(&p.ctl->mover_count, 1u);
   p.movers[pos] = Mover{v, bc, bdq};
 }
@@ -370,11 +420,12 @@ __global__ __launch_bounds__(kBlock) void k_hub_pick(DecideParams<W> p) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_hub_list(const uint32_t* len, uint32_t nl, uint32_t* list, Ctl* ctl) {
+__global__ __launch_bounds__(kBlock) void k_hub_list(const uint32_t* len, uint32_t nl, uint32_t hub_above,
+                                                     uint32_t* list, Ctl* ctl) {
   __shared__ unsigned int s2[2];
   for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < nl; base += (uint64_t)gridDim.x * kBlock) {
     const uint64_t i = base + threadIdx.x;
-    const bool hub = i < nl && len[i] > kBinMaxDeg[kBins - 2];
+    const bool hub = i < nl && len[i] > hub_above;
     block_append(list, &ctl->misc[6], hub, (uint32_t)i, s2);
   }
 }
@@ -389,10 +440,12 @@ __global__ __launch_bounds__(kBlock) void k_hub_sizes(const uint32_t* len, uint3
   }
 }
 
-int hub_layout(hipStream_t s, const uint32_t* len, uint32_t nl, HubLayout& h, Ctl* ctl, void* scan_tmp,
+int hub_layout(hipStream_t s, const uint32_t* len, uint32_t nl, uint32_t hub_above, HubLayout& h, Ctl* ctl,
+               void* scan_tmp,
                uint64_t* total_dev, uint32_t* count_out, uint64_t* slots_out) {
   hipLaunchKernelGGL(k_clear_misc6, dim3(1), dim3(1), 0, s, ctl);
-  hipLaunchKernelGGL(k_hub_list, dim3(grid_for(nl, kBlock, 4096)), dim3(kBlock), 0, s, len, nl, h.list, ctl);
+  hipLaunchKernelGGL(k_hub_list, dim3(grid_for(nl, kBlock, 4096)), dim3(kBlock), 0, s, len, nl, hub_above, h.list,
+                     ctl);
   unsigned int cnt = 0;
   if (hipMemcpyAsync(&cnt, &ctl->misc[6], sizeof(cnt), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
@@ -466,15 +519,17 @@ __global__ __launch_bounds__(kBlock) void k_apply_moves(ApplyParams p) {
     if (m < cnt) {
       const Mover mv = p.movers[m];
       v = mv.v;
-      const uint32_t d = p.C[v];
-      const long long k = p.K[v];
-      p.C[v] = mv.c;
-      atomicAdd((unsigned long long*)&p.S[d], (unsigned long long)(-k));
-      atomicAdd((unsigned long long*)&p.S[mv.c], (unsigned long long)k);
-      atomicSub(&p.size[d], 1u);
-      atomicAdd(&p.size[mv.c], 1u);
-      dqsum += gain_fixed(mv.dq);
-      if (p.dS) p.dS[d] = 1;
+      if (!p.applied) {
+        const uint32_t d = p.C[v];
+        const long long k = p.K[v];
+        p.C[v] = mv.c;
+        atomicAdd((unsigned long long*)&p.S[d], (unsigned long long)(-k));
+        atomicAdd((unsigned long long*)&p.S[mv.c], (unsigned long long)k);
+        atomicSub(&p.size[d], 1u);
+        atomicAdd(&p.size[mv.c], 1u);
+        dqsum += gain_fixed(mv.dq);
+        if (p.dS) p.dS[d] = 1;
+      }
       nch = (p.len[v] + kMarkChunk - 1) / kMarkChunk;
     }
     // wavefront prefix of the chunk counts, one atomic per wavefront
@@ -564,9 +619,9 @@ void launch_distribute(hipStream_t s, const uint32_t* in_list, const unsigned in
 }
 
 void launch_bin(hipStream_t s, const uint32_t* list, const unsigned int* count, uint32_t n_upper, const uint32_t* len,
-                const uint8_t* in_range, uint32_t* bin_lists, size_t stride, Ctl* ctl) {
+                const uint8_t* in_range, uint32_t* bin_lists, size_t stride, const BinCfg& cfg, Ctl* ctl) {
   hipLaunchKernelGGL(k_bin, dim3(grid_for(n_upper, kBlock, 4096)), dim3(kBlock), 0, s, list, count, len, in_range,
-                     bin_lists, stride, ctl);
+                     bin_lists, stride, cfg, ctl);
 }
 
 template <typename W, bool REFINE>

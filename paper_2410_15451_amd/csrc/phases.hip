@@ -20,8 +20,8 @@ static int grid_n(uint64_t n, int per_block = kBlock, int cap = 8192) {
 // ---------------------------------------------------------------------------
 // Per-level helpers
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_degree_hist(const uint32_t* len, uint32_t n, unsigned long long* bins,
-                                                        unsigned int* maxdeg) {
+__global__ __launch_bounds__(kBlock) void k_degree_hist(const uint32_t* len, uint32_t n, BinCfg cfg,
+                                                        unsigned long long* bins, unsigned int* maxdeg) {
   __shared__ unsigned int lb[kBins];
   __shared__ unsigned int lmax;
   if (threadIdx.x < kBins) lb[threadIdx.x] = 0;
@@ -30,7 +30,7 @@ __global__ __launch_bounds__(kBlock) void k_degree_hist(const uint32_t* len, uin
   GRID_STRIDE(i, n) {
     const uint32_t d = len[i];
     if (d > 0) {
-      atomicAdd(&lb[bin_of_degree(d)], 1u);
+      atomicAdd(&lb[bin_of_degree(d, cfg)], 1u);
       atomicMax(&lmax, d);
     }
   }
@@ -39,9 +39,10 @@ __global__ __launch_bounds__(kBlock) void k_degree_hist(const uint32_t* len, uin
   if (threadIdx.x == 0 && lmax) atomicMax(maxdeg, lmax);
 }
 
-void launch_degree_hist(hipStream_t s, const uint32_t* len, uint32_t n, unsigned long long* bins_out,
+void launch_degree_hist(hipStream_t s, const uint32_t* len, uint32_t n, const BinCfg& cfg, unsigned long long* bins_out,
                         unsigned int* maxdeg_out) {
-  hipLaunchKernelGGL(k_degree_hist, dim3(grid_n(n, kBlock, 2048)), dim3(kBlock), 0, s, len, n, bins_out, maxdeg_out);
+  hipLaunchKernelGGL(k_degree_hist, dim3(grid_n(n, kBlock, 2048)), dim3(kBlock), 0, s, len, n, cfg, bins_out,
+                     maxdeg_out);
 }
 
 // Weighted degree of every row, one wavefront per row.
@@ -648,7 +649,8 @@ struct AggItem {
 template <typename W>
 __global__ __launch_bounds__(kBlock) void k_agg_big_insert(Rows<W> g, const uint32_t* C, const uint32_t* members,
                                                            const BigComm* bc, const AggItem* items, uint32_t nitems,
-                                                           uint32_t* gkeys, unsigned long long* gvals) {
+                                                           uint32_t* gkeys, unsigned long long* gvals,
+                                                           unsigned long long* units) {
   constexpr uint32_t kStage = 2048, kSlots = 4096;
   __shared__ int64_t sstart[kBlock];
   __shared__ uint32_t spre[kBlock];
@@ -660,6 +662,7 @@ __global__ __launch_bounds__(kBlock) void k_agg_big_insert(Rows<W> g, const uint
   }
   __syncthreads();
   __shared__ unsigned long long red[kBlock / kWave];
+  unsigned long long entries = 0;
   for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const AggItem x = items[it];
     const BigComm b = bc[x.big];
@@ -694,6 +697,7 @@ __global__ __launch_bounds__(kBlock) void k_agg_big_insert(Rows<W> g, const uint
       spre[threadIdx.x] = inc + add;
       __syncthreads();
       const uint32_t total = spre[kBlock - 1];
+      entries += total;
       for (uint32_t xb = 0; xb < total; xb += kStage) {
         const uint32_t xe = min(total, xb + kStage);
         for (uint32_t xx = xb + threadIdx.x; xx < xe; xx += kBlock) {
@@ -728,6 +732,7 @@ __global__ __launch_bounds__(kBlock) void k_agg_big_insert(Rows<W> g, const uint
     self = block_sum(self, red);
     if (threadIdx.x == 0 && self) table_add(tk, tv, b.mask, b.c, self);
   }
+  if (threadIdx.x == 0 && units && entries) atomicAdd(units, entries);
 }
 
 __global__ __launch_bounds__(kBlock) void k_agg_big_compact(const BigComm* bc, const AggItem* items, uint32_t nitems,
@@ -843,8 +848,13 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
     (void)hipMemcpyAsync(di + ins.size(), cmp.data(), sizeof(AggItem) * cmp.size(), hipMemcpyHostToDevice, s);
     fill_u32(s, b.gkeys, kNone, used);
     fill_u64(s, (uint64_t*)b.gvals, 0, used);
+    // the input graph's big communities are timed as LEIDEN_KT_AGG_BIG
+    const bool timed = sizeof(W) == 4;
+    if (timed) kt_mark(LEIDEN_KT_AGG_BIG, s);
     hipLaunchKernelGGL(k_agg_big_insert<W>, dim3(std::min<size_t>(ins.size(), 4096)), dim3(kBlock), 0, s, g, C,
-                       b.members, (const BigComm*)b.bigc, di, (uint32_t)ins.size(), b.gkeys, b.gvals);
+                       b.members, (const BigComm*)b.bigc, di, (uint32_t)ins.size(), b.gkeys, b.gvals,
+                       timed ? &ctl->kt_units[LEIDEN_KT_AGG_BIG] : nullptr);
+    if (timed) kt_mark(LEIDEN_KT_AGG_BIG, s);
     hipLaunchKernelGGL(k_agg_big_compact, dim3(std::min<size_t>(cmp.size(), 4096)), dim3(kBlock), 0, s,
                        (const BigComm*)b.bigc, di + ins.size(), (uint32_t)cmp.size(), b.gkeys, b.gvals,
                        (const uint64_t*)out_start, out_len, out_cols, out_w, Kout);

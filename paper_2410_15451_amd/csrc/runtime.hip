@@ -103,6 +103,8 @@ struct leiden_graph {
   bool has_state = false;
   Buf st_C, st_K, st_S, st_dS;
   uint32_t stamp = 0;  // iteration stamp, never reused
+  BinCfg bincfg = kDefaultBins;  // degree-bin thresholds (tunable)
+  float tune_ms = 0;             // probe time of the last autotuning
   // level-0 degree bins
   uint64_t bins0[kBins] = {0};
   uint32_t maxdeg0 = 0;
@@ -156,7 +158,9 @@ struct KtScope {
   ~KtScope() { tl_ktimer = nullptr; }
 };
 
-double kt_unit_bytes(int which) { return which == LEIDEN_KT_HUB_INSERT ? 12.0 : 0.0; }
+double kt_unit_bytes(int which) {
+  return which == LEIDEN_KT_HUB_INSERT || which == LEIDEN_KT_AGG_BIG ? 12.0 : 0.0;
+}
 
 // After the call's final synchronisation: launches, device time, units, bytes.
 void kt_collect(leiden_graph* G, int which, leiden_stats* st) {
@@ -294,7 +298,8 @@ leiden_status setup_hubs(leiden_graph* G, hipStream_t s, const uint32_t* len, ui
               G->hub_mask.as<uint32_t>(), G->hub_size.as<uint64_t>(), G->hub_kid.as<unsigned long long>()};
   uint32_t cnt = 0;
   uint64_t slots = 0;
-  if (hub_layout(s, len, nl, h, dctl(G), G->scan_tmp.p, G->small.as<uint64_t>() + 64, &cnt, &slots) != 0)
+  if (hub_layout(s, len, nl, G->bincfg.max_deg[kBins - 2], h, dctl(G), G->scan_tmp.p, G->small.as<uint64_t>() + 64,
+                 &cnt, &slots) != 0)
     return fail(LEIDEN_EDEVICE, "hub layout failed");
   // work items (at most one per 2048 entries plus one per hub), claim counters
   const size_t hc = std::max<uint32_t>(cnt, 1);
@@ -345,7 +350,7 @@ leiden_status level_bins(leiden_graph* G, hipStream_t s, const uint32_t* len, ui
                          uint32_t* maxdeg) {
   unsigned long long* d = G->small.as<unsigned long long>();
   fill_u64(s, (uint64_t*)d, 0, kBins + 1);
-  launch_degree_hist(s, len, nl, d, (unsigned int*)(d + kBins));
+  launch_degree_hist(s, len, nl, G->bincfg, d, (unsigned int*)(d + kBins));
   unsigned long long h[kBins + 1];
   HIPCHK(hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -384,7 +389,9 @@ template <typename W>
 leiden_status local_move(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, LevelState& L, const RunOpts& ro,
                          bool first_pass, double tau, const QConst& qc, const uint64_t bins[kBins], uint32_t maxdeg,
                          PassOut& out) {
-  const uint32_t P = ro.o.move_classes;
+  // the asynchronous mode runs one class per iteration and moves at once
+  const bool async = !ro.o.deterministic;
+  const uint32_t P = async ? 1 : ro.o.move_classes;
   Ctl* ctl = dctl(G);
   uint32_t* iter_list = G->iter_list.as<uint32_t>();
   uint32_t* next_list = G->next_list.as<uint32_t>();
@@ -398,6 +405,8 @@ leiden_status local_move(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
   dp.inv_2m2 = qc.inv_2m2;
   dp.movers = G->movers.as<Mover>();
   dp.ctl = ctl;
+  dp.async = async ? 1 : 0;
+  dp.dS = ro.dynamic ? L.dS : nullptr;
   bind_hubs(G, dp);
   const uint8_t* in_range = first_pass ? ro.in_range : nullptr;
   for (uint32_t li = 0; li < ro.o.max_iters; ++li) {
@@ -410,7 +419,7 @@ leiden_status local_move(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
     for (uint32_t k = 0; k < P; ++k) {
       launch_subround_reset(s, ctl);
       launch_bin(s, G->cls_lists.as<uint32_t>() + (size_t)k * nl, &ctl->cls_count[k], nl, g.len, in_range,
-                 G->bin_lists.as<uint32_t>(), (size_t)nl, ctl);
+                 G->bin_lists.as<uint32_t>(), (size_t)nl, G->bincfg, ctl);
       launch_decide_all<W, false>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, maxdeg);
       ApplyParams ap{};
       ap.start = g.start;
@@ -433,6 +442,7 @@ leiden_status local_move(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
       ap.cls_stride = nl;
       ap.next_list = next_list;
       ap.mark_items = G->mark_items.as<unsigned long long>();
+      ap.applied = async ? 1 : 0;
       launch_apply_moves(s, ap, nl, G->mark_items.bytes / 8);
     }
     CHK(read_ctl(G, s));
@@ -450,7 +460,9 @@ leiden_status local_move(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
 template <typename W>
 leiden_status refine(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, LevelState& L, const RunOpts& ro,
                      const QConst& qc, const uint64_t bins[kBins], uint32_t maxdeg) {
-  const uint32_t R = ro.o.refine_rounds;
+  // the asynchronous mode refines every isolated vertex in one round
+  const bool async = !ro.o.deterministic;
+  const uint32_t R = async ? 1 : ro.o.refine_rounds;
   Ctl* ctl = dctl(G);
   launch_cls_reset(s, ctl);
   launch_refine_reset(s, nl, L.C, G->CB.as<uint32_t>(), L.S, L.K, L.size, L.dR, R, G->cls_lists.as<uint32_t>(),
@@ -467,11 +479,12 @@ leiden_status refine(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, Lev
   dp.inv_2m2 = qc.inv_2m2;
   dp.movers = G->movers.as<Mover>();
   dp.ctl = ctl;
+  dp.async = async ? 1 : 0;
   bind_hubs(G, dp);
   for (uint32_t r = 0; r < R; ++r) {
     launch_subround_reset(s, ctl);
     launch_bin(s, G->cls_lists.as<uint32_t>() + (size_t)r * nl, &ctl->cls_count[r], nl, g.len, nullptr,
-               G->bin_lists.as<uint32_t>(), (size_t)nl, ctl);
+               G->bin_lists.as<uint32_t>(), (size_t)nl, G->bincfg, ctl);
     dp.colour = r;
     launch_decide_all<W, true>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, maxdeg);
     launch_apply_refine(s, L.C, L.S, L.K, L.size, G->movers.as<Mover>(), ctl, nl);
@@ -491,7 +504,7 @@ leiden_status split(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, Leve
   launch_split_sample<W>(s, g, L.C, lab, list, key, rest, ctl, nl);
   // vertices outside their community's main tree, by degree
   launch_subround_reset(s, ctl);
-  launch_bin(s, rest, &ctl->split_rest, nl, g.len, nullptr, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl);
+  launch_bin(s, rest, &ctl->split_rest, nl, g.len, nullptr, G->bin_lists.as<uint32_t>(), (size_t)nl, G->bincfg, ctl);
   launch_split_union<W>(s, g, L.C, lab, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins);
   launch_split_finish(s, L.C, lab, list, ctl, nl);
   return LEIDEN_OK;
@@ -635,8 +648,7 @@ leiden_status check_opts(const leiden_opts& o) {
   if (o.tau_re_den == 0 || o.tol_decline == 0 || o.max_iters == 0)
     return fail(LEIDEN_EINVAL, "tau_re_den, tol_decline and max_iters must be > 0");
   if (!(o.tau >= 0.0)) return fail(LEIDEN_EINVAL, "tau must be >= 0");
-  if (!o.deterministic) return fail(LEIDEN_EINVAL, "only the deterministic schedule is available");
-  if (o.timed_kernel < LEIDEN_KT_NONE || o.timed_kernel > LEIDEN_KT_HUB_INSERT)
+  if (o.timed_kernel < LEIDEN_KT_NONE || o.timed_kernel > LEIDEN_KT_AGG_BIG)
     return fail(LEIDEN_EINVAL, "unknown timed_kernel");
   return LEIDEN_OK;
 }
@@ -704,6 +716,82 @@ leiden_status rebuild(leiden_graph* G, hipStream_t s, const uint32_t* reserve) {
   return LEIDEN_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Degree-bin autotuning.  The probe is one local-moving iteration of the
+// synchronous schedule over every vertex of the input graph, starting from
+// singleton communities, with decisions only (nothing is applied), timed with
+// events; it runs the same decide kernels as the first iteration of a static
+// run.  Coordinate descent over the five thresholds, each tried at a few
+// multiples of its current value within the capacity of its bin.
+// ---------------------------------------------------------------------------
+bool bins_valid(const BinCfg& c) {
+  for (int b = 0; b < kBins - 1; ++b) {
+    if (c.max_deg[b] < 1 || c.max_deg[b] > kBinCap[b]) return false;
+    if (b > 0 && c.max_deg[b] <= c.max_deg[b - 1]) return false;
+  }
+  return true;
+}
+
+leiden_status probe_decide(leiden_graph* G, hipStream_t s, const leiden_opts& o, float* ms_out) {
+  const uint32_t n = G->n;
+  const uint32_t P = o.move_classes;
+  Ctl* ctl = dctl(G);
+  LevelState L = level_state(G);
+  uint64_t bins[kBins];
+  uint32_t maxdeg = 0;
+  CHK(level_bins(G, s, G->g.len, n, bins, &maxdeg));
+  if (bins[kBins - 1]) CHK(setup_hubs(G, s, G->g.len, n));
+  unsigned long long* m2d = G->small.as<unsigned long long>() + 128;
+  sum_i64(s, L.K, n, m2d);
+  unsigned long long M2 = 0;
+  HIPCHK(hipMemcpyAsync(&M2, m2d, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const QConst qc = make_qconst(M2 ? M2 : 1);
+  DecideParams<uint32_t> dp{};
+  dp.g = rows0(G);
+  dp.C = L.C;
+  dp.K = L.K;
+  dp.S = L.S;
+  dp.size = L.size;
+  dp.inv_m = qc.inv_m;
+  dp.inv_2m2 = qc.inv_2m2;
+  dp.movers = G->movers.as<Mover>();
+  dp.ctl = ctl;
+  bind_hubs(G, dp);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, s));
+  const uint32_t stamp = ++G->stamp;
+  launch_cls_reset(s, ctl);
+  launch_distribute(s, nullptr, nullptr, n, 0, P, stamp, G->pend.as<uint32_t>(), G->cls_lists.as<uint32_t>(),
+                    (size_t)n, ctl);
+  for (uint32_t k = 0; k < P; ++k) {
+    launch_subround_reset(s, ctl);
+    launch_bin(s, G->cls_lists.as<uint32_t>() + (size_t)k * n, &ctl->cls_count[k], n, G->g.len, nullptr,
+               G->bin_lists.as<uint32_t>(), (size_t)n, G->bincfg, ctl);
+    launch_decide_all<uint32_t, false>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)n, ctl->bin_count, bins, maxdeg);
+  }
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventSynchronize(e1));
+  ++G->stamp;
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms_out = ms;
+  return LEIDEN_OK;
+}
+
+// Level-0 degree bins after a change of thresholds.
+leiden_status refresh_bins0(leiden_graph* G) {
+  hipStream_t s = G->own;
+  CHK(level_bins(G, s, G->g.len, G->n, G->bins0, &G->maxdeg0));
+  HIPCHK(hipStreamSynchronize(s));
+  return LEIDEN_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -735,9 +823,89 @@ const char* leiden_kernel_name(int32_t kernel) {
       return "";
     case LEIDEN_KT_HUB_INSERT:
       return "lm::k_hub_chunk<unsigned int, false>";
+    case LEIDEN_KT_AGG_BIG:
+      return "lm::k_agg_big_insert<unsigned int>";
     default:
       return nullptr;
   }
+}
+
+
+leiden_status leiden_get_tuning(leiden_graph* G, leiden_tuning* out) {
+  g_err.clear();
+  if (!G || !out) return fail(LEIDEN_EINVAL, "null argument");
+  std::memset(out, 0, sizeof(*out));
+  for (int b = 0; b < kBins - 1; ++b) out->bin_max_degree[b] = G->bincfg.max_deg[b];
+  out->probe_ms = G->tune_ms;
+  return LEIDEN_OK;
+}
+
+leiden_status leiden_set_tuning(leiden_graph* G, const leiden_tuning* t) {
+  g_err.clear();
+  if (!G || !t) return fail(LEIDEN_EINVAL, "null argument");
+  BinCfg c = kDefaultBins;
+  for (int b = 0; b < kBins - 1; ++b) c.max_deg[b] = t->bin_max_degree[b];
+  if (!bins_valid(c))
+    return fail(LEIDEN_EINVAL, "bin thresholds must increase and stay within %u, %u, %u, %u, %u", kBinCap[0],
+                kBinCap[1], kBinCap[2], kBinCap[3], kBinCap[4]);
+  G->bincfg = c;
+  CHK(refresh_bins0(G));
+  return LEIDEN_OK;
+}
+
+leiden_status leiden_autotune(leiden_graph* G, const leiden_opts* opts, leiden_tuning* out) {
+  g_err.clear();
+  if (!G) return fail(LEIDEN_EINVAL, "null handle");
+  leiden_opts o;
+  leiden_default_opts(&o);
+  if (opts) o = *opts;
+  CHK(check_opts(o));
+  HIPCHK(hipSetDevice(G->device));
+  hipStream_t s = stream_of(G, opts);
+  CHK(ensure_workspace(G, std::max(o.move_classes, o.refine_rounds)));
+  const uint32_t n = G->n;
+  // singleton start on the input graph
+  zero_ctl(G, s);
+  LevelState L = level_state(G);
+  launch_row_sums_u32(s, rows0(G), n, L.K);
+  HIPCHK(hipMemcpyAsync(L.S, L.K, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s));
+  iota_u32(s, L.C, n);
+  fill_u32(s, L.size, 1, n);
+  auto measure = [&](const BinCfg& c, float* best) -> leiden_status {
+    G->bincfg = c;
+    float a = 0, b = 0;
+    CHK(probe_decide(G, s, o, &a));
+    CHK(probe_decide(G, s, o, &b));
+    *best = std::min(a, b);
+    return LEIDEN_OK;
+  };
+  BinCfg cur = G->bincfg;
+  float cur_ms = 0;
+  CHK(measure(cur, &cur_ms));
+  static const double kSteps[] = {0.5, 0.75, 1.5, 2.0};
+  for (int round = 0; round < 2; ++round) {
+    bool improved = false;
+    for (int b = 0; b < kBins - 1; ++b) {
+      for (double f : kSteps) {
+        BinCfg c = cur;
+        c.max_deg[b] = std::min<uint32_t>(kBinCap[b], std::max<uint32_t>(1, (uint32_t)(cur.max_deg[b] * f)));
+        if (c.max_deg[b] == cur.max_deg[b] || !bins_valid(c)) continue;
+        float ms = 0;
+        CHK(measure(c, &ms));
+        if (ms < cur_ms * 0.98f) {  // keep a change only for a clear gain
+          cur = c;
+          cur_ms = ms;
+          improved = true;
+        }
+      }
+    }
+    if (!improved) break;
+  }
+  G->bincfg = cur;
+  G->tune_ms = cur_ms;
+  CHK(refresh_bins0(G));
+  if (out) CHK(leiden_get_tuning(G, out));
+  return LEIDEN_OK;
 }
 
 const char* leiden_last_error(void) { return g_err.c_str(); }

@@ -24,7 +24,14 @@ stand in for them):
     probabilities (a, b, c, d), self-loops and duplicates dropped, a seeded vertex
     permutation, unit weights;
   * random batch (Section 5.1.4): a fraction of |E| undirected updates, 80%
-    insertions of uniform absent pairs and 20% deletions of uniform existing edges.
+    insertions of uniform absent pairs and 20% deletions of uniform existing edges;
+  * kNN-style graphs for the batched form: points from a 16-d standard normal,
+    quantised to integers so distances are exact on every machine; buckets by
+    the sign pattern of ceil(log2(n / 512)) random projections; in each bucket
+    the 32 nearest points of every point, of which 15 chosen uniformly become
+    its neighbours; symmetrised by union; weight
+    clamp(1 + floor(100 exp(-d^2 / D)), 1, 100) with D the median neighbour d^2;
+    many such graphs with vertex counts log-uniform in a range.
 """
 from __future__ import annotations
 
@@ -218,3 +225,57 @@ def keys_after_batch(existing_keys: np.ndarray, dels: np.ndarray, ins: np.ndarra
 def batch_size_for(nnz_directed: int, frac: float) -> int:
     """Number of undirected updates for a batch of ``frac * |E|`` (|E| counts directed entries)."""
     return max(1, int(round(frac * nnz_directed)))
+
+
+def knn_graph(n: int, k: int = 15, dim: int = 16, cand: int = 32, seed: int = BASE_SEED + 4) -> Csr:
+    """kNN-style graph on n random points (recipe in the module docstring)."""
+    rng = rng_for(seed)
+    X = np.round(rng.standard_normal((n, dim)) * 256.0).astype(np.int64)
+    nproj = max(0, int(np.ceil(np.log2(max(n, 1) / 512.0))))
+    if nproj:
+        R = rng.standard_normal((dim, nproj))
+        bits = (X.astype(np.float64) @ R) > 0
+        bucket = (bits * (1 << np.arange(nproj))).sum(axis=1)
+    else:
+        bucket = np.zeros(n, np.int64)
+    order = np.argsort(bucket, kind="stable")
+    starts = np.searchsorted(bucket[order], np.arange((1 << nproj) + 1))
+    us, vs, ds = [], [], []
+    for b in range(1 << nproj):
+        idx = order[starts[b]:starts[b + 1]]
+        m = idx.shape[0]
+        if m < 2:
+            continue
+        P = X[idx]
+        sq = (P * P).sum(axis=1)
+        D2 = sq[:, None] + sq[None, :] - 2 * (P @ P.T)  # exact in int64
+        np.fill_diagonal(D2, np.iinfo(np.int64).max // (m + 1))  # never among the nearest; no overflow below
+        c = min(cand, m - 1)
+        # the c nearest of each point, ties to the lower index
+        key = D2 * m + np.arange(m)[None, :]
+        near = np.argpartition(key, c - 1, axis=1)[:, :c] if c < m else np.argsort(key, axis=1)[:, :c]
+        pick = min(k, c)
+        sel = np.argsort(rng.random((m, c)), axis=1)[:, :pick]
+        nb = np.take_along_axis(near, sel, axis=1)
+        us.append(np.repeat(idx, pick))
+        vs.append(idx[nb.reshape(-1)])
+        ds.append(np.take_along_axis(D2, nb, axis=1).reshape(-1))
+    if not us:
+        return csr_from_undirected(n, np.zeros(0, np.uint32), np.zeros(0, np.uint32))
+    u = np.concatenate(us).astype(np.int64)
+    v = np.concatenate(vs).astype(np.int64)
+    d2 = np.concatenate(ds)
+    lo, hi = np.minimum(u, v), np.maximum(u, v)
+    key = lo * n + hi
+    key, first = np.unique(key, return_index=True)  # union of both directions
+    d2 = d2[first]
+    Dm = float(np.median(d2)) if d2.shape[0] else 1.0
+    w = np.clip(1 + np.floor(100.0 * np.exp(-d2.astype(np.float64) / max(Dm, 1.0))), 1, 100).astype(np.uint32)
+    return csr_from_undirected(n, (key // n).astype(np.uint32), (key % n).astype(np.uint32), w)
+
+
+def knn_forest(count: int, n_min: int = 1000, n_max: int = 200000, seed: int = BASE_SEED + 4):
+    """``count`` kNN-style graphs with vertex counts log-uniform in [n_min, n_max]."""
+    rng = rng_for(seed)
+    ns = np.round(np.exp(rng.uniform(np.log(n_min), np.log(n_max), count))).astype(np.int64)
+    return [knn_graph(int(x), seed=seed + 1 + i) for i, x in enumerate(ns)]

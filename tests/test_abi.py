@@ -33,15 +33,21 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "leiden.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu\\n", sizeof(leiden_opts), sizeof(leiden_stats),'
-                   ' offsetof(leiden_opts, stream), offsetof(leiden_stats, nnz)); return 0;}\n')
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(leiden_opts),'
+                   ' sizeof(leiden_stats), offsetof(leiden_opts, stream), offsetof(leiden_stats, nnz),'
+                   ' offsetof(leiden_opts, timed_kernel), offsetof(leiden_stats, kt_bytes),'
+                   ' sizeof(leiden_tuning), offsetof(leiden_tuning, probe_ms)); return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)])
-    a, b, c, d = map(int, subprocess.check_output([str(exe)]).split())
+    a, b, c, d, e, f, g, h = map(int, subprocess.check_output([str(exe)]).split())
     assert a == ctypes.sizeof(binding.LeidenOpts)
     assert b == ctypes.sizeof(binding.LeidenStats)
     assert c == binding.LeidenOpts.stream.offset
     assert d == binding.LeidenStats.nnz.offset
+    assert e == binding.LeidenOpts.timed_kernel.offset
+    assert f == binding.LeidenStats.kt_bytes.offset
+    assert g == ctypes.sizeof(binding.LeidenTuning)
+    assert h == binding.LeidenTuning.probe_ms.offset
 
 
 def test_default_opts_without_gpu():

@@ -276,3 +276,85 @@ def test_rmat22_benchmark_configuration(lm, orc):
     assert np.array_equal(Ks, K)
     S = np.bincount(C1, weights=K.astype(np.float64), minlength=g.n).astype(np.int64)  # exact below 2^53
     assert np.array_equal(Ss, S)
+
+
+# ---------------------------------------------------------------------------
+# Asynchronous mode (deterministic = 0): moves are applied at once against the
+# live state (one class per iteration, one refinement round with the
+# compare-and-swap guard), so memberships are not reproducible.  The bar is
+# modularity within 1e-3 of the oracle's sequential run of the paper's
+# asynchronous algorithm, a reported modularity equal to Eq. 1 of the returned
+# membership, and a valid membership.
+# ---------------------------------------------------------------------------
+ASYNC_TOL = 1e-3
+
+
+def _check_async_result(orc, g, r):
+    C = r.membership
+    assert C.shape == (g.n,) and int(C.max()) < g.n
+    assert abs(r.q - orc.modularity(g, C)) <= 1e-12
+
+
+@pytest.mark.parametrize("which", ["planted", "rmat12", "rmat16"])
+def test_async_static_modularity(lm, orc, which):
+    g = inputs.planted_partition() if which == "planted" else inputs.rmat(int(which[4:]), seed=3)
+    _, q_seq, _ = orc.static(g, schedule=orc.SEQ)
+    G = _graph(lm, g)
+    r = G.static(deterministic=0)
+    _check_async_result(orc, g, r)
+    assert abs(r.q - q_seq) <= ASYNC_TOL, (which, r.q, q_seq)
+
+
+@pytest.mark.parametrize("mode", ["nd", "ds", "df"])
+def test_async_updates_modularity(lm, orc, mode):
+    g = inputs.rmat(14, seed=8)
+    G = _graph(lm, g)
+    G.static(deterministic=0)
+    C0, _, _ = orc.static(g, schedule=orc.SEQ)
+    state = orc.initial_state(g, C0)
+    cur = g
+    for bi, (dels, ins) in enumerate(_stream(g, [10, 100, 1000], seed=51)):
+        gt, dw = orc.apply_batch(cur, dels, ins)
+        r = G.update(dels, ins, mode=mode, deterministic=0)
+        _check_async_result(orc, gt, r)
+        _, state, q_seq, _ = orc.update(gt, dw, ins, state, mode, schedule=orc.SEQ)
+        assert abs(r.q - q_seq) <= ASYNC_TOL, (mode, bi, r.q, q_seq)
+        cur = gt
+
+
+# ---------------------------------------------------------------------------
+# Degree-bin thresholds (autotuner): they choose the kernel that evaluates a
+# vertex, never the decision, so every valid setting gives the oracle's
+# memberships.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("bins", [(8, 32, 128, 512, 2048), (4, 16, 64, 256, 1024), (15, 63, 255, 1023, 4095),
+                                  (1, 2, 3, 4, 5)])
+def test_bin_thresholds_do_not_change_results(lm, orc, bins):
+    g = inputs.rmat(13, seed=12)
+    G = _graph(lm, g)
+    G.set_tuning(bins)
+    assert G.tuning()["bin_max_degree"] == list(bins)
+    r = G.static()
+    C, q, _ = orc.static(g)
+    assert np.array_equal(r.membership, C) and r.q == q
+    (dels, ins), = _stream(g, [500], seed=61)
+    gt, dw = orc.apply_batch(g, dels, ins)
+    r1 = G.update(dels, ins, mode="df")
+    C1, _, q1, _ = orc.update(gt, dw, ins, orc.initial_state(g, C), "df")
+    assert np.array_equal(r1.membership, C1) and r1.q == q1
+
+
+def test_autotune_and_invalid_thresholds(lm, orc):
+    g = inputs.rmat(14, seed=13)
+    G = _graph(lm, g)
+    t = G.autotune()
+    b = t["bin_max_degree"]
+    assert all(x < y for x, y in zip(b, b[1:])) and t["probe_ms"] > 0
+    assert all(x <= cap for x, cap in zip(b, (15, 63, 255, 1023, 4095)))
+    r = G.static()
+    C, q, _ = orc.static(g)
+    assert np.array_equal(r.membership, C) and r.q == q
+    for bad in [(8, 8, 128, 512, 2048), (16, 32, 128, 512, 2048), (8, 32, 128, 512, 5000), (0, 32, 128, 512, 2048)]:
+        with pytest.raises(lm.LeidenError):
+            G.set_tuning(bad)
+    assert G.tuning()["bin_max_degree"] == b

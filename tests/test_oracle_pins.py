@@ -641,3 +641,17 @@ def test_ds_marking_follows_its_definition(orc):
     assert pdf["in_range"].all()
     pnd = orc.prepare(gt, dw, ins, st, "nd")
     assert pnd["affected"].all() and pnd["in_range"].all()
+
+
+def test_knn_inputs_are_valid_graphs():
+    """The kNN-style generator (batched workload) yields simple symmetric
+    graphs with weights in 1..100, identically on every call."""
+    g = inputs.knn_graph(3000, seed=5)
+    h = inputs.knn_graph(3000, seed=5)
+    assert np.array_equal(g.cols, h.cols) and np.array_equal(g.w, h.w)
+    rows = np.repeat(np.arange(g.n), np.diff(g.offs))
+    assert not np.any(rows == g.cols)
+    assert int(g.w.min()) >= 1 and int(g.w.max()) <= 100
+    fwd = set(zip(rows.tolist(), g.cols.tolist(), g.w.tolist()))
+    assert all((c, r, w) in fwd for r, c, w in fwd)
+    assert np.diff(g.offs).min() >= 1
