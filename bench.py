@@ -119,6 +119,108 @@ def stored_traffic(kernel, workload):
     return r.get("hbm_bytes_per_launch")
 
 
+def run_batched(args, binding, inputs):
+    """Many independent kNN-style graphs: static Leiden on all, then one DF
+    update of 1e-3 |E| each; batched over worker streams against one graph at
+    a time on the same GPU, memberships compared."""
+    import numpy as np
+    t0 = time.time()
+    gs = inputs.knn_forest(args.graphs, 1000, 20000, seed=inputs.BASE_SEED + 4)
+    edges = sum(g.nnz for g in gs)
+    log("batched: %d kNN graphs, %d entries (%.1f s to generate)" % (len(gs), edges, time.time() - t0))
+    batches = [inputs.random_batch(g.n, g.undirected_keys(), inputs.batch_size_for(g.nnz, 1e-3), seed=700 + k,
+                                   w_range=(1, 100)) for k, g in enumerate(gs)]
+    res = {}
+    for label, streams in (("single", 1), ("batched", args.streams)):
+        hs = [binding.Graph.from_csr(g) for g in gs]
+        binding.batch_run(hs[:2], streams=1)  # warm-up of the runtime
+        hs = [binding.Graph.from_csr(g) for g in gs]
+        ta = time.perf_counter()
+        C0, _ = binding.batch_run(hs, streams=streams)
+        tb = time.perf_counter()
+        C1, _ = binding.batch_run(hs, batches, mode="df", streams=streams)
+        tc = time.perf_counter()
+        res[label] = {"static_s": tb - ta, "update_s": tc - tb, "C0": C0, "C1": C1}
+        del hs
+    same = all(np.array_equal(a, b) for a, b in zip(res["single"]["C0"], res["batched"]["C0"])) and \
+        all(np.array_equal(a, b) for a, b in zip(res["single"]["C1"], res["batched"]["C1"]))
+    b, s1 = res["batched"], res["single"]
+    return {"metric": "edges/s, batched static + DF update over many kNN graphs (1 GPU)",
+            "value": 2 * edges / (b["static_s"] + b["update_s"]), "unit": "edges/s", "n_gpus": 1,
+            "higher_is_better": True, "data": "synthetic", "dtype": "int64+f64",
+            "config": {"workload": "knn_forest", "graphs": len(gs), "n_range": [1000, 20000], "entries": edges,
+                       "streams": args.streams, "update_frac": 1e-3},
+            "batched": {"static_s": b["static_s"], "update_s": b["update_s"]},
+            "one_graph_at_a_time": {"static_s": s1["static_s"], "update_s": s1["update_s"]},
+            "speedup": (s1["static_s"] + s1["update_s"]) / (b["static_s"] + b["update_s"]),
+            "identical_memberships": bool(same)}
+
+
+def run_serving(args, binding, inputs):
+    """Tenant R-MAT graphs in a server under an HBM budget; a Poisson stream
+    of DF update requests (sizes log-uniform, 80/20 insert/delete) at a rate
+    set from the measured single-stream capacity."""
+    import numpy as np
+    scales = [16, 16, 17, 17, 18, 18, 19, 19]
+    t0 = time.time()
+    gs = [inputs.rmat(sc, seed=inputs.BASE_SEED + 5 + k) for k, sc in enumerate(scales)]
+    log("serving: %d tenants (%.1f s to generate)" % (len(gs), time.time() - t0))
+    rng = np.random.default_rng(inputs.BASE_SEED + 6)
+    nreq = args.requests
+    targets = rng.integers(0, len(gs), nreq + 20)
+    sizes = np.round(np.exp(rng.uniform(np.log(1e2), np.log(2e4), nreq + 20))).astype(np.int64)
+    keys = [g.undirected_keys() for g in gs]
+    reqs = []
+    for k in range(nreq + 20):
+        t = int(targets[k])
+        d, i = inputs.random_batch(gs[t].n, keys[t], int(sizes[k]), seed=900 + k)
+        keys[t] = inputs.keys_after_batch(keys[t], d, i)
+        reqs.append((t, d, i))
+    srv = binding.Server(hbm_budget_bytes=64 << 30, workers=args.streams)
+    ids = [srv.add_graph(g) for g in gs]
+    # capacity: the first 20 requests back to back on the server
+    ta = time.perf_counter()
+    for t, d, i in reqs[:20]:
+        srv.wait(srv.submit(ids[t], d, i, mode="df"))
+    per_req = (time.perf_counter() - ta) / 20
+    lam = 0.7 / per_req * args.streams  # offered load: 70% of the streams' capacity
+    gaps = rng.exponential(1.0 / lam, nreq)
+    srv2 = binding.Server(hbm_budget_bytes=64 << 30, workers=args.streams)
+    ids2 = [srv2.add_graph(g) for g in gs]
+    # replay the first 20 to bring the second server's graphs to the same point
+    for t, d, i in reqs[:20]:
+        srv2.wait(srv2.submit(ids2[t], d, i, mode="df"))
+    srv2_stats0 = srv2.stats()
+    tickets = []
+    start = time.perf_counter()
+    due = start
+    for k in range(nreq):
+        due += gaps[k]
+        now = time.perf_counter()
+        if due > now:
+            time.sleep(due - now)
+        t, d, i = reqs[20 + k]
+        tickets.append(srv2.submit(ids2[t], d, i, mode="df"))
+    lat, svc = [], []
+    for tk in tickets:
+        _, la, sv = srv2.wait(tk)
+        lat.append(la)
+        svc.append(sv)
+    wall = time.perf_counter() - start
+    upd = int(sum(reqs[20 + k][1].shape[0] + reqs[20 + k][2].shape[0] for k in range(nreq)))
+    srv.close()
+    srv2.close()
+    return {"metric": "serving: p50/p99 update latency and sustained updated edges/s (1 GPU)",
+            "value": upd / wall, "unit": "updated_edges/s", "n_gpus": 1, "higher_is_better": True,
+            "data": "synthetic", "dtype": "int64+f64",
+            "config": {"workload": "rmat_tenants", "scales": scales, "requests": nreq,
+                       "batch_sizes": "log-uniform 1e2..2e4 undirected updates, 80/20", "workers": args.streams,
+                       "offered_load": "Poisson at 70% of measured capacity"},
+            "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
+            "service_ms": {"p50": percentile(svc, 50), "p99": percentile(svc, 99)},
+            "single_request_ms_back_to_back": per_req * 1e3, "completed_before": srv2_stats0["completed"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,6 +234,12 @@ def main():
     ap.add_argument("--cpu-scale", type=int, default=20)
     ap.add_argument("--cpu-reps", type=int, default=24)
     ap.add_argument("--timed-kernel", default="agg_big", help="kernel timed with HIP events for the roofline")
+    ap.add_argument("--workload", default="rmat", choices=["rmat", "batched", "serving"],
+                    help="rmat: the 4M-vertex R-MAT DF stream (default); batched: many kNN graphs at once; "
+                         "serving: tenant R-MAT graphs under a Poisson stream of update requests")
+    ap.add_argument("--graphs", type=int, default=128, help="batched: number of kNN graphs")
+    ap.add_argument("--streams", type=int, default=8, help="batched / serving: worker streams")
+    ap.add_argument("--requests", type=int, default=300, help="serving: measured requests")
     ap.add_argument("--marker", type=int, default=0,
                     help="launch a spin kernel right before and after the timed steps (profile windowing)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -146,6 +254,12 @@ def main():
     import torch
 
     from paper_2410_15451_amd import binding, inputs
+    if args.workload == "batched":
+        print(json.dumps(run_batched(args, binding, inputs)), flush=True)
+        return
+    if args.workload == "serving":
+        print(json.dumps(run_serving(args, binding, inputs)), flush=True)
+        return
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     sp = stream.cuda_stream
@@ -163,7 +277,7 @@ def main():
     log("graph: n=%d nnz=%d maxdeg=%d (%.1f s)" % (g.n, g.nnz, int(g.degrees().max()), time.time() - t0))
     nb = inputs.batch_size_for(g.nnz, args.frac)
     ctx = args.context_steps
-    total_batches = args.warmup + args.steps + 2 * ctx
+    total_batches = args.warmup + args.steps + 3 * ctx
     batches = inputs.random_batch_stream(g.n, g.undirected_keys(), nb, total_batches,
                                          seed=inputs.BASE_SEED + 2 + 1000)
     dev_batches = [(torch.from_numpy(d.view(np.int32)).to(dev), torch.from_numpy(i.view(np.int32)).to(dev))
@@ -223,6 +337,10 @@ def main():
     for mode in [m for m in ("nd", "ds") if m != args.mode and ctx]:
         ts = [run_update(mode)[0] for _ in range(ctx)]
         context[mode + "_ms"] = 1e3 * sum(ts) / len(ts)
+    if ctx:
+        # the asynchronous mode on the same stream (not reproducible, faster)
+        ts = [run_update(args.mode, deterministic=0)[0] for _ in range(ctx)]
+        context["async_" + args.mode + "_ms"] = 1e3 * sum(ts) / len(ts)
     ts = []
     for _ in range(ctx):
         torch.cuda.synchronize()

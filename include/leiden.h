@@ -79,7 +79,8 @@ typedef struct {
   int32_t compute_modularity; /* 1: fill *q_out with Eq. 1 of the result; 0: NaN */
   void* stream;           /* hipStream_t or NULL */
   int32_t timed_kernel;   /* a leiden_kernel to time with HIP events on the stream, or LEIDEN_KT_NONE */
-  int32_t pad_;
+  int32_t split_all;      /* 1: split every community not marked for refinement (the ablation of
+                             Section 4.3), 0: only the communities marked to be split (default) */
 } leiden_opts;
 
 /* Per-call statistics. */

@@ -31,7 +31,8 @@ class OracleOpts(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("tau_re_num", ctypes.c_uint32), ("tau_re_den", ctypes.c_uint32),
                 ("tol_decline", ctypes.c_uint32), ("max_iters", ctypes.c_uint32),
                 ("max_passes", ctypes.c_uint32), ("schedule", ctypes.c_int32),
-                ("move_classes", ctypes.c_uint32), ("refine_rounds", ctypes.c_uint32)]
+                ("move_classes", ctypes.c_uint32), ("refine_rounds", ctypes.c_uint32),
+                ("split_all", ctypes.c_int32)]
 
 
 class OracleStats(ctypes.Structure):
@@ -115,7 +116,7 @@ def _c(a, dtype):
 
 
 def make_opts(schedule=JACOBI, tau=1e-2, tau_re=(3, 5), tol_decline=10, max_iters=20, max_passes=10,
-              move_classes=8, refine_rounds=8):
+              move_classes=8, refine_rounds=8, split_all=0):
     o = OracleOpts()
     lib().oracle_default_opts(ctypes.byref(o))
     o.tau = tau
@@ -123,6 +124,7 @@ def make_opts(schedule=JACOBI, tau=1e-2, tau_re=(3, 5), tol_decline=10, max_iter
     o.tol_decline, o.max_iters, o.max_passes = tol_decline, max_iters, max_passes
     o.schedule = schedule
     o.move_classes, o.refine_rounds = move_classes, refine_rounds
+    o.split_all = split_all
     return o
 
 

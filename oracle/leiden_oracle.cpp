@@ -77,6 +77,8 @@ typedef struct {
   int32_t schedule;     /* 0 = SEQ, 1 = JACOBI */
   uint32_t move_classes;  /* JACOBI: vertex classes per local-moving iteration (8) */
   uint32_t refine_rounds; /* JACOBI: colour rounds of the refinement (8) */
+  int32_t split_all;      /* 1: split every community not marked for refinement (Section 4.3's
+                             comparison with selective splitting), 0: selective (default) */
 } oracle_opts;
 
 typedef struct {
@@ -400,7 +402,7 @@ void subset_renumber(Level& L) {
  * to be refined is replaced by the connected components of the subgraph its
  * vertices induce, each labelled by its minimum vertex.  Returns the number
  * of communities split-marked. */
-u64 split_communities(Level& L) {
+u64 split_communities(Level& L, bool split_all) {
   u32 n = L.G.n;
   std::vector<u32> out = L.C;
   std::vector<u8> seen(n, 0);
@@ -409,7 +411,7 @@ u64 split_communities(Level& L) {
   u64 marked = 0;
   for (u32 s = 0; s < n; ++s) {
     u32 c = L.C[s];
-    if (!(L.dS[c] && !L.dR[c])) continue;
+    if (!((split_all || L.dS[c]) && !L.dR[c])) continue;
     if (!counted[c]) {
       counted[c] = 1;
       marked++;
@@ -698,7 +700,7 @@ std::vector<u32> leiden(const Graph& G0, const std::vector<u32>& Cprev, const st
     }
     u32 li = mr.iterations;
     subset_renumber(L);
-    u64 split_marked = split_communities(L);
+    u64 split_marked = split_communities(L, o.split_all != 0);
     if (st && lp == 0) st->split_marked = split_marked;
     std::vector<u32> CB = L.C;
     u64 rmoves = 0;
@@ -738,6 +740,7 @@ oracle_opts default_opts() {
   o.schedule = 1;
   o.move_classes = 8;
   o.refine_rounds = 8;
+  o.split_all = 0;
   return o;
 }
 
@@ -812,7 +815,7 @@ void oracle_split(uint32_t n, const int64_t* offs, const uint32_t* cols, const u
   L.C.assign(C, C + n);
   L.dS.assign(split, split + n);
   L.dR.assign(refine_flags, refine_flags + n);
-  split_communities(L);
+  split_communities(L, false);
   std::memcpy(C, L.C.data(), sizeof(uint32_t) * n);
 }
 

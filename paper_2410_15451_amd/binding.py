@@ -6,7 +6,9 @@ never falls back to anything else: without the built library it raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import weakref
 import os
 from dataclasses import dataclass
 
@@ -45,7 +47,7 @@ class LeidenOpts(ctypes.Structure):
                 ("tol_decline", ctypes.c_uint32), ("max_iters", ctypes.c_uint32), ("max_passes", ctypes.c_uint32),
                 ("move_classes", ctypes.c_uint32), ("refine_rounds", ctypes.c_uint32),
                 ("deterministic", ctypes.c_int32), ("compute_modularity", ctypes.c_int32),
-                ("stream", ctypes.c_void_p), ("timed_kernel", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("stream", ctypes.c_void_p), ("timed_kernel", ctypes.c_int32), ("split_all", ctypes.c_int32)]
 
 
 class LeidenStats(ctypes.Structure):
@@ -193,6 +195,26 @@ class Result:
     stats: dict
 
 
+# Live handles and servers, closed at interpreter exit (servers first: their
+# worker threads must be joined while the HIP runtime is still up).
+_LIVE_SERVERS = weakref.WeakSet()
+_LIVE_GRAPHS = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for s in list(_LIVE_SERVERS):
+        try:
+            s.close()
+        except Exception:
+            pass
+    for g in list(_LIVE_GRAPHS):
+        try:
+            g.close()
+        except Exception:
+            pass
+
+
 class Graph:
     """A graph handle on one GPU (owns the device CSR and the community state)."""
 
@@ -213,6 +235,7 @@ class Graph:
         self._h = h
         self.n = n
         self.device = device
+        _LIVE_GRAPHS.add(self)
 
     @classmethod
     def from_csr(cls, csr, **kw):
@@ -361,6 +384,7 @@ class Server:
         _check(lib().leiden_server_create(device, ctypes.c_uint64(int(hbm_budget_bytes)), workers, ctypes.byref(h)))
         self._h = h
         self._n = {}
+        _LIVE_SERVERS.add(self)
 
     def add_graph(self, csr, slack=0.2, **opts):
         o = default_opts(**opts)

@@ -84,7 +84,7 @@ __global__ __launch_bounds__(kBlock) void k_bin(const uint32_t* list, const unsi
 // ---------------------------------------------------------------------------
 template <typename W, bool REFINE>
 __device__ inline bool allowed_target(const DecideParams<W>& p, uint32_t c) {
-  if (!REFINE || p.async) return true;
+  if (!REFINE) return true;
   return p.size[c] >= 2 || vertex_colour(c, p.R) != p.colour;
 }
 

@@ -389,9 +389,9 @@ template <typename W>
 leiden_status local_move(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, LevelState& L, const RunOpts& ro,
                          bool first_pass, double tau, const QConst& qc, const uint64_t bins[kBins], uint32_t maxdeg,
                          PassOut& out) {
-  // the asynchronous mode runs one class per iteration and moves at once
+  // the asynchronous mode keeps the class sub-rounds but moves at once
   const bool async = !ro.o.deterministic;
-  const uint32_t P = async ? 1 : ro.o.move_classes;
+  const uint32_t P = ro.o.move_classes;
   Ctl* ctl = dctl(G);
   uint32_t* iter_list = G->iter_list.as<uint32_t>();
   uint32_t* next_list = G->next_list.as<uint32_t>();
@@ -460,9 +460,9 @@ leiden_status local_move(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
 template <typename W>
 leiden_status refine(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, LevelState& L, const RunOpts& ro,
                      const QConst& qc, const uint64_t bins[kBins], uint32_t maxdeg) {
-  // the asynchronous mode refines every isolated vertex in one round
+  // the asynchronous mode keeps the colour rounds but moves at once
   const bool async = !ro.o.deterministic;
-  const uint32_t R = async ? 1 : ro.o.refine_rounds;
+  const uint32_t R = ro.o.refine_rounds;
   Ctl* ctl = dctl(G);
   launch_cls_reset(s, ctl);
   launch_refine_reset(s, nl, L.C, G->CB.as<uint32_t>(), L.S, L.K, L.size, L.dR, R, G->cls_lists.as<uint32_t>(),
@@ -519,6 +519,8 @@ leiden_status run_pass(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, L
   if (bins[kBins - 1]) CHK(setup_hubs(G, s, g.len, nl));
   CHK(local_move<W>(G, s, g, nl, L, ro, pass == 0, tau, qc, bins, maxdeg, po));
   if (st && pass < 16) st->iters[pass] = po.iters, st->subrounds[pass] = po.subrounds;
+  // split-all ablation: every community not marked for refinement is split
+  if (ro.o.split_all) fill_u8(s, L.dS, 1, nl);
   subset_renumber(s, nl, L.C, L.S, L.size, L.dS, L.dR, L.rb, dctl(G));
   CHK(read_ctl(G, s));
   const uint32_t nsplit = G->hctl->misc[0], nref = G->hctl->misc[1];
@@ -648,6 +650,7 @@ leiden_status check_opts(const leiden_opts& o) {
   if (o.tau_re_den == 0 || o.tol_decline == 0 || o.max_iters == 0)
     return fail(LEIDEN_EINVAL, "tau_re_den, tol_decline and max_iters must be > 0");
   if (!(o.tau >= 0.0)) return fail(LEIDEN_EINVAL, "tau must be >= 0");
+  if (o.split_all != 0 && o.split_all != 1) return fail(LEIDEN_EINVAL, "split_all must be 0 or 1");
   if (o.timed_kernel < LEIDEN_KT_NONE || o.timed_kernel > LEIDEN_KT_AGG_BIG)
     return fail(LEIDEN_EINVAL, "unknown timed_kernel");
   return LEIDEN_OK;
@@ -813,7 +816,7 @@ leiden_status leiden_default_opts(leiden_opts* o) {
   o->compute_modularity = 1;
   o->stream = nullptr;
   o->timed_kernel = LEIDEN_KT_NONE;
-  o->pad_ = 0;
+  o->split_all = 0;
   return LEIDEN_OK;
 }
 

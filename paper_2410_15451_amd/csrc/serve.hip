@@ -81,7 +81,7 @@ struct Tenant {
 struct leiden_server {
   int device = 0;
   uint64_t budget = 0, used = 0;
-  std::vector<Tenant> tenants;
+  std::deque<Tenant> tenants;  // deque: workers hold references while graphs are added
   std::deque<uint64_t> queue;  // waiting tickets in arrival order
   std::unordered_map<uint64_t, Request> req;
   uint64_t next_ticket = 1;

@@ -655,3 +655,24 @@ def test_knn_inputs_are_valid_graphs():
     fwd = set(zip(rows.tolist(), g.cols.tolist(), g.w.tolist()))
     assert all((c, r, w) in fwd for r, c, w in fwd)
     assert np.diff(g.offs).min() >= 1
+
+
+def test_split_all_splits_untouched_disconnected_communities(orc):
+    """Section 4.3 compares selective splitting with splitting every community
+    not marked for refinement.  A community that is already disconnected and
+    untouched by the batch is split only under split-all."""
+    # two triangles {0,1,2}, {3,4,5} held in one (disconnected) community, and a
+    # 4-cycle 6-7-8-9 that receives a chord: an intra-community insertion, so
+    # DF marks no vertex and nothing is marked for splitting or refinement
+    g = inputs.csr_from_undirected(10, [0, 0, 1, 3, 3, 4, 6, 7, 8, 6], [1, 2, 2, 4, 5, 5, 7, 8, 9, 9])
+    C = np.array([0, 0, 0, 0, 0, 0, 6, 6, 6, 6], np.uint32)
+    state = orc.initial_state(g, C)
+    ins = np.array([[6, 8, 1]], np.uint32)
+    gt, dw = orc.apply_batch(g, np.zeros((0, 2), np.uint32), ins)
+    sel, _, _, st0 = orc.update(gt, dw, ins, state, "df")
+    assert np.array_equal(sel, C) and st0["split_marked"] == 0 and st0["refine_marked"] == 0
+    alls, _, _, st1 = orc.update(gt, dw, ins, state, "df", split_all=1)
+    # {0,1,2} keeps label 0 (tie on overlap, lower minimum vertex); {3,4,5}
+    # takes the smallest ID that was not a previous label
+    assert list(alls) == [0, 0, 0, 1, 1, 1, 6, 6, 6, 6]
+    assert st1["split_marked"] == 2
