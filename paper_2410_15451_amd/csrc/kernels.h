@@ -101,10 +101,21 @@ size_t scan_tmp_bytes(size_t n);
 void exclusive_scan_u64(hipStream_t s, const uint64_t* in, uint64_t* out, size_t n, uint64_t* total, void* tmp);
 
 // scatter.hip: block-privatised scatter reductions over i < n
-void scatter_add_i64(hipStream_t s, const uint32_t* key, const int64_t* val, uint64_t n, int64_t* out);
-void scatter_add_u32_to_u64(hipStream_t s, const uint32_t* key, const uint32_t* val, uint64_t n, uint64_t* out);
-void scatter_count(hipStream_t s, const uint32_t* key, uint64_t n, uint32_t* out);
-void scatter_min_index(hipStream_t s, const uint32_t* key, uint64_t n, uint32_t* out);
+// Scatter reductions over keys below key_range (the output length).  With a
+// workspace of scatter_ws_bytes(n, key_range) set in tl_scatter_ws, large
+// inputs take the bucketed path (no global atomics).
+struct ScatterWs {
+  void* p;
+  size_t bytes;
+};
+extern thread_local const ScatterWs* tl_scatter_ws;
+size_t scatter_ws_bytes(uint64_t n, uint64_t key_range);
+void scatter_add_i64(hipStream_t s, const uint32_t* key, const int64_t* val, uint64_t n, int64_t* out,
+                     uint64_t key_range);
+void scatter_add_u32_to_u64(hipStream_t s, const uint32_t* key, const uint32_t* val, uint64_t n, uint64_t* out,
+                            uint64_t key_range);
+void scatter_count(hipStream_t s, const uint32_t* key, uint64_t n, uint32_t* out, uint64_t key_range);
+void scatter_min_index(hipStream_t s, const uint32_t* key, uint64_t n, uint32_t* out, uint64_t key_range);
 
 // phases.hip
 void fill_u64(hipStream_t s, uint64_t* p, uint64_t v, size_t n);

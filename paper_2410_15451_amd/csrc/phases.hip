@@ -66,12 +66,12 @@ void launch_row_sums_u32(hipStream_t s, Rows<uint32_t> g, uint32_t n, int64_t* K
 
 void launch_count_members(hipStream_t s, const uint32_t* C, uint32_t n, uint32_t* size) {
   fill_u32(s, size, 0, n);
-  scatter_count(s, C, n, size);
+  scatter_count(s, C, n, size, n);
 }
 
 void launch_sigma_from(hipStream_t s, const uint32_t* C, const int64_t* K, uint32_t n, int64_t* S) {
   fill_i64(s, S, 0, n);
-  scatter_add_i64(s, C, K, n, S);
+  scatter_add_i64(s, C, K, n, S, n);
 }
 
 // ---------------------------------------------------------------------------
@@ -114,7 +114,7 @@ void subset_renumber(hipStream_t s, uint32_t n, uint32_t* C, int64_t*& S, uint32
   fill_u32(s, b.size2, 0, n);
   fill_u8(s, b.dS2, 0, n);
   fill_u8(s, b.dR2, 0, n);
-  scatter_min_index(s, C, n, b.rep);
+  scatter_min_index(s, C, n, b.rep, n);
   hipLaunchKernelGGL(k_move_by_label, dim3(grid_n(n)), dim3(kBlock), 0, s, n, b.rep, S, size, dS, dR, b.S2, b.size2,
                      b.dS2, b.dR2, ctl);
   hipLaunchKernelGGL(k_relabel, dim3(grid_n(n)), dim3(kBlock), 0, s, C, n, b.rep);
@@ -788,8 +788,8 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
               uint32_t* out_len, uint32_t* out_cols, int64_t* out_w, int64_t* Kout, Ctl* ctl) {
   fill_u32(s, b.comm_count, 0, nc);
   fill_u64(s, b.comm_deg, 0, nc);
-  scatter_count(s, C, n, b.comm_count);
-  scatter_add_u32_to_u64(s, C, g.len, n, b.comm_deg);
+  scatter_count(s, C, n, b.comm_count, n);
+  scatter_add_u32_to_u64(s, C, g.len, n, b.comm_deg, n);
   exclusive_scan_u32(s, b.comm_count, b.comm_off, nc, b.total, b.scan_tmp);
   (void)hipMemcpyAsync(b.comm_off + nc, b.total, sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
   fill_u32(s, b.comm_fill, 0, nc);
@@ -886,7 +886,7 @@ void launch_static_relabel(hipStream_t s, const uint32_t* C, uint32_t n, uint32_
                            uint64_t* rank, uint32_t* out, void* scan_tmp, uint64_t* total) {
   if (n == 0) return;
   fill_u32(s, minv, kNone, n);
-  scatter_min_index(s, C, n, minv);
+  scatter_min_index(s, C, n, minv, n);
   hipLaunchKernelGGL(k_first_flag, dim3(grid_n(n)), dim3(kBlock), 0, s, C, n, minv, flag);
   exclusive_scan_u32(s, flag, rank, n, total, scan_tmp);
   hipLaunchKernelGGL(k_rank_label, dim3(grid_n(n)), dim3(kBlock), 0, s, C, n, minv, rank, out);
@@ -957,7 +957,7 @@ __global__ void k_mod_final(const unsigned long long* sig_part, const unsigned l
 void modularity_parts(hipStream_t s, Rows<uint32_t> g, uint32_t n, const uint32_t* C, const int64_t* K, int64_t* Sig,
                       unsigned long long* partials, int nblocks, ModParts* out_dev) {
   fill_i64(s, Sig, 0, n);
-  scatter_add_i64(s, C, K, n, Sig);
+  scatter_add_i64(s, C, K, n, Sig, n);
   hipLaunchKernelGGL(k_mod_sigma, dim3(nblocks), dim3(kBlock), 0, s, g, n, C, partials);
   hipLaunchKernelGGL(k_mod_square, dim3(nblocks), dim3(kBlock), 0, s, n, Sig, partials + nblocks);
   hipLaunchKernelGGL(k_mod_final, dim3(1), dim3(1), 0, s, partials, partials + nblocks, nblocks, out_dev);
@@ -1109,7 +1109,7 @@ void track(hipStream_t s, uint32_t n, const uint32_t* Ccur, const uint32_t* Cpre
   fill_u32(s, b.is_old, 0, n);
   fill_u64(s, (uint64_t*)b.hkeys, ~0ull, slots);
   fill_u64(s, (uint64_t*)b.hvals, 0, slots);
-  scatter_min_index(s, Ccur, n, b.minv);
+  scatter_min_index(s, Ccur, n, b.minv, n);
   hipLaunchKernelGGL(k_track_pairs, dim3(grid_n(n, 1024, 4096)), dim3(kBlock), 0, s, n, Ccur, Cprev, K, b.hkeys,
                      b.hvals, b.hmask, b.is_old);
   fill_i64(s, (int64_t*)b.best_w, -1, n);

@@ -123,6 +123,7 @@ struct leiden_graph {
   Buf bt_src, bt_dst, bt_w, bt_del, bt_slot, bt_rowcnt, bt_rowidx, bt_touched, bt_segcnt, bt_segoff, bt_newlen,
       bt_outoff, bt_ssrc, bt_sdst, bt_sw, bt_sdel, bt_sid, bt_spre, bt_tdst, bt_tw, bt_tdel, bt_mcols, bt_mw, bt_in, bt_oldlen, bt_oldoff, bt_dest;
   Buf rb_cols, rb_w, rb_off, rb_reserve;
+  Buf scatter_ws;  // bucketed scatter reductions over n items
   size_t ws_n = 0, ws_classes = 0;
   uint64_t ws_nnz = 0;
   bool rowcnt_ready = false;
@@ -138,6 +139,7 @@ struct leiden_graph {
 
 namespace lm {
 thread_local KTimer* tl_ktimer = nullptr;
+thread_local const ScatterWs* tl_scatter_ws = nullptr;
 }
 
 namespace {
@@ -156,6 +158,17 @@ struct KtScope {
     tl_ktimer = &G->kt;
   }
   ~KtScope() { tl_ktimer = nullptr; }
+};
+
+// Points the scatter reductions at the handle's workspace for one call.
+struct ScatterScope {
+  ScatterWs ws;
+  explicit ScatterScope(leiden_graph* G) {
+    ws.p = G->scatter_ws.p;
+    ws.bytes = G->scatter_ws.bytes;
+    tl_scatter_ws = ws.p ? &ws : nullptr;
+  }
+  ~ScatterScope() { tl_scatter_ws = nullptr; }
 };
 
 double kt_unit_bytes(int which) {
@@ -272,6 +285,7 @@ leiden_status ensure_workspace(leiden_graph* G, uint32_t classes) {
   CHK(G->partials.reserve(3 * 1024 * u64));
   CHK(G->modparts.reserve(sizeof(ModParts)));
   CHK(G->rb_reserve.reserve(n * u32));
+  CHK(G->scatter_ws.reserve(scatter_ws_bytes(n, n)));
   CHK(G->rb_off.reserve((n + 1) * u64));
   G->ws_n = n;
   G->ws_nnz = nnz;
@@ -1012,6 +1026,7 @@ leiden_status leiden_static(leiden_graph* G, const leiden_opts* opts, uint32_t* 
   if (stats) std::memset(stats, 0, sizeof(*stats));
   KtScope kts(G, o.timed_kernel);
   CHK(ensure_workspace(G, std::max(o.move_classes, o.refine_rounds)));
+  ScatterScope scs(G);
   hipEvent_t e0, e1, e2;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -1091,6 +1106,7 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   KtScope kts(G, o.timed_kernel);
   const uint32_t n = G->n;
   CHK(ensure_workspace(G, std::max(o.move_classes, o.refine_rounds)));
+  ScatterScope scs(G);
   CHK(G->st_C.reserve((size_t)std::max<uint32_t>(n, 1) * 4));
   CHK(G->st_K.reserve((size_t)std::max<uint32_t>(n, 1) * 8));
   CHK(G->st_S.reserve((size_t)std::max<uint32_t>(n, 1) * 8));

@@ -1,8 +1,16 @@
-// Block-privatised scatter reductions.  Community sizes are very skewed
-// (a few communities can hold a large share of all vertices), so a plain
-// atomic per vertex on out[C[i]] serialises on the hot addresses.  Each block
-// first reduces a tile of 1024 items in an LDS hash table and then issues one
-// global atomic per distinct key of the tile.
+// Scatter reductions out[key[i]] (+)= val[i] or min= i.  Community sizes are
+// very skewed (a few communities can hold a large share of all vertices), so
+// a plain atomic per vertex on out[C[i]] serialises on the hot addresses.
+//
+// Small inputs: each block reduces a tile of 1024 items in an LDS hash table
+// and issues one global atomic per distinct key of the tile.
+//
+// Large inputs (a workspace is set): the same tile reduction writes each
+// tile's distinct (key, value) pairs to a staging array instead; the pairs
+// are then counted per key bucket (4096 consecutive keys) and block, the
+// counts scanned, the pairs placed bucket by bucket, and one block per bucket
+// combines its pairs in a dense LDS array and updates its 4096 outputs with
+// plain stores.  No global atomics, every pass streams.
 #include "kernels.h"
 
 namespace lm {
@@ -98,21 +106,226 @@ __global__ __launch_bounds__(kBlock) void k_scatter_min_index(const uint32_t* ke
   }
 }
 
-void scatter_add_i64(hipStream_t s, const uint32_t* key, const int64_t* val, uint64_t n, int64_t* out) {
-  if (n) hipLaunchKernelGGL((k_scatter_add<int64_t, int64_t>), dim3(grid_tiles(n)), dim3(kBlock), 0, s, key, val, n, out);
+// ---------------------------------------------------------------------------
+// Bucketed form.  Op::kMin: value = item index, combine = min; otherwise sum.
+// ---------------------------------------------------------------------------
+constexpr int kBkBits = 12;
+constexpr uint32_t kBkKeys = 1u << kBkBits;
+constexpr int kBkBlocks = 256;  // blocks of the counting and placing passes
+constexpr uint64_t kBkMinItems = 1u << 18;
+
+enum class Op { kSum, kCount, kMin };
+
+// Phase A: tile t's distinct pairs go to stage[t * kScTile ...], their count
+// to tile_cnt[t].
+template <Op OP, typename V>
+__global__ __launch_bounds__(kBlock) void k_bk_tiles(const uint32_t* key, const V* val, uint64_t n, uint32_t* sk,
+                                                     unsigned long long* sv, uint32_t* tile_cnt) {
+  __shared__ uint32_t hk[kScSlots];
+  __shared__ unsigned long long hv[kScSlots];
+  __shared__ unsigned int used;
+  const uint64_t ntiles = (n + kScTile - 1) / kScTile;
+  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const uint64_t base = t * kScTile;
+    for (int q = threadIdx.x; q < kScSlots; q += kBlock) {
+      hk[q] = kNone;
+      hv[q] = OP == Op::kMin ? ~0ull : 0ull;
+    }
+    if (threadIdx.x == 0) used = 0;
+    __syncthreads();
+    for (int q = threadIdx.x; q < kScTile; q += kBlock) {
+      const uint64_t i = base + q;
+      if (i >= n) continue;
+      const uint32_t k = key[i];
+      uint32_t h = slot_hash(k, kScSlots - 1);
+      while (true) {
+        const uint32_t o = atomicCAS(&hk[h], kNone, k);
+        if (o == kNone || o == k) break;
+        h = (h + 1) & (kScSlots - 1);
+      }
+      if (OP == Op::kMin)
+        atomicMin(&hv[h], (unsigned long long)i);
+      else if (OP == Op::kCount)
+        atomicAdd(&hv[h], 1ull);
+      else
+        atomicAdd(&hv[h], (unsigned long long)val[i]);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < kScSlots; q += kBlock) {
+      const uint32_t k = hk[q];
+      if (k == kNone) continue;
+      const unsigned int pos = atomicAdd(&used, 1u);
+      sk[base + pos] = k;
+      sv[base + pos] = hv[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) tile_cnt[t] = used;
+    __syncthreads();
+  }
 }
 
-void scatter_add_u32_to_u64(hipStream_t s, const uint32_t* key, const uint32_t* val, uint64_t n, uint64_t* out) {
-  if (n)
-    hipLaunchKernelGGL((k_scatter_add<uint32_t, uint64_t>), dim3(grid_tiles(n)), dim3(kBlock), 0, s, key, val, n, out);
+// Phases B and D share the partition of tiles over kBkBlocks blocks.
+__device__ inline void bk_tile_range(uint64_t ntiles, uint64_t* t0, uint64_t* t1) {
+  const uint64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+  *t0 = min(ntiles, (uint64_t)blockIdx.x * per);
+  *t1 = min(ntiles, *t0 + per);
 }
 
-void scatter_count(hipStream_t s, const uint32_t* key, uint64_t n, uint32_t* out) {
-  if (n) hipLaunchKernelGGL(k_scatter_count<uint32_t>, dim3(grid_tiles(n)), dim3(kBlock), 0, s, key, n, out);
+// Phase B: mat[bucket * kBkBlocks + block] = pairs of that bucket in the block's tiles.
+__global__ __launch_bounds__(kBlock) void k_bk_count(const uint32_t* sk, const uint32_t* tile_cnt, uint64_t ntiles,
+                                                     uint32_t nb, uint32_t* mat) {
+  extern __shared__ unsigned int hist[];
+  for (uint32_t b = threadIdx.x; b < nb; b += kBlock) hist[b] = 0;
+  __syncthreads();
+  uint64_t t0, t1;
+  bk_tile_range(ntiles, &t0, &t1);
+  for (uint64_t t = t0; t < t1; ++t) {
+    const uint32_t c = tile_cnt[t];
+    for (uint32_t q = threadIdx.x; q < c; q += kBlock) atomicAdd(&hist[sk[t * kScTile + q] >> kBkBits], 1u);
+  }
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < nb; b += kBlock) mat[(size_t)b * kBkBlocks + blockIdx.x] = hist[b];
 }
 
-void scatter_min_index(hipStream_t s, const uint32_t* key, uint64_t n, uint32_t* out) {
-  if (n) hipLaunchKernelGGL(k_scatter_min_index, dim3(grid_tiles(n)), dim3(kBlock), 0, s, key, n, out);
+// Phase D: place the pairs bucket by bucket.
+__global__ __launch_bounds__(kBlock) void k_bk_place(const uint32_t* sk, const unsigned long long* sv,
+                                                     const uint32_t* tile_cnt, uint64_t ntiles, uint32_t nb,
+                                                     const uint64_t* off, uint32_t* bk, unsigned long long* bv) {
+  extern __shared__ unsigned int cur[];
+  for (uint32_t b = threadIdx.x; b < nb; b += kBlock) cur[b] = (unsigned int)off[(size_t)b * kBkBlocks + blockIdx.x];
+  __syncthreads();
+  uint64_t t0, t1;
+  bk_tile_range(ntiles, &t0, &t1);
+  for (uint64_t t = t0; t < t1; ++t) {
+    const uint32_t c = tile_cnt[t];
+    for (uint32_t q = threadIdx.x; q < c; q += kBlock) {
+      const uint32_t k = sk[t * kScTile + q];
+      const unsigned int pos = atomicAdd(&cur[k >> kBkBits], 1u);
+      bk[pos] = k;
+      bv[pos] = sv[t * kScTile + q];
+    }
+  }
+}
+
+// Phase E: one block per bucket combines its pairs densely and updates out.
+template <Op OP, typename O>
+__global__ __launch_bounds__(kBlock) void k_bk_reduce(const uint32_t* bk, const unsigned long long* bv,
+                                                      const uint64_t* off, const uint64_t* total, uint32_t nb,
+                                                      uint64_t key_range, O* out) {
+  __shared__ unsigned long long acc[kBkKeys];
+  for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    for (uint32_t q = threadIdx.x; q < kBkKeys; q += kBlock) acc[q] = OP == Op::kMin ? ~0ull : 0ull;
+    __syncthreads();
+    const uint64_t lo = off[(size_t)b * kBkBlocks];
+    const uint64_t hi = b + 1 < nb ? off[(size_t)(b + 1) * kBkBlocks] : *total;
+    for (uint64_t x = lo + threadIdx.x; x < hi; x += kBlock) {
+      const uint32_t k = bk[x] & (kBkKeys - 1);
+      if (OP == Op::kMin)
+        atomicMin(&acc[k], bv[x]);
+      else
+        atomicAdd(&acc[k], bv[x]);
+    }
+    __syncthreads();
+    const uint64_t k0 = (uint64_t)b << kBkBits;
+    for (uint32_t q = threadIdx.x; q < kBkKeys; q += kBlock) {
+      const uint64_t k = k0 + q;
+      if (k >= key_range) break;
+      const unsigned long long a = acc[q];
+      if (OP == Op::kMin) {
+        if (a != ~0ull && (O)a < out[k]) out[k] = (O)a;
+      } else if (a) {
+        out[k] = (O)((unsigned long long)out[k] + a);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Workspace layout for n items and keys below key_range.
+struct BkLayout {
+  uint64_t ntiles;
+  uint32_t nb;
+  size_t o_sk, o_sv, o_tc, o_bk, o_bv, o_mat, o_off, o_tot, o_tmp, bytes;
+};
+
+BkLayout bk_layout(uint64_t n, uint64_t key_range) {
+  BkLayout L;
+  L.ntiles = (n + kScTile - 1) / kScTile;
+  L.nb = (uint32_t)((key_range + kBkKeys - 1) / kBkKeys);
+  const size_t nm = (size_t)L.nb * kBkBlocks;
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  size_t o = 0;
+  L.o_sk = o;
+  o = al(o + L.ntiles * kScTile * 4);
+  L.o_sv = o;
+  o = al(o + L.ntiles * kScTile * 8);
+  L.o_tc = o;
+  o = al(o + L.ntiles * 4);
+  L.o_bk = o;
+  o = al(o + n * 4);
+  L.o_bv = o;
+  o = al(o + n * 8);
+  L.o_mat = o;
+  o = al(o + nm * 4);
+  L.o_off = o;
+  o = al(o + (nm + 1) * 8);
+  L.o_tot = o;
+  o = al(o + 8);
+  L.o_tmp = o;
+  o = al(o + scan_tmp_bytes(nm) + 64);
+  L.bytes = o;
+  return L;
+}
+
+template <Op OP, typename V, typename O>
+bool bucketed(hipStream_t s, const uint32_t* key, const V* val, uint64_t n, uint64_t key_range, O* out) {
+  const ScatterWs* ws = tl_scatter_ws;
+  if (!ws || n < kBkMinItems || key_range == 0) return false;
+  const BkLayout L = bk_layout(n, key_range);
+  if (L.bytes > ws->bytes || (size_t)L.nb * 4 > 64 * 1024) return false;
+  char* p = (char*)ws->p;
+  uint32_t* sk = (uint32_t*)(p + L.o_sk);
+  unsigned long long* sv = (unsigned long long*)(p + L.o_sv);
+  uint32_t* tc = (uint32_t*)(p + L.o_tc);
+  uint32_t* bk = (uint32_t*)(p + L.o_bk);
+  unsigned long long* bv = (unsigned long long*)(p + L.o_bv);
+  uint32_t* mat = (uint32_t*)(p + L.o_mat);
+  uint64_t* off = (uint64_t*)(p + L.o_off);
+  uint64_t* tot = (uint64_t*)(p + L.o_tot);
+  void* tmp = p + L.o_tmp;
+  const size_t lds = (size_t)L.nb * 4;
+  hipLaunchKernelGGL((k_bk_tiles<OP, V>), dim3(std::min<uint64_t>(L.ntiles, 4096)), dim3(kBlock), 0, s, key, val, n,
+                     sk, sv, tc);
+  hipLaunchKernelGGL(k_bk_count, dim3(kBkBlocks), dim3(kBlock), lds, s, sk, tc, L.ntiles, L.nb, mat);
+  exclusive_scan_u32(s, mat, off, (size_t)L.nb * kBkBlocks, tot, tmp);
+  hipLaunchKernelGGL(k_bk_place, dim3(kBkBlocks), dim3(kBlock), lds, s, sk, sv, tc, L.ntiles, L.nb, off, bk, bv);
+  hipLaunchKernelGGL((k_bk_reduce<OP, O>), dim3(std::min<uint32_t>(L.nb, 4096)), dim3(kBlock), 0, s, bk, bv, off,
+                     tot, L.nb, key_range, out);
+  return true;
+}
+
+size_t scatter_ws_bytes(uint64_t n, uint64_t key_range) { return bk_layout(n, key_range).bytes; }
+
+void scatter_add_i64(hipStream_t s, const uint32_t* key, const int64_t* val, uint64_t n, int64_t* out,
+                     uint64_t key_range) {
+  if (!n || bucketed<Op::kSum>(s, key, val, n, key_range, out)) return;
+  hipLaunchKernelGGL((k_scatter_add<int64_t, int64_t>), dim3(grid_tiles(n)), dim3(kBlock), 0, s, key, val, n, out);
+}
+
+void scatter_add_u32_to_u64(hipStream_t s, const uint32_t* key, const uint32_t* val, uint64_t n, uint64_t* out,
+                            uint64_t key_range) {
+  if (!n || bucketed<Op::kSum>(s, key, val, n, key_range, out)) return;
+  hipLaunchKernelGGL((k_scatter_add<uint32_t, uint64_t>), dim3(grid_tiles(n)), dim3(kBlock), 0, s, key, val, n, out);
+}
+
+void scatter_count(hipStream_t s, const uint32_t* key, uint64_t n, uint32_t* out, uint64_t key_range) {
+  if (!n || bucketed<Op::kCount, uint32_t>(s, key, nullptr, n, key_range, out)) return;
+  hipLaunchKernelGGL(k_scatter_count<uint32_t>, dim3(grid_tiles(n)), dim3(kBlock), 0, s, key, n, out);
+}
+
+void scatter_min_index(hipStream_t s, const uint32_t* key, uint64_t n, uint32_t* out, uint64_t key_range) {
+  if (!n || bucketed<Op::kMin, uint32_t>(s, key, nullptr, n, key_range, out)) return;
+  hipLaunchKernelGGL(k_scatter_min_index, dim3(grid_tiles(n)), dim3(kBlock), 0, s, key, n, out);
 }
 
 }  // namespace lm
