@@ -31,7 +31,11 @@ stand in for them):
     the 32 nearest points of every point, of which 15 chosen uniformly become
     its neighbours; symmetrised by union; weight
     clamp(1 + floor(100 exp(-d^2 / D)), 1, 100) with D the median neighbour d^2;
-    many such graphs with vertex counts log-uniform in a range.
+    many such graphs with vertex counts log-uniform in a range;
+  * temporal stream (stands in for the SNAP temporal graphs of the paper's
+    real-world experiment): the distinct undirected edges of an R-MAT graph in
+    a seeded random arrival order; the first 90% form the initial graph and
+    the rest arrive as consecutive insertion batches.
 """
 from __future__ import annotations
 
@@ -279,3 +283,20 @@ def knn_forest(count: int, n_min: int = 1000, n_max: int = 200000, seed: int = B
     rng = rng_for(seed)
     ns = np.round(np.exp(rng.uniform(np.log(n_min), np.log(n_max), count))).astype(np.int64)
     return [knn_graph(int(x), seed=seed + 1 + i) for i, x in enumerate(ns)]
+
+
+def temporal_stream(scale: int, seed: int = BASE_SEED + 7, preload: float = 0.9):
+    """(initial Csr with the first `preload` share of the edges, remaining
+    edges as uint32[m, 3] insertions (u, v, 1) in arrival order)."""
+    g = rmat(scale, seed=seed)
+    keys = g.undirected_keys()
+    order = rng_for(seed + 1).permutation(keys.shape[0])
+    keys = keys[order]
+    k0 = int(round(preload * keys.shape[0]))
+    first = np.sort(keys[:k0])
+    g0 = csr_from_undirected(g.n, (first >> np.uint64(32)).astype(np.uint32),
+                             (first & np.uint64(0xFFFFFFFF)).astype(np.uint32))
+    rest = keys[k0:]
+    ins = np.stack([(rest >> np.uint64(32)).astype(np.uint32), (rest & np.uint64(0xFFFFFFFF)).astype(np.uint32),
+                    np.ones(rest.shape[0], np.uint32)], axis=1)
+    return g0, ins

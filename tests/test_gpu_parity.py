@@ -381,3 +381,12 @@ def test_split_all_ablation(lm, orc):
         assert np.array_equal(r.membership, C1) and r.q == q1, bi
         assert r.stats["split_marked"] == st1["split_marked"], (r.stats["split_marked"], st1["split_marked"])
         cur = gt
+
+
+def test_temporal_replay_insertions(lm, orc):
+    """Consecutive insertion-only batches on a preloaded temporal stream (the
+    cumulative DeltaSigma carries across batches), against the oracle."""
+    g0, stream = inputs.temporal_stream(12)
+    B = 200
+    batches = [(np.zeros((0, 2), np.uint32), stream[k * B:(k + 1) * B]) for k in range(12)]
+    _run_updates(lm, orc, g0, batches, "df")

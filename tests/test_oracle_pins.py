@@ -676,3 +676,16 @@ def test_split_all_splits_untouched_disconnected_communities(orc):
     # takes the smallest ID that was not a previous label
     assert list(alls) == [0, 0, 0, 1, 1, 1, 6, 6, 6, 6]
     assert st1["split_marked"] == 2
+
+
+def test_temporal_stream_partitions_the_edges():
+    """The temporal stream's preload and arrivals together are exactly the
+    source graph's edges, each once."""
+    g0, stream = inputs.temporal_stream(10, seed=5)
+    full = inputs.rmat(10, seed=5)
+    k0 = g0.undirected_keys()
+    ks = (stream[:, 0].astype(np.uint64) << np.uint64(32)) | stream[:, 1].astype(np.uint64)
+    both = np.sort(np.concatenate([k0, ks]))
+    assert np.array_equal(both, full.undirected_keys())
+    assert np.all(stream[:, 0] < stream[:, 1]) and np.all(stream[:, 2] == 1)
+    assert abs(k0.shape[0] - 0.9 * both.shape[0]) <= 1
