@@ -419,8 +419,9 @@ int batch_prepare(hipStream_t s, uint32_t n, const uint32_t* del, uint64_t n_del
   const uint64_t ne = 2 * nb;
   if (nb)
     hipLaunchKernelGGL(k_expand, dim3(grid_n(nb)), dim3(kBlock), 0, s, del, n_del, ins, n_ins, n, b, ctl);
-  unsigned int hv[2] = {0, 0};
-  (void)hipMemcpyAsync(hv, &ctl->error, sizeof(hv), hipMemcpyDeviceToHost, s);  // error, touched
+  unsigned int* hv = (unsigned int*)pinned_stage(8);
+  if (!hv) return -100;
+  (void)hipMemcpyAsync(hv, &ctl->error, 2 * sizeof(unsigned int), hipMemcpyDeviceToHost, s);  // error, touched
   if (hipStreamSynchronize(s) != hipSuccess) return -100;
   const uint64_t nt = hv[1];
   *n_touched_host = nt;
@@ -449,10 +450,11 @@ int batch_validate(hipStream_t s, Rows<uint32_t> g, uint32_t n, uint64_t n_entri
   (void)n_touched;
   if (n_entries)
     hipLaunchKernelGGL(k_validate, dim3(grid_n(n_entries)), dim3(kBlock), 0, s, n_entries, g, b, ctl);
-  unsigned int err = 0;
-  (void)hipMemcpyAsync(&err, &ctl->error, sizeof(err), hipMemcpyDeviceToHost, s);
+  unsigned int* err = (unsigned int*)pinned_stage(4);
+  if (!err) return -100;
+  (void)hipMemcpyAsync(err, &ctl->error, sizeof(unsigned int), hipMemcpyDeviceToHost, s);
   if (hipStreamSynchronize(s) != hipSuccess) return -100;
-  return (int)err;
+  return (int)*err;
 }
 
 int batch_merge(hipStream_t s, int64_t* start, uint32_t* len, uint32_t* cap, uint32_t* cols, uint32_t* w,
@@ -463,7 +465,8 @@ int batch_merge(hipStream_t s, int64_t* start, uint32_t* len, uint32_t* cap, uin
   exclusive_scan_u32(s, b.new_len, b.out_off, nt, b.total, b.scan_tmp);
   hipLaunchKernelGGL(k_old_len, dim3(grid_n(nt)), dim3(kBlock), 0, s, nt, len, b);
   exclusive_scan_u32(s, b.old_len, b.old_off, nt, b.total + 1, b.scan_tmp);
-  unsigned long long hv[4] = {0, 0, 0, 0};  // need, top, merged total, old total
+  unsigned long long* hv = (unsigned long long*)pinned_stage(32);  // need, top, merged total, old total
+  if (!hv) return -100;
   (void)hipMemcpyAsync(&hv[0], &ctl->overflow_need, sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
   (void)hipMemcpyAsync(&hv[1], edge_top, sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
   (void)hipMemcpyAsync(&hv[2], b.total, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);

@@ -97,6 +97,9 @@ void fill_i64(hipStream_t s, int64_t* p, int64_t v, size_t n);
 void iota_u32(hipStream_t s, uint32_t* p, size_t n);
 // exclusive scan of n values (u32 in, u64 out); writes the total to *total (device) if non-null
 void exclusive_scan_u32(hipStream_t s, const uint32_t* in, uint64_t* out, size_t n, uint64_t* total, void* tmp);
+// Pinned host memory of at least `bytes` owned by the calling thread (NULL on
+// failure); valid until its next call on this thread.
+void* pinned_stage(size_t bytes);
 size_t scan_tmp_bytes(size_t n);
 void exclusive_scan_u64(hipStream_t s, const uint64_t* in, uint64_t* out, size_t n, uint64_t* total, void* tmp);
 

@@ -446,19 +446,21 @@ int hub_layout(hipStream_t s, const uint32_t* len, uint32_t nl, uint32_t hub_abo
   hipLaunchKernelGGL(k_clear_misc6, dim3(1), dim3(1), 0, s, ctl);
   hipLaunchKernelGGL(k_hub_list, dim3(grid_for(nl, kBlock, 4096)), dim3(kBlock), 0, s, len, nl, hub_above, h.list,
                      ctl);
-  unsigned int cnt = 0;
-  if (hipMemcpyAsync(&cnt, &ctl->misc[6], sizeof(cnt), hipMemcpyDeviceToHost, s) != hipSuccess ||
+  unsigned int* pc = (unsigned int*)pinned_stage(4);
+  if (!pc || hipMemcpyAsync(pc, &ctl->misc[6], sizeof(unsigned int), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return -1;
+  const unsigned int cnt = *pc;
   *count_out = cnt;
   *slots_out = 0;
   if (cnt == 0) return 0;
   hipLaunchKernelGGL(k_hub_sizes, dim3(grid_for(cnt, kBlock, 1024)), dim3(kBlock), 0, s, len, cnt, h);
   exclusive_scan_u64(s, h.size_tmp, h.off, cnt, total_dev, scan_tmp);
-  uint64_t slots = 0;
-  if (hipMemcpyAsync(&slots, total_dev, sizeof(slots), hipMemcpyDeviceToHost, s) != hipSuccess ||
+  uint64_t* ps = (uint64_t*)pinned_stage(8);
+  if (!ps || hipMemcpyAsync(ps, total_dev, sizeof(uint64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return -1;
+  const uint64_t slots = *ps;
   *slots_out = slots;
   return 0;
 }

@@ -3,6 +3,8 @@
 // dendrogram lookup, aggregation (Alg. 9), modularity (Eq. 1), static output
 // labels and community tracking (Alg. 12).  All are O(n) or O(|E|) sweeps with
 // integer atomics, so their results do not depend on thread timing.
+#include <cstring>
+
 #include "kernels.h"
 
 namespace lm {
@@ -808,18 +810,23 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
                      b.comm_off, b.small_lists + (size_t)nc, &ctl->misc[3], (const uint64_t*)out_start, out_len,
                      out_cols, out_w, Kout);
   // big communities: plan global tables on the host
-  unsigned int nbig = 0;
-  (void)hipMemcpyAsync(&nbig, &ctl->misc[4], sizeof(nbig), hipMemcpyDeviceToHost, s);
+  unsigned int* pn = (unsigned int*)pinned_stage(4);
+  if (!pn) return -1;
+  (void)hipMemcpyAsync(pn, &ctl->misc[4], sizeof(unsigned int), hipMemcpyDeviceToHost, s);
   if (hipStreamSynchronize(s) != hipSuccess) return -1;
+  const unsigned int nbig = *pn;
   if (nbig == 0) return 0;
   const uint32_t* big = b.small_lists + 2 * (size_t)nc;
   hipLaunchKernelGGL(k_big_info, dim3(grid_n(nbig)), dim3(kBlock), 0, s, big, &ctl->misc[4], b.comm_off, b.cap_off,
                      b.big_info);
-  std::vector<uint64_t> info(3 * (size_t)nbig);
-  std::vector<uint32_t> ids(nbig);
-  (void)hipMemcpyAsync(info.data(), b.big_info, sizeof(uint64_t) * 3 * nbig, hipMemcpyDeviceToHost, s);
-  (void)hipMemcpyAsync(ids.data(), big, sizeof(uint32_t) * nbig, hipMemcpyDeviceToHost, s);
+  const size_t ib = sizeof(uint64_t) * 3 * nbig, idb = sizeof(uint32_t) * nbig;
+  char* st = (char*)pinned_stage(ib + idb);
+  if (!st) return -1;
+  (void)hipMemcpyAsync(st, b.big_info, ib, hipMemcpyDeviceToHost, s);
+  (void)hipMemcpyAsync(st + ib, big, idb, hipMemcpyDeviceToHost, s);
   if (hipStreamSynchronize(s) != hipSuccess) return -1;
+  const std::vector<uint64_t> info((const uint64_t*)st, (const uint64_t*)(st + ib));
+  const std::vector<uint32_t> ids((const uint32_t*)(st + ib), (const uint32_t*)(st + ib + idb));
   constexpr uint64_t kMemChunk = 256, kSlotChunk = 4096;
   const uint64_t item_cap = b.item_cap;
   uint32_t first = 0;
@@ -843,9 +850,18 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
       ++last;
     }
     AggItem* di = (AggItem*)b.items;
-    (void)hipMemcpyAsync(b.bigc, rc.data(), sizeof(BigComm) * rc.size(), hipMemcpyHostToDevice, s);
-    (void)hipMemcpyAsync(di, ins.data(), sizeof(AggItem) * ins.size(), hipMemcpyHostToDevice, s);
-    (void)hipMemcpyAsync(di + ins.size(), cmp.data(), sizeof(AggItem) * cmp.size(), hipMemcpyHostToDevice, s);
+    // through pinned memory: the copies queue behind the kernels instead of
+    // each waiting for the stream (the round ends with a synchronisation)
+    const size_t rb = sizeof(BigComm) * rc.size(), ib2 = sizeof(AggItem) * ins.size(),
+                 cb = sizeof(AggItem) * cmp.size();
+    char* hs = (char*)pinned_stage(rb + ib2 + cb);
+    if (!hs) return -1;
+    std::memcpy(hs, rc.data(), rb);
+    std::memcpy(hs + rb, ins.data(), ib2);
+    std::memcpy(hs + rb + ib2, cmp.data(), cb);
+    (void)hipMemcpyAsync(b.bigc, hs, rb, hipMemcpyHostToDevice, s);
+    (void)hipMemcpyAsync(di, hs + rb, ib2, hipMemcpyHostToDevice, s);
+    (void)hipMemcpyAsync(di + ins.size(), hs + rb + ib2, cb, hipMemcpyHostToDevice, s);
     fill_u32(s, b.gkeys, kNone, used);
     fill_u64(s, (uint64_t*)b.gvals, 0, used);
     // the input graph's big communities are timed as LEIDEN_KT_AGG_BIG

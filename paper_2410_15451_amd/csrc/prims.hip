@@ -1,4 +1,6 @@
 // Fill and exclusive-scan primitives.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace lm {
@@ -138,6 +140,37 @@ static void exclusive_scan(hipStream_t s, const T* in, uint64_t* out, size_t n, 
   hipLaunchKernelGGL(k_tile_reduce<T>, dim3(ntiles), dim3(kBlock), 0, s, in, n, sums);
   hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, sums, ntiles, total);
   hipLaunchKernelGGL(k_tile_scan<T>, dim3(ntiles), dim3(kBlock), 0, s, in, n, sums, out);
+}
+
+// Per-thread pinned host buffer for small device-to-host reads: a copy into
+// pageable memory is staged by the runtime and returns only when done, so a
+// few reads in a row cost a round trip each; into pinned memory they queue
+// behind the kernels and one synchronisation covers them all.
+namespace {
+struct PinnedStage {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~PinnedStage() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+thread_local PinnedStage tl_stage;
+}  // namespace
+
+void* pinned_stage(size_t bytes) {
+  if (bytes > tl_stage.bytes) {
+    if (tl_stage.p) (void)hipHostFree(tl_stage.p);
+    tl_stage.p = nullptr;
+    tl_stage.bytes = 0;
+    const size_t want = std::max<size_t>(bytes, 1 << 16);
+    if (hipHostMalloc(&tl_stage.p, want, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      tl_stage.p = nullptr;
+      return nullptr;
+    }
+    tl_stage.bytes = want;
+  }
+  return tl_stage.p;
 }
 
 void exclusive_scan_u32(hipStream_t s, const uint32_t* in, uint64_t* out, size_t n, uint64_t* total, void* tmp) {

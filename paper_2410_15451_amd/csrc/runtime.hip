@@ -352,6 +352,17 @@ leiden_status read_ctl(leiden_graph* G, hipStream_t s) {
   return LEIDEN_OK;
 }
 
+// One small value from device memory through the pinned stage.
+template <typename T>
+leiden_status read_dev(hipStream_t s, T* out, const void* dev) {
+  T* p = (T*)pinned_stage(sizeof(T));
+  if (!p) return fail(LEIDEN_ENOMEM, "pinned staging buffer");
+  HIPCHK(hipMemcpyAsync(p, dev, sizeof(T), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *out = *p;
+  return LEIDEN_OK;
+}
+
 __global__ void k_zero_ctl(Ctl* c) {
   unsigned int* p = (unsigned int*)c;
   for (size_t i = threadIdx.x; i < sizeof(Ctl) / 4; i += blockDim.x) p[i] = 0;
@@ -365,8 +376,9 @@ leiden_status level_bins(leiden_graph* G, hipStream_t s, const uint32_t* len, ui
   unsigned long long* d = G->small.as<unsigned long long>();
   fill_u64(s, (uint64_t*)d, 0, kBins + 1);
   launch_degree_hist(s, len, nl, G->bincfg, d, (unsigned int*)(d + kBins));
-  unsigned long long h[kBins + 1];
-  HIPCHK(hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, s));
+  unsigned long long* h = (unsigned long long*)pinned_stage(sizeof(unsigned long long) * (kBins + 1));
+  if (!h) return fail(LEIDEN_ENOMEM, "pinned staging buffer");
+  HIPCHK(hipMemcpyAsync(h, d, sizeof(unsigned long long) * (kBins + 1), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   for (int b = 0; b < kBins; ++b) bins[b] = h[b];
   *maxdeg = (uint32_t)h[kBins];
@@ -554,8 +566,7 @@ leiden_status next_level(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
   uint64_t* total = G->small.as<uint64_t>() + 64;
   dense_renumber(s, nl, L.C, G->flag.as<uint32_t>(), G->newid.as<uint64_t>(), total, G->scan_tmp.p);
   uint64_t nc = 0;
-  HIPCHK(hipMemcpyAsync(&nc, total, sizeof(nc), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  CHK(read_dev(s, &nc, total));
   launch_lookup(s, G->Ctop.as<uint32_t>(), L.C, G->n);
   Buf& bs = useA ? G->lvA_start : G->lvB_start;
   Buf& bl = useA ? G->lvA_len : G->lvB_len;
@@ -676,11 +687,15 @@ leiden_status modularity_of(leiden_graph* G, hipStream_t s, const uint32_t* C, c
   modularity_parts(s, rows0(G), G->n, C, K, G->sig.as<int64_t>(), G->partials.as<unsigned long long>(), nb, mp);
   unsigned long long* m2d = G->small.as<unsigned long long>() + 128;
   sum_i64(s, K, G->n, m2d);
+  char* st = (char*)pinned_stage(sizeof(ModParts) + 8);
+  if (!st) return fail(LEIDEN_ENOMEM, "pinned staging buffer");
+  HIPCHK(hipMemcpyAsync(st, mp, sizeof(ModParts), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(st + sizeof(ModParts), m2d, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
   ModParts h;
   unsigned long long M2 = 0;
-  HIPCHK(hipMemcpyAsync(&h, mp, sizeof(h), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&M2, m2d, sizeof(M2), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  std::memcpy(&h, st, sizeof(ModParts));
+  std::memcpy(&M2, st + sizeof(ModParts), 8);
   if (M2 == 0) {
     *q = 0.0;
     return LEIDEN_OK;
@@ -713,8 +728,7 @@ leiden_status rebuild(leiden_graph* G, hipStream_t s, const uint32_t* reserve) {
   CHK(G->rb_off.reserve((uint64_t)(n + 1) * 8));
   rebuild_caps(s, n, G->g.len, reserve, G->slack, G->g.cap, G->rb_off.as<uint64_t>(), G->scan_tmp.p, total);
   uint64_t tot = 0;
-  HIPCHK(hipMemcpyAsync(&tot, total, sizeof(tot), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  CHK(read_dev(s, &tot, total));
   const uint64_t cap = tot + tot / 8 + 4096;
   Buf nc, nw;
   CHK(nc.reserve(cap * 4));
@@ -762,8 +776,7 @@ leiden_status probe_decide(leiden_graph* G, hipStream_t s, const leiden_opts& o,
   unsigned long long* m2d = G->small.as<unsigned long long>() + 128;
   sum_i64(s, L.K, n, m2d);
   unsigned long long M2 = 0;
-  HIPCHK(hipMemcpyAsync(&M2, m2d, 8, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  CHK(read_dev(s, &M2, m2d));
   const QConst qc = make_qconst(M2 ? M2 : 1);
   DecideParams<uint32_t> dp{};
   dp.g = rows0(G);
@@ -1043,8 +1056,7 @@ leiden_status leiden_static(leiden_graph* G, const leiden_opts* opts, uint32_t* 
   unsigned long long* m2d = G->small.as<unsigned long long>() + 128;
   sum_i64(s, L.K, n, m2d);
   unsigned long long M2 = 0;
-  HIPCHK(hipMemcpyAsync(&M2, m2d, 8, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  CHK(read_dev(s, &M2, m2d));
   RunOpts ro{o, false, 0, nullptr, true};
   CHK(run_leiden(G, s, L, ro, M2, stats));
   // dense output labels by minimum vertex; new state (C, K, Sigma, DeltaSigma = 0)
@@ -1147,8 +1159,7 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
     unsigned int* fl = (unsigned int*)(G->small.as<uint64_t>() + 300);
     label_check(s, pm, G->has_state ? Cprev : nullptr, n, fl);
     unsigned int f = 0;
-    HIPCHK(hipMemcpyAsync(&f, fl, 4, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    CHK(read_dev(s, &f, fl));
     if (f & 1) return fail(LEIDEN_EINVAL, "prev_membership has a label >= n");
     if (f & 2) restart = true;
     if (restart) HIPCHK(hipMemcpyAsync(Cprev, pm, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
@@ -1208,8 +1219,7 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
       if (rc == 0) break;
       if (rc < 0) return fail(LEIDEN_EDEVICE, "batch merge failed");
       // short of merge scratch or overflow room
-      HIPCHK(hipMemcpyAsync(&mneed, bb.total, 8, hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
+      CHK(read_dev(s, &mneed, bb.total));
       if (mneed > bb.mcap) {
         CHK(G->bt_mcols.reserve(mneed * 4 + 4096));
         CHK(G->bt_mw.reserve(mneed * 4 + 4096));
@@ -1263,8 +1273,7 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   unsigned long long* m2d = G->small.as<unsigned long long>() + 128;
   sum_i64(s, L.K, n, m2d);
   unsigned long long M2 = 0;
-  HIPCHK(hipMemcpyAsync(&M2, m2d, 8, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  CHK(read_dev(s, &M2, m2d));
   // vertex marking (first pass): the first unprocessed list goes to next_list
   RunOpts ro{o, true, (int)mode, nullptr, false};
   const uint32_t first_stamp = G->stamp + 1;
@@ -1369,8 +1378,7 @@ leiden_status leiden_modularity(leiden_graph* G, const uint32_t* membership, int
   unsigned int* fl = (unsigned int*)(G->small.as<uint64_t>() + 300);
   label_check(s, C, nullptr, n, fl);
   unsigned int f = 0;
-  HIPCHK(hipMemcpyAsync(&f, fl, 4, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  CHK(read_dev(s, &f, fl));
   if (f & 1) return fail(LEIDEN_EINVAL, "membership has a label >= n");
   int64_t* K = G->K.as<int64_t>();
   launch_row_sums_u32(s, rows0(G), n, K);
