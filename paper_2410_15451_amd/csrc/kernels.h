@@ -75,8 +75,10 @@ struct ApplyParams {
 void launch_distribute(hipStream_t s, const uint32_t* in_list, const unsigned int* in_count, uint32_t n_upper,
                        uint32_t li, uint32_t P, uint32_t stamp, uint32_t* pend_mark, uint32_t* cls_lists,
                        size_t stride, Ctl* ctl);
+// hub_items (may be NULL): hubs also queue their row chunks for the hub kernels
 void launch_bin(hipStream_t s, const uint32_t* list, const unsigned int* count, uint32_t n_upper, const uint32_t* len,
-                const uint8_t* in_range, uint32_t* bin_lists, size_t stride, const BinCfg& cfg, Ctl* ctl);
+                const uint8_t* in_range, uint32_t* bin_lists, size_t stride, const BinCfg& cfg,
+                unsigned long long* hub_items, Ctl* ctl);
 // maxdeg: largest degree of the level (sizes the hub kernels)
 template <typename W, bool REFINE>
 void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, size_t stride, unsigned int* bin_counts,

@@ -50,9 +50,14 @@ __global__ __launch_bounds__(kBlock) void k_distribute(const uint32_t* in_list, 
 // (Delta-screening, first pass) and vertices without entries are processed
 // without a decision.
 // ---------------------------------------------------------------------------
+// Hub vertices also queue their row chunks as work items of the hub kernels
+// (hub_items, when given).
+constexpr uint32_t kHubChunk = 2048, kHubSlots = 4096;
+
 __global__ __launch_bounds__(kBlock) void k_bin(const uint32_t* list, const unsigned int* count,
                                                 const uint32_t* len, const uint8_t* in_range, uint32_t* bin_lists,
-                                                size_t stride, BinCfg cfg, Ctl* ctl) {
+                                                size_t stride, BinCfg cfg, unsigned long long* hub_items,
+                                                Ctl* ctl) {
   __shared__ unsigned int lcount[kBins], lbase[kBins];
   const uint32_t cnt = *count;
   for (uint32_t base = blockIdx.x * kBlock; base < cnt; base += gridDim.x * kBlock) {
@@ -74,6 +79,11 @@ __global__ __launch_bounds__(kBlock) void k_bin(const uint32_t* list, const unsi
       lbase[threadIdx.x] = atomicAdd(&ctl->bin_count[threadIdx.x], lcount[threadIdx.x]);
     __syncthreads();
     if (b >= 0) bin_lists[(size_t)b * stride + lbase[b] + pos] = v;
+    if (b == kBins - 1 && hub_items) {
+      const uint32_t nch = (len[v] + kHubChunk - 1) / kHubChunk;
+      const unsigned int first = atomicAdd(&ctl->hub_items, nch);
+      for (uint32_t k = 0; k < nch; ++k) hub_items[first + k] = ((unsigned long long)v << 32) | k;
+    }
     __syncthreads();
   }
 }
@@ -147,18 +157,18 @@ __device__ inline void emit_decision(const DecideParams<W>& p, uint32_t v, uint3
   p.movers[pos] = Mover{v, bc, bdq};
 }
 
-// G lanes per vertex (G <= 64, groups inside one wavefront), T slots each.
+// G lanes per vertex (G <= 64, groups inside one wavefront), T slots each;
+// this block is block `blk` of `nblk` working on the list.
 template <int G, int T, typename W, bool REFINE>
-__global__ __launch_bounds__(kBlock) void k_decide_group(DecideParams<W> p) {
+__device__ inline unsigned long long decide_group_body(const DecideParams<W>& p, const uint32_t* list, uint32_t cnt,
+                                                       uint32_t blk, uint32_t nblk, uint32_t* keys,
+                                                       unsigned long long* vals) {
   constexpr int GPB = kBlock / G;
-  __shared__ uint32_t keys[GPB * T];
-  __shared__ unsigned long long vals[GPB * T];
   const int g = threadIdx.x / G, lane = threadIdx.x % G;
   uint32_t* tk = keys + g * T;
   unsigned long long* tv = vals + g * T;
-  const uint32_t cnt = *p.count;
   unsigned long long edges = 0;
-  for (uint32_t base = blockIdx.x * GPB; base < cnt; base += gridDim.x * GPB) {
+  for (uint32_t base = blk * GPB; base < cnt; base += nblk * GPB) {
     const uint32_t item = base + g;
     for (int s = lane; s < T; s += G) {
       tk[s] = kNone;
@@ -169,7 +179,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_group(DecideParams<W> p) {
     uint32_t v = 0, d = 0;
     unsigned long long kid = 0;
     if (valid) {
-      v = p.list[item];
+      v = list[item];
       d = p.C[v];
       if (REFINE && p.size[d] != 1) valid = false;  // no longer isolated
     }
@@ -210,6 +220,31 @@ __global__ __launch_bounds__(kBlock) void k_decide_group(DecideParams<W> p) {
     if (valid && lane == 0) emit_decision<W, REFINE>(p, v, d, bdq, bc);
     __syncthreads();
   }
+  return edges;
+}
+
+// The three wavefront bins in one launch: the first n0 blocks take bin 0
+// (8 lanes, 16 slots per vertex), the next n1 bin 1 (32 / 64), the rest
+// bin 2 (64 / 256).
+struct SmallBins {
+  const uint32_t* list[3];
+  const unsigned int* count[3];
+  uint32_t n0, n1, n2;
+};
+
+template <typename W, bool REFINE>
+__global__ __launch_bounds__(kBlock) void k_decide_small(DecideParams<W> p, SmallBins sb) {
+  __shared__ uint32_t keys[1024];
+  __shared__ unsigned long long vals[1024];
+  unsigned long long edges = 0;
+  const uint32_t b = blockIdx.x;
+  if (b < sb.n0)
+    edges = decide_group_body<8, 16, W, REFINE>(p, sb.list[0], *sb.count[0], b, sb.n0, keys, vals);
+  else if (b < sb.n0 + sb.n1)
+    edges = decide_group_body<32, 64, W, REFINE>(p, sb.list[1], *sb.count[1], b - sb.n0, sb.n1, keys, vals);
+  else
+    edges = decide_group_body<64, 256, W, REFINE>(p, sb.list[2], *sb.count[2], b - sb.n0 - sb.n1, sb.n2, keys,
+                                                  vals);
   if (edges) atomicAdd(&p.ctl->edges, edges);
 }
 
@@ -285,20 +320,6 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(DecideParams<W> p) {
 // and clears what it used.  Hubs usually see few distinct communities, so
 // the global atomics per chunk are few.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kHubChunk = 2048, kHubSlots = 4096;
-
-template <typename W, bool REFINE>
-__global__ __launch_bounds__(kBlock) void k_hub_items(DecideParams<W> p) {
-  const uint32_t cnt = *p.count;
-  for (uint32_t h = blockIdx.x * kBlock + threadIdx.x; h < cnt; h += gridDim.x * kBlock) {
-    const uint32_t v = p.list[h];
-    if (REFINE && p.size[p.C[v]] != 1) continue;  // only isolated vertices are refined
-    const uint32_t nch = (p.g.len[v] + kHubChunk - 1) / kHubChunk;
-    const unsigned int base = atomicAdd(&p.ctl->hub_items, nch);
-    for (uint32_t k = 0; k < nch; ++k) p.hub_items[base + k] = ((unsigned long long)v << 32) | k;
-  }
-}
-
 template <typename W, bool REFINE>
 __global__ __launch_bounds__(kBlock) void k_hub_chunk(DecideParams<W> p) {
   __shared__ uint32_t lk[kHubSlots];
@@ -315,6 +336,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_chunk(DecideParams<W> p) {
     const unsigned long long item = p.hub_items[it];
     const uint32_t v = (uint32_t)(item >> 32), k = (uint32_t)item;
     const uint32_t d = p.C[v];
+    if (REFINE && p.size[d] != 1) continue;  // block-uniform: only isolated vertices are refined
     const uint32_t hi = p.hub_idx[v];
     const int64_t s0 = p.g.start[v];
     const uint32_t L = p.g.len[v];
@@ -621,9 +643,10 @@ void launch_distribute(hipStream_t s, const uint32_t* in_list, const unsigned in
 }
 
 void launch_bin(hipStream_t s, const uint32_t* list, const unsigned int* count, uint32_t n_upper, const uint32_t* len,
-                const uint8_t* in_range, uint32_t* bin_lists, size_t stride, const BinCfg& cfg, Ctl* ctl) {
+                const uint8_t* in_range, uint32_t* bin_lists, size_t stride, const BinCfg& cfg,
+                unsigned long long* hub_items, Ctl* ctl) {
   hipLaunchKernelGGL(k_bin, dim3(grid_for(n_upper, kBlock, 4096)), dim3(kBlock), 0, s, list, count, len, in_range,
-                     bin_lists, stride, cfg, ctl);
+                     bin_lists, stride, cfg, hub_items, ctl);
 }
 
 template <typename W, bool REFINE>
@@ -631,24 +654,25 @@ void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, si
                        const uint64_t* bin_upper, uint32_t maxdeg) {
   // bin 0: 8 lanes / 16 slots, bin 1: 32 / 64, bin 2: 64 / 256,
   // bin 3: block / 1024, bin 4: block / 4096, bin 5: hubs (all blocks per hub)
-  for (int b = 0; b < kBins; ++b) {
+  // bins 0-2 in one launch
+  {
+    SmallBins sb{};
+    uint32_t* nb[3] = {&sb.n0, &sb.n1, &sb.n2};
+    const int lanes[3] = {8, 32, 64};
+    for (int b = 0; b < 3; ++b) {
+      sb.list[b] = bin_lists + (size_t)b * stride;
+      sb.count[b] = bin_counts + b;
+      *nb[b] = bin_upper[b] ? (uint32_t)grid_for(bin_upper[b], kBlock / lanes[b], 2048) : 0;
+    }
+    const uint32_t total = sb.n0 + sb.n1 + sb.n2;
+    if (total) hipLaunchKernelGGL((k_decide_small<W, REFINE>), dim3(total), dim3(kBlock), 0, s, p, sb);
+  }
+  for (int b = 3; b < kBins; ++b) {
     if (bin_upper[b] == 0) continue;
     DecideParams<W> q = p;
     q.list = bin_lists + (size_t)b * stride;
     q.count = bin_counts + b;
     switch (b) {
-      case 0:
-        hipLaunchKernelGGL((k_decide_group<8, 16, W, REFINE>), dim3(grid_for(bin_upper[b], kBlock / 8, 2048)),
-                           dim3(kBlock), 0, s, q);
-        break;
-      case 1:
-        hipLaunchKernelGGL((k_decide_group<32, 64, W, REFINE>), dim3(grid_for(bin_upper[b], kBlock / 32, 2048)),
-                           dim3(kBlock), 0, s, q);
-        break;
-      case 2:
-        hipLaunchKernelGGL((k_decide_group<64, 256, W, REFINE>), dim3(grid_for(bin_upper[b], kBlock / 64, 2048)),
-                           dim3(kBlock), 0, s, q);
-        break;
       case 3:
         hipLaunchKernelGGL((k_decide_block<1024, W, REFINE>), dim3(grid_for(bin_upper[b], 1, 2048)), dim3(kBlock), 0,
                            s, q);
@@ -658,7 +682,6 @@ void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, si
                            s, q);
         break;
       default: {
-        hipLaunchKernelGGL((k_hub_items<W, REFINE>), dim3(grid_for(bin_upper[b], kBlock, 64)), dim3(kBlock), 0, s, q);
         if (sizeof(W) == 4 && !REFINE) kt_mark(LEIDEN_KT_HUB_INSERT, s);
         hipLaunchKernelGGL((k_hub_chunk<W, REFINE>), dim3(grid_for(bin_upper[b] * (maxdeg / kHubChunk + 1), 1, 1536)),
                            dim3(kBlock), 0, s, q);

@@ -445,7 +445,7 @@ leiden_status local_move(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
     for (uint32_t k = 0; k < P; ++k) {
       launch_subround_reset(s, ctl);
       launch_bin(s, G->cls_lists.as<uint32_t>() + (size_t)k * nl, &ctl->cls_count[k], nl, g.len, in_range,
-                 G->bin_lists.as<uint32_t>(), (size_t)nl, G->bincfg, ctl);
+                 G->bin_lists.as<uint32_t>(), (size_t)nl, G->bincfg, G->hub_items.as<unsigned long long>(), ctl);
       launch_decide_all<W, false>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, maxdeg);
       ApplyParams ap{};
       ap.start = g.start;
@@ -510,7 +510,7 @@ leiden_status refine(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, Lev
   for (uint32_t r = 0; r < R; ++r) {
     launch_subround_reset(s, ctl);
     launch_bin(s, G->cls_lists.as<uint32_t>() + (size_t)r * nl, &ctl->cls_count[r], nl, g.len, nullptr,
-               G->bin_lists.as<uint32_t>(), (size_t)nl, G->bincfg, ctl);
+               G->bin_lists.as<uint32_t>(), (size_t)nl, G->bincfg, G->hub_items.as<unsigned long long>(), ctl);
     dp.colour = r;
     launch_decide_all<W, true>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, maxdeg);
     launch_apply_refine(s, L.C, L.S, L.K, L.size, G->movers.as<Mover>(), ctl, nl);
@@ -530,7 +530,8 @@ leiden_status split(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, Leve
   launch_split_sample<W>(s, g, L.C, lab, list, key, rest, ctl, nl);
   // vertices outside their community's main tree, by degree
   launch_subround_reset(s, ctl);
-  launch_bin(s, rest, &ctl->split_rest, nl, g.len, nullptr, G->bin_lists.as<uint32_t>(), (size_t)nl, G->bincfg, ctl);
+  launch_bin(s, rest, &ctl->split_rest, nl, g.len, nullptr, G->bin_lists.as<uint32_t>(), (size_t)nl, G->bincfg,
+             nullptr, ctl);
   launch_split_union<W>(s, g, L.C, lab, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins);
   launch_split_finish(s, L.C, lab, list, ctl, nl);
   return LEIDEN_OK;
@@ -800,7 +801,7 @@ leiden_status probe_decide(leiden_graph* G, hipStream_t s, const leiden_opts& o,
   for (uint32_t k = 0; k < P; ++k) {
     launch_subround_reset(s, ctl);
     launch_bin(s, G->cls_lists.as<uint32_t>() + (size_t)k * n, &ctl->cls_count[k], n, G->g.len, nullptr,
-               G->bin_lists.as<uint32_t>(), (size_t)n, G->bincfg, ctl);
+               G->bin_lists.as<uint32_t>(), (size_t)n, G->bincfg, G->hub_items.as<unsigned long long>(), ctl);
     launch_decide_all<uint32_t, false>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)n, ctl->bin_count, bins, maxdeg);
   }
   HIPCHK(hipEventRecord(e1, s));
