@@ -32,6 +32,12 @@ struct DecideParams {
   unsigned long long* hub_vals;
   uint32_t* hub_occ;           // per hub (same offsets as the table): claimed slots
   unsigned int* hub_nocc;      // hub index -> claimed slots (kept zero between uses)
+  // pick in segments: per hub and segment the best candidate, and a
+  // completion counter per hub (kept zero between uses)
+  uint32_t pick_segs;
+  double* hub_pdq;
+  uint32_t* hub_pc;
+  unsigned int* hub_done;
   unsigned long long* hub_items;  // (hub vertex, chunk) work items of the current sub-round
 };
 
@@ -75,6 +81,14 @@ struct ApplyParams {
 void launch_distribute(hipStream_t s, const uint32_t* in_list, const unsigned int* in_count, uint32_t n_upper,
                        uint32_t li, uint32_t P, uint32_t stamp, uint32_t* pend_mark, uint32_t* cls_lists,
                        size_t stride, Ctl* ctl);
+// Segments of the hub pick (kernel grid y): enough for the level's longest
+// row at kHubPickSeg claimed slots each, at most kHubPickMaxSegs.
+constexpr uint32_t kHubPickSeg = 4096, kHubPickMaxSegs = 64;
+inline uint32_t hub_pick_segs(uint32_t maxdeg) {
+  const uint32_t s = maxdeg / kHubPickSeg + 1;
+  return s < kHubPickMaxSegs ? s : kHubPickMaxSegs;
+}
+
 // hub_items (may be NULL): hubs also queue their row chunks for the hub kernels
 void launch_bin(hipStream_t s, const uint32_t* list, const unsigned int* count, uint32_t n_upper, const uint32_t* len,
                 const uint8_t* in_range, uint32_t* bin_lists, size_t stride, const BinCfg& cfg,

@@ -400,26 +400,40 @@ __global__ __launch_bounds__(kBlock) void k_hub_chunk(DecideParams<W> p) {
   }
 }
 
+// Pick: the claimed slots of a hub are split into at most gridDim.y segments
+// of at least kHubPickSeg slots; block (x, y) takes segment y of the hubs x,
+// x + gridDim.x, ...  Each segment's
+// best candidate goes to the hub's partial results; the last segment to
+// finish (a completion counter) combines them in segment order, emits the
+// decision and resets the hub's counters.  Every participating block reads
+// the claim count before it counts itself done, so the count is stable
+// until the last one resets it.
 template <typename W, bool REFINE>
 __global__ __launch_bounds__(kBlock) void k_hub_pick(DecideParams<W> p) {
   __shared__ double rdq[kBlock / kWave];
   __shared__ uint32_t rc[kBlock / kWave];
+  __shared__ unsigned int last;
   const uint32_t cnt = *p.count;
+  const uint32_t y = blockIdx.y;
   for (uint32_t h = blockIdx.x; h < cnt; h += gridDim.x) {
     const uint32_t v = p.list[h];
     const uint32_t d = p.C[v];
     if (REFINE && p.size[d] != 1) continue;  // block-uniform; nothing was summed
     const uint32_t hi = p.hub_idx[v];
+    const uint32_t nocc = __atomic_load_n(&p.hub_nocc[hi], __ATOMIC_RELAXED);
+    const uint32_t seg = max(kHubPickSeg, (nocc + gridDim.y - 1) / gridDim.y);
+    const uint32_t nseg = nocc == 0 ? 1 : (nocc + seg - 1) / seg;
+    if (y >= nseg) continue;  // block-uniform; this block takes no part for this hub
     const uint64_t off = p.hub_off[hi];
     uint32_t* tk = p.hub_keys + off;
     unsigned long long* tv = p.hub_vals + off;
     const uint32_t* occ = p.hub_occ + off;
-    const uint32_t nocc = p.hub_nocc[hi];
     const int64_t kid = (int64_t)p.hub_kid[hi];
     const int64_t ki = p.K[v], sd = p.S[d];
     double bdq = -INFINITY;
     uint32_t bc = kNone;
-    for (uint32_t q = threadIdx.x; q < nocc; q += kBlock) {
+    const uint32_t q1 = min(nocc, (y + 1) * seg);
+    for (uint32_t q = y * seg + threadIdx.x; q < q1; q += kBlock) {
       const uint32_t sl = occ[q];
       const uint32_t c = tk[sl];
       const int64_t kic = (int64_t)tv[sl];
@@ -434,9 +448,36 @@ __global__ __launch_bounds__(kBlock) void k_hub_pick(DecideParams<W> p) {
     }
     block_best(bdq, bc, rdq, rc);
     if (threadIdx.x == 0) {
-      p.hub_kid[hi] = 0;
-      p.hub_nocc[hi] = 0;
-      emit_decision<W, REFINE>(p, v, d, bdq, bc);
+      if (nseg == 1) {
+        last = 1;
+      } else {
+        const size_t slot = (size_t)hi * p.pick_segs + y;
+        p.hub_pdq[slot] = bdq;
+        p.hub_pc[slot] = bc;
+        __threadfence();
+        last = atomicAdd(&p.hub_done[hi], 1u) == nseg - 1 ? 1u : 0u;
+        if (last) {
+          __threadfence();
+          bdq = -INFINITY;
+          bc = kNone;
+          for (uint32_t r = 0; r < nseg; ++r) {
+            const size_t sr = (size_t)hi * p.pick_segs + r;
+            const double x = __longlong_as_double(
+                (long long)__atomic_load_n(reinterpret_cast<unsigned long long*>(&p.hub_pdq[sr]), __ATOMIC_RELAXED));
+            const uint32_t xc = __atomic_load_n(&p.hub_pc[sr], __ATOMIC_RELAXED);
+            if (better(x, xc, bdq, bc)) {
+              bdq = x;
+              bc = xc;
+            }
+          }
+          p.hub_done[hi] = 0;
+        }
+      }
+      if (last) {
+        p.hub_kid[hi] = 0;
+        p.hub_nocc[hi] = 0;
+        emit_decision<W, REFINE>(p, v, d, bdq, bc);
+      }
     }
     __syncthreads();
   }
@@ -686,7 +727,8 @@ void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, si
         hipLaunchKernelGGL((k_hub_chunk<W, REFINE>), dim3(grid_for(bin_upper[b] * (maxdeg / kHubChunk + 1), 1, 1536)),
                            dim3(kBlock), 0, s, q);
         if (sizeof(W) == 4 && !REFINE) kt_mark(LEIDEN_KT_HUB_INSERT, s);
-        hipLaunchKernelGGL((k_hub_pick<W, REFINE>), dim3(grid_for(bin_upper[b], 1, 1024)), dim3(kBlock), 0, s, q);
+        hipLaunchKernelGGL((k_hub_pick<W, REFINE>), dim3(grid_for(bin_upper[b], 1, 1024), p.pick_segs),
+                           dim3(kBlock), 0, s, q);
         break;
       }
     }

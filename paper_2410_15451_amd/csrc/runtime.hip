@@ -116,7 +116,7 @@ struct leiden_graph {
   Buf agg_count, agg_off, agg_fill, agg_members, agg_deg, agg_cap, agg_lists, agg_bigcap, agg_tbl, agg_keys, agg_vals,
       agg_items, mark_items;
   Buf hub_keys, hub_vals, hub_list, hub_idx, hub_off, hub_mask, hub_size, hub_kid;
-  Buf hub_items, hub_occ, hub_nocc;
+  Buf hub_items, hub_occ, hub_nocc, hub_pdq, hub_pc, hub_done;
   Buf tr_minv, tr_hk, tr_hv, tr_bw, tr_bv, tr_cw, tr_cb, tr_old, tr_flag, tr_rank, tr_frank, tr_fid, tr_label,
       tr_matched;
   Buf dV, dE, dC, sig, partials, modparts;
@@ -323,6 +323,13 @@ leiden_status setup_hubs(leiden_graph* G, hipStream_t s, const uint32_t* len, ui
     fill_u32(s, G->hub_nocc.as<uint32_t>(), 0, G->hub_nocc.bytes / 4);
   }
   CHK(G->hub_occ.reserve(std::max<uint64_t>(slots, 1) * 4));
+  // segmented pick: per hub up to kHubPickMaxSegs partial results
+  CHK(G->hub_pdq.reserve(hc * kHubPickMaxSegs * 8));
+  CHK(G->hub_pc.reserve(hc * kHubPickMaxSegs * 4));
+  if (G->hub_done.bytes < hc * 4) {
+    CHK(G->hub_done.reserve(hc * 4));
+    fill_u32(s, G->hub_done.as<uint32_t>(), 0, G->hub_done.bytes / 4);
+  }
   if (slots * 4 > G->hub_keys.bytes || slots * 8 > G->hub_vals.bytes) {
     const uint64_t want = slots + slots / 4 + 4096;
     CHK(G->hub_keys.reserve(want * 4));
@@ -344,6 +351,10 @@ void bind_hubs(leiden_graph* G, DecideParams<W>& dp) {
   dp.hub_items = G->hub_items.as<unsigned long long>();
   dp.hub_occ = G->hub_occ.as<uint32_t>();
   dp.hub_nocc = G->hub_nocc.as<unsigned int>();
+  dp.hub_pdq = G->hub_pdq.as<double>();
+  dp.hub_pc = G->hub_pc.as<uint32_t>();
+  dp.hub_done = G->hub_done.as<unsigned int>();
+  dp.pick_segs = 1;  // callers widen it from the level's maximum degree (hub_pick_segs)
 }
 
 leiden_status read_ctl(leiden_graph* G, hipStream_t s) {
@@ -434,6 +445,7 @@ leiden_status local_move(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
   dp.async = async ? 1 : 0;
   dp.dS = ro.dynamic ? L.dS : nullptr;
   bind_hubs(G, dp);
+  dp.pick_segs = hub_pick_segs(maxdeg);
   const uint8_t* in_range = first_pass ? ro.in_range : nullptr;
   for (uint32_t li = 0; li < ro.o.max_iters; ++li) {
     const uint32_t stamp = ++G->stamp;
@@ -507,6 +519,7 @@ leiden_status refine(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, Lev
   dp.ctl = ctl;
   dp.async = async ? 1 : 0;
   bind_hubs(G, dp);
+  dp.pick_segs = hub_pick_segs(maxdeg);
   for (uint32_t r = 0; r < R; ++r) {
     launch_subround_reset(s, ctl);
     launch_bin(s, G->cls_lists.as<uint32_t>() + (size_t)r * nl, &ctl->cls_count[r], nl, g.len, nullptr,
@@ -790,6 +803,7 @@ leiden_status probe_decide(leiden_graph* G, hipStream_t s, const leiden_opts& o,
   dp.movers = G->movers.as<Mover>();
   dp.ctl = ctl;
   bind_hubs(G, dp);
+  dp.pick_segs = hub_pick_segs(maxdeg);
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
