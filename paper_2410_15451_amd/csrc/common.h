@@ -275,6 +275,42 @@ __device__ inline void block_append(uint32_t* list, unsigned int* count, bool pr
   __syncthreads();
 }
 
+// Keyed append of a block's tile.  Every thread of the block calls this
+// (block-uniform control flow) with U (key, value) pairs; key kNone appends
+// nothing, any other key is below nk <= kBlock.  Per key the whole tile
+// reserves one run of that key's list with a single global atomic: all
+// atomics on one address are serialised device-wide, so per-wavefront
+// reservations on a few shared counters cost far more than the writes.
+// scnt[nk] must hold zeros on entry and holds zeros again on return; sbase[nk]
+// is scratch.  list_of(key, list, count) names the key's list and counter.
+template <int U, typename ListOf>
+__device__ inline void tile_append(const uint32_t (&key)[U], const uint32_t (&val)[U], uint32_t nk,
+                                   unsigned int* scnt, unsigned int* sbase, ListOf list_of) {
+  uint32_t off[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) off[u] = key[u] == kNone ? 0u : atomicAdd(&scnt[key[u]], 1u);
+  __syncthreads();
+  if (threadIdx.x < nk) {
+    const unsigned int c = scnt[threadIdx.x];
+    if (c) {
+      uint32_t* list;
+      unsigned int* count;
+      list_of(threadIdx.x, list, count);
+      sbase[threadIdx.x] = atomicAdd(count, c);
+    }
+    scnt[threadIdx.x] = 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (key[u] == kNone) continue;
+    uint32_t* list;
+    unsigned int* count;
+    list_of(key[u], list, count);
+    list[sbase[key[u]] + off[u]] = val[u];
+  }
+}
+
 __host__ __device__ inline uint32_t pow2_at_least(uint32_t x) {
   uint32_t p = 1;
   while (p < x) p <<= 1;

@@ -18,30 +18,34 @@ __global__ void k_clear_misc6(Ctl* ctl) { ctl->misc[6] = 0; }
 // ---------------------------------------------------------------------------
 // Class distribution (start of a local-moving iteration)
 // ---------------------------------------------------------------------------
+constexpr int kDistU = 8;  // list entries per thread of a tile
 __global__ __launch_bounds__(kBlock) void k_distribute(const uint32_t* in_list, const unsigned int* in_count,
                                                        uint32_t n_all, uint32_t li, uint32_t P, uint32_t stamp,
                                                        uint32_t* pend_mark, uint32_t* cls_lists, size_t stride,
                                                        Ctl* ctl) {
-  __shared__ unsigned int lcount[kMaxClasses], lbase[kMaxClasses];
+  __shared__ unsigned int scnt[kMaxClasses], sbase[kMaxClasses];
+  if (threadIdx.x < kMaxClasses) scnt[threadIdx.x] = 0;
+  __syncthreads();
   const uint32_t cnt = in_count ? *in_count : n_all;
-  for (uint32_t base = blockIdx.x * kBlock; base < cnt; base += gridDim.x * kBlock) {
-    if (threadIdx.x < kMaxClasses) lcount[threadIdx.x] = 0;
-    __syncthreads();
-    const uint32_t i = base + threadIdx.x;
-    uint32_t v = 0, k = 0, pos = 0;
-    const bool ok = i < cnt;
-    if (ok) {
-      v = in_list ? in_list[i] : i;
-      k = vertex_class(v, li, P);
-      pend_mark[v] = stamp;
-      pos = atomicAdd(&lcount[k], 1u);
+  constexpr uint32_t tile = kBlock * kDistU;
+  for (uint32_t base = blockIdx.x * tile; base < cnt; base += gridDim.x * tile) {
+    uint32_t key[kDistU], val[kDistU];
+#pragma unroll
+    for (int u = 0; u < kDistU; ++u) {
+      const uint32_t i = base + u * kBlock + threadIdx.x;
+      key[u] = kNone;
+      val[u] = 0;
+      if (i < cnt) {
+        const uint32_t v = in_list ? in_list[i] : i;
+        key[u] = vertex_class(v, li, P);
+        val[u] = v;
+        pend_mark[v] = stamp;
+      }
     }
-    __syncthreads();
-    if (threadIdx.x < P && lcount[threadIdx.x] > 0)
-      lbase[threadIdx.x] = atomicAdd(&ctl->cls_count[threadIdx.x], lcount[threadIdx.x]);
-    __syncthreads();
-    if (ok) cls_lists[(size_t)k * stride + lbase[k] + pos] = v;
-    __syncthreads();
+    tile_append<kDistU>(key, val, P, scnt, sbase, [&](uint32_t k, uint32_t*& list, unsigned int*& count) {
+      list = cls_lists + (size_t)k * stride;
+      count = &ctl->cls_count[k];
+    });
   }
 }
 
@@ -54,37 +58,42 @@ __global__ __launch_bounds__(kBlock) void k_distribute(const uint32_t* in_list, 
 // (hub_items, when given).
 constexpr uint32_t kHubChunk = 2048, kHubSlots = 4096;
 
+constexpr int kBinU = 4;  // list entries per thread of a tile
 __global__ __launch_bounds__(kBlock) void k_bin(const uint32_t* list, const unsigned int* count,
                                                 const uint32_t* len, const uint8_t* in_range, uint32_t* bin_lists,
                                                 size_t stride, BinCfg cfg, unsigned long long* hub_items,
                                                 Ctl* ctl) {
-  __shared__ unsigned int lcount[kBins], lbase[kBins];
+  __shared__ unsigned int scnt[kBins], sbase[kBins];
+  if (threadIdx.x < kBins) scnt[threadIdx.x] = 0;
+  __syncthreads();
   const uint32_t cnt = *count;
-  for (uint32_t base = blockIdx.x * kBlock; base < cnt; base += gridDim.x * kBlock) {
-    if (threadIdx.x < kBins) lcount[threadIdx.x] = 0;
-    __syncthreads();
-    const uint32_t i = base + threadIdx.x;
-    uint32_t v = 0, pos = 0;
-    int b = -1;
-    if (i < cnt) {
-      v = list[i];
-      const uint32_t d = len[v];
-      if (d > 0 && (!in_range || in_range[v])) {
-        b = bin_of_degree(d, cfg);
-        pos = atomicAdd(&lcount[b], 1u);
+  constexpr uint32_t tile = kBlock * kBinU;
+  for (uint32_t base = blockIdx.x * tile; base < cnt; base += gridDim.x * tile) {
+    uint32_t key[kBinU], val[kBinU];
+#pragma unroll
+    for (int u = 0; u < kBinU; ++u) {
+      const uint32_t i = base + u * kBlock + threadIdx.x;
+      key[u] = kNone;
+      val[u] = 0;
+      if (i < cnt) {
+        const uint32_t v = list[i];
+        const uint32_t d = len[v];
+        if (d > 0 && (!in_range || in_range[v])) {
+          const int b = bin_of_degree(d, cfg);
+          key[u] = (uint32_t)b;
+          val[u] = v;
+          if (b == kBins - 1 && hub_items) {
+            const uint32_t nch = (d + kHubChunk - 1) / kHubChunk;
+            const unsigned int first = atomicAdd(&ctl->hub_items, nch);
+            for (uint32_t k = 0; k < nch; ++k) hub_items[first + k] = ((unsigned long long)v << 32) | k;
+          }
+        }
       }
     }
-    __syncthreads();
-    if (threadIdx.x < kBins && lcount[threadIdx.x] > 0)
-      lbase[threadIdx.x] = atomicAdd(&ctl->bin_count[threadIdx.x], lcount[threadIdx.x]);
-    __syncthreads();
-    if (b >= 0) bin_lists[(size_t)b * stride + lbase[b] + pos] = v;
-    if (b == kBins - 1 && hub_items) {
-      const uint32_t nch = (len[v] + kHubChunk - 1) / kHubChunk;
-      const unsigned int first = atomicAdd(&ctl->hub_items, nch);
-      for (uint32_t k = 0; k < nch; ++k) hub_items[first + k] = ((unsigned long long)v << 32) | k;
-    }
-    __syncthreads();
+    tile_append<kBinU>(key, val, kBins, scnt, sbase, [&](uint32_t b, uint32_t*& l, unsigned int*& c) {
+      l = bin_lists + (size_t)b * stride;
+      c = &ctl->bin_count[b];
+    });
   }
 }
 
@@ -141,8 +150,33 @@ __device__ inline void local_move_async(const DecideParams<W>& p, uint32_t v, ui
   p.movers[pos] = Mover{v, c, dq};
 }
 
+// Movers decided by one block gather in LDS and join the mover list a batch
+// at a time: the list's counter sees one atomic per batch, where one per
+// wavefront would queue tens of thousands on a single address per sub-round.
+constexpr uint32_t kMoverStage = 256;
+struct MoverStage {
+  Mover m[kMoverStage];
+  unsigned int n, base;
+};
+
+// Every thread of the block calls this (block-uniform), after a
+// __syncthreads that follows the last push.
+__device__ inline void stage_flush(MoverStage& st, Ctl* ctl, Mover* movers) {
+  const unsigned int n = st.n;
+  if (n == 0) return;
+  if (threadIdx.x == 0) st.base = atomicAdd(&ctl->mover_count, n);
+  __syncthreads();
+  for (uint32_t t = threadIdx.x; t < n; t += kBlock) movers[st.base + t] = st.m[t];
+  __syncthreads();
+  if (threadIdx.x == 0) st.n = 0;
+  __syncthreads();
+}
+
+// st: the block's stage (room for this call guaranteed by the caller), or
+// null to append straight to the global list.
 template <typename W, bool REFINE>
-__device__ inline void emit_decision(const DecideParams<W>& p, uint32_t v, uint32_t d, double bdq, uint32_t bc) {
+__device__ inline void emit_decision(const DecideParams<W>& p, uint32_t v, uint32_t d, double bdq, uint32_t bc,
+                                     MoverStage* st = nullptr) {
   if (bc == kNone || !(bdq > 0.0)) return;
   // two singletons of one class would swap forever: only the higher label moves
   if (!REFINE && p.size[d] == 1 && p.size[bc] == 1 && bc > d) return;
@@ -151,6 +185,10 @@ __device__ inline void emit_decision(const DecideParams<W>& p, uint32_t v, uint3
       refine_move_async(p, v, d, bc);
     else
       local_move_async(p, v, d, bdq, bc);
+    return;
+  }
+  if (st) {
+    st->m[atomicAdd(&st->n, 1u)] = Mover{v, bc, bdq};
     return;
   }
   const unsigned int pos = atomicAdd(&p.ctl->mover_count, 1u);
@@ -162,8 +200,9 @@ __device__ inline void emit_decision(const DecideParams<W>& p, uint32_t v, uint3
 template <int G, int T, typename W, bool REFINE>
 __device__ inline unsigned long long decide_group_body(const DecideParams<W>& p, const uint32_t* list, uint32_t cnt,
                                                        uint32_t blk, uint32_t nblk, uint32_t* keys,
-                                                       unsigned long long* vals) {
+                                                       unsigned long long* vals, MoverStage& st) {
   constexpr int GPB = kBlock / G;
+  static_assert(GPB <= kMoverStage, "one round of decisions must fit the stage");
   const int g = threadIdx.x / G, lane = threadIdx.x % G;
   uint32_t* tk = keys + g * T;
   unsigned long long* tv = vals + g * T;
@@ -217,9 +256,12 @@ __device__ inline unsigned long long decide_group_body(const DecideParams<W>& p,
       }
     }
     group_best<G>(bdq, bc);
-    if (valid && lane == 0) emit_decision<W, REFINE>(p, v, d, bdq, bc);
+    if (valid && lane == 0) emit_decision<W, REFINE>(p, v, d, bdq, bc, &st);
     __syncthreads();
+    if (st.n + GPB > kMoverStage) stage_flush(st, p.ctl, p.movers);
   }
+  __syncthreads();
+  stage_flush(st, p.ctl, p.movers);
   return edges;
 }
 
@@ -236,15 +278,18 @@ template <typename W, bool REFINE>
 __global__ __launch_bounds__(kBlock) void k_decide_small(DecideParams<W> p, SmallBins sb) {
   __shared__ uint32_t keys[1024];
   __shared__ unsigned long long vals[1024];
+  __shared__ MoverStage st;
+  if (threadIdx.x == 0) st.n = 0;
+  __syncthreads();
   unsigned long long edges = 0;
   const uint32_t b = blockIdx.x;
   if (b < sb.n0)
-    edges = decide_group_body<8, 16, W, REFINE>(p, sb.list[0], *sb.count[0], b, sb.n0, keys, vals);
+    edges = decide_group_body<8, 16, W, REFINE>(p, sb.list[0], *sb.count[0], b, sb.n0, keys, vals, st);
   else if (b < sb.n0 + sb.n1)
-    edges = decide_group_body<32, 64, W, REFINE>(p, sb.list[1], *sb.count[1], b - sb.n0, sb.n1, keys, vals);
+    edges = decide_group_body<32, 64, W, REFINE>(p, sb.list[1], *sb.count[1], b - sb.n0, sb.n1, keys, vals, st);
   else
     edges = decide_group_body<64, 256, W, REFINE>(p, sb.list[2], *sb.count[2], b - sb.n0 - sb.n1, sb.n2, keys,
-                                                  vals);
+                                                  vals, st);
   if (edges) atomicAdd(&p.ctl->edges, edges);
 }
 
@@ -256,9 +301,12 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(DecideParams<W> p) {
   __shared__ unsigned long long red[kBlock / kWave];
   __shared__ double rdq[kBlock / kWave];
   __shared__ uint32_t rc[kBlock / kWave];
+  __shared__ MoverStage st;
   constexpr uint32_t mask = T - 1;
   const uint32_t cnt = *p.count;
   unsigned long long edges = 0;
+  if (threadIdx.x == 0) st.n = 0;
+  __syncthreads();
   for (uint32_t item = blockIdx.x; item < cnt; item += gridDim.x) {
     const uint32_t v = p.list[item];
     const uint32_t d = p.C[v];
@@ -303,9 +351,12 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(DecideParams<W> p) {
       }
     }
     block_best(bdq, bc, rdq, rc);
-    if (valid && threadIdx.x == 0) emit_decision<W, REFINE>(p, v, d, bdq, bc);
+    if (valid && threadIdx.x == 0) emit_decision<W, REFINE>(p, v, d, bdq, bc, &st);
     __syncthreads();
+    if (st.n == kMoverStage) stage_flush(st, p.ctl, p.movers);
   }
+  __syncthreads();
+  stage_flush(st, p.ctl, p.movers);
   if (edges) atomicAdd(&p.ctl->edges, edges);
 }
 
@@ -538,48 +589,45 @@ int hub_layout(hipStream_t s, const uint32_t* len, uint32_t nl, uint32_t hub_abo
 // stamp is read first and claimed by exchange only when it is not set).
 // Every active lane of the wavefront calls this together; lanes without a
 // neighbour pass kNone.
-__device__ inline void mark_neighbour(const ApplyParams& p, uint32_t j) {
-  uint32_t key = kNone;
-  if (j != kNone) {
-    const uint32_t kj = vertex_class(j, p.li, p.P);
-    if (kj > p.k) {
-      if (__atomic_load_n(&p.pend_mark[j], __ATOMIC_RELAXED) != p.stamp &&
-          atomicExch(&p.pend_mark[j], p.stamp) != p.stamp)
-        key = kj;
-    } else {
-      if (__atomic_load_n(&p.unproc_mark[j], __ATOMIC_RELAXED) != p.stamp + 1 &&
-          atomicExch(&p.unproc_mark[j], p.stamp + 1) != p.stamp + 1)
-        key = p.P;
-    }
+// The list a marked neighbour joins: a neighbour of a later class joins that
+// class's sub-round of this iteration (key = its class), any other one is
+// queued as unprocessed for the next iteration (key = P); kNone if it was
+// marked already.
+__device__ inline uint32_t mark_key(const ApplyParams& p, uint32_t j) {
+  if (j == kNone) return kNone;
+  const uint32_t kj = vertex_class(j, p.li, p.P);
+  if (kj > p.k) {
+    if (__atomic_load_n(&p.pend_mark[j], __ATOMIC_RELAXED) != p.stamp &&
+        atomicExch(&p.pend_mark[j], p.stamp) != p.stamp)
+      return kj;
+  } else {
+    if (__atomic_load_n(&p.unproc_mark[j], __ATOMIC_RELAXED) != p.stamp + 1 &&
+        atomicExch(&p.unproc_mark[j], p.stamp + 1) != p.stamp + 1)
+      return p.P;
   }
-  wave_append(key, j, [&](uint32_t k, uint32_t*& list, unsigned int*& count) {
-    if (k < p.P) {
-      list = p.cls_lists + (size_t)k * p.cls_stride;
-      count = &p.ctl->cls_count[k];
-    } else {
-      list = p.next_list;
-      count = &p.ctl->next_count;
-    }
-  });
+  return kNone;
 }
 
 // Local-moving moves: one thread per mover moves the vertex (C, Sigma, member
 // counts, gain sum, split flag of the source community) and cuts its row into
 // chunks of kMarkChunk entries, queued as marking work items; then one
-// wavefront per item marks the neighbours (a neighbour of a later class joins
-// that class's sub-round of this iteration, any other neighbour is queued as
-// unprocessed for the next iteration).  Long and short rows thus spread evenly
-// over the machine.
+// wavefront per item marks the neighbours.  Long and short rows thus spread
+// evenly over the machine.  Both kernels reserve list space once per block
+// tile, not per wavefront.
 constexpr uint32_t kMarkChunk = kWave;
+constexpr int kMarkU = 8;  // marking items per wavefront of a tile
 
 __global__ __launch_bounds__(kBlock) void k_apply_moves(ApplyParams p) {
-  const uint32_t lane = threadIdx.x % kWave;
+  __shared__ unsigned int wtot[kBlock / kWave];
+  __shared__ unsigned int sbase;
+  __shared__ unsigned long long red[kBlock / kWave];
+  const uint32_t lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
   const uint32_t cnt = p.ctl->mover_count;
   long long dqsum = 0;
   const uint32_t stride = gridDim.x * kBlock;
-  // every lane runs every iteration (wavefront-uniform loop)
-  for (uint32_t base = blockIdx.x * kBlock + (threadIdx.x - lane); base < cnt; base += stride) {
-    const uint32_t m = base + lane;
+  // block-uniform loop: every thread runs every iteration
+  for (uint32_t base = blockIdx.x * kBlock; base < cnt; base += stride) {
+    const uint32_t m = base + threadIdx.x;
     uint32_t nch = 0, v = 0;
     if (m < cnt) {
       const Mover mv = p.movers[m];
@@ -597,35 +645,64 @@ __global__ __launch_bounds__(kBlock) void k_apply_moves(ApplyParams p) {
       }
       nch = (p.len[v] + kMarkChunk - 1) / kMarkChunk;
     }
-    // wavefront prefix of the chunk counts, one atomic per wavefront
+    // wavefront prefix of the chunk counts, then one reservation per block
     uint32_t incl = nch;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
       const uint32_t y = __shfl_up(incl, o);
       if ((int)lane >= o) incl += y;
     }
-    const uint32_t total = __shfl(incl, kWave - 1);
-    unsigned int first = 0;
-    if (lane == kWave - 1 && total) first = atomicAdd(&p.ctl->mark_items, total);
-    first = __shfl(first, kWave - 1);
-    for (uint32_t k = 0; k < nch; ++k) p.mark_items[first + incl - nch + k] = ((unsigned long long)v << 32) | k;
+    if (lane == kWave - 1) wtot[wv] = incl;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < kBlock / kWave; ++q) {
+      const uint32_t t = wtot[q];
+      if (q < wv) before += t;
+      total += t;
+    }
+    if (threadIdx.x == 0 && total) sbase = atomicAdd(&p.ctl->mark_items, total);
+    __syncthreads();
+    const uint32_t first = sbase + before + incl - nch;
+    for (uint32_t k = 0; k < nch; ++k) p.mark_items[first + k] = ((unsigned long long)v << 32) | k;
+    __syncthreads();
   }
-  dqsum = group_sum<kWave>(dqsum);
-  if (lane == 0 && dqsum != 0) atomicAdd(&p.ctl->dq_fixed, (unsigned long long)dqsum);
+  dqsum = (long long)block_sum((unsigned long long)dqsum, red);
+  if (threadIdx.x == 0 && dqsum != 0) atomicAdd(&p.ctl->dq_fixed, (unsigned long long)dqsum);
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&p.ctl->total_moves, (unsigned long long)cnt);
 }
 
 __global__ __launch_bounds__(kBlock) void k_mark_items(ApplyParams p) {
-  const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
-  const uint32_t lane = threadIdx.x % kWave;
-  const uint32_t nwaves = gridDim.x * (kBlock / kWave);
+  __shared__ unsigned int scnt[kMaxClasses + 1], sbase[kMaxClasses + 1];
+  const uint32_t wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  if (threadIdx.x <= kMaxClasses) scnt[threadIdx.x] = 0;
+  __syncthreads();
   const uint32_t items = p.ctl->mark_items;
-  for (uint32_t it = wave; it < items; it += nwaves) {
-    const unsigned long long item = p.mark_items[it];
-    const uint32_t v = (uint32_t)(item >> 32), k = (uint32_t)item;
-    const uint32_t L = p.len[v];
-    const uint32_t e = k * kMarkChunk + lane;
-    mark_neighbour(p, e < L ? p.cols[p.start[v] + e] : kNone);
+  constexpr uint32_t tile = kMarkU * (kBlock / kWave);
+  for (uint32_t base = blockIdx.x * tile; base < items; base += gridDim.x * tile) {
+    uint32_t key[kMarkU], val[kMarkU];
+#pragma unroll
+    for (int u = 0; u < kMarkU; ++u) {
+      const uint32_t it = base + u * (kBlock / kWave) + wv;
+      uint32_t j = kNone;
+      if (it < items) {
+        const unsigned long long item = p.mark_items[it];
+        const uint32_t v = (uint32_t)(item >> 32), k = (uint32_t)item;
+        const uint32_t e = k * kMarkChunk + lane;
+        if (e < p.len[v]) j = p.cols[p.start[v] + e];
+      }
+      key[u] = mark_key(p, j);
+      val[u] = j;
+    }
+    tile_append<kMarkU>(key, val, p.P + 1, scnt, sbase, [&](uint32_t k, uint32_t*& list, unsigned int*& count) {
+      if (k < p.P) {
+        list = p.cls_lists + (size_t)k * p.cls_stride;
+        count = &p.ctl->cls_count[k];
+      } else {
+        list = p.next_list;
+        count = &p.ctl->next_count;
+      }
+    });
   }
 }
 
@@ -679,14 +756,14 @@ static int grid_for(uint64_t items, int per_block, int cap) {
 void launch_distribute(hipStream_t s, const uint32_t* in_list, const unsigned int* in_count, uint32_t n_upper,
                        uint32_t li, uint32_t P, uint32_t stamp, uint32_t* pend_mark, uint32_t* cls_lists,
                        size_t stride, Ctl* ctl) {
-  hipLaunchKernelGGL(k_distribute, dim3(grid_for(n_upper, kBlock, 4096)), dim3(kBlock), 0, s, in_list, in_count,
+  hipLaunchKernelGGL(k_distribute, dim3(grid_for(n_upper, kBlock * kDistU, 4096)), dim3(kBlock), 0, s, in_list, in_count,
                      n_upper, li, P, stamp, pend_mark, cls_lists, stride, ctl);
 }
 
 void launch_bin(hipStream_t s, const uint32_t* list, const unsigned int* count, uint32_t n_upper, const uint32_t* len,
                 const uint8_t* in_range, uint32_t* bin_lists, size_t stride, const BinCfg& cfg,
                 unsigned long long* hub_items, Ctl* ctl) {
-  hipLaunchKernelGGL(k_bin, dim3(grid_for(n_upper, kBlock, 4096)), dim3(kBlock), 0, s, list, count, len, in_range,
+  hipLaunchKernelGGL(k_bin, dim3(grid_for(n_upper, kBlock * kBinU, 4096)), dim3(kBlock), 0, s, list, count, len, in_range,
                      bin_lists, stride, cfg, hub_items, ctl);
 }
 
@@ -746,7 +823,8 @@ template void launch_decide_all<int64_t, true>(hipStream_t, DecideParams<int64_t
 
 void launch_apply_moves(hipStream_t s, const ApplyParams& p, uint32_t n_upper, uint64_t items_upper) {
   hipLaunchKernelGGL(k_apply_moves, dim3(grid_for(n_upper, kBlock, 1024)), dim3(kBlock), 0, s, p);
-  hipLaunchKernelGGL(k_mark_items, dim3(grid_for(items_upper, kBlock / kWave, 2048)), dim3(kBlock), 0, s, p);
+  hipLaunchKernelGGL(k_mark_items, dim3(grid_for(items_upper, kMarkU * (kBlock / kWave), 2048)), dim3(kBlock), 0, s,
+                     p);
 }
 
 void launch_apply_refine(hipStream_t s, uint32_t* C, int64_t* S, const int64_t* K, uint32_t* size,
