@@ -123,13 +123,25 @@ __device__ inline bool better(double dq, uint32_t c, double bdq, uint32_t bc) {
   return dq > bdq || (dq == bdq && c < bc);
 }
 
-__device__ inline uint32_t slot_hash(uint32_t key, uint32_t mask) { return (key * 2654435761u ^ (key >> 15)) & mask; }
+// Home slot of a key: the low bits of a full-avalanche mixing.  (The low bits
+// of a plain multiplicative hash depend only on the key's low bits, and the
+// labels of aggregated levels often share few low-bit patterns: such a table
+// degenerates into probe chains of hundreds of slots.)
+__device__ inline uint32_t slot_hash(uint32_t key, uint32_t mask) { return fmix32(key) & mask; }
+
+// Salt of the tables whose slot order becomes the order of an aggregated row.
+// A row listed in slot order is sorted by that table's hash: a table of the
+// same hash filled from a run of such a row (a hub chunk) would see keys of
+// nearly equal home slots and degenerate into long probe chains, so rows are
+// ordered by a differently salted hash than every table that reads them.
+constexpr uint32_t kRowSalt = 0x9e3779b9u;
 
 // Open-addressing insert-or-add into a table of `mask + 1` slots (keys kNone
 // when free); the table always has more slots than distinct keys.
 template <typename KeyPtr, typename ValPtr>
-__device__ inline void table_add(KeyPtr keys, ValPtr vals, uint32_t mask, uint32_t key, unsigned long long w) {
-  uint32_t h = slot_hash(key, mask);
+__device__ inline void table_add(KeyPtr keys, ValPtr vals, uint32_t mask, uint32_t key, unsigned long long w,
+                                 uint32_t salt = 0) {
+  uint32_t h = slot_hash(key ^ salt, mask);
   while (true) {
     uint32_t k = __atomic_load_n(&keys[h], __ATOMIC_RELAXED);
     if (k == key) {
@@ -145,6 +157,87 @@ __device__ inline void table_add(KeyPtr keys, ValPtr vals, uint32_t mask, uint32
     }
     h = (h + 1) & mask;
   }
+}
+
+// Streamed table_add over a lane's entries e = e, e + step, ... < e1:
+// entry(e, key, w) yields the key and weight of entry e, or key kNone for an
+// entry that is not inserted.  Entries are fetched kStreamBatch at a time
+// (all lanes together, so the loads overlap), then inserted with a lane whose
+// probe has ended taking its next fetched entry at once: a long probe holds
+// up only its own lane, where a plain loop over table_add runs every entry
+// at the pace of the wavefront's longest probe.
+constexpr int kStreamBatch = 4;
+template <typename KeyPtr, typename ValPtr, typename Entry>
+__device__ inline void table_accumulate(KeyPtr keys, ValPtr vals, uint32_t mask, uint32_t e, uint32_t e1,
+                                        uint32_t step, Entry entry) {
+  for (; e < e1; e += kStreamBatch * step) {
+    uint32_t kk[kStreamBatch];
+    unsigned long long ww[kStreamBatch];
+#pragma unroll
+    for (int u = 0; u < kStreamBatch; ++u) {
+      kk[u] = kNone;
+      ww[u] = 0;
+      const uint32_t x = e + u * step;
+      if (x < e1) entry(x, kk[u], ww[u]);
+    }
+    int next = 0;
+    uint32_t key = kNone, h = 0;
+    unsigned long long w = 0;
+    while (true) {
+      if (key == kNone) {
+        // the next fetched entry to insert (unrolled selection keeps kk / ww in registers)
+#pragma unroll
+        for (int u = 0; u < kStreamBatch; ++u) {
+          if (key == kNone && u >= next && kk[u] != kNone) {
+            key = kk[u];
+            w = ww[u];
+            next = u + 1;
+          }
+        }
+        if (key == kNone) break;
+        h = slot_hash(key, mask);
+      }
+      const uint32_t k = __atomic_load_n(&keys[h], __ATOMIC_RELAXED);
+      if (k == key) {
+        atomicAdd(&vals[h], w);
+        key = kNone;
+        continue;
+      }
+      if (k == kNone) {
+        const uint32_t o = atomicCAS(&keys[h], kNone, key);
+        if (o == kNone || o == key) {
+          atomicAdd(&vals[h], w);
+          key = kNone;
+          continue;
+        }
+      }
+      h = (h + 1) & mask;
+    }
+  }
+}
+
+// table_add that gives up after probing every slot once: false when the key
+// found no slot (the table is full), and the sum of that key is then missing.
+template <typename KeyPtr, typename ValPtr>
+__device__ inline bool table_add_bounded(KeyPtr keys, ValPtr vals, uint32_t mask, uint32_t key,
+                                         unsigned long long w) {
+  uint32_t h = slot_hash(key, mask);
+  for (uint32_t probe = 0; probe <= mask; ++probe) {
+    const uint32_t k = __atomic_load_n(&keys[h], __ATOMIC_RELAXED);
+    if (k == key) {
+      atomicAdd(&vals[h], w);
+      return true;
+    }
+    if (k == kNone) {
+      const uint32_t o = atomicCAS(&keys[h], kNone, key);
+      if (o == kNone || o == key) {
+        atomicAdd(&vals[h], w);
+        return true;
+      }
+    }
+    h = (h + 1) & mask;
+  }
+  return false;
 }
 
 template <int G, typename T>

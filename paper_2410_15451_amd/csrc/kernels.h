@@ -23,15 +23,21 @@ struct DecideParams {
   Ctl* ctl;
   int async;             // 1: moves are applied at once against the live state
   uint8_t* dS;           // split flags for asynchronous local moves (dynamic runs) or null
-  // hub bin: every hub of the level owns a clean table in the arena
+  // hub bin: a hub of degree L has nch = ceil(L / kHubChunk) chunks; chunk k
+  // owns staging slots [k * kHubChunk, (k + 1) * kHubChunk) of the hub's
+  // region, holding its distinct communities sorted by bucket (2^rbits
+  // buckets of about kHubBucket communities each), and column k of the hub's
+  // (R + 1) x nch matrix of bucket starts within the chunk (row R: the
+  // chunk's total).
   const uint32_t* hub_idx;   // vertex -> hub index (hubs only)
-  const uint64_t* hub_off;   // hub index -> first slot in the arena
-  const uint32_t* hub_mask;  // hub index -> slots - 1
+  const uint64_t* hub_off;   // hub index -> first staging slot
+  const uint64_t* hub_moff;  // hub index -> first matrix entry
+  const uint32_t* hub_rbits; // hub index -> log2 of its bucket count
   unsigned long long* hub_kid;  // hub index -> K_{i->d} accumulator (kept zero between uses)
   uint32_t* hub_keys;
   unsigned long long* hub_vals;
-  uint32_t* hub_occ;           // per hub (same offsets as the table): claimed slots
-  unsigned int* hub_nocc;      // hub index -> claimed slots (kept zero between uses)
+  uint16_t* hub_mat;
+  unsigned int* hub_live;    // hub index -> 1 while the hub takes part in the sub-round (kept zero between uses)
   // pick in segments: per hub and segment the best candidate, and a
   // completion counter per hub (kept zero between uses)
   uint32_t pick_segs;
@@ -41,20 +47,28 @@ struct DecideParams {
   unsigned long long* hub_items;  // (hub vertex, chunk) work items of the current sub-round
 };
 
-// Hub layout of one level: hubs (degree above the last LDS bin) get table
-// regions of pow2(2 * degree) slots in one arena.
+// Hub layout of one level: a hub (degree above the last LDS bin) of degree
+// L gets nch = ceil(L / kHubChunk) chunks of staging slots and R =
+// pow2(ceil(L / kHubBucket)) buckets (at most 2^kHubMaxRbits), with an
+// (R + 1) x nch matrix of 16-bit bucket starts.
+constexpr uint32_t kHubChunk = 2048, kHubSlots = 4096;
+constexpr uint32_t kHubBucketBits = 10, kHubBucket = 1u << kHubBucketBits;
+constexpr uint32_t kHubMaxRbits = 11;  // at most 2048 buckets per hub (LDS counters)
 struct HubLayout {
   uint32_t* list;       // hubs of the level
   uint32_t* idx;        // vertex -> hub index (valid for hubs)
-  uint64_t* off;        // hub index -> arena offset (count + 1)
-  uint32_t* mask;       // hub index -> slots - 1
+  uint64_t* off;        // hub index -> staging offset (count + 1)
+  uint64_t* moff;       // hub index -> matrix offset (count + 1)
+  uint32_t* rbits;      // hub index -> log2 of the bucket count
   uint64_t* size_tmp;   // scratch (count)
+  uint64_t* msize_tmp;  // scratch (count)
   unsigned long long* kid;
 };
-// fills list / idx / off / mask for the level; returns the arena slots needed in *slots
+// fills list / idx / off / moff / rbits for the level; returns the hub count,
+// the staging slots and the matrix entries needed
 int hub_layout(hipStream_t s, const uint32_t* len, uint32_t nl, uint32_t hub_above, HubLayout& h, Ctl* ctl,
-               void* scan_tmp,
-               uint64_t* total_dev, uint32_t* count_out, uint64_t* slots_out);
+               void* scan_tmp, uint64_t* total_dev, uint32_t* count_out, uint64_t* slots_out,
+               uint64_t* mat_out);
 
 struct ApplyParams {
   const int64_t* start;
@@ -81,12 +95,14 @@ struct ApplyParams {
 void launch_distribute(hipStream_t s, const uint32_t* in_list, const unsigned int* in_count, uint32_t n_upper,
                        uint32_t li, uint32_t P, uint32_t stamp, uint32_t* pend_mark, uint32_t* cls_lists,
                        size_t stride, Ctl* ctl);
-// Segments of the hub pick (kernel grid y): enough for the level's longest
-// row at kHubPickSeg claimed slots each, at most kHubPickMaxSegs.
-constexpr uint32_t kHubPickSeg = 4096, kHubPickMaxSegs = 64;
+// Segments of the hub pick (kernel grid y): one per bucket of the level's
+// longest row, at most kHubPickMaxSegs.
+constexpr uint32_t kHubPickMaxSegs = 16;
 inline uint32_t hub_pick_segs(uint32_t maxdeg) {
-  const uint32_t s = maxdeg / kHubPickSeg + 1;
-  return s < kHubPickMaxSegs ? s : kHubPickMaxSegs;
+  const uint32_t units = maxdeg / kHubBucket + 1;
+  uint32_t s = 1;
+  while (s < units && s < kHubPickMaxSegs) s <<= 1;
+  return s;
 }
 
 // hub_items (may be NULL): hubs also queue their row chunks for the hub kernels

@@ -56,7 +56,6 @@ __global__ __launch_bounds__(kBlock) void k_distribute(const uint32_t* in_list, 
 // ---------------------------------------------------------------------------
 // Hub vertices also queue their row chunks as work items of the hub kernels
 // (hub_items, when given).
-constexpr uint32_t kHubChunk = 2048, kHubSlots = 4096;
 
 constexpr int kBinU = 4;  // list entries per thread of a tile
 __global__ __launch_bounds__(kBlock) void k_bin(const uint32_t* list, const unsigned int* count,
@@ -227,17 +226,16 @@ __device__ inline unsigned long long decide_group_body(const DecideParams<W>& p,
       const uint32_t L = p.g.len[v];
       const uint32_t bnd = REFINE ? p.CB[v] : 0;
       if (!REFINE && lane == 0) edges += L;
-      for (uint32_t e = lane; e < L; e += G) {
+      table_accumulate(tk, tv, T - 1, lane, L, G, [&](uint32_t e, uint32_t& key, unsigned long long& w) {
         const uint32_t j = p.g.cols[s0 + e];
-        if (j == v) continue;
-        if (REFINE && p.CB[j] != bnd) continue;
+        if (j == v || (REFINE && p.CB[j] != bnd)) return;
         const uint32_t c = p.C[j];
-        const unsigned long long w = (unsigned long long)p.g.w[s0 + e];
+        w = (unsigned long long)p.g.w[s0 + e];
         if (c == d)
           kid += w;
         else
-          table_add(tk, tv, T - 1, c, w);
-      }
+          key = c;
+      });
     }
     __syncthreads();
     kid = group_sum<G>(kid);
@@ -322,17 +320,16 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(DecideParams<W> p) {
       const uint32_t L = p.g.len[v];
       const uint32_t bnd = REFINE ? p.CB[v] : 0;
       if (!REFINE && threadIdx.x == 0) edges += L;
-      for (uint32_t e = threadIdx.x; e < L; e += kBlock) {
+      table_accumulate(tk, tv, mask, threadIdx.x, L, kBlock, [&](uint32_t e, uint32_t& key, unsigned long long& w) {
         const uint32_t j = p.g.cols[s0 + e];
-        if (j == v) continue;
-        if (REFINE && p.CB[j] != bnd) continue;
+        if (j == v || (REFINE && p.CB[j] != bnd)) return;
         const uint32_t c = p.C[j];
-        const unsigned long long w = (unsigned long long)p.g.w[s0 + e];
+        w = (unsigned long long)p.g.w[s0 + e];
         if (c == d)
           kid += w;
         else
-          table_add(tk, tv, mask, c, w);
-      }
+          key = c;
+      });
     }
     __syncthreads();
     kid = block_sum(kid, red);
@@ -361,25 +358,72 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(DecideParams<W> p) {
 }
 
 // ---------------------------------------------------------------------------
-// Hub bin (degree above the last LDS bin).  Rows are cut into chunks of
-// kHubChunk entries and every (hub, chunk) pair is a work item of one block.
-// The block sums its chunk by community in an LDS table, adds its K_{i->d}
-// share to the hub's accumulator, and adds each distinct community once to
-// the hub's table in global memory (at least 2 * degree slots, so it never
-// fills), noting newly claimed slots in the hub's occupancy list.  Then one
-// block per hub evaluates only the occupied slots, picks the best community
-// and clears what it used.  Hubs usually see few distinct communities, so
-// the global atomics per chunk are few.
+// Hub bin (degree above the last LDS bin): a group-by over the hub's row with
+// no global hash table and no global counters (global atomics are slow, and
+// those on one address are serialised device-wide).  Rows are cut into
+// chunks of kHubChunk entries and every (hub, chunk) pair is a work item of
+// one block, which
+//  - sums its chunk by community in an LDS table and adds its K_{i->d} share
+//    to the hub's accumulator,
+//  - sorts the chunk's distinct communities by bucket (top bits of
+//    fmix32(community)) into the chunk's own staging slots, and writes the
+//    bucket starts into the chunk's column of the hub's matrix.
+// The pick then gives each block buckets of a hub: a bucket's runs in all
+// chunks are summed in an LDS table and the communities found are evaluated;
+// the hub's last block combines the blocks' best candidates in a fixed order
+// and emits the decision.
 // ---------------------------------------------------------------------------
+__device__ inline uint32_t hub_bucket(uint32_t c, uint32_t rb) { return rb ? fmix32(c) >> (32 - rb) : 0u; }
+
+// In-place exclusive scan of a[0, n) (n <= kPer * kBlock) by the whole block;
+// returns the total.  wsum holds kBlock / kWave words.
+template <uint32_t kPer>
+__device__ inline uint32_t block_exclusive_scan(unsigned int* a, uint32_t n, unsigned int* wsum) {
+  const uint32_t lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  unsigned int x[kPer], tot = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; ++q) {
+    const uint32_t i = threadIdx.x * kPer + q;
+    x[q] = i < n ? a[i] : 0u;
+    tot += x[q];
+  }
+  unsigned int incl = tot;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const unsigned int y = __shfl_up(incl, o);
+    if ((int)lane >= o) incl += y;
+  }
+  if (lane == kWave - 1) wsum[wv] = incl;
+  __syncthreads();
+  unsigned int run = incl - tot, total = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < kBlock / kWave; ++q) {
+    if (q < wv) run += wsum[q];
+    total += wsum[q];
+  }
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; ++q) {
+    const uint32_t i = threadIdx.x * kPer + q;
+    if (i < n) a[i] = run;
+    run += x[q];
+  }
+  __syncthreads();
+  return total;
+}
+
 template <typename W, bool REFINE>
 __global__ __launch_bounds__(kBlock) void k_hub_chunk(DecideParams<W> p) {
+  constexpr uint32_t kNB = 1u << kHubMaxRbits;
   __shared__ uint32_t lk[kHubSlots];
   __shared__ unsigned long long lv[kHubSlots];
+  __shared__ unsigned int lcnt[kNB + 1];
+  __shared__ unsigned int wsum[kBlock / kWave];
   __shared__ unsigned long long red[kBlock / kWave];
   for (uint32_t sl = threadIdx.x; sl < kHubSlots; sl += kBlock) {
     lk[sl] = kNone;
     lv[sl] = 0;
   }
+  for (uint32_t b = threadIdx.x; b <= kNB; b += kBlock) lcnt[b] = 0;
   __syncthreads();
   const uint32_t items = p.ctl->hub_items;
   unsigned long long edges = 0;
@@ -394,56 +438,51 @@ __global__ __launch_bounds__(kBlock) void k_hub_chunk(DecideParams<W> p) {
     const uint32_t cb = k * kHubChunk, ce = min(L, cb + kHubChunk);
     const uint32_t bnd = REFINE ? p.CB[v] : 0;
     unsigned long long kid = 0;
-    for (uint32_t e = cb + threadIdx.x; e < ce; e += kBlock) {
-      const uint32_t j = p.g.cols[s0 + e];
-      if (j == v) continue;
-      if (REFINE && p.CB[j] != bnd) continue;
-      const uint32_t c = p.C[j];
-      const unsigned long long w = (unsigned long long)p.g.w[s0 + e];
-      if (c == d)
-        kid += w;
-      else
-        table_add(lk, lv, kHubSlots - 1, c, w);
-    }
+    table_accumulate(lk, lv, kHubSlots - 1, cb + threadIdx.x, ce, kBlock,
+                     [&](uint32_t e, uint32_t& key, unsigned long long& w) {
+                       const uint32_t j = p.g.cols[s0 + e];
+                       if (j == v || (REFINE && p.CB[j] != bnd)) return;
+                       const uint32_t c = p.C[j];
+                       w = (unsigned long long)p.g.w[s0 + e];
+                       if (c == d)
+                         kid += w;
+                       else
+                         key = c;
+                     });
     kid = block_sum(kid, red);
     if (threadIdx.x == 0) {
       if (kid) atomicAdd(&p.hub_kid[hi], kid);
+      if (k == 0) p.hub_live[hi] = 1;
       if (!REFINE) edges += ce - cb;
     }
-    const uint64_t off = p.hub_off[hi];
-    uint32_t* tk = p.hub_keys + off;
-    unsigned long long* tv = p.hub_vals + off;
-    uint32_t* occ = p.hub_occ + off;
-    const uint32_t mask = p.hub_mask[hi];
+    __syncthreads();
+    const uint32_t rb = p.hub_rbits[hi], R = 1u << rb;
+    const uint32_t nch = (L + kHubChunk - 1) / kHubChunk;
+    // counting sort of the chunk's distinct communities by bucket
+    for (uint32_t sl = threadIdx.x; sl < kHubSlots; sl += kBlock) {
+      const uint32_t c = lk[sl];
+      if (c != kNone) atomicAdd(&lcnt[hub_bucket(c, rb)], 1u);
+    }
+    __syncthreads();
+    const uint32_t total = block_exclusive_scan<kNB / kBlock>(lcnt, R, wsum);
+    if (threadIdx.x == 0) lcnt[R] = total;
+    __syncthreads();
+    uint16_t* col = p.hub_mat + p.hub_moff[hi] + k;
+    for (uint32_t b = threadIdx.x; b <= R; b += kBlock) col[(size_t)b * nch] = (uint16_t)lcnt[b];
+    __syncthreads();
+    uint32_t* tk = p.hub_keys + p.hub_off[hi] + cb;
+    unsigned long long* tv = p.hub_vals + p.hub_off[hi] + cb;
     for (uint32_t sl = threadIdx.x; sl < kHubSlots; sl += kBlock) {
       const uint32_t c = lk[sl];
       if (c == kNone) continue;
-      const unsigned long long w = lv[sl];
+      const unsigned int pos = atomicAdd(&lcnt[hub_bucket(c, rb)], 1u);
+      tk[pos] = c;
+      tv[pos] = lv[sl];
       lk[sl] = kNone;
       lv[sl] = 0;
-      uint32_t h = slot_hash(c, mask);
-      while (true) {
-        const uint32_t o0 = __atomic_load_n(&tk[h], __ATOMIC_RELAXED);
-        if (o0 == c) {
-          atomicAdd(&tv[h], w);
-          break;
-        }
-        if (o0 == kNone) {
-          const uint32_t o = atomicCAS(&tk[h], kNone, c);
-          if (o == kNone) {
-            atomicAdd(&tv[h], w);
-            occ[atomicAdd(&p.hub_nocc[hi], 1u)] = h;
-            break;
-          }
-          if (o == c) {
-            atomicAdd(&tv[h], w);
-            break;
-          }
-        }
-        h = (h + 1) & mask;
-      }
     }
     __syncthreads();
+    for (uint32_t b = threadIdx.x; b <= R; b += kBlock) lcnt[b] = 0;
   }
   if (edges) {
     atomicAdd(&p.ctl->edges, edges);
@@ -451,50 +490,121 @@ __global__ __launch_bounds__(kBlock) void k_hub_chunk(DecideParams<W> p) {
   }
 }
 
-// Pick: the claimed slots of a hub are split into at most gridDim.y segments
-// of at least kHubPickSeg slots; block (x, y) takes segment y of the hubs x,
-// x + gridDim.x, ...  Each segment's
-// best candidate goes to the hub's partial results; the last segment to
-// finish (a completion counter) combines them in segment order, emits the
-// decision and resets the hub's counters.  Every participating block reads
-// the claim count before it counts itself done, so the count is stable
-// until the last one resets it.
+// Pick: the hub's buckets are taken in G = 2^gb groups of consecutive
+// buckets (top gb bits of the mixing), G the smallest power of two with about
+// kHubBucket staged entries per group; block (x, y) of a grid with gridDim.y
+// segments takes groups y, y + nseg, ... of the hubs x, x + gridDim.x, ...
+// (nseg = min(G, gridDim.y)).  A group's runs are taken kPickWin chunks at a
+// time (run lengths scanned in LDS, each entry found by binary search) and
+// summed in an LDS table sized for the group.  Should a group hold more
+// distinct communities than the table, it is taken in 2^q sub-groups by the
+// next q bits of the same mixing (a bijection, so distinct communities
+// eventually part).  Each segment's best candidate goes to the hub's partial results;
+// the last segment to finish combines them in segment order.  Every block
+// reads the hub's accumulators before it counts itself done, so they are
+// stable until the last one resets them.
+constexpr uint32_t kPickWin = 2048;
+
 template <typename W, bool REFINE>
 __global__ __launch_bounds__(kBlock) void k_hub_pick(DecideParams<W> p) {
+  __shared__ uint32_t tk[kHubSlots];
+  __shared__ unsigned long long tv[kHubSlots];
+  __shared__ unsigned int rpre[kPickWin];  // exclusive prefix of the window's run lengths
+  __shared__ uint16_t rst[kPickWin];       // run starts within their chunks
+  __shared__ unsigned int wsum[kBlock / kWave];
   __shared__ double rdq[kBlock / kWave];
   __shared__ uint32_t rc[kBlock / kWave];
-  __shared__ unsigned int last;
+  __shared__ unsigned long long red[kBlock / kWave];
+  __shared__ unsigned int last, full;
+  bool clean = false;  // the table is cleared once, by blocks that get work
   const uint32_t cnt = *p.count;
   const uint32_t y = blockIdx.y;
   for (uint32_t h = blockIdx.x; h < cnt; h += gridDim.x) {
     const uint32_t v = p.list[h];
     const uint32_t d = p.C[v];
-    if (REFINE && p.size[d] != 1) continue;  // block-uniform; nothing was summed
     const uint32_t hi = p.hub_idx[v];
-    const uint32_t nocc = __atomic_load_n(&p.hub_nocc[hi], __ATOMIC_RELAXED);
-    const uint32_t seg = max(kHubPickSeg, (nocc + gridDim.y - 1) / gridDim.y);
-    const uint32_t nseg = nocc == 0 ? 1 : (nocc + seg - 1) / seg;
+    // taking part was settled by the chunk kernel: asynchronous refinement
+    // moves made by this kernel may change community sizes meanwhile
+    if (p.hub_live[hi] == 0) continue;  // block-uniform; nothing was summed
+    const uint32_t rb = p.hub_rbits[hi], R = 1u << rb;
+    const uint32_t nch = (p.g.len[v] + kHubChunk - 1) / kHubChunk;
+    const uint16_t* mat = p.hub_mat + p.hub_moff[hi];
+    // staged entries of the hub (row R of the matrix: the chunks' totals)
+    // decide how many buckets one group of this pick takes
+    unsigned long long tot = 0;
+    for (uint32_t c = threadIdx.x; c < nch; c += kBlock) tot += mat[(size_t)R * nch + c];
+    tot = block_sum(tot, red);
+    uint32_t gb = 0;
+    while (gb < rb && ((unsigned long long)kHubBucket << gb) < tot) ++gb;
+    const uint32_t G = 1u << gb, span = rb - gb;
+    const uint32_t nseg = min(G, gridDim.y);
     if (y >= nseg) continue;  // block-uniform; this block takes no part for this hub
-    const uint64_t off = p.hub_off[hi];
-    uint32_t* tk = p.hub_keys + off;
-    unsigned long long* tv = p.hub_vals + off;
-    const uint32_t* occ = p.hub_occ + off;
+    if (!clean) {
+      for (uint32_t sl = threadIdx.x; sl < kHubSlots; sl += kBlock) {
+        tk[sl] = kNone;
+        tv[sl] = 0;
+      }
+      __syncthreads();
+      clean = true;
+    }
+    const uint32_t* sk = p.hub_keys + p.hub_off[hi];
+    const unsigned long long* sv = p.hub_vals + p.hub_off[hi];
     const int64_t kid = (int64_t)p.hub_kid[hi];
     const int64_t ki = p.K[v], sd = p.S[d];
     double bdq = -INFINITY;
     uint32_t bc = kNone;
-    const uint32_t q1 = min(nocc, (y + 1) * seg);
-    for (uint32_t q = y * seg + threadIdx.x; q < q1; q += kBlock) {
-      const uint32_t sl = occ[q];
-      const uint32_t c = tk[sl];
-      const int64_t kic = (int64_t)tv[sl];
-      tk[sl] = kNone;
-      tv[sl] = 0;
-      if (!allowed_target<W, REFINE>(p, c)) continue;
-      const double dq = delta_q(kic, kid, ki, p.S[c], sd, p.inv_m, p.inv_2m2);
-      if (better(dq, c, bdq, bc)) {
-        bdq = dq;
-        bc = c;
+    for (uint32_t grp = y; grp < G; grp += nseg) {
+      // buckets [b0, b1) of this group: contiguous in every chunk
+      const uint32_t b0 = grp << span, b1 = (grp + 1) << span;
+      for (uint32_t q = 0;; ++q) {  // sub-group bits
+        bool fits = true;
+        for (uint32_t sub = 0; sub < (1u << q) && fits; ++sub) {
+          uint32_t mask = kHubSlots - 1;
+          if (threadIdx.x == 0) full = 0;
+          for (uint32_t c0 = 0; c0 < nch; c0 += kPickWin) {
+            const uint32_t cw = min(kPickWin, nch - c0);
+            for (uint32_t i = threadIdx.x; i < cw; i += kBlock) {
+              const uint32_t s = mat[(size_t)b0 * nch + c0 + i], e = mat[(size_t)b1 * nch + c0 + i];
+              rst[i] = (uint16_t)s;
+              rpre[i] = e - s;
+            }
+            __syncthreads();
+            const uint32_t n = block_exclusive_scan<kPickWin / kBlock>(rpre, cw, wsum);
+            if (nch <= kPickWin) mask = min(kHubSlots, pow2_at_least(2 * n)) - 1;
+            for (uint32_t x = threadIdx.x; x < n; x += kBlock) {
+              // chunk i of the window with rpre[i] <= x < rpre[i + 1]
+              uint32_t lo = 0, hi2 = cw - 1;
+              while (lo < hi2) {
+                const uint32_t mid = (lo + hi2 + 1) >> 1;
+                if (rpre[mid] <= x)
+                  lo = mid;
+                else
+                  hi2 = mid - 1;
+              }
+              const size_t pos = (size_t)(c0 + lo) * kHubChunk + rst[lo] + (x - rpre[lo]);
+              const uint32_t c = sk[pos];
+              if (q && ((fmix32(c) << gb) >> (32 - q)) != sub) continue;
+              if (!table_add_bounded(tk, tv, mask, c, sv[pos])) full = 1;
+            }
+            __syncthreads();
+          }
+          fits = full == 0;
+          for (uint32_t sl = threadIdx.x; sl <= mask; sl += kBlock) {
+            const uint32_t c = tk[sl];
+            if (c == kNone) continue;
+            if (fits && allowed_target<W, REFINE>(p, c)) {
+              const double dq = delta_q((int64_t)tv[sl], kid, ki, p.S[c], sd, p.inv_m, p.inv_2m2);
+              if (better(dq, c, bdq, bc)) {
+                bdq = dq;
+                bc = c;
+              }
+            }
+            tk[sl] = kNone;
+            tv[sl] = 0;
+          }
+          __syncthreads();
+        }
+        if (fits) break;
       }
     }
     block_best(bdq, bc, rdq, rc);
@@ -526,7 +636,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_pick(DecideParams<W> p) {
       }
       if (last) {
         p.hub_kid[hi] = 0;
-        p.hub_nocc[hi] = 0;
+        p.hub_live[hi] = 0;
         emit_decision<W, REFINE>(p, v, d, bdq, bc);
       }
     }
@@ -547,16 +657,21 @@ __global__ __launch_bounds__(kBlock) void k_hub_list(const uint32_t* len, uint32
 __global__ __launch_bounds__(kBlock) void k_hub_sizes(const uint32_t* len, uint32_t cnt, HubLayout h) {
   for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < cnt; k += gridDim.x * kBlock) {
     const uint32_t v = h.list[k];
-    const uint32_t t = pow2_at_least(2 * len[v]);
-    h.size_tmp[k] = t;
-    h.mask[k] = t - 1;
+    const uint32_t L = len[v];
+    const uint32_t nch = (L + kHubChunk - 1) / kHubChunk;
+    const uint32_t R = pow2_at_least((L + kHubBucket - 1) >> kHubBucketBits);
+    uint32_t rb = 0;
+    while ((1u << rb) < R && rb < kHubMaxRbits) ++rb;
+    h.size_tmp[k] = (uint64_t)nch * kHubChunk;
+    h.msize_tmp[k] = (uint64_t)((1u << rb) + 1) * nch;
+    h.rbits[k] = rb;
     h.idx[v] = k;
   }
 }
 
 int hub_layout(hipStream_t s, const uint32_t* len, uint32_t nl, uint32_t hub_above, HubLayout& h, Ctl* ctl,
-               void* scan_tmp,
-               uint64_t* total_dev, uint32_t* count_out, uint64_t* slots_out) {
+               void* scan_tmp, uint64_t* total_dev, uint32_t* count_out, uint64_t* slots_out,
+               uint64_t* mat_out) {
   hipLaunchKernelGGL(k_clear_misc6, dim3(1), dim3(1), 0, s, ctl);
   hipLaunchKernelGGL(k_hub_list, dim3(grid_for(nl, kBlock, 4096)), dim3(kBlock), 0, s, len, nl, hub_above, h.list,
                      ctl);
@@ -567,15 +682,17 @@ int hub_layout(hipStream_t s, const uint32_t* len, uint32_t nl, uint32_t hub_abo
   const unsigned int cnt = *pc;
   *count_out = cnt;
   *slots_out = 0;
+  *mat_out = 0;
   if (cnt == 0) return 0;
   hipLaunchKernelGGL(k_hub_sizes, dim3(grid_for(cnt, kBlock, 1024)), dim3(kBlock), 0, s, len, cnt, h);
   exclusive_scan_u64(s, h.size_tmp, h.off, cnt, total_dev, scan_tmp);
-  uint64_t* ps = (uint64_t*)pinned_stage(8);
-  if (!ps || hipMemcpyAsync(ps, total_dev, sizeof(uint64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+  exclusive_scan_u64(s, h.msize_tmp, h.moff, cnt, total_dev + 1, scan_tmp);
+  uint64_t* ps = (uint64_t*)pinned_stage(16);
+  if (!ps || hipMemcpyAsync(ps, total_dev, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return -1;
-  const uint64_t slots = *ps;
-  *slots_out = slots;
+  *slots_out = ps[0];
+  *mat_out = ps[1];
   return 0;
 }
 
@@ -583,16 +700,11 @@ int hub_layout(hipStream_t s, const uint32_t* len, uint32_t nl, uint32_t hub_abo
 // Apply kernels
 // ---------------------------------------------------------------------------
 
-// A neighbour j of a mover in class k: if j's class comes later it joins
-// that class's sub-round of this iteration, otherwise it is queued as
-// unprocessed for the next iteration (each vertex at most once per list: the
-// stamp is read first and claimed by exchange only when it is not set).
-// Every active lane of the wavefront calls this together; lanes without a
-// neighbour pass kNone.
-// The list a marked neighbour joins: a neighbour of a later class joins that
-// class's sub-round of this iteration (key = its class), any other one is
-// queued as unprocessed for the next iteration (key = P); kNone if it was
-// marked already.
+// The list a marked neighbour j joins: a neighbour of a later class joins
+// that class's sub-round of this iteration (key = its class), any other one
+// is queued as unprocessed for the next iteration (key = P); kNone if it was
+// marked already (each vertex at most once per list: the stamp is read first
+// and claimed by exchange only when it is not set).
 __device__ inline uint32_t mark_key(const ApplyParams& p, uint32_t j) {
   if (j == kNone) return kNone;
   const uint32_t kj = vertex_class(j, p.li, p.P);
@@ -804,7 +916,7 @@ void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, si
         hipLaunchKernelGGL((k_hub_chunk<W, REFINE>), dim3(grid_for(bin_upper[b] * (maxdeg / kHubChunk + 1), 1, 1536)),
                            dim3(kBlock), 0, s, q);
         if (sizeof(W) == 4 && !REFINE) kt_mark(LEIDEN_KT_HUB_INSERT, s);
-        hipLaunchKernelGGL((k_hub_pick<W, REFINE>), dim3(grid_for(bin_upper[b], 1, 1024), p.pick_segs),
+        hipLaunchKernelGGL((k_hub_pick<W, REFINE>), dim3(grid_for(bin_upper[b], 1, 512), p.pick_segs),
                            dim3(kBlock), 0, s, q);
         break;
       }

@@ -544,7 +544,7 @@ __device__ inline void agg_accumulate(Rows<W> g, const uint32_t* C, const uint32
         const long long sp = __shfl((long long)st, p, G);
         if (x < total) {
           const int64_t e = sp + (x - (p > 0 ? before : 0u));
-          table_add(tk, tv, mask, C[g.cols[e]], (unsigned long long)g.w[e]);
+          table_add(tk, tv, mask, C[g.cols[e]], (unsigned long long)g.w[e], kRowSalt);
         }
       }
     } else {
@@ -567,7 +567,7 @@ __device__ inline void agg_accumulate(Rows<W> g, const uint32_t* C, const uint32
         }
         const uint32_t before = lo > 0 ? spre[lo - 1] : 0;
         const int64_t e = sstart[lo] + (x - before);
-        table_add(tk, tv, mask, C[g.cols[e]], (unsigned long long)g.w[e]);
+        table_add(tk, tv, mask, C[g.cols[e]], (unsigned long long)g.w[e], kRowSalt);
       }
       __syncthreads();
     }
@@ -702,29 +702,30 @@ __global__ __launch_bounds__(kBlock) void k_agg_big_insert(Rows<W> g, const uint
       entries += total;
       for (uint32_t xb = 0; xb < total; xb += kStage) {
         const uint32_t xe = min(total, xb + kStage);
-        for (uint32_t xx = xb + threadIdx.x; xx < xe; xx += kBlock) {
-          int lo = 0, hi = kBlock - 1;
-          while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (spre[mid] > xx)
-              hi = mid;
-            else
-              lo = mid + 1;
-          }
-          const uint32_t before = lo > 0 ? spre[lo - 1] : 0;
-          const int64_t e = sstart[lo] + (xx - before);
-          const uint32_t c = C[g.cols[e]];
-          const unsigned long long w = (unsigned long long)g.w[e];
-          if (c == b.c)
-            self += w;
-          else
-            table_add(lk, lv, kSlots - 1, c, w);
-        }
+        table_accumulate(lk, lv, kSlots - 1, xb + threadIdx.x, xe, kBlock,
+                         [&](uint32_t xx, uint32_t& key, unsigned long long& w) {
+                           int lo = 0, hi = kBlock - 1;
+                           while (lo < hi) {
+                             const int mid = (lo + hi) >> 1;
+                             if (spre[mid] > xx)
+                               hi = mid;
+                             else
+                               lo = mid + 1;
+                           }
+                           const uint32_t before = lo > 0 ? spre[lo - 1] : 0;
+                           const int64_t e = sstart[lo] + (xx - before);
+                           const uint32_t c = C[g.cols[e]];
+                           w = (unsigned long long)g.w[e];
+                           if (c == b.c)
+                             self += w;
+                           else
+                             key = c;
+                         });
         __syncthreads();
         for (int s = threadIdx.x; s < (int)kSlots; s += kBlock) {
           const uint32_t k = lk[s];
           if (k == kNone) continue;
-          table_add(tk, tv, b.mask, k, lv[s]);
+          table_add(tk, tv, b.mask, k, lv[s], kRowSalt);
           lk[s] = kNone;
           lv[s] = 0;
         }
@@ -732,7 +733,7 @@ __global__ __launch_bounds__(kBlock) void k_agg_big_insert(Rows<W> g, const uint
       }
     }
     self = block_sum(self, red);
-    if (threadIdx.x == 0 && self) table_add(tk, tv, b.mask, b.c, self);
+    if (threadIdx.x == 0 && self) table_add(tk, tv, b.mask, b.c, self, kRowSalt);
   }
   if (threadIdx.x == 0 && units && entries) atomicAdd(units, entries);
 }

@@ -115,8 +115,8 @@ struct leiden_graph {
   Buf lvA_start, lvA_len, lvA_cols, lvA_w, lvB_start, lvB_len, lvB_cols, lvB_w;
   Buf agg_count, agg_off, agg_fill, agg_members, agg_deg, agg_cap, agg_lists, agg_bigcap, agg_tbl, agg_keys, agg_vals,
       agg_items, mark_items;
-  Buf hub_keys, hub_vals, hub_list, hub_idx, hub_off, hub_mask, hub_size, hub_kid;
-  Buf hub_items, hub_occ, hub_nocc, hub_pdq, hub_pc, hub_done;
+  Buf hub_keys, hub_vals, hub_list, hub_idx, hub_off, hub_moff, hub_rbits, hub_size, hub_msize, hub_kid;
+  Buf hub_items, hub_mat, hub_live, hub_pdq, hub_pc, hub_done;
   Buf tr_minv, tr_hk, tr_hv, tr_bw, tr_bv, tr_cw, tr_cb, tr_old, tr_flag, tr_rank, tr_frank, tr_fid, tr_label,
       tr_matched;
   Buf dV, dE, dC, sig, partials, modparts;
@@ -302,27 +302,29 @@ leiden_status setup_hubs(leiden_graph* G, hipStream_t s, const uint32_t* len, ui
   CHK(G->hub_list.reserve(n * 4));
   CHK(G->hub_idx.reserve(n * 4));
   CHK(G->hub_off.reserve((n + 1) * 8));
-  CHK(G->hub_mask.reserve(n * 4));
+  CHK(G->hub_moff.reserve((n + 1) * 8));
+  CHK(G->hub_msize.reserve(n * 8));
+  CHK(G->hub_rbits.reserve(n * 4));
   CHK(G->hub_size.reserve(n * 8));
   if (G->hub_kid.bytes < n * 8) {
     CHK(G->hub_kid.reserve(n * 8));
     HIPCHK(hipMemsetAsync(G->hub_kid.p, 0, n * 8, s));
   }
-  HubLayout h{G->hub_list.as<uint32_t>(), G->hub_idx.as<uint32_t>(), G->hub_off.as<uint64_t>(),
-              G->hub_mask.as<uint32_t>(), G->hub_size.as<uint64_t>(), G->hub_kid.as<unsigned long long>()};
+  HubLayout h{G->hub_list.as<uint32_t>(), G->hub_idx.as<uint32_t>(),   G->hub_off.as<uint64_t>(),
+              G->hub_moff.as<uint64_t>(), G->hub_rbits.as<uint32_t>(), G->hub_size.as<uint64_t>(),
+              G->hub_msize.as<uint64_t>(), G->hub_kid.as<unsigned long long>()};
   uint32_t cnt = 0;
-  uint64_t slots = 0;
+  uint64_t slots = 0, mat = 0;
   if (hub_layout(s, len, nl, G->bincfg.max_deg[kBins - 2], h, dctl(G), G->scan_tmp.p, G->small.as<uint64_t>() + 64,
-                 &cnt, &slots) != 0)
+                 &cnt, &slots, &mat) != 0)
     return fail(LEIDEN_EDEVICE, "hub layout failed");
-  // work items (at most one per 2048 entries plus one per hub), claim counters
   const size_t hc = std::max<uint32_t>(cnt, 1);
-  CHK(G->hub_items.reserve((slots / 4096 + hc + 1) * 8));
-  if (G->hub_nocc.bytes < hc * 4) {
-    CHK(G->hub_nocc.reserve(hc * 4));
-    fill_u32(s, G->hub_nocc.as<uint32_t>(), 0, G->hub_nocc.bytes / 4);
+  CHK(G->hub_items.reserve((slots / kHubChunk + 1) * 8));  // one per chunk
+  CHK(G->hub_mat.reserve(std::max<uint64_t>(mat, 1) * 2));
+  if (G->hub_live.bytes < hc * 4) {
+    CHK(G->hub_live.reserve(hc * 4));
+    fill_u32(s, G->hub_live.as<uint32_t>(), 0, G->hub_live.bytes / 4);
   }
-  CHK(G->hub_occ.reserve(std::max<uint64_t>(slots, 1) * 4));
   // segmented pick: per hub up to kHubPickMaxSegs partial results
   CHK(G->hub_pdq.reserve(hc * kHubPickMaxSegs * 8));
   CHK(G->hub_pc.reserve(hc * kHubPickMaxSegs * 4));
@@ -330,13 +332,9 @@ leiden_status setup_hubs(leiden_graph* G, hipStream_t s, const uint32_t* len, ui
     CHK(G->hub_done.reserve(hc * 4));
     fill_u32(s, G->hub_done.as<uint32_t>(), 0, G->hub_done.bytes / 4);
   }
-  if (slots * 4 > G->hub_keys.bytes || slots * 8 > G->hub_vals.bytes) {
-    const uint64_t want = slots + slots / 4 + 4096;
-    CHK(G->hub_keys.reserve(want * 4));
-    CHK(G->hub_vals.reserve(want * 8));
-    fill_u32(s, G->hub_keys.as<uint32_t>(), kNone, G->hub_keys.bytes / 4);
-    fill_u64(s, G->hub_vals.as<uint64_t>(), 0, G->hub_vals.bytes / 8);
-  }
+  // staging: every slot is written before it is read
+  CHK(G->hub_keys.reserve(std::max<uint64_t>(slots, 1) * 4));
+  CHK(G->hub_vals.reserve(std::max<uint64_t>(slots, 1) * 8));
   return LEIDEN_OK;
 }
 
@@ -344,13 +342,14 @@ template <typename W>
 void bind_hubs(leiden_graph* G, DecideParams<W>& dp) {
   dp.hub_idx = G->hub_idx.as<uint32_t>();
   dp.hub_off = G->hub_off.as<uint64_t>();
-  dp.hub_mask = G->hub_mask.as<uint32_t>();
+  dp.hub_rbits = G->hub_rbits.as<uint32_t>();
   dp.hub_kid = G->hub_kid.as<unsigned long long>();
   dp.hub_keys = G->hub_keys.as<uint32_t>();
   dp.hub_vals = G->hub_vals.as<unsigned long long>();
   dp.hub_items = G->hub_items.as<unsigned long long>();
-  dp.hub_occ = G->hub_occ.as<uint32_t>();
-  dp.hub_nocc = G->hub_nocc.as<unsigned int>();
+  dp.hub_moff = G->hub_moff.as<uint64_t>();
+  dp.hub_mat = G->hub_mat.as<uint16_t>();
+  dp.hub_live = G->hub_live.as<unsigned int>();
   dp.hub_pdq = G->hub_pdq.as<double>();
   dp.hub_pc = G->hub_pc.as<uint32_t>();
   dp.hub_done = G->hub_done.as<unsigned int>();
