@@ -220,8 +220,8 @@ __device__ inline void table_accumulate(KeyPtr keys, ValPtr vals, uint32_t mask,
 // found no slot (the table is full), and the sum of that key is then missing.
 template <typename KeyPtr, typename ValPtr>
 __device__ inline bool table_add_bounded(KeyPtr keys, ValPtr vals, uint32_t mask, uint32_t key,
-                                         unsigned long long w) {
-  uint32_t h = slot_hash(key, mask);
+                                         unsigned long long w, uint32_t salt = 0) {
+  uint32_t h = slot_hash(key ^ salt, mask);
   for (uint32_t probe = 0; probe <= mask; ++probe) {
     const uint32_t k = __atomic_load_n(&keys[h], __ATOMIC_RELAXED);
     if (k == key) {
@@ -402,6 +402,42 @@ __device__ inline void tile_append(const uint32_t (&key)[U], const uint32_t (&va
     list_of(key[u], list, count);
     list[sbase[key[u]] + off[u]] = val[u];
   }
+}
+
+// In-place exclusive scan of a[0, n) (n <= kPer * kBlock) by the whole block;
+// returns the total.  wsum holds kBlock / kWave words.
+template <uint32_t kPer>
+__device__ inline uint32_t block_exclusive_scan(unsigned int* a, uint32_t n, unsigned int* wsum) {
+  const uint32_t lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  unsigned int x[kPer], tot = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; ++q) {
+    const uint32_t i = threadIdx.x * kPer + q;
+    x[q] = i < n ? a[i] : 0u;
+    tot += x[q];
+  }
+  unsigned int incl = tot;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const unsigned int y = __shfl_up(incl, o);
+    if ((int)lane >= o) incl += y;
+  }
+  if (lane == kWave - 1) wsum[wv] = incl;
+  __syncthreads();
+  unsigned int run = incl - tot, total = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < kBlock / kWave; ++q) {
+    if (q < wv) run += wsum[q];
+    total += wsum[q];
+  }
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; ++q) {
+    const uint32_t i = threadIdx.x * kPer + q;
+    if (i < n) a[i] = run;
+    run += x[q];
+  }
+  __syncthreads();
+  return total;
 }
 
 __host__ __device__ inline uint32_t pow2_at_least(uint32_t x) {

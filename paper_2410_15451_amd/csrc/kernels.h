@@ -200,13 +200,16 @@ struct AggBufs {
   uint64_t* total;        // device scalars
   void* scan_tmp;
   uint32_t* small_lists;  // communities per bin (small, medium, big), n each
-  uint64_t* big_info;     // (member begin, member end, capacity) of each big community, 3 n
-  void* bigc;             // per-round table descriptors of big communities (16 B each, n)
+  uint64_t* big_info;     // (member begin, member end, capacity, entries) of each big community, 4 n
+  void* bigc;             // per-round descriptors of big communities (32 B each, n)
   void* items;            // per-round work items (24 B each, item_cap)
   uint64_t item_cap;
-  uint32_t* gkeys;
-  unsigned long long* gvals;
-  size_t gcap;            // slots available in gkeys / gvals
+  unsigned int* stage_cnt;       // per-round stage columns used (n)
+  unsigned long long* self_acc;  // per-round own-key sums (n)
+  uint32_t* skeys;               // staging slots (scap)
+  unsigned long long* svals;
+  uint16_t* smat;                // bucket-start matrices (mcap entries)
+  size_t scap, mcap;
 };
 template <typename W>
 int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t nc, AggBufs& b, int64_t* out_start,

@@ -375,42 +375,6 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(DecideParams<W> p) {
 // ---------------------------------------------------------------------------
 __device__ inline uint32_t hub_bucket(uint32_t c, uint32_t rb) { return rb ? fmix32(c) >> (32 - rb) : 0u; }
 
-// In-place exclusive scan of a[0, n) (n <= kPer * kBlock) by the whole block;
-// returns the total.  wsum holds kBlock / kWave words.
-template <uint32_t kPer>
-__device__ inline uint32_t block_exclusive_scan(unsigned int* a, uint32_t n, unsigned int* wsum) {
-  const uint32_t lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
-  unsigned int x[kPer], tot = 0;
-#pragma unroll
-  for (uint32_t q = 0; q < kPer; ++q) {
-    const uint32_t i = threadIdx.x * kPer + q;
-    x[q] = i < n ? a[i] : 0u;
-    tot += x[q];
-  }
-  unsigned int incl = tot;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const unsigned int y = __shfl_up(incl, o);
-    if ((int)lane >= o) incl += y;
-  }
-  if (lane == kWave - 1) wsum[wv] = incl;
-  __syncthreads();
-  unsigned int run = incl - tot, total = 0;
-#pragma unroll
-  for (uint32_t q = 0; q < kBlock / kWave; ++q) {
-    if (q < wv) run += wsum[q];
-    total += wsum[q];
-  }
-#pragma unroll
-  for (uint32_t q = 0; q < kPer; ++q) {
-    const uint32_t i = threadIdx.x * kPer + q;
-    if (i < n) a[i] = run;
-    run += x[q];
-  }
-  __syncthreads();
-  return total;
-}
-
 template <typename W, bool REFINE>
 __global__ __launch_bounds__(kBlock) void k_hub_chunk(DecideParams<W> p) {
   constexpr uint32_t kNB = 1u << kHubMaxRbits;

@@ -494,15 +494,18 @@ __global__ __launch_bounds__(kBlock) void k_comm_classify(uint32_t nc, const uin
   }
 }
 
-// Member ranges and row capacities of the big communities (for host planning).
+// Member ranges, row capacities and entry counts of the big communities (for
+// host planning).
 __global__ __launch_bounds__(kBlock) void k_big_info(const uint32_t* big, const unsigned int* nbig,
-                                                     const uint64_t* moff, const uint64_t* cap, uint64_t* info) {
+                                                     const uint64_t* moff, const uint64_t* cap, const uint64_t* deg,
+                                                     uint64_t* info) {
   const uint32_t cnt = *nbig;
   GRID_STRIDE(k, cnt) {
     const uint32_t c = big[k];
-    info[3 * k] = moff[c];
-    info[3 * k + 1] = moff[c + 1];
-    info[3 * k + 2] = cap[c];
+    info[4 * k] = moff[c];
+    info[4 * k + 1] = moff[c + 1];
+    info[4 * k + 2] = cap[c];
+    info[4 * k + 3] = deg[c];
   }
 }
 
@@ -629,49 +632,62 @@ __global__ __launch_bounds__(kBlock) void k_agg_lds(Rows<W> g, const uint32_t* C
   }
 }
 
-// Big communities: every community of a round owns a global table; blocks
-// take work items (a chunk of one community's members) and insert into that
-// table, then other items (a chunk of one table's slots) compact it into the
-// super row.
+// Big communities: a group-by of each community's entries with no global
+// hash table (global atomics are slow, those on one address slowest).  Work
+// items are runs of at most kBigMembers members of one community; an item's
+// entries are taken kBigStage at a time.  Each stage is summed by key in an
+// LDS table (the community's own key is summed in registers: most entries of
+// a large community stay inside it), and its distinct keys are sorted by
+// bucket (top bits of the salted mixing) into a stage column of the
+// community's staging area, with the bucket starts in column col of the
+// community's (R + 1) x smax matrix.  The emit kernel then sums each group of
+// buckets over all columns in an LDS table and writes the distinct keys into
+// the super row.
+constexpr uint32_t kBigMembers = 256, kBigStage = 2048, kBigSlots = 4096;
+constexpr uint32_t kBigBucketBits = 10, kBigMaxRbits = 11, kEmitWin = 2048;
+
 struct BigComm {
-  uint32_t c;
-  uint32_t mask;
-  uint64_t toff;
+  uint32_t c;      // community
+  uint32_t rbits;  // log2 of its bucket count
+  uint32_t smax;   // stage columns reserved
+  uint32_t pad;
+  uint64_t soff;   // first staging slot (smax * kBigStage slots)
+  uint64_t moff;   // first matrix entry ((R + 1) * smax entries)
 };
 struct AggItem {
   uint32_t big;
   uint32_t pad;
-  uint64_t a, b;
+  uint64_t a, b;  // member range
 };
 
-// Each item's entries are summed by key in an LDS table, 2048 entries at a
-// time, and each distinct key is then added once to the community's global
-// table: a community's internal edges all carry the same key, and adding them
-// one by one would serialise on one global slot.
+__device__ inline uint32_t big_mix(uint32_t c) { return fmix32(c ^ kRowSalt); }
+
 template <typename W>
-__global__ __launch_bounds__(kBlock) void k_agg_big_insert(Rows<W> g, const uint32_t* C, const uint32_t* members,
-                                                           const BigComm* bc, const AggItem* items, uint32_t nitems,
-                                                           uint32_t* gkeys, unsigned long long* gvals,
-                                                           unsigned long long* units) {
-  constexpr uint32_t kStage = 2048, kSlots = 4096;
+__global__ __launch_bounds__(kBlock) void k_agg_stage(Rows<W> g, const uint32_t* C, const uint32_t* members,
+                                                      const BigComm* bc, const AggItem* items, uint32_t nitems,
+                                                      uint32_t* skeys, unsigned long long* svals, uint16_t* smat,
+                                                      unsigned int* stage_cnt, unsigned long long* self_acc,
+                                                      unsigned long long* units) {
+  constexpr uint32_t kNB = 1u << kBigMaxRbits;
   __shared__ int64_t sstart[kBlock];
   __shared__ uint32_t spre[kBlock];
-  __shared__ uint32_t lk[kSlots];
-  __shared__ unsigned long long lv[kSlots];
-  for (int s = threadIdx.x; s < (int)kSlots; s += kBlock) {
-    lk[s] = kNone;
-    lv[s] = 0;
-  }
-  __syncthreads();
+  __shared__ uint32_t lk[kBigSlots];
+  __shared__ unsigned long long lv[kBigSlots];
+  __shared__ unsigned int lcnt[kNB + 1];
+  __shared__ unsigned int wsum[kBlock / kWave];
   __shared__ unsigned long long red[kBlock / kWave];
+  __shared__ unsigned int scol;
+  for (uint32_t sl = threadIdx.x; sl < kBigSlots; sl += kBlock) {
+    lk[sl] = kNone;
+    lv[sl] = 0;
+  }
+  for (uint32_t q = threadIdx.x; q <= kNB; q += kBlock) lcnt[q] = 0;
+  __syncthreads();
   unsigned long long entries = 0;
   for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const AggItem x = items[it];
     const BigComm b = bc[x.big];
-    uint32_t* tk = gkeys + b.toff;
-    unsigned long long* tv = gvals + b.toff;
-    // most entries of a large community stay inside it: that key is summed in
-    // registers instead of one LDS slot shared by every lane
+    const uint32_t rb = b.rbits, R = 1u << rb;
     unsigned long long self = 0;
     for (uint64_t mb = x.a; mb < x.b; mb += kBlock) {
       const uint64_t mi = mb + threadIdx.x;
@@ -700,9 +716,9 @@ __global__ __launch_bounds__(kBlock) void k_agg_big_insert(Rows<W> g, const uint
       __syncthreads();
       const uint32_t total = spre[kBlock - 1];
       entries += total;
-      for (uint32_t xb = 0; xb < total; xb += kStage) {
-        const uint32_t xe = min(total, xb + kStage);
-        table_accumulate(lk, lv, kSlots - 1, xb + threadIdx.x, xe, kBlock,
+      for (uint32_t xb = 0; xb < total; xb += kBigStage) {
+        const uint32_t xe = min(total, xb + kBigStage);
+        table_accumulate(lk, lv, kBigSlots - 1, xb + threadIdx.x, xe, kBlock,
                          [&](uint32_t xx, uint32_t& key, unsigned long long& w) {
                            int lo = 0, hi = kBlock - 1;
                            while (lo < hi) {
@@ -722,68 +738,171 @@ __global__ __launch_bounds__(kBlock) void k_agg_big_insert(Rows<W> g, const uint
                              key = c;
                          });
         __syncthreads();
-        for (int s = threadIdx.x; s < (int)kSlots; s += kBlock) {
-          const uint32_t k = lk[s];
-          if (k == kNone) continue;
-          table_add(tk, tv, b.mask, k, lv[s], kRowSalt);
-          lk[s] = kNone;
-          lv[s] = 0;
+        // the stage's distinct keys per bucket, their starts, and a column
+        for (uint32_t sl = threadIdx.x; sl < kBigSlots; sl += kBlock) {
+          const uint32_t c = lk[sl];
+          if (c != kNone) atomicAdd(&lcnt[rb ? big_mix(c) >> (32 - rb) : 0u], 1u);
         }
+        __syncthreads();
+        const uint32_t nd = block_exclusive_scan<kNB / kBlock>(lcnt, R, wsum);
+        if (threadIdx.x == 0) {
+          lcnt[R] = nd;
+          scol = atomicAdd(&stage_cnt[x.big], 1u);
+        }
+        __syncthreads();
+        const uint32_t col = scol;
+        for (uint32_t q = threadIdx.x; q <= R; q += kBlock) smat[b.moff + (size_t)q * b.smax + col] = (uint16_t)lcnt[q];
+        __syncthreads();
+        uint32_t* tk = skeys + b.soff + (size_t)col * kBigStage;
+        unsigned long long* tv = svals + b.soff + (size_t)col * kBigStage;
+        for (uint32_t sl = threadIdx.x; sl < kBigSlots; sl += kBlock) {
+          const uint32_t c = lk[sl];
+          if (c == kNone) continue;
+          const unsigned int pos = atomicAdd(&lcnt[rb ? big_mix(c) >> (32 - rb) : 0u], 1u);
+          tk[pos] = c;
+          tv[pos] = lv[sl];
+          lk[sl] = kNone;
+          lv[sl] = 0;
+        }
+        __syncthreads();
+        for (uint32_t q = threadIdx.x; q <= R; q += kBlock) lcnt[q] = 0;
         __syncthreads();
       }
     }
     self = block_sum(self, red);
-    if (threadIdx.x == 0 && self) table_add(tk, tv, b.mask, b.c, self, kRowSalt);
+    if (threadIdx.x == 0 && self) atomicAdd(&self_acc[x.big], self);
   }
   if (threadIdx.x == 0 && units && entries) atomicAdd(units, entries);
 }
 
-__global__ __launch_bounds__(kBlock) void k_agg_big_compact(const BigComm* bc, const AggItem* items, uint32_t nitems,
-                                                            const uint32_t* gkeys, const unsigned long long* gvals,
-                                                            const uint64_t* cap_off, uint32_t* out_len,
-                                                            uint32_t* out_cols, int64_t* out_w, int64_t* Kout) {
-  __shared__ unsigned int s_cnt, s_base;
+// Block (x, y): groups y, y + nseg, ... of the communities x, x + gridDim.x,
+// ... of the round.  A community's buckets are taken in G = 2^gb groups of
+// consecutive buckets, G the smallest power of two with about 2^kBigBucketBits
+// staged entries per group.  A group's runs (one per stage column) are summed
+// in an LDS table sized for the group; should the group hold more distinct
+// keys than the table, it is taken in 2^q sub-groups by the next q bits of the
+// same mixing (a bijection, so distinct keys eventually part).  Each group
+// reserves its part of the super row with one atomic; block y = 0 also adds
+// the community's own key.
+__global__ __launch_bounds__(kBlock) void k_agg_emit(const BigComm* bc, uint32_t nbig, const uint32_t* skeys,
+                                                     const unsigned long long* svals, const uint16_t* smat,
+                                                     const unsigned int* stage_cnt,
+                                                     const unsigned long long* self_acc, const uint64_t* cap_off,
+                                                     uint32_t* out_len, uint32_t* out_cols, int64_t* out_w,
+                                                     int64_t* Kout) {
+  __shared__ uint32_t tk[kBigSlots];
+  __shared__ unsigned long long tv[kBigSlots];
+  __shared__ unsigned int rpre[kEmitWin];
+  __shared__ uint16_t rst[kEmitWin];
+  __shared__ unsigned int wsum[kBlock / kWave];
   __shared__ unsigned long long red[kBlock / kWave];
-  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const AggItem x = items[it];
-    const BigComm b = bc[x.big];
+  __shared__ unsigned int full, nout, obase;
+  bool clean = false;
+  const uint32_t y = blockIdx.y;
+  for (uint32_t r = blockIdx.x; r < nbig; r += gridDim.x) {
+    const BigComm b = bc[r];
+    const uint32_t rb = b.rbits, R = 1u << rb;
+    const uint32_t nst = stage_cnt[r];
+    const uint16_t* mat = smat + b.moff;
     const uint64_t o = cap_off[b.c];
-    unsigned long long ksum = 0;
-    for (uint64_t sb = x.a; sb < x.b; sb += kBlock) {
-      const uint64_t sl = sb + threadIdx.x;
-      uint32_t d = kNone;
-      unsigned long long w = 0;
-      if (sl < x.b) {
-        d = gkeys[b.toff + sl];
-        w = gvals[b.toff + sl];
+    if (y == 0 && threadIdx.x == 0) {
+      const unsigned long long self = self_acc[r];
+      if (self) {
+        const unsigned int p = atomicAdd(&out_len[b.c], 1u);
+        out_cols[o + p] = b.c;
+        out_w[o + p] = (int64_t)self;
+        atomicAdd((unsigned long long*)&Kout[b.c], self);
       }
-      if (threadIdx.x == 0) s_cnt = 0;
-      __syncthreads();
-      unsigned int pos = 0;
-      if (d != kNone) pos = atomicAdd(&s_cnt, 1u);
-      __syncthreads();
-      if (threadIdx.x == 0 && s_cnt) s_base = atomicAdd(&out_len[b.c], s_cnt);
-      __syncthreads();
-      if (d != kNone) {
-        out_cols[o + s_base + pos] = d;
-        out_w[o + s_base + pos] = (int64_t)w;
-        ksum += w;
-      }
-      __syncthreads();
     }
-    ksum = block_sum(ksum, red);
-    if (threadIdx.x == 0 && ksum) atomicAdd((unsigned long long*)&Kout[b.c], ksum);
+    unsigned long long tot = 0;
+    for (uint32_t c = threadIdx.x; c < nst; c += kBlock) tot += mat[(size_t)R * b.smax + c];
+    tot = block_sum(tot, red);
+    uint32_t gb = 0;
+    while (gb < rb && ((unsigned long long)1 << (kBigBucketBits + gb)) < tot) ++gb;
+    const uint32_t G = 1u << gb, span = rb - gb;
+    const uint32_t nseg = min(G, gridDim.y);
+    if (y >= nseg) continue;  // block-uniform
+    if (!clean) {
+      for (uint32_t sl = threadIdx.x; sl < kBigSlots; sl += kBlock) {
+        tk[sl] = kNone;
+        tv[sl] = 0;
+      }
+      __syncthreads();
+      clean = true;
+    }
+    for (uint32_t grp = y; grp < G; grp += nseg) {
+      const uint32_t b0 = grp << span, b1 = (grp + 1) << span;
+      for (uint32_t q = 0;; ++q) {  // sub-group bits
+        bool fits = true;
+        for (uint32_t sub = 0; sub < (1u << q) && fits; ++sub) {
+          uint32_t mask = kBigSlots - 1;
+          if (threadIdx.x == 0) {
+            full = 0;
+            nout = 0;
+          }
+          for (uint32_t c0 = 0; c0 < nst; c0 += kEmitWin) {
+            const uint32_t cw = min(kEmitWin, nst - c0);
+            for (uint32_t i = threadIdx.x; i < cw; i += kBlock) {
+              const uint32_t s0 = mat[(size_t)b0 * b.smax + c0 + i], s1 = mat[(size_t)b1 * b.smax + c0 + i];
+              rst[i] = (uint16_t)s0;
+              rpre[i] = s1 - s0;
+            }
+            __syncthreads();
+            const uint32_t n = block_exclusive_scan<kEmitWin / kBlock>(rpre, cw, wsum);
+            if (nst <= kEmitWin) mask = min(kBigSlots, pow2_at_least(2 * n)) - 1;
+            for (uint32_t xx = threadIdx.x; xx < n; xx += kBlock) {
+              uint32_t lo = 0, hi = cw - 1;
+              while (lo < hi) {
+                const uint32_t mid = (lo + hi + 1) >> 1;
+                if (rpre[mid] <= xx)
+                  lo = mid;
+                else
+                  hi = mid - 1;
+              }
+              const size_t pos = b.soff + (size_t)(c0 + lo) * kBigStage + rst[lo] + (xx - rpre[lo]);
+              const uint32_t c = skeys[pos];
+              if (q && ((big_mix(c) << gb) >> (32 - q)) != sub) continue;
+              if (!table_add_bounded(tk, tv, mask, c, svals[pos], kRowSalt)) full = 1;
+            }
+            __syncthreads();
+          }
+          fits = full == 0;
+          unsigned long long ksum = 0;
+          if (fits) {
+            for (uint32_t sl = threadIdx.x; sl <= mask; sl += kBlock)
+              if (tk[sl] != kNone) {
+                atomicAdd(&nout, 1u);
+                ksum += tv[sl];
+              }
+          }
+          ksum = block_sum(ksum, red);
+          if (fits && threadIdx.x == 0 && nout) {
+            obase = atomicAdd(&out_len[b.c], nout);
+            atomicAdd((unsigned long long*)&Kout[b.c], ksum);
+            nout = 0;
+          }
+          __syncthreads();
+          for (uint32_t sl = threadIdx.x; sl <= mask; sl += kBlock) {
+            const uint32_t c = tk[sl];
+            if (c == kNone) continue;
+            if (fits) {
+              const unsigned int p = obase + atomicAdd(&nout, 1u);
+              out_cols[o + p] = c;
+              out_w[o + p] = (int64_t)tv[sl];
+            }
+            tk[sl] = kNone;
+            tv[sl] = 0;
+          }
+          __syncthreads();
+        }
+        if (fits) break;
+      }
+    }
   }
 }
 
 __global__ void k_zero_misc_agg(Ctl* ctl) {
   if (threadIdx.x < 3) ctl->misc[2 + threadIdx.x] = 0;
-}
-
-static uint64_t next_pow2(uint64_t x) {
-  uint64_t p = 1;
-  while (p < x) p <<= 1;
-  return p;
 }
 
 template <typename W>
@@ -810,7 +929,7 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
   hipLaunchKernelGGL((k_agg_lds<kBlock, 4096, W>), dim3(grid_n(nc, 1, 2048)), dim3(kBlock), 0, s, g, C, b.members,
                      b.comm_off, b.small_lists + (size_t)nc, &ctl->misc[3], (const uint64_t*)out_start, out_len,
                      out_cols, out_w, Kout);
-  // big communities: plan global tables on the host
+  // big communities: plan staging areas on the host
   unsigned int* pn = (unsigned int*)pinned_stage(4);
   if (!pn) return -1;
   (void)hipMemcpyAsync(pn, &ctl->misc[4], sizeof(unsigned int), hipMemcpyDeviceToHost, s);
@@ -819,8 +938,8 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
   if (nbig == 0) return 0;
   const uint32_t* big = b.small_lists + 2 * (size_t)nc;
   hipLaunchKernelGGL(k_big_info, dim3(grid_n(nbig)), dim3(kBlock), 0, s, big, &ctl->misc[4], b.comm_off, b.cap_off,
-                     b.big_info);
-  const size_t ib = sizeof(uint64_t) * 3 * nbig, idb = sizeof(uint32_t) * nbig;
+                     b.comm_deg, b.big_info);
+  const size_t ib = sizeof(uint64_t) * 4 * nbig, idb = sizeof(uint32_t) * nbig;
   char* st = (char*)pinned_stage(ib + idb);
   if (!st) return -1;
   (void)hipMemcpyAsync(st, b.big_info, ib, hipMemcpyDeviceToHost, s);
@@ -828,52 +947,57 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
   if (hipStreamSynchronize(s) != hipSuccess) return -1;
   const std::vector<uint64_t> info((const uint64_t*)st, (const uint64_t*)(st + ib));
   const std::vector<uint32_t> ids((const uint32_t*)(st + ib), (const uint32_t*)(st + ib + idb));
-  constexpr uint64_t kMemChunk = 256, kSlotChunk = 4096;
-  const uint64_t item_cap = b.item_cap;
   uint32_t first = 0;
   while (first < nbig) {
-    // a round: as many communities as their tables (and work items) fit
+    // a round: as many communities as their staging areas, matrices and
+    // work items fit
     std::vector<BigComm> rc;
-    std::vector<AggItem> ins, cmp;
-    uint64_t used = 0;
+    std::vector<AggItem> ins;
+    uint64_t used = 0, mused = 0;
     uint32_t last = first;
+    uint32_t max_rb = 0;
     while (last < nbig) {
-      const uint64_t m0 = info[3 * last], m1 = info[3 * last + 1], cap = info[3 * last + 2];
-      const uint64_t t = next_pow2(2 * cap);
-      const uint64_t nitems = (m1 - m0 + kMemChunk - 1) / kMemChunk + (t + kSlotChunk - 1) / kSlotChunk;
-      if (t > b.gcap || nitems > item_cap) return -2;
-      if (last > first && (used + t > b.gcap || ins.size() + cmp.size() + nitems > item_cap)) break;
+      const uint64_t m0 = info[4 * last], m1 = info[4 * last + 1], cap = info[4 * last + 2], deg = info[4 * last + 3];
+      const uint64_t nitems = (m1 - m0 + kBigMembers - 1) / kBigMembers;
+      // every item's stages hold at most kBigStage entries: deg / kBigStage + one partial stage per item
+      const uint64_t smax = deg / kBigStage + nitems + 1;
+      uint32_t rb = 0;
+      while (rb < kBigMaxRbits && ((uint64_t)1 << (kBigBucketBits + rb)) < std::min(cap, deg)) ++rb;
+      const uint64_t slots = smax * kBigStage, ment = (((uint64_t)1 << rb) + 1) * smax;
+      if (slots > b.scap || ment > b.mcap || nitems > b.item_cap) return -2;
+      if (last > first && (used + slots > b.scap || mused + ment > b.mcap || ins.size() + nitems > b.item_cap))
+        break;
       const uint32_t r = (uint32_t)rc.size();
-      rc.push_back(BigComm{ids[last], (uint32_t)(t - 1), used});
-      for (uint64_t a = m0; a < m1; a += kMemChunk) ins.push_back(AggItem{r, 0, a, std::min(m1, a + kMemChunk)});
-      for (uint64_t a = 0; a < t; a += kSlotChunk) cmp.push_back(AggItem{r, 0, a, std::min(t, a + kSlotChunk)});
-      used += t;
+      rc.push_back(BigComm{ids[last], rb, (uint32_t)smax, 0, used, mused});
+      for (uint64_t a = m0; a < m1; a += kBigMembers) ins.push_back(AggItem{r, 0, a, std::min(m1, a + kBigMembers)});
+      used += slots;
+      mused += ment;
+      max_rb = std::max(max_rb, rb);
       ++last;
     }
+    const uint32_t nr = (uint32_t)rc.size();
     AggItem* di = (AggItem*)b.items;
     // through pinned memory: the copies queue behind the kernels instead of
     // each waiting for the stream (the round ends with a synchronisation)
-    const size_t rb = sizeof(BigComm) * rc.size(), ib2 = sizeof(AggItem) * ins.size(),
-                 cb = sizeof(AggItem) * cmp.size();
-    char* hs = (char*)pinned_stage(rb + ib2 + cb);
+    const size_t rb_bytes = sizeof(BigComm) * nr, ib2 = sizeof(AggItem) * ins.size();
+    char* hs = (char*)pinned_stage(rb_bytes + ib2);
     if (!hs) return -1;
-    std::memcpy(hs, rc.data(), rb);
-    std::memcpy(hs + rb, ins.data(), ib2);
-    std::memcpy(hs + rb + ib2, cmp.data(), cb);
-    (void)hipMemcpyAsync(b.bigc, hs, rb, hipMemcpyHostToDevice, s);
-    (void)hipMemcpyAsync(di, hs + rb, ib2, hipMemcpyHostToDevice, s);
-    (void)hipMemcpyAsync(di + ins.size(), hs + rb + ib2, cb, hipMemcpyHostToDevice, s);
-    fill_u32(s, b.gkeys, kNone, used);
-    fill_u64(s, (uint64_t*)b.gvals, 0, used);
+    std::memcpy(hs, rc.data(), rb_bytes);
+    std::memcpy(hs + rb_bytes, ins.data(), ib2);
+    (void)hipMemcpyAsync(b.bigc, hs, rb_bytes, hipMemcpyHostToDevice, s);
+    (void)hipMemcpyAsync(di, hs + rb_bytes, ib2, hipMemcpyHostToDevice, s);
+    fill_u32(s, b.stage_cnt, 0, nr);
+    fill_u64(s, (uint64_t*)b.self_acc, 0, nr);
     // the input graph's big communities are timed as LEIDEN_KT_AGG_BIG
     const bool timed = sizeof(W) == 4;
     if (timed) kt_mark(LEIDEN_KT_AGG_BIG, s);
-    hipLaunchKernelGGL(k_agg_big_insert<W>, dim3(std::min<size_t>(ins.size(), 4096)), dim3(kBlock), 0, s, g, C,
-                       b.members, (const BigComm*)b.bigc, di, (uint32_t)ins.size(), b.gkeys, b.gvals,
-                       timed ? &ctl->kt_units[LEIDEN_KT_AGG_BIG] : nullptr);
+    hipLaunchKernelGGL(k_agg_stage<W>, dim3(std::min<size_t>(ins.size(), 4096)), dim3(kBlock), 0, s, g, C, b.members,
+                       (const BigComm*)b.bigc, di, (uint32_t)ins.size(), b.skeys, b.svals, b.smat, b.stage_cnt,
+                       b.self_acc, timed ? &ctl->kt_units[LEIDEN_KT_AGG_BIG] : nullptr);
     if (timed) kt_mark(LEIDEN_KT_AGG_BIG, s);
-    hipLaunchKernelGGL(k_agg_big_compact, dim3(std::min<size_t>(cmp.size(), 4096)), dim3(kBlock), 0, s,
-                       (const BigComm*)b.bigc, di + ins.size(), (uint32_t)cmp.size(), b.gkeys, b.gvals,
+    const uint32_t gy = std::min<uint32_t>(16, 1u << max_rb);
+    hipLaunchKernelGGL(k_agg_emit, dim3(std::min<uint32_t>(nr, 1024), gy), dim3(kBlock), 0, s,
+                       (const BigComm*)b.bigc, nr, b.skeys, b.svals, b.smat, b.stage_cnt, b.self_acc,
                        (const uint64_t*)out_start, out_len, out_cols, out_w, Kout);
     if (hipStreamSynchronize(s) != hipSuccess) return -1;  // host vectors must outlive the copies
     first = last;

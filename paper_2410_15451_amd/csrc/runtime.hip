@@ -114,7 +114,7 @@ struct leiden_graph {
   Buf flag, newid, scan_tmp, ctl, small;
   Buf lvA_start, lvA_len, lvA_cols, lvA_w, lvB_start, lvB_len, lvB_cols, lvB_w;
   Buf agg_count, agg_off, agg_fill, agg_members, agg_deg, agg_cap, agg_lists, agg_bigcap, agg_tbl, agg_keys, agg_vals,
-      agg_items, mark_items;
+      agg_mat, agg_items, mark_items;
   Buf hub_keys, hub_vals, hub_list, hub_idx, hub_off, hub_moff, hub_rbits, hub_size, hub_msize, hub_kid;
   Buf hub_items, hub_mat, hub_live, hub_pdq, hub_pc, hub_done;
   Buf tr_minv, tr_hk, tr_hv, tr_bw, tr_bv, tr_cw, tr_cb, tr_old, tr_flag, tr_rank, tr_frank, tr_fid, tr_label,
@@ -256,13 +256,16 @@ leiden_status ensure_workspace(leiden_graph* G, uint32_t classes) {
   CHK(G->agg_deg.reserve(n * u64));
   CHK(G->agg_cap.reserve((n + 1) * u64));
   CHK(G->agg_lists.reserve(3 * n * u32));
-  CHK(G->agg_bigcap.reserve(3 * n * u64));
-  CHK(G->agg_tbl.reserve(n * 16));
+  CHK(G->agg_bigcap.reserve(4 * n * u64));
+  CHK(G->agg_tbl.reserve(n * 48));  // per-round descriptors (32 B) and counters (4 + 8 B) of big communities
   CHK(G->agg_items.reserve(kAggItems * 24));
   CHK(G->mark_items.reserve((nnz / 64 + n + 1) * 8));
-  const uint64_t gcap = std::max<uint64_t>(2 * next_pow2(2 * n), 1 << 16);
-  CHK(G->agg_keys.reserve(gcap * u32));
-  CHK(G->agg_vals.reserve(gcap * u64));
+  // staging for the big communities of an aggregation: every entry once, plus
+  // one partial stage per work item of 256 members and per community
+  const uint64_t scap = nnz + 8 * (uint64_t)n + (1 << 16);
+  CHK(G->agg_keys.reserve(scap * u32));
+  CHK(G->agg_vals.reserve(scap * u64));
+  CHK(G->agg_mat.reserve((scap + scap / 1024 + 4096) * 2));
   const uint64_t hslots = next_pow2(2 * n);
   CHK(G->tr_minv.reserve(n * u32));
   CHK(G->tr_hk.reserve(hslots * u64));
@@ -599,9 +602,13 @@ leiden_status next_level(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
   ab.bigc = G->agg_tbl.p;
   ab.items = G->agg_items.p;
   ab.item_cap = kAggItems;
-  ab.gkeys = G->agg_keys.as<uint32_t>();
-  ab.gvals = G->agg_vals.as<unsigned long long>();
-  ab.gcap = G->agg_keys.bytes / 4;
+  ab.stage_cnt = (unsigned int*)((char*)G->agg_tbl.p + 32 * (size_t)G->n);
+  ab.self_acc = (unsigned long long*)((char*)G->agg_tbl.p + 40 * (size_t)G->n);
+  ab.skeys = G->agg_keys.as<uint32_t>();
+  ab.svals = G->agg_vals.as<unsigned long long>();
+  ab.smat = G->agg_mat.as<uint16_t>();
+  ab.scap = G->agg_keys.bytes / 4;
+  ab.mcap = G->agg_mat.bytes / 2;
   // K of the next level goes to whichever of the two K buffers is not current
   int64_t* Kn = L.K == G->K.as<int64_t>() ? G->Kb.as<int64_t>() : G->K.as<int64_t>();
   int rc = aggregate<W>(s, g, nl, L.C, (uint32_t)nc, ab, bs.as<int64_t>(), bl.as<uint32_t>(), bc.as<uint32_t>(),
@@ -868,7 +875,7 @@ const char* leiden_kernel_name(int32_t kernel) {
     case LEIDEN_KT_HUB_INSERT:
       return "lm::k_hub_chunk<unsigned int, false>";
     case LEIDEN_KT_AGG_BIG:
-      return "lm::k_agg_big_insert<unsigned int>";
+      return "lm::k_agg_stage<unsigned int>";
     default:
       return nullptr;
   }
