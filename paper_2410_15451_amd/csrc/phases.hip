@@ -644,7 +644,7 @@ __global__ __launch_bounds__(kBlock) void k_agg_lds(Rows<W> g, const uint32_t* C
 // buckets over all columns in an LDS table and writes the distinct keys into
 // the super row.
 constexpr uint32_t kBigMembers = 256, kBigStage = 2048, kBigSlots = 4096;
-constexpr uint32_t kBigBucketBits = 10, kBigMaxRbits = 11, kEmitWin = 2048;
+constexpr uint32_t kBigBucketBits = 10, kBigMaxRbits = 11, kEmitWin = 2048, kEmitSlices = 256;
 
 struct BigComm {
   uint32_t c;      // community
@@ -775,8 +775,9 @@ __global__ __launch_bounds__(kBlock) void k_agg_stage(Rows<W> g, const uint32_t*
   if (threadIdx.x == 0 && units && entries) atomicAdd(units, entries);
 }
 
-// Block (x, y): groups y, y + nseg, ... of the communities x, x + gridDim.x,
-// ... of the round.  A community's buckets are taken in G = 2^gb groups of
+// Work items (community r, slice y of nseg): groups y, y + nseg, ... of
+// community r, so a community with many groups gets many blocks.  A
+// community's buckets are taken in G = 2^gb groups of
 // consecutive buckets, G the smallest power of two with about 2^kBigBucketBits
 // staged entries per group.  A group's runs (one per stage column) are summed
 // in an LDS table sized for the group; should the group hold more distinct
@@ -784,7 +785,8 @@ __global__ __launch_bounds__(kBlock) void k_agg_stage(Rows<W> g, const uint32_t*
 // same mixing (a bijection, so distinct keys eventually part).  Each group
 // reserves its part of the super row with one atomic; block y = 0 also adds
 // the community's own key.
-__global__ __launch_bounds__(kBlock) void k_agg_emit(const BigComm* bc, uint32_t nbig, const uint32_t* skeys,
+__global__ __launch_bounds__(kBlock) void k_agg_emit(const BigComm* bc, const AggItem* items, uint32_t nitems,
+                                                     const uint32_t* skeys,
                                                      const unsigned long long* svals, const uint16_t* smat,
                                                      const unsigned int* stage_cnt,
                                                      const unsigned long long* self_acc, const uint64_t* cap_off,
@@ -798,8 +800,9 @@ __global__ __launch_bounds__(kBlock) void k_agg_emit(const BigComm* bc, uint32_t
   __shared__ unsigned long long red[kBlock / kWave];
   __shared__ unsigned int full, nout, obase;
   bool clean = false;
-  const uint32_t y = blockIdx.y;
-  for (uint32_t r = blockIdx.x; r < nbig; r += gridDim.x) {
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const AggItem x = items[it];
+    const uint32_t r = x.big, y = x.pad, nslice = (uint32_t)x.a;
     const BigComm b = bc[r];
     const uint32_t rb = b.rbits, R = 1u << rb;
     const uint32_t nst = stage_cnt[r];
@@ -820,7 +823,7 @@ __global__ __launch_bounds__(kBlock) void k_agg_emit(const BigComm* bc, uint32_t
     uint32_t gb = 0;
     while (gb < rb && ((unsigned long long)1 << (kBigBucketBits + gb)) < tot) ++gb;
     const uint32_t G = 1u << gb, span = rb - gb;
-    const uint32_t nseg = min(G, gridDim.y);
+    const uint32_t nseg = min(G, nslice);
     if (y >= nseg) continue;  // block-uniform
     if (!clean) {
       for (uint32_t sl = threadIdx.x; sl < kBigSlots; sl += kBlock) {
@@ -953,9 +956,8 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
     // work items fit
     std::vector<BigComm> rc;
     std::vector<AggItem> ins;
-    uint64_t used = 0, mused = 0;
+    uint64_t used = 0, mused = 0, nemitted = 0;
     uint32_t last = first;
-    uint32_t max_rb = 0;
     while (last < nbig) {
       const uint64_t m0 = info[4 * last], m1 = info[4 * last + 1], cap = info[4 * last + 2], deg = info[4 * last + 3];
       const uint64_t nitems = (m1 - m0 + kBigMembers - 1) / kBigMembers;
@@ -964,18 +966,26 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
       uint32_t rb = 0;
       while (rb < kBigMaxRbits && ((uint64_t)1 << (kBigBucketBits + rb)) < std::min(cap, deg)) ++rb;
       const uint64_t slots = smax * kBigStage, ment = (((uint64_t)1 << rb) + 1) * smax;
-      if (slots > b.scap || ment > b.mcap || nitems > b.item_cap) return -2;
-      if (last > first && (used + slots > b.scap || mused + ment > b.mcap || ins.size() + nitems > b.item_cap))
+      const uint64_t nemit = std::min<uint64_t>(kEmitSlices, (uint64_t)1 << rb);
+      if (slots > b.scap || ment > b.mcap || nitems + nemit > b.item_cap) return -2;
+      if (last > first &&
+          (used + slots > b.scap || mused + ment > b.mcap || ins.size() + nemitted + nitems + nemit > b.item_cap))
         break;
       const uint32_t r = (uint32_t)rc.size();
       rc.push_back(BigComm{ids[last], rb, (uint32_t)smax, 0, used, mused});
       for (uint64_t a = m0; a < m1; a += kBigMembers) ins.push_back(AggItem{r, 0, a, std::min(m1, a + kBigMembers)});
       used += slots;
       mused += ment;
-      max_rb = std::max(max_rb, rb);
+      nemitted += nemit;
       ++last;
     }
     const uint32_t nr = (uint32_t)rc.size();
+    const size_t nins = ins.size();
+    // emit items: (community, slice of up to kEmitSlices) after the stage items
+    for (uint32_t r = 0; r < nr; ++r) {
+      const uint32_t ns = std::min<uint32_t>(kEmitSlices, 1u << rc[r].rbits);
+      for (uint32_t y = 0; y < ns; ++y) ins.push_back(AggItem{r, y, ns, 0});
+    }
     AggItem* di = (AggItem*)b.items;
     // through pinned memory: the copies queue behind the kernels instead of
     // each waiting for the stream (the round ends with a synchronisation)
@@ -991,13 +1001,13 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
     // the input graph's big communities are timed as LEIDEN_KT_AGG_BIG
     const bool timed = sizeof(W) == 4;
     if (timed) kt_mark(LEIDEN_KT_AGG_BIG, s);
-    hipLaunchKernelGGL(k_agg_stage<W>, dim3(std::min<size_t>(ins.size(), 4096)), dim3(kBlock), 0, s, g, C, b.members,
-                       (const BigComm*)b.bigc, di, (uint32_t)ins.size(), b.skeys, b.svals, b.smat, b.stage_cnt,
+    hipLaunchKernelGGL(k_agg_stage<W>, dim3(std::min<size_t>(nins, 4096)), dim3(kBlock), 0, s, g, C, b.members,
+                       (const BigComm*)b.bigc, di, (uint32_t)nins, b.skeys, b.svals, b.smat, b.stage_cnt,
                        b.self_acc, timed ? &ctl->kt_units[LEIDEN_KT_AGG_BIG] : nullptr);
     if (timed) kt_mark(LEIDEN_KT_AGG_BIG, s);
-    const uint32_t gy = std::min<uint32_t>(16, 1u << max_rb);
-    hipLaunchKernelGGL(k_agg_emit, dim3(std::min<uint32_t>(nr, 1024), gy), dim3(kBlock), 0, s,
-                       (const BigComm*)b.bigc, nr, b.skeys, b.svals, b.smat, b.stage_cnt, b.self_acc,
+    const size_t nemit = ins.size() - nins;
+    hipLaunchKernelGGL(k_agg_emit, dim3(std::min<size_t>(nemit, 8192)), dim3(kBlock), 0, s, (const BigComm*)b.bigc,
+                       di + nins, (uint32_t)nemit, b.skeys, b.svals, b.smat, b.stage_cnt, b.self_acc,
                        (const uint64_t*)out_start, out_len, out_cols, out_w, Kout);
     if (hipStreamSynchronize(s) != hipSuccess) return -1;  // host vectors must outlive the copies
     first = last;
