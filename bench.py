@@ -229,6 +229,39 @@ def run_temporal(args, binding, inputs):
             "by_fraction": out}
 
 
+def run_ablation(args, binding, inputs):
+    """Refinement and split ablations of Sections 4.2 and 4.3: the same DF
+    update stream replayed from one static result with the refinement
+    threshold tau_re = 0.1 .. 0.9, and with every community that is not
+    refined split (split-all) instead of only the marked ones; reports the
+    mean update time and the final modularity of each setting."""
+    import numpy as np
+    g = inputs.rmat(args.scale, seed=inputs.BASE_SEED + 2)
+    nb = inputs.batch_size_for(g.nnz, args.frac)
+    nbat = 10
+    batches = inputs.random_batch_stream(g.n, g.undirected_keys(), nb, nbat, seed=inputs.BASE_SEED + 2 + 2000)
+    settings = [("tau_re=%d/10" % k, {"tau_re": (k, 10)}) for k in range(1, 10)]
+    settings.append(("split_all (tau_re=6/10)", {"split_all": 1}))
+    out = {}
+    for name, kw in settings:
+        G = binding.Graph.from_csr(g)  # the same graph and static result for every setting
+        G.static()
+        ts = []
+        for d, i in batches:
+            t = time.perf_counter()
+            r = G.update(d, i, mode="df", **kw)
+            ts.append(time.perf_counter() - t)
+        out[name] = {"ms_per_update": 1e3 * float(np.mean(ts)), "q_final": r.q}
+        log("ablation %s: %.2f ms/update, q %.5f" % (name, out[name]["ms_per_update"], r.q))
+        G.close()
+    return {"metric": "ablation: DF update time and final modularity per refinement / split setting",
+            "value": out["tau_re=6/10"]["ms_per_update"], "unit": "ms/update", "n_gpus": 1,
+            "higher_is_better": False, "data": "synthetic", "dtype": "int64+f64",
+            "config": {"workload": "rmat%d_ablation" % args.scale, "n": g.n, "nnz": g.nnz,
+                       "batch_undirected_updates": nb, "updates": nbat, "value_is": "tau_re = 0.6"},
+            "by_setting": out}
+
+
 def run_serving(args, binding, inputs):
     """Tenant R-MAT graphs in a server under an HBM budget; a Poisson stream
     of DF update requests (sizes log-uniform, 80/20 insert/delete) at a rate
@@ -307,7 +340,8 @@ def main():
     ap.add_argument("--cpu-scale", type=int, default=20)
     ap.add_argument("--cpu-reps", type=int, default=24)
     ap.add_argument("--timed-kernel", default="agg_big", help="kernel timed with HIP events for the roofline")
-    ap.add_argument("--workload", default="rmat", choices=["rmat", "batched", "serving", "stability", "temporal"],
+    ap.add_argument("--workload", default="rmat",
+                    choices=["rmat", "batched", "serving", "stability", "temporal", "ablation"],
                     help="rmat: the 4M-vertex R-MAT DF stream (default); batched: many kNN graphs at once; "
                          "serving: tenant R-MAT graphs under a Poisson stream of update requests")
     ap.add_argument("--graphs", type=int, default=128, help="batched: number of kNN graphs")
@@ -338,6 +372,9 @@ def main():
         return
     if args.workload == "temporal":
         print(json.dumps(run_temporal(args, binding, inputs)), flush=True)
+        return
+    if args.workload == "ablation":
+        print(json.dumps(run_ablation(args, binding, inputs)), flush=True)
         return
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
