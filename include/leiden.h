@@ -63,7 +63,10 @@ typedef enum {
   LEIDEN_KT_AGG_BIG = 2
 } leiden_kernel;
 /* (LEIDEN_KT_HUB_INSERT is the kernel that sums chunks of hub rows by
- * community in LDS and merges them into per-hub tables.) */
+ * community in LDS and stages each chunk's distinct communities sorted by
+ * hash bucket; LEIDEN_KT_AGG_BIG is the kernel that does the same for 2048-
+ * entry stages of a large community's member rows.  leiden_kernel_name gives
+ * their profiler names.) */
 
 /* Parameters (defaults from Section 5.1.2). */
 typedef struct {
