@@ -50,7 +50,11 @@ struct Buf {
   }
   leiden_status reserve(size_t b) {
     if (b <= bytes) return LEIDEN_OK;
-    if (p) (void)hipFree(p);
+    // kernels queued earlier on any stream may still read the old block
+    if (p) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(p);
+    }
     p = nullptr;
     bytes = 0;
     size_t want = std::max<size_t>(b, 256);
@@ -203,8 +207,11 @@ void bind_graph(leiden_graph* G) {
 
 Rows<uint32_t> rows0(leiden_graph* G) { return Rows<uint32_t>{G->g.start, G->g.len, G->g.cols, G->g.w}; }
 
-// Allocate every n- and nnz-sized array a run needs.
-leiden_status ensure_workspace(leiden_graph* G, uint32_t classes) {
+// Allocate every n- and nnz-sized array a run needs.  Arrays that must start
+// zeroed are cleared on the call's stream s: a hipMemset on the null stream
+// is asynchronous to the host and not ordered with the non-blocking streams
+// the calls run on, so it could land after the first kernels of the call.
+leiden_status ensure_workspace(leiden_graph* G, hipStream_t s, uint32_t classes) {
   const size_t n = std::max<size_t>(G->n, 1);
   uint64_t nnz = std::max<uint64_t>(G->nnz, 1);
   if (G->ws_n >= n && G->ws_nnz >= nnz && G->ws_classes >= classes) return LEIDEN_OK;
@@ -228,8 +235,8 @@ leiden_status ensure_workspace(leiden_graph* G, uint32_t classes) {
   if (G->pend.bytes < n * u32) {
     CHK(G->pend.reserve(n * u32));
     CHK(G->unproc.reserve(n * u32));
-    HIPCHK(hipMemset(G->pend.p, 0, n * u32));
-    HIPCHK(hipMemset(G->unproc.p, 0, n * u32));
+    fill_u32(s, G->pend.as<uint32_t>(), 0, n);
+    fill_u32(s, G->unproc.as<uint32_t>(), 0, n);
   }
   CHK(G->cls_lists.reserve(n * u32 * classes));
   CHK(G->bin_lists.reserve(n * u32 * kBins));
@@ -913,7 +920,7 @@ leiden_status leiden_autotune(leiden_graph* G, const leiden_opts* opts, leiden_t
   CHK(check_opts(o));
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = stream_of(G, opts);
-  CHK(ensure_workspace(G, std::max(o.move_classes, o.refine_rounds)));
+  CHK(ensure_workspace(G, s, std::max(o.move_classes, o.refine_rounds)));
   const uint32_t n = G->n;
   // singleton start on the input graph
   zero_ctl(G, s);
@@ -1059,7 +1066,7 @@ leiden_status leiden_static(leiden_graph* G, const leiden_opts* opts, uint32_t* 
   hipStream_t s = stream_of(G, opts);
   if (stats) std::memset(stats, 0, sizeof(*stats));
   KtScope kts(G, o.timed_kernel);
-  CHK(ensure_workspace(G, std::max(o.move_classes, o.refine_rounds)));
+  CHK(ensure_workspace(G, s, std::max(o.move_classes, o.refine_rounds)));
   ScatterScope scs(G);
   hipEvent_t e0, e1, e2;
   HIPCHK(hipEventCreate(&e0));
@@ -1138,7 +1145,7 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   if (stats) std::memset(stats, 0, sizeof(*stats));
   KtScope kts(G, o.timed_kernel);
   const uint32_t n = G->n;
-  CHK(ensure_workspace(G, std::max(o.move_classes, o.refine_rounds)));
+  CHK(ensure_workspace(G, s, std::max(o.move_classes, o.refine_rounds)));
   ScatterScope scs(G);
   CHK(G->st_C.reserve((size_t)std::max<uint32_t>(n, 1) * 4));
   CHK(G->st_K.reserve((size_t)std::max<uint32_t>(n, 1) * 8));
@@ -1160,7 +1167,7 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   if (!G->rowcnt_ready) {
     CHK(G->bt_rowcnt.reserve(nn * 4));
     CHK(G->bt_rowidx.reserve(nn * 4));
-    HIPCHK(hipMemset(G->bt_rowcnt.p, 0, nn * 4));
+    fill_u32(s, G->bt_rowcnt.as<uint32_t>(), 0, nn);
     G->rowcnt_ready = true;
   }
   CHK(G->scan_tmp.reserve(scan_tmp_bytes(std::max<uint64_t>(nn, nE)) + 64));
@@ -1265,7 +1272,7 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   // level-0 degree bins after the batch
   CHK(level_bins(G, s, G->g.len, n, G->bins0, &G->maxdeg0));
   G->nnz = G->nnz - 2 * n_del + 2 * n_ins;
-  CHK(ensure_workspace(G, std::max(o.move_classes, o.refine_rounds)));  // nnz-sized scratch
+  CHK(ensure_workspace(G, s, std::max(o.move_classes, o.refine_rounds)));  // nnz-sized scratch
   HIPCHK(hipEventRecord(e1, s));
   // auxiliary state: restart or continue
   LevelState L = level_state(G);
@@ -1392,7 +1399,7 @@ leiden_status leiden_modularity(leiden_graph* G, const uint32_t* membership, int
   if (!G || !membership || !q_out) return fail(LEIDEN_EINVAL, "null argument");
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = G->own;
-  CHK(ensure_workspace(G, 8));
+  CHK(ensure_workspace(G, s, 8));
   const uint32_t n = G->n;
   uint32_t* C = G->C.as<uint32_t>();
   CHK(copy_in(s, C, membership, sizeof(uint32_t) * n, on_device));
@@ -1457,7 +1464,7 @@ leiden_status leiden_state_import(leiden_graph* G, const uint32_t* C, const int6
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = G->own;
   const uint32_t n = G->n;
-  CHK(ensure_workspace(G, 8));
+  CHK(ensure_workspace(G, s, 8));
   for (Buf* b : {&G->st_C}) CHK(b->reserve((size_t)std::max<uint32_t>(n, 1) * 4));
   for (Buf* b : {&G->st_K, &G->st_S, &G->st_dS}) CHK(b->reserve((size_t)std::max<uint32_t>(n, 1) * 8));
   // check on the host: labels < n, K = row sums, Sigma = sums of K by label

@@ -9,11 +9,7 @@ import pytest
 
 from paper_2410_15451_amd import inputs
 
-# A run of these tests (their first GPU run) ended with the GPU reported
-# faulted after the test session had finished; the cause is not shown yet, so
-# they stay off the GPU until it is.
-pytestmark = [pytest.mark.gpu,
-              pytest.mark.skip(reason="first GPU run ended with a GPU fault after the session; cause not shown yet")]
+pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
