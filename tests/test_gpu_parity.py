@@ -49,6 +49,45 @@ def test_static_rmat(lm, orc, scale, seed):
     _check_static(lm, orc, g, "rmat%d" % scale)
 
 
+def _fmix32(x):
+    """MurmurHash3's 32-bit finaliser, vectorised (the mixing the kernels use
+    to bucket a hub's communities)."""
+    h = np.asarray(x, dtype=np.uint64) & np.uint64(0xFFFFFFFF)
+    h ^= h >> np.uint64(16)
+    h = (h * np.uint64(0x85EBCA6B)) & np.uint64(0xFFFFFFFF)
+    h ^= h >> np.uint64(13)
+    h = (h * np.uint64(0xC2B2AE35)) & np.uint64(0xFFFFFFFF)
+    h ^= h >> np.uint64(16)
+    return h
+
+
+def test_static_hub_bucket_overflow(lm, orc):
+    """A hub of degree 8000 (8 hash buckets) whose neighbours all land in
+    bucket 0 (top three bits of the mixing zero): in the first sub-round
+    every neighbour is still a singleton, so the pick's first group holds
+    8000 distinct communities, more than its LDS table, and must be taken in
+    sub-groups by further bits.  The result must still be the oracle's."""
+    n = 1 << 17
+    ids = np.arange(n, dtype=np.uint64)
+    mix = _fmix32(ids)
+    hub = int(ids[(mix % np.uint64(8)) == 0][0])  # class 0 of the first iteration
+    cand = ids[((mix >> np.uint64(29)) == 0) & (ids != hub)][:8000]
+    assert cand.shape[0] == 8000
+    rng = np.random.default_rng(11)
+    others = np.setdiff1d(np.arange(n), [hub])
+    u = rng.choice(others, 3 * n)
+    v = rng.choice(others, 3 * n)
+    keep = u != v
+    key = np.unique(np.minimum(u[keep], v[keep]).astype(np.uint64) << np.uint64(32) |
+                    np.maximum(u[keep], v[keep]).astype(np.uint64))
+    bu = (key >> np.uint64(32)).astype(np.int64)
+    bv = (key & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    hu = np.full(8000, hub, np.int64)
+    g = inputs.csr_from_undirected(n, np.concatenate([bu, hu]), np.concatenate([bv, cand.astype(np.int64)]))
+    assert int(g.degrees()[hub]) == 8000
+    _check_static(lm, orc, g, "hub-bucket-overflow")
+
+
 @pytest.mark.parametrize("P,R", [(1, 1), (3, 5), (8, 8), (32, 2)])
 def test_static_schedule_parameters(lm, orc, P, R):
     g = inputs.rmat(11, seed=7)
