@@ -485,23 +485,67 @@ int batch_merge(hipStream_t s, int64_t* start, uint32_t* len, uint32_t* cap, uin
 // Alg. 11: K and Sigma by the old memberships; DeltaSigma counts deletions and
 // insertions alike.  Integer atomics, so the order of entries is irrelevant.
 // ---------------------------------------------------------------------------
+// A block sums a tile of kAuxTile entries per community in LDS first: a few
+// large communities collect most entries, and atomics on one address are
+// serialised device-wide, so per-wavefront sums still queued hundreds of
+// microseconds on Sigma of the largest communities.
+constexpr uint32_t kAuxTile = 1024, kAuxSlots = 2048;
+
 __global__ __launch_bounds__(kBlock) void k_aux_update(uint64_t ne, BatchBufs b, const uint32_t* Cprev, int64_t* K,
                                                        int64_t* S, int64_t* dSig) {
-  GRID_STRIDE(q, ne) {
-    const uint32_t i = b.seg_src[q];
-    const uint32_t c = Cprev[i];
-    const long long w = (long long)b.seg_w[q];
-    const long long sgn = b.seg_del[q] ? -w : w;
-    atomicAdd((unsigned long long*)&K[i], (unsigned long long)sgn);
-    // large communities collect many entries: one atomic per community and wavefront
-    wave_add2_by_key(c, sgn, w, (long long*)S, (long long*)dSig);
+  __shared__ uint32_t tk[kAuxSlots];
+  __shared__ unsigned long long ts[kAuxSlots], tw[kAuxSlots];
+  for (uint32_t sl = threadIdx.x; sl < kAuxSlots; sl += kBlock) {
+    tk[sl] = kNone;
+    ts[sl] = 0;
+    tw[sl] = 0;
+  }
+  __syncthreads();
+  for (uint64_t base = (uint64_t)blockIdx.x * kAuxTile; base < ne; base += (uint64_t)gridDim.x * kAuxTile) {
+    for (uint64_t q = base + threadIdx.x; q < base + kAuxTile; q += kBlock) {
+      uint32_t i = kNone, c = kNone;
+      long long w = 0, sgn = 0;
+      if (q < ne) {
+        i = b.seg_src[q];
+        c = Cprev[i];
+        w = (long long)b.seg_w[q];
+        sgn = b.seg_del[q] ? -w : w;
+      }
+      // entries are grouped by source: one atomic per vertex and wavefront
+      wave_add_by_key(i, sgn, (long long*)K);
+      if (c == kNone) continue;
+      uint32_t h = slot_hash(c, kAuxSlots - 1);
+      while (true) {
+        const uint32_t k = __atomic_load_n(&tk[h], __ATOMIC_RELAXED);
+        if (k == c) break;
+        if (k == kNone) {
+          const uint32_t o = atomicCAS(&tk[h], kNone, c);
+          if (o == kNone || o == c) break;
+        }
+        h = (h + 1) & (kAuxSlots - 1);
+      }
+      atomicAdd(&ts[h], (unsigned long long)sgn);
+      atomicAdd(&tw[h], (unsigned long long)w);
+    }
+    __syncthreads();
+    for (uint32_t sl = threadIdx.x; sl < kAuxSlots; sl += kBlock) {
+      const uint32_t c = tk[sl];
+      if (c == kNone) continue;
+      atomicAdd((unsigned long long*)&S[c], ts[sl]);
+      atomicAdd((unsigned long long*)&dSig[c], tw[sl]);
+      tk[sl] = kNone;
+      ts[sl] = 0;
+      tw[sl] = 0;
+    }
+    __syncthreads();
   }
 }
 
 void launch_aux_update(hipStream_t s, const BatchBufs& b, uint64_t n_entries, const uint32_t* Cprev, int64_t* K,
                        int64_t* S, int64_t* dSig) {
   if (n_entries)
-    hipLaunchKernelGGL(k_aux_update, dim3(grid_n(n_entries)), dim3(kBlock), 0, s, n_entries, b, Cprev, K, S, dSig);
+    hipLaunchKernelGGL(k_aux_update, dim3(grid_n(n_entries, kAuxTile, 2048)), dim3(kBlock), 0, s, n_entries, b, Cprev,
+                       K, S, dSig);
 }
 
 // Alg. 5 (dynamic branch): split flags for intra-community deletions; refine
@@ -653,20 +697,35 @@ void launch_mark_ds(hipStream_t s, const BatchBufs& b, uint64_t n_entries, uint6
 }
 
 // Flag array -> vertex list (order irrelevant), stamping each listed vertex.
+constexpr int kFlagsU = 8;  // flags per thread of a tile
 __global__ __launch_bounds__(kBlock) void k_flags_to_list(const uint8_t* flags, uint32_t n, uint32_t* list,
                                                           unsigned int* count, uint32_t* mark, uint32_t stamp) {
-  __shared__ unsigned int s2[2];
-  for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < n; base += (uint64_t)gridDim.x * kBlock) {
-    const uint64_t i = base + threadIdx.x;
-    const bool on = i < n && flags[i];
-    if (on) mark[i] = stamp;
-    block_append(list, count, on, (uint32_t)i, s2);
+  __shared__ unsigned int scnt[1], sbase[1];
+  if (threadIdx.x == 0) scnt[0] = 0;
+  __syncthreads();
+  constexpr uint32_t tile = kBlock * kFlagsU;
+  for (uint64_t base = (uint64_t)blockIdx.x * tile; base < n; base += (uint64_t)gridDim.x * tile) {
+    uint32_t key[kFlagsU], val[kFlagsU];
+#pragma unroll
+    for (int u = 0; u < kFlagsU; ++u) {
+      const uint64_t i = base + u * kBlock + threadIdx.x;
+      const bool on = i < n && flags[i];
+      if (on) mark[i] = stamp;
+      key[u] = on ? 0u : kNone;
+      val[u] = (uint32_t)i;
+    }
+    tile_append<kFlagsU>(key, val, 1, scnt, sbase, [&](uint32_t, uint32_t*& l, unsigned int*& c) {
+      l = list;
+      c = count;
+    });
   }
 }
 
 void launch_flags_to_list(hipStream_t s, const uint8_t* flags, uint32_t n, uint32_t* list, unsigned int* count,
                           uint32_t* mark, uint32_t stamp) {
-  if (n) hipLaunchKernelGGL(k_flags_to_list, dim3(grid_n(n)), dim3(kBlock), 0, s, flags, n, list, count, mark, stamp);
+  if (n)
+    hipLaunchKernelGGL(k_flags_to_list, dim3(grid_n(n, kBlock * kFlagsU)), dim3(kBlock), 0, s, flags, n, list, count,
+                       mark, stamp);
 }
 
 }  // namespace lm

@@ -353,19 +353,20 @@ __device__ inline void wave_add2_by_key(uint32_t key, long long va, long long vb
   }
 }
 
-// Block-wide append: every thread of the block calls this (block-uniform
-// control flow); threads with `pred` append `v`.  One global atomic per block.
-// `s2` is two words of shared memory.
-__device__ inline void block_append(uint32_t* list, unsigned int* count, bool pred, uint32_t v, unsigned int* s2) {
-  if (threadIdx.x == 0) s2[0] = 0;
-  __syncthreads();
-  unsigned int pos = 0;
-  if (pred) pos = atomicAdd(&s2[0], 1u);
-  __syncthreads();
-  if (threadIdx.x == 0 && s2[0]) s2[1] = atomicAdd(count, s2[0]);
-  __syncthreads();
-  if (pred) list[s2[1] + pos] = v;
-  __syncthreads();
+// wave_add2_by_key for one array.
+__device__ inline void wave_add_by_key(uint32_t key, long long va, long long* a) {
+  const uint32_t lane = threadIdx.x % kWave;
+  unsigned long long pending = __ballot(key != kNone);
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const uint32_t lk = __shfl(key, leader);
+    const unsigned long long mask = __ballot(key == lk) & pending;
+    long long sa = ((mask >> lane) & 1ull) ? va : 0;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) sa += __shfl_xor(sa, o);
+    if ((int)lane == leader) atomicAdd((unsigned long long*)&a[lk], (unsigned long long)sa);
+    pending &= ~mask;
+  }
 }
 
 // Keyed append of a block's tile.  Every thread of the block calls this

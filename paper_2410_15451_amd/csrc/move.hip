@@ -608,13 +608,25 @@ __global__ __launch_bounds__(kBlock) void k_hub_pick(DecideParams<W> p) {
   }
 }
 
+constexpr int kListU = 8;  // elements per thread of a tile
 __global__ __launch_bounds__(kBlock) void k_hub_list(const uint32_t* len, uint32_t nl, uint32_t hub_above,
                                                      uint32_t* list, Ctl* ctl) {
-  __shared__ unsigned int s2[2];
-  for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < nl; base += (uint64_t)gridDim.x * kBlock) {
-    const uint64_t i = base + threadIdx.x;
-    const bool hub = i < nl && len[i] > hub_above;
-    block_append(list, &ctl->misc[6], hub, (uint32_t)i, s2);
+  __shared__ unsigned int scnt[1], sbase[1];
+  if (threadIdx.x == 0) scnt[0] = 0;
+  __syncthreads();
+  constexpr uint32_t tile = kBlock * kListU;
+  for (uint64_t base = (uint64_t)blockIdx.x * tile; base < nl; base += (uint64_t)gridDim.x * tile) {
+    uint32_t key[kListU], val[kListU];
+#pragma unroll
+    for (int u = 0; u < kListU; ++u) {
+      const uint64_t i = base + u * kBlock + threadIdx.x;
+      key[u] = i < nl && len[i] > hub_above ? 0u : kNone;
+      val[u] = (uint32_t)i;
+    }
+    tile_append<kListU>(key, val, 1, scnt, sbase, [&](uint32_t, uint32_t*& l, unsigned int*& c) {
+      l = list;
+      c = &ctl->misc[6];
+    });
   }
 }
 
@@ -637,7 +649,7 @@ int hub_layout(hipStream_t s, const uint32_t* len, uint32_t nl, uint32_t hub_abo
                void* scan_tmp, uint64_t* total_dev, uint32_t* count_out, uint64_t* slots_out,
                uint64_t* mat_out) {
   hipLaunchKernelGGL(k_clear_misc6, dim3(1), dim3(1), 0, s, ctl);
-  hipLaunchKernelGGL(k_hub_list, dim3(grid_for(nl, kBlock, 4096)), dim3(kBlock), 0, s, len, nl, hub_above, h.list,
+  hipLaunchKernelGGL(k_hub_list, dim3(grid_for(nl, kBlock * kListU, 4096)), dim3(kBlock), 0, s, len, nl, hub_above, h.list,
                      ctl);
   unsigned int* pc = (unsigned int*)pinned_stage(4);
   if (!pc || hipMemcpyAsync(pc, &ctl->misc[6], sizeof(unsigned int), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -693,10 +705,39 @@ __device__ inline uint32_t mark_key(const ApplyParams& p, uint32_t j) {
 constexpr uint32_t kMarkChunk = kWave;
 constexpr int kMarkU = 8;  // marking items per wavefront of a tile
 
+// Community deltas of a block's movers are summed in LDS and added once per
+// community and iteration: movers gather in a few large communities, and
+// atomics on one address are serialised device-wide.
+constexpr uint32_t kApplySlots = 1024;
+__device__ inline void apply_delta(uint32_t* tk, unsigned long long* ts, unsigned int* tn, uint32_t c, long long ds,
+                                   int dn) {
+  uint32_t h = slot_hash(c, kApplySlots - 1);
+  while (true) {
+    const uint32_t k = __atomic_load_n(&tk[h], __ATOMIC_RELAXED);
+    if (k == c) break;
+    if (k == kNone) {
+      const uint32_t o = atomicCAS(&tk[h], kNone, c);
+      if (o == kNone || o == c) break;
+    }
+    h = (h + 1) & (kApplySlots - 1);
+  }
+  atomicAdd(&ts[h], (unsigned long long)ds);
+  atomicAdd(&tn[h], (unsigned int)dn);
+}
+
 __global__ __launch_bounds__(kBlock) void k_apply_moves(ApplyParams p) {
   __shared__ unsigned int wtot[kBlock / kWave];
   __shared__ unsigned int sbase;
   __shared__ unsigned long long red[kBlock / kWave];
+  __shared__ uint32_t tk[kApplySlots];
+  __shared__ unsigned long long ts[kApplySlots];
+  __shared__ unsigned int tn[kApplySlots];
+  for (uint32_t sl = threadIdx.x; sl < kApplySlots; sl += kBlock) {
+    tk[sl] = kNone;
+    ts[sl] = 0;
+    tn[sl] = 0;
+  }
+  __syncthreads();
   const uint32_t lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
   const uint32_t cnt = p.ctl->mover_count;
   long long dqsum = 0;
@@ -712,10 +753,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_moves(ApplyParams p) {
         const uint32_t d = p.C[v];
         const long long k = p.K[v];
         p.C[v] = mv.c;
-        atomicAdd((unsigned long long*)&p.S[d], (unsigned long long)(-k));
-        atomicAdd((unsigned long long*)&p.S[mv.c], (unsigned long long)k);
-        atomicSub(&p.size[d], 1u);
-        atomicAdd(&p.size[mv.c], 1u);
+        apply_delta(tk, ts, tn, d, -k, -1);
+        apply_delta(tk, ts, tn, mv.c, k, 1);
         dqsum += gain_fixed(mv.dq);
         if (p.dS) p.dS[d] = 1;
       }
@@ -738,6 +777,16 @@ __global__ __launch_bounds__(kBlock) void k_apply_moves(ApplyParams p) {
       total += t;
     }
     if (threadIdx.x == 0 && total) sbase = atomicAdd(&p.ctl->mark_items, total);
+    // the iteration's community deltas (every insert happened before the barrier above)
+    for (uint32_t sl = threadIdx.x; sl < kApplySlots; sl += kBlock) {
+      const uint32_t c = tk[sl];
+      if (c == kNone) continue;
+      if (ts[sl]) atomicAdd((unsigned long long*)&p.S[c], ts[sl]);
+      if (tn[sl]) atomicAdd(&p.size[c], tn[sl]);
+      tk[sl] = kNone;
+      ts[sl] = 0;
+      tn[sl] = 0;
+    }
     __syncthreads();
     const uint32_t first = sbase + before + incl - nch;
     for (uint32_t k = 0; k < nch; ++k) p.mark_items[first + k] = ((unsigned long long)v << 32) | k;

@@ -9,6 +9,8 @@
 
 namespace lm {
 
+constexpr int kTileU = 4;  // elements per thread of a list-building tile
+
 static int grid_n(uint64_t n, int per_block = kBlock, int cap = 8192) {
   uint64_t b = (n + per_block - 1) / per_block;
   if (b < 1) b = 1;
@@ -149,18 +151,30 @@ constexpr uint32_t kSplitSample = 4;
 __global__ __launch_bounds__(kBlock) void k_split_init(uint32_t n, const uint32_t* C, const uint8_t* dS,
                                                        const uint8_t* dR, uint32_t* lab, uint32_t* list,
                                                        unsigned long long* main_key, Ctl* ctl) {
-  __shared__ unsigned int s2[2];
-  for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < n; base += (uint64_t)gridDim.x * kBlock) {
-    const uint64_t i = base + threadIdx.x;
-    bool in = false;
-    if (i < n) {
-      const uint32_t c = C[i];
-      lab[i] = (uint32_t)i;
-      in = dS[c] && !dR[c];
-      // the label of a community is its minimum member: one writer per community
-      if (in && c == (uint32_t)i) main_key[c] = 0;
+  __shared__ unsigned int scnt[1], sbase[1];
+  if (threadIdx.x == 0) scnt[0] = 0;
+  __syncthreads();
+  constexpr uint32_t tile = kBlock * kTileU;
+  for (uint64_t base = (uint64_t)blockIdx.x * tile; base < n; base += (uint64_t)gridDim.x * tile) {
+    uint32_t key[kTileU], val[kTileU];
+#pragma unroll
+    for (int u = 0; u < kTileU; ++u) {
+      const uint64_t i = base + u * kBlock + threadIdx.x;
+      key[u] = kNone;
+      val[u] = (uint32_t)i;
+      if (i < n) {
+        const uint32_t c = C[i];
+        lab[i] = (uint32_t)i;
+        const bool in = dS[c] && !dR[c];
+        // the label of a community is its minimum member: one writer per community
+        if (in && c == (uint32_t)i) main_key[c] = 0;
+        if (in) key[u] = 0;
+      }
     }
-    block_append(list, &ctl->split_count, in, (uint32_t)i, s2);
+    tile_append<kTileU>(key, val, 1, scnt, sbase, [&](uint32_t, uint32_t*& l, unsigned int*& cn) {
+      l = list;
+      cn = &ctl->split_count;
+    });
   }
 }
 
@@ -235,21 +249,32 @@ __global__ __launch_bounds__(kBlock) void k_split_main(const uint32_t* len, cons
 __global__ __launch_bounds__(kBlock) void k_split_rest(uint32_t n, const uint32_t* C, const uint32_t* lab,
                                                        const uint32_t* list, const unsigned long long* main_key,
                                                        uint32_t* rest, Ctl* ctl) {
-  __shared__ unsigned int s2[2];
+  __shared__ unsigned int scnt[1], sbase[1];
+  if (threadIdx.x == 0) scnt[0] = 0;
+  __syncthreads();
   const uint32_t cnt = ctl->split_count;
-  for (uint32_t base = blockIdx.x * kBlock; base < cnt; base += gridDim.x * kBlock) {
-    const uint32_t it = base + threadIdx.x;
-    bool out = false;
-    uint32_t u = 0;
-    if (it < cnt) {
-      u = list[it];
-      const uint32_t c = C[u];
-      const unsigned long long key = main_key[c];
-      uint32_t m = key ? 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull) : c;
-      if (m >= n || C[m] != c) m = c;  // any choice is correct; this one is always in range
-      out = lab[u] != lab[m];  // both are roots after compression
+  constexpr uint32_t tile = kBlock * kTileU;
+  for (uint32_t base = blockIdx.x * tile; base < cnt; base += gridDim.x * tile) {
+    uint32_t kk[kTileU], val[kTileU];
+#pragma unroll
+    for (int q = 0; q < kTileU; ++q) {
+      const uint32_t it = base + q * kBlock + threadIdx.x;
+      kk[q] = kNone;
+      val[q] = 0;
+      if (it < cnt) {
+        const uint32_t u = list[it];
+        const uint32_t c = C[u];
+        const unsigned long long key = main_key[c];
+        uint32_t m = key ? 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull) : c;
+        if (m >= n || C[m] != c) m = c;  // any choice is correct; this one is always in range
+        if (lab[u] != lab[m]) kk[q] = 0;  // both are roots after compression
+        val[q] = u;
+      }
     }
-    block_append(rest, &ctl->split_rest, out, u, s2);
+    tile_append<kTileU>(kk, val, 1, scnt, sbase, [&](uint32_t, uint32_t*& l, unsigned int*& cn) {
+      l = rest;
+      cn = &ctl->split_rest;
+    });
   }
 }
 
@@ -294,7 +319,8 @@ void launch_split_init(hipStream_t s, uint32_t n, const uint32_t* C, const uint8
                        uint32_t* lab, uint32_t* list, unsigned long long* main_key, Ctl* ctl) {
   hipLaunchKernelGGL(k_split_reset, dim3(1), dim3(1), 0, s, ctl);
   if (n)
-    hipLaunchKernelGGL(k_split_init, dim3(grid_n(n)), dim3(kBlock), 0, s, n, C, dS, dR, lab, list, main_key, ctl);
+    hipLaunchKernelGGL(k_split_init, dim3(grid_n(n, kBlock * kTileU)), dim3(kBlock), 0, s, n, C, dS, dR, lab, list,
+                       main_key, ctl);
 }
 
 template <typename W>
@@ -303,7 +329,8 @@ void launch_split_sample(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* 
   hipLaunchKernelGGL((k_split_sample<W>), dim3(grid_n(n_upper)), dim3(kBlock), 0, s, g, C, lab, list, ctl);
   hipLaunchKernelGGL(k_split_compress, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, lab, list, ctl);
   hipLaunchKernelGGL(k_split_main, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, g.len, C, list, main_key, ctl);
-  hipLaunchKernelGGL(k_split_rest, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, n_upper, C, lab, list, main_key, rest,
+  hipLaunchKernelGGL(k_split_rest, dim3(grid_n(n_upper, kBlock * kTileU)), dim3(kBlock), 0, s, n_upper, C, lab, list,
+                     main_key, rest,
                      ctl);
 }
 
@@ -479,18 +506,29 @@ constexpr uint64_t kAggSmall = 128, kAggMedium = 2048;
 __global__ __launch_bounds__(kBlock) void k_comm_classify(uint32_t nc, const uint64_t* deg, uint64_t* cap,
                                                           uint32_t* out_len, int64_t* Kout, uint32_t* lists,
                                                           size_t stride, Ctl* ctl) {
-  __shared__ unsigned int s2[2];
-  for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < nc; base += (uint64_t)gridDim.x * kBlock) {
-    const uint64_t c = base + threadIdx.x;
-    int k = -1;
-    if (c < nc) {
-      const uint64_t d = deg[c];
-      cap[c] = d < nc ? d : nc;
-      out_len[c] = 0;
-      Kout[c] = 0;
-      if (d > 0) k = d <= kAggSmall ? 0 : (d <= kAggMedium ? 1 : 2);
+  __shared__ unsigned int scnt[3], sbase[3];
+  if (threadIdx.x < 3) scnt[threadIdx.x] = 0;
+  __syncthreads();
+  constexpr uint32_t tile = kBlock * kTileU;
+  for (uint64_t base = (uint64_t)blockIdx.x * tile; base < nc; base += (uint64_t)gridDim.x * tile) {
+    uint32_t key[kTileU], val[kTileU];
+#pragma unroll
+    for (int u = 0; u < kTileU; ++u) {
+      const uint64_t c = base + u * kBlock + threadIdx.x;
+      key[u] = kNone;
+      val[u] = (uint32_t)c;
+      if (c < nc) {
+        const uint64_t d = deg[c];
+        cap[c] = d < nc ? d : nc;
+        out_len[c] = 0;
+        Kout[c] = 0;
+        if (d > 0) key[u] = d <= kAggSmall ? 0u : (d <= kAggMedium ? 1u : 2u);
+      }
     }
-    for (int b = 0; b < 3; ++b) block_append(lists + (size_t)b * stride, &ctl->misc[2 + b], k == b, (uint32_t)c, s2);
+    tile_append<kTileU>(key, val, 3, scnt, sbase, [&](uint32_t b, uint32_t*& l, unsigned int*& cn) {
+      l = lists + (size_t)b * stride;
+      cn = &ctl->misc[2 + b];
+    });
   }
 }
 
@@ -922,7 +960,8 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
                      b.members);
   hipLaunchKernelGGL(k_zero_misc_agg, dim3(1), dim3(64), 0, s, ctl);
   // capacity per community -> super-row starts
-  hipLaunchKernelGGL(k_comm_classify, dim3(grid_n(nc)), dim3(kBlock), 0, s, nc, b.comm_deg, b.cap_off, out_len, Kout,
+  hipLaunchKernelGGL(k_comm_classify, dim3(grid_n(nc, kBlock * kTileU)), dim3(kBlock), 0, s, nc, b.comm_deg, b.cap_off,
+                     out_len, Kout,
                      b.small_lists, (size_t)nc, ctl);
   exclusive_scan_u64(s, b.cap_off, (uint64_t*)out_start, nc, b.total, b.scan_tmp);
   // kernel launches for small / medium communities read their counts on device
