@@ -208,16 +208,15 @@ __device__ inline void uf_union(uint32_t* p, uint32_t a, uint32_t b) {
 template <typename W>
 __global__ __launch_bounds__(kBlock) void k_split_sample(Rows<W> g, const uint32_t* C, uint32_t* lab,
                                                          const uint32_t* list, const Ctl* ctl) {
-  const uint32_t cnt = ctl->split_count;
-  GRID_STRIDE(it, cnt) {
-    const uint32_t u = list[it];
-    const uint32_t c = C[u];
-    const int64_t s0 = g.start[u];
-    const uint32_t L = min(g.len[u], kSplitSample);
-    for (uint32_t e = 0; e < L; ++e) {
-      const uint32_t j = g.cols[s0 + e];
-      if (j != u && C[j] == c) uf_union(lab, u, j);
-    }
+  // one thread per (vertex, sampled entry): the unions of a vertex run side
+  // by side instead of one after another
+  const uint64_t cnt = (uint64_t)ctl->split_count * kSplitSample;
+  GRID_STRIDE(q, cnt) {
+    const uint32_t u = list[q / kSplitSample];
+    const uint32_t e = (uint32_t)(q % kSplitSample);
+    if (e >= g.len[u]) continue;
+    const uint32_t j = g.cols[g.start[u] + e];
+    if (j != u && C[j] == C[u]) uf_union(lab, u, j);
   }
 }
 
@@ -326,7 +325,8 @@ void launch_split_init(hipStream_t s, uint32_t n, const uint32_t* C, const uint8
 template <typename W>
 void launch_split_sample(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* lab, const uint32_t* list,
                          unsigned long long* main_key, uint32_t* rest, Ctl* ctl, uint32_t n_upper) {
-  hipLaunchKernelGGL((k_split_sample<W>), dim3(grid_n(n_upper)), dim3(kBlock), 0, s, g, C, lab, list, ctl);
+  hipLaunchKernelGGL((k_split_sample<W>), dim3(grid_n((uint64_t)n_upper * kSplitSample)), dim3(kBlock), 0, s, g, C,
+                     lab, list, ctl);
   hipLaunchKernelGGL(k_split_compress, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, lab, list, ctl);
   hipLaunchKernelGGL(k_split_main, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, g.len, C, list, main_key, ctl);
   hipLaunchKernelGGL(k_split_rest, dim3(grid_n(n_upper, kBlock * kTileU)), dim3(kBlock), 0, s, n_upper, C, lab, list,
