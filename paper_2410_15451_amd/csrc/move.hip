@@ -649,8 +649,8 @@ int hub_layout(hipStream_t s, const uint32_t* len, uint32_t nl, uint32_t hub_abo
                void* scan_tmp, uint64_t* total_dev, uint32_t* count_out, uint64_t* slots_out,
                uint64_t* mat_out) {
   hipLaunchKernelGGL(k_clear_misc6, dim3(1), dim3(1), 0, s, ctl);
-  hipLaunchKernelGGL(k_hub_list, dim3(grid_for(nl, kBlock * kListU, 4096)), dim3(kBlock), 0, s, len, nl, hub_above, h.list,
-                     ctl);
+  hipLaunchKernelGGL(k_hub_list, dim3(grid_for(nl, kBlock * kListU, 4096)), dim3(kBlock), 0, s, len, nl, hub_above,
+                     h.list, ctl);
   unsigned int* pc = (unsigned int*)pinned_stage(4);
   if (!pc || hipMemcpyAsync(pc, &ctl->misc[6], sizeof(unsigned int), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
@@ -881,15 +881,15 @@ static int grid_for(uint64_t items, int per_block, int cap) {
 void launch_distribute(hipStream_t s, const uint32_t* in_list, const unsigned int* in_count, uint32_t n_upper,
                        uint32_t li, uint32_t P, uint32_t stamp, uint32_t* pend_mark, uint32_t* cls_lists,
                        size_t stride, Ctl* ctl) {
-  hipLaunchKernelGGL(k_distribute, dim3(grid_for(n_upper, kBlock * kDistU, 4096)), dim3(kBlock), 0, s, in_list, in_count,
-                     n_upper, li, P, stamp, pend_mark, cls_lists, stride, ctl);
+  hipLaunchKernelGGL(k_distribute, dim3(grid_for(n_upper, kBlock * kDistU, 4096)), dim3(kBlock), 0, s, in_list,
+                     in_count, n_upper, li, P, stamp, pend_mark, cls_lists, stride, ctl);
 }
 
 void launch_bin(hipStream_t s, const uint32_t* list, const unsigned int* count, uint32_t n_upper, const uint32_t* len,
                 const uint8_t* in_range, uint32_t* bin_lists, size_t stride, const BinCfg& cfg,
                 unsigned long long* hub_items, Ctl* ctl) {
-  hipLaunchKernelGGL(k_bin, dim3(grid_for(n_upper, kBlock * kBinU, 4096)), dim3(kBlock), 0, s, list, count, len, in_range,
-                     bin_lists, stride, cfg, hub_items, ctl);
+  hipLaunchKernelGGL(k_bin, dim3(grid_for(n_upper, kBlock * kBinU, 4096)), dim3(kBlock), 0, s, list, count, len,
+                     in_range, bin_lists, stride, cfg, hub_items, ctl);
 }
 
 template <typename W, bool REFINE>
@@ -958,7 +958,9 @@ void launch_apply_refine(hipStream_t s, uint32_t* C, int64_t* S, const int64_t* 
                      ctl);
 }
 
-void launch_subround_reset(hipStream_t s, Ctl* ctl) { hipLaunchKernelGGL(k_subround_reset, dim3(1), dim3(64), 0, s, ctl); }
+void launch_subround_reset(hipStream_t s, Ctl* ctl) {
+  hipLaunchKernelGGL(k_subround_reset, dim3(1), dim3(64), 0, s, ctl);
+}
 
 void launch_iteration_reset(hipStream_t s, Ctl* ctl, uint32_t P) {
   hipLaunchKernelGGL(k_iteration_reset, dim3(1), dim3(64), 0, s, ctl, P);

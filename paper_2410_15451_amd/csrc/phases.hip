@@ -97,8 +97,15 @@ __global__ __launch_bounds__(kBlock) void k_move_by_label(uint32_t n, const uint
     nsplit += (dS[c] && !dR[c]) ? 1u : 0u;
     nref += dR[c] ? 1u : 0u;
   }
-  if (nsplit) atomicAdd(&ctl->misc[0], nsplit);
-  if (nref) atomicAdd(&ctl->misc[1], nref);
+  // one atomic per block: per-thread (or per-wavefront) counts on these two
+  // words queued one atomic after another
+  __shared__ unsigned long long red[kBlock / kWave];
+  const unsigned long long ns = block_sum((unsigned long long)nsplit, red);
+  const unsigned long long nr = block_sum((unsigned long long)nref, red);
+  if (threadIdx.x == 0) {
+    if (ns) atomicAdd(&ctl->misc[0], (unsigned int)ns);
+    if (nr) atomicAdd(&ctl->misc[1], (unsigned int)nr);
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_relabel(uint32_t* C, uint32_t n, const uint32_t* rep) {
@@ -119,8 +126,8 @@ void subset_renumber(hipStream_t s, uint32_t n, uint32_t* C, int64_t*& S, uint32
   fill_u8(s, b.dS2, 0, n);
   fill_u8(s, b.dR2, 0, n);
   scatter_min_index(s, C, n, b.rep, n);
-  hipLaunchKernelGGL(k_move_by_label, dim3(grid_n(n)), dim3(kBlock), 0, s, n, b.rep, S, size, dS, dR, b.S2, b.size2,
-                     b.dS2, b.dR2, ctl);
+  hipLaunchKernelGGL(k_move_by_label, dim3(grid_n(n, kBlock, 1024)), dim3(kBlock), 0, s, n, b.rep, S, size, dS, dR,
+                     b.S2, b.size2, b.dS2, b.dR2, ctl);
   hipLaunchKernelGGL(k_relabel, dim3(grid_n(n)), dim3(kBlock), 0, s, C, n, b.rep);
   std::swap(S, b.S2);
   std::swap(size, b.size2);
@@ -330,8 +337,7 @@ void launch_split_sample(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* 
   hipLaunchKernelGGL(k_split_compress, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, lab, list, ctl);
   hipLaunchKernelGGL(k_split_main, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, g.len, C, list, main_key, ctl);
   hipLaunchKernelGGL(k_split_rest, dim3(grid_n(n_upper, kBlock * kTileU)), dim3(kBlock), 0, s, n_upper, C, lab, list,
-                     main_key, rest,
-                     ctl);
+                     main_key, rest, ctl);
 }
 
 // Full rows of the vertices outside their community's main tree, by degree
@@ -382,32 +388,34 @@ template void launch_split_union<int64_t>(hipStream_t, Rows<int64_t>, const uint
 __global__ __launch_bounds__(kBlock) void k_refine_reset(uint32_t n, uint32_t* C, uint32_t* CB, int64_t* S,
                                                          const int64_t* K, uint32_t* size, const uint8_t* dR,
                                                          uint32_t R, uint32_t* col_lists, size_t stride, Ctl* ctl) {
-  __shared__ unsigned int lcount[kMaxClasses], lbase[kMaxClasses];
+  __shared__ unsigned int scnt[kMaxClasses], sbase[kMaxClasses];
+  if (threadIdx.x < kMaxClasses) scnt[threadIdx.x] = 0;
+  __syncthreads();
   bool any = false;
-  for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < n; base += (uint64_t)gridDim.x * kBlock) {
-    if (threadIdx.x < kMaxClasses) lcount[threadIdx.x] = 0;
-    __syncthreads();
-    const uint64_t i = base + threadIdx.x;
-    int col = -1;
-    unsigned int pos = 0;
-    if (i < n) {
-      const uint32_t b = C[i];
-      CB[i] = b;
-      if (dR[b]) {
-        C[i] = (uint32_t)i;
-        S[i] = K[i];
-        size[i] = 1;
-        any = true;
-        col = (int)vertex_colour((uint32_t)i, R);
-        pos = atomicAdd(&lcount[col], 1u);
+  constexpr uint32_t tile = kBlock * kTileU;
+  for (uint64_t base = (uint64_t)blockIdx.x * tile; base < n; base += (uint64_t)gridDim.x * tile) {
+    uint32_t key[kTileU], val[kTileU];
+#pragma unroll
+    for (int u = 0; u < kTileU; ++u) {
+      const uint64_t i = base + u * kBlock + threadIdx.x;
+      key[u] = kNone;
+      val[u] = (uint32_t)i;
+      if (i < n) {
+        const uint32_t b = C[i];
+        CB[i] = b;
+        if (dR[b]) {
+          C[i] = (uint32_t)i;
+          S[i] = K[i];
+          size[i] = 1;
+          any = true;
+          key[u] = vertex_colour((uint32_t)i, R);
+        }
       }
     }
-    __syncthreads();
-    if (threadIdx.x < R && lcount[threadIdx.x] > 0)
-      lbase[threadIdx.x] = atomicAdd(&ctl->cls_count[threadIdx.x], lcount[threadIdx.x]);
-    __syncthreads();
-    if (col >= 0) col_lists[(size_t)col * stride + lbase[col] + pos] = (uint32_t)i;
-    __syncthreads();
+    tile_append<kTileU>(key, val, R, scnt, sbase, [&](uint32_t col, uint32_t*& l, unsigned int*& c) {
+      l = col_lists + (size_t)col * stride;
+      c = &ctl->cls_count[col];
+    });
   }
   if (any) ctl->refined_any = 1;
 }
@@ -415,8 +423,9 @@ __global__ __launch_bounds__(kBlock) void k_refine_reset(uint32_t n, uint32_t* C
 void launch_refine_reset(hipStream_t s, uint32_t n, uint32_t* C, uint32_t* CB, int64_t* S, const int64_t* K,
                          uint32_t* size, const uint8_t* dR, uint32_t R, uint32_t* col_lists, size_t stride,
                          Ctl* ctl) {
-  if (n) hipLaunchKernelGGL(k_refine_reset, dim3(grid_n(n)), dim3(kBlock), 0, s, n, C, CB, S, K, size, dR, R,
-                            col_lists, stride, ctl);
+  if (n)
+    hipLaunchKernelGGL(k_refine_reset, dim3(grid_n(n, kBlock * kTileU)), dim3(kBlock), 0, s, n, C, CB, S, K, size, dR,
+                       R, col_lists, stride, ctl);
 }
 
 // ---------------------------------------------------------------------------
@@ -961,8 +970,7 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
   hipLaunchKernelGGL(k_zero_misc_agg, dim3(1), dim3(64), 0, s, ctl);
   // capacity per community -> super-row starts
   hipLaunchKernelGGL(k_comm_classify, dim3(grid_n(nc, kBlock * kTileU)), dim3(kBlock), 0, s, nc, b.comm_deg, b.cap_off,
-                     out_len, Kout,
-                     b.small_lists, (size_t)nc, ctl);
+                     out_len, Kout, b.small_lists, (size_t)nc, ctl);
   exclusive_scan_u64(s, b.cap_off, (uint64_t*)out_start, nc, b.total, b.scan_tmp);
   // kernel launches for small / medium communities read their counts on device
   hipLaunchKernelGGL((k_agg_lds<64, 256, W>), dim3(grid_n(nc, kBlock / 64, 2048)), dim3(kBlock), 0, s, g, C, b.members,
