@@ -1232,7 +1232,10 @@ __global__ __launch_bounds__(kBlock) void k_track_best_w(const unsigned long lon
   GRID_STRIDE(sl, slots) {
     const unsigned long long k = hk[sl];
     if (k == kNone64) continue;
-    atomicMax(&best_w[k >> 32], hv[sl]);
+    // read first: most updates would not raise the maximum, and atomics on
+    // one address (a large community's entry) are serialised device-wide
+    long long* slot = &best_w[k >> 32];
+    if (__atomic_load_n(slot, __ATOMIC_RELAXED) < hv[sl]) atomicMax(slot, hv[sl]);
   }
 }
 
@@ -1243,7 +1246,8 @@ __global__ __launch_bounds__(kBlock) void k_track_best_c(const unsigned long lon
     const unsigned long long k = hk[sl];
     if (k == kNone64) continue;
     const uint32_t b = (uint32_t)(k >> 32), c = (uint32_t)k;
-    if (hv[sl] == best_w[b]) atomicMin(&best_vmin[b], minv[c]);
+    if (hv[sl] == best_w[b] && __atomic_load_n(&best_vmin[b], __ATOMIC_RELAXED) > minv[c])
+      atomicMin(&best_vmin[b], minv[c]);
   }
 }
 
@@ -1252,7 +1256,8 @@ __global__ __launch_bounds__(kBlock) void k_track_cand_w(uint32_t n, const uint3
   GRID_STRIDE(b, n) {
     const uint32_t vm = best_vmin[b];
     if (vm == kNone) continue;
-    atomicMax(&cand_w[Ccur[vm]], best_w[b]);
+    long long* slot = &cand_w[Ccur[vm]];
+    if (__atomic_load_n(slot, __ATOMIC_RELAXED) < best_w[b]) atomicMax(slot, best_w[b]);
   }
 }
 
@@ -1263,7 +1268,7 @@ __global__ __launch_bounds__(kBlock) void k_track_cand_b(uint32_t n, const uint3
     const uint32_t vm = best_vmin[b];
     if (vm == kNone) continue;
     const uint32_t c = Ccur[vm];
-    if (best_w[b] == cand_w[c]) atomicMin(&cand_b[c], (uint32_t)b);
+    if (best_w[b] == cand_w[c] && __atomic_load_n(&cand_b[c], __ATOMIC_RELAXED) > b) atomicMin(&cand_b[c], (uint32_t)b);
   }
 }
 
