@@ -121,8 +121,8 @@ typedef struct leiden_graph leiden_graph;
  * The thresholds must increase and stay within 15, 63, 255, 1023 and 4095 (a
  * bin's table must hold every distinct community of its rows).  They decide
  * only which kernel evaluates a vertex, never the result (memberships are
- * identical for every valid setting).  Defaults 8, 32, 128,
- * 512, 2048. */
+ * identical for every valid setting).  Defaults: the capacities 15, 63,
+ * 255, 1023, 4095. */
 typedef struct {
   uint32_t bin_max_degree[5];
   uint32_t pad_;
