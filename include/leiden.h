@@ -152,7 +152,9 @@ leiden_status leiden_default_opts(leiden_opts* opts);
  * must be sorted by column; unsorted rows, duplicate entries, self-loops,
  * zero weights, IDs >= n or an asymmetric matrix give LEIDEN_EINVAL.  `slack`
  * >= 0 reserves room per row for future insertions (fraction of the row
- * length).  *out receives the handle. */
+ * length); each row holds two spans of that capacity on the device (a batch
+ * writes the updated row into the spare one), so the handle takes about
+ * 2 (1 + slack) nnz entries of 8 bytes.  *out receives the handle. */
 leiden_status leiden_graph_create(int device, uint32_t n, uint64_t nnz, const int64_t* offsets,
                                   const uint32_t* cols, const uint32_t* w, int on_device, double slack,
                                   leiden_graph** out);

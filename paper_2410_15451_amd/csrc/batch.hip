@@ -5,10 +5,12 @@
 // Every undirected update becomes its two directed entries.  Entries are
 // grouped by source row (counting by row, one segment per touched row) and
 // sorted by destination inside each segment; validation then checks each
-// entry against the sorted old row, and the merge writes each new sorted row
-// to scratch before it is committed in place (or into the overflow area when
-// the row outgrows its capacity).  Nothing is written to the graph before
-// validation has passed, so a rejected batch leaves the graph unchanged.
+// entry against the sorted old row.  Every row owns two spans of its
+// capacity: the merge writes the new sorted row into the spare span (or a
+// fresh pair of spans in the overflow area when the row outgrows its
+// capacity) and the spans swap roles afterwards, so no merged row is copied
+// back.  Nothing is written to the graph before validation has passed, so a
+// rejected batch leaves the graph unchanged.
 #include "kernels.h"
 
 namespace lm {
@@ -84,7 +86,9 @@ __global__ __launch_bounds__(kBlock) void k_row_cnt_clear(uint64_t nt, BatchBufs
 // ---------------------------------------------------------------------------
 // Sorting each segment by destination (src is equal inside a segment).
 // Short segments: one thread, insertion sort.  Medium: one block, bitonic
-// sort in LDS.  Long: one block, bottom-up merge sort through scratch.
+// sort in LDS.  Long: one block, bottom-up merge sort through scratch.  The
+// short-segment pass lists the medium and long segments, so the block sorts
+// visit only those.
 // ---------------------------------------------------------------------------
 __device__ inline void seg_swap(BatchBufs& b, uint64_t x, uint64_t y) {
   uint32_t t;
@@ -93,24 +97,31 @@ __device__ inline void seg_swap(BatchBufs& b, uint64_t x, uint64_t y) {
   t = b.seg_del[x]; b.seg_del[x] = b.seg_del[y]; b.seg_del[y] = t;
 }
 
-constexpr uint32_t kSortShort = 32, kSortLds = 2048;
+constexpr uint32_t kSortShort = 8, kSortLds = 2048;
 
-__global__ __launch_bounds__(kBlock) void k_sort_short(uint64_t nt, BatchBufs b) {
+__global__ __launch_bounds__(kBlock) void k_sort_short(uint64_t nt, BatchBufs b, Ctl* ctl) {
   GRID_STRIDE(t, nt) {
     const uint64_t s0 = b.seg_off[t], s1 = b.seg_off[t + 1];
-    if (s1 - s0 > kSortShort) continue;
+    const uint64_t L = s1 - s0;
+    const uint32_t which = L > kSortLds ? 1u : (L > kSortShort ? 0u : kNone);
+    wave_append(which, (uint32_t)t, [&](uint32_t k, uint32_t*& l, unsigned int*& c) {
+      l = k ? b.sort_long : b.sort_mid;
+      c = &ctl->sort_count[k];
+    });
+    if (which != kNone) continue;
     for (uint64_t i = s0 + 1; i < s1; ++i)
       for (uint64_t j = i; j > s0 && b.seg_dst[j - 1] > b.seg_dst[j]; --j) seg_swap(b, j - 1, j);
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_sort_lds(uint64_t nt, BatchBufs b) {
+__global__ __launch_bounds__(kBlock) void k_sort_lds(BatchBufs b, const Ctl* ctl) {
   __shared__ uint32_t key[kSortLds];
   __shared__ uint32_t idx[kSortLds];
-  for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+  const unsigned int cnt = ctl->sort_count[0];
+  for (unsigned int it = blockIdx.x; it < cnt; it += gridDim.x) {
+    const uint32_t t = b.sort_mid[it];
     const uint64_t s0 = b.seg_off[t], s1 = b.seg_off[t + 1];
     const uint32_t L = (uint32_t)(s1 - s0);
-    if (L <= kSortShort || L > kSortLds) continue;
     uint32_t P = 1;
     while (P < L) P <<= 1;
     for (uint32_t i = threadIdx.x; i < P; i += kBlock) {
@@ -155,11 +166,12 @@ __global__ __launch_bounds__(kBlock) void k_sort_lds(uint64_t nt, BatchBufs b) {
 
 // One block per long segment: merge runs of width 1, 2, 4, ... between the
 // segment and its scratch copy; each thread merges one pair of runs.
-__global__ __launch_bounds__(kBlock) void k_sort_long(uint64_t nt, BatchBufs b) {
-  for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+__global__ __launch_bounds__(kBlock) void k_sort_long(BatchBufs b, const Ctl* ctl) {
+  const unsigned int cnt = ctl->sort_count[1];
+  for (unsigned int it = blockIdx.x; it < cnt; it += gridDim.x) {
+    const uint32_t t = b.sort_long[it];
     const uint64_t s0 = b.seg_off[t], s1 = b.seg_off[t + 1];
     const uint64_t L = s1 - s0;
-    if (L <= kSortLds) continue;
     uint32_t *ad = b.seg_dst + s0, *aw = b.seg_w + s0, *ax = b.seg_del + s0;
     uint32_t *bd = b.tmp_dst + s0, *bw = b.tmp_w + s0, *bx = b.tmp_del + s0;
     for (uint64_t width = 1; width < L; width <<= 1) {
@@ -197,18 +209,6 @@ __global__ __launch_bounds__(kBlock) void k_sort_long(uint64_t nt, BatchBufs b) 
 // Validation against G^{t-1}: no pair twice, deletions present (their old
 // weight is recorded), insertions absent.
 // ---------------------------------------------------------------------------
-__device__ inline int64_t row_find(const uint32_t* cols, int64_t s0, uint32_t L, uint32_t key) {
-  uint32_t lo = 0, hi = L;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (cols[s0 + mid] < key)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return (lo < L && cols[s0 + lo] == key) ? s0 + lo : -1;
-}
-
 __device__ inline uint32_t row_lower_bound(const uint32_t* cols, int64_t s0, uint32_t L, uint32_t key) {
   uint32_t lo = 0, hi = L;
   while (lo < hi) {
@@ -221,6 +221,8 @@ __device__ inline uint32_t row_lower_bound(const uint32_t* cols, int64_t s0, uin
   return lo;
 }
 
+// Also records each entry's lower bound in its old row, which places it (and
+// the old entries around it) in the merged row.
 __global__ __launch_bounds__(kBlock) void k_validate(uint64_t ne, Rows<uint32_t> g, BatchBufs b, Ctl* ctl) {
   unsigned int err = 0;
   GRID_STRIDE(q, ne) {
@@ -228,13 +230,17 @@ __global__ __launch_bounds__(kBlock) void k_validate(uint64_t ne, Rows<uint32_t>
     const uint32_t d = b.seg_dst[q];
     if (q + 1 < b.seg_off[t + 1] && b.seg_dst[q + 1] == d) err |= kErrDup;
     const uint32_t r = b.seg_src[q];
-    const int64_t pos = row_find(g.cols, g.start[r], g.len[r], d);
+    const int64_t s0 = g.start[r];
+    const uint32_t L = g.len[r];
+    const uint32_t lb = row_lower_bound(g.cols, s0, L, d);
+    const bool present = lb < L && g.cols[s0 + lb] == d;
+    b.seg_lb[q] = lb;
     if (b.seg_del[q]) {
-      if (pos < 0)
+      if (!present)
         err |= kErrAbsent;
       else
-        b.seg_w[q] = g.w[pos];
-    } else if (pos >= 0) {
+        b.seg_w[q] = g.w[s0 + lb];
+    } else if (present) {
       err |= kErrPresent;
     }
   }
@@ -244,6 +250,9 @@ __global__ __launch_bounds__(kBlock) void k_validate(uint64_t ne, Rows<uint32_t>
 // ---------------------------------------------------------------------------
 // Merge planning, merge and commit
 // ---------------------------------------------------------------------------
+// capacity of each span of a row that outgrew its spans
+__device__ inline uint32_t grown_cap(uint32_t nl) { return nl + (nl >> 2) + 4; }
+
 __global__ __launch_bounds__(kBlock) void k_new_len(uint64_t nt, const uint32_t* len, const uint32_t* cap,
                                                     BatchBufs b, Ctl* ctl) {
   unsigned long long need = 0;
@@ -254,38 +263,13 @@ __global__ __launch_bounds__(kBlock) void k_new_len(uint64_t nt, const uint32_t*
     const uint64_t inss = (s1 - s0) - dels;
     const uint32_t nl = (uint32_t)(len[r] - dels + inss);
     b.new_len[t] = nl;
-    if (nl > cap[r]) need += nl + (nl >> 2) + 4;
+    if (nl > cap[r]) need += 2 * (uint64_t)grown_cap(nl);
   }
   if (need) atomicAdd(&ctl->overflow_need, need);
 }
 
-// Merge, one thread per entry: every old entry and every inserted entry
-// computes its position in the merged sorted row directly.  Rows are found by
-// binary search over per-row offsets, so long rows spread over all threads.
-__device__ inline uint64_t row_of(const uint64_t* off, uint64_t nt, uint64_t x) {
-  // largest t < nt with off[t] <= x
-  uint64_t lo = 0, hi = nt;
-  while (hi - lo > 1) {
-    const uint64_t mid = (lo + hi) >> 1;
-    if (off[mid] <= x)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
-// Entry-parallel walk over rows: the entries [0, tot) of consecutive rows
-// (row t owns [off[t], off[t + 1])) are cut into one contiguous range per
-// block.  A block finds the row of its first entry by binary search, then
-// stages kRowWin row offsets at a time in LDS; each thread finds its row in
-// that window, and the next tile starts from the row of the tile's last
-// entry.  Rows beyond the window (only when a tile spans more rows than the
-// window holds) are found by binary search.  f(t, x) runs once per entry x.
-constexpr uint32_t kRowWin = 512;
-
+// largest t in [lo, hi) with off[t] <= x, given off[lo] <= x
 __device__ inline uint64_t row_in(const uint64_t* off, uint64_t lo, uint64_t hi, uint64_t x) {
-  // largest t in [lo, hi) with off[t] <= x, given off[lo] <= x
   while (hi - lo > 1) {
     const uint64_t mid = (lo + hi) >> 1;
     if (off[mid] <= x)
@@ -296,118 +280,148 @@ __device__ inline uint64_t row_in(const uint64_t* off, uint64_t lo, uint64_t hi,
   return lo;
 }
 
-template <typename F>
-__device__ inline void block_rows_for_each(const uint64_t* off, uint64_t nt, uint64_t tot, F f) {
-  __shared__ uint64_t woff[kRowWin];
-  __shared__ uint64_t t0s, tnext;
+// Destination span of each touched row: its spare span, or a fresh pair of
+// spans above the bump pointer when the merged row outgrows the capacity.
+__global__ __launch_bounds__(kBlock) void k_plan_rows(uint64_t nt, const int64_t* alt, const uint32_t* cap,
+                                                      BatchBufs b, unsigned long long* edge_top) {
+  GRID_STRIDE(t, nt) {
+    const uint32_t r = b.touched[t];
+    const uint32_t nl = b.new_len[t];
+    if (nl > cap[r])
+      b.dest[t] = (uint64_t)atomicAdd(edge_top, 2ull * grown_cap(nl));
+    else
+      b.dest[t] = (uint64_t)alt[r];
+  }
+}
+
+// Runs of old entries.  Between two consecutive segment entries of a row the
+// old entries keep their order and all move by the same amount: the
+// insertions before them minus the deletions before them.  Run q + t ends at
+// segment entry q (of touched row t); run seg_off[t + 1] + t is the row's
+// tail.  A deleted entry is the old entry at its lower bound, so the next run
+// starts just after it.
+__device__ inline void run_plan(uint64_t i, uint64_t s0, uint64_t q, uint32_t end, int64_t src0, uint64_t dst0,
+                                BatchBufs& b) {
+  uint32_t a = 0;
+  if (q > s0) a = b.seg_lb[q - 1] + (b.seg_del[q - 1] ? 1u : 0u);
+  const uint64_t dels = b.seg_pre[q] - b.seg_pre[s0];
+  const uint64_t inss = (q - s0) - dels;
+  b.run_len[i] = end - a;
+  b.run_src[i] = src0 + a;
+  b.run_dst[i] = (int64_t)(dst0 + a + inss - dels);
+}
+
+__global__ __launch_bounds__(kBlock) void k_runs_seg(uint64_t ne, const int64_t* start, BatchBufs b) {
+  GRID_STRIDE(q, ne) {
+    const uint32_t t = b.seg_id[q];
+    run_plan(q + t, b.seg_off[t], q, b.seg_lb[q], start[b.touched[t]], b.dest[t], b);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_runs_tail(uint64_t nt, const int64_t* start, const uint32_t* len,
+                                                      BatchBufs b) {
+  GRID_STRIDE(t, nt) {
+    const uint32_t r = b.touched[t];
+    const uint64_t s1 = b.seg_off[t + 1];
+    run_plan(s1 + t, b.seg_off[t], s1, len[r], start[r], b.dest[t], b);
+  }
+}
+
+// Entry-parallel copy of the runs.  Each block takes one contiguous range of
+// the entries; it keeps a window of kRunWin runs (offsets, sources and
+// destinations) in LDS and loads the next window only when its entries run
+// past the current one.  A thread finds the run of its entry in the window:
+// the run of its previous entry if that still holds it (long runs), else by
+// binary search.
+constexpr uint32_t kRunWin = 512, kCopyTile = 4 * kBlock;
+// blocks of the run copy (the entry count is known on the device only)
+constexpr int kCopyGrid = 2048;
+
+__global__ __launch_bounds__(kBlock) void k_copy_runs(uint64_t nruns, const uint64_t* total, uint32_t* cols,
+                                                      uint32_t* w, BatchBufs b) {
+  __shared__ uint64_t woff[kRunWin + 1];
+  __shared__ int64_t wsrc[kRunWin], wdst[kRunWin];
+  __shared__ uint64_t sbase;
+  const uint64_t tot = *total;
   const uint64_t per = (tot + gridDim.x - 1) / gridDim.x;
   const uint64_t xb = (uint64_t)blockIdx.x * per, xe = min(tot, xb + per);
   if (xb >= xe) return;  // block-uniform
-  if (threadIdx.x == 0) t0s = row_in(off, 0, nt, xb);
-  __syncthreads();
-  for (uint64_t x0 = xb; x0 < xe; x0 += kBlock) {
-    const uint64_t t0 = t0s;
-    const uint64_t w = min((uint64_t)kRowWin, nt - t0);
-    for (uint32_t k = threadIdx.x; k < w; k += kBlock) woff[k] = off[t0 + k];
-    __syncthreads();
-    const uint64_t x = x0 + threadIdx.x;
-    const uint64_t xl = min(x0 + kBlock, xe) - 1;
-    if (x <= xl) {
-      uint64_t t;
-      if (w == kRowWin && x >= woff[w - 1]) {
-        t = row_in(off, t0 + w - 1, nt, x);
-      } else {
-        uint64_t lo = 0, hi = w;
+  uint64_t base = 0;
+  uint32_t wn = 0, j = 0;
+  bool have = false;
+  for (uint64_t x0 = xb; x0 < xe;) {
+    if (!have || x0 >= woff[wn]) {
+      // the run holding x0 lies at or after the end of the current window
+      if (threadIdx.x == 0) sbase = row_in(b.run_off, have ? base + wn : 0, nruns, x0);
+      __syncthreads();
+      base = sbase;
+      wn = (uint32_t)min((uint64_t)kRunWin, nruns - base);
+      for (uint32_t k = threadIdx.x; k <= wn; k += kBlock) {
+        const uint64_t t = base + k;
+        woff[k] = t < nruns ? b.run_off[t] : tot;
+        if (k < wn) {
+          wsrc[k] = b.run_src[t];
+          wdst[k] = b.run_dst[t];
+        }
+      }
+      __syncthreads();
+      have = true;
+      j = 0;
+    }
+    const uint64_t x1 = min(min(x0 + kCopyTile, woff[wn]), xe);
+    for (uint64_t x = x0 + threadIdx.x; x < x1; x += kBlock) {
+      if (woff[j + 1] <= x) {  // largest run j < wn with woff[j] <= x
+        uint32_t lo = j + 1, hi = wn;
         while (hi - lo > 1) {
-          const uint64_t mid = (lo + hi) >> 1;
+          const uint32_t mid = (lo + hi) >> 1;
           if (woff[mid] <= x)
             lo = mid;
           else
             hi = mid;
         }
-        t = t0 + lo;
+        j = lo;
       }
-      f(t, x);
-      if (x == xl) tnext = t;
+      const uint64_t k = x - woff[j];
+      const int64_t src = wsrc[j] + (int64_t)k, dst = wdst[j] + (int64_t)k;
+      cols[dst] = cols[src];
+      w[dst] = w[src];
     }
-    __syncthreads();
-    if (threadIdx.x == 0) t0s = tnext;
-    __syncthreads();
+    x0 = x1;
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_old_len(uint64_t nt, const uint32_t* len, BatchBufs b) {
-  GRID_STRIDE(t, nt) b.old_len[t] = len[b.touched[t]];
-}
-
-__device__ inline void merge_old_entry(uint64_t t, uint64_t x, const Rows<uint32_t>& g, const BatchBufs& b) {
-  const uint32_t r = b.touched[t];
-  const uint32_t p = (uint32_t)(x - b.old_off[t]);
-  const uint64_t s0 = b.seg_off[t];
-  const uint32_t L = (uint32_t)(b.seg_off[t + 1] - s0);
-  const int64_t r0 = g.start[r];
-  const uint32_t y = g.cols[r0 + p];
-  uint32_t lo = 0, hi = L;  // first segment entry with dst >= y
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (b.seg_dst[s0 + mid] < y)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  if (lo < L && b.seg_dst[s0 + lo] == y) return;  // deleted (insertions of present pairs were rejected)
-  const uint64_t dels = b.seg_pre[s0 + lo] - b.seg_pre[s0];
-  const uint64_t inss = lo - dels;
-  const uint64_t pos = b.out_off[t] + p - dels + inss;
-  b.mcols[pos] = y;
-  b.mw[pos] = g.w[r0 + p];
-}
-
-__global__ __launch_bounds__(kBlock) void k_merge_old(uint64_t nt, const uint64_t* total_old, Rows<uint32_t> g,
-                                                      BatchBufs b) {
-  block_rows_for_each(b.old_off, nt, *total_old, [&](uint64_t t, uint64_t x) { merge_old_entry(t, x, g, b); });
-}
-
-__global__ __launch_bounds__(kBlock) void k_merge_ins(uint64_t ne, Rows<uint32_t> g, BatchBufs b) {
+// Inserted entries land at their lower bound, shifted like the run before.
+__global__ __launch_bounds__(kBlock) void k_merge_ins(uint64_t ne, uint32_t* cols, uint32_t* w, BatchBufs b) {
   GRID_STRIDE(q, ne) {
     if (b.seg_del[q]) continue;
     const uint32_t t = b.seg_id[q];
-    const uint32_t r = b.touched[t];
     const uint64_t s0 = b.seg_off[t];
-    const uint32_t y = b.seg_dst[q];
-    const uint32_t lb = row_lower_bound(g.cols, g.start[r], g.len[r], y);
     const uint64_t dels = b.seg_pre[q] - b.seg_pre[s0];
     const uint64_t inss = (q - s0) - dels;
-    const uint64_t pos = b.out_off[t] + lb - dels + inss;
-    b.mcols[pos] = y;
-    b.mw[pos] = b.seg_w[q];
+    const uint64_t pos = b.dest[t] + b.seg_lb[q] + inss - dels;
+    cols[pos] = b.seg_dst[q];
+    w[pos] = b.seg_w[q];
   }
 }
 
-// Per touched row: destination of the merged row (in place, or a new span in
-// the overflow area when it outgrew its capacity) and the new length.
-__global__ __launch_bounds__(kBlock) void k_commit_rows(uint64_t nt, int64_t* start, uint32_t* len, uint32_t* cap,
-                                                        BatchBufs b, unsigned long long* edge_top) {
+// The spans swap roles (or the row moves to its fresh pair) and the new
+// length is published.
+__global__ __launch_bounds__(kBlock) void k_commit_rows(uint64_t nt, int64_t* start, int64_t* alt, uint32_t* len,
+                                                        uint32_t* cap, BatchBufs b) {
   GRID_STRIDE(t, nt) {
     const uint32_t r = b.touched[t];
     const uint32_t nl = b.new_len[t];
+    const int64_t d = (int64_t)b.dest[t];
     if (nl > cap[r]) {
-      const uint32_t nc = nl + (nl >> 2) + 4;
-      start[r] = (int64_t)atomicAdd(edge_top, (unsigned long long)nc);
+      const uint32_t nc = grown_cap(nl);
+      alt[r] = d + nc;
       cap[r] = nc;
+    } else {
+      alt[r] = start[r];
     }
-    b.dest[t] = (uint64_t)start[r];
+    start[r] = d;
     len[r] = nl;
   }
-}
-
-__global__ __launch_bounds__(kBlock) void k_commit_copy(uint64_t nt, const uint64_t* total_new, uint32_t* cols,
-                                                        uint32_t* w, BatchBufs b) {
-  block_rows_for_each(b.out_off, nt, *total_new, [&](uint64_t t, uint64_t x) {
-    const uint64_t d = b.dest[t] + (x - b.out_off[t]);
-    cols[d] = b.mcols[x];
-    w[d] = b.mw[x];
-  });
 }
 
 // ---------------------------------------------------------------------------
@@ -435,9 +449,9 @@ int batch_prepare(hipStream_t s, uint32_t n, const uint32_t* del, uint64_t n_del
   (void)hipMemcpyAsync(b.seg_off + nt, b.total, sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
   hipLaunchKernelGGL(k_scatter, dim3(grid_n(ne)), dim3(kBlock), 0, s, ne, b);
   hipLaunchKernelGGL(k_row_cnt_clear, dim3(grid_n(nt)), dim3(kBlock), 0, s, nt, b);
-  hipLaunchKernelGGL(k_sort_short, dim3(grid_n(nt)), dim3(kBlock), 0, s, nt, b);
-  hipLaunchKernelGGL(k_sort_lds, dim3(grid_n(nt, 1, 1024)), dim3(kBlock), 0, s, nt, b);
-  hipLaunchKernelGGL(k_sort_long, dim3(grid_n(nt, 1, 256)), dim3(kBlock), 0, s, nt, b);
+  hipLaunchKernelGGL(k_sort_short, dim3(grid_n(nt)), dim3(kBlock), 0, s, nt, b, ctl);
+  hipLaunchKernelGGL(k_sort_lds, dim3(grid_n(nt, 1, 1024)), dim3(kBlock), 0, s, b, ctl);
+  hipLaunchKernelGGL(k_sort_long, dim3(grid_n(nt, 1, 256)), dim3(kBlock), 0, s, b, ctl);
   // prefix counts of deletions inside segments (for the merge positions)
   exclusive_scan_u32(s, b.seg_del, b.seg_pre, ne, b.total, b.scan_tmp);
   (void)hipMemcpyAsync(b.seg_pre + ne, b.total, sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
@@ -457,27 +471,26 @@ int batch_validate(hipStream_t s, Rows<uint32_t> g, uint32_t n, uint64_t n_entri
   return (int)*err;
 }
 
-int batch_merge(hipStream_t s, int64_t* start, uint32_t* len, uint32_t* cap, uint32_t* cols, uint32_t* w,
-                uint64_t n_touched, BatchBufs& b, unsigned long long* edge_top, uint64_t edge_cap, Ctl* ctl) {
+int batch_merge(hipStream_t s, int64_t* start, int64_t* alt, uint32_t* len, uint32_t* cap, uint32_t* cols,
+                uint32_t* w, uint64_t n_touched, BatchBufs& b, unsigned long long* edge_top, uint64_t edge_cap,
+                Ctl* ctl) {
   const uint64_t nt = n_touched;
   if (nt == 0) return 0;
   hipLaunchKernelGGL(k_new_len, dim3(grid_n(nt)), dim3(kBlock), 0, s, nt, len, cap, b, ctl);
-  exclusive_scan_u32(s, b.new_len, b.out_off, nt, b.total, b.scan_tmp);
-  hipLaunchKernelGGL(k_old_len, dim3(grid_n(nt)), dim3(kBlock), 0, s, nt, len, b);
-  exclusive_scan_u32(s, b.old_len, b.old_off, nt, b.total + 1, b.scan_tmp);
-  unsigned long long* hv = (unsigned long long*)pinned_stage(32);  // need, top, merged total, old total
+  unsigned long long* hv = (unsigned long long*)pinned_stage(16);  // overflow need, bump pointer
   if (!hv) return -100;
   (void)hipMemcpyAsync(&hv[0], &ctl->overflow_need, sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
   (void)hipMemcpyAsync(&hv[1], edge_top, sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
-  (void)hipMemcpyAsync(&hv[2], b.total, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
   if (hipStreamSynchronize(s) != hipSuccess) return -100;
-  if (hv[1] + hv[0] > edge_cap || hv[2] > b.mcap) return 1;
-  Rows<uint32_t> g{start, len, cols, w};
-  if (hv[3]) hipLaunchKernelGGL(k_merge_old, dim3(grid_n(hv[3])), dim3(kBlock), 0, s, nt, b.total + 1, g, b);
-  const uint64_t nent = b.n_entries;
-  if (nent) hipLaunchKernelGGL(k_merge_ins, dim3(grid_n(nent)), dim3(kBlock), 0, s, nent, g, b);
-  hipLaunchKernelGGL(k_commit_rows, dim3(grid_n(nt)), dim3(kBlock), 0, s, nt, start, len, cap, b, edge_top);
-  if (hv[2]) hipLaunchKernelGGL(k_commit_copy, dim3(grid_n(hv[2])), dim3(kBlock), 0, s, nt, b.total, cols, w, b);
+  if (hv[1] + hv[0] > edge_cap) return 1;
+  const uint64_t ne = b.n_entries, nruns = ne + nt;
+  hipLaunchKernelGGL(k_plan_rows, dim3(grid_n(nt)), dim3(kBlock), 0, s, nt, alt, cap, b, edge_top);
+  if (ne) hipLaunchKernelGGL(k_runs_seg, dim3(grid_n(ne)), dim3(kBlock), 0, s, ne, start, b);
+  hipLaunchKernelGGL(k_runs_tail, dim3(grid_n(nt)), dim3(kBlock), 0, s, nt, start, len, b);
+  exclusive_scan_u32(s, b.run_len, b.run_off, nruns, b.total, b.scan_tmp);
+  hipLaunchKernelGGL(k_copy_runs, dim3(kCopyGrid), dim3(kBlock), 0, s, nruns, b.total, cols, w, b);
+  if (ne) hipLaunchKernelGGL(k_merge_ins, dim3(grid_n(ne)), dim3(kBlock), 0, s, ne, cols, w, b);
+  hipLaunchKernelGGL(k_commit_rows, dim3(grid_n(nt)), dim3(kBlock), 0, s, nt, start, alt, len, cap, b);
   return 0;
 }
 

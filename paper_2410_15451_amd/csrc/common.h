@@ -72,6 +72,7 @@ struct Ctl {
   unsigned int init_count;           // vertices marked affected by the batch
   unsigned long long overflow_need;  // entries to relocate into the overflow area
   unsigned int mark_items;           // neighbour-marking work items of the current sub-round
+  unsigned int sort_count[2];        // batch segments left to the block sorts (LDS, merge)
   unsigned int misc[8];
   unsigned long long kt_units[4];    // work units of the timed kernels (indexed by leiden_kernel)
 };

@@ -78,14 +78,13 @@ __global__ __launch_bounds__(kBlock) void k_caps_from_offs(uint32_t n, const int
 
 __global__ __launch_bounds__(kBlock) void k_copy_rows(uint32_t n, const int64_t* src_start, const uint32_t* len,
                                                       const uint32_t* src_cols, const uint32_t* src_w,
-                                                      const uint64_t* dst_start, uint32_t* dst_cols,
-                                                      uint32_t* dst_w) {
+                                                      const uint64_t* off, uint32_t* dst_cols, uint32_t* dst_w) {
   const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
   const uint32_t lane = threadIdx.x % kWave;
   const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
   for (uint64_t i = wave; i < n; i += nwaves) {
     const int64_t a = src_start[i];
-    const uint64_t d = dst_start[i];
+    const uint64_t d = 2 * off[i];
     const uint32_t L = len[i];
     for (uint32_t e = lane; e < L; e += kWave) {
       dst_cols[d + e] = src_cols[a + e];
@@ -94,8 +93,12 @@ __global__ __launch_bounds__(kBlock) void k_copy_rows(uint32_t n, const int64_t*
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_start_from(uint32_t n, const uint64_t* off, int64_t* start) {
-  GRID_STRIDE(i, n) start[i] = (int64_t)off[i];
+__global__ __launch_bounds__(kBlock) void k_start_from(uint32_t n, const uint64_t* off, const uint32_t* cap,
+                                                       int64_t* start, int64_t* alt) {
+  GRID_STRIDE(i, n) {
+    start[i] = (int64_t)(2 * off[i]);
+    alt[i] = (int64_t)(2 * off[i] + cap[i]);
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_caps_rebuild(uint32_t n, const uint32_t* len, const uint32_t* reserve,
@@ -163,12 +166,13 @@ void rebuild_caps(hipStream_t s, uint32_t n, const uint32_t* len, const uint32_t
   exclusive_scan_u32(s, cap, off_tmp, n, total_dev, scan_tmp);
 }
 
-void copy_rows(hipStream_t s, uint32_t n, const int64_t* src_start, const uint32_t* len, const uint32_t* src_cols,
-               const uint32_t* src_w, const uint64_t* dst_off, uint32_t* dst_cols, uint32_t* dst_w, int64_t* new_start) {
+void copy_rows(hipStream_t s, uint32_t n, const int64_t* src_start, const uint32_t* len, const uint32_t* cap,
+               const uint32_t* src_cols, const uint32_t* src_w, const uint64_t* off, uint32_t* dst_cols,
+               uint32_t* dst_w, int64_t* new_start, int64_t* new_alt) {
   if (!n) return;
   hipLaunchKernelGGL(k_copy_rows, dim3(grid_n(n, kBlock / kWave, 16384)), dim3(kBlock), 0, s, n, src_start, len,
-                     src_cols, src_w, dst_off, dst_cols, dst_w);
-  hipLaunchKernelGGL(k_start_from, dim3(grid_n(n)), dim3(kBlock), 0, s, n, dst_off, new_start);
+                     src_cols, src_w, off, dst_cols, dst_w);
+  hipLaunchKernelGGL(k_start_from, dim3(grid_n(n)), dim3(kBlock), 0, s, n, off, cap, new_start, new_alt);
 }
 
 void reserve_touched(hipStream_t s, uint64_t nt, const uint32_t* touched, const uint32_t* new_len, uint32_t* reserve) {

@@ -279,10 +279,7 @@ struct BatchBufs {
   uint32_t* seg_cnt;
   uint64_t* seg_off;   // nt + 1
   uint32_t* new_len;
-  uint64_t* out_off;   // merged-row offsets (nt + 1)
-  uint32_t* old_len;   // length of the row before the batch
-  uint64_t* old_off;   // exclusive prefix of old_len (nt + 1)
-  uint64_t* dest;      // where the merged row is written in the slack CSR
+  uint64_t* dest;      // span that receives the merged row in the slack CSR
   uint64_t n_entries;  // directed entries (2 per update)
   // entries grouped by row and sorted by destination
   uint32_t* seg_src;
@@ -291,13 +288,18 @@ struct BatchBufs {
   uint32_t* seg_del;
   uint32_t* seg_id;
   uint64_t* seg_pre;   // exclusive prefix of seg_del (ne + 1)
+  uint32_t* seg_lb;    // position of the entry's destination in the old row (lower bound)
+  uint32_t* sort_mid;  // touched rows whose segment the LDS sort takes
+  uint32_t* sort_long; // touched rows whose segment the merge sort takes
   uint32_t* tmp_dst;   // merge-sort scratch for long segments
   uint32_t* tmp_w;
   uint32_t* tmp_del;
-  // merged rows
-  uint32_t* mcols;
-  uint32_t* mw;
-  uint64_t mcap;
+  // old entries move in runs with one shift each: run i of touched row t lies
+  // between its segment entries; ne + nt runs
+  uint32_t* run_len;
+  uint64_t* run_off;   // exclusive prefix of run_len (ne + nt + 1)
+  int64_t* run_src;    // first old entry of the run
+  int64_t* run_dst;    // its place in the merged row
   void* scan_tmp;
   uint64_t* total;
 };
@@ -306,8 +308,9 @@ int batch_prepare(hipStream_t s, uint32_t n, const uint32_t* del, uint64_t n_del
 int batch_validate(hipStream_t s, Rows<uint32_t> g, uint32_t n, uint64_t n_entries, uint64_t n_touched, BatchBufs& b,
                    Ctl* ctl);
 // applies the validated batch; returns 1 if the overflow area is exhausted (nothing written)
-int batch_merge(hipStream_t s, int64_t* start, uint32_t* len, uint32_t* cap, uint32_t* cols, uint32_t* w,
-                uint64_t n_touched, BatchBufs& b, unsigned long long* edge_top, uint64_t edge_cap, Ctl* ctl);
+int batch_merge(hipStream_t s, int64_t* start, int64_t* alt, uint32_t* len, uint32_t* cap, uint32_t* cols,
+                uint32_t* w, uint64_t n_touched, BatchBufs& b, unsigned long long* edge_top, uint64_t edge_cap,
+                Ctl* ctl);
 void launch_aux_update(hipStream_t s, const BatchBufs& b, uint64_t n_entries, const uint32_t* Cprev, int64_t* K,
                        int64_t* S, int64_t* dSig);
 void launch_mark_communities(hipStream_t s, const BatchBufs& b, uint64_t n_entries, const uint32_t* Cprev,

@@ -100,7 +100,7 @@ struct leiden_graph {
   uint32_t n = 0;
   float slack = 0.2f;
   SlackCsr g;
-  Buf b_start, b_len, b_cap, b_cols, b_w;
+  Buf b_start, b_alt, b_len, b_cap, b_cols, b_w;
   Buf b_top;  // unsigned long long bump pointer of the overflow area
   uint64_t nnz = 0;
   // auxiliary state (Section 4.4): C, K, Sigma, DeltaSigma
@@ -125,7 +125,8 @@ struct leiden_graph {
       tr_matched;
   Buf dV, dE, dC, sig, partials, modparts;
   Buf bt_src, bt_dst, bt_w, bt_del, bt_slot, bt_rowcnt, bt_rowidx, bt_touched, bt_segcnt, bt_segoff, bt_newlen,
-      bt_outoff, bt_ssrc, bt_sdst, bt_sw, bt_sdel, bt_sid, bt_spre, bt_tdst, bt_tw, bt_tdel, bt_mcols, bt_mw, bt_in, bt_oldlen, bt_oldoff, bt_dest;
+      bt_ssrc, bt_sdst, bt_sw, bt_sdel, bt_sid, bt_spre, bt_slb, bt_sortl, bt_tdst, bt_tw, bt_tdel, bt_in, bt_dest, bt_rlen,
+      bt_roff, bt_rsrc, bt_rdst;
   Buf rb_cols, rb_w, rb_off, rb_reserve;
   Buf scatter_ws;  // bucketed scatter reductions over n items
   size_t ws_n = 0, ws_classes = 0;
@@ -199,6 +200,7 @@ hipStream_t stream_of(leiden_graph* g, const leiden_opts* o) {
 
 void bind_graph(leiden_graph* G) {
   G->g.start = G->b_start.as<int64_t>();
+  G->g.alt = G->b_alt.as<int64_t>();
   G->g.len = G->b_len.as<uint32_t>();
   G->g.cap = G->b_cap.as<uint32_t>();
   G->g.cols = G->b_cols.as<uint32_t>();
@@ -747,6 +749,10 @@ leiden_status copy_in(hipStream_t s, void* dst, const void* src, size_t bytes, i
   return LEIDEN_OK;
 }
 
+// Entries allocated for a layout whose row capacities sum to tot: two spans
+// per row plus an overflow area for rows that outgrow them.
+uint64_t edge_capacity(uint64_t tot) { return 2 * tot + tot / 4 + 8192; }
+
 // Rebuild the slack CSR so every row has room for `reserve` entries (or its
 // current length when reserve is null), with fresh per-row slack.
 leiden_status rebuild(leiden_graph* G, hipStream_t s, const uint32_t* reserve) {
@@ -756,13 +762,13 @@ leiden_status rebuild(leiden_graph* G, hipStream_t s, const uint32_t* reserve) {
   rebuild_caps(s, n, G->g.len, reserve, G->slack, G->g.cap, G->rb_off.as<uint64_t>(), G->scan_tmp.p, total);
   uint64_t tot = 0;
   CHK(read_dev(s, &tot, total));
-  const uint64_t cap = tot + tot / 8 + 4096;
+  const uint64_t cap = edge_capacity(tot);
   Buf nc, nw;
   CHK(nc.reserve(cap * 4));
   CHK(nw.reserve(cap * 4));
-  copy_rows(s, n, G->g.start, G->g.len, G->g.cols, G->g.w, G->rb_off.as<uint64_t>(), nc.as<uint32_t>(),
-            nw.as<uint32_t>(), G->g.start);
-  unsigned long long top = tot;
+  copy_rows(s, n, G->g.start, G->g.len, G->g.cap, G->g.cols, G->g.w, G->rb_off.as<uint64_t>(), nc.as<uint32_t>(),
+            nw.as<uint32_t>(), G->g.start, G->g.alt);
+  unsigned long long top = 2 * tot;
   HIPCHK(hipMemcpyAsync(G->b_top.p, &top, sizeof(top), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   std::swap(G->b_cols.p, nc.p);
@@ -1016,7 +1022,8 @@ leiden_status leiden_graph_create(int device, uint32_t n, uint64_t nnz, const in
   if (err & 4) return bail(fail(LEIDEN_EINVAL, "matrix is not symmetric (missing or unequal reverse entry)"));
   // slack layout
   const size_t nn = std::max<size_t>(n, 1);
-  if ((st = G->b_start.reserve(nn * 8)) || (st = G->b_len.reserve(nn * 4)) || (st = G->b_cap.reserve(nn * 4)) ||
+  if ((st = G->b_start.reserve(nn * 8)) || (st = G->b_alt.reserve(nn * 8)) || (st = G->b_len.reserve(nn * 4)) ||
+      (st = G->b_cap.reserve(nn * 4)) ||
       (st = G->b_top.reserve(8)) || (st = G->rb_off.reserve((nn + 1) * 8)) ||
       (st = G->scan_tmp.reserve(scan_tmp_bytes(std::max<uint64_t>(nn, 2 * nnz)) + 64)))
     return bail(st);
@@ -1026,13 +1033,13 @@ leiden_status leiden_graph_create(int device, uint32_t n, uint64_t nnz, const in
   uint64_t tot = 0;
   if (hipMemcpyAsync(&tot, total, 8, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
     return bail(fail(LEIDEN_EDEVICE, "layout failed"));
-  const uint64_t cap = tot + tot / 8 + 4096;
+  const uint64_t cap = edge_capacity(tot);
   if ((st = G->b_cols.reserve(cap * 4)) || (st = G->b_w.reserve(cap * 4))) return bail(st);
   bind_graph(G);
   G->g.edge_cap = cap;
-  copy_rows(s, n, in_offs.as<int64_t>(), G->g.len, in_cols.as<uint32_t>(), in_w.as<uint32_t>(),
-            G->rb_off.as<uint64_t>(), G->g.cols, G->g.w, G->g.start);
-  unsigned long long top = tot;
+  copy_rows(s, n, in_offs.as<int64_t>(), G->g.len, G->g.cap, in_cols.as<uint32_t>(), in_w.as<uint32_t>(),
+            G->rb_off.as<uint64_t>(), G->g.cols, G->g.w, G->g.start, G->g.alt);
+  unsigned long long top = 2 * tot;
   if (hipMemcpyAsync(G->b_top.p, &top, 8, hipMemcpyHostToDevice, s) != hipSuccess) return bail(fail(LEIDEN_EDEVICE, "copy"));
   G->bins0[0] = 0;
   if ((st = level_bins(G, s, G->g.len, n, G->bins0, &G->maxdeg0))) return bail(st);
@@ -1156,21 +1163,25 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   const size_t nn = std::max<size_t>(n, 1), nE = std::max<uint64_t>(ne, 1);
   CHK(G->bt_in.reserve((2 * n_del + 3 * n_ins + 1) * 4));
   for (Buf* b : {&G->bt_src, &G->bt_dst, &G->bt_w, &G->bt_del, &G->bt_slot, &G->bt_ssrc, &G->bt_sdst, &G->bt_sw,
-                 &G->bt_sdel, &G->bt_sid, &G->bt_tdst, &G->bt_tw, &G->bt_tdel, &G->bt_touched, &G->bt_segcnt,
-                 &G->bt_newlen, &G->bt_oldlen})
+                 &G->bt_sdel, &G->bt_sid, &G->bt_slb, &G->bt_tdst, &G->bt_tw, &G->bt_tdel, &G->bt_touched,
+                 &G->bt_segcnt, &G->bt_newlen})
     CHK(b->reserve(nE * 4));
-  CHK(G->bt_oldoff.reserve((nE + 1) * 8));
   CHK(G->bt_dest.reserve(nE * 8));
+  CHK(G->bt_sortl.reserve(2 * nE * 4));
   CHK(G->bt_segoff.reserve((nE + 1) * 8));
-  CHK(G->bt_outoff.reserve((nE + 1) * 8));
   CHK(G->bt_spre.reserve((nE + 1) * 8));
+  // runs of old entries: one per segment entry and one per touched row
+  CHK(G->bt_rlen.reserve(2 * nE * 4));
+  CHK(G->bt_roff.reserve((2 * nE + 1) * 8));
+  CHK(G->bt_rsrc.reserve(2 * nE * 8));
+  CHK(G->bt_rdst.reserve(2 * nE * 8));
   if (!G->rowcnt_ready) {
     CHK(G->bt_rowcnt.reserve(nn * 4));
     CHK(G->bt_rowidx.reserve(nn * 4));
     fill_u32(s, G->bt_rowcnt.as<uint32_t>(), 0, nn);
     G->rowcnt_ready = true;
   }
-  CHK(G->scan_tmp.reserve(scan_tmp_bytes(std::max<uint64_t>(nn, nE)) + 64));
+  CHK(G->scan_tmp.reserve(scan_tmp_bytes(std::max<uint64_t>(nn, 2 * nE)) + 64));
   hipEvent_t e0, e1, e2, e3;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -1208,9 +1219,6 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   bb.seg_cnt = G->bt_segcnt.as<uint32_t>();
   bb.seg_off = G->bt_segoff.as<uint64_t>();
   bb.new_len = G->bt_newlen.as<uint32_t>();
-  bb.out_off = G->bt_outoff.as<uint64_t>();
-  bb.old_len = G->bt_oldlen.as<uint32_t>();
-  bb.old_off = G->bt_oldoff.as<uint64_t>();
   bb.dest = G->bt_dest.as<uint64_t>();
   bb.n_entries = ne;
   bb.seg_src = G->bt_ssrc.as<uint32_t>();
@@ -1219,6 +1227,13 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   bb.seg_del = G->bt_sdel.as<uint32_t>();
   bb.seg_id = G->bt_sid.as<uint32_t>();
   bb.seg_pre = G->bt_spre.as<uint64_t>();
+  bb.seg_lb = G->bt_slb.as<uint32_t>();
+  bb.sort_mid = G->bt_sortl.as<uint32_t>();
+  bb.sort_long = G->bt_sortl.as<uint32_t>() + nE;
+  bb.run_len = G->bt_rlen.as<uint32_t>();
+  bb.run_off = G->bt_roff.as<uint64_t>();
+  bb.run_src = G->bt_rsrc.as<int64_t>();
+  bb.run_dst = G->bt_rdst.as<int64_t>();
   bb.tmp_dst = G->bt_tdst.as<uint32_t>();
   bb.tmp_w = G->bt_tw.as<uint32_t>();
   bb.tmp_del = G->bt_tdel.as<uint32_t>();
@@ -1235,26 +1250,12 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   if (rc & 4) return fail(LEIDEN_EINVAL, "invalid batch: insertion of a present edge");
   // merge into the slack CSR (rebuild with more room if the overflow area is short)
   {
-    uint64_t mneed = 0;
-    // upper bound of merged entries: touched rows' lengths + insertions
-    CHK(G->bt_mcols.reserve(std::max<uint64_t>(G->bt_mcols.bytes / 4, 1024) * 4));
-    bb.mcols = G->bt_mcols.as<uint32_t>();
-    bb.mw = G->bt_mw.as<uint32_t>();
-    bb.mcap = std::min(G->bt_mcols.bytes, G->bt_mw.bytes) / 4;
     for (int attempt = 0; attempt < 3; ++attempt) {
-      rc = batch_merge(s, G->g.start, G->g.len, G->g.cap, G->g.cols, G->g.w, nt, bb,
+      rc = batch_merge(s, G->g.start, G->g.alt, G->g.len, G->g.cap, G->g.cols, G->g.w, nt, bb,
                        G->b_top.as<unsigned long long>(), G->g.edge_cap, dctl(G));
       if (rc == 0) break;
       if (rc < 0) return fail(LEIDEN_EDEVICE, "batch merge failed");
-      // short of merge scratch or overflow room
-      CHK(read_dev(s, &mneed, bb.total));
-      if (mneed > bb.mcap) {
-        CHK(G->bt_mcols.reserve(mneed * 4 + 4096));
-        CHK(G->bt_mw.reserve(mneed * 4 + 4096));
-        bb.mcols = G->bt_mcols.as<uint32_t>();
-        bb.mw = G->bt_mw.as<uint32_t>();
-        bb.mcap = std::min(G->bt_mcols.bytes, G->bt_mw.bytes) / 4;
-      }
+      // short of overflow room
       unsigned long long need = 0, top = 0;
       HIPCHK(hipMemcpyAsync(&need, &dctl(G)->overflow_need, 8, hipMemcpyDeviceToHost, s));
       HIPCHK(hipMemcpyAsync(&top, G->b_top.p, 8, hipMemcpyDeviceToHost, s));
