@@ -53,7 +53,10 @@ struct DecideParams {
 // (R + 1) x nch matrix of 16-bit bucket starts.
 constexpr uint32_t kHubChunk = 2048, kHubSlots = 4096;
 constexpr uint32_t kHubBucketBits = 10, kHubBucket = 1u << kHubBucketBits;
-constexpr uint32_t kHubMaxRbits = 11;  // at most 2048 buckets per hub (LDS counters)
+// At most 256 buckets per hub: every chunk writes R + 1 scattered 16-bit
+// bucket starts (one column of the matrix), and the smaller counter array
+// leaves room for a third block per CU; the pick's groups just get larger.
+constexpr uint32_t kHubMaxRbits = 8;
 struct HubLayout {
   uint32_t* list;       // hubs of the level
   uint32_t* idx;        // vertex -> hub index (valid for hubs)

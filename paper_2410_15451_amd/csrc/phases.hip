@@ -689,9 +689,11 @@ __global__ __launch_bounds__(kBlock) void k_agg_lds(Rows<W> g, const uint32_t* C
 // community's staging area, with the bucket starts in column col of the
 // community's (R + 1) x smax matrix.  The emit kernel then sums each group of
 // buckets over all columns in an LDS table and writes the distinct keys into
-// the super row.
+// the super row.  At most 256 buckets (2^kBigMaxRbits): each stage column is
+// R + 1 scattered 16-bit stores, and the counters' LDS then leaves room for
+// three blocks per CU.
 constexpr uint32_t kBigMembers = 256, kBigStage = 2048, kBigSlots = 4096;
-constexpr uint32_t kBigBucketBits = 10, kBigMaxRbits = 11, kEmitWin = 2048, kEmitSlices = 256;
+constexpr uint32_t kBigBucketBits = 10, kBigMaxRbits = 8, kEmitWin = 2048, kEmitSlices = 256;
 
 struct BigComm {
   uint32_t c;      // community
