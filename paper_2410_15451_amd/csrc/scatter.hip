@@ -207,37 +207,96 @@ __global__ __launch_bounds__(kBlock) void k_bk_place(const uint32_t* sk, const u
   }
 }
 
-// Phase E: one block per bucket combines its pairs densely and updates out.
+// Phase E: work items of at most kBkSlice pairs: a bucket with more pairs is
+// cut into equal slices.  Renumbered community IDs fill only the first
+// buckets, so one block per bucket left a few blocks with all the pairs.
+// item_start[b] is the first item of bucket b (item_start[nb] = items).
+constexpr uint64_t kBkSlice = 8192;
+
+__global__ __launch_bounds__(kBlock) void k_bk_items(const uint64_t* off, const uint64_t* total, uint32_t nb,
+                                                     uint32_t* item_start) {
+  __shared__ uint32_t wsum[kBlock / kWave];
+  const uint32_t per = (nb + kBlock - 1) / kBlock;
+  const uint32_t b0 = min(nb, threadIdx.x * per), b1 = min(nb, b0 + per);
+  auto start = [&](uint32_t b) { return b < nb ? off[(size_t)b * kBkBlocks] : *total; };
+  auto slices = [&](uint32_t b) { return (uint32_t)((start(b + 1) - start(b) + kBkSlice - 1) / kBkSlice); };
+  uint32_t mine = 0;
+  for (uint32_t b = b0; b < b1; ++b) mine += slices(b);
+  // exclusive block scan of the per-thread sums
+  const uint32_t lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  uint32_t inc = mine;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t y = __shfl_up(inc, o);
+    if ((int)lane >= o) inc += y;
+  }
+  if (lane == kWave - 1) wsum[wv] = inc;
+  __syncthreads();
+  uint32_t base = inc - mine;
+  for (uint32_t q = 0; q < wv; ++q) base += wsum[q];
+  for (uint32_t b = b0; b < b1; ++b) {
+    item_start[b] = base;
+    base += slices(b);
+  }
+  if (threadIdx.x == kBlock - 1) item_start[nb] = base;  // the last thread's range ends at nb
+}
+
 template <Op OP, typename O>
 __global__ __launch_bounds__(kBlock) void k_bk_reduce(const uint32_t* bk, const unsigned long long* bv,
                                                       const uint64_t* off, const uint64_t* total, uint32_t nb,
-                                                      uint64_t key_range, O* out) {
+                                                      const uint32_t* item_start, uint64_t key_range, O* out) {
   __shared__ unsigned long long acc[kBkKeys];
-  for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
-    for (uint32_t q = threadIdx.x; q < kBkKeys; q += kBlock) acc[q] = OP == Op::kMin ? ~0ull : 0ull;
-    __syncthreads();
-    const uint64_t lo = off[(size_t)b * kBkBlocks];
-    const uint64_t hi = b + 1 < nb ? off[(size_t)(b + 1) * kBkBlocks] : *total;
-    for (uint64_t x = lo + threadIdx.x; x < hi; x += kBlock) {
-      const uint32_t k = bk[x] & (kBkKeys - 1);
-      if (OP == Op::kMin)
-        atomicMin(&acc[k], bv[x]);
+  __shared__ uint32_t sb;
+  const uint32_t it = blockIdx.x;
+  if (it >= item_start[nb]) return;  // block-uniform
+  if (threadIdx.x == 0) {            // last bucket whose first item is <= it
+    uint32_t lo = 0, hi = nb;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (item_start[mid] <= it)
+        lo = mid;
       else
-        atomicAdd(&acc[k], bv[x]);
+        hi = mid;
     }
-    __syncthreads();
-    const uint64_t k0 = (uint64_t)b << kBkBits;
-    for (uint32_t q = threadIdx.x; q < kBkKeys; q += kBlock) {
-      const uint64_t k = k0 + q;
-      if (k >= key_range) break;
-      const unsigned long long a = acc[q];
-      if (OP == Op::kMin) {
-        if (a != ~0ull && (O)a < out[k]) out[k] = (O)a;
-      } else if (a) {
-        out[k] = (O)((unsigned long long)out[k] + a);
+    sb = lo;
+  }
+  for (uint32_t q = threadIdx.x; q < kBkKeys; q += kBlock) acc[q] = OP == Op::kMin ? ~0ull : 0ull;
+  __syncthreads();
+  const uint32_t b = sb;
+  const uint32_t s = it - item_start[b], ns = item_start[b + 1] - item_start[b];
+  const uint64_t lo = off[(size_t)b * kBkBlocks];
+  const uint64_t len = (b + 1 < nb ? off[(size_t)(b + 1) * kBkBlocks] : *total) - lo;
+  const uint64_t x0 = lo + len * s / ns, x1 = lo + len * (s + 1) / ns;
+  for (uint64_t x = x0 + threadIdx.x; x < x1; x += kBlock) {
+    const uint32_t k = bk[x] & (kBkKeys - 1);
+    if (OP == Op::kMin)
+      atomicMin(&acc[k], bv[x]);
+    else
+      atomicAdd(&acc[k], bv[x]);
+  }
+  __syncthreads();
+  const uint64_t k0 = (uint64_t)b << kBkBits;
+  for (uint32_t q = threadIdx.x; q < kBkKeys; q += kBlock) {
+    const uint64_t k = k0 + q;
+    if (k >= key_range) break;
+    const unsigned long long a = acc[q];
+    if (OP == Op::kMin) {
+      if (a == ~0ull) continue;
+      if (ns > 1) {
+        static_assert(OP != Op::kMin || sizeof(O) == 4, "minimum index outputs are 32-bit");
+        atomicMin((unsigned int*)&out[k], (unsigned int)a);
+      } else if ((O)a < out[k]) {
+        out[k] = (O)a;
       }
+    } else {
+      if (!a) continue;
+      if (ns == 1)
+        out[k] = (O)((unsigned long long)out[k] + a);
+      else if (sizeof(O) == 8)
+        atomicAdd((unsigned long long*)&out[k], a);
+      else
+        atomicAdd((unsigned int*)&out[k], (unsigned int)a);
     }
-    __syncthreads();
   }
 }
 
@@ -245,7 +304,7 @@ __global__ __launch_bounds__(kBlock) void k_bk_reduce(const uint32_t* bk, const 
 struct BkLayout {
   uint64_t ntiles;
   uint32_t nb;
-  size_t o_sk, o_sv, o_tc, o_bk, o_bv, o_mat, o_off, o_tot, o_tmp, bytes;
+  size_t o_sk, o_sv, o_tc, o_bk, o_bv, o_mat, o_off, o_tot, o_items, o_tmp, bytes;
 };
 
 BkLayout bk_layout(uint64_t n, uint64_t key_range) {
@@ -271,6 +330,8 @@ BkLayout bk_layout(uint64_t n, uint64_t key_range) {
   o = al(o + (nm + 1) * 8);
   L.o_tot = o;
   o = al(o + 8);
+  L.o_items = o;
+  o = al(o + ((size_t)L.nb + 1) * 4);
   L.o_tmp = o;
   o = al(o + scan_tmp_bytes(nm) + 64);
   L.bytes = o;
@@ -292,6 +353,7 @@ bool bucketed(hipStream_t s, const uint32_t* key, const V* val, uint64_t n, uint
   uint32_t* mat = (uint32_t*)(p + L.o_mat);
   uint64_t* off = (uint64_t*)(p + L.o_off);
   uint64_t* tot = (uint64_t*)(p + L.o_tot);
+  uint32_t* items = (uint32_t*)(p + L.o_items);
   void* tmp = p + L.o_tmp;
   const size_t lds = (size_t)L.nb * 4;
   hipLaunchKernelGGL((k_bk_tiles<OP, V>), dim3(std::min<uint64_t>(L.ntiles, 4096)), dim3(kBlock), 0, s, key, val, n,
@@ -299,8 +361,11 @@ bool bucketed(hipStream_t s, const uint32_t* key, const V* val, uint64_t n, uint
   hipLaunchKernelGGL(k_bk_count, dim3(kBkBlocks), dim3(kBlock), lds, s, sk, tc, L.ntiles, L.nb, mat);
   exclusive_scan_u32(s, mat, off, (size_t)L.nb * kBkBlocks, tot, tmp);
   hipLaunchKernelGGL(k_bk_place, dim3(kBkBlocks), dim3(kBlock), lds, s, sk, sv, tc, L.ntiles, L.nb, off, bk, bv);
-  hipLaunchKernelGGL((k_bk_reduce<OP, O>), dim3(std::min<uint32_t>(L.nb, 4096)), dim3(kBlock), 0, s, bk, bv, off,
-                     tot, L.nb, key_range, out);
+  hipLaunchKernelGGL(k_bk_items, dim3(1), dim3(kBlock), 0, s, off, tot, L.nb, items);
+  // at most one item per bucket plus one per kBkSlice pairs (pairs <= n)
+  const uint64_t max_items = (uint64_t)L.nb + n / kBkSlice + 1;
+  hipLaunchKernelGGL((k_bk_reduce<OP, O>), dim3((uint32_t)max_items), dim3(kBlock), 0, s, bk, bv, off, tot, L.nb,
+                     items, key_range, out);
   return true;
 }
 
