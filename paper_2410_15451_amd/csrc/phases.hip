@@ -237,15 +237,20 @@ __global__ __launch_bounds__(kBlock) void k_split_compress(uint32_t* lab, const 
 
 // main tree of a community: that of its highest-degree member among those
 // with more than kSplitMainDeg entries (lowest ID on ties), else that of its
-// label vertex
+// label vertex.  Launched once per degree band, highest band first: a large
+// community's maximum is then set by its few hubs, and its many members of
+// lower degree find it already above their key with a plain read instead of
+// all racing to one address with atomics.
 constexpr uint32_t kSplitMainDeg = 128;
+constexpr uint32_t kSplitMainBands[] = {32768, 4096, 1024, kSplitMainDeg};
 __global__ __launch_bounds__(kBlock) void k_split_main(const uint32_t* len, const uint32_t* C, const uint32_t* list,
-                                                       unsigned long long* main_key, const Ctl* ctl) {
+                                                       unsigned long long* main_key, const Ctl* ctl, uint32_t lo,
+                                                       uint32_t hi) {
   const uint32_t cnt = ctl->split_count;
   GRID_STRIDE(it, cnt) {
     const uint32_t u = list[it];
     const uint32_t L = len[u];
-    if (L <= kSplitMainDeg) continue;
+    if (L <= lo || L > hi) continue;
     const unsigned long long key = ((unsigned long long)L << 32) | (unsigned long long)(0xFFFFFFFFu - u);
     unsigned long long* slot = &main_key[C[u]];
     if (__atomic_load_n(slot, __ATOMIC_RELAXED) < key) atomicMax(slot, key);
@@ -335,7 +340,11 @@ void launch_split_sample(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* 
   hipLaunchKernelGGL((k_split_sample<W>), dim3(grid_n((uint64_t)n_upper * kSplitSample)), dim3(kBlock), 0, s, g, C,
                      lab, list, ctl);
   hipLaunchKernelGGL(k_split_compress, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, lab, list, ctl);
-  hipLaunchKernelGGL(k_split_main, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, g.len, C, list, main_key, ctl);
+  uint32_t hi = 0xFFFFFFFFu;
+  for (const uint32_t lo : kSplitMainBands) {
+    hipLaunchKernelGGL(k_split_main, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, g.len, C, list, main_key, ctl, lo, hi);
+    hi = lo;
+  }
   hipLaunchKernelGGL(k_split_rest, dim3(grid_n(n_upper, kBlock * kTileU)), dim3(kBlock), 0, s, n_upper, C, lab, list,
                      main_key, rest, ctl);
 }
@@ -1229,15 +1238,22 @@ __global__ __launch_bounds__(kBlock) void k_track_pairs(uint32_t n, const uint32
   }
 }
 
+// The maxima of the overlap weights are taken in two launches, weights of at
+// least kTrackHeavy first: a large community's maximum is then in place
+// before its many light pairs arrive, and those find it with a plain read
+// (atomics on one address are serialised device-wide).
+constexpr long long kTrackHeavy = 1ll << 16;
+
 __global__ __launch_bounds__(kBlock) void k_track_best_w(const unsigned long long* hk, const long long* hv,
-                                                         uint64_t slots, long long* best_w) {
+                                                         uint64_t slots, long long* best_w, bool heavy) {
   GRID_STRIDE(sl, slots) {
     const unsigned long long k = hk[sl];
     if (k == kNone64) continue;
-    // read first: most updates would not raise the maximum, and atomics on
-    // one address (a large community's entry) are serialised device-wide
+    const long long w = hv[sl];
+    if ((w >= kTrackHeavy) != heavy) continue;
+    // read first: most updates would not raise the maximum
     long long* slot = &best_w[k >> 32];
-    if (__atomic_load_n(slot, __ATOMIC_RELAXED) < hv[sl]) atomicMax(slot, hv[sl]);
+    if (__atomic_load_n(slot, __ATOMIC_RELAXED) < w) atomicMax(slot, w);
   }
 }
 
@@ -1254,12 +1270,14 @@ __global__ __launch_bounds__(kBlock) void k_track_best_c(const unsigned long lon
 }
 
 __global__ __launch_bounds__(kBlock) void k_track_cand_w(uint32_t n, const uint32_t* Ccur, const long long* best_w,
-                                                         const uint32_t* best_vmin, long long* cand_w) {
+                                                         const uint32_t* best_vmin, long long* cand_w, bool heavy) {
   GRID_STRIDE(b, n) {
     const uint32_t vm = best_vmin[b];
     if (vm == kNone) continue;
+    const long long w = best_w[b];
+    if ((w >= kTrackHeavy) != heavy) continue;
     long long* slot = &cand_w[Ccur[vm]];
-    if (__atomic_load_n(slot, __ATOMIC_RELAXED) < best_w[b]) atomicMax(slot, best_w[b]);
+    if (__atomic_load_n(slot, __ATOMIC_RELAXED) < w) atomicMax(slot, w);
   }
 }
 
@@ -1319,12 +1337,16 @@ void track(hipStream_t s, uint32_t n, const uint32_t* Ccur, const uint32_t* Cpre
                      b.hvals, b.hmask, b.is_old);
   fill_i64(s, (int64_t*)b.best_w, -1, n);
   fill_u32(s, b.best_vmin, kNone, n);
-  hipLaunchKernelGGL(k_track_best_w, dim3(grid_n(slots)), dim3(kBlock), 0, s, b.hkeys, b.hvals, slots, b.best_w);
+  for (const bool heavy : {true, false})
+    hipLaunchKernelGGL(k_track_best_w, dim3(grid_n(slots)), dim3(kBlock), 0, s, b.hkeys, b.hvals, slots, b.best_w,
+                       heavy);
   hipLaunchKernelGGL(k_track_best_c, dim3(grid_n(slots)), dim3(kBlock), 0, s, b.hkeys, b.hvals, slots, b.best_w,
                      b.minv, b.best_vmin);
   fill_i64(s, (int64_t*)b.cand_w, -1, n);
   fill_u32(s, b.cand_b, kNone, n);
-  hipLaunchKernelGGL(k_track_cand_w, dim3(grid_n(n)), dim3(kBlock), 0, s, n, Ccur, b.best_w, b.best_vmin, b.cand_w);
+  for (const bool heavy : {true, false})
+    hipLaunchKernelGGL(k_track_cand_w, dim3(grid_n(n)), dim3(kBlock), 0, s, n, Ccur, b.best_w, b.best_vmin, b.cand_w,
+                       heavy);
   hipLaunchKernelGGL(k_track_cand_b, dim3(grid_n(n)), dim3(kBlock), 0, s, n, Ccur, b.best_w, b.best_vmin, b.cand_w,
                      b.cand_b);
   uint32_t* freeflag = b.label;  // scratch reuse
