@@ -21,6 +21,7 @@ struct DecideParams {
   const unsigned int* count;
   Mover* movers;
   Ctl* ctl;
+  unsigned long long* edge_parts;  // edge scans, kEdgeParts counters kEdgeStride apart
   int async;             // 1: moves are applied at once against the live state
   uint8_t* dS;           // split flags for asynchronous local moves (dynamic runs) or null
   // hub bin: a hub of degree L has nch = ceil(L / kHubChunk) chunks; chunk k
@@ -46,6 +47,17 @@ struct DecideParams {
   unsigned int* hub_done;
   unsigned long long* hub_items;  // (hub vertex, chunk) work items of the current sub-round
 };
+
+// Edge-scan counters of the decide kernels: each block adds to counter
+// blockIdx.x % kEdgeParts, each on its own 256-byte line, folded into
+// Ctl::edges at the end of a call.  Thousands of blocks that finish
+// together and all add to one address queue on it (atomics on one address
+// are serialised device-wide): one shared counter cost the small-degree
+// decide kernel about 90 of its 127 µs.
+constexpr uint32_t kEdgeParts = 64, kEdgeStride = 32;
+__device__ inline void add_edges(unsigned long long* parts, unsigned long long e) {
+  if (e && parts) atomicAdd(&parts[(blockIdx.x % kEdgeParts) * kEdgeStride], e);
+}
 
 // Hub layout of one level: a hub (degree above the last LDS bin) of degree
 // L gets nch = ceil(L / kHubChunk) chunks of staging slots and R =

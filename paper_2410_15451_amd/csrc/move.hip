@@ -288,7 +288,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_small(DecideParams<W> p, Smal
   else
     edges = decide_group_body<64, 256, W, REFINE>(p, sb.list[2], *sb.count[2], b - sb.n0 - sb.n1, sb.n2, keys,
                                                   vals, st);
-  if (edges) atomicAdd(&p.ctl->edges, edges);
+  add_edges(p.edge_parts, edges);
 }
 
 // One block (kBlock lanes) per vertex, T-slot table in LDS.
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(DecideParams<W> p) {
   }
   __syncthreads();
   stage_flush(st, p.ctl, p.movers);
-  if (edges) atomicAdd(&p.ctl->edges, edges);
+  add_edges(p.edge_parts, edges);
 }
 
 // ---------------------------------------------------------------------------
@@ -449,7 +449,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_chunk(DecideParams<W> p) {
     for (uint32_t b = threadIdx.x; b <= R; b += kBlock) lcnt[b] = 0;
   }
   if (edges) {
-    atomicAdd(&p.ctl->edges, edges);
+    add_edges(p.edge_parts, edges);
     if (sizeof(W) == 4 && !REFINE) atomicAdd(&p.ctl->kt_units[LEIDEN_KT_HUB_INSERT], edges);
   }
 }

@@ -102,6 +102,7 @@ struct leiden_graph {
   SlackCsr g;
   Buf b_start, b_alt, b_len, b_cap, b_cols, b_w;
   Buf b_top;  // unsigned long long bump pointer of the overflow area
+  Buf edge_parts;  // edge-scan counters of the decide kernels (kEdgeParts x kEdgeStride)
   uint64_t nnz = 0;
   // auxiliary state (Section 4.4): C, K, Sigma, DeltaSigma
   bool has_state = false;
@@ -253,6 +254,7 @@ leiden_status ensure_workspace(leiden_graph* G, hipStream_t s, uint32_t classes)
   CHK(G->newid.reserve((n + 1) * u64));
   CHK(G->scan_tmp.reserve(scan_tmp_bytes(std::max<uint64_t>(n, 2 * nnz)) + 64));
   CHK(G->ctl.reserve(sizeof(Ctl)));
+  CHK(G->edge_parts.reserve(sizeof(unsigned long long) * kEdgeParts * kEdgeStride));
   CHK(G->small.reserve(4096));
   for (Buf* b : {&G->lvA_start, &G->lvB_start}) CHK(b->reserve(n * u64));
   for (Buf* b : {&G->lvA_len, &G->lvB_len}) CHK(b->reserve(n * u32));
@@ -352,6 +354,7 @@ leiden_status setup_hubs(leiden_graph* G, hipStream_t s, const uint32_t* len, ui
 
 template <typename W>
 void bind_hubs(leiden_graph* G, DecideParams<W>& dp) {
+  dp.edge_parts = G->edge_parts.as<unsigned long long>();
   dp.hub_idx = G->hub_idx.as<uint32_t>();
   dp.hub_off = G->hub_off.as<uint64_t>();
   dp.hub_rbits = G->hub_rbits.as<uint32_t>();
@@ -385,12 +388,34 @@ leiden_status read_dev(hipStream_t s, T* out, const void* dev) {
   return LEIDEN_OK;
 }
 
-__global__ void k_zero_ctl(Ctl* c) {
+__global__ void k_zero_ctl(Ctl* c, unsigned long long* parts) {
   unsigned int* p = (unsigned int*)c;
   for (size_t i = threadIdx.x; i < sizeof(Ctl) / 4; i += blockDim.x) p[i] = 0;
+  if (parts)
+    for (uint32_t i = threadIdx.x; i < kEdgeParts * kEdgeStride; i += blockDim.x) parts[i] = 0;
 }
 
-void zero_ctl(leiden_graph* G, hipStream_t s) { hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(256), 0, s, dctl(G)); }
+void zero_ctl(leiden_graph* G, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(256), 0, s, dctl(G), G->edge_parts.as<unsigned long long>());
+}
+
+// Ctl::edges += the decide kernels' edge-scan counters, which are cleared.
+__global__ void k_fold_edges(Ctl* c, unsigned long long* parts) {
+  unsigned long long e = 0;
+  if (threadIdx.x < kEdgeParts) {
+    e = parts[threadIdx.x * kEdgeStride];
+    parts[threadIdx.x * kEdgeStride] = 0;
+  }
+  e = group_sum<kWave>(e);
+  if (threadIdx.x == 0) c->edges += e;
+}
+
+// read_ctl with the edge-scan counters folded in first (end of a call)
+leiden_status read_ctl_final(leiden_graph* G, hipStream_t s) {
+  if (G->edge_parts.p)
+    hipLaunchKernelGGL(k_fold_edges, dim3(1), dim3(kWave), 0, s, dctl(G), G->edge_parts.as<unsigned long long>());
+  return read_ctl(G, s);
+}
 
 // Degree bins (vertex counts per bin) and max degree of one level.
 leiden_status level_bins(leiden_graph* G, hipStream_t s, const uint32_t* len, uint32_t nl, uint64_t bins[kBins],
@@ -1114,7 +1139,7 @@ leiden_status leiden_static(leiden_graph* G, const leiden_opts* opts, uint32_t* 
   HIPCHK(hipStreamSynchronize(s));
   if (q_out) *q_out = q;
   if (stats) {
-    CHK(read_ctl(G, s));
+    CHK(read_ctl_final(G, s));
     float ms = 0;
     (void)hipEventElapsedTime(&ms, e0, e2);
     stats->ms_total = ms;
@@ -1372,7 +1397,7 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   HIPCHK(hipStreamSynchronize(s));
   if (q_out) *q_out = q;
   if (stats) {
-    CHK(read_ctl(G, s));
+    CHK(read_ctl_final(G, s));
     float ms = 0;
     (void)hipEventElapsedTime(&ms, e0, e3);
     stats->ms_total = ms;
