@@ -169,8 +169,9 @@ void scatter_min_index(hipStream_t s, const uint32_t* key, uint64_t n, uint32_t*
 
 // phases.hip
 void fill_u64(hipStream_t s, uint64_t* p, uint64_t v, size_t n);
+// bins_out / maxdeg_out are added to; parts: 64 x 16 u64 of scratch
 void launch_degree_hist(hipStream_t s, const uint32_t* len, uint32_t n, const BinCfg& cfg, unsigned long long* bins_out,
-                        unsigned int* maxdeg_out);
+                        unsigned int* maxdeg_out, unsigned long long* parts);
 void launch_row_sums_u32(hipStream_t s, Rows<uint32_t> g, uint32_t n, int64_t* K);
 void launch_count_members(hipStream_t s, const uint32_t* C, uint32_t n, uint32_t* size);
 void launch_sigma_from(hipStream_t s, const uint32_t* C, const int64_t* K, uint32_t n, int64_t* S);

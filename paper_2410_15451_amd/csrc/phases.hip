@@ -24,8 +24,12 @@ static int grid_n(uint64_t n, int per_block = kBlock, int cap = 8192) {
 // ---------------------------------------------------------------------------
 // Per-level helpers
 // ---------------------------------------------------------------------------
+// Each block adds its counts to one of kHistParts partial rows (own cache
+// line each), summed by k_hist_fold: blocks that finish together and all add
+// to the same few words queue on them.
+constexpr uint32_t kHistParts = kWave, kHistStride = 16;
 __global__ __launch_bounds__(kBlock) void k_degree_hist(const uint32_t* len, uint32_t n, BinCfg cfg,
-                                                        unsigned long long* bins, unsigned int* maxdeg) {
+                                                        unsigned long long* parts) {
   __shared__ unsigned int lb[kBins];
   __shared__ unsigned int lmax;
   if (threadIdx.x < kBins) lb[threadIdx.x] = 0;
@@ -39,14 +43,29 @@ __global__ __launch_bounds__(kBlock) void k_degree_hist(const uint32_t* len, uin
     }
   }
   __syncthreads();
-  if (threadIdx.x < kBins && lb[threadIdx.x]) atomicAdd(&bins[threadIdx.x], (unsigned long long)lb[threadIdx.x]);
-  if (threadIdx.x == 0 && lmax) atomicMax(maxdeg, lmax);
+  unsigned long long* part = parts + (size_t)(blockIdx.x % kHistParts) * kHistStride;
+  if (threadIdx.x < kBins && lb[threadIdx.x]) atomicAdd(&part[threadIdx.x], (unsigned long long)lb[threadIdx.x]);
+  if (threadIdx.x == 0 && lmax) atomicMax(&part[kBins], (unsigned long long)lmax);
+}
+
+// one wavefront, lane p reads partial row p
+__global__ void k_hist_fold(const unsigned long long* parts, unsigned long long* bins, unsigned int* maxdeg) {
+  const unsigned long long* row = parts + (size_t)threadIdx.x * kHistStride;
+  for (int q = 0; q < kBins; ++q) {
+    const unsigned long long c = group_sum<kWave>(row[q]);
+    if (threadIdx.x == 0) bins[q] += c;
+  }
+  unsigned long long m = row[kBins];
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) m = max(m, (unsigned long long)__shfl_xor(m, o));
+  if (threadIdx.x == 0 && m > *maxdeg) *maxdeg = (unsigned int)m;
 }
 
 void launch_degree_hist(hipStream_t s, const uint32_t* len, uint32_t n, const BinCfg& cfg, unsigned long long* bins_out,
-                        unsigned int* maxdeg_out) {
-  hipLaunchKernelGGL(k_degree_hist, dim3(grid_n(n, kBlock, 2048)), dim3(kBlock), 0, s, len, n, cfg, bins_out,
-                     maxdeg_out);
+                        unsigned int* maxdeg_out, unsigned long long* parts) {
+  fill_u64(s, (uint64_t*)parts, 0, (size_t)kHistParts * kHistStride);
+  hipLaunchKernelGGL(k_degree_hist, dim3(grid_n(n, kBlock, 2048)), dim3(kBlock), 0, s, len, n, cfg, parts);
+  hipLaunchKernelGGL(k_hist_fold, dim3(1), dim3(kWave), 0, s, parts, bins_out, maxdeg_out);
 }
 
 // Weighted degree of every row, one wavefront per row.

@@ -103,6 +103,7 @@ struct leiden_graph {
   Buf b_start, b_alt, b_len, b_cap, b_cols, b_w;
   Buf b_top;  // unsigned long long bump pointer of the overflow area
   Buf edge_parts;  // edge-scan counters of the decide kernels (kEdgeParts x kEdgeStride)
+  Buf hist_parts;  // partial rows of the degree histogram (64 x 16 u64)
   uint64_t nnz = 0;
   // auxiliary state (Section 4.4): C, K, Sigma, DeltaSigma
   bool has_state = false;
@@ -421,8 +422,9 @@ leiden_status read_ctl_final(leiden_graph* G, hipStream_t s) {
 leiden_status level_bins(leiden_graph* G, hipStream_t s, const uint32_t* len, uint32_t nl, uint64_t bins[kBins],
                          uint32_t* maxdeg) {
   unsigned long long* d = G->small.as<unsigned long long>();
+  CHK(G->hist_parts.reserve(sizeof(unsigned long long) * 64 * 16));
   fill_u64(s, (uint64_t*)d, 0, kBins + 1);
-  launch_degree_hist(s, len, nl, G->bincfg, d, (unsigned int*)(d + kBins));
+  launch_degree_hist(s, len, nl, G->bincfg, d, (unsigned int*)(d + kBins), G->hist_parts.as<unsigned long long>());
   unsigned long long* h = (unsigned long long*)pinned_stage(sizeof(unsigned long long) * (kBins + 1));
   if (!h) return fail(LEIDEN_ENOMEM, "pinned staging buffer");
   HIPCHK(hipMemcpyAsync(h, d, sizeof(unsigned long long) * (kBins + 1), hipMemcpyDeviceToHost, s));
