@@ -333,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void k_runs_tail(uint64_t nt, const int64_t
 // past the current one.  A thread finds the run of its entry in the window:
 // the run of its previous entry if that still holds it (long runs), else by
 // binary search.
-constexpr uint32_t kRunWin = 512, kCopyTile = 4 * kBlock;
+constexpr uint32_t kRunWin = 512, kCopyU = 4, kCopyTile = kCopyU * kBlock;
 // blocks of the run copy (the entry count is known on the device only)
 constexpr int kCopyGrid = 2048;
 
@@ -369,22 +369,38 @@ __global__ __launch_bounds__(kBlock) void k_copy_runs(uint64_t nruns, const uint
       j = 0;
     }
     const uint64_t x1 = min(min(x0 + kCopyTile, woff[wn]), xe);
-    for (uint64_t x = x0 + threadIdx.x; x < x1; x += kBlock) {
-      if (woff[j + 1] <= x) {  // largest run j < wn with woff[j] <= x
-        uint32_t lo = j + 1, hi = wn;
-        while (hi - lo > 1) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (woff[mid] <= x)
-            lo = mid;
-          else
-            hi = mid;
+    // all loads of the tile first, then the stores: sources and destinations
+    // lie in different spans, so the loads need not wait for earlier stores
+    uint32_t vc[kCopyU], vw[kCopyU];
+    int64_t vd[kCopyU];
+#pragma unroll
+    for (uint32_t u = 0; u < kCopyU; ++u) {
+      const uint64_t x = x0 + threadIdx.x + (uint64_t)u * kBlock;
+      vd[u] = -1;
+      if (x < x1) {
+        if (woff[j + 1] <= x) {  // largest run j < wn with woff[j] <= x
+          uint32_t lo = j + 1, hi = wn;
+          while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (woff[mid] <= x)
+              lo = mid;
+            else
+              hi = mid;
+          }
+          j = lo;
         }
-        j = lo;
+        const uint64_t k = x - woff[j];
+        const int64_t src = wsrc[j] + (int64_t)k;
+        vd[u] = wdst[j] + (int64_t)k;
+        vc[u] = cols[src];
+        vw[u] = w[src];
       }
-      const uint64_t k = x - woff[j];
-      const int64_t src = wsrc[j] + (int64_t)k, dst = wdst[j] + (int64_t)k;
-      cols[dst] = cols[src];
-      w[dst] = w[src];
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kCopyU; ++u) {
+      if (vd[u] < 0) continue;
+      cols[vd[u]] = vc[u];
+      w[vd[u]] = vw[u];
     }
     x0 = x1;
   }
