@@ -87,8 +87,13 @@ def lib():
         L.oracle_aggregate.argtypes = [u32, P, P, P, P, u32, P, P, P]
         L.oracle_aggregate.restype = i64
         L.oracle_split.argtypes = [u32, P, P, P, P, P, P]
-        L.oracle_move_trace.argtypes = [u32, P, P, P, P, dbl, u32, P, i64]
-        L.oracle_move_trace.restype = i64
+        L.oracle_trace_enable.argtypes = [i32]
+        L.oracle_trace_moves.argtypes = [P, P, i64]
+        L.oracle_trace_moves.restype = i64
+        L.oracle_trace_passes.argtypes = [P, P, u32]
+        L.oracle_trace_passes.restype = u32
+        L.oracle_trace_projection.argtypes = [u32, i32, P]
+        L.oracle_trace_projection.restype = i32
         L.oracle_static.argtypes = [u32, P, P, P, P, P, P, P]
         L.oracle_static.restype = i32
         L.oracle_apply_batch.argtypes = [u32, P, P, P, P, u64, P, u64, P, P, P, P]
@@ -182,17 +187,50 @@ def split(g, C, split_flags, refine_flags):
     return C
 
 
-def move_trace(g, C=None, tau=1e-2, max_iters=20):
-    """One SEQ local-moving phase; returns (C after, [(v, from, to, dq)])."""
-    C = np.arange(g.n, dtype=np.uint32) if C is None else _c(C, np.uint32).copy()
-    cap = 4 * max(g.nnz, g.n) + 16
-    tr = np.zeros(4 * cap, np.uint64)
-    cnt = lib().oracle_move_trace(g.n, _p(_c(g.offs, np.int64)), _p(_c(g.cols, np.uint32)),
-                                  _p(_c(g.w, np.uint32)), _p(C), tau, max_iters, _p(tr), cap)
-    cnt = min(cnt, cap)
-    t = tr[:4 * cnt].reshape(-1, 4)
-    moves = [(int(a), int(b), int(c), float(np.array([d], np.uint64).view(np.float64)[0])) for a, b, c, d in t]
-    return C, moves
+@dataclass
+class PassRecord:
+    iters: int      # local-moving iterations executed
+    refined: bool   # some community was refined
+    n_level: int    # vertices of the pass's level graph
+    moves: int      # local-moving moves
+    tau: float      # the pass's iteration tolerance
+    bound: np.ndarray    # communities of the input vertices by the pass's local-moving labels
+    refined_labels: np.ndarray  # ... and by its refined labels
+
+
+@dataclass
+class Trace:
+    moves: list     # (pass, iteration, vertex, from, to, dq) in order
+    passes: list    # PassRecord per pass
+
+
+def traced(fn, *a, n_input, **kw):
+    """Run ``fn(*a, **kw)`` (static or update) while the oracle records its
+    pass loop; returns (fn's result, Trace)."""
+    L = lib()
+    L.oracle_trace_enable(1)
+    try:
+        res = fn(*a, **kw)
+        cnt = L.oracle_trace_moves(None, None, 0)
+        rec = np.zeros(5 * max(cnt, 1), np.uint32)
+        dq = np.zeros(max(cnt, 1), np.float64)
+        L.oracle_trace_moves(_p(rec), _p(dq), cnt)
+        moves = [tuple(int(x) for x in rec[5 * k:5 * k + 5]) + (float(dq[k]),) for k in range(cnt)]
+        npass = L.oracle_trace_passes(None, None, 0)
+        prec = np.zeros(4 * max(npass, 1), np.uint32)
+        ptau = np.zeros(max(npass, 1), np.float64)
+        L.oracle_trace_passes(_p(prec), _p(ptau), npass)
+        passes = []
+        for p in range(npass):
+            b = np.zeros(n_input, np.uint32)
+            r = np.zeros(n_input, np.uint32)
+            L.oracle_trace_projection(p, 0, _p(b))
+            L.oracle_trace_projection(p, 1, _p(r))
+            passes.append(PassRecord(int(prec[4 * p]), bool(prec[4 * p + 1]), int(prec[4 * p + 2]),
+                                     int(prec[4 * p + 3]), float(ptau[p]), b, r))
+        return res, Trace(moves, passes)
+    finally:
+        L.oracle_trace_enable(0)
 
 
 def static(g, schedule=JACOBI, **kw):

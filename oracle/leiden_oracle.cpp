@@ -151,6 +151,26 @@ const double kTwo56 = 72057594037927936.0;
 i64 gain_to_fixed(double dq) { return (i64)(dq * kTwo56); }
 double fixed_to_gain(i64 s) { return (double)s / kTwo56; }
 
+/* Optional record of a run for the tests (never read by the algorithm): every
+ * local-moving move (pass, iteration, vertex, source and target community,
+ * gain), and for every pass of Alg. 4 its iteration count, tolerance, whether
+ * a community was refined, and the communities of the input vertices given by
+ * the pass's local-moving labels (the refinement bounds) and by its refined
+ * labels. */
+struct Trace {
+  u32 pass = 0;
+  std::vector<u32> move_rec;  // 5 per move: pass, iteration, vertex, from, to
+  std::vector<double> move_dq;
+  std::vector<u32> pass_rec;  // 4 per pass: iterations, refined, level vertices, moves
+  std::vector<double> pass_tau;
+  std::vector<std::vector<u32>> bound_proj, refined_proj;
+  void move(u32 li, u32 v, u32 from, u32 to, double dq) {
+    move_rec.insert(move_rec.end(), {pass, li, v, from, to});
+    move_dq.push_back(dq);
+  }
+};
+thread_local Trace* g_trace = nullptr;
+
 /* MurmurHash3 32-bit finaliser (Appleby): hashes vertex IDs into the classes
  * of the synchronous schedules. */
 u32 fmix32(u32 h) {
@@ -281,6 +301,7 @@ MoveResult move_seq(Level& L, std::vector<u8>& unprocessed, const std::vector<u8
       L.C[i] = ch.c;
       dQ += gain_to_fixed(ch.dq);
       r.moves++;
+      if (g_trace) g_trace->move(li, i, d, ch.c, ch.dq);
       for (i64 e = L.G.offs[i]; e < L.G.offs[i + 1]; ++e) unprocessed[L.G.cols[e]] = 1;
       if (dynamic) L.dS[d] = 1;
     }
@@ -347,6 +368,7 @@ MoveResult move_jacobi(Level& L, std::vector<u8>& unprocessed, const std::vector
         L.C[mv.i] = mv.c;
         dQ += gain_to_fixed(mv.dq);
         if (dynamic) L.dS[d] = 1;
+        if (g_trace) g_trace->move(li, mv.i, d, mv.c, mv.dq);
       }
       r.moves += moves.size();
       for (const Move& mv : moves) {
@@ -685,9 +707,11 @@ std::vector<u32> leiden(const Graph& G0, const std::vector<u32>& Cprev, const st
   L.dR = std::move(dR);
   std::vector<u8> unprocessed = F.affected;
   double tau = o.tau;
+  std::vector<u32> CB;  // C'_B: the refinement bounds of the current pass
   u32 lp = 0;
   for (; lp < o.max_passes; ++lp) {
     const std::vector<u8>* in_range = (lp == 0 && !F.range_all) ? &F.in_range : nullptr;
+    if (g_trace) g_trace->pass = lp;
     MoveResult mr = jacobi ? move_jacobi(L, unprocessed, in_range, dynamic, tau, k, o.max_iters, o.move_classes)
                            : move_seq(L, unprocessed, in_range, dynamic, tau, k, o.max_iters);
     if (st) {
@@ -702,12 +726,23 @@ std::vector<u32> leiden(const Graph& G0, const std::vector<u32>& Cprev, const st
     subset_renumber(L);
     u64 split_marked = split_communities(L, o.split_all != 0);
     if (st && lp == 0) st->split_marked = split_marked;
-    std::vector<u32> CB = L.C;
+    CB = L.C;
     u64 rmoves = 0;
     bool refined = refine(L, CB, k, jacobi, o.refine_rounds, &rmoves);
     if (st) {
       st->refine_moves += rmoves;
       if (lp == 0) st->refined_first_pass = refined ? 1 : 0;
+    }
+    if (g_trace) {
+      g_trace->pass_rec.insert(g_trace->pass_rec.end(), {li, refined ? 1u : 0u, L.G.n, (u32)mr.moves});
+      g_trace->pass_tau.push_back(tau);
+      std::vector<u32> pb(n), pr(n);
+      for (u32 v = 0; v < n; ++v) {
+        pb[v] = CB[C[v]];
+        pr[v] = L.C[C[v]];
+      }
+      g_trace->bound_proj.push_back(std::move(pb));
+      g_trace->refined_proj.push_back(std::move(pr));
     }
     if (li <= 1 && !refined) break;
     if (li <= 1 && lp > 0) break;
@@ -819,58 +854,49 @@ void oracle_split(uint32_t n, const int64_t* offs, const uint32_t* cols, const u
   std::memcpy(C, L.C.data(), sizeof(uint32_t) * n);
 }
 
-/* One local-moving phase (Alg. 6) of the static algorithm on the input
- * graph, SEQ schedule, recording every move in order: trace[4*k..] =
- * (vertex, from, to, bits of the double gain).  Returns the move count. */
-int64_t oracle_move_trace(uint32_t n, const int64_t* offs, const uint32_t* cols, const uint32_t* w, uint32_t* C,
-                          double tau, uint32_t max_iters, uint64_t* trace, int64_t trace_cap) {
-  Level L;
-  L.G = graph_from(n, offs, cols, w);
-  L.C.assign(C, C + n);
-  L.K = row_sums(L.G);
-  L.S.assign(n, 0);
-  L.size.assign(n, 0);
-  for (u32 i = 0; i < n; ++i) {
-    L.S[L.C[i]] += L.K[i];
-    L.size[L.C[i]]++;
+/* Recording of runs for the tests: oracle_trace_enable(1) starts a fresh
+ * record on the calling thread (0 drops it); the runs that follow append to
+ * it; the readers below copy it out. */
+void oracle_trace_enable(int on) {
+  static thread_local Trace t;
+  t = Trace();
+  g_trace = on ? &t : nullptr;
+}
+
+/* Moves in order: rec[5k..5k+4] = pass, iteration (0-based), vertex of the
+ * pass's level graph, source and target community; dq[k] = its gain.
+ * Returns the move count (copies at most cap). */
+int64_t oracle_trace_moves(uint32_t* rec, double* dq, int64_t cap) {
+  if (!g_trace) return 0;
+  int64_t cnt = (int64_t)g_trace->move_dq.size();
+  for (int64_t k = 0; k < std::min(cnt, cap); ++k) {
+    for (int f = 0; f < 5; ++f) rec[5 * k + f] = g_trace->move_rec[5 * k + f];
+    dq[k] = g_trace->move_dq[k];
   }
-  L.dS.assign(n, 0);
-  i64 M2 = 0;
-  for (i64 x : L.K) M2 += x;
-  if (M2 == 0) return 0;
-  Consts k = make_consts(M2);
-  std::vector<u8> unprocessed(n, 1);
-  Table H(n);
-  int64_t count = 0;
-  for (u32 li = 0; li < max_iters; ++li) {
-    i64 dQ = 0;
-    for (u32 i = 0; i < n; ++i) {
-      if (!unprocessed[i]) continue;
-      unprocessed[i] = 0;
-      scan_communities(H, L.G, L.C, i, false);
-      u32 d = L.C[i];
-      Choice ch = best_community(H, d, L.K[i], L.S, k, [](u32) { return true; });
-      H.clear();
-      if (!ch.found || !(ch.dq > 0.0)) continue;
-      if (count < trace_cap) {
-        u64 bits;
-        std::memcpy(&bits, &ch.dq, 8);
-        trace[4 * count + 0] = i;
-        trace[4 * count + 1] = d;
-        trace[4 * count + 2] = ch.c;
-        trace[4 * count + 3] = bits;
-      }
-      count++;
-      L.S[d] -= L.K[i];
-      L.S[ch.c] += L.K[i];
-      L.C[i] = ch.c;
-      dQ += gain_to_fixed(ch.dq);
-      for (i64 e = L.G.offs[i]; e < L.G.offs[i + 1]; ++e) unprocessed[L.G.cols[e]] = 1;
-    }
-    if (fixed_to_gain(dQ) <= tau) break;
+  return cnt;
+}
+
+/* Passes in order: rec[4p..4p+3] = local-moving iterations, refined (0/1),
+ * vertices of the level graph, local-moving moves; tau[p] = the pass's
+ * tolerance.  Returns the pass count (copies at most cap). */
+uint32_t oracle_trace_passes(uint32_t* rec, double* tau, uint32_t cap) {
+  if (!g_trace) return 0;
+  uint32_t cnt = (uint32_t)g_trace->pass_tau.size();
+  for (uint32_t p = 0; p < std::min(cnt, cap); ++p) {
+    for (int f = 0; f < 4; ++f) rec[4 * p + f] = g_trace->pass_rec[4 * p + f];
+    tau[p] = g_trace->pass_tau[p];
   }
-  std::memcpy(C, L.C.data(), sizeof(uint32_t) * n);
-  return count;
+  return cnt;
+}
+
+/* Communities of the input vertices after pass p: which = 0 by the pass's
+ * local-moving labels (the refinement bounds), 1 by its refined labels.
+ * out: uint32[n] of the input graph.  Returns 0, or -1 for no such pass. */
+int oracle_trace_projection(uint32_t p, int which, uint32_t* out) {
+  if (!g_trace || p >= g_trace->bound_proj.size()) return -1;
+  const std::vector<u32>& v = which ? g_trace->refined_proj[p] : g_trace->bound_proj[p];
+  std::memcpy(out, v.data(), sizeof(uint32_t) * v.size());
+  return 0;
 }
 
 /* Static Leiden: Alg. 4 with C^{t-1} = identity, Sigma = K, every community

@@ -1,9 +1,9 @@
 """The oracle's pins must catch plausible mistakes.
 
 Each case plants one mistake in a copy of the oracle source (a flipped sign, a
-dropped term, a transposed operand, a wrong index or tie-break), builds it on
-the CPU and runs the pin suite against it with ``LEIDEN_ORACLE_LIB``; at least
-one pin has to fail.  The committed oracle is never modified.
+dropped term, a transposed operand, a wrong index or tie-break, a wrong
+stopping rule), builds it on the CPU and runs the pin suites against it with
+``LEIDEN_ORACLE_LIB``; at least one pin has to fail.  The committed oracle is never modified.
 """
 import os
 import subprocess
@@ -42,6 +42,17 @@ MUTANTS = [
      "    if (id[C[i]] == kEmpty) id[C[i]] = next++;\n    out[i] = C[i];"),
     ("row_sums_unweighted", "    for (i64 e = G.offs[i]; e < G.offs[i + 1]; ++e) K[i] += G.w[e];", "    for (i64 e = G.offs[i]; e < G.offs[i + 1]; ++e) K[i] += 1;"),
     ("ds_mark_dropped", "      if (dE[i])\n        for (i64 e = G.offs[i]; e < G.offs[i + 1]; ++e) dV[G.cols[e]] = 1;", ""),
+    # convergence control (Alg. 4, Alg. 6)
+    ("seq_stop_strict", "      if (dynamic) L.dS[d] = 1;\n    }\n    r.iterations = li + 1;\n    if (fixed_to_gain(dQ) <= tau) break;",
+     "      if (dynamic) L.dS[d] = 1;\n    }\n    r.iterations = li + 1;\n    if (fixed_to_gain(dQ) < tau) break;"),
+    ("jacobi_stop_strict", "        }\n      }\n    }\n    r.iterations = li + 1;\n    if (fixed_to_gain(dQ) <= tau) break;",
+     "        }\n      }\n    }\n    r.iterations = li + 1;\n    if (fixed_to_gain(dQ) < tau) break;"),
+    ("iterations_zero_based", "    r.iterations = li + 1;", "    r.iterations = li;"),
+    ("no_tau_decline", "    tau = tau / (double)o.tol_decline;\n", ""),
+    ("final_lookup_unrefined", "  for (u32 v = 0; v < n; ++v) C[v] = L.C[C[v]];\n  return C;",
+     "  for (u32 v = 0; v < n; ++v) C[v] = CB[C[v]];\n  return C;"),
+    ("pass_break_ignores_refined", "    if (li <= 1 && !refined) break;", "    if (li <= 1) break;"),
+    ("pass_break_never_later", "    if (li <= 1 && lp > 0) break;\n", ""),
 ]
 
 
@@ -57,6 +68,7 @@ def test_pins_catch_planted_mistake(tmp_path, name, old, new):
                            str(cpp)])
     env = dict(os.environ, LEIDEN_ORACLE_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_convergence.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, "pins did not catch mutant %s:\n%s" % (name, r.stdout[-2000:])

@@ -300,26 +300,6 @@ def test_planted_partition_quality(orc):
 
 
 # --------------------------------------------------------------------------
-# Sequential local moving never lowers modularity; each move gains exactly dq
-# --------------------------------------------------------------------------
-def test_seq_moves_raise_q_by_their_gain(orc):
-    for seed in (1, 2):
-        g = random_graph(14, 0.3, seed=seed, wmax=4)
-        C0 = np.arange(g.n, dtype=np.uint32)
-        _, moves = orc.move_trace(g, C0)
-        assert moves
-        C = C0.tolist()
-        q = q_exact(g, C)
-        for v, frm, to, dq in moves:
-            assert C[v] == frm and dq > 0
-            C[v] = to
-            q2 = q_exact(g, C)
-            assert abs(float(q2 - q) - dq) <= 1e-14
-            assert q2 > q
-            q = q2
-
-
-# --------------------------------------------------------------------------
 # Split: plain connected-component definition
 # --------------------------------------------------------------------------
 def test_split_matches_component_definition(orc):
@@ -576,10 +556,10 @@ def test_equal_gains_go_to_lowest_label(orc):
     # star with centre 0 and leaves 1, 2 (unit weights): the sequential sweep
     # reaches 0 first; joining {1} or {2} gains the same, so 0 joins community 1.
     g = inputs.csr_from_edges(3, [(0, 1), (0, 2)])
-    _, moves = orc.move_trace(g)
-    assert moves[0][:3] == (0, 0, 1)
+    _, tr = orc.traced(orc.static, g, n_input=g.n, schedule=orc.SEQ)
+    assert tr.moves[0][:5] == (0, 0, 0, 0, 1)
     # dq = (1 - 0)/m - K0 (K0 + S1 - S0)/(2 m^2) with m = 2, K0 = S0 = 2, S1 = 1
-    assert moves[0][3] == 1 / 2 - 2 * (2 + 1 - 2) / (2 * 4)
+    assert tr.moves[0][5] == 1 / 2 - 2 * (2 + 1 - 2) / (2 * 4)
 
 
 def test_subset_renumber_uses_minimum_member(orc):
