@@ -86,6 +86,24 @@ typedef struct {
                              Section 4.3), 0: only the communities marked to be split (default) */
 } leiden_opts;
 
+/* Work counters of a call (leiden_stats.work), in the units of the data the
+ * method has to touch, with the bytes each unit stands for in
+ * leiden_stats.algo_bytes. */
+typedef enum {
+  LEIDEN_W_SCAN0 = 0,       /* local-moving row entries scanned on the input graph: 12 B
+                               (neighbour ID, weight, the neighbour's community) */
+  LEIDEN_W_SCAN_UP = 1,     /* the same on aggregated graphs: 16 B (64-bit weights) */
+  LEIDEN_W_DECIDED = 2,     /* local-moving decisions: 48 B (row offset, C, K, Sigma and size of the
+                               own community, candidate Sigma/size, C write) */
+  LEIDEN_W_REFINE_SCAN = 3, /* refinement row entries scanned: 16 B (+ the neighbour's bound) */
+  LEIDEN_W_MARKS = 4,       /* row entries of moved vertices (neighbours re-marked, Alg. 6): 4 B */
+  LEIDEN_W_SPLIT = 5,       /* row entries of vertices in communities being split (Alg. 7): 8 B */
+  LEIDEN_W_AGG_IN = 6,      /* row entries read by aggregation (Alg. 9): 12 B */
+  LEIDEN_W_AGG_OUT = 7,     /* super-edges written by aggregation: 12 B */
+  LEIDEN_W_MERGE = 8,       /* entries of the rows a batch rewrites: 16 B (read and write, ID and weight) */
+  LEIDEN_WORK_COUNT = 9
+} leiden_work;
+
 /* Per-call statistics. */
 typedef struct {
   uint32_t passes;
@@ -110,6 +128,14 @@ typedef struct {
   double kt_ms;              /* their summed device time */
   uint64_t kt_units;         /* work units they processed (see leiden_kernel) */
   double kt_bytes;           /* algorithmic bytes of those units */
+  uint64_t work[LEIDEN_WORK_COUNT]; /* work counters, indexed by leiden_work */
+  uint64_t sweep_vertices;   /* vertices of the passes over per-vertex arrays (Alg. 4 set-up and
+                                look-ups, Alg. 10, Alg. 8 reset, Alg. 12): 16 B each */
+  uint64_t batch_entries;    /* directed batch entries: 12 B each */
+  /* algorithmic bytes of the call: every work counter, the moves (32 B each:
+   * Sigma and size of two communities), the sweeps and the batch entries
+   * times their bytes */
+  double algo_bytes;
 } leiden_stats;
 
 typedef struct leiden_graph leiden_graph;
@@ -125,12 +151,18 @@ typedef struct leiden_graph leiden_graph;
  * 255, 1023, 4095. */
 typedef struct {
   uint32_t bin_max_degree[5];
-  uint32_t pad_;
+  /* Slots of the LDS table in which the aggregation (Alg. 9) sums a group of
+   * a large community's neighbouring communities: a power of two in
+   * 16..4096, or 0 for 4096.  A group with more distinct neighbours than the
+   * table is split in halves by hash bits until each part fits; smaller
+   * tables only take that path more often and never change the result. */
+  uint32_t agg_emit_slots;
   double probe_ms; /* time of the autotuning probe with these thresholds (0 if never tuned) */
 } leiden_tuning;
 
 leiden_status leiden_get_tuning(leiden_graph* g, leiden_tuning* out);
-/* LEIDEN_EINVAL if the thresholds are not increasing or exceed the limits. */
+/* LEIDEN_EINVAL if the thresholds are not increasing or exceed the limits, or
+ * agg_emit_slots is not 0 or a power of two in 16..4096. */
 leiden_status leiden_set_tuning(leiden_graph* g, const leiden_tuning* t);
 /* Choose the thresholds for this graph by measurement: coordinate descent
  * over each threshold at 1/2, 3/4, 3/2 and 2 times its value, timing one

@@ -29,6 +29,9 @@ EXPORTS = ("leiden_default_opts", "leiden_graph_create", "leiden_graph_destroy",
            "leiden_server_wait", "leiden_server_get_stats")
 
 
+# leiden_work order (work counters of a call)
+WORK_NAMES = ("scan0", "scan_up", "decided", "refine_scan", "marks", "split", "agg_in", "agg_out", "merge")
+
 # leiden_kernel values (timed kernels)
 KERNELS = {"none": 0, "hub_insert": 1, "agg_big": 2}
 
@@ -58,7 +61,9 @@ class LeidenStats(ctypes.Structure):
                 ("pad_", ctypes.c_int32), ("ms_total", ctypes.c_double), ("ms_batch", ctypes.c_double),
                 ("ms_modularity", ctypes.c_double), ("nnz", ctypes.c_uint64),
                 ("kt_launches", ctypes.c_uint32), ("kt_pad_", ctypes.c_uint32), ("kt_ms", ctypes.c_double),
-                ("kt_units", ctypes.c_uint64), ("kt_bytes", ctypes.c_double)]
+                ("kt_units", ctypes.c_uint64), ("kt_bytes", ctypes.c_double),
+                ("work", ctypes.c_uint64 * 9), ("sweep_vertices", ctypes.c_uint64),
+                ("batch_entries", ctypes.c_uint64), ("algo_bytes", ctypes.c_double)]
 
     def as_dict(self):
         p = self.passes
@@ -68,14 +73,18 @@ class LeidenStats(ctypes.Structure):
                 "refined_first_pass": self.refined_first_pass, "ms_total": self.ms_total,
                 "ms_batch": self.ms_batch, "ms_modularity": self.ms_modularity, "nnz": self.nnz,
                 "kt_launches": self.kt_launches, "kt_ms": self.kt_ms, "kt_units": self.kt_units,
-                "kt_bytes": self.kt_bytes}
+                "kt_bytes": self.kt_bytes, "work": dict(zip(WORK_NAMES, self.work)),
+                "sweep_vertices": self.sweep_vertices, "batch_entries": self.batch_entries,
+                "algo_bytes": self.algo_bytes}
 
 
 class LeidenTuning(ctypes.Structure):
-    _fields_ = [("bin_max_degree", ctypes.c_uint32 * 5), ("pad_", ctypes.c_uint32), ("probe_ms", ctypes.c_double)]
+    _fields_ = [("bin_max_degree", ctypes.c_uint32 * 5), ("agg_emit_slots", ctypes.c_uint32),
+                ("probe_ms", ctypes.c_double)]
 
     def as_dict(self):
-        return {"bin_max_degree": list(self.bin_max_degree), "probe_ms": self.probe_ms}
+        return {"bin_max_degree": list(self.bin_max_degree), "agg_emit_slots": self.agg_emit_slots,
+                "probe_ms": self.probe_ms}
 
 
 class LeidenBatchItem(ctypes.Structure):
@@ -326,10 +335,12 @@ class Graph:
         _check(lib().leiden_get_tuning(self._h, ctypes.byref(t)))
         return t.as_dict()
 
-    def set_tuning(self, bin_max_degree):
+    def set_tuning(self, bin_max_degree=None, agg_emit_slots=0):
         t = LeidenTuning()
-        for i, x in enumerate(bin_max_degree):
+        cur = self.tuning()["bin_max_degree"] if bin_max_degree is None else bin_max_degree
+        for i, x in enumerate(cur):
             t.bin_max_degree[i] = int(x)
+        t.agg_emit_slots = int(agg_emit_slots)
         _check(lib().leiden_set_tuning(self._h, ctypes.byref(t)))
 
     def autotune(self, **opts) -> dict:

@@ -654,6 +654,10 @@ __global__ __launch_bounds__(kBlock) void k_ds_del(uint64_t ne, BatchBufs b, con
   }
 }
 
+// Short segments (at most kDsShort entries): one wavefront, one lane per entry;
+// a lane sums the inserted weight of its community over the segment if it is
+// the community's first insertion there.
+constexpr uint32_t kDsShort = 64;
 __global__ __launch_bounds__(kBlock) void k_ds_ins(uint64_t nt, BatchBufs b, const uint32_t* Cprev, const int64_t* K,
                                                    const int64_t* S, double inv_m, double inv_2m2, uint8_t* dV,
                                                    uint8_t* dE, uint8_t* dC) {
@@ -662,26 +666,25 @@ __global__ __launch_bounds__(kBlock) void k_ds_ins(uint64_t nt, BatchBufs b, con
   const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
   for (uint64_t t = wave; t < nt; t += nwaves) {
     const uint64_t s0 = b.seg_off[t], s1 = b.seg_off[t + 1];
+    if (s1 - s0 > kDsShort) continue;  // wavefront-uniform: k_ds_ins_long
     const uint32_t i = b.touched[t];
     const uint32_t d = Cprev[i];
     double bdq = -INFINITY;
     uint32_t bc = kNone;
-    for (uint64_t qb = s0; qb < s1; qb += kWave) {
-      const uint64_t q = qb + lane;
-      if (q < s1 && !b.seg_del[q]) {
-        const uint32_t c = Cprev[b.seg_dst[q]];
-        bool first = c != d;
-        for (uint64_t p = s0; first && p < q; ++p)
-          if (!b.seg_del[p] && Cprev[b.seg_dst[p]] == c) first = false;
-        if (first) {
-          long long h = 0;
-          for (uint64_t p = s0; p < s1; ++p)
-            if (!b.seg_del[p] && Cprev[b.seg_dst[p]] == c) h += b.seg_w[p];
-          const double dq = delta_q(h, 0, K[i], S[c], S[d], inv_m, inv_2m2);
-          if (better(dq, c, bdq, bc)) {
-            bdq = dq;
-            bc = c;
-          }
+    const uint64_t q = s0 + lane;
+    if (q < s1 && !b.seg_del[q]) {
+      const uint32_t c = Cprev[b.seg_dst[q]];
+      bool first = c != d;
+      for (uint64_t p = s0; first && p < q; ++p)
+        if (!b.seg_del[p] && Cprev[b.seg_dst[p]] == c) first = false;
+      if (first) {
+        long long h = 0;
+        for (uint64_t p = s0; p < s1; ++p)
+          if (!b.seg_del[p] && Cprev[b.seg_dst[p]] == c) h += b.seg_w[p];
+        const double dq = delta_q(h, 0, K[i], S[c], S[d], inv_m, inv_2m2);
+        if (better(dq, c, bdq, bc)) {
+          bdq = dq;
+          bc = c;
         }
       }
     }
@@ -691,6 +694,84 @@ __global__ __launch_bounds__(kBlock) void k_ds_ins(uint64_t nt, BatchBufs b, con
       dE[i] = 1;
       dC[bc] = 1;
     }
+  }
+}
+
+// Long segments: one block per segment sums the inserted weight per community
+// in an LDS table, in 2^k partitions of the communities by hash (about
+// kDsPart insertions each); a partition whose distinct communities overflow
+// the table restarts the segment with twice the partitions.  The best
+// community is the same whatever the partitioning (largest gain, then lowest
+// ID), so the result equals the pairwise form's.
+constexpr uint32_t kDsSlots = 2048, kDsPart = 1024;
+__global__ __launch_bounds__(kBlock) void k_ds_ins_long(uint64_t nt, BatchBufs b, const uint32_t* Cprev,
+                                                        const int64_t* K, const int64_t* S, double inv_m,
+                                                        double inv_2m2, uint8_t* dV, uint8_t* dE, uint8_t* dC) {
+  __shared__ uint32_t tk[kDsSlots];
+  __shared__ unsigned long long tv[kDsSlots];
+  __shared__ unsigned long long red[kBlock / kWave];
+  __shared__ double rdq[kBlock / kWave];
+  __shared__ uint32_t rc[kBlock / kWave];
+  __shared__ unsigned int full;
+  for (uint32_t sl = threadIdx.x; sl < kDsSlots; sl += kBlock) {
+    tk[sl] = kNone;
+    tv[sl] = 0;
+  }
+  __syncthreads();
+  for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    const uint64_t s0 = b.seg_off[t], s1 = b.seg_off[t + 1];
+    if (s1 - s0 <= kDsShort) continue;  // block-uniform
+    const uint32_t i = b.touched[t];
+    const uint32_t d = Cprev[i];
+    unsigned long long nins = 0;
+    for (uint64_t q = s0 + threadIdx.x; q < s1; q += kBlock) nins += b.seg_del[q] ? 0u : 1u;
+    nins = block_sum(nins, red);
+    uint32_t P = 1;
+    while ((uint64_t)P * kDsPart < nins) P <<= 1;
+    double bdq = -INFINITY;
+    uint32_t bc = kNone;
+    for (uint32_t part = 0; part < P;) {
+      if (threadIdx.x == 0) full = 0;
+      __syncthreads();
+      for (uint64_t q = s0 + threadIdx.x; q < s1; q += kBlock) {
+        if (b.seg_del[q]) continue;
+        const uint32_t c = Cprev[b.seg_dst[q]];
+        if (c == d || (fmix32(c) & (P - 1)) != part) continue;
+        // salted home slots: the partition already fixes the low bits of fmix32(c)
+        if (!table_add_bounded(tk, tv, kDsSlots - 1, c, (unsigned long long)b.seg_w[q], kRowSalt)) full = 1;
+      }
+      __syncthreads();
+      const bool ok = full == 0;
+      for (uint32_t sl = threadIdx.x; sl < kDsSlots; sl += kBlock) {
+        const uint32_t c = tk[sl];
+        if (c == kNone) continue;
+        if (ok) {
+          const double dq = delta_q((int64_t)tv[sl], 0, K[i], S[c], S[d], inv_m, inv_2m2);
+          if (better(dq, c, bdq, bc)) {
+            bdq = dq;
+            bc = c;
+          }
+        }
+        tk[sl] = kNone;
+        tv[sl] = 0;
+      }
+      __syncthreads();
+      if (ok) {
+        ++part;
+      } else {  // too many communities in one partition: start over, finer
+        P <<= 1;
+        part = 0;
+        bdq = -INFINITY;
+        bc = kNone;
+      }
+    }
+    block_best(bdq, bc, rdq, rc);
+    if (threadIdx.x == 0 && bc != kNone) {
+      dV[i] = 1;
+      dE[i] = 1;
+      dC[bc] = 1;
+    }
+    __syncthreads();
   }
 }
 
@@ -719,6 +800,8 @@ void launch_mark_ds(hipStream_t s, const BatchBufs& b, uint64_t n_entries, uint6
     hipLaunchKernelGGL(k_ds_del, dim3(grid_n(n_entries)), dim3(kBlock), 0, s, n_entries, b, Cprev, dV, dE, dC);
     hipLaunchKernelGGL(k_ds_ins, dim3(grid_n(n_touched, kBlock / kWave)), dim3(kBlock), 0, s, n_touched, b, Cprev, K,
                        S, inv_m, inv_2m2, dV, dE, dC);
+    hipLaunchKernelGGL(k_ds_ins_long, dim3(grid_n(n_touched, 1, 2048)), dim3(kBlock), 0, s, n_touched, b, Cprev, K, S,
+                       inv_m, inv_2m2, dV, dE, dC);
     hipLaunchKernelGGL(k_ds_neighbours, dim3(grid_n(n_touched, kBlock / kWave)), dim3(kBlock), 0, s, n_touched, b, g,
                        dE, dV);
   }

@@ -75,6 +75,7 @@ struct Ctl {
   unsigned int sort_count[2];        // batch segments left to the block sorts (LDS, merge)
   unsigned int misc[8];
   unsigned long long kt_units[4];    // work units of the timed kernels (indexed by leiden_kernel)
+  unsigned long long units[16];      // work counters of the call (WorkUnit), folded at its end
 };
 
 // ---------------------------------------------------------------------------

@@ -48,15 +48,32 @@ struct DecideParams {
   unsigned long long* hub_items;  // (hub vertex, chunk) work items of the current sub-round
 };
 
-// Edge-scan counters of the decide kernels: each block adds to counter
-// blockIdx.x % kEdgeParts, each on its own 256-byte line, folded into
-// Ctl::edges at the end of a call.  Thousands of blocks that finish
-// together and all add to one address queue on it (atomics on one address
-// are serialised device-wide): one shared counter cost the small-degree
-// decide kernel about 90 of its 127 µs.
+// Work counters of a call (the units of the method's data access), spread
+// over kEdgeParts copies: each block adds to copy blockIdx.x % kEdgeParts,
+// each copy on its own 256-byte line, folded into Ctl::units at the end of a
+// call.  Thousands of blocks that finish together and all add to one address
+// queue on it (atomics on one address are serialised device-wide): one
+// shared counter cost the small-degree decide kernel about 90 of its 127 µs.
 constexpr uint32_t kEdgeParts = 64, kEdgeStride = 32;
+enum WorkUnit : uint32_t {
+  kWScan0 = 0,      // local-moving row entries scanned on the input graph
+  kWScanUp = 1,     // local-moving row entries scanned on aggregated graphs
+  kWDecided = 2,    // local-moving decisions (vertices evaluated)
+  kWRefScan = 3,    // refinement row entries scanned
+  kWMarks = 4,      // row entries of movers (neighbours re-marked)
+  kWSplit = 5,      // row entries of vertices in split communities
+  kWAggIn = 6,      // row entries read by aggregation
+  kWAggOut = 7,     // super-edges written by aggregation
+  kWMerge = 8,      // entries of rows rewritten by a batch merge (new lengths)
+  kWUnits = 9
+};
+__device__ inline void add_units(unsigned long long* parts, uint32_t unit, unsigned long long e) {
+  if (e && parts) atomicAdd(&parts[(blockIdx.x % kEdgeParts) * kEdgeStride + unit], e);
+}
+// local-moving scans of a level with weight type W
+template <typename W>
 __device__ inline void add_edges(unsigned long long* parts, unsigned long long e) {
-  if (e && parts) atomicAdd(&parts[(blockIdx.x % kEdgeParts) * kEdgeStride], e);
+  add_units(parts, sizeof(W) == 4 ? kWScan0 : kWScanUp, e);
 }
 
 // Hub layout of one level: a hub (degree above the last LDS bin) of degree
@@ -104,6 +121,7 @@ struct ApplyParams {
   uint32_t* next_list;
   unsigned long long* mark_items;  // (mover, chunk) marking work items of the sub-round
   int applied;         // 1: the decide kernels already moved the vertices (asynchronous mode)
+  unsigned long long* parts;  // work counters (WorkUnit) or null
 };
 
 // move.hip
@@ -139,6 +157,9 @@ void launch_cls_reset(hipStream_t s, Ctl* ctl);
 
 // prims.hip
 void fill_u32(hipStream_t s, uint32_t* p, uint32_t v, size_t n);
+// work counter `unit` (WorkUnit) += sum of len[i] (idx null) or len[idx[i]], i < n
+void count_units(hipStream_t s, const uint32_t* len, const uint32_t* idx, uint64_t n, unsigned long long* parts,
+                 uint32_t unit);
 void fill_u8(hipStream_t s, uint8_t* p, uint8_t v, size_t n);
 void fill_i64(hipStream_t s, int64_t* p, int64_t v, size_t n);
 void iota_u32(hipStream_t s, uint32_t* p, size_t n);
@@ -186,9 +207,9 @@ struct RenumberBufs {
 void subset_renumber(hipStream_t s, uint32_t n, uint32_t* C, int64_t*& S, uint32_t*& size, uint8_t*& dS,
                      uint8_t*& dR, RenumberBufs& b, Ctl* ctl);
 
-template <typename W>
 void launch_split_init(hipStream_t s, uint32_t n, const uint32_t* C, const uint8_t* dS, const uint8_t* dR,
-                       uint32_t* lab, uint32_t* list, unsigned long long* main_key, Ctl* ctl);
+                       uint32_t* lab, uint32_t* list, unsigned long long* main_key, Ctl* ctl, const uint32_t* len,
+                       unsigned long long* parts);
 template <typename W>
 void launch_split_sample(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* lab, const uint32_t* list,
                          unsigned long long* main_key, uint32_t* rest, Ctl* ctl, uint32_t n_upper);
@@ -226,6 +247,7 @@ struct AggBufs {
   unsigned long long* svals;
   uint16_t* smat;                // bucket-start matrices (mcap entries)
   size_t scap, mcap;
+  uint32_t emit_cap;             // slots of the emit kernel's LDS table (power of two, 16..4096)
 };
 template <typename W>
 int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t nc, AggBufs& b, int64_t* out_start,

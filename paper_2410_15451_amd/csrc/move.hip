@@ -194,12 +194,26 @@ __device__ inline void emit_decision(const DecideParams<W>& p, uint32_t v, uint3
   p.movers[pos] = Mover{v, bc, bdq};
 }
 
+// Work units of a decide kernel: local-moving scans and decisions, or
+// refinement scans.
+template <typename W, bool REFINE>
+__device__ inline void add_decide_units(unsigned long long* parts, unsigned long long edges,
+                                        unsigned long long verts) {
+  if (REFINE) {
+    add_units(parts, kWRefScan, edges);
+  } else {
+    add_edges<W>(parts, edges);
+    add_units(parts, kWDecided, verts);
+  }
+}
+
 // G lanes per vertex (G <= 64, groups inside one wavefront), T slots each;
 // this block is block `blk` of `nblk` working on the list.
 template <int G, int T, typename W, bool REFINE>
 __device__ inline unsigned long long decide_group_body(const DecideParams<W>& p, const uint32_t* list, uint32_t cnt,
                                                        uint32_t blk, uint32_t nblk, uint32_t* keys,
-                                                       unsigned long long* vals, MoverStage& st) {
+                                                       unsigned long long* vals, MoverStage& st,
+                                                       unsigned long long& verts) {
   constexpr int GPB = kBlock / G;
   static_assert(GPB <= kMoverStage, "one round of decisions must fit the stage");
   const int g = threadIdx.x / G, lane = threadIdx.x % G;
@@ -225,7 +239,10 @@ __device__ inline unsigned long long decide_group_body(const DecideParams<W>& p,
       const int64_t s0 = p.g.start[v];
       const uint32_t L = p.g.len[v];
       const uint32_t bnd = REFINE ? p.CB[v] : 0;
-      if (!REFINE && lane == 0) edges += L;
+      if (lane == 0) {
+        edges += L;
+        verts += 1;
+      }
       table_accumulate(tk, tv, T - 1, lane, L, G, [&](uint32_t e, uint32_t& key, unsigned long long& w) {
         const uint32_t j = p.g.cols[s0 + e];
         if (j == v || (REFINE && p.CB[j] != bnd)) return;
@@ -279,16 +296,17 @@ __global__ __launch_bounds__(kBlock) void k_decide_small(DecideParams<W> p, Smal
   __shared__ MoverStage st;
   if (threadIdx.x == 0) st.n = 0;
   __syncthreads();
-  unsigned long long edges = 0;
+  unsigned long long edges = 0, verts = 0;
   const uint32_t b = blockIdx.x;
   if (b < sb.n0)
-    edges = decide_group_body<8, 16, W, REFINE>(p, sb.list[0], *sb.count[0], b, sb.n0, keys, vals, st);
+    edges = decide_group_body<8, 16, W, REFINE>(p, sb.list[0], *sb.count[0], b, sb.n0, keys, vals, st, verts);
   else if (b < sb.n0 + sb.n1)
-    edges = decide_group_body<32, 64, W, REFINE>(p, sb.list[1], *sb.count[1], b - sb.n0, sb.n1, keys, vals, st);
+    edges =
+        decide_group_body<32, 64, W, REFINE>(p, sb.list[1], *sb.count[1], b - sb.n0, sb.n1, keys, vals, st, verts);
   else
     edges = decide_group_body<64, 256, W, REFINE>(p, sb.list[2], *sb.count[2], b - sb.n0 - sb.n1, sb.n2, keys,
-                                                  vals, st);
-  add_edges(p.edge_parts, edges);
+                                                  vals, st, verts);
+  add_decide_units<W, REFINE>(p.edge_parts, edges, verts);
 }
 
 // One block (kBlock lanes) per vertex, T-slot table in LDS.
@@ -302,7 +320,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(DecideParams<W> p) {
   __shared__ MoverStage st;
   constexpr uint32_t mask = T - 1;
   const uint32_t cnt = *p.count;
-  unsigned long long edges = 0;
+  unsigned long long edges = 0, verts = 0;
   if (threadIdx.x == 0) st.n = 0;
   __syncthreads();
   for (uint32_t item = blockIdx.x; item < cnt; item += gridDim.x) {
@@ -319,7 +337,10 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(DecideParams<W> p) {
       const int64_t s0 = p.g.start[v];
       const uint32_t L = p.g.len[v];
       const uint32_t bnd = REFINE ? p.CB[v] : 0;
-      if (!REFINE && threadIdx.x == 0) edges += L;
+      if (threadIdx.x == 0) {
+        edges += L;
+        verts += 1;
+      }
       table_accumulate(tk, tv, mask, threadIdx.x, L, kBlock, [&](uint32_t e, uint32_t& key, unsigned long long& w) {
         const uint32_t j = p.g.cols[s0 + e];
         if (j == v || (REFINE && p.CB[j] != bnd)) return;
@@ -354,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(DecideParams<W> p) {
   }
   __syncthreads();
   stage_flush(st, p.ctl, p.movers);
-  add_edges(p.edge_parts, edges);
+  add_decide_units<W, REFINE>(p.edge_parts, edges, verts);
 }
 
 // ---------------------------------------------------------------------------
@@ -390,7 +411,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_chunk(DecideParams<W> p) {
   for (uint32_t b = threadIdx.x; b <= kNB; b += kBlock) lcnt[b] = 0;
   __syncthreads();
   const uint32_t items = p.ctl->hub_items;
-  unsigned long long edges = 0;
+  unsigned long long edges = 0, verts = 0;
   for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
     const unsigned long long item = p.hub_items[it];
     const uint32_t v = (uint32_t)(item >> 32), k = (uint32_t)item;
@@ -416,8 +437,11 @@ __global__ __launch_bounds__(kBlock) void k_hub_chunk(DecideParams<W> p) {
     kid = block_sum(kid, red);
     if (threadIdx.x == 0) {
       if (kid) atomicAdd(&p.hub_kid[hi], kid);
-      if (k == 0) p.hub_live[hi] = 1;
-      if (!REFINE) edges += ce - cb;
+      if (k == 0) {
+        p.hub_live[hi] = 1;
+        verts += 1;
+      }
+      edges += ce - cb;
     }
     __syncthreads();
     const uint32_t rb = p.hub_rbits[hi], R = 1u << rb;
@@ -449,7 +473,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_chunk(DecideParams<W> p) {
     for (uint32_t b = threadIdx.x; b <= R; b += kBlock) lcnt[b] = 0;
   }
   if (edges) {
-    add_edges(p.edge_parts, edges);
+    add_decide_units<W, REFINE>(p.edge_parts, edges, verts);
     if (sizeof(W) == 4 && !REFINE) atomicAdd(&p.ctl->kt_units[LEIDEN_KT_HUB_INSERT], edges);
   }
 }
@@ -741,6 +765,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_moves(ApplyParams p) {
   const uint32_t lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
   const uint32_t cnt = p.ctl->mover_count;
   long long dqsum = 0;
+  unsigned long long marks = 0;
   const uint32_t stride = gridDim.x * kBlock;
   // block-uniform loop: every thread runs every iteration
   for (uint32_t base = blockIdx.x * kBlock; base < cnt; base += stride) {
@@ -759,6 +784,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_moves(ApplyParams p) {
         if (p.dS) p.dS[d] = 1;
       }
       nch = (p.len[v] + kMarkChunk - 1) / kMarkChunk;
+      marks += p.len[v];
     }
     // wavefront prefix of the chunk counts, then one reservation per block
     uint32_t incl = nch;
@@ -794,6 +820,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_moves(ApplyParams p) {
   }
   dqsum = (long long)block_sum((unsigned long long)dqsum, red);
   if (threadIdx.x == 0 && dqsum != 0) atomicAdd(&p.ctl->dq_fixed, (unsigned long long)dqsum);
+  marks = block_sum(marks, red);
+  if (threadIdx.x == 0) add_units(p.parts, kWMarks, marks);
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&p.ctl->total_moves, (unsigned long long)cnt);
 }
 

@@ -176,10 +176,13 @@ constexpr uint32_t kSplitSample = 4;
 
 __global__ __launch_bounds__(kBlock) void k_split_init(uint32_t n, const uint32_t* C, const uint8_t* dS,
                                                        const uint8_t* dR, uint32_t* lab, uint32_t* list,
-                                                       unsigned long long* main_key, Ctl* ctl) {
+                                                       unsigned long long* main_key, Ctl* ctl, const uint32_t* len,
+                                                       unsigned long long* parts) {
   __shared__ unsigned int scnt[1], sbase[1];
+  __shared__ unsigned long long red[kBlock / kWave];
   if (threadIdx.x == 0) scnt[0] = 0;
   __syncthreads();
+  unsigned long long entries = 0;
   constexpr uint32_t tile = kBlock * kTileU;
   for (uint64_t base = (uint64_t)blockIdx.x * tile; base < n; base += (uint64_t)gridDim.x * tile) {
     uint32_t key[kTileU], val[kTileU];
@@ -194,7 +197,10 @@ __global__ __launch_bounds__(kBlock) void k_split_init(uint32_t n, const uint32_
         const bool in = dS[c] && !dR[c];
         // the label of a community is its minimum member: one writer per community
         if (in && c == (uint32_t)i) main_key[c] = 0;
-        if (in) key[u] = 0;
+        if (in) {
+          key[u] = 0;
+          entries += len[i];
+        }
       }
     }
     tile_append<kTileU>(key, val, 1, scnt, sbase, [&](uint32_t, uint32_t*& l, unsigned int*& cn) {
@@ -202,6 +208,8 @@ __global__ __launch_bounds__(kBlock) void k_split_init(uint32_t n, const uint32_
       cn = &ctl->split_count;
     });
   }
+  entries = block_sum(entries, red);
+  if (threadIdx.x == 0) add_units(parts, kWSplit, entries);
 }
 
 __device__ inline uint32_t uf_find(uint32_t* p, uint32_t x) {
@@ -344,13 +352,13 @@ __global__ void k_split_reset(Ctl* ctl) {
   }
 }
 
-template <typename W>
 void launch_split_init(hipStream_t s, uint32_t n, const uint32_t* C, const uint8_t* dS, const uint8_t* dR,
-                       uint32_t* lab, uint32_t* list, unsigned long long* main_key, Ctl* ctl) {
+                       uint32_t* lab, uint32_t* list, unsigned long long* main_key, Ctl* ctl, const uint32_t* len,
+                       unsigned long long* parts) {
   hipLaunchKernelGGL(k_split_reset, dim3(1), dim3(1), 0, s, ctl);
   if (n)
     hipLaunchKernelGGL(k_split_init, dim3(grid_n(n, kBlock * kTileU)), dim3(kBlock), 0, s, n, C, dS, dR, lab, list,
-                       main_key, ctl);
+                       main_key, ctl, len, parts);
 }
 
 template <typename W>
@@ -396,10 +404,6 @@ void launch_split_finish(hipStream_t s, uint32_t* C, uint32_t* lab, const uint32
   hipLaunchKernelGGL(k_split_finish, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, C, lab, list, ctl);
 }
 
-template void launch_split_init<uint32_t>(hipStream_t, uint32_t, const uint32_t*, const uint8_t*, const uint8_t*,
-                                          uint32_t*, uint32_t*, unsigned long long*, Ctl*);
-template void launch_split_init<int64_t>(hipStream_t, uint32_t, const uint32_t*, const uint8_t*, const uint8_t*,
-                                         uint32_t*, uint32_t*, unsigned long long*, Ctl*);
 template void launch_split_sample<uint32_t>(hipStream_t, Rows<uint32_t>, const uint32_t*, uint32_t*,
                                             const uint32_t*, unsigned long long*, uint32_t*, Ctl*, uint32_t);
 template void launch_split_sample<int64_t>(hipStream_t, Rows<int64_t>, const uint32_t*, uint32_t*, const uint32_t*,
@@ -857,18 +861,19 @@ __global__ __launch_bounds__(kBlock) void k_agg_stage(Rows<W> g, const uint32_t*
 // community's buckets are taken in G = 2^gb groups of
 // consecutive buckets, G the smallest power of two with about 2^kBigBucketBits
 // staged entries per group.  A group's runs (one per stage column) are summed
-// in an LDS table sized for the group; should the group hold more distinct
-// keys than the table, it is taken in 2^q sub-groups by the next q bits of the
-// same mixing (a bijection, so distinct keys eventually part).  Each group
-// reserves its part of the super row with one atomic; block y = 0 also adds
-// the community's own key.
+// in an LDS table of at most `cap` slots sized for the group; a sub-group
+// holding more distinct keys than the table is split in two by the next bit of
+// the same mixing (a bijection, so distinct keys eventually part), depth
+// first, and only sub-groups that fit are written out, each exactly once.
+// Each written sub-group reserves its part of the super row with one atomic;
+// block y = 0 also adds the community's own key.
 __global__ __launch_bounds__(kBlock) void k_agg_emit(const BigComm* bc, const AggItem* items, uint32_t nitems,
                                                      const uint32_t* skeys,
                                                      const unsigned long long* svals, const uint16_t* smat,
                                                      const unsigned int* stage_cnt,
                                                      const unsigned long long* self_acc, const uint64_t* cap_off,
                                                      uint32_t* out_len, uint32_t* out_cols, int64_t* out_w,
-                                                     int64_t* Kout) {
+                                                     int64_t* Kout, uint32_t cap) {
   __shared__ uint32_t tk[kBigSlots];
   __shared__ unsigned long long tv[kBigSlots];
   __shared__ unsigned int rpre[kEmitWin];
@@ -912,70 +917,81 @@ __global__ __launch_bounds__(kBlock) void k_agg_emit(const BigComm* bc, const Ag
     }
     for (uint32_t grp = y; grp < G; grp += nseg) {
       const uint32_t b0 = grp << span, b1 = (grp + 1) << span;
-      for (uint32_t q = 0;; ++q) {  // sub-group bits
-        bool fits = true;
-        for (uint32_t sub = 0; sub < (1u << q) && fits; ++sub) {
-          uint32_t mask = kBigSlots - 1;
-          if (threadIdx.x == 0) {
-            full = 0;
-            nout = 0;
-          }
-          for (uint32_t c0 = 0; c0 < nst; c0 += kEmitWin) {
-            const uint32_t cw = min(kEmitWin, nst - c0);
-            for (uint32_t i = threadIdx.x; i < cw; i += kBlock) {
-              const uint32_t s0 = mat[(size_t)b0 * b.smax + c0 + i], s1 = mat[(size_t)b1 * b.smax + c0 + i];
-              rst[i] = (uint16_t)s0;
-              rpre[i] = s1 - s0;
-            }
-            __syncthreads();
-            const uint32_t n = block_exclusive_scan<kEmitWin / kBlock>(rpre, cw, wsum);
-            if (nst <= kEmitWin) mask = min(kBigSlots, pow2_at_least(2 * n)) - 1;
-            for (uint32_t xx = threadIdx.x; xx < n; xx += kBlock) {
-              uint32_t lo = 0, hi = cw - 1;
-              while (lo < hi) {
-                const uint32_t mid = (lo + hi + 1) >> 1;
-                if (rpre[mid] <= xx)
-                  lo = mid;
-                else
-                  hi = mid - 1;
-              }
-              const size_t pos = b.soff + (size_t)(c0 + lo) * kBigStage + rst[lo] + (xx - rpre[lo]);
-              const uint32_t c = skeys[pos];
-              if (q && ((big_mix(c) << gb) >> (32 - q)) != sub) continue;
-              if (!table_add_bounded(tk, tv, mask, c, svals[pos], kRowSalt)) full = 1;
-            }
-            __syncthreads();
-          }
-          fits = full == 0;
-          unsigned long long ksum = 0;
-          if (fits) {
-            for (uint32_t sl = threadIdx.x; sl <= mask; sl += kBlock)
-              if (tk[sl] != kNone) {
-                atomicAdd(&nout, 1u);
-                ksum += tv[sl];
-              }
-          }
-          ksum = block_sum(ksum, red);
-          if (fits && threadIdx.x == 0 && nout) {
-            obase = atomicAdd(&out_len[b.c], nout);
-            atomicAdd((unsigned long long*)&Kout[b.c], ksum);
-            nout = 0;
+      // sub-group (q, sub): keys whose q mixing bits after the group's bits
+      // equal sub; walked depth first over the leaves that fit
+      uint32_t q = 0, sub = 0;
+      for (;;) {
+        uint32_t mask = cap - 1;
+        if (threadIdx.x == 0) {
+          full = 0;
+          nout = 0;
+        }
+        for (uint32_t c0 = 0; c0 < nst; c0 += kEmitWin) {
+          const uint32_t cw = min(kEmitWin, nst - c0);
+          for (uint32_t i = threadIdx.x; i < cw; i += kBlock) {
+            const uint32_t s0 = mat[(size_t)b0 * b.smax + c0 + i], s1 = mat[(size_t)b1 * b.smax + c0 + i];
+            rst[i] = (uint16_t)s0;
+            rpre[i] = s1 - s0;
           }
           __syncthreads();
-          for (uint32_t sl = threadIdx.x; sl <= mask; sl += kBlock) {
-            const uint32_t c = tk[sl];
-            if (c == kNone) continue;
-            if (fits) {
-              const unsigned int p = obase + atomicAdd(&nout, 1u);
-              out_cols[o + p] = c;
-              out_w[o + p] = (int64_t)tv[sl];
+          const uint32_t n = block_exclusive_scan<kEmitWin / kBlock>(rpre, cw, wsum);
+          if (nst <= kEmitWin) mask = min(cap, pow2_at_least(2 * n)) - 1;
+          for (uint32_t xx = threadIdx.x; xx < n; xx += kBlock) {
+            uint32_t lo = 0, hi = cw - 1;
+            while (lo < hi) {
+              const uint32_t mid = (lo + hi + 1) >> 1;
+              if (rpre[mid] <= xx)
+                lo = mid;
+              else
+                hi = mid - 1;
             }
-            tk[sl] = kNone;
-            tv[sl] = 0;
+            const size_t pos = b.soff + (size_t)(c0 + lo) * kBigStage + rst[lo] + (xx - rpre[lo]);
+            const uint32_t c = skeys[pos];
+            if (q && ((big_mix(c) << gb) >> (32 - q)) != sub) continue;
+            if (!table_add_bounded(tk, tv, mask, c, svals[pos], kRowSalt)) full = 1;
           }
           __syncthreads();
         }
-        if (fits) break;
+        const bool fits = full == 0;
+        unsigned long long ksum = 0;
+        if (fits) {
+          for (uint32_t sl = threadIdx.x; sl <= mask; sl += kBlock)
+            if (tk[sl] != kNone) {
+              atomicAdd(&nout, 1u);
+              ksum += tv[sl];
+            }
+        }
+        ksum = block_sum(ksum, red);
+        if (fits && threadIdx.x == 0 && nout) {
+          obase = atomicAdd(&out_len[b.c], nout);
+          atomicAdd((unsigned long long*)&Kout[b.c], ksum);
+          nout = 0;
+        }
+        __syncthreads();
+        for (uint32_t sl = threadIdx.x; sl <= mask; sl += kBlock) {
+          const uint32_t c = tk[sl];
+          if (c == kNone) continue;
+          if (fits) {
+            const unsigned int p = obase + atomicAdd(&nout, 1u);
+            out_cols[o + p] = c;
+            out_w[o + p] = (int64_t)tv[sl];
+          }
+          tk[sl] = kNone;
+          tv[sl] = 0;
+        }
+        __syncthreads();
+        if (!fits) {  // split: its first half next
+          ++q;
+          sub <<= 1;
+          continue;
+        }
+        // written: the next leaf is the sibling of the nearest first half above
+        while (q > 0 && (sub & 1u)) {
+          sub >>= 1;
+          --q;
+        }
+        if (q == 0) break;
+        ++sub;
       }
     }
   }
@@ -1083,9 +1099,10 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
                        b.self_acc, timed ? &ctl->kt_units[LEIDEN_KT_AGG_BIG] : nullptr);
     if (timed) kt_mark(LEIDEN_KT_AGG_BIG, s);
     const size_t nemit = ins.size() - nins;
+    const uint32_t ecap = (b.emit_cap >= 16 && b.emit_cap <= kBigSlots) ? b.emit_cap : kBigSlots;
     hipLaunchKernelGGL(k_agg_emit, dim3(std::min<size_t>(nemit, 8192)), dim3(kBlock), 0, s, (const BigComm*)b.bigc,
                        di + nins, (uint32_t)nemit, b.skeys, b.svals, b.smat, b.stage_cnt, b.self_acc,
-                       (const uint64_t*)out_start, out_len, out_cols, out_w, Kout);
+                       (const uint64_t*)out_start, out_len, out_cols, out_w, Kout, ecap);
     if (hipStreamSynchronize(s) != hipSuccess) return -1;  // host vectors must outlive the copies
     first = last;
   }

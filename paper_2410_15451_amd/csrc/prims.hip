@@ -21,6 +21,23 @@ static int fill_grid(size_t n) {
   return (int)b;
 }
 
+// Work counter `unit` += the sum of len[i] (or len[idx[i]]) over i < n.
+__global__ __launch_bounds__(kBlock) void k_count_units(const uint32_t* len, const uint32_t* idx, uint64_t n,
+                                                        unsigned long long* parts, uint32_t unit) {
+  __shared__ unsigned long long red[kBlock / kWave];
+  unsigned long long e = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kBlock)
+    e += len[idx ? idx[i] : i];
+  e = block_sum(e, red);
+  if (threadIdx.x == 0) add_units(parts, unit, e);
+}
+
+void count_units(hipStream_t s, const uint32_t* len, const uint32_t* idx, uint64_t n, unsigned long long* parts,
+                 uint32_t unit) {
+  if (n && parts) hipLaunchKernelGGL(k_count_units, dim3(std::min<size_t>(fill_grid(n), 1024)), dim3(kBlock), 0, s,
+                                     len, idx, n, parts, unit);
+}
+
 void fill_u32(hipStream_t s, uint32_t* p, uint32_t v, size_t n) {
   if (n) hipLaunchKernelGGL(k_fill<uint32_t>, dim3(fill_grid(n)), dim3(kBlock), 0, s, p, v, n);
 }

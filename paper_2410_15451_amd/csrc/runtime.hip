@@ -111,6 +111,8 @@ struct leiden_graph {
   uint32_t stamp = 0;  // iteration stamp, never reused
   BinCfg bincfg = kDefaultBins;  // degree-bin thresholds (tunable)
   float tune_ms = 0;             // probe time of the last autotuning
+  uint32_t emit_slots = 4096;    // LDS table of the aggregation emit step (power of two, 16..4096)
+  uint64_t sweeps = 0;           // vertices of the per-vertex passes of the current call
   // level-0 degree bins
   uint64_t bins0[kBins] = {0};
   uint32_t maxdeg0 = 0;
@@ -194,6 +196,21 @@ void kt_collect(leiden_graph* G, int which, leiden_stats* st) {
   st->kt_ms = ms;
   st->kt_units = G->hctl->kt_units[which];
   st->kt_bytes = (double)st->kt_units * kt_unit_bytes(which);
+}
+
+// Work counters, sweeps and algorithmic bytes of the call into *st (after
+// read_ctl_final).  Bytes per unit as leiden.h states them.
+void fill_work(leiden_graph* G, leiden_stats* st, uint64_t batch_entries) {
+  static const double kUnitBytes[LEIDEN_WORK_COUNT] = {12, 16, 48, 16, 4, 8, 12, 12, 16};
+  double bytes = 0;
+  for (int u = 0; u < LEIDEN_WORK_COUNT; ++u) {
+    st->work[u] = G->hctl->units[u];
+    bytes += kUnitBytes[u] * (double)st->work[u];
+  }
+  st->sweep_vertices = G->sweeps;
+  st->batch_entries = batch_entries;
+  bytes += 32.0 * (double)G->hctl->total_moves + 16.0 * (double)G->sweeps + 12.0 * (double)batch_entries;
+  st->algo_bytes = bytes;
 }
 
 hipStream_t stream_of(leiden_graph* g, const leiden_opts* o) {
@@ -400,15 +417,21 @@ void zero_ctl(leiden_graph* G, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(256), 0, s, dctl(G), G->edge_parts.as<unsigned long long>());
 }
 
-// Ctl::edges += the decide kernels' edge-scan counters, which are cleared.
+// Ctl::units += the spread work counters, which are cleared; Ctl::edges +=
+// the local-moving scans.
 __global__ void k_fold_edges(Ctl* c, unsigned long long* parts) {
-  unsigned long long e = 0;
-  if (threadIdx.x < kEdgeParts) {
-    e = parts[threadIdx.x * kEdgeStride];
-    parts[threadIdx.x * kEdgeStride] = 0;
+  for (uint32_t u = 0; u < kWUnits; ++u) {
+    unsigned long long e = 0;
+    if (threadIdx.x < kEdgeParts) {
+      e = parts[threadIdx.x * kEdgeStride + u];
+      parts[threadIdx.x * kEdgeStride + u] = 0;
+    }
+    e = group_sum<kWave>(e);
+    if (threadIdx.x == 0) {
+      c->units[u] += e;
+      if (u == kWScan0 || u == kWScanUp) c->edges += e;
+    }
   }
-  e = group_sum<kWave>(e);
-  if (threadIdx.x == 0) c->edges += e;
 }
 
 // read_ctl with the edge-scan counters folded in first (end of a call)
@@ -519,6 +542,7 @@ leiden_status local_move(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
       ap.next_list = next_list;
       ap.mark_items = G->mark_items.as<unsigned long long>();
       ap.applied = async ? 1 : 0;
+      ap.parts = G->edge_parts.as<unsigned long long>();
       launch_apply_moves(s, ap, nl, G->mark_items.bytes / 8);
     }
     CHK(read_ctl(G, s));
@@ -577,7 +601,7 @@ leiden_status split(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, Leve
   uint32_t* list = G->split_list.as<uint32_t>();
   uint32_t* rest = G->split_rest.as<uint32_t>();
   unsigned long long* key = G->split_key.as<unsigned long long>();
-  launch_split_init<W>(s, nl, L.C, L.dS, L.dR, lab, list, key, ctl);
+  launch_split_init(s, nl, L.C, L.dS, L.dR, lab, list, key, ctl, g.len, G->edge_parts.as<unsigned long long>());
   launch_split_sample<W>(s, g, L.C, lab, list, key, rest, ctl, nl);
   // vertices outside their community's main tree, by degree
   launch_subround_reset(s, ctl);
@@ -600,6 +624,7 @@ leiden_status run_pass(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, L
   // split-all ablation: every community not marked for refinement is split
   if (ro.o.split_all) fill_u8(s, L.dS, 1, nl);
   subset_renumber(s, nl, L.C, L.S, L.size, L.dS, L.dR, L.rb, dctl(G));
+  G->sweeps += 2 * (uint64_t)nl;  // Alg. 10 and the refinement reset of Alg. 8
   CHK(read_ctl(G, s));
   const uint32_t nsplit = G->hctl->misc[0], nref = G->hctl->misc[1];
   if (nsplit > 0) CHK(split<W>(G, s, g, nl, L, bins));
@@ -645,11 +670,16 @@ leiden_status next_level(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
   ab.smat = G->agg_mat.as<uint16_t>();
   ab.scap = G->agg_keys.bytes / 4;
   ab.mcap = G->agg_mat.bytes / 2;
+  ab.emit_cap = G->emit_slots;
   // K of the next level goes to whichever of the two K buffers is not current
   int64_t* Kn = L.K == G->K.as<int64_t>() ? G->Kb.as<int64_t>() : G->K.as<int64_t>();
+  count_units(s, g.len, nullptr, nl, G->edge_parts.as<unsigned long long>(), kWAggIn);
   int rc = aggregate<W>(s, g, nl, L.C, (uint32_t)nc, ab, bs.as<int64_t>(), bl.as<uint32_t>(), bc.as<uint32_t>(),
                         bw.as<int64_t>(), Kn, dctl(G));
   if (rc != 0) return fail(LEIDEN_EDEVICE, "aggregation failed (%d)", rc);
+  count_units(s, bl.as<uint32_t>(), nullptr, nc, G->edge_parts.as<unsigned long long>(), kWAggOut);
+  // dense renumbering, C <- C'[C] over the input vertices, next-level set-up
+  G->sweeps += 2 * (uint64_t)nl + G->n + nc;
   // K' = Sigma' = weight of each super-vertex; C' = identity; all refined; none split
   HIPCHK(hipMemcpyAsync(L.S, Kn, sizeof(int64_t) * nc, hipMemcpyDeviceToDevice, s));
   L.K = Kn;
@@ -704,6 +734,7 @@ leiden_status run_leiden(leiden_graph* G, hipStream_t s, LevelState& L, const Ru
   }
   if (st) st->passes = pass < ro.o.max_passes ? pass + 1 : ro.o.max_passes;
   launch_lookup(s, G->Ctop.as<uint32_t>(), L.C, n);
+  G->sweeps += n;
   return LEIDEN_OK;
 }
 
@@ -927,6 +958,7 @@ leiden_status leiden_get_tuning(leiden_graph* G, leiden_tuning* out) {
   if (!G || !out) return fail(LEIDEN_EINVAL, "null argument");
   std::memset(out, 0, sizeof(*out));
   for (int b = 0; b < kBins - 1; ++b) out->bin_max_degree[b] = G->bincfg.max_deg[b];
+  out->agg_emit_slots = G->emit_slots;
   out->probe_ms = G->tune_ms;
   return LEIDEN_OK;
 }
@@ -939,6 +971,10 @@ leiden_status leiden_set_tuning(leiden_graph* G, const leiden_tuning* t) {
   if (!bins_valid(c))
     return fail(LEIDEN_EINVAL, "bin thresholds must increase and stay within %u, %u, %u, %u, %u", kBinCap[0],
                 kBinCap[1], kBinCap[2], kBinCap[3], kBinCap[4]);
+  const uint32_t es = t->agg_emit_slots ? t->agg_emit_slots : 4096;
+  if (es < 16 || es > 4096 || (es & (es - 1)))
+    return fail(LEIDEN_EINVAL, "agg_emit_slots must be 0 or a power of two in 16..4096");
+  G->emit_slots = es;
   G->bincfg = c;
   CHK(refresh_bins0(G));
   return LEIDEN_OK;
@@ -1109,6 +1145,7 @@ leiden_status leiden_static(leiden_graph* G, const leiden_opts* opts, uint32_t* 
   HIPCHK(hipEventRecord(e0, s));
   const uint32_t n = G->n;
   zero_ctl(G, s);
+  G->sweeps = 2 * (uint64_t)n;  // set-up of C', K, Sigma and the flags; dense output labels
   LevelState L = level_state(G);
   launch_row_sums_u32(s, rows0(G), n, L.K);
   HIPCHK(hipMemcpyAsync(L.S, L.K, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s));
@@ -1148,6 +1185,7 @@ leiden_status leiden_static(leiden_graph* G, const leiden_opts* opts, uint32_t* 
     (void)hipEventElapsedTime(&ms, e1, e2);
     stats->ms_modularity = ms;
     kt_collect(G, o.timed_kernel, stats);
+    fill_work(G, stats, 0);
     stats->affected = n;
     stats->moves = G->hctl->total_moves;
     stats->refine_moves = G->hctl->refine_moves;
@@ -1216,6 +1254,8 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   HIPCHK(hipEventCreate(&e3));
   HIPCHK(hipEventRecord(e0, s));
   zero_ctl(G, s);
+  // C^{t-1} and the auxiliary state into the run; tracking (two passes); Sigma^t
+  G->sweeps = 4 * (uint64_t)n;
   // previous memberships: validate and compare with the handle's state
   uint32_t* Cprev = G->st_C.as<uint32_t>();
   bool restart = !G->has_state;
@@ -1297,6 +1337,7 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
     }
     if (rc != 0) return fail(LEIDEN_ENOMEM, "could not make room for the batch");
   }
+  count_units(s, G->g.len, bb.touched, nt, G->edge_parts.as<unsigned long long>(), kWMerge);
   // level-0 degree bins after the batch
   CHK(level_bins(G, s, G->g.len, n, G->bins0, &G->maxdeg0));
   G->nnz = G->nnz - 2 * n_del + 2 * n_ins;
@@ -1408,6 +1449,7 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
     (void)hipEventElapsedTime(&ms, e2, e3);
     stats->ms_modularity = ms;
     kt_collect(G, o.timed_kernel, stats);
+    fill_work(G, stats, ne);
     stats->affected = affected;
     stats->refine_marked = refine_marked;
     stats->moves = G->hctl->total_moves;

@@ -23,6 +23,10 @@ stand in for them):
   * R-MAT: 2^scale vertices, edge_factor * 2^scale samples with quadrant
     probabilities (a, b, c, d), self-loops and duplicates dropped, a seeded vertex
     permutation, unit weights;
+  * Chung-Lu power law (stands in for the paper's largest graphs): expected
+    degrees W (i + i0)^(-1/(gamma - 1)) with the largest one and the mean
+    fixed, endpoint pairs drawn proportionally to them, self-loops and
+    duplicates dropped, weights uniform in 1..16, a seeded permutation;
   * random batch (Section 5.1.4): a fraction of |E| undirected updates, 80%
     insertions of uniform absent pairs and 20% deletions of uniform existing edges;
   * kNN-style graphs for the batched form: points from a 16-d standard normal,
@@ -154,6 +158,57 @@ def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c:
         perm = rng.permutation(n).astype(np.uint32)
         u, v = perm[u], perm[v]
     return csr_from_undirected(n, u, v)
+
+
+def chung_lu_weights(n: int, avg_degree: float, max_degree: float, gamma: float = 2.1):
+    """Expected degrees w_i = W (i + i0)^(-1/(gamma-1)), i = 0..n-1, with W and
+    i0 chosen so that w_0 = max_degree and the sum of w is avg_degree * n (the
+    sum taken as the integral of the power law over [i0, n + i0], solved by
+    bisection on i0)."""
+    a = 1.0 / (gamma - 1.0)
+    target = float(avg_degree) * n
+
+    def total(i0):
+        W = max_degree * i0 ** a
+        if abs(1.0 - a) < 1e-12:
+            return W * (np.log(n + i0) - np.log(i0))
+        return W * ((n + i0) ** (1.0 - a) - i0 ** (1.0 - a)) / (1.0 - a)
+
+    lo, hi = 1e-9, 1e12
+    for _ in range(200):  # total(i0) grows with i0
+        mid = np.sqrt(lo * hi)
+        if total(mid) < target:
+            lo = mid
+        else:
+            hi = mid
+    i0 = np.sqrt(lo * hi)
+    W = max_degree * i0 ** a
+    return W * (np.arange(n, dtype=np.float64) + i0) ** (-a)
+
+
+def chung_lu(n: int, avg_degree: float = 40.0, max_degree: float = 1e6, gamma: float = 2.1, wmax: int = 16,
+             seed: int = BASE_SEED + 3) -> Csr:
+    """Power-law graph of the Chung-Lu model: avg_degree * n / 2 endpoint pairs,
+    each endpoint drawn with probability proportional to its expected degree
+    (chung_lu_weights); self-loops and repeated pairs dropped, so the largest
+    degrees end somewhat below max_degree; weights uniform in 1..wmax per
+    undirected edge; a seeded vertex permutation."""
+    rng = rng_for(seed)
+    w = chung_lu_weights(n, avg_degree, max_degree, gamma)
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    m = int(round(avg_degree * n / 2))
+    u = np.minimum(np.searchsorted(cdf, rng.random(m), side="right"), n - 1).astype(np.uint64)
+    v = np.minimum(np.searchsorted(cdf, rng.random(m), side="right"), n - 1).astype(np.uint64)
+    keep = u != v
+    u, v = u[keep], v[keep]
+    key = np.unique((np.minimum(u, v) << np.uint64(32)) | np.maximum(u, v))
+    del u, v, keep
+    ww = rng.integers(1, wmax + 1, size=key.shape[0], dtype=np.int64).astype(np.uint32)
+    perm = rng.permutation(n).astype(np.uint32)
+    a = perm[(key >> np.uint64(32)).astype(np.int64)]
+    b = perm[(key & np.uint64(0xFFFFFFFF)).astype(np.int64)]
+    return csr_from_undirected(n, a, b, ww)
 
 
 def random_batch(n: int, existing_keys: np.ndarray, n_updates: int, seed: int,

@@ -84,6 +84,16 @@ def test_server_results_equal_alone(lm, orc):
             d, i = streams[k][b]
             r = G.update(d, i, mode=modes[k])
             assert np.array_equal(got[(k, b)].membership, r.membership) and got[(k, b)].q == r.q, (k, b)
+    # a sample against the oracle: two graphs' whole request chains
+    for k in (1, 3):
+        C0, _, _ = orc.static(gs[k])
+        st, cur = orc.initial_state(gs[k], C0), gs[k]
+        for b in range(3):
+            d, i = streams[k][b]
+            gt, dw = orc.apply_batch(cur, d, i)
+            C1, st, q1, _ = orc.update(gt, dw, i, st, modes[k])
+            assert np.array_equal(got[(k, b)].membership, C1) and got[(k, b)].q == q1, (k, b)
+            cur = gt
     for gid in ids:
         srv.remove_graph(gid)
     assert srv.stats()["hbm_reserved"] == 0

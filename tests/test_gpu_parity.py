@@ -454,3 +454,148 @@ def test_temporal_replay_insertions(lm, orc):
     B = 200
     batches = [(np.zeros((0, 2), np.uint32), stream[k * B:(k + 1) * B]) for k in range(12)]
     _run_updates(lm, orc, g0, batches, "df")
+
+
+# ---------------------------------------------------------------------------
+# Aggregation of large communities with small emit tables: a group of
+# neighbouring communities that does not fit the LDS table is split in halves
+# by hash bits until every part fits, and each part is written exactly once.
+# With 16 or 64 slots almost every group of the large communities takes that
+# path (several levels deep); the result must still be the oracle's.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("slots", [16, 64, 4096])
+def test_aggregation_emit_split_path(lm, orc, slots):
+    g = inputs.rmat(14, seed=15)
+    G = _graph(lm, g)
+    G.set_tuning(agg_emit_slots=slots)
+    assert G.tuning()["agg_emit_slots"] == slots
+    r = G.static()
+    C, q, st = orc.static(g)
+    assert np.array_equal(r.membership, C) and r.q == q
+    assert r.stats["passes"] == st["passes"] and r.stats["iters"] == st["iters"]
+    state = orc.initial_state(g, C)
+    cur = g
+    for bi, (dels, ins) in enumerate(_stream(g, [200, 4000], seed=131)):
+        gt, dw = orc.apply_batch(cur, dels, ins)
+        r1 = G.update(dels, ins, mode="nd")
+        C1, state, q1, st1 = orc.update(gt, dw, ins, state, "nd")
+        assert np.array_equal(r1.membership, C1) and r1.q == q1, (slots, bi)
+        assert r1.stats["passes"] == st1["passes"], (slots, bi)
+        cur = gt
+    for bad in (8, 100, 8192):
+        with pytest.raises(lm.LeidenError):
+            G.set_tuning(agg_emit_slots=bad)
+
+
+# ---------------------------------------------------------------------------
+# Auxiliary-state resume (Section 4.4): export C, K, Sigma, DeltaSigma after
+# an update, import them into a fresh handle holding the same graph, apply
+# the next batch there, and require the uninterrupted handle's result.
+# ---------------------------------------------------------------------------
+def test_state_export_import_roundtrip(lm, orc):
+    g = inputs.rmat(12, seed=16)
+    (d1, i1), (d2, i2), (d3, i3) = _stream(g, [300, 300, 300], seed=141)
+    A = _graph(lm, g)
+    A.static()
+    A.update(d1, i1, mode="df")
+    C, K, S, dS = A.state()
+    assert (dS != 0).any()  # cumulative changes carried to the next batch
+    offs, cols, w = A.export()
+    B = lm.Graph(offs, cols, w, n=g.n)
+    B.set_state(C, K, S, dS)
+    for mode, (d, i) in (("df", (d2, i2)), ("ds", (d3, i3))):
+        ra = A.update(d, i, mode=mode)
+        rb = B.update(d, i, mode=mode)
+        assert np.array_equal(ra.membership, rb.membership) and ra.q == rb.q, mode
+        assert ra.stats["passes"] == rb.stats["passes"] and ra.stats["iters"] == rb.stats["iters"]
+        for x, y in zip(A.state(), B.state()):
+            assert np.array_equal(x, y), mode
+    # and the resumed chain equals the oracle's
+    st = orc.State(C, K, S, dS)
+    cur = inputs.Csr(g.n, offs, cols, w)
+    for mode, (d, i) in (("df", (d2, i2)), ("ds", (d3, i3))):
+        gt, dw = orc.apply_batch(cur, d, i)
+        C1, st, q1, _ = orc.update(gt, dw, i, st, mode)
+        cur = gt
+    assert np.array_equal(B.state()[0], C1)
+    # an inconsistent state is refused and leaves the handle as it was
+    before = B.state()
+    with pytest.raises(lm.LeidenError):
+        B.set_state(C, K + 1, S, dS)
+    with pytest.raises(lm.LeidenError):
+        bad = C.copy()
+        bad[0] = g.n
+        B.set_state(bad, K, S, dS)
+    for x, y in zip(before, B.state()):
+        assert np.array_equal(x, y)
+
+
+# ---------------------------------------------------------------------------
+# Refinement threshold tau_re (Sections 4.2-4.3): the ablation's extreme
+# values, compared with the oracle under the same threshold, on batches
+# large enough for both to mark communities (the planted graph's communities
+# take about 1,460 of weight each; the last batch changes about 2,400 per
+# community, the second about 600).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("tau_re", [(1, 10), (9, 10)])
+@pytest.mark.parametrize("mode", ["ds", "df"])
+def test_refinement_threshold_values(lm, orc, tau_re, mode):
+    g = inputs.planted_partition()
+    G = _graph(lm, g)
+    r0 = G.static()
+    C0, _, _ = orc.static(g)
+    assert np.array_equal(r0.membership, C0)
+    state = orc.initial_state(g, C0)
+    cur = g
+    marked = 0
+    for bi, (dels, ins) in enumerate(_stream(g, [100, 3000, 12000], seed=151)):
+        gt, dw = orc.apply_batch(cur, dels, ins)
+        r = G.update(dels, ins, mode=mode, tau_re=tau_re)
+        C1, state, q1, st1 = orc.update(gt, dw, ins, state, mode, tau_re=tau_re)
+        assert np.array_equal(r.membership, C1) and r.q == q1, (tau_re, mode, bi)
+        assert r.stats["passes"] == st1["passes"] and r.stats["iters"] == st1["iters"]
+        Cs, Ks, Ss, dSs = G.state()
+        assert np.array_equal(dSs, state.dS)
+        marked += st1["refine_marked"]
+        cur = gt
+    assert marked > 0  # the threshold does mark communities for refinement
+
+
+# ---------------------------------------------------------------------------
+# Delta-screening with long batch segments: a vertex receiving hundreds of
+# inserted edges to many communities (summed per community in LDS
+# partitions), and a large uniform batch on R-MAT.
+# ---------------------------------------------------------------------------
+def test_ds_long_segments(lm, orc):
+    g = inputs.planted_partition()
+    keys = set(g.undirected_keys().tolist())
+    rng = np.random.default_rng(5)
+    ins = []
+    for v in rng.permutation(np.arange(1, g.n))[:600]:
+        a, b = 0, int(v)
+        if (a << 32 | b) not in keys:
+            ins.append((a, b, int(rng.integers(1, 9))))
+    ins = np.asarray(ins, np.uint32)
+    dels = np.zeros((0, 2), np.uint32)
+    _run_updates(lm, orc, g, [(dels, ins)], "ds")
+    gr = inputs.rmat(14, seed=18)
+    _run_updates(lm, orc, gr, _stream(gr, [inputs.batch_size_for(gr.nnz, 0.1)], seed=161), "ds")
+
+
+# ---------------------------------------------------------------------------
+# Power-law graph of the large-graph recipe (Chung-Lu, exponent 2.1, weights
+# 1..16) at 2^20 vertices: mean drawn degree 40 and a largest expected degree
+# of 2.5e5, so a hub keeps more than 1e5 neighbours after repeated pairs are
+# dropped.  Static Leiden and DF updates of 1e-4 and 1e-3 |E| (insertion
+# weights 1..16), everything against the oracle.
+# ---------------------------------------------------------------------------
+def test_chung_lu_power_law(lm, orc):
+    g = inputs.chung_lu(1 << 20, 40.0, 2.5e5)
+    assert int(g.degrees().max()) >= 100000
+    keys = g.undirected_keys()
+    batches = []
+    for k, f in enumerate((1e-4, 1e-3)):
+        d, i = inputs.random_batch(g.n, keys, inputs.batch_size_for(g.nnz, f), seed=171 + k, w_range=(1, 16))
+        batches.append((d, i))
+        keys = inputs.keys_after_batch(keys, d, i)
+    _run_updates(lm, orc, g, batches, "df")
