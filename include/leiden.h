@@ -221,6 +221,18 @@ leiden_status leiden_update(leiden_graph* g, const uint32_t* del, uint64_t n_del
  * current graph. */
 leiden_status leiden_modularity(leiden_graph* g, const uint32_t* membership, int on_device, double* q_out);
 
+/* leiden_modularity for callers that cannot allocate memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same value, computed without any allocation.  membership: device
+ * uint32[n] (labels < n, else LEIDEN_EINVAL); stream: hipStream_t or NULL
+ * for the handle's own; *q_out: host double.  The scratch memory is a fixed
+ * device array of the library (about 32 MiB per GPU, held until the process
+ * ends) shared by every call on that GPU, so n must not exceed 4,194,304
+ * (2^22; else LEIDEN_EINVAL) and calls that overlap on one GPU race: issue
+ * them from one thread or one stream at a time.  The call returns after
+ * its work on `stream` is complete. */
+leiden_status leiden_modularity_noalloc(leiden_graph* g, const uint32_t* membership, void* stream, double* q_out);
+
 /* Copy the current graph to host memory as a CSR with sorted rows:
  * offsets_out int64[n+1], cols_out uint32[nnz], w_out uint32[nnz] (size them
  * with leiden_graph_nnz). */

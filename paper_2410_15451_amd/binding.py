@@ -26,7 +26,7 @@ EXPORTS = ("leiden_default_opts", "leiden_graph_create", "leiden_graph_destroy",
            "leiden_state_import", "leiden_last_error", "leiden_kernel_name", "leiden_get_tuning",
            "leiden_set_tuning", "leiden_autotune", "leiden_batch_run", "leiden_server_create",
            "leiden_server_destroy", "leiden_server_add_graph", "leiden_server_remove_graph", "leiden_server_submit",
-           "leiden_server_wait", "leiden_server_get_stats")
+           "leiden_server_wait", "leiden_server_get_stats", "leiden_modularity_noalloc")
 
 
 # leiden_work order (work counters of a call)
@@ -141,6 +141,8 @@ def lib():
         L.leiden_update.restype = i32
         L.leiden_modularity.argtypes = [P, P, i32, P]
         L.leiden_modularity.restype = i32
+        L.leiden_modularity_noalloc.argtypes = [P, P, P, P]
+        L.leiden_modularity_noalloc.restype = i32
         L.leiden_graph_export.argtypes = [P, P, P, P]
         L.leiden_graph_export.restype = i32
         L.leiden_state_export.argtypes = [P, P, P, P, P]
@@ -311,6 +313,18 @@ class Graph:
         p, dev = _ptr(membership)
         q = ctypes.c_double()
         _check(lib().leiden_modularity(self._h, p, dev, ctypes.byref(q)))
+        return q.value
+
+    def modularity_noalloc(self, membership, stream=None) -> float:
+        """Eq. 1 of a device-resident membership without any allocation by
+        the library (leiden_modularity_noalloc)."""
+        if not hasattr(membership, "data_ptr"):
+            raise TypeError("membership must be a device tensor")
+        pm, dev = _ptr(membership)
+        if not dev:
+            raise TypeError("membership must be a device tensor")
+        q = ctypes.c_double()
+        _check(lib().leiden_modularity_noalloc(self._h, pm, ctypes.c_void_p(stream), ctypes.byref(q)))
         return q.value
 
     def export(self):

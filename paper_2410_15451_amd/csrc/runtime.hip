@@ -11,6 +11,7 @@
 
 #include "../../include/leiden.h"
 #include "graph.h"
+#include "noalloc.h"
 
 using namespace lm;
 
@@ -1481,6 +1482,19 @@ leiden_status leiden_modularity(leiden_graph* G, const uint32_t* membership, int
   int64_t* K = G->K.as<int64_t>();
   launch_row_sums_u32(s, rows0(G), n, K);
   return modularity_of(G, s, C, K, q_out);
+}
+
+leiden_status leiden_modularity_noalloc(leiden_graph* G, const uint32_t* membership, void* stream, double* q_out) {
+  g_err.clear();
+  if (!G || !membership || !q_out) return fail(LEIDEN_EINVAL, "null argument");
+  if (G->n > kNoAllocMaxN)
+    return fail(LEIDEN_EINVAL, "n = %u exceeds the %u vertices of the scratch array", G->n, kNoAllocMaxN);
+  HIPCHK(hipSetDevice(G->device));
+  hipStream_t s = stream ? (hipStream_t)stream : G->own;
+  const int rc = noalloc_modularity(s, G->device, rows0(G), G->n, membership, q_out);
+  if (rc == 2) return fail(LEIDEN_EINVAL, "membership has a label >= n");
+  if (rc != 0) return fail(LEIDEN_EDEVICE, "modularity without allocation failed");
+  return LEIDEN_OK;
 }
 
 leiden_status leiden_graph_export(leiden_graph* G, int64_t* offsets_out, uint32_t* cols_out, uint32_t* w_out) {
