@@ -45,13 +45,22 @@ def percentile(xs, p):
 
 
 def cpu_baseline(scale, frac, reps, seed):
-    """The oracle (single-threaded CPU) on a bounded sample: R-MAT at `scale`
-    with the same recipe, its own static run (untimed), then `reps` DF updates
-    of frac*|E| timed around the algorithm only."""
+    """The oracle (single-threaded CPU, pinned to one core) on a bounded
+    sample: R-MAT at `scale` with the same recipe, its own static run
+    (untimed), then `reps` DF updates of frac*|E| timed around the algorithm
+    only.  (On the 2^22 graph itself the oracle's own static run, which the
+    DF updates start from, takes minutes of CPU time: beyond the sample's
+    budget, so a smaller graph of the same recipe stands in.)"""
     import numpy as np
 
     import oracle
     from paper_2410_15451_amd import inputs
+    pinned = False
+    try:
+        os.sched_setaffinity(0, {min(os.sched_getaffinity(0))})
+        pinned = True
+    except (AttributeError, OSError):
+        pass
     g = inputs.rmat(scale, seed=seed)
     C0, _, _ = oracle.static(g)
     st = oracle.initial_state(g, C0)
@@ -70,7 +79,9 @@ def cpu_baseline(scale, frac, reps, seed):
         edges += gt.nnz
     return {"value": edges / tsum, "unit": "edges/s", "cores": 1, "kind": "oracle",
             "sample": "R-MAT scale %d (same recipe, |E|=%d), %d DF updates of %g|E| after an untimed oracle static "
-                      "run; single-threaded C++ oracle, %.1f s timed" % (scale, g.nnz, reps, frac, tsum),
+                      "run; single-threaded C++ oracle%s, %.1f s timed; not the 2^22 graph: the oracle's static run "
+                      "there, which the updates start from, takes minutes" % (
+                          scale, g.nnz, reps, frac, " pinned to one core" if pinned else "", tsum),
             "host": host_info()}
 
 
@@ -93,30 +104,46 @@ def host_info():
 
 
 def kernel_source_digest():
-    """Digest of the sources the timed kernel is built from: a stored counter
-    reading is only reported while it still describes the same code."""
+    """Digest of the library sources: a stored counter reading is only
+    reported while it still describes the same code."""
+    import glob
     import hashlib
     h = hashlib.sha256()
-    for f in ("common.h", "kernels.h", "move.hip", "phases.hip"):
-        with open(os.path.join(ROOT, "paper_2410_15451_amd", "csrc", f), "rb") as fh:
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2410_15451_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def stored_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel factor), or
-    None when there is none for the current kernel source."""
+def stored_traffic(scope, workload, field):
+    """HBM bytes (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel factor)
+    from the committed rocprofv3 counter summary: per launch of a kernel or
+    per step of a whole call (`scope`), or None when there is none for the
+    current library source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    r = rec.get(kernel, {}).get(workload)
+    r = rec.get(scope, {}).get(workload)
     if not r or r.get("source_digest") != kernel_source_digest():
         return None
-    return r.get("hbm_bytes_per_launch")
+    return r.get(field)
+
+
+def call_roofline(stats, ms, scope, workload):
+    """Whole-call roofline: the algorithmic bytes the library counts on the
+    device (work counters times their bytes per unit) over the call time."""
+    algo = sum(s["algo_bytes"] for s in stats) / len(stats)
+    achieved = algo / (ms * 1e-3) / 1e9
+    work = {k: sum(s["work"][k] for s in stats) / len(stats) for k in stats[0]["work"]}
+    for k in ("moves", "sweep_vertices", "batch_entries"):
+        work[k] = sum(s[k] for s in stats) / len(stats)
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": stored_traffic(scope, workload, "hbm_bytes_per_step"),
+            "scope": scope, "algo_bytes_per_call": algo, "ms_per_call": ms, "work_per_call": work}
 
 
 def run_batched(args, binding, inputs):
@@ -480,21 +507,26 @@ def main():
 
     mean = {k: sum(s[k] for s in stats) / len(stats) for k in ("ms_total", "ms_batch", "edges_scanned", "moves",
                                                                  "affected", "passes")}
-    # roofline of the timed kernel: algorithmic bytes per launch over its
-    # average launch time (HIP events on the call's stream)
+    workload = "rmat%d_%s_update_%g" % (args.scale, args.mode, args.frac)
+    # whole-call rooflines (the DF update step and the static run): device
+    # work counters times their algorithmic bytes, over the measured time
+    roof = call_roofline(stats, T / args.steps * 1e3, "update", workload)
+    roof_static = call_roofline([rs.stats], t_static * 1e3, "static", "rmat%d_static" % args.scale)
+    # a single kernel inside the step, timed with HIP events on its stream:
+    # algorithmic bytes per launch over its average launch time
     launches = sum(s["kt_launches"] for s in stats)
     kt_ms = sum(s["kt_ms"] for s in stats)
     kt_bytes = sum(s["kt_bytes"] for s in stats)
-    workload = "rmat%d_%s_update_%g" % (args.scale, args.mode, args.frac)
     kname = binding.kernel_name(args.timed_kernel)
-    roof = None
+    kroof = None
     if launches and kt_ms > 0:
         achieved = kt_bytes / (kt_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(kname, workload), "kernel": kname,
-                "launches": launches, "avg_launch_ms": kt_ms / launches, "bytes_per_launch": kt_bytes / launches,
-                "units_per_launch": sum(s["kt_units"] for s in stats) / launches,
-                "share_of_step": kt_ms / (T * 1e3)}
+        kroof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(kname, workload, "hbm_bytes_per_launch"),
+                 "kernel": kname, "launches": launches, "avg_launch_ms": kt_ms / launches,
+                 "bytes_per_launch": kt_bytes / launches,
+                 "units_per_launch": sum(s["kt_units"] for s in stats) / launches,
+                 "share_of_step": kt_ms / (T * 1e3)}
     line = {
         "metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": T / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -505,7 +537,8 @@ def main():
         "static_edges_per_s": g.nnz / t_static, "static_ms": t_static * 1e3,
         "batch_edges_per_s": 2 * nb * args.steps / T,
         "modularity": {"static": q_static, "after_updates": q_dyn},
-        "step_stats_mean": mean, "context": context, "roofline": roof,
+        "step_stats_mean": mean, "context": context, "roofline": roof, "roofline_static": roof_static,
+        "roofline_kernel": kroof,
     }
     if args.cpu_baseline:
         t = time.time()

@@ -76,7 +76,7 @@ typedef struct {
   uint32_t tol_decline;   /* TOLERANCE_DECLINE_FACTOR, 10 */
   uint32_t max_iters;     /* MAX_ITERATIONS per pass, 20 */
   uint32_t max_passes;    /* MAX_PASSES, 10 */
-  uint32_t move_classes;  /* vertex classes of the synchronous local-moving sub-rounds, 8 (1..32) */
+  uint32_t move_classes;  /* vertex classes of the synchronous local-moving sub-rounds, 4 (1..32) */
   uint32_t refine_rounds; /* colour rounds of the synchronous refinement, 8 (1..32) */
   int32_t deterministic;  /* 1: synchronous schedule, bit-exact and reproducible */
   int32_t compute_modularity; /* 1: fill *q_out with Eq. 1 of the result; 0: NaN */

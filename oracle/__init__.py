@@ -121,7 +121,7 @@ def _c(a, dtype):
 
 
 def make_opts(schedule=JACOBI, tau=1e-2, tau_re=(3, 5), tol_decline=10, max_iters=20, max_passes=10,
-              move_classes=8, refine_rounds=8, split_all=0):
+              move_classes=4, refine_rounds=8, split_all=0):
     o = OracleOpts()
     lib().oracle_default_opts(ctypes.byref(o))
     o.tau = tau

@@ -75,7 +75,7 @@ typedef struct {
   uint32_t max_iters;   /* MAX_ITERATIONS per pass (20) */
   uint32_t max_passes;  /* MAX_PASSES (10) */
   int32_t schedule;     /* 0 = SEQ, 1 = JACOBI */
-  uint32_t move_classes;  /* JACOBI: vertex classes per local-moving iteration (8) */
+  uint32_t move_classes;  /* JACOBI: vertex classes per local-moving iteration (4) */
   uint32_t refine_rounds; /* JACOBI: colour rounds of the refinement (8) */
   int32_t split_all;      /* 1: split every community not marked for refinement (Section 4.3's
                              comparison with selective splitting), 0: selective (default) */
@@ -773,7 +773,7 @@ oracle_opts default_opts() {
   o.max_iters = 20;
   o.max_passes = 10;
   o.schedule = 1;
-  o.move_classes = 8;
+  o.move_classes = 4;
   o.refine_rounds = 8;
   o.split_all = 0;
   return o;

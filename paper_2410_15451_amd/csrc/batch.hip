@@ -593,9 +593,9 @@ __global__ __launch_bounds__(kBlock) void k_mark_comm(uint64_t ne, BatchBufs b, 
   GRID_STRIDE(q, ne) {
     const uint32_t c = Cprev[b.seg_src[q]], d = Cprev[b.seg_dst[q]];
     if (c != d) continue;
-    if (b.seg_del[q]) dS[c] = 1;
+    if (b.seg_del[q]) raise_flag(dS, c);
     const long long sg = S[c];
-    if (ratio_exceeds((unsigned long long)dSig[c], (unsigned long long)(sg > 0 ? sg : 0), num, den)) dR[c] = 1;
+    if (ratio_exceeds((unsigned long long)dSig[c], (unsigned long long)(sg > 0 ? sg : 0), num, den)) raise_flag(dR, c);
   }
 }
 
@@ -650,7 +650,7 @@ __global__ __launch_bounds__(kBlock) void k_ds_del(uint64_t ne, BatchBufs b, con
     if (Cprev[i] != Cprev[j]) continue;
     dV[i] = 1;
     dE[i] = 1;
-    dC[Cprev[j]] = 1;
+    raise_flag(dC, Cprev[j]);
   }
 }
 
@@ -681,7 +681,8 @@ __global__ __launch_bounds__(kBlock) void k_ds_ins(uint64_t nt, BatchBufs b, con
         long long h = 0;
         for (uint64_t p = s0; p < s1; ++p)
           if (!b.seg_del[p] && Cprev[b.seg_dst[p]] == c) h += b.seg_w[p];
-        const double dq = delta_q(h, 0, K[i], S[c], S[d], inv_m, inv_2m2);
+        const double dq = b.f_gid ? delta_q(h, 0, K[i], S[c], S[d], b.f_inv[2 * b.f_gid[i]], b.f_inv[2 * b.f_gid[i] + 1])
+                                  : delta_q(h, 0, K[i], S[c], S[d], inv_m, inv_2m2);
         if (better(dq, c, bdq, bc)) {
           bdq = dq;
           bc = c;
@@ -723,6 +724,8 @@ __global__ __launch_bounds__(kBlock) void k_ds_ins_long(uint64_t nt, BatchBufs b
     if (s1 - s0 <= kDsShort) continue;  // block-uniform
     const uint32_t i = b.touched[t];
     const uint32_t d = Cprev[i];
+    const double im = b.f_gid ? b.f_inv[2 * b.f_gid[i]] : inv_m;
+    const double i2 = b.f_gid ? b.f_inv[2 * b.f_gid[i] + 1] : inv_2m2;
     unsigned long long nins = 0;
     for (uint64_t q = s0 + threadIdx.x; q < s1; q += kBlock) nins += b.seg_del[q] ? 0u : 1u;
     nins = block_sum(nins, red);
@@ -746,7 +749,7 @@ __global__ __launch_bounds__(kBlock) void k_ds_ins_long(uint64_t nt, BatchBufs b
         const uint32_t c = tk[sl];
         if (c == kNone) continue;
         if (ok) {
-          const double dq = delta_q((int64_t)tv[sl], 0, K[i], S[c], S[d], inv_m, inv_2m2);
+          const double dq = delta_q((int64_t)tv[sl], 0, K[i], S[c], S[d], im, i2);
           if (better(dq, c, bdq, bc)) {
             bdq = dq;
             bc = c;

@@ -64,7 +64,7 @@ struct Ctl {
   unsigned int mover_count;
   unsigned int refined_any;          // some vertex lies in a refined bound
   unsigned int split_count;          // vertices of split-marked communities
-  unsigned int changed;              // unused
+  unsigned int split_wide;           // split vertices with long rows (wider sample)
   unsigned int split_rest;           // split vertices outside their community's main tree
   unsigned int hub_items;            // (hub, chunk) work items of the current sub-round
   unsigned int error;                // batch validation error code
@@ -76,7 +76,41 @@ struct Ctl {
   unsigned int misc[8];
   unsigned long long kt_units[4];    // work units of the timed kernels (indexed by leiden_kernel)
   unsigned long long units[16];      // work counters of the call (WorkUnit), folded at its end
+  // A forest of independent graphs in one block-diagonal level graph (all
+  // null for one graph): the graph of every vertex of the level, each
+  // graph's first vertex at the level, each graph's Eq. 2 constants (1/m,
+  // 1/(2 m^2)) and iteration gain sum, per graph whether it still iterates
+  // local moving and whether it is still in the pass loop, and per graph
+  // whether it marked a community for refinement in the current pass.
+  const uint32_t* f_gid;
+  const uint32_t* f_base;
+  const double* f_inv;
+  unsigned long long* f_dq;
+  const uint8_t* f_move;
+  const uint8_t* f_pass;
+  uint8_t* f_refined;
 };
+
+// The forest fields of a control block, read once per kernel.
+struct ForestView {
+  const uint32_t* gid;
+  const uint32_t* base;
+  const double* inv;
+  unsigned long long* dq;
+  const uint8_t* move;
+  const uint8_t* pass;
+  uint8_t* refined;
+  // v's ID inside its graph (the schedules hash graph-local IDs, so that
+  // every graph is processed as it would be alone)
+  __device__ uint32_t local(uint32_t v) const { return gid ? v - base[gid[v]] : v; }
+  // v's graph still iterates local moving
+  __device__ bool moving(uint32_t v) const { return !move || move[gid[v]]; }
+  // v's graph is still in the pass loop
+  __device__ bool live(uint32_t v) const { return !pass || pass[gid[v]]; }
+};
+__device__ inline ForestView forest_view(const Ctl* c) {
+  return ForestView{c->f_gid, c->f_base, c->f_inv, c->f_dq, c->f_move, c->f_pass, c->f_refined};
+}
 
 // ---------------------------------------------------------------------------
 // Device helpers
@@ -120,6 +154,35 @@ __device__ inline double delta_q(int64_t kic, int64_t kid, int64_t ki, int64_t s
 __device__ inline long long gain_fixed(double dq) {
 #pragma clang fp contract(off)
   return (long long)(dq * 72057594037927936.0);
+}
+
+// Reads of locations that other threads of the same launch write.
+//  peek: a hint read in front of an atomic or a store that decides by itself
+//    (a stale value only costs a redundant atomic or store); a plain load, so
+//    that it may hit in the caches.  System-scope atomic loads bypass them, and
+//    thousands of lanes reading one hot word (the flag of a large community)
+//    then queue at one memory channel.
+//  ld_dev / st_dev: device-scope relaxed accesses, for values a loop acts on
+//    (union-find parents, live state of the asynchronous schedule).
+template <typename T>
+__device__ inline T peek(const T* p) {
+  return *p;
+}
+template <typename T>
+__device__ inline T ld_dev(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ inline void st_dev(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Raise a flag that many threads may raise at once (e.g. one per member of a
+// large community): read first, since stores to one line from every CU
+// queue on it.
+template <typename T>
+__device__ inline void raise_flag(T* a, size_t i) {
+  if (!peek(&a[i])) a[i] = 1;
 }
 
 // (dq, c) order of the best-community choice: larger gain first, then lower ID.
@@ -209,6 +272,62 @@ __device__ inline void table_accumulate(KeyPtr keys, ValPtr vals, uint32_t mask,
       }
       if (k == kNone) {
         const uint32_t o = atomicCAS(&keys[h], kNone, key);
+        if (o == kNone || o == key) {
+          atomicAdd(&vals[h], w);
+          key = kNone;
+          continue;
+        }
+      }
+      h = (h + 1) & mask;
+    }
+  }
+}
+
+// table_accumulate that also lists the slots it takes (list[*nlist] = slot,
+// LDS counter; the first `cap` of them), so that the table can be read and
+// cleared by its used slots instead of all of them (when *nlist <= cap).
+template <typename KeyPtr, typename ValPtr, typename Entry>
+__device__ inline void table_accumulate_listed(KeyPtr keys, ValPtr vals, uint32_t mask, uint32_t e, uint32_t e1,
+                                               uint32_t step, uint16_t* list, unsigned int* nlist, uint32_t cap,
+                                               Entry entry) {
+  for (; e < e1; e += kStreamBatch * step) {
+    uint32_t kk[kStreamBatch];
+    unsigned long long ww[kStreamBatch];
+#pragma unroll
+    for (int u = 0; u < kStreamBatch; ++u) {
+      kk[u] = kNone;
+      ww[u] = 0;
+      const uint32_t x = e + u * step;
+      if (x < e1) entry(x, kk[u], ww[u]);
+    }
+    int next = 0;
+    uint32_t key = kNone, h = 0;
+    unsigned long long w = 0;
+    while (true) {
+      if (key == kNone) {
+#pragma unroll
+        for (int u = 0; u < kStreamBatch; ++u) {
+          if (key == kNone && u >= next && kk[u] != kNone) {
+            key = kk[u];
+            w = ww[u];
+            next = u + 1;
+          }
+        }
+        if (key == kNone) break;
+        h = slot_hash(key, mask);
+      }
+      const uint32_t k = __atomic_load_n(&keys[h], __ATOMIC_RELAXED);
+      if (k == key) {
+        atomicAdd(&vals[h], w);
+        key = kNone;
+        continue;
+      }
+      if (k == kNone) {
+        const uint32_t o = atomicCAS(&keys[h], kNone, key);
+        if (o == kNone) {
+          const unsigned int x = atomicAdd(nlist, 1u);
+          if (x < cap) list[x] = (uint16_t)h;
+        }
         if (o == kNone || o == key) {
           atomicAdd(&vals[h], w);
           key = kNone;

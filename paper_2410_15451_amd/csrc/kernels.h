@@ -142,10 +142,18 @@ inline uint32_t hub_pick_segs(uint32_t maxdeg) {
 void launch_bin(hipStream_t s, const uint32_t* list, const unsigned int* count, uint32_t n_upper, const uint32_t* len,
                 const uint8_t* in_range, uint32_t* bin_lists, size_t stride, const BinCfg& cfg,
                 unsigned long long* hub_items, Ctl* ctl);
-// maxdeg: largest degree of the level (sizes the hub kernels)
+// Side streams of a sub-round's decide kernels: the degree bins read the same
+// state and only append movers, so their kernels run side by side (forked
+// from and joined back into the call's stream by events).
+struct DecideStreams {
+  hipStream_t aux[3];
+  hipEvent_t fork, join[3];
+};
+// maxdeg: largest degree of the level (sizes the hub kernels); ds may be null
+// (everything on s)
 template <typename W, bool REFINE>
 void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, size_t stride, unsigned int* bin_counts,
-                       const uint64_t* bin_upper, uint32_t maxdeg);
+                       const uint64_t* bin_upper, uint32_t maxdeg, const DecideStreams* ds);
 // long_rows: the level has rows longer than the wavefront path handles
 // items_upper: upper bound of the marking work items (entries / 64 + vertices)
 void launch_apply_moves(hipStream_t s, const ApplyParams& p, uint32_t n_upper, uint64_t items_upper);
@@ -208,11 +216,12 @@ void subset_renumber(hipStream_t s, uint32_t n, uint32_t* C, int64_t*& S, uint32
                      uint8_t*& dR, RenumberBufs& b, Ctl* ctl);
 
 void launch_split_init(hipStream_t s, uint32_t n, const uint32_t* C, const uint8_t* dS, const uint8_t* dR,
-                       uint32_t* lab, uint32_t* list, unsigned long long* main_key, Ctl* ctl, const uint32_t* len,
-                       unsigned long long* parts);
+                       uint32_t* lab, uint32_t* list, uint32_t* wide, unsigned long long* main_key, Ctl* ctl,
+                       const uint32_t* len, unsigned long long* parts);
 template <typename W>
 void launch_split_sample(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* lab, const uint32_t* list,
-                         unsigned long long* main_key, uint32_t* rest, Ctl* ctl, uint32_t n_upper);
+                         const uint32_t* wide, unsigned long long* main_key, uint32_t* rest, Ctl* ctl,
+                         uint32_t n_upper);
 template <typename W>
 void launch_split_union(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* lab, const uint32_t* bin_lists,
                         size_t stride, const unsigned int* bin_counts, const uint64_t* bin_upper);
@@ -265,9 +274,13 @@ void modularity_parts(hipStream_t s, Rows<uint32_t> g, uint32_t n, const uint32_
 
 struct TrackBufs {
   uint32_t* minv;
-  unsigned long long* hkeys;
+  unsigned long long* hkeys;  // pair table (empty between calls)
   long long* hvals;
   uint64_t hmask;
+  int64_t* Kc;                // per vertex: its weight if its pair is its community's common pair
+  int64_t* wcom;              // per community: weight of its common pair, then Sigma_c
+  uint32_t* owners;           // slots of the rare pairs
+  unsigned int* owner_count;
   long long* best_w;
   uint32_t* best_vmin;
   long long* cand_w;
@@ -281,9 +294,17 @@ struct TrackBufs {
   uint8_t* matched;
   void* scan_tmp;
   uint64_t* total;
+  // a forest's graph of each vertex and first vertex of each graph (null for
+  // one graph): every graph draws fresh labels from its own ID range
+  const uint32_t* f_gid;
+  const uint32_t* f_base;
 };
+// out: tracked labels; S_out: Sigma^t by tracked label.  rep (may be null):
+// after one pass without refinement, every vertex's label after local moving
+// and before Alg. 10 (every label of Ccur is then its community's minimum
+// vertex)
 void track(hipStream_t s, uint32_t n, const uint32_t* Ccur, const uint32_t* Cprev, const int64_t* K, uint32_t* out,
-           TrackBufs& b);
+           int64_t* S_out, const uint32_t* rep, TrackBufs& b);
 
 // Per-launch timing of one kernel with HIP events on the launch stream.  The
 // runtime points tl_ktimer at the handle's timer for the duration of a call
@@ -340,6 +361,9 @@ struct BatchBufs {
   int64_t* run_dst;    // its place in the merged row
   void* scan_tmp;
   uint64_t* total;
+  // a forest's graph of each vertex and per-graph Eq. 2 constants (null for one graph)
+  const uint32_t* f_gid;
+  const double* f_inv;
 };
 int batch_prepare(hipStream_t s, uint32_t n, const uint32_t* del, uint64_t n_del, const uint32_t* ins, uint64_t n_ins,
                   BatchBufs& b, Ctl* ctl, uint64_t* n_touched_host);

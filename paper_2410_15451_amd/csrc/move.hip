@@ -27,6 +27,7 @@ __global__ __launch_bounds__(kBlock) void k_distribute(const uint32_t* in_list, 
   if (threadIdx.x < kMaxClasses) scnt[threadIdx.x] = 0;
   __syncthreads();
   const uint32_t cnt = in_count ? *in_count : n_all;
+  const ForestView F = forest_view(ctl);
   constexpr uint32_t tile = kBlock * kDistU;
   for (uint32_t base = blockIdx.x * tile; base < cnt; base += gridDim.x * tile) {
     uint32_t key[kDistU], val[kDistU];
@@ -37,9 +38,11 @@ __global__ __launch_bounds__(kBlock) void k_distribute(const uint32_t* in_list, 
       val[u] = 0;
       if (i < cnt) {
         const uint32_t v = in_list ? in_list[i] : i;
-        key[u] = vertex_class(v, li, P);
-        val[u] = v;
-        pend_mark[v] = stamp;
+        if (F.moving(v)) {
+          key[u] = vertex_class(F.local(v), li, P);
+          val[u] = v;
+          pend_mark[v] = stamp;
+        }
       }
     }
     tile_append<kDistU>(key, val, P, scnt, sbase, [&](uint32_t k, uint32_t*& list, unsigned int*& count) {
@@ -101,9 +104,22 @@ __global__ __launch_bounds__(kBlock) void k_bin(const uint32_t* list, const unsi
 // targets that cannot move in the same colour round) instead of Alg. 6.
 // ---------------------------------------------------------------------------
 template <typename W, bool REFINE>
-__device__ inline bool allowed_target(const DecideParams<W>& p, uint32_t c) {
+__device__ inline bool allowed_target(const DecideParams<W>& p, const ForestView& F, uint32_t c) {
   if (!REFINE) return true;
-  return p.size[c] >= 2 || vertex_colour(c, p.R) != p.colour;
+  return p.size[c] >= 2 || vertex_colour(F.local(c), p.R) != p.colour;
+}
+
+// Eq. 2 constants of vertex v's graph.
+template <typename W>
+__device__ inline void eq2_consts(const DecideParams<W>& p, const ForestView& F, uint32_t v, double& im,
+                                  double& i2) {
+  im = p.inv_m;
+  i2 = p.inv_2m2;
+  if (F.gid) {
+    const uint32_t q = F.gid[v];
+    im = F.inv[2 * q];
+    i2 = F.inv[2 * q + 1];
+  }
 }
 
 // Asynchronous refinement move of isolated vertex v from its singleton d into
@@ -116,7 +132,7 @@ template <typename W>
 __device__ inline void refine_move_async(const DecideParams<W>& p, uint32_t v, uint32_t d, uint32_t c) {
   uint32_t* size = const_cast<uint32_t*>(p.size);
   if (atomicCAS(&size[d], 1u, 0u) != 1u) return;
-  uint32_t s = __atomic_load_n(&size[c], __ATOMIC_RELAXED);
+  uint32_t s = ld_dev(&size[c]);
   while (s != 0) {
     const uint32_t o = atomicCAS(&size[c], s, s + 1);
     if (o == s) break;
@@ -127,7 +143,7 @@ __device__ inline void refine_move_async(const DecideParams<W>& p, uint32_t v, u
     return;
   }
   const long long k = p.K[v];
-  __atomic_store_n(const_cast<uint32_t*>(&p.C[v]), c, __ATOMIC_RELAXED);
+  st_dev(const_cast<uint32_t*>(&p.C[v]), c);
   atomicAdd((unsigned long long*)const_cast<int64_t*>(&p.S[d]), (unsigned long long)(-k));
   atomicAdd((unsigned long long*)const_cast<int64_t*>(&p.S[c]), (unsigned long long)k);
   atomicAdd(&p.ctl->refine_moves, 1ull);
@@ -138,13 +154,14 @@ __device__ inline void refine_move_async(const DecideParams<W>& p, uint32_t v, u
 template <typename W>
 __device__ inline void local_move_async(const DecideParams<W>& p, uint32_t v, uint32_t d, double dq, uint32_t c) {
   const long long k = p.K[v];
-  __atomic_store_n(const_cast<uint32_t*>(&p.C[v]), c, __ATOMIC_RELAXED);
+  st_dev(const_cast<uint32_t*>(&p.C[v]), c);
   atomicAdd((unsigned long long*)const_cast<int64_t*>(&p.S[d]), (unsigned long long)(-k));
   atomicAdd((unsigned long long*)const_cast<int64_t*>(&p.S[c]), (unsigned long long)k);
   atomicSub(const_cast<uint32_t*>(&p.size[d]), 1u);
   atomicAdd(const_cast<uint32_t*>(&p.size[c]), 1u);
-  if (p.dS) p.dS[d] = 1;
-  atomicAdd(&p.ctl->dq_fixed, (unsigned long long)gain_fixed(dq));
+  if (p.dS) raise_flag(p.dS, d);
+  const Ctl* ctl = p.ctl;
+  atomicAdd(ctl->f_gid ? &ctl->f_dq[ctl->f_gid[v]] : &p.ctl->dq_fixed, (unsigned long long)gain_fixed(dq));
   const unsigned int pos = atomicAdd(&p.ctl->mover_count, 1u);
   p.movers[pos] = Mover{v, c, dq};
 }
@@ -209,22 +226,32 @@ __device__ inline void add_decide_units(unsigned long long* parts, unsigned long
 
 // G lanes per vertex (G <= 64, groups inside one wavefront), T slots each;
 // this block is block `blk` of `nblk` working on the list.
-template <int G, int T, typename W, bool REFINE>
+// LISTED: the tables start empty, each keeps a list of the slots it takes
+// (slot_lists, T per group, counts in nslots), and a vertex reads and clears
+// only those: a vertex of a few hundred entries has far fewer distinct
+// communities than its table has slots.
+template <int G, int T, typename W, bool REFINE, bool LISTED = false>
 __device__ inline unsigned long long decide_group_body(const DecideParams<W>& p, const uint32_t* list, uint32_t cnt,
                                                        uint32_t blk, uint32_t nblk, uint32_t* keys,
                                                        unsigned long long* vals, MoverStage& st,
-                                                       unsigned long long& verts) {
+                                                       unsigned long long& verts, uint16_t* slot_lists = nullptr,
+                                                       unsigned int* nslots = nullptr) {
   constexpr int GPB = kBlock / G;
   static_assert(GPB <= kMoverStage, "one round of decisions must fit the stage");
   const int g = threadIdx.x / G, lane = threadIdx.x % G;
   uint32_t* tk = keys + g * T;
   unsigned long long* tv = vals + g * T;
+  uint16_t* sl = LISTED ? slot_lists + g * T : nullptr;
+  unsigned int* nsl = LISTED ? nslots + g : nullptr;
+  const ForestView F = forest_view(p.ctl);
   unsigned long long edges = 0;
   for (uint32_t base = blk * GPB; base < cnt; base += nblk * GPB) {
     const uint32_t item = base + g;
-    for (int s = lane; s < T; s += G) {
-      tk[s] = kNone;
-      tv[s] = 0;
+    if (!LISTED) {
+      for (int s = lane; s < T; s += G) {
+        tk[s] = kNone;
+        tv[s] = 0;
+      }
     }
     __syncthreads();
     bool valid = item < cnt;
@@ -243,7 +270,7 @@ __device__ inline unsigned long long decide_group_body(const DecideParams<W>& p,
         edges += L;
         verts += 1;
       }
-      table_accumulate(tk, tv, T - 1, lane, L, G, [&](uint32_t e, uint32_t& key, unsigned long long& w) {
+      auto entry = [&](uint32_t e, uint32_t& key, unsigned long long& w) {
         const uint32_t j = p.g.cols[s0 + e];
         if (j == v || (REFINE && p.CB[j] != bnd)) return;
         const uint32_t c = p.C[j];
@@ -252,18 +279,26 @@ __device__ inline unsigned long long decide_group_body(const DecideParams<W>& p,
           kid += w;
         else
           key = c;
-      });
+      };
+      if (LISTED)
+        table_accumulate_listed(tk, tv, T - 1, lane, L, G, sl, nsl, (uint32_t)T, entry);
+      else
+        table_accumulate(tk, tv, T - 1, lane, L, G, entry);
     }
     __syncthreads();
     kid = group_sum<G>(kid);
     double bdq = -INFINITY;
     uint32_t bc = kNone;
+    const uint32_t nused = LISTED ? *nsl : (uint32_t)T;
     if (valid) {
       const int64_t ki = p.K[v], sd = p.S[d];
-      for (int s = lane; s < T; s += G) {
+      double im, i2;
+      eq2_consts(p, F, v, im, i2);
+      for (uint32_t x = lane; x < nused; x += G) {
+        const uint32_t s = LISTED ? sl[x] : x;
         const uint32_t c = tk[s];
-        if (c == kNone || !allowed_target<W, REFINE>(p, c)) continue;
-        const double dq = delta_q((int64_t)tv[s], (int64_t)kid, ki, p.S[c], sd, p.inv_m, p.inv_2m2);
+        if (c == kNone || !allowed_target<W, REFINE>(p, F, c)) continue;
+        const double dq = delta_q((int64_t)tv[s], (int64_t)kid, ki, p.S[c], sd, im, i2);
         if (better(dq, c, bdq, bc)) {
           bdq = dq;
           bc = c;
@@ -272,7 +307,15 @@ __device__ inline unsigned long long decide_group_body(const DecideParams<W>& p,
     }
     group_best<G>(bdq, bc);
     if (valid && lane == 0) emit_decision<W, REFINE>(p, v, d, bdq, bc, &st);
+    if (LISTED) {  // back to empty: only the slots this vertex took
+      for (uint32_t x = lane; x < nused; x += G) {
+        const uint32_t s = sl[x];
+        tk[s] = kNone;
+        tv[s] = 0;
+      }
+    }
     __syncthreads();
+    if (LISTED && lane == 0) *nsl = 0;
     if (st.n + GPB > kMoverStage) stage_flush(st, p.ctl, p.movers);
   }
   __syncthreads();
@@ -309,28 +352,38 @@ __global__ __launch_bounds__(kBlock) void k_decide_small(DecideParams<W> p, Smal
   add_decide_units<W, REFINE>(p.edge_parts, edges, verts);
 }
 
-// One block (kBlock lanes) per vertex, T-slot table in LDS.
+// One block (kBlock lanes) per vertex, T-slot table in LDS.  The table
+// starts empty and lists the slots it takes: a vertex reads and clears only
+// those (its distinct communities are usually far fewer than the slots).
 template <int T, typename W, bool REFINE>
 __global__ __launch_bounds__(kBlock) void k_decide_block(DecideParams<W> p) {
+  // slot list of at most LC entries (a vertex with more distinct communities
+  // reads and clears the whole table); 512 keeps three 4096-slot blocks per CU
+  constexpr uint32_t LC = T < 512 ? T : 512;
   __shared__ uint32_t tk[T];
   __shared__ unsigned long long tv[T];
+  __shared__ uint16_t used[LC];
+  __shared__ unsigned int nused;
   __shared__ unsigned long long red[kBlock / kWave];
   __shared__ double rdq[kBlock / kWave];
   __shared__ uint32_t rc[kBlock / kWave];
   __shared__ MoverStage st;
   constexpr uint32_t mask = T - 1;
   const uint32_t cnt = *p.count;
+  const ForestView F = forest_view(p.ctl);
   unsigned long long edges = 0, verts = 0;
-  if (threadIdx.x == 0) st.n = 0;
+  for (uint32_t s = threadIdx.x; s <= mask; s += kBlock) {
+    tk[s] = kNone;
+    tv[s] = 0;
+  }
+  if (threadIdx.x == 0) {
+    st.n = 0;
+    nused = 0;
+  }
   __syncthreads();
   for (uint32_t item = blockIdx.x; item < cnt; item += gridDim.x) {
     const uint32_t v = p.list[item];
     const uint32_t d = p.C[v];
-    for (uint32_t s = threadIdx.x; s <= mask; s += kBlock) {
-      tk[s] = kNone;
-      tv[s] = 0;
-    }
-    __syncthreads();
     const bool valid = !(REFINE && p.size[d] != 1);
     unsigned long long kid = 0;
     if (valid) {
@@ -341,27 +394,33 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(DecideParams<W> p) {
         edges += L;
         verts += 1;
       }
-      table_accumulate(tk, tv, mask, threadIdx.x, L, kBlock, [&](uint32_t e, uint32_t& key, unsigned long long& w) {
-        const uint32_t j = p.g.cols[s0 + e];
-        if (j == v || (REFINE && p.CB[j] != bnd)) return;
-        const uint32_t c = p.C[j];
-        w = (unsigned long long)p.g.w[s0 + e];
-        if (c == d)
-          kid += w;
-        else
-          key = c;
-      });
+      table_accumulate_listed(tk, tv, mask, threadIdx.x, L, kBlock, used, &nused, LC,
+                              [&](uint32_t e, uint32_t& key, unsigned long long& w) {
+                                const uint32_t j = p.g.cols[s0 + e];
+                                if (j == v || (REFINE && p.CB[j] != bnd)) return;
+                                const uint32_t c = p.C[j];
+                                w = (unsigned long long)p.g.w[s0 + e];
+                                if (c == d)
+                                  kid += w;
+                                else
+                                  key = c;
+                              });
     }
     __syncthreads();
     kid = block_sum(kid, red);
     double bdq = -INFINITY;
     uint32_t bc = kNone;
+    const bool listed = nused <= LC;
+    const uint32_t nu = listed ? nused : T;
     if (valid) {
       const int64_t ki = p.K[v], sd = p.S[d];
-      for (uint32_t s = threadIdx.x; s <= mask; s += kBlock) {
+      double im, i2;
+      eq2_consts(p, F, v, im, i2);
+      for (uint32_t x = threadIdx.x; x < nu; x += kBlock) {
+        const uint32_t s = listed ? used[x] : x;
         const uint32_t c = tk[s];
-        if (c == kNone || !allowed_target<W, REFINE>(p, c)) continue;
-        const double dq = delta_q((int64_t)tv[s], (int64_t)kid, ki, p.S[c], sd, p.inv_m, p.inv_2m2);
+        if (c == kNone || !allowed_target<W, REFINE>(p, F, c)) continue;
+        const double dq = delta_q((int64_t)tv[s], (int64_t)kid, ki, p.S[c], sd, im, i2);
         if (better(dq, c, bdq, bc)) {
           bdq = dq;
           bc = c;
@@ -370,8 +429,15 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(DecideParams<W> p) {
     }
     block_best(bdq, bc, rdq, rc);
     if (valid && threadIdx.x == 0) emit_decision<W, REFINE>(p, v, d, bdq, bc, &st);
+    for (uint32_t x = threadIdx.x; x < nu; x += kBlock) {  // back to empty
+      const uint32_t s = listed ? used[x] : x;
+      tk[s] = kNone;
+      tv[s] = 0;
+    }
     __syncthreads();
+    if (threadIdx.x == 0) nused = 0;
     if (st.n == kMoverStage) stage_flush(st, p.ctl, p.movers);
+    __syncthreads();  // the reset before the next vertex's inserts
   }
   __syncthreads();
   stage_flush(st, p.ctl, p.movers);
@@ -507,6 +573,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_pick(DecideParams<W> p) {
   bool clean = false;  // the table is cleared once, by blocks that get work
   const uint32_t cnt = *p.count;
   const uint32_t y = blockIdx.y;
+  const ForestView F = forest_view(p.ctl);
   for (uint32_t h = blockIdx.x; h < cnt; h += gridDim.x) {
     const uint32_t v = p.list[h];
     const uint32_t d = p.C[v];
@@ -539,6 +606,8 @@ __global__ __launch_bounds__(kBlock) void k_hub_pick(DecideParams<W> p) {
     const unsigned long long* sv = p.hub_vals + p.hub_off[hi];
     const int64_t kid = (int64_t)p.hub_kid[hi];
     const int64_t ki = p.K[v], sd = p.S[d];
+    double im, i2;
+    eq2_consts(p, F, v, im, i2);
     double bdq = -INFINITY;
     uint32_t bc = kNone;
     for (uint32_t grp = y; grp < G; grp += nseg) {
@@ -580,8 +649,8 @@ __global__ __launch_bounds__(kBlock) void k_hub_pick(DecideParams<W> p) {
           for (uint32_t sl = threadIdx.x; sl <= mask; sl += kBlock) {
             const uint32_t c = tk[sl];
             if (c == kNone) continue;
-            if (fits && allowed_target<W, REFINE>(p, c)) {
-              const double dq = delta_q((int64_t)tv[sl], kid, ki, p.S[c], sd, p.inv_m, p.inv_2m2);
+            if (fits && allowed_target<W, REFINE>(p, F, c)) {
+              const double dq = delta_q((int64_t)tv[sl], kid, ki, p.S[c], sd, im, i2);
               if (better(dq, c, bdq, bc)) {
                 bdq = dq;
                 bc = c;
@@ -612,8 +681,8 @@ __global__ __launch_bounds__(kBlock) void k_hub_pick(DecideParams<W> p) {
           for (uint32_t r = 0; r < nseg; ++r) {
             const size_t sr = (size_t)hi * p.pick_segs + r;
             const double x = __longlong_as_double(
-                (long long)__atomic_load_n(reinterpret_cast<unsigned long long*>(&p.hub_pdq[sr]), __ATOMIC_RELAXED));
-            const uint32_t xc = __atomic_load_n(&p.hub_pc[sr], __ATOMIC_RELAXED);
+                (long long)ld_dev(reinterpret_cast<const unsigned long long*>(&p.hub_pdq[sr])));
+            const uint32_t xc = ld_dev(&p.hub_pc[sr]);
             if (better(x, xc, bdq, bc)) {
               bdq = x;
               bc = xc;
@@ -707,13 +776,13 @@ int hub_layout(hipStream_t s, const uint32_t* len, uint32_t nl, uint32_t hub_abo
 // and claimed by exchange only when it is not set).
 __device__ inline uint32_t mark_key(const ApplyParams& p, uint32_t j) {
   if (j == kNone) return kNone;
-  const uint32_t kj = vertex_class(j, p.li, p.P);
+  const uint32_t kj = vertex_class(p.ctl->f_gid ? j - p.ctl->f_base[p.ctl->f_gid[j]] : j, p.li, p.P);
   if (kj > p.k) {
-    if (__atomic_load_n(&p.pend_mark[j], __ATOMIC_RELAXED) != p.stamp &&
+    if (peek(&p.pend_mark[j]) != p.stamp &&
         atomicExch(&p.pend_mark[j], p.stamp) != p.stamp)
       return kj;
   } else {
-    if (__atomic_load_n(&p.unproc_mark[j], __ATOMIC_RELAXED) != p.stamp + 1 &&
+    if (peek(&p.unproc_mark[j]) != p.stamp + 1 &&
         atomicExch(&p.unproc_mark[j], p.stamp + 1) != p.stamp + 1)
       return p.P;
   }
@@ -764,6 +833,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_moves(ApplyParams p) {
   __syncthreads();
   const uint32_t lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
   const uint32_t cnt = p.ctl->mover_count;
+  const uint32_t* fgid = p.ctl->f_gid;
   long long dqsum = 0;
   unsigned long long marks = 0;
   const uint32_t stride = gridDim.x * kBlock;
@@ -780,8 +850,11 @@ __global__ __launch_bounds__(kBlock) void k_apply_moves(ApplyParams p) {
         p.C[v] = mv.c;
         apply_delta(tk, ts, tn, d, -k, -1);
         apply_delta(tk, ts, tn, mv.c, k, 1);
-        dqsum += gain_fixed(mv.dq);
-        if (p.dS) p.dS[d] = 1;
+        if (fgid)
+          atomicAdd(&p.ctl->f_dq[fgid[v]], (unsigned long long)gain_fixed(mv.dq));
+        else
+          dqsum += gain_fixed(mv.dq);
+        if (p.dS) raise_flag(p.dS, d);
       }
       nch = (p.len[v] + kMarkChunk - 1) / kMarkChunk;
       marks += p.len[v];
@@ -922,10 +995,21 @@ void launch_bin(hipStream_t s, const uint32_t* list, const unsigned int* count, 
 
 template <typename W, bool REFINE>
 void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, size_t stride, unsigned int* bin_counts,
-                       const uint64_t* bin_upper, uint32_t maxdeg) {
-  // bin 0: 8 lanes / 16 slots, bin 1: 32 / 64, bin 2: 64 / 256,
-  // bin 3: block / 1024, bin 4: block / 4096, bin 5: hubs (all blocks per hub)
-  // bins 0-2 in one launch
+                       const uint64_t* bin_upper, uint32_t maxdeg, const DecideStreams* ds) {
+  // bin 0: 8 lanes / 16 slots, bin 1: 32 / 64, bin 2: 64 / 256 (in one
+  // launch on s); bin 3: block / 1024, bin 4: block / 4096, bin 5: hubs (all
+  // blocks per hub), each on its own side stream when ds is given
+  bool forked = false;
+  auto side = [&](int k) -> hipStream_t {
+    if (!ds) return s;
+    if (!forked) {
+      (void)hipEventRecord(ds->fork, s);
+      forked = true;
+    }
+    (void)hipStreamWaitEvent(ds->aux[k], ds->fork, 0);
+    return ds->aux[k];
+  };
+  bool used[3] = {false, false, false};
   {
     SmallBins sb{};
     uint32_t* nb[3] = {&sb.n0, &sb.n1, &sb.n2};
@@ -943,36 +1027,44 @@ void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, si
     DecideParams<W> q = p;
     q.list = bin_lists + (size_t)b * stride;
     q.count = bin_counts + b;
+    const hipStream_t t = side(b - 3);
+    used[b - 3] = true;
     switch (b) {
       case 3:
         hipLaunchKernelGGL((k_decide_block<1024, W, REFINE>), dim3(grid_for(bin_upper[b], 1, 2048)), dim3(kBlock), 0,
-                           s, q);
+                           t, q);
         break;
       case 4:
         hipLaunchKernelGGL((k_decide_block<4096, W, REFINE>), dim3(grid_for(bin_upper[b], 1, 1024)), dim3(kBlock), 0,
-                           s, q);
+                           t, q);
         break;
       default: {
-        if (sizeof(W) == 4 && !REFINE) kt_mark(LEIDEN_KT_HUB_INSERT, s);
+        if (sizeof(W) == 4 && !REFINE) kt_mark(LEIDEN_KT_HUB_INSERT, t);
         hipLaunchKernelGGL((k_hub_chunk<W, REFINE>), dim3(grid_for(bin_upper[b] * (maxdeg / kHubChunk + 1), 1, 1536)),
-                           dim3(kBlock), 0, s, q);
-        if (sizeof(W) == 4 && !REFINE) kt_mark(LEIDEN_KT_HUB_INSERT, s);
+                           dim3(kBlock), 0, t, q);
+        if (sizeof(W) == 4 && !REFINE) kt_mark(LEIDEN_KT_HUB_INSERT, t);
         hipLaunchKernelGGL((k_hub_pick<W, REFINE>), dim3(grid_for(bin_upper[b], 1, 512), p.pick_segs),
-                           dim3(kBlock), 0, s, q);
+                           dim3(kBlock), 0, t, q);
         break;
       }
     }
   }
+  if (ds)
+    for (int k = 0; k < 3; ++k)
+      if (used[k]) {
+        (void)hipEventRecord(ds->join[k], ds->aux[k]);
+        (void)hipStreamWaitEvent(s, ds->join[k], 0);
+      }
 }
 
 template void launch_decide_all<uint32_t, false>(hipStream_t, DecideParams<uint32_t>, uint32_t*, size_t,
-                                                 unsigned int*, const uint64_t*, uint32_t);
+                                                 unsigned int*, const uint64_t*, uint32_t, const DecideStreams*);
 template void launch_decide_all<uint32_t, true>(hipStream_t, DecideParams<uint32_t>, uint32_t*, size_t,
-                                                unsigned int*, const uint64_t*, uint32_t);
+                                                unsigned int*, const uint64_t*, uint32_t, const DecideStreams*);
 template void launch_decide_all<int64_t, false>(hipStream_t, DecideParams<int64_t>, uint32_t*, size_t,
-                                                unsigned int*, const uint64_t*, uint32_t);
+                                                unsigned int*, const uint64_t*, uint32_t, const DecideStreams*);
 template void launch_decide_all<int64_t, true>(hipStream_t, DecideParams<int64_t>, uint32_t*, size_t, unsigned int*,
-                                               const uint64_t*, uint32_t);
+                                               const uint64_t*, uint32_t, const DecideStreams*);
 
 void launch_apply_moves(hipStream_t s, const ApplyParams& p, uint32_t n_upper, uint64_t items_upper) {
   hipLaunchKernelGGL(k_apply_moves, dim3(grid_for(n_upper, kBlock, 1024)), dim3(kBlock), 0, s, p);

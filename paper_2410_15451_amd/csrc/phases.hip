@@ -106,6 +106,8 @@ __global__ __launch_bounds__(kBlock) void k_move_by_label(uint32_t n, const uint
                                                           int64_t* S2, uint32_t* size2, uint8_t* dS2, uint8_t* dR2,
                                                           Ctl* ctl) {
   unsigned int nsplit = 0, nref = 0;
+  uint8_t* frefined = ctl->f_refined;
+  const uint32_t* fgid = ctl->f_gid;
   GRID_STRIDE(c, n) {
     const uint32_t r = rep[c];
     if (r == kNone) continue;
@@ -115,6 +117,7 @@ __global__ __launch_bounds__(kBlock) void k_move_by_label(uint32_t n, const uint
     dR2[r] = dR[c];
     nsplit += (dS[c] && !dR[c]) ? 1u : 0u;
     nref += dR[c] ? 1u : 0u;
+    if (frefined && dR[c]) raise_flag(frefined, fgid[r]);
   }
   // one atomic per block: per-thread (or per-wavefront) counts on these two
   // words queued one atomic after another
@@ -164,7 +167,8 @@ void subset_renumber(hipStream_t s, uint32_t n, uint32_t* C, int64_t*& S, uint32
 // its tree), in the sampled form of Sutton et al., "Optimizing Parallel Graph
 // Connectivity Computation via Subgraph Sampling" (IPDPS 2018):
 //   1. union each split vertex with the same-community neighbours among the
-//      first kSplitSample entries of its row, then compress;
+//      first kSplitSample entries of its row (a vertex of more than
+//      kSplitWideMin entries: the first kSplitSample + kWave), then compress;
 //   2. per community one main tree (that of its highest-degree member, or of
 //      its label vertex, the minimum member after subset renumbering); a
 //      vertex already in it skips its row (each of its edges is either inside
@@ -172,15 +176,15 @@ void subset_renumber(hipStream_t s, uint32_t n, uint32_t* C, int64_t*& S, uint32
 //   3. every other split vertex unions all its same-community neighbours;
 //   4. compress: the root of each vertex is its component's minimum vertex.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kSplitSample = 4;
+constexpr uint32_t kSplitSample = 4, kSplitWideMin = 64;
 
 __global__ __launch_bounds__(kBlock) void k_split_init(uint32_t n, const uint32_t* C, const uint8_t* dS,
                                                        const uint8_t* dR, uint32_t* lab, uint32_t* list,
-                                                       unsigned long long* main_key, Ctl* ctl, const uint32_t* len,
-                                                       unsigned long long* parts) {
-  __shared__ unsigned int scnt[1], sbase[1];
+                                                       uint32_t* wide, unsigned long long* main_key, Ctl* ctl,
+                                                       const uint32_t* len, unsigned long long* parts) {
+  __shared__ unsigned int scnt[2], sbase[2];
   __shared__ unsigned long long red[kBlock / kWave];
-  if (threadIdx.x == 0) scnt[0] = 0;
+  if (threadIdx.x < 2) scnt[threadIdx.x] = 0;
   __syncthreads();
   unsigned long long entries = 0;
   constexpr uint32_t tile = kBlock * kTileU;
@@ -207,6 +211,14 @@ __global__ __launch_bounds__(kBlock) void k_split_init(uint32_t n, const uint32_
       l = list;
       cn = &ctl->split_count;
     });
+    // the long rows again, in their own list
+#pragma unroll
+    for (int u = 0; u < kTileU; ++u)
+      if (key[u] != kNone && len[val[u]] <= kSplitWideMin) key[u] = kNone;
+    tile_append<kTileU>(key, val, 1, scnt + 1, sbase + 1, [&](uint32_t, uint32_t*& l, unsigned int*& cn) {
+      l = wide;
+      cn = &ctl->split_wide;
+    });
   }
   entries = block_sum(entries, red);
   if (threadIdx.x == 0) add_units(parts, kWSplit, entries);
@@ -214,12 +226,12 @@ __global__ __launch_bounds__(kBlock) void k_split_init(uint32_t n, const uint32_
 
 __device__ inline uint32_t uf_find(uint32_t* p, uint32_t x) {
   // path halving: every pointer written is an ancestor of the node
-  uint32_t px = __atomic_load_n(&p[x], __ATOMIC_RELAXED);
+  uint32_t px = ld_dev(&p[x]);
   while (px != x) {
-    const uint32_t gp = __atomic_load_n(&p[px], __ATOMIC_RELAXED);
-    if (gp != px) __atomic_store_n(&p[x], gp, __ATOMIC_RELAXED);
+    const uint32_t gp = ld_dev(&p[px]);
+    if (gp != px) st_dev(&p[x], gp);
     x = gp;
-    px = __atomic_load_n(&p[x], __ATOMIC_RELAXED);
+    px = ld_dev(&p[x]);
   }
   return x;
 }
@@ -254,6 +266,23 @@ __global__ __launch_bounds__(kBlock) void k_split_sample(Rows<W> g, const uint32
   }
 }
 
+// Long rows sample kSplitWide more entries: a high-degree vertex left
+// outside its community's main tree would union its whole row.  One thread
+// per (long-row vertex, extra entry), like the first sample.
+constexpr uint32_t kSplitWide = 64;
+template <typename W>
+__global__ __launch_bounds__(kBlock) void k_split_sample_wide(Rows<W> g, const uint32_t* C, uint32_t* lab,
+                                                              const uint32_t* wide, const Ctl* ctl) {
+  const uint64_t cnt = (uint64_t)ctl->split_wide * kSplitWide;
+  GRID_STRIDE(q, cnt) {
+    const uint32_t u = wide[q / kSplitWide];
+    const uint32_t e = kSplitSample + (uint32_t)(q % kSplitWide);
+    if (e >= g.len[u]) continue;
+    const uint32_t j = g.cols[g.start[u] + e];
+    if (j != u && C[j] == C[u]) uf_union(lab, u, j);
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_split_compress(uint32_t* lab, const uint32_t* list, const Ctl* ctl) {
   const uint32_t cnt = ctl->split_count;
   GRID_STRIDE(it, cnt) {
@@ -280,7 +309,7 @@ __global__ __launch_bounds__(kBlock) void k_split_main(const uint32_t* len, cons
     if (L <= lo || L > hi) continue;
     const unsigned long long key = ((unsigned long long)L << 32) | (unsigned long long)(0xFFFFFFFFu - u);
     unsigned long long* slot = &main_key[C[u]];
-    if (__atomic_load_n(slot, __ATOMIC_RELAXED) < key) atomicMax(slot, key);
+    if (peek(slot) < key) atomicMax(slot, key);
   }
 }
 
@@ -349,23 +378,27 @@ __global__ void k_split_reset(Ctl* ctl) {
   if (threadIdx.x == 0) {
     ctl->split_count = 0;
     ctl->split_rest = 0;
+    ctl->split_wide = 0;
   }
 }
 
 void launch_split_init(hipStream_t s, uint32_t n, const uint32_t* C, const uint8_t* dS, const uint8_t* dR,
-                       uint32_t* lab, uint32_t* list, unsigned long long* main_key, Ctl* ctl, const uint32_t* len,
-                       unsigned long long* parts) {
+                       uint32_t* lab, uint32_t* list, uint32_t* wide, unsigned long long* main_key, Ctl* ctl,
+                       const uint32_t* len, unsigned long long* parts) {
   hipLaunchKernelGGL(k_split_reset, dim3(1), dim3(1), 0, s, ctl);
   if (n)
     hipLaunchKernelGGL(k_split_init, dim3(grid_n(n, kBlock * kTileU)), dim3(kBlock), 0, s, n, C, dS, dR, lab, list,
-                       main_key, ctl, len, parts);
+                       wide, main_key, ctl, len, parts);
 }
 
 template <typename W>
 void launch_split_sample(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* lab, const uint32_t* list,
-                         unsigned long long* main_key, uint32_t* rest, Ctl* ctl, uint32_t n_upper) {
+                         const uint32_t* wide, unsigned long long* main_key, uint32_t* rest, Ctl* ctl,
+                         uint32_t n_upper) {
   hipLaunchKernelGGL((k_split_sample<W>), dim3(grid_n((uint64_t)n_upper * kSplitSample)), dim3(kBlock), 0, s, g, C,
                      lab, list, ctl);
+  hipLaunchKernelGGL((k_split_sample_wide<W>), dim3(grid_n((uint64_t)n_upper * kSplitWide, kBlock, 4096)),
+                     dim3(kBlock), 0, s, g, C, lab, wide, ctl);
   hipLaunchKernelGGL(k_split_compress, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, lab, list, ctl);
   uint32_t hi = 0xFFFFFFFFu;
   for (const uint32_t lo : kSplitMainBands) {
@@ -405,9 +438,10 @@ void launch_split_finish(hipStream_t s, uint32_t* C, uint32_t* lab, const uint32
 }
 
 template void launch_split_sample<uint32_t>(hipStream_t, Rows<uint32_t>, const uint32_t*, uint32_t*,
-                                            const uint32_t*, unsigned long long*, uint32_t*, Ctl*, uint32_t);
+                                            const uint32_t*, const uint32_t*, unsigned long long*, uint32_t*, Ctl*,
+                                            uint32_t);
 template void launch_split_sample<int64_t>(hipStream_t, Rows<int64_t>, const uint32_t*, uint32_t*, const uint32_t*,
-                                           unsigned long long*, uint32_t*, Ctl*, uint32_t);
+                                           const uint32_t*, unsigned long long*, uint32_t*, Ctl*, uint32_t);
 template void launch_split_union<uint32_t>(hipStream_t, Rows<uint32_t>, const uint32_t*, uint32_t*, const uint32_t*,
                                            size_t, const unsigned int*, const uint64_t*);
 template void launch_split_union<int64_t>(hipStream_t, Rows<int64_t>, const uint32_t*, uint32_t*, const uint32_t*,
@@ -424,6 +458,7 @@ __global__ __launch_bounds__(kBlock) void k_refine_reset(uint32_t n, uint32_t* C
   if (threadIdx.x < kMaxClasses) scnt[threadIdx.x] = 0;
   __syncthreads();
   bool any = false;
+  const ForestView F = forest_view(ctl);
   constexpr uint32_t tile = kBlock * kTileU;
   for (uint64_t base = (uint64_t)blockIdx.x * tile; base < n; base += (uint64_t)gridDim.x * tile) {
     uint32_t key[kTileU], val[kTileU];
@@ -435,12 +470,13 @@ __global__ __launch_bounds__(kBlock) void k_refine_reset(uint32_t n, uint32_t* C
       if (i < n) {
         const uint32_t b = C[i];
         CB[i] = b;
-        if (dR[b]) {
+        // a graph of a forest that left the pass loop keeps its communities
+        if (dR[b] && F.live((uint32_t)i)) {
           C[i] = (uint32_t)i;
           S[i] = K[i];
           size[i] = 1;
           any = true;
-          key[u] = vertex_colour((uint32_t)i, R);
+          key[u] = vertex_colour(F.local((uint32_t)i), R);
         }
       }
     }
@@ -464,7 +500,7 @@ void launch_refine_reset(hipStream_t s, uint32_t n, uint32_t* C, uint32_t* CB, i
 // Dense renumbering in ascending label order, and dendrogram lookup.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_flag_labels(const uint32_t* C, uint32_t n, uint32_t* flag) {
-  GRID_STRIDE(i, n) flag[C[i]] = 1;
+  GRID_STRIDE(i, n) raise_flag(flag, C[i]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_apply_newid(uint32_t* C, uint32_t n, const uint64_t* newid) {
@@ -1224,7 +1260,7 @@ __device__ inline uint64_t pair_slot(unsigned long long key, uint64_t mask) {
 __device__ inline uint64_t pair_insert(unsigned long long* hk, uint64_t mask, unsigned long long key) {
   uint64_t h = pair_slot(key, mask);
   while (true) {
-    const unsigned long long k = __atomic_load_n(&hk[h], __ATOMIC_RELAXED);
+    const unsigned long long k = ld_dev(&hk[h]);
     if (k == key) return h;
     if (k == kNone64) {
       const unsigned long long o = atomicCAS(&hk[h], kNone64, key);
@@ -1234,12 +1270,19 @@ __device__ inline uint64_t pair_insert(unsigned long long* hk, uint64_t mask, un
   }
 }
 
-// Overlap weights of (old, current) community pairs.  Each tile of 1024
-// vertices first sums its pairs in LDS (unchanged communities make a few
-// pairs very hot), then adds each distinct pair once to the global table.
-__global__ __launch_bounds__(kBlock) void k_track_pairs(uint32_t n, const uint32_t* Ccur, const uint32_t* Cprev,
-                                                        const int64_t* K, unsigned long long* hk, long long* hv,
-                                                        uint64_t mask, uint32_t* is_old) {
+// Pairs (old label b, current community c) of the vertices.  With rep given
+// (one pass without refinement: rep[v] is v's label after local moving and
+// before Alg. 10 renumbered it, i.e. the old label whose community c
+// continues), a vertex's pair is common when b = rep[minv[c]]: the pair of
+// every vertex that stayed.  Its weight goes to Kc, summed per community by a
+// bucketed scatter.  The other (rare) pairs, and every pair when rep is null,
+// are summed per tile of 1024 vertices in LDS and then added once per tile to
+// the global pair table; the slots a tile creates are listed.
+__global__ __launch_bounds__(kBlock) void k_track_split(uint32_t n, const uint32_t* Ccur, const uint32_t* Cprev,
+                                                        const int64_t* K, const uint32_t* minv, const uint32_t* rep,
+                                                        int64_t* Kc, unsigned long long* hk, long long* hv,
+                                                        uint64_t mask, uint32_t* owners, unsigned int* owner_count,
+                                                        uint32_t* is_old) {
   constexpr int kTile = 1024, kSlots = 2048;
   __shared__ unsigned long long lk[kSlots];
   __shared__ unsigned long long lv[kSlots];
@@ -1252,9 +1295,14 @@ __global__ __launch_bounds__(kBlock) void k_track_pairs(uint32_t n, const uint32
     for (int t = threadIdx.x; t < kTile; t += kBlock) {
       const uint64_t i = base + t;
       if (i >= n) continue;
-      const uint32_t b = Cprev[i];
-      is_old[b] = 1;
-      const unsigned long long key = ((unsigned long long)b << 32) | Ccur[i];
+      const uint32_t b = Cprev[i], c = Ccur[i];
+      // read first: the members of a large community all name one old label,
+      // and stores to one line from every CU queue on it
+      if (!peek(&is_old[b])) is_old[b] = 1;
+      const bool common = rep && rep[minv[c]] == b;
+      Kc[i] = common ? K[i] : 0;
+      if (common) continue;
+      const unsigned long long key = ((unsigned long long)b << 32) | c;
       uint32_t h = (uint32_t)pair_slot(key, kSlots - 1);
       while (true) {
         const unsigned long long o = atomicCAS(&lk[h], kNone64, key);
@@ -1264,14 +1312,58 @@ __global__ __launch_bounds__(kBlock) void k_track_pairs(uint32_t n, const uint32
       atomicAdd(&lv[h], (unsigned long long)K[i]);
     }
     __syncthreads();
-    for (int s = threadIdx.x; s < kSlots; s += kBlock) {
+    for (int s0 = 0; s0 < kSlots; s0 += kBlock) {
+      const int s = s0 + threadIdx.x;
       const unsigned long long key = lk[s];
-      if (key == kNone64) continue;
-      const uint64_t h = pair_insert(hk, mask, key);
-      atomicAdd((unsigned long long*)&hv[h], lv[s]);
+      uint32_t created = kNone, slot = 0;
+      if (key != kNone64) {
+        uint64_t h = pair_slot(key, mask);
+        while (true) {
+          const unsigned long long k = ld_dev(&hk[h]);
+          if (k == key) break;
+          if (k == kNone64) {
+            const unsigned long long o = atomicCAS(&hk[h], kNone64, key);
+            if (o == kNone64) {
+              created = 0;
+              break;
+            }
+            if (o == key) break;
+          }
+          h = (h + 1) & mask;
+        }
+        atomicAdd((unsigned long long*)&hv[h], lv[s]);
+        slot = (uint32_t)h;
+      }
+      wave_append(created, slot, [&](uint32_t, uint32_t*& l, unsigned int*& cnt) {
+        l = owners;
+        cnt = owner_count;
+      });
     }
     __syncthreads();
   }
+}
+
+// A pair of the two sources: item x < n is community x's common pair (when
+// x is a community and common pairs are in use), item n + k the k-th listed
+// rare pair.
+struct TrackPair {
+  uint32_t b, c;
+  long long w;
+  bool ok;
+};
+__device__ inline TrackPair track_pair(uint64_t x, uint32_t n, const uint32_t* rep, const uint32_t* minv,
+                                       const int64_t* wcom, const unsigned long long* hk, const long long* hv,
+                                       const uint32_t* owners) {
+  TrackPair p{0, 0, 0, false};
+  if (x < n) {
+    const uint32_t m = rep ? minv[x] : kNone;
+    if (m != kNone) p = TrackPair{rep[m], (uint32_t)x, (long long)wcom[x], true};
+  } else {
+    const uint32_t h = owners[x - n];
+    const unsigned long long k = hk[h];
+    p = TrackPair{(uint32_t)(k >> 32), (uint32_t)k, hv[h], true};
+  }
+  return p;
 }
 
 // The maxima of the overlap weights are taken in two launches, weights of at
@@ -1280,28 +1372,32 @@ __global__ __launch_bounds__(kBlock) void k_track_pairs(uint32_t n, const uint32
 // (atomics on one address are serialised device-wide).
 constexpr long long kTrackHeavy = 1ll << 16;
 
-__global__ __launch_bounds__(kBlock) void k_track_best_w(const unsigned long long* hk, const long long* hv,
-                                                         uint64_t slots, long long* best_w, bool heavy) {
-  GRID_STRIDE(sl, slots) {
-    const unsigned long long k = hk[sl];
-    if (k == kNone64) continue;
-    const long long w = hv[sl];
-    if ((w >= kTrackHeavy) != heavy) continue;
+__global__ __launch_bounds__(kBlock) void k_track_best_w(uint32_t n, const uint32_t* rep, const uint32_t* minv,
+                                                         const int64_t* wcom, const unsigned long long* hk,
+                                                         const long long* hv, const uint32_t* owners,
+                                                         const unsigned int* owner_count, long long* best_w,
+                                                         bool heavy) {
+  const uint64_t items = (uint64_t)n + *owner_count;
+  GRID_STRIDE(x, items) {
+    const TrackPair p = track_pair(x, n, rep, minv, wcom, hk, hv, owners);
+    if (!p.ok || (p.w >= kTrackHeavy) != heavy) continue;
     // read first: most updates would not raise the maximum
-    long long* slot = &best_w[k >> 32];
-    if (__atomic_load_n(slot, __ATOMIC_RELAXED) < w) atomicMax(slot, w);
+    long long* slot = &best_w[p.b];
+    if (peek(slot) < p.w) atomicMax(slot, p.w);
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_track_best_c(const unsigned long long* hk, const long long* hv,
-                                                         uint64_t slots, const long long* best_w,
-                                                         const uint32_t* minv, uint32_t* best_vmin) {
-  GRID_STRIDE(sl, slots) {
-    const unsigned long long k = hk[sl];
-    if (k == kNone64) continue;
-    const uint32_t b = (uint32_t)(k >> 32), c = (uint32_t)k;
-    if (hv[sl] == best_w[b] && __atomic_load_n(&best_vmin[b], __ATOMIC_RELAXED) > minv[c])
-      atomicMin(&best_vmin[b], minv[c]);
+__global__ __launch_bounds__(kBlock) void k_track_best_c(uint32_t n, const uint32_t* rep, const uint32_t* minv,
+                                                         const int64_t* wcom, const unsigned long long* hk,
+                                                         const long long* hv, const uint32_t* owners,
+                                                         const unsigned int* owner_count, const long long* best_w,
+                                                         uint32_t* best_vmin) {
+  const uint64_t items = (uint64_t)n + *owner_count;
+  GRID_STRIDE(x, items) {
+    const TrackPair p = track_pair(x, n, rep, minv, wcom, hk, hv, owners);
+    if (!p.ok) continue;
+    const uint32_t vm = minv[p.c];
+    if (p.w == best_w[p.b] && peek(&best_vmin[p.b]) > vm) atomicMin(&best_vmin[p.b], vm);
   }
 }
 
@@ -1313,7 +1409,7 @@ __global__ __launch_bounds__(kBlock) void k_track_cand_w(uint32_t n, const uint3
     const long long w = best_w[b];
     if ((w >= kTrackHeavy) != heavy) continue;
     long long* slot = &cand_w[Ccur[vm]];
-    if (__atomic_load_n(slot, __ATOMIC_RELAXED) < w) atomicMax(slot, w);
+    if (peek(slot) < w) atomicMax(slot, w);
   }
 }
 
@@ -1324,7 +1420,7 @@ __global__ __launch_bounds__(kBlock) void k_track_cand_b(uint32_t n, const uint3
     const uint32_t vm = best_vmin[b];
     if (vm == kNone) continue;
     const uint32_t c = Ccur[vm];
-    if (best_w[b] == cand_w[c] && __atomic_load_n(&cand_b[c], __ATOMIC_RELAXED) > b) atomicMin(&cand_b[c], (uint32_t)b);
+    if (best_w[b] == cand_w[c] && peek(&cand_b[c]) > b) atomicMin(&cand_b[c], (uint32_t)b);
   }
 }
 
@@ -1340,44 +1436,125 @@ __global__ __launch_bounds__(kBlock) void k_track_flags(uint32_t n, const uint32
   }
 }
 
+// Position of the r-th item (by a scan over the whole level) of x's graph in
+// that graph's segment of a per-vertex array: in a forest, every graph ranks
+// its own free IDs and unmatched communities from zero, in its own ID range.
+__device__ inline uint64_t graph_pos(const uint32_t* gid, const uint32_t* base, const uint64_t* rank, uint32_t x,
+                                     uint64_t r) {
+  if (!gid) return r;
+  const uint32_t b = base[gid[x]];
+  return b + (r - rank[b]);
+}
+
 __global__ __launch_bounds__(kBlock) void k_track_free(uint32_t n, const uint32_t* freeflag, const uint64_t* free_rank,
-                                                       uint32_t* free_id) {
-  GRID_STRIDE(x, n) if (freeflag[x]) free_id[free_rank[x]] = (uint32_t)x;
+                                                       uint32_t* free_id, const uint32_t* fgid, const uint32_t* fbase) {
+  GRID_STRIDE(x, n) if (freeflag[x]) free_id[graph_pos(fgid, fbase, free_rank, (uint32_t)x, free_rank[x])] = (uint32_t)x;
 }
 
 __global__ __launch_bounds__(kBlock) void k_track_label(uint32_t n, const uint32_t* Ccur, const uint32_t* minv,
                                                         const uint32_t* cand_b, const uint64_t* rank,
-                                                        const uint32_t* free_id, uint32_t* out, uint8_t* matched) {
+                                                        const uint32_t* free_id, uint32_t* out, uint8_t* matched,
+                                                        const uint32_t* fgid, const uint32_t* fbase) {
   GRID_STRIDE(i, n) {
     const uint32_t c = Ccur[i];
     const uint32_t b = cand_b[c];
     if (b != kNone) {
       out[i] = b;
-      matched[b] = 1;
+      raise_flag(matched, b);
     } else {
-      out[i] = free_id[rank[minv[c]]];
+      const uint32_t m = minv[c];
+      out[i] = free_id[graph_pos(fgid, fbase, rank, m, rank[m])];
     }
   }
 }
 
+// Sigma^t of every community: its common weight plus its rare pairs'.  A
+// block sums its range of rare pairs per community in LDS first (a large
+// community receives pairs from many old communities, and atomics on one
+// address queue device-wide), flushing when its table is half full.
+__global__ __launch_bounds__(kBlock) void k_track_rare_sigma(const unsigned long long* hk, const long long* hv,
+                                                             const uint32_t* owners, const unsigned int* owner_count,
+                                                             int64_t* wcom) {
+  constexpr uint32_t kSlots = 2048, kChunk = kSlots / 2;
+  __shared__ uint32_t tk[kSlots];
+  __shared__ unsigned long long tv[kSlots];
+  for (uint32_t s = threadIdx.x; s < kSlots; s += kBlock) {
+    tk[s] = kNone;
+    tv[s] = 0;
+  }
+  __syncthreads();
+  const uint32_t cnt = *owner_count;
+  const uint32_t per = (cnt + gridDim.x - 1) / gridDim.x;
+  const uint32_t a = blockIdx.x * per, e = min(cnt, a + per);
+  for (uint32_t base = a; base < e; base += kChunk) {
+    for (uint32_t k = base + threadIdx.x; k < min(e, base + kChunk); k += kBlock) {
+      const uint32_t h = owners[k];
+      table_add(tk, tv, kSlots - 1, (uint32_t)hk[h], (unsigned long long)hv[h]);
+    }
+    __syncthreads();
+    for (uint32_t s = threadIdx.x; s < kSlots; s += kBlock) {
+      const uint32_t c = tk[s];
+      if (c == kNone) continue;
+      atomicAdd((unsigned long long*)&wcom[c], tv[s]);
+      tk[s] = kNone;
+      tv[s] = 0;
+    }
+    __syncthreads();
+  }
+}
+
+// Sigma^t under the tracked labels: S[label of c] = Sigma_c.
+__global__ __launch_bounds__(kBlock) void k_track_sigma(uint32_t n, const uint32_t* minv, const uint32_t* cand_b,
+                                                        const uint64_t* rank, const uint32_t* free_id,
+                                                        const int64_t* sig, int64_t* S, const uint32_t* fgid,
+                                                        const uint32_t* fbase) {
+  GRID_STRIDE(c, n) {
+    const uint32_t m = minv[c];
+    if (m == kNone) continue;
+    const uint32_t b = cand_b[c];
+    S[b != kNone ? b : free_id[graph_pos(fgid, fbase, rank, m, rank[m])]] = sig[c];
+  }
+}
+
+// The pair table's used slots back to empty (the table stays clean between calls).
+__global__ __launch_bounds__(kBlock) void k_track_clear(unsigned long long* hk, long long* hv, const uint32_t* owners,
+                                                        const unsigned int* owner_count) {
+  GRID_STRIDE(k, *owner_count) {
+    const uint32_t h = owners[k];
+    hk[h] = kNone64;
+    hv[h] = 0;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_track_minv_self(uint32_t n, const uint32_t* Ccur, uint32_t* minv) {
+  GRID_STRIDE(v, n) if (Ccur[v] == (uint32_t)v) minv[v] = (uint32_t)v;
+}
+
 void track(hipStream_t s, uint32_t n, const uint32_t* Ccur, const uint32_t* Cprev, const int64_t* K, uint32_t* out,
-           TrackBufs& b) {
+           int64_t* S_out, const uint32_t* rep, TrackBufs& b) {
   if (n == 0) return;
-  const uint64_t slots = b.hmask + 1;
+  // minimum vertex of each current community (with rep, labels are minimum vertices)
   fill_u32(s, b.minv, kNone, n);
+  if (rep)
+    hipLaunchKernelGGL(k_track_minv_self, dim3(grid_n(n)), dim3(kBlock), 0, s, n, Ccur, b.minv);
+  else
+    scatter_min_index(s, Ccur, n, b.minv, n);
   fill_u32(s, b.is_old, 0, n);
-  fill_u64(s, (uint64_t*)b.hkeys, ~0ull, slots);
-  fill_u64(s, (uint64_t*)b.hvals, 0, slots);
-  scatter_min_index(s, Ccur, n, b.minv, n);
-  hipLaunchKernelGGL(k_track_pairs, dim3(grid_n(n, 1024, 4096)), dim3(kBlock), 0, s, n, Ccur, Cprev, K, b.hkeys,
-                     b.hvals, b.hmask, b.is_old);
+  fill_u32(s, b.owner_count, 0, 1);
+  hipLaunchKernelGGL(k_track_split, dim3(grid_n(n, 1024, 4096)), dim3(kBlock), 0, s, n, Ccur, Cprev, K, b.minv, rep,
+                     b.Kc, b.hkeys, b.hvals, b.hmask, b.owners, b.owner_count, b.is_old);
+  if (rep) {
+    fill_i64(s, b.wcom, 0, n);
+    scatter_add_i64(s, Ccur, b.Kc, n, b.wcom, n);
+  }
   fill_i64(s, (int64_t*)b.best_w, -1, n);
   fill_u32(s, b.best_vmin, kNone, n);
+  const int gp = grid_n(2 * (uint64_t)n);
   for (const bool heavy : {true, false})
-    hipLaunchKernelGGL(k_track_best_w, dim3(grid_n(slots)), dim3(kBlock), 0, s, b.hkeys, b.hvals, slots, b.best_w,
-                       heavy);
-  hipLaunchKernelGGL(k_track_best_c, dim3(grid_n(slots)), dim3(kBlock), 0, s, b.hkeys, b.hvals, slots, b.best_w,
-                     b.minv, b.best_vmin);
+    hipLaunchKernelGGL(k_track_best_w, dim3(gp), dim3(kBlock), 0, s, n, rep, b.minv, b.wcom, b.hkeys, b.hvals,
+                       b.owners, b.owner_count, b.best_w, heavy);
+  hipLaunchKernelGGL(k_track_best_c, dim3(gp), dim3(kBlock), 0, s, n, rep, b.minv, b.wcom, b.hkeys, b.hvals,
+                     b.owners, b.owner_count, b.best_w, b.best_vmin);
   fill_i64(s, (int64_t*)b.cand_w, -1, n);
   fill_u32(s, b.cand_b, kNone, n);
   for (const bool heavy : {true, false})
@@ -1390,10 +1567,24 @@ void track(hipStream_t s, uint32_t n, const uint32_t* Ccur, const uint32_t* Cpre
                      freeflag);
   exclusive_scan_u32(s, b.flag, b.rank, n, b.total, b.scan_tmp);
   exclusive_scan_u32(s, freeflag, b.free_rank, n, b.total, b.scan_tmp);
-  hipLaunchKernelGGL(k_track_free, dim3(grid_n(n)), dim3(kBlock), 0, s, n, freeflag, b.free_rank, b.free_id);
+  hipLaunchKernelGGL(k_track_free, dim3(grid_n(n)), dim3(kBlock), 0, s, n, freeflag, b.free_rank, b.free_id, b.f_gid,
+                     b.f_base);
   fill_u8(s, b.matched, 0, n);
   hipLaunchKernelGGL(k_track_label, dim3(grid_n(n)), dim3(kBlock), 0, s, n, Ccur, b.minv, b.cand_b, b.rank,
-                     b.free_id, out, b.matched);
+                     b.free_id, out, b.matched, b.f_gid, b.f_base);
+  // Sigma^t under the tracked labels: with common pairs, each community's
+  // common weight plus its (few) rare pairs'; else a scatter over the vertices
+  if (rep) {
+    hipLaunchKernelGGL(k_track_rare_sigma, dim3(128), dim3(kBlock), 0, s, b.hkeys, b.hvals, b.owners,
+                       b.owner_count, b.wcom);
+    fill_i64(s, S_out, 0, n);
+    hipLaunchKernelGGL(k_track_sigma, dim3(grid_n(n)), dim3(kBlock), 0, s, n, b.minv, b.cand_b, b.rank, b.free_id,
+                       b.wcom, S_out, b.f_gid, b.f_base);
+  } else {
+    launch_sigma_from(s, out, K, n, S_out);
+  }
+  // the pair table back to empty
+  hipLaunchKernelGGL(k_track_clear, dim3(grid_n(n)), dim3(kBlock), 0, s, b.hkeys, b.hvals, b.owners, b.owner_count);
 }
 
 }  // namespace lm

@@ -114,12 +114,14 @@ struct leiden_graph {
   float tune_ms = 0;             // probe time of the last autotuning
   uint32_t emit_slots = 4096;    // LDS table of the aggregation emit step (power of two, 16..4096)
   uint64_t sweeps = 0;           // vertices of the per-vertex passes of the current call
+  uint32_t run_passes = 0;       // passes of the last run of Alg. 4
+  bool run_refined0 = false;     // its first pass refined some community
   // level-0 degree bins
   uint64_t bins0[kBins] = {0};
   uint32_t maxdeg0 = 0;
   // workspace
-  Buf C, K, Kb, Kt, S, S2, size, size2, dS, dS2, dR, dR2, CB, rep, Ctop, pend, unproc;
-  Buf cls_lists, bin_lists, iter_list, next_list, movers, split_list, split_rest, split_key, lab;
+  Buf C, K, Kb, Kt, S, S2, size, size2, dS, dS2, dR, dR2, CB, rep, Ctop, Cpre, pend, unproc;
+  Buf cls_lists, bin_lists, iter_list, next_list, movers, split_list, split_rest, split_key, split_wide, lab;
   Buf flag, newid, scan_tmp, ctl, small;
   Buf lvA_start, lvA_len, lvA_cols, lvA_w, lvB_start, lvB_len, lvB_cols, lvB_w;
   Buf agg_count, agg_off, agg_fill, agg_members, agg_deg, agg_cap, agg_lists, agg_bigcap, agg_tbl, agg_keys, agg_vals,
@@ -127,7 +129,8 @@ struct leiden_graph {
   Buf hub_keys, hub_vals, hub_list, hub_idx, hub_off, hub_moff, hub_rbits, hub_size, hub_msize, hub_kid;
   Buf hub_items, hub_mat, hub_live, hub_pdq, hub_pc, hub_done;
   Buf tr_minv, tr_hk, tr_hv, tr_bw, tr_bv, tr_cw, tr_cb, tr_old, tr_flag, tr_rank, tr_frank, tr_fid, tr_label,
-      tr_matched;
+      tr_matched, tr_kc, tr_wcom, tr_owners;
+  void* tr_clean = nullptr;  // pair table known empty (its allocation)
   Buf dV, dE, dC, sig, partials, modparts;
   Buf bt_src, bt_dst, bt_w, bt_del, bt_slot, bt_rowcnt, bt_rowidx, bt_touched, bt_segcnt, bt_segoff, bt_newlen,
       bt_ssrc, bt_sdst, bt_sw, bt_sdel, bt_sid, bt_spre, bt_slb, bt_sortl, bt_tdst, bt_tw, bt_tdel, bt_in, bt_dest, bt_rlen,
@@ -139,7 +142,14 @@ struct leiden_graph {
   bool rowcnt_ready = false;
   Ctl* hctl = nullptr;  // pinned mirror
   KTimer kt;
+  DecideStreams dstreams{};  // side streams of the decide kernels (created with the handle)
+  bool dstreams_ready = false;
   ~leiden_graph() {
+    if (dstreams_ready) {
+      for (hipStream_t& x : dstreams.aux) (void)hipStreamDestroy(x);
+      (void)hipEventDestroy(dstreams.fork);
+      for (hipEvent_t& e : dstreams.join) (void)hipEventDestroy(e);
+    }
     if (kt.ready)
       for (hipEvent_t& e : kt.ev) (void)hipEventDestroy(e);
     if (hctl) (void)hipHostFree(hctl);
@@ -254,6 +264,7 @@ leiden_status ensure_workspace(leiden_graph* G, hipStream_t s, uint32_t classes)
   CHK(G->CB.reserve(n * u32));
   CHK(G->rep.reserve(n * u32));
   CHK(G->Ctop.reserve(n * u32));
+  CHK(G->Cpre.reserve(n * u32));
   if (G->pend.bytes < n * u32) {
     CHK(G->pend.reserve(n * u32));
     CHK(G->unproc.reserve(n * u32));
@@ -267,6 +278,7 @@ leiden_status ensure_workspace(leiden_graph* G, hipStream_t s, uint32_t classes)
   CHK(G->movers.reserve(n * sizeof(Mover)));
   CHK(G->split_list.reserve(n * u32));
   CHK(G->split_rest.reserve(n * u32));
+  CHK(G->split_wide.reserve(n * u32));
   CHK(G->split_key.reserve(n * u64));
   CHK(G->lab.reserve(n * u32));
   CHK(G->flag.reserve(n * u32));
@@ -311,6 +323,9 @@ leiden_status ensure_workspace(leiden_graph* G, hipStream_t s, uint32_t classes)
   CHK(G->tr_fid.reserve(n * u32));
   CHK(G->tr_label.reserve(n * u32));
   CHK(G->tr_matched.reserve(n));
+  CHK(G->tr_kc.reserve(n * u64));
+  CHK(G->tr_wcom.reserve(n * u64));
+  CHK(G->tr_owners.reserve(n * u32 + 64));
   CHK(G->dV.reserve(n));
   CHK(G->dE.reserve(n));
   CHK(G->dC.reserve(n));
@@ -520,7 +535,8 @@ leiden_status local_move(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
       launch_subround_reset(s, ctl);
       launch_bin(s, G->cls_lists.as<uint32_t>() + (size_t)k * nl, &ctl->cls_count[k], nl, g.len, in_range,
                  G->bin_lists.as<uint32_t>(), (size_t)nl, G->bincfg, G->hub_items.as<unsigned long long>(), ctl);
-      launch_decide_all<W, false>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, maxdeg);
+      launch_decide_all<W, false>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, maxdeg,
+                                  &G->dstreams);
       ApplyParams ap{};
       ap.start = g.start;
       ap.len = g.len;
@@ -588,7 +604,8 @@ leiden_status refine(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, Lev
     launch_bin(s, G->cls_lists.as<uint32_t>() + (size_t)r * nl, &ctl->cls_count[r], nl, g.len, nullptr,
                G->bin_lists.as<uint32_t>(), (size_t)nl, G->bincfg, G->hub_items.as<unsigned long long>(), ctl);
     dp.colour = r;
-    launch_decide_all<W, true>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, maxdeg);
+    launch_decide_all<W, true>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, maxdeg,
+                               &G->dstreams);
     launch_apply_refine(s, L.C, L.S, L.K, L.size, G->movers.as<Mover>(), ctl, nl);
   }
   return LEIDEN_OK;
@@ -602,8 +619,9 @@ leiden_status split(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, Leve
   uint32_t* list = G->split_list.as<uint32_t>();
   uint32_t* rest = G->split_rest.as<uint32_t>();
   unsigned long long* key = G->split_key.as<unsigned long long>();
-  launch_split_init(s, nl, L.C, L.dS, L.dR, lab, list, key, ctl, g.len, G->edge_parts.as<unsigned long long>());
-  launch_split_sample<W>(s, g, L.C, lab, list, key, rest, ctl, nl);
+  uint32_t* wide = G->split_wide.as<uint32_t>();
+  launch_split_init(s, nl, L.C, L.dS, L.dR, lab, list, wide, key, ctl, g.len, G->edge_parts.as<unsigned long long>());
+  launch_split_sample<W>(s, g, L.C, lab, list, wide, key, rest, ctl, nl);
   // vertices outside their community's main tree, by degree
   launch_subround_reset(s, ctl);
   launch_bin(s, rest, &ctl->split_rest, nl, g.len, nullptr, G->bin_lists.as<uint32_t>(), (size_t)nl, G->bincfg,
@@ -624,6 +642,9 @@ leiden_status run_pass(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, L
   if (st && pass < 16) st->iters[pass] = po.iters, st->subrounds[pass] = po.subrounds;
   // split-all ablation: every community not marked for refinement is split
   if (ro.o.split_all) fill_u8(s, L.dS, 1, nl);
+  // the first pass's labels before Alg. 10 (tracking of a one-pass update)
+  if (pass == 0 && ro.dynamic)
+    HIPCHK(hipMemcpyAsync(G->Cpre.p, L.C, sizeof(uint32_t) * nl, hipMemcpyDeviceToDevice, s));
   subset_renumber(s, nl, L.C, L.S, L.size, L.dS, L.dR, L.rb, dctl(G));
   G->sweeps += 2 * (uint64_t)nl;  // Alg. 10 and the refinement reset of Alg. 8
   CHK(read_ctl(G, s));
@@ -633,6 +654,7 @@ leiden_status run_pass(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, L
   const bool refined = nref > 0;
   if (refined) CHK(refine<W>(G, s, g, nl, L, ro, qc, bins, maxdeg));
   if (st && pass == 0) st->refined_first_pass = refined ? 1 : 0;
+  if (pass == 0) G->run_refined0 = refined;
   *stop = (po.iters <= 1 && !refined) || (po.iters <= 1 && pass > 0);
   return LEIDEN_OK;
 }
@@ -700,6 +722,8 @@ leiden_status run_leiden(leiden_graph* G, hipStream_t s, LevelState& L, const Ru
                          leiden_stats* st) {
   const uint32_t n = G->n;
   iota_u32(s, G->Ctop.as<uint32_t>(), n);
+  G->run_passes = 0;
+  G->run_refined0 = false;
   if (M2 == 0 || n == 0) {  // no edges: every vertex stays alone
     iota_u32(s, L.C, n);
     return LEIDEN_OK;
@@ -733,7 +757,8 @@ leiden_status run_leiden(leiden_graph* G, hipStream_t s, LevelState& L, const Ru
     CHK(level_bins(G, s, cur.len, nl, bins, &maxdeg));
     tau = tau / (double)ro.o.tol_decline;
   }
-  if (st) st->passes = pass < ro.o.max_passes ? pass + 1 : ro.o.max_passes;
+  G->run_passes = pass < ro.o.max_passes ? pass + 1 : ro.o.max_passes;
+  if (st) st->passes = G->run_passes;
   launch_lookup(s, G->Ctop.as<uint32_t>(), L.C, n);
   G->sweeps += n;
   return LEIDEN_OK;
@@ -894,7 +919,8 @@ leiden_status probe_decide(leiden_graph* G, hipStream_t s, const leiden_opts& o,
     launch_subround_reset(s, ctl);
     launch_bin(s, G->cls_lists.as<uint32_t>() + (size_t)k * n, &ctl->cls_count[k], n, G->g.len, nullptr,
                G->bin_lists.as<uint32_t>(), (size_t)n, G->bincfg, G->hub_items.as<unsigned long long>(), ctl);
-    launch_decide_all<uint32_t, false>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)n, ctl->bin_count, bins, maxdeg);
+    launch_decide_all<uint32_t, false>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)n, ctl->bin_count, bins, maxdeg,
+                                       &G->dstreams);
   }
   HIPCHK(hipEventRecord(e1, s));
   HIPCHK(hipEventSynchronize(e1));
@@ -930,7 +956,7 @@ leiden_status leiden_default_opts(leiden_opts* o) {
   o->tol_decline = 10;
   o->max_iters = 20;
   o->max_passes = 10;
-  o->move_classes = 8;
+  o->move_classes = 4;
   o->refine_rounds = 8;
   o->deterministic = 1;
   o->compute_modularity = 1;
@@ -1063,6 +1089,15 @@ leiden_status leiden_graph_create(int device, uint32_t n, uint64_t nnz, const in
     return bail(fail(LEIDEN_EDEVICE, "stream creation failed"));
   if (hipHostMalloc((void**)&G->hctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess)
     return bail(fail(LEIDEN_EDEVICE, "pinned allocation failed"));
+  {
+    DecideStreams& d = G->dstreams;
+    bool ok = hipEventCreateWithFlags(&d.fork, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; k < 3 && ok; ++k)
+      ok = hipStreamCreateWithFlags(&d.aux[k], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&d.join[k], hipEventDisableTiming) == hipSuccess;
+    if (!ok) return bail(fail(LEIDEN_EDEVICE, "stream creation failed"));
+    G->dstreams_ready = true;
+  }
   hipStream_t s = G->own;
   leiden_status st;
   // upload the input CSR
@@ -1423,15 +1458,27 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   tb.free_id = G->tr_fid.as<uint32_t>();
   tb.label = G->tr_label.as<uint32_t>();
   tb.matched = G->tr_matched.as<uint8_t>();
+  tb.Kc = G->tr_kc.as<int64_t>();
+  tb.wcom = G->tr_wcom.as<int64_t>();
+  tb.owners = G->tr_owners.as<uint32_t>();
+  tb.owner_count = (unsigned int*)(G->small.as<uint64_t>() + 320);
+  if (G->tr_clean != G->tr_hk.p) {  // a fresh pair table starts empty; each call leaves it empty
+    fill_u64(s, (uint64_t*)G->tr_hk.p, ~0ull, tb.hmask + 1);
+    fill_u64(s, (uint64_t*)G->tr_hv.p, 0, tb.hmask + 1);
+    G->tr_clean = G->tr_hk.p;
+  }
+  // after one pass without refinement every label is its community's minimum
+  // vertex (Alg. 10 and the split's component labels), and each community
+  // continues the old community whose label it had before Alg. 10
+  const uint32_t* rep = (G->run_passes == 1 && !G->run_refined0) ? G->Cpre.as<uint32_t>() : nullptr;
   tb.scan_tmp = G->scan_tmp.p;
   tb.total = G->small.as<uint64_t>() + 64;
   uint32_t* out = G->flag.as<uint32_t>();  // free after the run
-  track(s, n, G->Ctop.as<uint32_t>(), Cprev, Kt, out, tb);
+  track(s, n, G->Ctop.as<uint32_t>(), Cprev, Kt, out, G->st_S.as<int64_t>(), rep, tb);
   // new state: C^t, K^t, Sigma^t by C^t, DeltaSigma^t kept for continued labels
   HIPCHK(hipMemcpyAsync(G->st_K.p, Kt, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s));
   dsig_out(s, n, tb.matched, dSig, G->st_dS.as<int64_t>());
   HIPCHK(hipMemcpyAsync(G->st_C.p, out, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
-  launch_sigma_from(s, G->st_C.as<uint32_t>(), G->st_K.as<int64_t>(), n, G->st_S.as<int64_t>());
   G->has_state = true;
   HIPCHK(hipEventRecord(e2, s));
   double q = std::numeric_limits<double>::quiet_NaN();

@@ -7,12 +7,13 @@ kernels DIR [--between REGEX] [--top N]
     first two dispatches whose name matches REGEX are counted (bench.py
     launches a marker kernel right before and right after its timed steps).
 
-counters FETCH_DIR WRITE_DIR --kernel NAME --calib-bytes B [--between REGEX]
+counters FETCH_DIR WRITE_DIR --kernel NAME --calib-bytes B [--between REGEX] [--steps K]
     Average FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the kernel whose
     name starts with NAME, each scaled by what the same counter reads for the
     first device copy of the run (bench.py's calibration copy of B bytes,
     which reads and writes B bytes), and the resulting HBM bytes per launch
-    as JSON.
+    as JSON.  NAME '*' sums every dispatch of the window instead and reports
+    the HBM bytes per step (the window holding K steps).
 
 Reads only rocprofv3's CSV files (--output-format csv).
 """
@@ -115,10 +116,24 @@ def _copy_factor(rows, calib_bytes):
     return (calib_bytes / 1024.0) / copies[0]
 
 
+def _window_sum(rows, between):
+    lo, hi = _window([r[1] for r in rows], between)
+    return sum(v for _, _, v in rows[lo:hi]), hi - lo
+
+
 def counters(args):
     fr = _counter_rows(args.fetch_dir, "FETCH_SIZE")
     wr = _counter_rows(args.write_dir, "WRITE_SIZE")
     ff, fw = _copy_factor(fr, args.calib_bytes), _copy_factor(wr, args.calib_bytes)
+    if args.kernel == "*":
+        fs, fn = _window_sum(fr, args.between)
+        ws, wn = _window_sum(wr, args.between)
+        out = {"kernel": "*", "steps": args.steps, "fetch_kib_per_step": fs / args.steps,
+               "write_kib_per_step": ws / args.steps, "fetch_factor": ff, "write_factor": fw,
+               "dispatches_fetch_run": fn, "dispatches_write_run": wn,
+               "hbm_bytes_per_step": (fs * ff + ws * fw) * 1024.0 / args.steps}
+        print(json.dumps(out, indent=1))
+        return
     fk, fn = _kernel_avg(fr, args.kernel, args.between)
     wk, wn = _kernel_avg(wr, args.kernel, args.between)
     out = {"kernel": args.kernel, "fetch_kib_per_launch": fk, "write_kib_per_launch": wk,
@@ -138,6 +153,7 @@ def main():
     c.add_argument("fetch_dir")
     c.add_argument("write_dir")
     c.add_argument("--kernel", required=True)
+    c.add_argument("--steps", type=int, default=1)
     c.add_argument("--calib-bytes", type=float, required=True)
     c.add_argument("--between", default="")
     a = ap.parse_args()

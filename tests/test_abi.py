@@ -55,4 +55,4 @@ def test_default_opts_without_gpu():
         pytest.skip("library not built")
     o = binding.default_opts()
     assert (o.tau, o.tau_re_num, o.tau_re_den, o.tol_decline, o.max_iters, o.max_passes) == (1e-2, 3, 5, 10, 20, 10)
-    assert (o.move_classes, o.refine_rounds, o.deterministic) == (8, 8, 1)
+    assert (o.move_classes, o.refine_rounds, o.deterministic) == (4, 8, 1)
