@@ -264,6 +264,48 @@ const char* leiden_last_error(void);
  * per-graph status.  Returns the first failure's status, else LEIDEN_OK.
  * opts->stream is ignored.
  * ------------------------------------------------------------------------- */
+/* ---------------------------------------------------------------------------
+ * Forest form: many independent graphs held as one block-diagonal graph, so
+ * that each phase of Alg. 4 (local moving, refinement, aggregation) and of
+ * the dynamic steps (Alg. 1-3, 7, 12) runs as one launch over all of them.
+ * Every graph gets the result it gets alone: its own 1/m in Eq. 2, its own
+ * stopping rules of Alg. 6 and Alg. 4 (gain sum, iteration count, refinement
+ * flag), and schedules hashed on its own vertex IDs.
+ *
+ * leiden_forest_create: graph q has graph_vertices[q] >= 1 vertices (host
+ * array); its vertices are the forest vertices first_q .. first_q +
+ * graph_vertices[q] - 1 with first_q the sum of the earlier counts.  The
+ * CSR is the forest's (n = sum of the counts; rules as leiden_graph_create);
+ * an entry joining two graphs gives LEIDEN_EINVAL.  The handle works with
+ * leiden_static, leiden_update, leiden_modularity, leiden_set_tuning,
+ * leiden_autotune and leiden_graph_export, with these differences:
+ *  - memberships in and out are labels inside each graph (vertex v of graph
+ *    q has its label in 0 .. graph_vertices[q] - 1; static labels are dense
+ *    per graph, ordered by minimum vertex);
+ *  - batch pairs name forest vertices, and a pair joining two graphs gives
+ *    LEIDEN_EINVAL;
+ *  - q_out receives NaN; Eq. 1 of every graph, and the passes and iteration
+ *    counts of the last run, come from leiden_forest_results;
+ *  - leiden_state_export / leiden_state_import and
+ *    leiden_modularity_noalloc give LEIDEN_EINVAL.
+ * leiden_graph_destroy releases it.
+ * ------------------------------------------------------------------------- */
+leiden_status leiden_forest_create(int device, uint32_t n_graphs, const uint32_t* graph_vertices, uint64_t nnz,
+                                   const int64_t* offsets, const uint32_t* cols, const uint32_t* w, int on_device,
+                                   double slack, leiden_graph** out);
+
+/* Per-graph results of the last leiden_static / leiden_update /
+ * leiden_modularity call on a forest (each pointer may be NULL):
+ * q: double[n_graphs] Eq. 1 (NaN when compute_modularity was 0);
+ * passes: uint32[n_graphs] passes of Alg. 4 (0 for a graph without edges);
+ * iters: uint32[n_graphs][16] local-moving iterations of the first 16
+ * passes.  LEIDEN_ESTATE before the first call. */
+leiden_status leiden_forest_results(leiden_graph* g, double* q, uint32_t* passes, uint32_t* iters);
+
+/* *n_graphs: graphs of a forest (0 for a single graph); first_vertex (may be
+ * NULL): uint32[n_graphs + 1] first forest vertex of every graph, then n. */
+leiden_status leiden_forest_info(leiden_graph* g, uint32_t* n_graphs, uint32_t* first_vertex);
+
 typedef struct {
   const uint32_t* del; /* uint32[n_del][2] */
   uint64_t n_del;

@@ -26,7 +26,10 @@ EXPORTS = ("leiden_default_opts", "leiden_graph_create", "leiden_graph_destroy",
            "leiden_state_import", "leiden_last_error", "leiden_kernel_name", "leiden_get_tuning",
            "leiden_set_tuning", "leiden_autotune", "leiden_batch_run", "leiden_server_create",
            "leiden_server_destroy", "leiden_server_add_graph", "leiden_server_remove_graph", "leiden_server_submit",
-           "leiden_server_wait", "leiden_server_get_stats", "leiden_modularity_noalloc")
+           "leiden_server_wait", "leiden_server_get_stats", "leiden_modularity_noalloc", "leiden_forest_create",
+           "leiden_forest_results", "leiden_forest_info")
+
+FOREST_ITER_HIST = 16  # passes whose iteration counts leiden_forest_results returns
 
 
 # leiden_work order (work counters of a call)
@@ -161,7 +164,10 @@ def lib():
                            ("leiden_server_remove_graph", [P, u32]),
                            ("leiden_server_submit", [P, u32, P, u64, P, u64, i32, P, ctypes.POINTER(u64)]),
                            ("leiden_server_wait", [P, u64, P, P, P, P, P]),
-                           ("leiden_server_get_stats", [P, P])):
+                           ("leiden_server_get_stats", [P, P]),
+                           ("leiden_forest_create", [i32, u32, P, u64, P, P, P, i32, dbl, ctypes.POINTER(P)]),
+                           ("leiden_forest_results", [P, P, P, P]),
+                           ("leiden_forest_info", [P, P, P])):
             getattr(L, name).argtypes = args
             getattr(L, name).restype = i32
         L.leiden_server_destroy.argtypes = [P]
@@ -367,6 +373,57 @@ class Graph:
     def set_state(self, C, K, S, dS):
         arrs = [np.ascontiguousarray(C, np.uint32)] + [np.ascontiguousarray(x, np.int64) for x in (K, S, dS)]
         _check(lib().leiden_state_import(self._h, *[_ptr(a)[0] for a in arrs]))
+
+
+class Forest(Graph):
+    """Many independent graphs in one handle (leiden_forest_create): every
+    phase runs as one launch over all of them.  Memberships are labels
+    inside each graph; batch pairs name forest vertices (first_vertex[q] +
+    the vertex inside graph q)."""
+
+    def __init__(self, sizes, offs, cols, w, device=0, slack=0.2):
+        sizes = np.ascontiguousarray(sizes, np.uint32)
+        if hasattr(offs, "data_ptr") != hasattr(cols, "data_ptr"):
+            raise TypeError("offsets, cols and w must all be numpy arrays or all torch tensors")
+        if not hasattr(offs, "data_ptr"):
+            offs = np.ascontiguousarray(offs, np.int64)
+            cols = np.ascontiguousarray(cols, np.uint32)
+            w = np.ascontiguousarray(w, np.uint32)
+        nnz = int(cols.shape[0])
+        po, dev = _ptr(offs)
+        pc, _ = _ptr(cols)
+        pw, _ = _ptr(w)
+        h = ctypes.c_void_p()
+        _check(lib().leiden_forest_create(device, int(sizes.shape[0]), sizes.ctypes.data, nnz, po, pc, pw, dev,
+                                          float(slack), ctypes.byref(h)))
+        self._h = h
+        self.n = int(sizes.sum(dtype=np.uint64))
+        self.device = device
+        self.sizes = sizes
+        self.first = np.zeros(sizes.shape[0] + 1, np.uint32)
+        nq = ctypes.c_uint32()
+        _check(lib().leiden_forest_info(self._h, ctypes.byref(nq), self.first.ctypes.data))
+        _LIVE_GRAPHS.add(self)
+
+    @property
+    def n_graphs(self) -> int:
+        return int(self.sizes.shape[0])
+
+    def results(self):
+        """(q float64[n_graphs], passes uint32[n_graphs], iters uint32[n_graphs, 16]) of the last call."""
+        nq = self.n_graphs
+        q = np.zeros(nq, np.float64)
+        passes = np.zeros(nq, np.uint32)
+        iters = np.zeros((nq, FOREST_ITER_HIST), np.uint32)
+        _check(lib().leiden_forest_results(self._h, q.ctypes.data, passes.ctypes.data, iters.ctypes.data))
+        return q, passes, iters
+
+    def modularity(self, membership):
+        """Eq. 1 of every graph (float64[n_graphs]) under labels inside each graph."""
+        super().modularity(membership)
+        q = np.zeros(self.n_graphs, np.float64)
+        _check(lib().leiden_forest_results(self._h, q.ctypes.data, None, None))
+        return q
 
 
 def _batch_arrays(dels, ins):

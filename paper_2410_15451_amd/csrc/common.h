@@ -89,6 +89,8 @@ struct Ctl {
   const uint8_t* f_move;
   const uint8_t* f_pass;
   uint8_t* f_refined;
+  unsigned int f_live;    // graphs still in the pass loop
+  unsigned int f_moving;  // graphs still iterating local moving
 };
 
 // The forest fields of a control block, read once per kernel.
@@ -158,23 +160,28 @@ __device__ inline long long gain_fixed(double dq) {
 
 // Reads of locations that other threads of the same launch write.
 //  peek: a hint read in front of an atomic or a store that decides by itself
-//    (a stale value only costs a redundant atomic or store); a plain load, so
-//    that it may hit in the caches.  System-scope atomic loads bypass them, and
-//    thousands of lanes reading one hot word (the flag of a large community)
-//    then queue at one memory channel.
-//  ld_dev / st_dev: device-scope relaxed accesses, for values a loop acts on
-//    (union-find parents, live state of the asynchronous schedule).
+//    (a stale value only costs a redundant atomic or store: the flags and
+//    maxima it guards only grow during a launch); a plain load, so that it may
+//    hit in the caches.  System-scope atomic loads bypass them, and thousands
+//    of lanes reading one hot word (the flag of a large community) then queue
+//    at one memory channel.
+//  ld_sys / st_sys: system-scope relaxed accesses, for values a loop acts on
+//    (union-find parents, hash-table keys, live state of the asynchronous
+//    schedule, partial results of other blocks).  Device-scope loads may be
+//    served by the issuing XCD's own L2, which does not see the other XCDs'
+//    writes during the launch; a retry loop can then read the same stale
+//    value forever.
 template <typename T>
 __device__ inline T peek(const T* p) {
   return *p;
 }
 template <typename T>
-__device__ inline T ld_dev(const T* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ inline T ld_sys(const T* p) {
+  return __atomic_load_n(p, __ATOMIC_RELAXED);
 }
 template <typename T>
-__device__ inline void st_dev(T* p, T v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ inline void st_sys(T* p, T v) {
+  __atomic_store_n(p, v, __ATOMIC_RELAXED);
 }
 
 // Raise a flag that many threads may raise at once (e.g. one per member of a

@@ -263,7 +263,8 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
               uint32_t* out_len, uint32_t* out_cols, int64_t* out_w, int64_t* Kout, Ctl* ctl);
 
 void launch_static_relabel(hipStream_t s, const uint32_t* C, uint32_t n, uint32_t* minv, uint32_t* flag,
-                           uint64_t* rank, uint32_t* out, void* scan_tmp, uint64_t* total);
+                           uint64_t* rank, uint32_t* out, void* scan_tmp, uint64_t* total, const uint32_t* fgid = nullptr,
+                           const uint32_t* fbase = nullptr);
 
 struct ModParts {
   unsigned long long sigma;
@@ -305,6 +306,40 @@ struct TrackBufs {
 // vertex)
 void track(hipStream_t s, uint32_t n, const uint32_t* Ccur, const uint32_t* Cprev, const int64_t* K, uint32_t* out,
            int64_t* S_out, const uint32_t* rep, TrackBufs& b);
+
+// forest.hip: per-graph state of a forest run (see the file's header).
+constexpr uint32_t kForestIterHist = 16;  // passes whose iteration counts are kept per graph
+struct ForestBufs {
+  uint32_t nq;
+  unsigned long long* m2;    // per graph 2m
+  double* inv;               // per graph 1/m, 1/(2 m^2)
+  unsigned long long* dq;    // per graph gain sum of the current iteration (2^56 fixed point)
+  uint8_t* move;             // per graph: still iterating local moving
+  uint8_t* pass;             // per graph: still in the pass loop
+  uint8_t* refined;          // per graph: refined a community in the current pass
+  uint32_t* cur_iters;       // per graph iterations of the current pass
+  uint32_t* passes;          // per graph passes of the run
+  uint32_t* iters_hist;      // kForestIterHist x nq iteration counts
+};
+void forest_gid(hipStream_t s, uint32_t n, uint32_t nq, const uint32_t* base, uint32_t* gid);
+void forest_next_base(hipStream_t s, uint32_t nq, uint32_t nl, const uint32_t* base, const uint64_t* newid,
+                      const uint64_t* total, uint32_t* next);
+void forest_check_rows(hipStream_t s, Rows<uint32_t> g, uint32_t n, const uint32_t* gid, const uint32_t* base,
+                       unsigned int* flags);
+void forest_check_batch(hipStream_t s, const uint32_t* del, uint64_t n_del, const uint32_t* ins, uint64_t n_ins,
+                        uint32_t n, const uint32_t* gid, unsigned int* flags);
+void forest_to_forest(hipStream_t s, uint32_t n, const uint32_t* gid, const uint32_t* base, const uint32_t* local,
+                      uint32_t* out, unsigned int* flags);
+void forest_to_local(hipStream_t s, uint32_t n, const uint32_t* gid, const uint32_t* base, const uint32_t* in,
+                     uint32_t* out);
+void forest_sum(hipStream_t s, uint32_t n, const uint32_t* gid, const int64_t* x, unsigned long long* out);
+void forest_modularity_parts(hipStream_t s, Rows<uint32_t> g, uint32_t n, uint32_t nq, const uint32_t* C,
+                             const int64_t* K, const uint32_t* gid, int64_t* Sig, unsigned long long* parts);
+void forest_start(hipStream_t s, const ForestBufs& f, Ctl* ctl);
+void forest_iter_end(hipStream_t s, const ForestBufs& f, double tau, uint32_t li, uint32_t max_iters, Ctl* ctl);
+void forest_pass_end(hipStream_t s, const ForestBufs& f, uint32_t pass, Ctl* ctl);
+void forest_bind(hipStream_t s, Ctl* ctl, const ForestBufs& f, const uint32_t* gid, const uint32_t* base);
+void forest_isolate(hipStream_t s, uint32_t n, const uint32_t* gid, const uint8_t* pass, uint32_t* C);
 
 // Per-launch timing of one kernel with HIP events on the launch stream.  The
 // runtime points tl_ktimer at the handle's timer for the duration of a call

@@ -132,7 +132,7 @@ template <typename W>
 __device__ inline void refine_move_async(const DecideParams<W>& p, uint32_t v, uint32_t d, uint32_t c) {
   uint32_t* size = const_cast<uint32_t*>(p.size);
   if (atomicCAS(&size[d], 1u, 0u) != 1u) return;
-  uint32_t s = ld_dev(&size[c]);
+  uint32_t s = ld_sys(&size[c]);
   while (s != 0) {
     const uint32_t o = atomicCAS(&size[c], s, s + 1);
     if (o == s) break;
@@ -143,7 +143,7 @@ __device__ inline void refine_move_async(const DecideParams<W>& p, uint32_t v, u
     return;
   }
   const long long k = p.K[v];
-  st_dev(const_cast<uint32_t*>(&p.C[v]), c);
+  st_sys(const_cast<uint32_t*>(&p.C[v]), c);
   atomicAdd((unsigned long long*)const_cast<int64_t*>(&p.S[d]), (unsigned long long)(-k));
   atomicAdd((unsigned long long*)const_cast<int64_t*>(&p.S[c]), (unsigned long long)k);
   atomicAdd(&p.ctl->refine_moves, 1ull);
@@ -154,7 +154,7 @@ __device__ inline void refine_move_async(const DecideParams<W>& p, uint32_t v, u
 template <typename W>
 __device__ inline void local_move_async(const DecideParams<W>& p, uint32_t v, uint32_t d, double dq, uint32_t c) {
   const long long k = p.K[v];
-  st_dev(const_cast<uint32_t*>(&p.C[v]), c);
+  st_sys(const_cast<uint32_t*>(&p.C[v]), c);
   atomicAdd((unsigned long long*)const_cast<int64_t*>(&p.S[d]), (unsigned long long)(-k));
   atomicAdd((unsigned long long*)const_cast<int64_t*>(&p.S[c]), (unsigned long long)k);
   atomicSub(const_cast<uint32_t*>(&p.size[d]), 1u);
@@ -681,8 +681,8 @@ __global__ __launch_bounds__(kBlock) void k_hub_pick(DecideParams<W> p) {
           for (uint32_t r = 0; r < nseg; ++r) {
             const size_t sr = (size_t)hi * p.pick_segs + r;
             const double x = __longlong_as_double(
-                (long long)ld_dev(reinterpret_cast<const unsigned long long*>(&p.hub_pdq[sr])));
-            const uint32_t xc = ld_dev(&p.hub_pc[sr]);
+                (long long)ld_sys(reinterpret_cast<const unsigned long long*>(&p.hub_pdq[sr])));
+            const uint32_t xc = ld_sys(&p.hub_pc[sr]);
             if (better(x, xc, bdq, bc)) {
               bdq = x;
               bc = xc;

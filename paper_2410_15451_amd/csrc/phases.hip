@@ -226,12 +226,12 @@ __global__ __launch_bounds__(kBlock) void k_split_init(uint32_t n, const uint32_
 
 __device__ inline uint32_t uf_find(uint32_t* p, uint32_t x) {
   // path halving: every pointer written is an ancestor of the node
-  uint32_t px = ld_dev(&p[x]);
+  uint32_t px = ld_sys(&p[x]);
   while (px != x) {
-    const uint32_t gp = ld_dev(&p[px]);
-    if (gp != px) st_dev(&p[x], gp);
+    const uint32_t gp = ld_sys(&p[px]);
+    if (gp != px) st_sys(&p[x], gp);
     x = gp;
-    px = ld_dev(&p[x]);
+    px = ld_sys(&p[x]);
   }
   return x;
 }
@@ -246,8 +246,12 @@ __device__ inline void uf_union(uint32_t* p, uint32_t a, uint32_t b) {
       a = b;
       b = t;
     }
-    // hang root b under the smaller root a; retry if b stopped being a root
-    if (atomicCAS(&p[b], b, a) == b) return;
+    // hang root b under the smaller root a; if b stopped being a root, go on
+    // from the parent the compare-and-swap found (a smaller ID), so that
+    // every retry makes progress whatever the loads above returned
+    const uint32_t o = atomicCAS(&p[b], b, a);
+    if (o == b) return;
+    b = o;
   }
 }
 
@@ -1158,19 +1162,31 @@ __global__ __launch_bounds__(kBlock) void k_first_flag(const uint32_t* C, uint32
   GRID_STRIDE(i, n) flag[i] = minv[C[i]] == (uint32_t)i ? 1u : 0u;
 }
 
+// In a forest every graph ranks its own communities from zero, and the label
+// is offset by the graph's first vertex.
 __global__ __launch_bounds__(kBlock) void k_rank_label(const uint32_t* C, uint32_t n, const uint32_t* minv,
-                                                       const uint64_t* rank, uint32_t* out) {
-  GRID_STRIDE(i, n) out[i] = (uint32_t)rank[minv[C[i]]];
+                                                       const uint64_t* rank, uint32_t* out, const uint32_t* fgid,
+                                                       const uint32_t* fbase) {
+  GRID_STRIDE(i, n) {
+    const uint32_t m = minv[C[i]];
+    if (fgid) {
+      const uint32_t b = fbase[fgid[i]];
+      out[i] = b + (uint32_t)(rank[m] - rank[b]);
+    } else {
+      out[i] = (uint32_t)rank[m];
+    }
+  }
 }
 
 void launch_static_relabel(hipStream_t s, const uint32_t* C, uint32_t n, uint32_t* minv, uint32_t* flag,
-                           uint64_t* rank, uint32_t* out, void* scan_tmp, uint64_t* total) {
+                           uint64_t* rank, uint32_t* out, void* scan_tmp, uint64_t* total, const uint32_t* fgid,
+                           const uint32_t* fbase) {
   if (n == 0) return;
   fill_u32(s, minv, kNone, n);
   scatter_min_index(s, C, n, minv, n);
   hipLaunchKernelGGL(k_first_flag, dim3(grid_n(n)), dim3(kBlock), 0, s, C, n, minv, flag);
   exclusive_scan_u32(s, flag, rank, n, total, scan_tmp);
-  hipLaunchKernelGGL(k_rank_label, dim3(grid_n(n)), dim3(kBlock), 0, s, C, n, minv, rank, out);
+  hipLaunchKernelGGL(k_rank_label, dim3(grid_n(n)), dim3(kBlock), 0, s, C, n, minv, rank, out, fgid, fbase);
 }
 
 // ---------------------------------------------------------------------------
@@ -1260,7 +1276,7 @@ __device__ inline uint64_t pair_slot(unsigned long long key, uint64_t mask) {
 __device__ inline uint64_t pair_insert(unsigned long long* hk, uint64_t mask, unsigned long long key) {
   uint64_t h = pair_slot(key, mask);
   while (true) {
-    const unsigned long long k = ld_dev(&hk[h]);
+    const unsigned long long k = ld_sys(&hk[h]);
     if (k == key) return h;
     if (k == kNone64) {
       const unsigned long long o = atomicCAS(&hk[h], kNone64, key);
@@ -1319,7 +1335,7 @@ __global__ __launch_bounds__(kBlock) void k_track_split(uint32_t n, const uint32
       if (key != kNone64) {
         uint64_t h = pair_slot(key, mask);
         while (true) {
-          const unsigned long long k = ld_dev(&hk[h]);
+          const unsigned long long k = ld_sys(&hk[h]);
           if (k == key) break;
           if (k == kNone64) {
             const unsigned long long o = atomicCAS(&hk[h], kNone64, key);

@@ -93,6 +93,34 @@ QConst make_qconst(uint64_t M2) {
   return q;
 }
 
+// A forest's graphs and its per-graph run state (see forest.hip).
+struct ForestState {
+  uint32_t nq = 0;
+  std::vector<uint32_t> first;  // first vertex of every graph (nq + 1; the last is n)
+  Buf gid0, base0;              // the input graph's
+  Buf gidA, baseA, gidB, baseB; // level graphs' (alternating)
+  const uint32_t* cur_gid = nullptr;
+  const uint32_t* cur_base = nullptr;
+  Buf m2, inv, dq, move, pass, refined, cur_iters, passes, iters_hist, parts, out_local;
+  // results of the last call
+  std::vector<double> q;
+  std::vector<uint32_t> passes_h, iters_h;
+  ForestBufs bufs() {
+    ForestBufs f{};
+    f.nq = nq;
+    f.m2 = m2.as<unsigned long long>();
+    f.inv = inv.as<double>();
+    f.dq = dq.as<unsigned long long>();
+    f.move = move.as<uint8_t>();
+    f.pass = pass.as<uint8_t>();
+    f.refined = refined.as<uint8_t>();
+    f.cur_iters = cur_iters.as<uint32_t>();
+    f.passes = passes.as<uint32_t>();
+    f.iters_hist = iters_hist.as<uint32_t>();
+    return f;
+  }
+};
+
 }  // namespace
 
 struct leiden_graph {
@@ -144,7 +172,9 @@ struct leiden_graph {
   KTimer kt;
   DecideStreams dstreams{};  // side streams of the decide kernels (created with the handle)
   bool dstreams_ready = false;
+  ForestState* forest = nullptr;  // a forest of independent graphs, or null
   ~leiden_graph() {
+    delete forest;
     if (dstreams_ready) {
       for (hipStream_t& x : dstreams.aux) (void)hipStreamDestroy(x);
       (void)hipEventDestroy(dstreams.fork);
@@ -562,9 +592,14 @@ leiden_status local_move(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
       ap.parts = G->edge_parts.as<unsigned long long>();
       launch_apply_moves(s, ap, nl, G->mark_items.bytes / 8);
     }
+    if (G->forest) forest_iter_end(s, G->forest->bufs(), tau, li, ro.o.max_iters, ctl);
     CHK(read_ctl(G, s));
     out.iters = li + 1;
     for (uint32_t k = 0; k < P; ++k) out.subrounds += G->hctl->cls_count[k] ? 1 : 0;
+    if (G->forest) {
+      if (G->hctl->f_moving == 0) break;  // every graph met its own stopping rule
+      continue;
+    }
     const double dq = (double)(long long)G->hctl->dq_fixed / 72057594037927936.0;
     if (dq <= tau) break;
   }
@@ -655,6 +690,13 @@ leiden_status run_pass(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, L
   if (refined) CHK(refine<W>(G, s, g, nl, L, ro, qc, bins, maxdeg));
   if (st && pass == 0) st->refined_first_pass = refined ? 1 : 0;
   if (pass == 0) G->run_refined0 = refined;
+  if (G->forest) {
+    // every graph by its own iteration count and refinement flag
+    forest_pass_end(s, G->forest->bufs(), pass, dctl(G));
+    CHK(read_ctl(G, s));
+    *stop = G->hctl->f_live == 0;
+    return LEIDEN_OK;
+  }
   *stop = (po.iters <= 1 && !refined) || (po.iters <= 1 && pass > 0);
   return LEIDEN_OK;
 }
@@ -668,6 +710,17 @@ leiden_status next_level(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
   uint64_t nc = 0;
   CHK(read_dev(s, &nc, total));
   launch_lookup(s, G->Ctop.as<uint32_t>(), L.C, G->n);
+  if (ForestState* FS = G->forest) {
+    // the next level's graphs: first super-vertices and the graph of each
+    const bool toA = FS->cur_gid != FS->gidA.as<uint32_t>();
+    uint32_t* nb = toA ? FS->baseA.as<uint32_t>() : FS->baseB.as<uint32_t>();
+    uint32_t* ng = toA ? FS->gidA.as<uint32_t>() : FS->gidB.as<uint32_t>();
+    forest_next_base(s, FS->nq, nl, FS->cur_base, G->newid.as<uint64_t>(), total, nb);
+    forest_gid(s, (uint32_t)nc, FS->nq, nb, ng);
+    forest_bind(s, dctl(G), FS->bufs(), ng, nb);
+    FS->cur_gid = ng;
+    FS->cur_base = nb;
+  }
   Buf& bs = useA ? G->lvA_start : G->lvB_start;
   Buf& bl = useA ? G->lvA_len : G->lvB_len;
   Buf& bc = useA ? G->lvA_cols : G->lvB_cols;
@@ -724,6 +777,15 @@ leiden_status run_leiden(leiden_graph* G, hipStream_t s, LevelState& L, const Ru
   iota_u32(s, G->Ctop.as<uint32_t>(), n);
   G->run_passes = 0;
   G->run_refined0 = false;
+  if (ForestState* FS = G->forest) {
+    // per-graph constants come from forest_prepare; graphs without edges
+    // take no part, and their vertices stay alone
+    FS->cur_gid = FS->gid0.as<uint32_t>();
+    FS->cur_base = FS->base0.as<uint32_t>();
+    forest_start(s, FS->bufs(), dctl(G));
+    forest_bind(s, dctl(G), FS->bufs(), FS->cur_gid, FS->cur_base);
+    forest_isolate(s, n, FS->cur_gid, FS->pass.as<uint8_t>(), L.C);
+  }
   if (M2 == 0 || n == 0) {  // no edges: every vertex stays alone
     iota_u32(s, L.C, n);
     return LEIDEN_OK;
@@ -818,6 +880,66 @@ leiden_status modularity_of(leiden_graph* G, hipStream_t s, const uint32_t* C, c
   const double first = (double)h.sigma / m2;
   const double second = (double)T / (m2 * m2);
   *q = first - second;
+  return LEIDEN_OK;
+}
+
+// A forest's per-graph 2m and Eq. 2 constants from the weighted degrees K
+// (the host formula of one graph, per graph).
+leiden_status forest_prepare(leiden_graph* G, hipStream_t s, const int64_t* K) {
+  ForestState* FS = G->forest;
+  const uint32_t nq = FS->nq;
+  fill_u64(s, FS->m2.as<uint64_t>(), 0, nq);
+  forest_sum(s, G->n, FS->gid0.as<uint32_t>(), K, FS->m2.as<unsigned long long>());
+  std::vector<unsigned long long> m2(nq);
+  HIPCHK(hipMemcpyAsync(m2.data(), FS->m2.p, 8 * (size_t)nq, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<double> inv(2 * (size_t)nq, 0.0);
+  for (uint32_t q = 0; q < nq; ++q) {
+    if (!m2[q]) continue;
+    const QConst c = make_qconst(m2[q]);
+    inv[2 * (size_t)q] = c.inv_m;
+    inv[2 * (size_t)q + 1] = c.inv_2m2;
+  }
+  HIPCHK(hipMemcpyAsync(FS->inv.p, inv.data(), 16 * (size_t)nq, hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return LEIDEN_OK;
+}
+
+// Per-graph results of a forest call: passes and iteration counts of the run
+// (when `ran`), and Eq. 1 of every graph under the forest labels C (NaN when
+// modularity is not asked for).
+leiden_status forest_collect(leiden_graph* G, hipStream_t s, bool ran, const uint32_t* C, const int64_t* K,
+                             bool modularity) {
+  ForestState* FS = G->forest;
+  const uint32_t nq = FS->nq;
+  if (ran) {
+    FS->passes_h.assign(nq, 0);
+    FS->iters_h.assign((size_t)kForestIterHist * nq, 0);
+    HIPCHK(hipMemcpyAsync(FS->passes_h.data(), FS->passes.p, 4 * (size_t)nq, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(FS->iters_h.data(), FS->iters_hist.p, 4 * (size_t)kForestIterHist * nq,
+                          hipMemcpyDeviceToHost, s));
+  }
+  FS->q.assign(nq, std::numeric_limits<double>::quiet_NaN());
+  std::vector<unsigned long long> parts;
+  if (modularity) {
+    forest_modularity_parts(s, rows0(G), G->n, nq, C, K, FS->gid0.as<uint32_t>(), G->sig.as<int64_t>(),
+                            FS->parts.as<unsigned long long>());
+    parts.resize(4 * (size_t)nq);
+    HIPCHK(hipMemcpyAsync(parts.data(), FS->parts.p, 32 * (size_t)nq, hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  for (uint32_t q = 0; q < nq && modularity; ++q) {
+    const unsigned long long M2 = parts[3 * (size_t)nq + q];
+    if (M2 == 0) {
+      FS->q[q] = 0.0;
+      continue;
+    }
+    const unsigned __int128 T = ((unsigned __int128)parts[nq + (size_t)q] << 64) | parts[2 * (size_t)nq + q];
+    const double m2 = (double)M2;
+    const double first = (double)parts[q] / m2;
+    const double second = (double)T / (m2 * m2);
+    FS->q[q] = first - second;
+  }
   return LEIDEN_OK;
 }
 
@@ -1154,6 +1276,91 @@ void leiden_graph_destroy(leiden_graph* g) {
   delete g;
 }
 
+leiden_status leiden_forest_create(int device, uint32_t n_graphs, const uint32_t* graph_vertices, uint64_t nnz,
+                                   const int64_t* offsets, const uint32_t* cols, const uint32_t* w, int on_device,
+                                   double slack, leiden_graph** out) {
+  g_err.clear();
+  if (!out) return fail(LEIDEN_EINVAL, "null output handle");
+  *out = nullptr;
+  if (n_graphs == 0 || !graph_vertices) return fail(LEIDEN_EINVAL, "a forest needs at least one graph");
+  std::vector<uint32_t> first(n_graphs + 1, 0);
+  uint64_t n = 0;
+  for (uint32_t q = 0; q < n_graphs; ++q) {
+    if (graph_vertices[q] == 0) return fail(LEIDEN_EINVAL, "graph %u has no vertices", q);
+    first[q] = (uint32_t)n;
+    n += graph_vertices[q];
+    if (n >= 0xFFFFFFFFull) return fail(LEIDEN_EINVAL, "too many vertices");
+  }
+  first[n_graphs] = (uint32_t)n;
+  leiden_graph* G = nullptr;
+  CHK(leiden_graph_create(device, (uint32_t)n, nnz, offsets, cols, w, on_device, slack, &G));
+  ForestState* FS = new ForestState();
+  G->forest = FS;
+  FS->nq = n_graphs;
+  FS->first = first;
+  auto bail = [&](leiden_status st) {
+    leiden_graph_destroy(G);
+    return st;
+  };
+  const size_t nn = std::max<uint64_t>(n, 1), nb = (size_t)n_graphs + 1;
+  leiden_status st;
+  if ((st = FS->gid0.reserve(nn * 4)) || (st = FS->gidA.reserve(nn * 4)) || (st = FS->gidB.reserve(nn * 4)) ||
+      (st = FS->base0.reserve(nb * 4)) || (st = FS->baseA.reserve(nb * 4)) || (st = FS->baseB.reserve(nb * 4)) ||
+      (st = FS->m2.reserve(nb * 8)) || (st = FS->inv.reserve(nb * 16)) || (st = FS->dq.reserve(nb * 8)) ||
+      (st = FS->move.reserve(nb)) || (st = FS->pass.reserve(nb)) || (st = FS->refined.reserve(nb)) ||
+      (st = FS->cur_iters.reserve(nb * 4)) || (st = FS->passes.reserve(nb * 4)) ||
+      (st = FS->iters_hist.reserve(nb * 4 * kForestIterHist)) || (st = FS->parts.reserve(nb * 32)) ||
+      (st = FS->out_local.reserve(nn * 4)))
+    return bail(st);
+  hipStream_t s = G->own;
+  if (hipMemcpyAsync(FS->base0.p, first.data(), nb * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+    return bail(fail(LEIDEN_EDEVICE, "copy"));
+  forest_gid(s, (uint32_t)n, n_graphs, FS->base0.as<uint32_t>(), FS->gid0.as<uint32_t>());
+  unsigned int* fl = (unsigned int*)(G->small.as<uint64_t>() + 300);
+  fill_u32(s, fl, 0, 1);
+  forest_check_rows(s, rows0(G), (uint32_t)n, FS->gid0.as<uint32_t>(), FS->base0.as<uint32_t>(), fl);
+  unsigned int f = 0;
+  if (hipMemcpyAsync(&f, fl, 4, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+    return bail(fail(LEIDEN_EDEVICE, "forest check failed"));
+  if (f) return bail(fail(LEIDEN_EINVAL, "an entry joins vertices of two graphs of the forest"));
+  *out = G;
+  return LEIDEN_OK;
+}
+
+leiden_status leiden_forest_results(leiden_graph* G, double* q, uint32_t* passes, uint32_t* iters) {
+  g_err.clear();
+  if (!G) return fail(LEIDEN_EINVAL, "null handle");
+  ForestState* FS = G->forest;
+  if (!FS) return fail(LEIDEN_EINVAL, "not a forest");
+  const uint32_t nq = FS->nq;
+  if (q) {
+    if (FS->q.size() != nq) return fail(LEIDEN_ESTATE, "no forest call yet");
+    std::memcpy(q, FS->q.data(), 8 * (size_t)nq);
+  }
+  if (passes || iters) {
+    if (FS->passes_h.size() != nq) return fail(LEIDEN_ESTATE, "no forest run yet");
+    if (passes) std::memcpy(passes, FS->passes_h.data(), 4 * (size_t)nq);
+    // graph-major: iters[q * kForestIterHist + pass]
+    if (iters)
+      for (uint32_t g = 0; g < nq; ++g)
+        for (uint32_t p = 0; p < kForestIterHist; ++p)
+          iters[(size_t)g * kForestIterHist + p] = FS->iters_h[(size_t)p * nq + g];
+  }
+  return LEIDEN_OK;
+}
+
+leiden_status leiden_forest_info(leiden_graph* G, uint32_t* n_graphs, uint32_t* first_vertex) {
+  g_err.clear();
+  if (!G || !n_graphs) return fail(LEIDEN_EINVAL, "null argument");
+  if (!G->forest) {
+    *n_graphs = 0;
+    return LEIDEN_OK;
+  }
+  *n_graphs = G->forest->nq;
+  if (first_vertex) std::memcpy(first_vertex, G->forest->first.data(), 4 * ((size_t)G->forest->nq + 1));
+  return LEIDEN_OK;
+}
+
 leiden_status leiden_graph_nnz(leiden_graph* g, uint64_t* nnz) {
   if (!g || !nnz) return fail(LEIDEN_EINVAL, "null argument");
   *nnz = g->nnz;
@@ -1192,6 +1399,8 @@ leiden_status leiden_static(leiden_graph* G, const leiden_opts* opts, uint32_t* 
   sum_i64(s, L.K, n, m2d);
   unsigned long long M2 = 0;
   CHK(read_dev(s, &M2, m2d));
+  ForestState* FS = G->forest;
+  if (FS) CHK(forest_prepare(G, s, L.K));
   RunOpts ro{o, false, 0, nullptr, true};
   CHK(run_leiden(G, s, L, ro, M2, stats));
   // dense output labels by minimum vertex; new state (C, K, Sigma, DeltaSigma = 0)
@@ -1201,15 +1410,23 @@ leiden_status leiden_static(leiden_graph* G, const leiden_opts* opts, uint32_t* 
   CHK(G->st_dS.reserve((size_t)std::max<uint32_t>(n, 1) * 8));
   uint32_t* out = G->st_C.as<uint32_t>();
   launch_static_relabel(s, G->Ctop.as<uint32_t>(), n, G->tr_minv.as<uint32_t>(), G->flag.as<uint32_t>(),
-                        G->newid.as<uint64_t>(), out, G->scan_tmp.p, G->small.as<uint64_t>() + 64);
+                        G->newid.as<uint64_t>(), out, G->scan_tmp.p, G->small.as<uint64_t>() + 64,
+                        FS ? FS->gid0.as<uint32_t>() : nullptr, FS ? FS->base0.as<uint32_t>() : nullptr);
   launch_row_sums_u32(s, rows0(G), n, G->st_K.as<int64_t>());
   launch_sigma_from(s, out, G->st_K.as<int64_t>(), n, G->st_S.as<int64_t>());
   fill_i64(s, G->st_dS.as<int64_t>(), 0, n);
   G->has_state = true;
   HIPCHK(hipEventRecord(e1, s));
   double q = std::numeric_limits<double>::quiet_NaN();
-  if (o.compute_modularity) CHK(modularity_of(G, s, out, G->st_K.as<int64_t>(), &q));
+  if (FS)
+    CHK(forest_collect(G, s, true, out, G->st_K.as<int64_t>(), o.compute_modularity != 0));
+  else if (o.compute_modularity)
+    CHK(modularity_of(G, s, out, G->st_K.as<int64_t>(), &q));
   HIPCHK(hipEventRecord(e2, s));
+  if (FS) {  // labels inside each graph
+    forest_to_local(s, n, FS->gid0.as<uint32_t>(), FS->base0.as<uint32_t>(), out, FS->out_local.as<uint32_t>());
+    out = FS->out_local.as<uint32_t>();
+  }
   CHK(copy_out(s, membership_out, out, sizeof(uint32_t) * n, out_on_device));
   HIPCHK(hipStreamSynchronize(s));
   if (q_out) *q_out = q;
@@ -1299,6 +1516,13 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
     uint32_t* pm = G->tr_label.as<uint32_t>();
     CHK(copy_in(s, pm, prev_membership, sizeof(uint32_t) * n, prev_on_device));
     unsigned int* fl = (unsigned int*)(G->small.as<uint64_t>() + 300);
+    if (G->forest) {  // labels inside each graph -> forest labels
+      fill_u32(s, fl, 0, 1);
+      forest_to_forest(s, n, G->forest->gid0.as<uint32_t>(), G->forest->base0.as<uint32_t>(), pm, pm, fl);
+      unsigned int f = 0;
+      CHK(read_dev(s, &f, fl));
+      if (f) return fail(LEIDEN_EINVAL, "prev_membership has a label not below its graph's vertex count");
+    }
     label_check(s, pm, G->has_state ? Cprev : nullptr, n, fl);
     unsigned int f = 0;
     CHK(read_dev(s, &f, fl));
@@ -1310,6 +1534,14 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   uint32_t* din = G->bt_in.as<uint32_t>();
   CHK(copy_in(s, din, del, sizeof(uint32_t) * 2 * n_del, batch_on_device));
   CHK(copy_in(s, din + 2 * n_del, ins, sizeof(uint32_t) * 3 * n_ins, batch_on_device));
+  if (G->forest) {
+    unsigned int* fl = (unsigned int*)(G->small.as<uint64_t>() + 300);
+    fill_u32(s, fl, 0, 1);
+    forest_check_batch(s, din, n_del, din + 2 * n_del, n_ins, n, G->forest->gid0.as<uint32_t>(), fl);
+    unsigned int f = 0;
+    CHK(read_dev(s, &f, fl));
+    if (f) return fail(LEIDEN_EINVAL, "invalid batch: a pair joins vertices of two graphs of the forest");
+  }
   BatchBufs bb{};
   bb.src = G->bt_src.as<uint32_t>();
   bb.dst = G->bt_dst.as<uint32_t>();
@@ -1407,6 +1639,12 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   sum_i64(s, L.K, n, m2d);
   unsigned long long M2 = 0;
   CHK(read_dev(s, &M2, m2d));
+  ForestState* FS = G->forest;
+  if (FS) {
+    CHK(forest_prepare(G, s, L.K));
+    bb.f_gid = FS->gid0.as<uint32_t>();
+    bb.f_inv = FS->inv.as<double>();
+  }
   // vertex marking (first pass): the first unprocessed list goes to next_list
   RunOpts ro{o, true, (int)mode, nullptr, false};
   const uint32_t first_stamp = G->stamp + 1;
@@ -1462,6 +1700,10 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   tb.wcom = G->tr_wcom.as<int64_t>();
   tb.owners = G->tr_owners.as<uint32_t>();
   tb.owner_count = (unsigned int*)(G->small.as<uint64_t>() + 320);
+  if (FS) {
+    tb.f_gid = FS->gid0.as<uint32_t>();
+    tb.f_base = FS->base0.as<uint32_t>();
+  }
   if (G->tr_clean != G->tr_hk.p) {  // a fresh pair table starts empty; each call leaves it empty
     fill_u64(s, (uint64_t*)G->tr_hk.p, ~0ull, tb.hmask + 1);
     fill_u64(s, (uint64_t*)G->tr_hv.p, 0, tb.hmask + 1);
@@ -1482,9 +1724,18 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   G->has_state = true;
   HIPCHK(hipEventRecord(e2, s));
   double q = std::numeric_limits<double>::quiet_NaN();
-  if (o.compute_modularity) CHK(modularity_of(G, s, G->st_C.as<uint32_t>(), G->st_K.as<int64_t>(), &q));
+  if (FS)
+    CHK(forest_collect(G, s, true, G->st_C.as<uint32_t>(), G->st_K.as<int64_t>(), o.compute_modularity != 0));
+  else if (o.compute_modularity)
+    CHK(modularity_of(G, s, G->st_C.as<uint32_t>(), G->st_K.as<int64_t>(), &q));
   HIPCHK(hipEventRecord(e3, s));
-  CHK(copy_out(s, membership_out, G->st_C.p, sizeof(uint32_t) * n, out_on_device));
+  const void* res = G->st_C.p;
+  if (FS) {  // labels inside each graph
+    forest_to_local(s, n, FS->gid0.as<uint32_t>(), FS->base0.as<uint32_t>(), G->st_C.as<uint32_t>(),
+                    FS->out_local.as<uint32_t>());
+    res = FS->out_local.p;
+  }
+  CHK(copy_out(s, membership_out, res, sizeof(uint32_t) * n, out_on_device));
   HIPCHK(hipStreamSynchronize(s));
   if (q_out) *q_out = q;
   if (stats) {
@@ -1528,12 +1779,24 @@ leiden_status leiden_modularity(leiden_graph* G, const uint32_t* membership, int
   if (f & 1) return fail(LEIDEN_EINVAL, "membership has a label >= n");
   int64_t* K = G->K.as<int64_t>();
   launch_row_sums_u32(s, rows0(G), n, K);
+  if (ForestState* FS = G->forest) {
+    // labels inside each graph; the per-graph values go to leiden_forest_results
+    CHK(copy_in(s, C, membership, sizeof(uint32_t) * n, on_device));
+    fill_u32(s, fl, 0, 1);
+    forest_to_forest(s, n, FS->gid0.as<uint32_t>(), FS->base0.as<uint32_t>(), C, C, fl);
+    CHK(read_dev(s, &f, fl));
+    if (f) return fail(LEIDEN_EINVAL, "membership has a label not below its graph's vertex count");
+    CHK(forest_collect(G, s, false, C, K, true));
+    *q_out = std::numeric_limits<double>::quiet_NaN();
+    return LEIDEN_OK;
+  }
   return modularity_of(G, s, C, K, q_out);
 }
 
 leiden_status leiden_modularity_noalloc(leiden_graph* G, const uint32_t* membership, void* stream, double* q_out) {
   g_err.clear();
   if (!G || !membership || !q_out) return fail(LEIDEN_EINVAL, "null argument");
+  if (G->forest) return fail(LEIDEN_EINVAL, "forests report modularity per graph (leiden_modularity)");
   if (G->n > kNoAllocMaxN)
     return fail(LEIDEN_EINVAL, "n = %u exceeds the %u vertices of the scratch array", G->n, kNoAllocMaxN);
   HIPCHK(hipSetDevice(G->device));
@@ -1576,6 +1839,7 @@ leiden_status leiden_graph_export(leiden_graph* G, int64_t* offsets_out, uint32_
 leiden_status leiden_state_export(leiden_graph* G, uint32_t* C, int64_t* K, int64_t* Sigma, int64_t* dSigma) {
   g_err.clear();
   if (!G) return fail(LEIDEN_EINVAL, "null handle");
+  if (G->forest) return fail(LEIDEN_EINVAL, "state export is for single graphs");
   if (!G->has_state) return fail(LEIDEN_ESTATE, "no state yet");
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = G->own;
@@ -1592,6 +1856,7 @@ leiden_status leiden_state_import(leiden_graph* G, const uint32_t* C, const int6
                                   const int64_t* dSigma) {
   g_err.clear();
   if (!G || !C || !K || !Sigma || !dSigma) return fail(LEIDEN_EINVAL, "null argument");
+  if (G->forest) return fail(LEIDEN_EINVAL, "state import is for single graphs");
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = G->own;
   const uint32_t n = G->n;

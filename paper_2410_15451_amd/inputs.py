@@ -36,6 +36,12 @@ stand in for them):
     its neighbours; symmetrised by union; weight
     clamp(1 + floor(100 exp(-d^2 / D)), 1, 100) with D the median neighbour d^2;
     many such graphs with vertex counts log-uniform in a range;
+  * kNN-style forests at full size (4,096 graphs of 10^3..2*10^5 vertices) are
+    made on the device by ``knn_forest_torch`` with the same point and weight
+    recipe, except that the 32 candidates of a point are the nearest among the
+    64 points around it in the order of (bucket, a random projection) rather
+    than among its whole bucket, and the weight is 1 + floor(99 D / (D + d^2))
+    (integer arithmetic);
   * temporal stream (stands in for the SNAP temporal graphs of the paper's
     real-world experiment): the distinct undirected edges of an R-MAT graph in
     a seeded random arrival order; the first 90% form the initial graph and
@@ -338,6 +344,127 @@ def knn_forest(count: int, n_min: int = 1000, n_max: int = 200000, seed: int = B
     rng = rng_for(seed)
     ns = np.round(np.exp(rng.uniform(np.log(n_min), np.log(n_max), count))).astype(np.int64)
     return [knn_graph(int(x), seed=seed + 1 + i) for i, x in enumerate(ns)]
+
+
+def knn_graph_torch(n: int, seed: int, device, k: int = 15, dim: int = 16, cand: int = 32, window: int = 32):
+    """kNN-style graph made with torch on ``device`` (recipe in the module
+    docstring); returns (offs int64[n+1], cols int32[nnz], w int32[nnz]) tensors
+    on the device (int32 holds the uint32 values of this size range)."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    f64 = torch.float64
+    X = torch.round(torch.randn((n, dim), generator=g, device=device, dtype=f64) * 256.0)
+    nproj = max(0, int(np.ceil(np.log2(max(n, 1) / 512.0))))
+    R = torch.randn((dim, nproj + 1), generator=g, device=device, dtype=f64)
+    P = X @ R
+    bucket = torch.zeros(n, dtype=torch.int64, device=device)
+    for b in range(nproj):
+        bucket |= (P[:, b] > 0).to(torch.int64) << b
+    # order by bucket, then by the last projection inside the bucket
+    proj_rank = torch.argsort(P[:, nproj], stable=True)
+    order = proj_rank[torch.argsort(bucket[proj_rank], stable=True)]
+    bs = bucket[order]
+    offs_w = torch.cat([torch.arange(-window, 0, device=device), torch.arange(1, window + 1, device=device)])
+    pos = torch.arange(n, device=device)
+    jpos = pos[:, None] + offs_w[None, :]
+    ok = (jpos >= 0) & (jpos < n)
+    jpos = jpos.clamp(0, max(n - 1, 0))
+    ok &= bs[jpos] == bs[:, None]
+    i_id = order
+    j_id = order[jpos]
+    d2 = ((X[i_id][:, None, :] - X[j_id]) ** 2).sum(dim=2)  # exact: integer values below 2^53
+    big = float(2 ** 52)
+    key = torch.where(ok, d2 * (2 * window) + torch.arange(2 * window, device=device, dtype=f64)[None, :], big)
+    c = min(cand, 2 * window)
+    near = torch.topk(key, c, dim=1, largest=False).indices
+    near_ok = torch.gather(key, 1, near) < big
+    pick = min(k, c)
+    rnd = torch.rand((n, c), generator=g, device=device, dtype=f64)
+    rnd = torch.where(near_ok, rnd, 2.0)
+    sel = torch.topk(rnd, pick, dim=1, largest=False).indices
+    nb = torch.gather(near, 1, sel)
+    valid = torch.gather(near_ok, 1, sel)
+    u = i_id[:, None].expand(-1, pick)[valid]
+    v = torch.gather(j_id, 1, nb)[valid]
+    dd = torch.gather(d2, 1, nb)[valid].to(torch.int64)
+    lo, hi = torch.minimum(u, v), torch.maximum(u, v)
+    ekey = lo * n + hi
+    ekey, perm = torch.sort(ekey, stable=True)
+    dd = dd[perm]
+    first = torch.ones_like(ekey, dtype=torch.bool)
+    if ekey.numel() > 1:
+        first[1:] = ekey[1:] != ekey[:-1]
+    ekey, dd = ekey[first], dd[first]
+    D = int(torch.median(dd).item()) if dd.numel() else 1
+    D = max(D, 1)
+    w = 1 + (99 * D) // (D + dd)
+    lo, hi = ekey // n, ekey % n
+    src = torch.cat([lo, hi])
+    dst = torch.cat([hi, lo])
+    ww = torch.cat([w, w])
+    o2 = torch.argsort(src * n + dst)
+    src, dst, ww = src[o2], dst[o2], ww[o2]
+    offs = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    offs[1:] = torch.cumsum(torch.bincount(src, minlength=n), 0)
+    return offs, dst.to(torch.int32), ww.to(torch.int32)
+
+
+def forest_sizes(count: int, n_min: int = 1000, n_max: int = 200000, seed: int = BASE_SEED + 4) -> np.ndarray:
+    """Vertex counts log-uniform in [n_min, n_max] (uint32[count])."""
+    rng = rng_for(seed)
+    return np.round(np.exp(rng.uniform(np.log(n_min), np.log(n_max), count))).astype(np.uint32)
+
+
+def knn_forest_torch(sizes, device, seed: int = BASE_SEED + 5, progress=None):
+    """The block-diagonal CSR of kNN-style graphs with the given vertex counts,
+    made on ``device``: (offs int64[N+1], cols int32[nnz], w int32[nnz]) with
+    graph q on vertices first_q .. first_q + sizes[q] - 1 (graph q from seed +
+    q).  ``progress(q)`` is called after every 256 graphs."""
+    import torch
+
+    offs_l, cols_l, w_l = [], [], []
+    vbase, ebase = 0, 0
+    for q, nq in enumerate(np.asarray(sizes, np.int64)):
+        o, c, w = knn_graph_torch(int(nq), seed + q, device)
+        offs_l.append(o[:-1] + ebase)
+        cols_l.append(c + vbase)
+        w_l.append(w)
+        vbase += int(nq)
+        ebase += int(c.numel())
+        if progress and (q + 1) % 256 == 0:
+            progress(q + 1)
+    offs_l.append(torch.tensor([ebase], dtype=torch.int64, device=device))
+    return torch.cat(offs_l), torch.cat(cols_l), torch.cat(w_l)
+
+
+def forest_graph(offs, cols, w, first, q: int) -> Csr:
+    """Graph q of a forest CSR (host numpy or torch arrays) as a Csr with its own vertex IDs."""
+    a, b = int(first[q]), int(first[q + 1])
+    o = np.asarray(offs[a:b + 1].cpu() if hasattr(offs, "cpu") else offs[a:b + 1], np.int64)
+    e0, e1 = int(o[0]), int(o[-1])
+    c = cols[e0:e1]
+    ww = w[e0:e1]
+    c = np.asarray(c.cpu() if hasattr(c, "cpu") else c).astype(np.int64) - a
+    ww = np.asarray(ww.cpu() if hasattr(ww, "cpu") else ww).astype(np.uint32)
+    return Csr(b - a, o - e0, c.astype(np.uint32), ww)
+
+
+def forest_csr(graphs):
+    """The block-diagonal forest CSR of host Csr graphs: (sizes uint32[q], Csr)."""
+    sizes = np.array([g.n for g in graphs], np.uint32)
+    first = np.zeros(len(graphs) + 1, np.int64)
+    np.cumsum(sizes, out=first[1:])
+    offs, cols, w = [np.zeros(1, np.int64)], [], []
+    e = 0
+    for g, f in zip(graphs, first):
+        offs.append(g.offs[1:] + e)
+        cols.append(g.cols.astype(np.int64) + f)
+        w.append(g.w)
+        e += g.nnz
+    return sizes, Csr(int(first[-1]), np.concatenate(offs), np.concatenate(cols).astype(np.uint32),
+                      np.concatenate(w).astype(np.uint32))
 
 
 def temporal_stream(scale: int, seed: int = BASE_SEED + 7, preload: float = 0.9):

@@ -281,8 +281,10 @@ def test_rmat22_benchmark_configuration(lm, orc):
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rmat22_df.json")
     with open(path) as f:
         gold = json.load(f)
+    import sys
     g = inputs.rmat(22, seed=inputs.BASE_SEED + 2)
     assert (g.n, g.nnz) == (gold["n"], gold["nnz"])
+    print("rmat22: graph made", file=sys.stderr, flush=True)
     G = _graph(lm, g)
     dev = torch.device("cuda:0")
     out = torch.zeros(g.n, dtype=torch.int32, device=dev)
@@ -291,6 +293,7 @@ def test_rmat22_benchmark_configuration(lm, orc):
     assert _digest(C0) == gold["static"]["membership_sha256"]
     assert r0.q == gold["static"]["q"]
     assert r0.stats["passes"] == gold["static"]["passes"] and r0.stats["iters"] == gold["static"]["iters"]
+    print("rmat22: static checked", file=sys.stderr, flush=True)
     nb = inputs.batch_size_for(g.nnz, 1e-3)
     assert nb == gold["batch_undirected_updates"]
     (dels, ins), _ = inputs.random_batch_stream(g.n, g.undirected_keys(), nb, 2, seed=inputs.BASE_SEED + 2 + 1000)
@@ -302,6 +305,7 @@ def test_rmat22_benchmark_configuration(lm, orc):
     assert r1.q == gold["df"]["q"]
     assert r1.stats["passes"] == gold["df"]["passes"] and r1.stats["iters"] == gold["df"]["iters"]
     assert r1.stats["affected"] == gold["df"]["affected"]
+    print("rmat22: update checked", file=sys.stderr, flush=True)
     # the updated graph, entry by entry
     gt, _ = orc.apply_batch(g, dels, ins)
     offs, cols, w = G.export()
