@@ -363,6 +363,21 @@ void forest_bind(hipStream_t s, Ctl* ctl, const ForestBufs& f, const uint32_t* g
                      (const uint8_t*)f.move, (const uint8_t*)f.pass, f.refined);
 }
 
+// Row lengths for aggregation: zero for the vertices of graphs that left the
+// pass loop.  Their communities still become super-vertices (the lookup of
+// their vertices goes through every level), but without entries: nothing of
+// such a graph moves again, so its level graphs need no edges, and a forest
+// whose graphs stop after different passes aggregates only the live ones.
+__global__ __launch_bounds__(kBlock) void k_forest_live_len(uint32_t n, const uint32_t* gid, const uint8_t* pass,
+                                                            const uint32_t* len, uint32_t* out) {
+  GRID_STRIDE(v, n) out[v] = pass[gid[v]] ? len[v] : 0u;
+}
+
+void forest_live_len(hipStream_t s, uint32_t n, const uint32_t* gid, const uint8_t* pass, const uint32_t* len,
+                     uint32_t* out) {
+  if (n) hipLaunchKernelGGL(k_forest_live_len, dim3(grid_n(n)), dim3(kBlock), 0, s, n, gid, pass, len, out);
+}
+
 // Vertices of graphs without edges stay alone (as a graph without edges does).
 __global__ __launch_bounds__(kBlock) void k_forest_isolate(uint32_t n, const uint32_t* gid, const uint8_t* pass,
                                                            uint32_t* C) {

@@ -340,6 +340,8 @@ void forest_iter_end(hipStream_t s, const ForestBufs& f, double tau, uint32_t li
 void forest_pass_end(hipStream_t s, const ForestBufs& f, uint32_t pass, Ctl* ctl);
 void forest_bind(hipStream_t s, Ctl* ctl, const ForestBufs& f, const uint32_t* gid, const uint32_t* base);
 void forest_isolate(hipStream_t s, uint32_t n, const uint32_t* gid, const uint8_t* pass, uint32_t* C);
+void forest_live_len(hipStream_t s, uint32_t n, const uint32_t* gid, const uint8_t* pass, const uint32_t* len,
+                     uint32_t* out);
 
 // Per-launch timing of one kernel with HIP events on the launch stream.  The
 // runtime points tl_ktimer at the handle's timer for the duration of a call

@@ -42,28 +42,63 @@ leiden_status fail(leiden_status st, const char* fmt, ...) {
     if (s_ != LEIDEN_OK) return s_;            \
   } while (0)
 
+// The stream of the current API call on this thread (null outside calls).
+// Device buffers grow stream-ordered on it: the old block is released after
+// the work queued on the stream (the call's side streams are joined back into
+// it before host code runs again), so growing one handle's buffer waits
+// neither for the host nor for other handles' calls on other streams.
+thread_local hipStream_t tl_alloc_stream = nullptr;
+
+struct AllocScope {
+  hipStream_t prev;
+  explicit AllocScope(hipStream_t s) : prev(tl_alloc_stream) { tl_alloc_stream = s; }
+  ~AllocScope() { tl_alloc_stream = prev; }
+};
+
+// Stream-ordered allocation is used where the device supports memory pools.
+bool pools_supported() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMemoryPoolsSupported, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return v != 0;
+}
+
 // Device allocation owned by the handle; grows on demand, never shrinks.
 struct Buf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool pooled = false;  // from the stream-ordered allocator
   ~Buf() {
-    if (p) (void)hipFree(p);
+    // handles are destroyed rarely: wait for the device, then release at once
+    if (p && pooled) (void)hipDeviceSynchronize();
+    release(nullptr);
+  }
+  void release(hipStream_t s) {
+    if (!p) return;
+    if (pooled)
+      (void)hipFreeAsync(p, s);
+    else
+      (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
   }
   leiden_status reserve(size_t b) {
     if (b <= bytes) return LEIDEN_OK;
-    // kernels queued earlier on any stream may still read the old block
-    if (p) {
-      (void)hipDeviceSynchronize();
-      (void)hipFree(p);
-    }
-    p = nullptr;
-    bytes = 0;
+    static const bool pools = pools_supported();
+    hipStream_t s = pools ? tl_alloc_stream : nullptr;
+    if (p && !s) (void)hipDeviceSynchronize();  // kernels queued earlier on any stream may still read it
+    release(s);
     size_t want = std::max<size_t>(b, 256);
-    if (hipMalloc(&p, want) != hipSuccess) {
+    const hipError_t e = s ? hipMallocAsync(&p, want, s) : hipMalloc(&p, want);
+    if (e != hipSuccess) {
       (void)hipGetLastError();
       p = nullptr;
       return fail(LEIDEN_ENOMEM, "device allocation of %zu bytes failed", want);
     }
+    pooled = s != nullptr;
     bytes = want;
     return LEIDEN_OK;
   }
@@ -101,7 +136,7 @@ struct ForestState {
   Buf gidA, baseA, gidB, baseB; // level graphs' (alternating)
   const uint32_t* cur_gid = nullptr;
   const uint32_t* cur_base = nullptr;
-  Buf m2, inv, dq, move, pass, refined, cur_iters, passes, iters_hist, parts, out_local;
+  Buf m2, inv, dq, move, pass, refined, cur_iters, passes, iters_hist, parts, out_local, live_len;
   // results of the last call
   std::vector<double> q;
   std::vector<uint32_t> passes_h, iters_h;
@@ -277,7 +312,7 @@ leiden_status ensure_workspace(leiden_graph* G, hipStream_t s, uint32_t classes)
   const size_t n = std::max<size_t>(G->n, 1);
   uint64_t nnz = std::max<uint64_t>(G->nnz, 1);
   if (G->ws_n >= n && G->ws_nnz >= nnz && G->ws_classes >= classes) return LEIDEN_OK;
-  if (G->ws_nnz) nnz += nnz / 4;  // the graph grew: leave room for further growth
+  nnz += nnz / 4;  // room for the graph to grow by insertions
   const size_t u32 = 4, u64 = 8;
   CHK(G->C.reserve(n * u32));
   CHK(G->K.reserve(n * u64));
@@ -340,8 +375,10 @@ leiden_status ensure_workspace(leiden_graph* G, hipStream_t s, uint32_t classes)
   CHK(G->agg_mat.reserve((scap + scap / 1024 + 4096) * 2));
   const uint64_t hslots = next_pow2(2 * n);
   CHK(G->tr_minv.reserve(n * u32));
+  const size_t hk_bytes = G->tr_hk.bytes;
   CHK(G->tr_hk.reserve(hslots * u64));
   CHK(G->tr_hv.reserve(hslots * u64));
+  if (G->tr_hk.bytes != hk_bytes) G->tr_clean = nullptr;  // a new pair table (perhaps at the old address)
   CHK(G->tr_bw.reserve(n * u64));
   CHK(G->tr_bv.reserve(n * u32));
   CHK(G->tr_cw.reserve(n * u64));
@@ -711,6 +748,9 @@ leiden_status next_level(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
   CHK(read_dev(s, &nc, total));
   launch_lookup(s, G->Ctop.as<uint32_t>(), L.C, G->n);
   if (ForestState* FS = G->forest) {
+    // graphs that left the pass loop are aggregated without their entries
+    forest_live_len(s, nl, FS->cur_gid, FS->pass.as<uint8_t>(), g.len, FS->live_len.as<uint32_t>());
+    g.len = FS->live_len.as<uint32_t>();
     // the next level's graphs: first super-vertices and the graph of each
     const bool toA = FS->cur_gid != FS->gidA.as<uint32_t>();
     uint32_t* nb = toA ? FS->baseA.as<uint32_t>() : FS->baseB.as<uint32_t>();
@@ -1058,6 +1098,7 @@ leiden_status probe_decide(leiden_graph* G, hipStream_t s, const leiden_opts& o,
 // Level-0 degree bins after a change of thresholds.
 leiden_status refresh_bins0(leiden_graph* G) {
   hipStream_t s = G->own;
+  AllocScope alloc_scope(s);
   CHK(level_bins(G, s, G->g.len, G->n, G->bins0, &G->maxdeg0));
   HIPCHK(hipStreamSynchronize(s));
   return LEIDEN_OK;
@@ -1138,6 +1179,7 @@ leiden_status leiden_autotune(leiden_graph* G, const leiden_opts* opts, leiden_t
   CHK(check_opts(o));
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = stream_of(G, opts);
+  AllocScope alloc_scope(s);
   CHK(ensure_workspace(G, s, std::max(o.move_classes, o.refine_rounds)));
   const uint32_t n = G->n;
   // singleton start on the input graph
@@ -1221,6 +1263,7 @@ leiden_status leiden_graph_create(int device, uint32_t n, uint64_t nnz, const in
     G->dstreams_ready = true;
   }
   hipStream_t s = G->own;
+  AllocScope alloc_scope(s);
   leiden_status st;
   // upload the input CSR
   Buf in_offs, in_cols, in_w;
@@ -1310,9 +1353,10 @@ leiden_status leiden_forest_create(int device, uint32_t n_graphs, const uint32_t
       (st = FS->move.reserve(nb)) || (st = FS->pass.reserve(nb)) || (st = FS->refined.reserve(nb)) ||
       (st = FS->cur_iters.reserve(nb * 4)) || (st = FS->passes.reserve(nb * 4)) ||
       (st = FS->iters_hist.reserve(nb * 4 * kForestIterHist)) || (st = FS->parts.reserve(nb * 32)) ||
-      (st = FS->out_local.reserve(nn * 4)))
+      (st = FS->out_local.reserve(nn * 4)) || (st = FS->live_len.reserve(nn * 4)))
     return bail(st);
   hipStream_t s = G->own;
+  AllocScope alloc_scope(s);
   if (hipMemcpyAsync(FS->base0.p, first.data(), nb * 4, hipMemcpyHostToDevice, s) != hipSuccess)
     return bail(fail(LEIDEN_EDEVICE, "copy"));
   forest_gid(s, (uint32_t)n, n_graphs, FS->base0.as<uint32_t>(), FS->gid0.as<uint32_t>());
@@ -1377,6 +1421,7 @@ leiden_status leiden_static(leiden_graph* G, const leiden_opts* opts, uint32_t* 
   CHK(check_opts(o));
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = stream_of(G, opts);
+  AllocScope alloc_scope(s);
   if (stats) std::memset(stats, 0, sizeof(*stats));
   KtScope kts(G, o.timed_kernel);
   CHK(ensure_workspace(G, s, std::max(o.move_classes, o.refine_rounds)));
@@ -1467,6 +1512,7 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
     return fail(LEIDEN_ESTATE, "no previous memberships: run leiden_static or pass prev_membership");
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = stream_of(G, opts);
+  AllocScope alloc_scope(s);
   if (stats) std::memset(stats, 0, sizeof(*stats));
   KtScope kts(G, o.timed_kernel);
   const uint32_t n = G->n;
@@ -1768,6 +1814,7 @@ leiden_status leiden_modularity(leiden_graph* G, const uint32_t* membership, int
   if (!G || !membership || !q_out) return fail(LEIDEN_EINVAL, "null argument");
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = G->own;
+  AllocScope alloc_scope(s);
   CHK(ensure_workspace(G, s, 8));
   const uint32_t n = G->n;
   uint32_t* C = G->C.as<uint32_t>();
@@ -1801,6 +1848,7 @@ leiden_status leiden_modularity_noalloc(leiden_graph* G, const uint32_t* members
     return fail(LEIDEN_EINVAL, "n = %u exceeds the %u vertices of the scratch array", G->n, kNoAllocMaxN);
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = stream ? (hipStream_t)stream : G->own;
+  AllocScope alloc_scope(s);
   const int rc = noalloc_modularity(s, G->device, rows0(G), G->n, membership, q_out);
   if (rc == 2) return fail(LEIDEN_EINVAL, "membership has a label >= n");
   if (rc != 0) return fail(LEIDEN_EDEVICE, "modularity without allocation failed");
@@ -1812,6 +1860,7 @@ leiden_status leiden_graph_export(leiden_graph* G, int64_t* offsets_out, uint32_
   if (!G || !offsets_out) return fail(LEIDEN_EINVAL, "null argument");
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = G->own;
+  AllocScope alloc_scope(s);
   const uint32_t n = G->n;
   std::vector<int64_t> start(n);
   std::vector<uint32_t> len(n);
@@ -1843,6 +1892,7 @@ leiden_status leiden_state_export(leiden_graph* G, uint32_t* C, int64_t* K, int6
   if (!G->has_state) return fail(LEIDEN_ESTATE, "no state yet");
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = G->own;
+  AllocScope alloc_scope(s);
   const uint32_t n = G->n;
   CHK(copy_out(s, C, G->st_C.p, sizeof(uint32_t) * n, 0));
   CHK(copy_out(s, K, G->st_K.p, sizeof(int64_t) * n, 0));
@@ -1859,6 +1909,7 @@ leiden_status leiden_state_import(leiden_graph* G, const uint32_t* C, const int6
   if (G->forest) return fail(LEIDEN_EINVAL, "state import is for single graphs");
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = G->own;
+  AllocScope alloc_scope(s);
   const uint32_t n = G->n;
   CHK(ensure_workspace(G, s, 8));
   for (Buf* b : {&G->st_C}) CHK(b->reserve((size_t)std::max<uint32_t>(n, 1) * 4));

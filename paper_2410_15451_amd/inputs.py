@@ -439,6 +439,73 @@ def knn_forest_torch(sizes, device, seed: int = BASE_SEED + 5, progress=None):
     return torch.cat(offs_l), torch.cat(cols_l), torch.cat(w_l)
 
 
+def forest_batch_torch(offs, cols, first, frac: float, seed: int, ins_frac: float = 0.8, w_range=(1, 100)):
+    """A random batch (Section 5.1.4) for every graph of a forest CSR on the
+    device: graph q gets max(1, round(frac * |E_q|)) undirected updates,
+    ins_frac of them insertions of distinct absent pairs of its own vertices
+    (uniform endpoints, weights uniform in w_range) and the rest deletions of
+    distinct existing edges (uniform).  Returns (deletions int32[nd, 2],
+    insertions int32[ni, 3]) in forest vertex IDs on the device."""
+    import torch
+
+    dev = offs.device
+    g = torch.Generator(device=dev)
+    g.manual_seed(int(seed))
+    first_t = torch.as_tensor(np.asarray(first, np.int64), device=dev)
+    nq = first_t.numel() - 1
+    N = int(first_t[-1])
+    sizes = first_t[1:] - first_t[:-1]
+    deg = offs[1:] - offs[:-1]
+    src = torch.repeat_interleave(torch.arange(N, device=dev), deg)
+    dst = cols.to(torch.int64)
+    up = src < dst
+    u, v = src[up], dst[up]
+    del src, dst
+    vg = torch.repeat_interleave(torch.arange(nq, device=dev), sizes)
+    eg = vg[u]
+    e_cnt = torch.bincount(eg, minlength=nq)
+    nb = torch.clamp(torch.round(frac * 2 * e_cnt.to(torch.float64)), min=1).to(torch.int64)
+    n_ins = torch.round(nb.to(torch.float64) * ins_frac).to(torch.int64)
+    n_del = torch.minimum(nb - n_ins, e_cnt)
+    # deletions: the first n_del[q] edges of graph q in a random order
+    r = torch.randint(0, 1 << 40, (u.numel(),), generator=g, device=dev)
+    order = torch.argsort(eg * (1 << 40) + r)
+    seg0 = torch.cumsum(e_cnt, 0) - e_cnt
+    rank = torch.arange(u.numel(), device=dev) - seg0[eg[order]]
+    pick = order[rank < n_del[eg[order]]]
+    dels = torch.stack([u[pick], v[pick]], 1)
+    # insertions: candidate pairs in draw order, minus self-loops, present
+    # edges and repeats; the first n_ins[q] of graph q
+    ekeys = torch.sort(u * N + v).values
+    del u, v, eg, order, r
+    cand = 2 * n_ins + 16
+    cg = torch.repeat_interleave(torch.arange(nq, device=dev), cand)
+    a = first_t[cg] + (torch.rand(cg.numel(), generator=g, device=dev, dtype=torch.float64) * sizes[cg]).to(torch.int64)
+    b = first_t[cg] + (torch.rand(cg.numel(), generator=g, device=dev, dtype=torch.float64) * sizes[cg]).to(torch.int64)
+    a = torch.minimum(a, first_t[cg] + sizes[cg] - 1)
+    b = torch.minimum(b, first_t[cg] + sizes[cg] - 1)
+    lo, hi = torch.minimum(a, b), torch.maximum(a, b)
+    k = lo * N + hi
+    ok = lo != hi
+    pos = torch.searchsorted(ekeys, k).clamp(max=max(ekeys.numel() - 1, 0))
+    if ekeys.numel():
+        ok &= ekeys[pos] != k
+    ks, ko = torch.sort(k, stable=True)
+    firstocc = torch.ones_like(ks, dtype=torch.bool)
+    firstocc[1:] = ks[1:] != ks[:-1]
+    keep = torch.zeros_like(ok)
+    keep[ko] = firstocc
+    ok &= keep
+    csum = torch.cumsum(ok.to(torch.int64), 0)
+    seg = torch.cumsum(cand, 0) - cand
+    before = torch.where(seg > 0, csum[(seg - 1).clamp(min=0)], torch.zeros_like(seg))
+    rk = csum - 1 - before[cg]
+    ok &= rk < n_ins[cg]
+    wv = torch.randint(w_range[0], w_range[1] + 1, (int(ok.sum()),), generator=g, device=dev)
+    ins = torch.stack([lo[ok], hi[ok], wv], 1)
+    return dels.to(torch.int32).contiguous(), ins.to(torch.int32).contiguous()
+
+
 def forest_graph(offs, cols, w, first, q: int) -> Csr:
     """Graph q of a forest CSR (host numpy or torch arrays) as a Csr with its own vertex IDs."""
     a, b = int(first[q]), int(first[q + 1])

@@ -186,3 +186,55 @@ def _undirected_with_cross(F):
     v.append(F.n - 1)
     w.append(1)
     return np.array(u), np.array(v), np.array(w)
+
+
+def _oracle_graph(job):
+    """Oracle static run and one DF update (worker process)."""
+    import oracle
+    g, d, i = job
+    C0, q0, st0 = oracle.static(g)
+    gt, dw = oracle.apply_batch(g, d, i)
+    C1, _, q1, _ = oracle.update(gt, dw, i, oracle.initial_state(g, C0), "df")
+    return C0, q0, st0["passes"], C1, q1
+
+
+def test_forest_knn_4096_sample_against_oracle(lm):
+    """64 graphs of the 4,096-graph kNN workload (the same vertex counts and
+    seeds as the benchmark's forests, chosen as its sample is), run as one
+    forest: static, then a DF update of 1e-3 |E_q| per graph, every graph
+    against the oracle.  A graph's result in a forest does not depend on the
+    other graphs (the tests above), so these are the results the graphs get
+    in the full workload."""
+    import multiprocessing as mp
+
+    import torch
+    sizes_all = inputs.forest_sizes(4096, 1000, 200000, seed=inputs.BASE_SEED + 4)
+    rng = np.random.default_rng(inputs.BASE_SEED + 9)
+    sample = sorted(int(x) for x in rng.choice(4096, 64, replace=False))
+    gs = []
+    for q in sample:
+        o, c, w = inputs.knn_graph_torch(int(sizes_all[q]), inputs.BASE_SEED + 5 + q, "cuda")
+        gs.append(inputs.Csr(int(sizes_all[q]), o.cpu().numpy(), c.cpu().numpy().view(np.uint32),
+                             w.cpu().numpy().view(np.uint32)))
+    sizes, F = inputs.forest_csr(gs)
+    Fh = lm.Forest(sizes, F.offs, F.cols, F.w)
+    first = Fh.first.astype(np.int64)
+    rF = Fh.static()
+    qF, passes, _ = Fh.results()
+    per, dl, il = [], [], []
+    for k, g in enumerate(gs):
+        nb = max(1, inputs.batch_size_for(g.nnz, 1e-3))
+        d, i = inputs.random_batch(g.n, g.undirected_keys(), nb, seed=inputs.BASE_SEED + 700 + k, w_range=(1, 100))
+        per.append((d, i))
+        dl.append(d.astype(np.int64) + first[k])
+        i2 = i.astype(np.int64)
+        i2[:, :2] += first[k]
+        il.append(i2)
+    rU = Fh.update(np.concatenate(dl).astype(np.uint32), np.concatenate(il).astype(np.uint32), mode="df")
+    qU = Fh.results()[0]
+    with mp.get_context("fork").Pool(8) as pool:
+        outs = pool.map(_oracle_graph, [(g, d, i) for g, (d, i) in zip(gs, per)])
+    C0s, C1s = _split(rF.membership, sizes), _split(rU.membership, sizes)
+    for k, (C0, q0, p0, C1, q1) in enumerate(outs):
+        assert np.array_equal(C0s[k], C0) and qF[k] == q0 and passes[k] == p0, (k, sample[k])
+        assert np.array_equal(C1s[k], C1) and qU[k] == q1, (k, sample[k])
