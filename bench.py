@@ -381,75 +381,130 @@ def run_ablation(args, binding, inputs):
 
 
 def run_serving(args, binding, inputs):
-    """Tenant R-MAT graphs in a server under an HBM budget; a Poisson stream
-    of DF update requests (sizes log-uniform, 80/20 insert/delete) at a rate
-    set from the measured single-stream capacity."""
+    """Serving form: eight tenant R-MAT graphs (scales 20, 20, 21, 21, 22, 22,
+    23, 23; edge factor 16; unit weights; made on the GPU) in a server with
+    args.streams workers.  Admission: a budget that holds seven of the eight
+    estimated footprints refuses the eighth; the measured server admits all.
+    Requests: target graph uniform, B = round(exp(U[ln 1e2, ln 1e6]))
+    undirected updates (80% insertions of absent pairs, 20% deletions of
+    existing edges, consecutive slices of per-tenant pools, so every request
+    is valid in its graph's order), DF update each.  Capacity = 1 / the mean
+    service time of back-to-back requests; then Poisson arrivals at each of
+    args.loads times the capacity.  Latency = completion - arrival, service =
+    completion - start; updated edges/s = undirected updates over first
+    arrival to last completion."""
     import numpy as np
-    scales = [16, 16, 17, 17, 18, 18, 19, 19]
-    t0 = time.time()
-    gs = [inputs.rmat(sc, seed=inputs.BASE_SEED + 5 + k) for k, sc in enumerate(scales)]
-    log("serving: %d tenants (%.1f s to generate)" % (len(gs), time.time() - t0))
-    rng = np.random.default_rng(inputs.BASE_SEED + 6)
+    import torch
+    dev = torch.device("cuda:0")
+    scales = [20, 20, 21, 21, 22, 22, 23, 23]
+    loads = [float(x) for x in args.loads.split(",")]
     nreq = args.requests
-    targets = rng.integers(0, len(gs), nreq + 20)
-    sizes = np.round(np.exp(rng.uniform(np.log(1e2), np.log(2e4), nreq + 20))).astype(np.int64)
-    keys = [g.undirected_keys() for g in gs]
+    nwarm = args.warm_requests
+    rng = np.random.default_rng(inputs.BASE_SEED + 6)
+    total = nwarm + nreq * len(loads)
+    targets = rng.integers(0, len(scales), total)
+    bsz = np.round(np.exp(rng.uniform(np.log(1e2), np.log(1e6), total))).astype(np.int64)
+    n_del = np.round(0.2 * bsz).astype(np.int64)
+    n_ins = bsz - n_del
+    t0 = time.time()
+    tenants = []
+    for k, sc in enumerate(scales):
+        offs, cols, w = inputs.rmat_torch(sc, inputs.BASE_SEED + 50 + k, dev)
+        mine = targets == k
+        d, i = inputs.update_pool_torch(offs, cols, int(n_del[mine].sum()), int(n_ins[mine].sum()),
+                                        seed=inputs.BASE_SEED + 60 + k)
+        torch.cuda.synchronize()
+        tenants.append({"n": offs.numel() - 1, "offs": offs, "cols": cols, "w": w, "dels": d, "ins": i, "d0": 0,
+                        "i0": 0})
+        log("serving: tenant %d (scale %d): %d entries, pools %d / %d" % (k, sc, cols.numel(), d.shape[0],
+                                                                          i.shape[0]))
+    log("serving: tenants made in %.1f s" % (time.time() - t0))
     reqs = []
-    for k in range(nreq + 20):
-        t = int(targets[k])
-        d, i = inputs.random_batch(gs[t].n, keys[t], int(sizes[k]), seed=900 + k)
-        keys[t] = inputs.keys_after_batch(keys[t], d, i)
-        reqs.append((t, d, i))
-    srv = binding.Server(hbm_budget_bytes=64 << 30, workers=args.streams)
-    ids = [srv.add_graph(g) for g in gs]
-    # one request at a time (the first 10), then capacity: the next 10
-    # submitted together (the workers overlap up to one request per tenant)
-    ta = time.perf_counter()
-    for t, d, i in reqs[:10]:
-        srv.wait(srv.submit(ids[t], d, i, mode="df"))
-    per_req = (time.perf_counter() - ta) / 10
-    ta = time.perf_counter()
-    burst = [srv.submit(ids[t], d, i, mode="df") for t, d, i in reqs[10:20]]
-    for tk in burst:
-        srv.wait(tk)
-    capacity = 10 / (time.perf_counter() - ta)
-    lam = 0.7 * capacity  # offered load: 70% of the measured capacity
-    gaps = rng.exponential(1.0 / lam, nreq)
-    srv2 = binding.Server(hbm_budget_bytes=64 << 30, workers=args.streams)
-    ids2 = [srv2.add_graph(g) for g in gs]
-    # replay the first 20 to bring the second server's graphs to the same point
-    for t, d, i in reqs[:20]:
-        srv2.wait(srv2.submit(ids2[t], d, i, mode="df"))
-    srv2_stats0 = srv2.stats()
-    tickets = []
-    start = time.perf_counter()
-    due = start
-    for k in range(nreq):
-        due += gaps[k]
-        now = time.perf_counter()
-        if due > now:
-            time.sleep(due - now)
-        t, d, i = reqs[20 + k]
-        tickets.append(srv2.submit(ids2[t], d, i, mode="df"))
-    lat, svc = [], []
-    for tk in tickets:
-        _, la, sv = srv2.wait(tk)
-        lat.append(la)
-        svc.append(sv)
-    wall = time.perf_counter() - start
-    upd = int(sum(reqs[20 + k][1].shape[0] + reqs[20 + k][2].shape[0] for k in range(nreq)))
+    for r in range(total):
+        t = tenants[int(targets[r])]
+        d = t["dels"][t["d0"]:t["d0"] + int(n_del[r])]
+        i = t["ins"][t["i0"]:t["i0"] + int(n_ins[r])]
+        t["d0"] += d.shape[0]
+        t["i0"] += i.shape[0]
+        reqs.append((int(targets[r]), d, i))
+    # admission: a budget that holds the seven smallest footprints refuses the largest
+    est = [binding.server_footprint(t["n"], int(t["cols"].numel()), 0.2) for t in tenants]
+    order = np.argsort(est)
+    budget7 = int(sum(est[j] for j in order[:7]) + (64 << 20))
+    srvA = binding.Server(hbm_budget_bytes=budget7, workers=args.streams)
+    admitted, refused = 0, 0
+    for j in order:
+        t = tenants[j]
+        try:
+            srvA.add_graph_device(t["n"], t["offs"], t["cols"], t["w"])
+            admitted += 1
+        except binding.LeidenError:
+            refused += 1
+    srvA.close()
+    del srvA
+    srv = binding.Server(hbm_budget_bytes=int(sum(est) + (1 << 30)), workers=args.streams)
+    ids = [srv.add_graph_device(t["n"], t["offs"], t["cols"], t["w"]) for t in tenants]
+    for t in tenants:
+        del t["offs"], t["cols"], t["w"]
+    torch.cuda.empty_cache()
+    # warm-up and single-stream capacity: back-to-back requests
+    svc0 = []
+    for r in range(nwarm):
+        tg, d, i = reqs[r]
+        _, la, sv = srv.wait(srv.submit(ids[tg], d, i, mode="df"))
+        svc0.append(sv)
+    mean_svc = float(np.mean(svc0[len(svc0) // 5:]))
+    capacity = 1e3 / mean_svc
+    log("serving: %d warm-up requests, mean service %.2f ms, capacity %.1f req/s" % (nwarm, mean_svc, capacity))
+    res = []
+    base = nwarm
+    for load in loads:
+        lam = load * capacity
+        gaps = rng.exponential(1.0 / lam, nreq)
+        tickets = []
+        start = time.perf_counter()
+        due = start
+        for k in range(nreq):
+            due += gaps[k]
+            now = time.perf_counter()
+            if due > now:
+                time.sleep(due - now)
+            tg, d, i = reqs[base + k]
+            tickets.append(srv.submit(ids[tg], d, i, mode="df"))
+            if (k + 1) % 100 == 0:
+                log("serving: load %.1f: %d requests submitted" % (load, k + 1))
+        lat, svc = [], []
+        for k, tk in enumerate(tickets):
+            _, la, sv = srv.wait(tk)
+            lat.append(la)
+            svc.append(sv)
+            if (k + 1) % 100 == 0:
+                log("serving: load %.1f: %d requests done" % (load, k + 1))
+        wall = time.perf_counter() - start
+        upd = int(sum(reqs[base + k][1].shape[0] + reqs[base + k][2].shape[0] for k in range(nreq)))
+        res.append({"load": load, "offered_req_per_s": lam, "requests": nreq,
+                    "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
+                    "service_ms": {"p50": percentile(svc, 50), "p99": percentile(svc, 99)},
+                    "updated_edges_per_s": upd / wall})
+        log("serving: load %.1f: latency p50 %.2f p99 %.2f ms, service p50 %.2f p99 %.2f ms, %.3g updated edges/s"
+            % (load, res[-1]["latency_ms"]["p50"], res[-1]["latency_ms"]["p99"], res[-1]["service_ms"]["p50"],
+               res[-1]["service_ms"]["p99"], res[-1]["updated_edges_per_s"]))
+        base += nreq
+    st = srv.stats()
     srv.close()
-    srv2.close()
+    top = res[-1]
     return {"metric": "serving: p50/p99 update latency and sustained updated edges/s (1 GPU)",
-            "value": upd / wall, "unit": "updated_edges/s", "n_gpus": 1, "higher_is_better": True,
-            "data": "synthetic", "dtype": "int64+f64",
-            "config": {"workload": "rmat_tenants", "scales": scales, "requests": nreq,
-                       "batch_sizes": "log-uniform 1e2..2e4 undirected updates, 80/20", "workers": args.streams,
-                       "offered_load": "Poisson at 70% of measured capacity"},
-            "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
-            "service_ms": {"p50": percentile(svc, 50), "p99": percentile(svc, 99)},
-            "single_request_ms_back_to_back": per_req * 1e3, "capacity_req_per_s": capacity,
-            "offered_req_per_s": lam, "completed_before": srv2_stats0["completed"]}
+            "value": top["updated_edges_per_s"], "unit": "updated_edges/s", "n_gpus": 1, "higher_is_better": True,
+            "data": "synthetic", "dtype": "int64+f64", "vs_baseline": None,
+            "config": {"workload": "rmat_tenants_serving", "scales": scales, "edge_factor": 16,
+                       "warm_up_requests": nwarm, "requests_per_load": nreq, "loads": loads,
+                       "batch_sizes": "round(exp(U[ln 1e2, ln 1e6])) undirected updates, 80/20",
+                       "workers": args.streams, "mode": "df", "deterministic": True},
+            "latency_ms": top["latency_ms"], "service_ms": top["service_ms"], "per_load": res,
+            "single_stream_capacity_req_per_s": capacity, "mean_service_ms_back_to_back": mean_svc,
+            "admission": {"budget_bytes": budget7, "admitted": admitted, "refused": refused,
+                          "estimates_bytes": est},
+            "completed": st["completed"], "failed": st["failed"]}
 
 
 def main():
@@ -473,8 +528,10 @@ def main():
     ap.add_argument("--graphs", type=int, default=4096, help="forest: number of kNN graphs")
     ap.add_argument("--forest-entries", type=float, default=1.2e9, help="forest: most entries of one forest")
     ap.add_argument("--single-sample", type=int, default=128, help="forest: graphs also run one at a time")
-    ap.add_argument("--streams", type=int, default=8, help="batched / serving: worker streams")
-    ap.add_argument("--requests", type=int, default=300, help="serving: measured requests")
+    ap.add_argument("--streams", type=int, default=4, help="serving: worker streams")
+    ap.add_argument("--requests", type=int, default=500, help="serving: measured requests per load")
+    ap.add_argument("--warm-requests", type=int, default=50, help="serving: back-to-back warm-up requests")
+    ap.add_argument("--loads", default="0.3,0.5,0.7,0.9", help="serving: offered loads (fractions of capacity)")
     ap.add_argument("--marker", type=int, default=0,
                     help="launch a spin kernel right before and after the timed steps (profile windowing)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,

@@ -343,6 +343,9 @@ typedef struct {
 leiden_status leiden_server_create(int device, uint64_t hbm_budget_bytes, uint32_t workers, leiden_server** out);
 /* Waits for running requests, then frees every graph and the server. */
 void leiden_server_destroy(leiden_server* s);
+/* *bytes: the estimated device footprint the admission charges for a graph
+ * of n vertices and nnz directed entries held with the given slack. */
+leiden_status leiden_server_footprint(uint32_t n, uint64_t nnz, double slack, uint64_t* bytes);
 /* Admit a graph (arguments as leiden_graph_create) and run leiden_static on
  * it (opts may be NULL).  LEIDEN_ENOMEM when its estimated footprint does not
  * fit in what is left of the budget; *graph_id receives its ID. */

@@ -27,7 +27,7 @@ EXPORTS = ("leiden_default_opts", "leiden_graph_create", "leiden_graph_destroy",
            "leiden_set_tuning", "leiden_autotune", "leiden_batch_run", "leiden_server_create",
            "leiden_server_destroy", "leiden_server_add_graph", "leiden_server_remove_graph", "leiden_server_submit",
            "leiden_server_wait", "leiden_server_get_stats", "leiden_modularity_noalloc", "leiden_forest_create",
-           "leiden_forest_results", "leiden_forest_info")
+           "leiden_forest_results", "leiden_forest_info", "leiden_server_footprint")
 
 FOREST_ITER_HIST = 16  # passes whose iteration counts leiden_forest_results returns
 
@@ -167,7 +167,8 @@ def lib():
                            ("leiden_server_get_stats", [P, P]),
                            ("leiden_forest_create", [i32, u32, P, u64, P, P, P, i32, dbl, ctypes.POINTER(P)]),
                            ("leiden_forest_results", [P, P, P, P]),
-                           ("leiden_forest_info", [P, P, P])):
+                           ("leiden_forest_info", [P, P, P]),
+                           ("leiden_server_footprint", [u32, u64, dbl, ctypes.POINTER(u64)])):
             getattr(L, name).argtypes = args
             getattr(L, name).restype = i32
         L.leiden_server_destroy.argtypes = [P]
@@ -457,6 +458,13 @@ def batch_run(graphs, batches=None, mode="df", streams=8, **opts):
     return outs, q
 
 
+def server_footprint(n, nnz, slack=0.2) -> int:
+    """Device bytes the server's admission charges for a graph (leiden_server_footprint)."""
+    b = ctypes.c_uint64()
+    _check(lib().leiden_server_footprint(n, ctypes.c_uint64(nnz), ctypes.c_double(slack), ctypes.byref(b)))
+    return int(b.value)
+
+
 class Server:
     """Serving form: tenant graphs under an HBM budget, update requests served
     by `workers` streams in arrival order (one request per graph at a time)."""
@@ -478,6 +486,16 @@ class Server:
                                              _ptr(cols)[0], _ptr(w)[0], 0, ctypes.c_double(slack), ctypes.byref(o),
                                              ctypes.byref(gid)))
         self._n[gid.value] = csr.n
+        return gid.value
+
+    def add_graph_device(self, n, offs, cols, w, slack=0.2, **opts):
+        """Admit a graph given as device tensors (int64 offsets, 32-bit cols and weights)."""
+        o = default_opts(**opts)
+        gid = ctypes.c_uint32()
+        _check(lib().leiden_server_add_graph(self._h, n, ctypes.c_uint64(int(cols.shape[0])), offs.data_ptr(),
+                                             cols.data_ptr(), w.data_ptr(), 1, ctypes.c_double(slack),
+                                             ctypes.byref(o), ctypes.byref(gid)))
+        self._n[gid.value] = n
         return gid.value
 
     def remove_graph(self, gid):

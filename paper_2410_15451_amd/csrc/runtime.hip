@@ -43,10 +43,11 @@ leiden_status fail(leiden_status st, const char* fmt, ...) {
   } while (0)
 
 // The stream of the current API call on this thread (null outside calls).
-// Device buffers grow stream-ordered on it: the old block is released after
-// the work queued on the stream (the call's side streams are joined back into
-// it before host code runs again), so growing one handle's buffer waits
-// neither for the host nor for other handles' calls on other streams.
+// Every kernel that reads a handle's buffers runs on that stream or on a side
+// stream joined back into it before host code runs again, and earlier calls
+// ended with a synchronisation of their own stream; so a buffer of the handle
+// can be released once this stream is idle, without waiting for the whole
+// device (other handles' calls on other streams keep running).
 thread_local hipStream_t tl_alloc_stream = nullptr;
 
 struct AllocScope {
@@ -55,50 +56,31 @@ struct AllocScope {
   ~AllocScope() { tl_alloc_stream = prev; }
 };
 
-// Stream-ordered allocation is used where the device supports memory pools.
-bool pools_supported() {
-  int dev = 0, v = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return false;
-  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMemoryPoolsSupported, dev) != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-  return v != 0;
-}
-
 // Device allocation owned by the handle; grows on demand, never shrinks.
 struct Buf {
   void* p = nullptr;
   size_t bytes = 0;
-  bool pooled = false;  // from the stream-ordered allocator
   ~Buf() {
-    // handles are destroyed rarely: wait for the device, then release at once
-    if (p && pooled) (void)hipDeviceSynchronize();
-    release(nullptr);
-  }
-  void release(hipStream_t s) {
-    if (!p) return;
-    if (pooled)
-      (void)hipFreeAsync(p, s);
-    else
-      (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
+    if (p) (void)hipFree(p);
   }
   leiden_status reserve(size_t b) {
     if (b <= bytes) return LEIDEN_OK;
-    static const bool pools = pools_supported();
-    hipStream_t s = pools ? tl_alloc_stream : nullptr;
-    if (p && !s) (void)hipDeviceSynchronize();  // kernels queued earlier on any stream may still read it
-    release(s);
+    if (p) {
+      // kernels queued earlier may still read the old block
+      if (tl_alloc_stream)
+        (void)hipStreamSynchronize(tl_alloc_stream);
+      else
+        (void)hipDeviceSynchronize();
+      (void)hipFree(p);
+    }
+    p = nullptr;
+    bytes = 0;
     size_t want = std::max<size_t>(b, 256);
-    const hipError_t e = s ? hipMallocAsync(&p, want, s) : hipMalloc(&p, want);
-    if (e != hipSuccess) {
+    if (hipMalloc(&p, want) != hipSuccess) {
       (void)hipGetLastError();
       p = nullptr;
       return fail(LEIDEN_ENOMEM, "device allocation of %zu bytes failed", want);
     }
-    pooled = s != nullptr;
     bytes = want;
     return LEIDEN_OK;
   }

@@ -154,6 +154,12 @@ void worker_main(leiden_server* S) {
 
 extern "C" {
 
+leiden_status leiden_server_footprint(uint32_t n, uint64_t nnz, double slack, uint64_t* bytes) {
+  if (!bytes || !(slack >= 0.0)) return LEIDEN_EINVAL;
+  *bytes = handle_bytes(n, nnz, slack);
+  return LEIDEN_OK;
+}
+
 leiden_status leiden_server_create(int device, uint64_t hbm_budget_bytes, uint32_t workers, leiden_server** out) {
   if (!out || workers == 0 || workers > 64) return LEIDEN_EINVAL;
   int count = 0;

@@ -42,6 +42,10 @@ stand in for them):
     64 points around it in the order of (bucket, a random projection) rather
     than among its whole bucket, and the weight is 1 + floor(99 D / (D + d^2))
     (integer arithmetic);
+  * serving tenants: R-MAT graphs by the recipe above made on the device by
+    ``rmat_torch`` (torch random streams), and per tenant one pool of distinct
+    edges to delete and distinct absent pairs to insert whose prefixes make
+    a valid stream of batches;
   * temporal stream (stands in for the SNAP temporal graphs of the paper's
     real-world experiment): the distinct undirected edges of an R-MAT graph in
     a seeded random arrival order; the first 90% form the initial graph and
@@ -409,6 +413,94 @@ def knn_graph_torch(n: int, seed: int, device, k: int = 15, dim: int = 16, cand:
     offs = torch.zeros(n + 1, dtype=torch.int64, device=device)
     offs[1:] = torch.cumsum(torch.bincount(src, minlength=n), 0)
     return offs, dst.to(torch.int32), ww.to(torch.int32)
+
+
+def rmat_torch(scale: int, seed: int, device, edge_factor: int = 16, a: float = 0.57, b: float = 0.19,
+               c: float = 0.19):
+    """R-MAT graph by the recipe of ``rmat`` made with torch on ``device``
+    (its own random streams, so not the same graph as ``rmat`` with the same
+    seed); returns (offs int64[n+1], cols int32[nnz], w int32[nnz]) tensors."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    n = 1 << scale
+    m = edge_factor * n
+    src = torch.zeros(m, dtype=torch.int64, device=device)
+    dst = torch.zeros(m, dtype=torch.int64, device=device)
+    ab, abc = a + b, a + b + c
+    for lvl in range(scale):
+        r = torch.rand(m, generator=g, device=device)
+        bit = 1 << (scale - 1 - lvl)
+        src |= (r >= ab).to(torch.int64) * bit
+        dst |= (((r >= a) & (r < ab)) | (r >= abc)).to(torch.int64) * bit
+        del r
+    keep = src != dst
+    lo = torch.minimum(src, dst)[keep]
+    hi = torch.maximum(src, dst)[keep]
+    del src, dst, keep
+    key = torch.unique(lo * n + hi)
+    del lo, hi
+    perm = torch.randperm(n, generator=g, device=device)
+    u, v = perm[key // n], perm[key % n]
+    del key
+    s2 = torch.cat([u, v])
+    d2 = torch.cat([v, u])
+    del u, v
+    order = torch.argsort(s2 * n + d2)
+    s2, d2 = s2[order], d2[order]
+    offs = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    offs[1:] = torch.cumsum(torch.bincount(s2, minlength=n), 0)
+    return offs, d2.to(torch.int32), torch.ones_like(d2, dtype=torch.int32)
+
+
+def update_pool_torch(offs, cols, n_del: int, n_ins: int, seed: int, w_range=(1, 1)):
+    """Distinct existing edges to delete (n_del, uniform) and distinct absent
+    pairs to insert (n_ins, uniform endpoints, weights uniform in w_range) for
+    a graph on the device; any prefix of each, taken in order, is a valid
+    stream of batches (Section 5.1.4).  Returns host numpy arrays
+    (uint32[n_del, 2], uint32[n_ins, 3])."""
+    import torch
+
+    dev = offs.device
+    g = torch.Generator(device=dev)
+    g.manual_seed(int(seed))
+    n = offs.numel() - 1
+    src = torch.repeat_interleave(torch.arange(n, device=dev), offs[1:] - offs[:-1])
+    dst = cols.to(torch.int64)
+    up = src < dst
+    u, v = src[up], dst[up]
+    del src, dst, up
+    keys = torch.sort(u * n + v).values
+    n_del = min(n_del, keys.numel())
+    pick = torch.randperm(keys.numel(), generator=g, device=dev)[:n_del]
+    dk = keys[pick]
+    dels = torch.stack([dk // n, dk % n], 1)
+    got = []
+    have = 0
+    seen = torch.zeros(0, dtype=torch.int64, device=dev)
+    while have < n_ins:
+        want = 2 * (n_ins - have) + 16
+        a = torch.randint(0, n, (want,), generator=g, device=dev)
+        b = torch.randint(0, n, (want,), generator=g, device=dev)
+        lo, hi = torch.minimum(a, b), torch.maximum(a, b)
+        k = (lo * n + hi)[lo != hi]
+        pos = torch.searchsorted(keys, k).clamp(max=max(keys.numel() - 1, 0))
+        k = k[keys[pos] != k]
+        ks, ko = torch.sort(k, stable=True)
+        first = torch.ones_like(ks, dtype=torch.bool)
+        first[1:] = ks[1:] != ks[:-1]
+        k = k[torch.sort(ko[first]).values]  # first occurrences, in draw order
+        if seen.numel():
+            k = k[~torch.isin(k, seen)]
+        k = k[:n_ins - have]
+        got.append(k)
+        seen = torch.cat([seen, k])
+        have += k.numel()
+    k = torch.cat(got) if got else torch.zeros(0, dtype=torch.int64, device=dev)
+    wv = torch.randint(w_range[0], w_range[1] + 1, (k.numel(),), generator=g, device=dev)
+    ins = torch.stack([k // n, k % n, wv], 1)
+    return dels.cpu().numpy().astype(np.uint32), ins.cpu().numpy().astype(np.uint32)
 
 
 def forest_sizes(count: int, n_min: int = 1000, n_max: int = 200000, seed: int = BASE_SEED + 4) -> np.ndarray:
