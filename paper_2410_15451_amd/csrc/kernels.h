@@ -274,19 +274,20 @@ void modularity_parts(hipStream_t s, Rows<uint32_t> g, uint32_t n, const uint32_
                       unsigned long long* partials, int nblocks, ModParts* out_dev);
 
 struct TrackBufs {
+  uint32_t* head;             // in: minimum vertex of every old label (kNone: not a label); out: those of the new labels
+  uint32_t* cb;               // per old label: the current community of its head
   uint32_t* minv;
   unsigned long long* hkeys;  // pair table (empty between calls)
   long long* hvals;
   uint64_t hmask;
-  int64_t* Kc;                // per vertex: its weight if its pair is its community's common pair
-  int64_t* wcom;              // per community: weight of its common pair, then Sigma_c
+  int64_t* Kc;                // per vertex: its weight if its pair is (its old label, cb of it)
+  int64_t* wb;                // per old label: weight of its common pair
   uint32_t* owners;           // slots of the rare pairs
   unsigned int* owner_count;
   long long* best_w;
   uint32_t* best_vmin;
   long long* cand_w;
   uint32_t* cand_b;
-  uint32_t* is_old;
   uint32_t* flag;
   uint64_t* rank;
   uint64_t* free_rank;
@@ -300,12 +301,14 @@ struct TrackBufs {
   const uint32_t* f_gid;
   const uint32_t* f_base;
 };
-// out: tracked labels; S_out: Sigma^t by tracked label.  rep (may be null):
-// after one pass without refinement, every vertex's label after local moving
-// and before Alg. 10 (every label of Ccur is then its community's minimum
-// vertex)
+// out: tracked labels; S_out: Sigma^t by tracked label.  labels_are_min:
+// every label of Ccur is its community's minimum vertex (saves a scatter).
 void track(hipStream_t s, uint32_t n, const uint32_t* Ccur, const uint32_t* Cprev, const int64_t* K, uint32_t* out,
-           int64_t* S_out, const uint32_t* rep, TrackBufs& b);
+           int64_t* S_out, bool labels_are_min, TrackBufs& b);
+// head[label] = minimum vertex of the community of each label of C
+void track_heads_of(hipStream_t s, uint32_t n, const uint32_t* C, uint32_t* head);
+// heads of dense static labels (flag: minimum vertices, out: their labels)
+void static_heads(hipStream_t s, uint32_t n, const uint32_t* flag, const uint32_t* out, uint32_t* head);
 
 // forest.hip: per-graph state of a forest run (see the file's header).
 constexpr uint32_t kForestIterHist = 16;  // passes whose iteration counts are kept per graph

@@ -1286,38 +1286,47 @@ __device__ inline uint64_t pair_insert(unsigned long long* hk, uint64_t mask, un
   }
 }
 
-// Pairs (old label b, current community c) of the vertices.  With rep given
-// (one pass without refinement: rep[v] is v's label after local moving and
-// before Alg. 10 renumbered it, i.e. the old label whose community c
-// continues), a vertex's pair is common when b = rep[minv[c]]: the pair of
-// every vertex that stayed.  Its weight goes to Kc, summed per community by a
-// bucketed scatter.  The other (rare) pairs, and every pair when rep is null,
-// are summed per tile of 1024 vertices in LDS and then added once per tile to
-// the global pair table; the slots a tile creates are listed.
+// The community each old label continues in the first place: cb[x] =
+// Ccur[head[x]], the current community of the old community's minimum vertex
+// (kNone when x is not an old label).  Any choice is exact (it only decides
+// which pairs are summed in place); this one holds most vertices of x.
+__global__ __launch_bounds__(kBlock) void k_track_cb(uint32_t n, const uint32_t* head, const uint32_t* Ccur,
+                                                     uint32_t* cb) {
+  GRID_STRIDE(x, n) {
+    const uint32_t h = head[x];
+    cb[x] = h == kNone ? kNone : Ccur[h];
+  }
+}
+
+// Pairs (old label b, current community c) of the vertices.  A vertex whose
+// pair is (b, cb[b]) is common: its weight goes to Kc, summed per old label
+// by a bucketed scatter.  The other (rare) pairs are summed per tile of 1024
+// vertices in LDS and then added once per tile to the global pair table; the
+// slots a tile creates are listed.
 __global__ __launch_bounds__(kBlock) void k_track_split(uint32_t n, const uint32_t* Ccur, const uint32_t* Cprev,
-                                                        const int64_t* K, const uint32_t* minv, const uint32_t* rep,
-                                                        int64_t* Kc, unsigned long long* hk, long long* hv,
-                                                        uint64_t mask, uint32_t* owners, unsigned int* owner_count,
-                                                        uint32_t* is_old) {
+                                                        const int64_t* K, const uint32_t* cb, int64_t* Kc,
+                                                        unsigned long long* hk, long long* hv, uint64_t mask,
+                                                        uint32_t* owners, unsigned int* owner_count) {
   constexpr int kTile = 1024, kSlots = 2048;
   __shared__ unsigned long long lk[kSlots];
   __shared__ unsigned long long lv[kSlots];
+  __shared__ unsigned int nrare;
   for (uint64_t base = (uint64_t)blockIdx.x * kTile; base < n; base += (uint64_t)gridDim.x * kTile) {
     for (int s = threadIdx.x; s < kSlots; s += kBlock) {
       lk[s] = kNone64;
       lv[s] = 0;
     }
+    if (threadIdx.x == 0) nrare = 0;
     __syncthreads();
+    unsigned int mine = 0;
     for (int t = threadIdx.x; t < kTile; t += kBlock) {
       const uint64_t i = base + t;
       if (i >= n) continue;
       const uint32_t b = Cprev[i], c = Ccur[i];
-      // read first: the members of a large community all name one old label,
-      // and stores to one line from every CU queue on it
-      if (!peek(&is_old[b])) is_old[b] = 1;
-      const bool common = rep && rep[minv[c]] == b;
+      const bool common = cb[b] == c;
       Kc[i] = common ? K[i] : 0;
       if (common) continue;
+      ++mine;
       const unsigned long long key = ((unsigned long long)b << 32) | c;
       uint32_t h = (uint32_t)pair_slot(key, kSlots - 1);
       while (true) {
@@ -1327,53 +1336,54 @@ __global__ __launch_bounds__(kBlock) void k_track_split(uint32_t n, const uint32
       }
       atomicAdd(&lv[h], (unsigned long long)K[i]);
     }
+    if (mine) atomicAdd(&nrare, mine);
     __syncthreads();
-    for (int s0 = 0; s0 < kSlots; s0 += kBlock) {
-      const int s = s0 + threadIdx.x;
-      const unsigned long long key = lk[s];
-      uint32_t created = kNone, slot = 0;
-      if (key != kNone64) {
-        uint64_t h = pair_slot(key, mask);
-        while (true) {
-          const unsigned long long k = ld_sys(&hk[h]);
-          if (k == key) break;
-          if (k == kNone64) {
-            const unsigned long long o = atomicCAS(&hk[h], kNone64, key);
-            if (o == kNone64) {
-              created = 0;
-              break;
+    if (nrare) {  // block-uniform
+      for (int s0 = 0; s0 < kSlots; s0 += kBlock) {
+        const int s = s0 + threadIdx.x;
+        const unsigned long long key = lk[s];
+        uint32_t created = kNone, slot = 0;
+        if (key != kNone64) {
+          uint64_t h = pair_slot(key, mask);
+          while (true) {
+            const unsigned long long k = ld_sys(&hk[h]);
+            if (k == key) break;
+            if (k == kNone64) {
+              const unsigned long long o = atomicCAS(&hk[h], kNone64, key);
+              if (o == kNone64) {
+                created = 0;
+                break;
+              }
+              if (o == key) break;
             }
-            if (o == key) break;
+            h = (h + 1) & mask;
           }
-          h = (h + 1) & mask;
+          atomicAdd((unsigned long long*)&hv[h], lv[s]);
+          slot = (uint32_t)h;
         }
-        atomicAdd((unsigned long long*)&hv[h], lv[s]);
-        slot = (uint32_t)h;
+        wave_append(created, slot, [&](uint32_t, uint32_t*& l, unsigned int*& cnt) {
+          l = owners;
+          cnt = owner_count;
+        });
       }
-      wave_append(created, slot, [&](uint32_t, uint32_t*& l, unsigned int*& cnt) {
-        l = owners;
-        cnt = owner_count;
-      });
     }
     __syncthreads();
   }
 }
 
-// A pair of the two sources: item x < n is community x's common pair (when
-// x is a community and common pairs are in use), item n + k the k-th listed
-// rare pair.
+// A pair of the two sources: item x < n is old label x's common pair (when x
+// is an old label), item n + k the k-th listed rare pair.
 struct TrackPair {
   uint32_t b, c;
   long long w;
   bool ok;
 };
-__device__ inline TrackPair track_pair(uint64_t x, uint32_t n, const uint32_t* rep, const uint32_t* minv,
-                                       const int64_t* wcom, const unsigned long long* hk, const long long* hv,
-                                       const uint32_t* owners) {
+__device__ inline TrackPair track_pair(uint64_t x, uint32_t n, const uint32_t* cb, const int64_t* wb,
+                                       const unsigned long long* hk, const long long* hv, const uint32_t* owners) {
   TrackPair p{0, 0, 0, false};
   if (x < n) {
-    const uint32_t m = rep ? minv[x] : kNone;
-    if (m != kNone) p = TrackPair{rep[m], (uint32_t)x, (long long)wcom[x], true};
+    const uint32_t c = cb[x];
+    if (c != kNone) p = TrackPair{(uint32_t)x, c, (long long)wb[x], true};
   } else {
     const uint32_t h = owners[x - n];
     const unsigned long long k = hk[h];
@@ -1388,14 +1398,13 @@ __device__ inline TrackPair track_pair(uint64_t x, uint32_t n, const uint32_t* r
 // (atomics on one address are serialised device-wide).
 constexpr long long kTrackHeavy = 1ll << 16;
 
-__global__ __launch_bounds__(kBlock) void k_track_best_w(uint32_t n, const uint32_t* rep, const uint32_t* minv,
-                                                         const int64_t* wcom, const unsigned long long* hk,
-                                                         const long long* hv, const uint32_t* owners,
-                                                         const unsigned int* owner_count, long long* best_w,
-                                                         bool heavy) {
+__global__ __launch_bounds__(kBlock) void k_track_best_w(uint32_t n, const uint32_t* cb, const int64_t* wb,
+                                                         const unsigned long long* hk, const long long* hv,
+                                                         const uint32_t* owners, const unsigned int* owner_count,
+                                                         long long* best_w, bool heavy) {
   const uint64_t items = (uint64_t)n + *owner_count;
   GRID_STRIDE(x, items) {
-    const TrackPair p = track_pair(x, n, rep, minv, wcom, hk, hv, owners);
+    const TrackPair p = track_pair(x, n, cb, wb, hk, hv, owners);
     if (!p.ok || (p.w >= kTrackHeavy) != heavy) continue;
     // read first: most updates would not raise the maximum
     long long* slot = &best_w[p.b];
@@ -1403,14 +1412,14 @@ __global__ __launch_bounds__(kBlock) void k_track_best_w(uint32_t n, const uint3
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_track_best_c(uint32_t n, const uint32_t* rep, const uint32_t* minv,
-                                                         const int64_t* wcom, const unsigned long long* hk,
-                                                         const long long* hv, const uint32_t* owners,
-                                                         const unsigned int* owner_count, const long long* best_w,
+__global__ __launch_bounds__(kBlock) void k_track_best_c(uint32_t n, const uint32_t* cb, const int64_t* wb,
+                                                         const unsigned long long* hk, const long long* hv,
+                                                         const uint32_t* owners, const unsigned int* owner_count,
+                                                         const uint32_t* minv, const long long* best_w,
                                                          uint32_t* best_vmin) {
   const uint64_t items = (uint64_t)n + *owner_count;
   GRID_STRIDE(x, items) {
-    const TrackPair p = track_pair(x, n, rep, minv, wcom, hk, hv, owners);
+    const TrackPair p = track_pair(x, n, cb, wb, hk, hv, owners);
     if (!p.ok) continue;
     const uint32_t vm = minv[p.c];
     if (p.w == best_w[p.b] && peek(&best_vmin[p.b]) > vm) atomicMin(&best_vmin[p.b], vm);
@@ -1443,12 +1452,12 @@ __global__ __launch_bounds__(kBlock) void k_track_cand_b(uint32_t n, const uint3
 // flag[v] = v is the minimum vertex of an unmatched current community;
 // freeflag[x] = x is not an old label
 __global__ __launch_bounds__(kBlock) void k_track_flags(uint32_t n, const uint32_t* Ccur, const uint32_t* minv,
-                                                        const uint32_t* cand_b, const uint32_t* is_old, uint32_t* flag,
+                                                        const uint32_t* cand_b, const uint32_t* head, uint32_t* flag,
                                                         uint32_t* freeflag) {
   GRID_STRIDE(i, n) {
     const uint32_t c = Ccur[i];
     flag[i] = (minv[c] == (uint32_t)i && cand_b[c] == kNone) ? 1u : 0u;
-    freeflag[i] = is_old[i] ? 0u : 1u;
+    freeflag[i] = head[i] == kNone ? 1u : 0u;
   }
 }
 
@@ -1467,6 +1476,14 @@ __global__ __launch_bounds__(kBlock) void k_track_free(uint32_t n, const uint32_
   GRID_STRIDE(x, n) if (freeflag[x]) free_id[graph_pos(fgid, fbase, free_rank, (uint32_t)x, free_rank[x])] = (uint32_t)x;
 }
 
+// The tracked label of community c: its matched old label, else the next
+// free ID (by its minimum vertex).
+__device__ inline uint32_t tracked_label(uint32_t c, uint32_t m, const uint32_t* cand_b, const uint64_t* rank,
+                                         const uint32_t* free_id, const uint32_t* fgid, const uint32_t* fbase) {
+  const uint32_t b = cand_b[c];
+  return b != kNone ? b : free_id[graph_pos(fgid, fbase, rank, m, rank[m])];
+}
+
 __global__ __launch_bounds__(kBlock) void k_track_label(uint32_t n, const uint32_t* Ccur, const uint32_t* minv,
                                                         const uint32_t* cand_b, const uint64_t* rank,
                                                         const uint32_t* free_id, uint32_t* out, uint8_t* matched,
@@ -1478,57 +1495,20 @@ __global__ __launch_bounds__(kBlock) void k_track_label(uint32_t n, const uint32
       out[i] = b;
       raise_flag(matched, b);
     } else {
-      const uint32_t m = minv[c];
-      out[i] = free_id[graph_pos(fgid, fbase, rank, m, rank[m])];
+      out[i] = tracked_label(c, minv[c], cand_b, rank, free_id, fgid, fbase);
     }
   }
 }
 
-// Sigma^t of every community: its common weight plus its rare pairs'.  A
-// block sums its range of rare pairs per community in LDS first (a large
-// community receives pairs from many old communities, and atomics on one
-// address queue device-wide), flushing when its table is half full.
-__global__ __launch_bounds__(kBlock) void k_track_rare_sigma(const unsigned long long* hk, const long long* hv,
-                                                             const uint32_t* owners, const unsigned int* owner_count,
-                                                             int64_t* wcom) {
-  constexpr uint32_t kSlots = 2048, kChunk = kSlots / 2;
-  __shared__ uint32_t tk[kSlots];
-  __shared__ unsigned long long tv[kSlots];
-  for (uint32_t s = threadIdx.x; s < kSlots; s += kBlock) {
-    tk[s] = kNone;
-    tv[s] = 0;
-  }
-  __syncthreads();
-  const uint32_t cnt = *owner_count;
-  const uint32_t per = (cnt + gridDim.x - 1) / gridDim.x;
-  const uint32_t a = blockIdx.x * per, e = min(cnt, a + per);
-  for (uint32_t base = a; base < e; base += kChunk) {
-    for (uint32_t k = base + threadIdx.x; k < min(e, base + kChunk); k += kBlock) {
-      const uint32_t h = owners[k];
-      table_add(tk, tv, kSlots - 1, (uint32_t)hk[h], (unsigned long long)hv[h]);
-    }
-    __syncthreads();
-    for (uint32_t s = threadIdx.x; s < kSlots; s += kBlock) {
-      const uint32_t c = tk[s];
-      if (c == kNone) continue;
-      atomicAdd((unsigned long long*)&wcom[c], tv[s]);
-      tk[s] = kNone;
-      tv[s] = 0;
-    }
-    __syncthreads();
-  }
-}
-
-// Sigma^t under the tracked labels: S[label of c] = Sigma_c.
-__global__ __launch_bounds__(kBlock) void k_track_sigma(uint32_t n, const uint32_t* minv, const uint32_t* cand_b,
+// The minimum vertex of every community under its tracked label, for the
+// next call (head must be all kNone before).
+__global__ __launch_bounds__(kBlock) void k_track_heads(uint32_t n, const uint32_t* minv, const uint32_t* cand_b,
                                                         const uint64_t* rank, const uint32_t* free_id,
-                                                        const int64_t* sig, int64_t* S, const uint32_t* fgid,
-                                                        const uint32_t* fbase) {
+                                                        const uint32_t* fgid, const uint32_t* fbase, uint32_t* head) {
   GRID_STRIDE(c, n) {
     const uint32_t m = minv[c];
     if (m == kNone) continue;
-    const uint32_t b = cand_b[c];
-    S[b != kNone ? b : free_id[graph_pos(fgid, fbase, rank, m, rank[m])]] = sig[c];
+    head[tracked_label((uint32_t)c, m, cand_b, rank, free_id, fgid, fbase)] = m;
   }
 }
 
@@ -1546,31 +1526,38 @@ __global__ __launch_bounds__(kBlock) void k_track_minv_self(uint32_t n, const ui
   GRID_STRIDE(v, n) if (Ccur[v] == (uint32_t)v) minv[v] = (uint32_t)v;
 }
 
+// head[label] = minimum vertex of the community of each label of C.
+void track_heads_of(hipStream_t s, uint32_t n, const uint32_t* C, uint32_t* head) {
+  fill_u32(s, head, kNone, n);
+  scatter_min_index(s, C, n, head, n);
+}
+
 void track(hipStream_t s, uint32_t n, const uint32_t* Ccur, const uint32_t* Cprev, const int64_t* K, uint32_t* out,
-           int64_t* S_out, const uint32_t* rep, TrackBufs& b) {
+           int64_t* S_out, bool labels_are_min, TrackBufs& b) {
   if (n == 0) return;
-  // minimum vertex of each current community (with rep, labels are minimum vertices)
+  // minimum vertex of each current community
   fill_u32(s, b.minv, kNone, n);
-  if (rep)
+  if (labels_are_min)
     hipLaunchKernelGGL(k_track_minv_self, dim3(grid_n(n)), dim3(kBlock), 0, s, n, Ccur, b.minv);
   else
     scatter_min_index(s, Ccur, n, b.minv, n);
-  fill_u32(s, b.is_old, 0, n);
+  // overlap weights: common pairs per old label, rare pairs in the table
+  hipLaunchKernelGGL(k_track_cb, dim3(grid_n(n)), dim3(kBlock), 0, s, n, b.head, Ccur, b.cb);
   fill_u32(s, b.owner_count, 0, 1);
-  hipLaunchKernelGGL(k_track_split, dim3(grid_n(n, 1024, 4096)), dim3(kBlock), 0, s, n, Ccur, Cprev, K, b.minv, rep,
-                     b.Kc, b.hkeys, b.hvals, b.hmask, b.owners, b.owner_count, b.is_old);
-  if (rep) {
-    fill_i64(s, b.wcom, 0, n);
-    scatter_add_i64(s, Ccur, b.Kc, n, b.wcom, n);
-  }
+  hipLaunchKernelGGL(k_track_split, dim3(grid_n(n, 1024, 4096)), dim3(kBlock), 0, s, n, Ccur, Cprev, K, b.cb, b.Kc,
+                     b.hkeys, b.hvals, b.hmask, b.owners, b.owner_count);
+  fill_i64(s, b.wb, 0, n);
+  scatter_add_i64(s, Cprev, b.Kc, n, b.wb, n);
+  // best current community of every old label, then the best old label of
+  // every current community
   fill_i64(s, (int64_t*)b.best_w, -1, n);
   fill_u32(s, b.best_vmin, kNone, n);
   const int gp = grid_n(2 * (uint64_t)n);
   for (const bool heavy : {true, false})
-    hipLaunchKernelGGL(k_track_best_w, dim3(gp), dim3(kBlock), 0, s, n, rep, b.minv, b.wcom, b.hkeys, b.hvals,
-                       b.owners, b.owner_count, b.best_w, heavy);
-  hipLaunchKernelGGL(k_track_best_c, dim3(gp), dim3(kBlock), 0, s, n, rep, b.minv, b.wcom, b.hkeys, b.hvals,
-                     b.owners, b.owner_count, b.best_w, b.best_vmin);
+    hipLaunchKernelGGL(k_track_best_w, dim3(gp), dim3(kBlock), 0, s, n, b.cb, b.wb, b.hkeys, b.hvals, b.owners,
+                       b.owner_count, b.best_w, heavy);
+  hipLaunchKernelGGL(k_track_best_c, dim3(gp), dim3(kBlock), 0, s, n, b.cb, b.wb, b.hkeys, b.hvals, b.owners,
+                     b.owner_count, b.minv, b.best_w, b.best_vmin);
   fill_i64(s, (int64_t*)b.cand_w, -1, n);
   fill_u32(s, b.cand_b, kNone, n);
   for (const bool heavy : {true, false})
@@ -1579,7 +1566,7 @@ void track(hipStream_t s, uint32_t n, const uint32_t* Ccur, const uint32_t* Cpre
   hipLaunchKernelGGL(k_track_cand_b, dim3(grid_n(n)), dim3(kBlock), 0, s, n, Ccur, b.best_w, b.best_vmin, b.cand_w,
                      b.cand_b);
   uint32_t* freeflag = b.label;  // scratch reuse
-  hipLaunchKernelGGL(k_track_flags, dim3(grid_n(n)), dim3(kBlock), 0, s, n, Ccur, b.minv, b.cand_b, b.is_old, b.flag,
+  hipLaunchKernelGGL(k_track_flags, dim3(grid_n(n)), dim3(kBlock), 0, s, n, Ccur, b.minv, b.cand_b, b.head, b.flag,
                      freeflag);
   exclusive_scan_u32(s, b.flag, b.rank, n, b.total, b.scan_tmp);
   exclusive_scan_u32(s, freeflag, b.free_rank, n, b.total, b.scan_tmp);
@@ -1588,19 +1575,27 @@ void track(hipStream_t s, uint32_t n, const uint32_t* Ccur, const uint32_t* Cpre
   fill_u8(s, b.matched, 0, n);
   hipLaunchKernelGGL(k_track_label, dim3(grid_n(n)), dim3(kBlock), 0, s, n, Ccur, b.minv, b.cand_b, b.rank,
                      b.free_id, out, b.matched, b.f_gid, b.f_base);
-  // Sigma^t under the tracked labels: with common pairs, each community's
-  // common weight plus its (few) rare pairs'; else a scatter over the vertices
-  if (rep) {
-    hipLaunchKernelGGL(k_track_rare_sigma, dim3(128), dim3(kBlock), 0, s, b.hkeys, b.hvals, b.owners,
-                       b.owner_count, b.wcom);
-    fill_i64(s, S_out, 0, n);
-    hipLaunchKernelGGL(k_track_sigma, dim3(grid_n(n)), dim3(kBlock), 0, s, n, b.minv, b.cand_b, b.rank, b.free_id,
-                       b.wcom, S_out, b.f_gid, b.f_base);
-  } else {
-    launch_sigma_from(s, out, K, n, S_out);
-  }
+  // the heads of the tracked labels, for the next call
+  fill_u32(s, b.head, kNone, n);
+  hipLaunchKernelGGL(k_track_heads, dim3(grid_n(n)), dim3(kBlock), 0, s, n, b.minv, b.cand_b, b.rank, b.free_id,
+                     b.f_gid, b.f_base, b.head);
+  // Sigma^t under the tracked labels
+  launch_sigma_from(s, out, K, n, S_out);
   // the pair table back to empty
   hipLaunchKernelGGL(k_track_clear, dim3(grid_n(n)), dim3(kBlock), 0, s, b.hkeys, b.hvals, b.owners, b.owner_count);
+}
+
+// head[label] of dense static labels: the first vertex of every community
+// (flag[i] = i is its community's minimum vertex) under its output label.
+__global__ __launch_bounds__(kBlock) void k_heads_from_first(uint32_t n, const uint32_t* flag, const uint32_t* out,
+                                                             uint32_t* head) {
+  GRID_STRIDE(i, n) if (flag[i]) head[out[i]] = (uint32_t)i;
+}
+
+void static_heads(hipStream_t s, uint32_t n, const uint32_t* flag, const uint32_t* out, uint32_t* head) {
+  if (n == 0) return;
+  fill_u32(s, head, kNone, n);
+  hipLaunchKernelGGL(k_heads_from_first, dim3(grid_n(n)), dim3(kBlock), 0, s, n, flag, out, head);
 }
 
 }  // namespace lm

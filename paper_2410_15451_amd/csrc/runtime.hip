@@ -154,6 +154,8 @@ struct leiden_graph {
   // auxiliary state (Section 4.4): C, K, Sigma, DeltaSigma
   bool has_state = false;
   Buf st_C, st_K, st_S, st_dS;
+  Buf st_head;               // minimum vertex of every label of st_C (kNone: not a label)
+  bool heads_valid = false;  // st_head describes st_C
   uint32_t stamp = 0;  // iteration stamp, never reused
   BinCfg bincfg = kDefaultBins;  // degree-bin thresholds (tunable)
   float tune_ms = 0;             // probe time of the last autotuning
@@ -165,7 +167,7 @@ struct leiden_graph {
   uint64_t bins0[kBins] = {0};
   uint32_t maxdeg0 = 0;
   // workspace
-  Buf C, K, Kb, Kt, S, S2, size, size2, dS, dS2, dR, dR2, CB, rep, Ctop, Cpre, pend, unproc;
+  Buf C, K, Kb, Kt, S, S2, size, size2, dS, dS2, dR, dR2, CB, rep, Ctop, pend, unproc;
   Buf cls_lists, bin_lists, iter_list, next_list, movers, split_list, split_rest, split_key, split_wide, lab;
   Buf flag, newid, scan_tmp, ctl, small;
   Buf lvA_start, lvA_len, lvA_cols, lvA_w, lvB_start, lvB_len, lvB_cols, lvB_w;
@@ -311,7 +313,6 @@ leiden_status ensure_workspace(leiden_graph* G, hipStream_t s, uint32_t classes)
   CHK(G->CB.reserve(n * u32));
   CHK(G->rep.reserve(n * u32));
   CHK(G->Ctop.reserve(n * u32));
-  CHK(G->Cpre.reserve(n * u32));
   if (G->pend.bytes < n * u32) {
     CHK(G->pend.reserve(n * u32));
     CHK(G->unproc.reserve(n * u32));
@@ -696,9 +697,6 @@ leiden_status run_pass(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, L
   if (st && pass < 16) st->iters[pass] = po.iters, st->subrounds[pass] = po.subrounds;
   // split-all ablation: every community not marked for refinement is split
   if (ro.o.split_all) fill_u8(s, L.dS, 1, nl);
-  // the first pass's labels before Alg. 10 (tracking of a one-pass update)
-  if (pass == 0 && ro.dynamic)
-    HIPCHK(hipMemcpyAsync(G->Cpre.p, L.C, sizeof(uint32_t) * nl, hipMemcpyDeviceToDevice, s));
   subset_renumber(s, nl, L.C, L.S, L.size, L.dS, L.dR, L.rb, dctl(G));
   G->sweeps += 2 * (uint64_t)nl;  // Alg. 10 and the refinement reset of Alg. 8
   CHK(read_ctl(G, s));
@@ -1439,6 +1437,9 @@ leiden_status leiden_static(leiden_graph* G, const leiden_opts* opts, uint32_t* 
   launch_static_relabel(s, G->Ctop.as<uint32_t>(), n, G->tr_minv.as<uint32_t>(), G->flag.as<uint32_t>(),
                         G->newid.as<uint64_t>(), out, G->scan_tmp.p, G->small.as<uint64_t>() + 64,
                         FS ? FS->gid0.as<uint32_t>() : nullptr, FS ? FS->base0.as<uint32_t>() : nullptr);
+  CHK(G->st_head.reserve((size_t)std::max<uint32_t>(n, 1) * 4));
+  static_heads(s, n, G->flag.as<uint32_t>(), out, G->st_head.as<uint32_t>());
+  G->heads_valid = true;
   launch_row_sums_u32(s, rows0(G), n, G->st_K.as<int64_t>());
   launch_sigma_from(s, out, G->st_K.as<int64_t>(), n, G->st_S.as<int64_t>());
   fill_i64(s, G->st_dS.as<int64_t>(), 0, n);
@@ -1717,7 +1718,10 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   tb.best_vmin = G->tr_bv.as<uint32_t>();
   tb.cand_w = G->tr_cw.as<long long>();
   tb.cand_b = G->tr_cb.as<uint32_t>();
-  tb.is_old = G->tr_old.as<uint32_t>();
+  CHK(G->st_head.reserve((size_t)std::max<uint32_t>(n, 1) * 4));
+  tb.head = G->st_head.as<uint32_t>();
+  tb.cb = G->tr_old.as<uint32_t>();
+  if (restart || !G->heads_valid) track_heads_of(s, n, Cprev, tb.head);
   tb.flag = G->tr_flag.as<uint32_t>();
   tb.rank = G->tr_rank.as<uint64_t>();
   tb.free_rank = G->tr_frank.as<uint64_t>();
@@ -1725,7 +1729,7 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   tb.label = G->tr_label.as<uint32_t>();
   tb.matched = G->tr_matched.as<uint8_t>();
   tb.Kc = G->tr_kc.as<int64_t>();
-  tb.wcom = G->tr_wcom.as<int64_t>();
+  tb.wb = G->tr_wcom.as<int64_t>();
   tb.owners = G->tr_owners.as<uint32_t>();
   tb.owner_count = (unsigned int*)(G->small.as<uint64_t>() + 320);
   if (FS) {
@@ -1738,13 +1742,13 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
     G->tr_clean = G->tr_hk.p;
   }
   // after one pass without refinement every label is its community's minimum
-  // vertex (Alg. 10 and the split's component labels), and each community
-  // continues the old community whose label it had before Alg. 10
-  const uint32_t* rep = (G->run_passes == 1 && !G->run_refined0) ? G->Cpre.as<uint32_t>() : nullptr;
+  // vertex (Alg. 10 and the split's component labels)
+  const bool labels_are_min = G->run_passes == 1 && !G->run_refined0;
   tb.scan_tmp = G->scan_tmp.p;
   tb.total = G->small.as<uint64_t>() + 64;
   uint32_t* out = G->flag.as<uint32_t>();  // free after the run
-  track(s, n, G->Ctop.as<uint32_t>(), Cprev, Kt, out, G->st_S.as<int64_t>(), rep, tb);
+  track(s, n, G->Ctop.as<uint32_t>(), Cprev, Kt, out, G->st_S.as<int64_t>(), labels_are_min, tb);
+  G->heads_valid = true;
   // new state: C^t, K^t, Sigma^t by C^t, DeltaSigma^t kept for continued labels
   HIPCHK(hipMemcpyAsync(G->st_K.p, Kt, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s));
   dsig_out(s, n, tb.matched, dSig, G->st_dS.as<int64_t>());
@@ -1916,6 +1920,7 @@ leiden_status leiden_state_import(leiden_graph* G, const uint32_t* C, const int6
   CHK(copy_in(s, G->st_dS.p, dSigma, sizeof(int64_t) * n, 0));
   HIPCHK(hipStreamSynchronize(s));
   G->has_state = true;
+  G->heads_valid = false;
   return LEIDEN_OK;
 }
 
