@@ -172,6 +172,7 @@ def run_forest(args, binding, inputs):
     keep = ssample
     host = {}
     tot = {"entries": 0, "entries_after": 0, "static_s": 0.0, "update_s": 0.0, "gen_s": 0.0, "updates": 0}
+    tunes = []
     log("forest: %d graphs, %d vertices, %d forests" % (args.graphs, int(sizes.sum()), len(chunks)))
     for c, qs in enumerate(chunks):
         t0 = time.time()
@@ -196,6 +197,7 @@ def run_forest(args, binding, inputs):
         del offs, cols, w
         torch.cuda.empty_cache()
         tot["gen_s"] += time.time() - t0
+        tune = F.autotune()  # degree-bin thresholds and the aggregation's emit table for this forest
         F.static(compute_modularity=0)  # warm-up: workspace
         torch.cuda.synchronize()
         ta = time.perf_counter()
@@ -226,7 +228,8 @@ def run_forest(args, binding, inputs):
             % (c, len(qs), nnz, (tb - ta) * 1e3, (td - tc) * 1e3, dels.shape[0] + ins.shape[0], st["ms_total"], st["ms_batch"],
                st["passes"], int((fpasses > 1).sum()), st["iters"], st["affected"], st["moves"],
                st["edges_scanned"]))
-        log("forest %d: update work %s, subrounds %s" % (c, st["work"], st["subrounds"]))
+        log("forest %d: update work %s, subrounds %s; tuning %s" % (c, st["work"], st["subrounds"], tune))
+        tunes.append(tune)
         F.close()
         del dels, ins
         torch.cuda.empty_cache()
@@ -271,7 +274,7 @@ def run_forest(args, binding, inputs):
                                     "update_edges_per_s": single_rate},
             "speedup_update_vs_one_at_a_time": forest_rate / single_rate,
             "speedup_static_vs_one_at_a_time": (tot["entries"] / tot["static_s"]) / (s_entries / s_static),
-            "identical_memberships_sample": bool(same)}
+            "identical_memberships_sample": bool(same), "autotuned": tunes}
 
 
 def run_stability(args, binding, inputs):
@@ -279,7 +282,7 @@ def run_stability(args, binding, inputs):
     delete a random batch (G^1), then insert the same edges back (G^2 = G^0),
     updating the communities each time; report the share of vertices whose
     community ID on G^2 equals the one of the static run on G^0, for batch
-    sizes 1e-6 .. 1e-1 |E| and the three dynamic modes (tracking keeps IDs)."""
+    sizes 1e-7 .. 1e-1 |E| and the three dynamic modes (tracking keeps IDs)."""
     import numpy as np
     g = inputs.rmat(args.scale, seed=inputs.BASE_SEED + 2)
     keys = g.undirected_keys()
@@ -289,7 +292,7 @@ def run_stability(args, binding, inputs):
     out = {}
     for mode in ("nd", "ds", "df"):
         row = {}
-        for k, f in enumerate((1e-6, 1e-5, 1e-4, 1e-3, 1e-2, 1e-1)):
+        for k, f in enumerate((1e-7, 1e-6, 1e-5, 1e-4, 1e-3, 1e-2, 1e-1)):
             nb = max(1, inputs.batch_size_for(g.nnz, f))
             dels, _ = inputs.random_batch(g.n, keys, nb, seed=1300 + k, ins_frac=0.0)
             ins = np.concatenate([dels, np.ones((dels.shape[0], 1), np.uint32)], axis=1)

@@ -158,6 +158,7 @@ typedef struct {
    * tables only take that path more often and never change the result. */
   uint32_t agg_emit_slots;
   double probe_ms; /* time of the autotuning probe with these thresholds (0 if never tuned) */
+  double agg_probe_ms; /* time of the aggregation probe with this emit table (0 if never tuned) */
 } leiden_tuning;
 
 leiden_status leiden_get_tuning(leiden_graph* g, leiden_tuning* out);
@@ -167,9 +168,11 @@ leiden_status leiden_set_tuning(leiden_graph* g, const leiden_tuning* t);
 /* Choose the thresholds for this graph by measurement: coordinate descent
  * over each threshold at 1/2, 3/4, 3/2 and 2 times its value, timing one
  * decide-only local-moving iteration over every vertex from singleton
- * communities (on opts->stream); keeps the fastest setting in the handle and
- * returns it in *out (may be NULL).  The handle's graph and state are
- * unchanged. */
+ * communities (on opts->stream); then the aggregation's emit table
+ * (agg_emit_slots) among 4096, 2048, 1024 and 512 slots, timing one
+ * aggregation of the graph under a probe membership (every vertex with its
+ * smallest neighbour).  Keeps the fastest setting in the handle and returns
+ * it in *out (may be NULL).  The handle's graph and state are unchanged. */
 leiden_status leiden_autotune(leiden_graph* g, const leiden_opts* opts, leiden_tuning* out);
 
 /* Symbol of a leiden_kernel as profilers list it (NULL for an unknown value). */

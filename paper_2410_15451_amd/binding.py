@@ -83,11 +83,11 @@ class LeidenStats(ctypes.Structure):
 
 class LeidenTuning(ctypes.Structure):
     _fields_ = [("bin_max_degree", ctypes.c_uint32 * 5), ("agg_emit_slots", ctypes.c_uint32),
-                ("probe_ms", ctypes.c_double)]
+                ("probe_ms", ctypes.c_double), ("agg_probe_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {"bin_max_degree": list(self.bin_max_degree), "agg_emit_slots": self.agg_emit_slots,
-                "probe_ms": self.probe_ms}
+                "probe_ms": self.probe_ms, "agg_probe_ms": self.agg_probe_ms}
 
 
 class LeidenBatchItem(ctypes.Structure):

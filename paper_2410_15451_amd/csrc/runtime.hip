@@ -159,6 +159,7 @@ struct leiden_graph {
   uint32_t stamp = 0;  // iteration stamp, never reused
   BinCfg bincfg = kDefaultBins;  // degree-bin thresholds (tunable)
   float tune_ms = 0;             // probe time of the last autotuning
+  float tune_agg_ms = 0;         // aggregation probe time with the chosen emit table
   uint32_t emit_slots = 4096;    // LDS table of the aggregation emit step (power of two, 16..4096)
   uint64_t sweeps = 0;           // vertices of the per-vertex passes of the current call
   uint32_t run_passes = 0;       // passes of the last run of Alg. 4
@@ -719,6 +720,33 @@ leiden_status run_pass(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, L
 }
 
 // Aggregate level g (labels L.C renumbered densely) into the next level.
+// The aggregation's work buffers of the handle.
+AggBufs agg_bufs(leiden_graph* G, uint64_t* total) {
+  AggBufs ab{};
+  ab.comm_count = G->agg_count.as<uint32_t>();
+  ab.comm_off = G->agg_off.as<uint64_t>();
+  ab.comm_fill = G->agg_fill.as<uint32_t>();
+  ab.members = G->agg_members.as<uint32_t>();
+  ab.comm_deg = G->agg_deg.as<uint64_t>();
+  ab.cap_off = G->agg_cap.as<uint64_t>();
+  ab.total = total;
+  ab.scan_tmp = G->scan_tmp.p;
+  ab.small_lists = G->agg_lists.as<uint32_t>();
+  ab.big_info = G->agg_bigcap.as<uint64_t>();
+  ab.bigc = G->agg_tbl.p;
+  ab.items = G->agg_items.p;
+  ab.item_cap = kAggItems;
+  ab.stage_cnt = (unsigned int*)((char*)G->agg_tbl.p + 32 * (size_t)G->n);
+  ab.self_acc = (unsigned long long*)((char*)G->agg_tbl.p + 40 * (size_t)G->n);
+  ab.skeys = G->agg_keys.as<uint32_t>();
+  ab.svals = G->agg_vals.as<unsigned long long>();
+  ab.smat = G->agg_mat.as<uint16_t>();
+  ab.scap = G->agg_keys.bytes / 4;
+  ab.mcap = G->agg_mat.bytes / 2;
+  ab.emit_cap = G->emit_slots;
+  return ab;
+}
+
 template <typename W>
 leiden_status next_level(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, LevelState& L, bool useA,
                          Rows<int64_t>* out, uint32_t* nc_out) {
@@ -745,28 +773,7 @@ leiden_status next_level(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
   Buf& bl = useA ? G->lvA_len : G->lvB_len;
   Buf& bc = useA ? G->lvA_cols : G->lvB_cols;
   Buf& bw = useA ? G->lvA_w : G->lvB_w;
-  AggBufs ab{};
-  ab.comm_count = G->agg_count.as<uint32_t>();
-  ab.comm_off = G->agg_off.as<uint64_t>();
-  ab.comm_fill = G->agg_fill.as<uint32_t>();
-  ab.members = G->agg_members.as<uint32_t>();
-  ab.comm_deg = G->agg_deg.as<uint64_t>();
-  ab.cap_off = G->agg_cap.as<uint64_t>();
-  ab.total = total;
-  ab.scan_tmp = G->scan_tmp.p;
-  ab.small_lists = G->agg_lists.as<uint32_t>();
-  ab.big_info = G->agg_bigcap.as<uint64_t>();
-  ab.bigc = G->agg_tbl.p;
-  ab.items = G->agg_items.p;
-  ab.item_cap = kAggItems;
-  ab.stage_cnt = (unsigned int*)((char*)G->agg_tbl.p + 32 * (size_t)G->n);
-  ab.self_acc = (unsigned long long*)((char*)G->agg_tbl.p + 40 * (size_t)G->n);
-  ab.skeys = G->agg_keys.as<uint32_t>();
-  ab.svals = G->agg_vals.as<unsigned long long>();
-  ab.smat = G->agg_mat.as<uint16_t>();
-  ab.scap = G->agg_keys.bytes / 4;
-  ab.mcap = G->agg_mat.bytes / 2;
-  ab.emit_cap = G->emit_slots;
+  AggBufs ab = agg_bufs(G, total);
   // K of the next level goes to whichever of the two K buffers is not current
   int64_t* Kn = L.K == G->K.as<int64_t>() ? G->Kb.as<int64_t>() : G->K.as<int64_t>();
   count_units(s, g.len, nullptr, nl, G->edge_parts.as<unsigned long long>(), kWAggIn);
@@ -1075,6 +1082,56 @@ leiden_status probe_decide(leiden_graph* G, hipStream_t s, const leiden_opts& o,
   return LEIDEN_OK;
 }
 
+// Probe membership for timing the aggregation: every vertex joins its
+// smallest neighbour (or stays alone), one wavefront per row.  Communities
+// then range from pairs to the stars of low-ID hubs.
+__global__ __launch_bounds__(kBlock) void k_probe_min_label(Rows<uint32_t> g, uint32_t n, uint32_t* C) {
+  const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const uint32_t lane = threadIdx.x % kWave;
+  const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
+  for (uint64_t i = wave; i < n; i += nwaves) {
+    uint32_t m = (uint32_t)i;
+    const int64_t s0 = g.start[i];
+    for (uint32_t e = lane; e < g.len[i]; e += kWave) m = min(m, g.cols[s0 + e]);
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) m = min(m, (uint32_t)__shfl_xor(m, o));
+    if (lane == 0) C[i] = m;
+  }
+}
+
+// One aggregation (Alg. 9) of the input graph under the probe membership with
+// an emit table of `slots` slots, timed with events; the handle's graph and
+// state are not touched (the level buffers are scratch between calls).
+leiden_status probe_aggregate(leiden_graph* G, hipStream_t s, uint32_t slots, float* ms_out) {
+  const uint32_t n = G->n;
+  uint32_t* C = G->CB.as<uint32_t>();
+  const uint64_t nwave_blocks = std::min<uint64_t>(16384, (n + kBlock / kWave - 1) / (kBlock / kWave));
+  hipLaunchKernelGGL(k_probe_min_label, dim3((uint32_t)std::max<uint64_t>(nwave_blocks, 1)), dim3(kBlock), 0, s,
+                     rows0(G), n, C);
+  uint64_t* total = G->small.as<uint64_t>() + 64;
+  dense_renumber(s, n, C, G->flag.as<uint32_t>(), G->newid.as<uint64_t>(), total, G->scan_tmp.p);
+  uint64_t nc = 0;
+  CHK(read_dev(s, &nc, total));
+  AggBufs ab = agg_bufs(G, total);
+  ab.emit_cap = slots;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, s));
+  const int rc = aggregate<uint32_t>(s, rows0(G), n, C, (uint32_t)nc, ab, G->lvA_start.as<int64_t>(),
+                                     G->lvA_len.as<uint32_t>(), G->lvA_cols.as<uint32_t>(), G->lvA_w.as<int64_t>(),
+                                     G->Kb.as<int64_t>(), dctl(G));
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != 0) return fail(LEIDEN_EDEVICE, "aggregation probe failed (%d)", rc);
+  *ms_out = ms;
+  return LEIDEN_OK;
+}
+
 // Level-0 degree bins after a change of thresholds.
 leiden_status refresh_bins0(leiden_graph* G) {
   hipStream_t s = G->own;
@@ -1130,6 +1187,7 @@ leiden_status leiden_get_tuning(leiden_graph* G, leiden_tuning* out) {
   for (int b = 0; b < kBins - 1; ++b) out->bin_max_degree[b] = G->bincfg.max_deg[b];
   out->agg_emit_slots = G->emit_slots;
   out->probe_ms = G->tune_ms;
+  out->agg_probe_ms = G->tune_agg_ms;
   return LEIDEN_OK;
 }
 
@@ -1202,6 +1260,22 @@ leiden_status leiden_autotune(leiden_graph* G, const leiden_opts* opts, leiden_t
   G->bincfg = cur;
   G->tune_ms = cur_ms;
   CHK(refresh_bins0(G));
+  // the aggregation's emit table: the fastest of a few sizes (the default
+  // unless another is clearly faster)
+  uint32_t best_slots = G->emit_slots;
+  float best_agg = 0;
+  for (const uint32_t slots : {4096u, 2048u, 1024u, 512u}) {
+    float a = 0, b = 0;
+    CHK(probe_aggregate(G, s, slots, &a));
+    CHK(probe_aggregate(G, s, slots, &b));
+    const float t = std::min(a, b);
+    if (slots == 4096u || t < best_agg * 0.98f) {
+      best_slots = slots;
+      best_agg = t;
+    }
+  }
+  G->emit_slots = best_slots;
+  G->tune_agg_ms = best_agg;
   if (out) CHK(leiden_get_tuning(G, out));
   return LEIDEN_OK;
 }

@@ -338,10 +338,23 @@ ASYNC_TOL_PLANTED = 2e-2
 ASYNC_TOL_CHAIN = 1e-2
 
 
+def _communities_connected(g, C):
+    """Every community induces a connected subgraph (Leiden's guarantee,
+    which the refinement phase provides): the components of the graph kept
+    to intra-community edges are exactly the communities."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+    src = np.repeat(np.arange(g.n), np.diff(g.offs))
+    m = C[src] == C[g.cols]
+    A = csr_matrix((np.ones(int(m.sum())), (src[m], g.cols[m].astype(np.int64))), shape=(g.n, g.n))
+    return connected_components(A, directed=False)[0] == np.unique(C).shape[0]
+
+
 def _check_async_result(orc, g, r):
     C = r.membership
     assert C.shape == (g.n,) and int(C.max()) < g.n
     assert abs(r.q - orc.modularity(g, C)) <= 1e-12
+    assert _communities_connected(g, C)
 
 
 @pytest.mark.parametrize("which", ["planted", "rmat12", "rmat16"])
@@ -423,6 +436,9 @@ def test_autotune_and_invalid_thresholds(lm, orc):
     b = t["bin_max_degree"]
     assert all(x < y for x, y in zip(b, b[1:])) and t["probe_ms"] > 0
     assert all(x <= cap for x, cap in zip(b, (15, 63, 255, 1023, 4095)))
+    # the aggregation's emit table is tuned too
+    assert t["agg_emit_slots"] in (512, 1024, 2048, 4096) and t["agg_probe_ms"] > 0
+    assert G.tuning()["agg_emit_slots"] == t["agg_emit_slots"]
     r = G.static()
     C, q, _ = orc.static(g)
     assert np.array_equal(r.membership, C) and r.q == q
@@ -603,3 +619,30 @@ def test_chung_lu_power_law(lm, orc):
         batches.append((d, i))
         keys = inputs.keys_after_batch(keys, d, i)
     _run_updates(lm, orc, g, batches, "df")
+
+
+@pytest.mark.parametrize("frac", [1e-3, 1e-1])
+def test_stability_delete_reinsert(lm, orc, frac):
+    """The stability experiment (Section 4.1) through the library: from the
+    static result on G^0, delete a random batch, then insert the same edges
+    back; every step equals the oracle, so the share of vertices that keep
+    their static community ID is the oracle's."""
+    g = inputs.rmat(12, seed=61)
+    nb = max(1, inputs.batch_size_for(g.nnz, frac))
+    dels, _ = inputs.random_batch(g.n, g.undirected_keys(), nb, seed=62, ins_frac=0.0)
+    ins = np.concatenate([dels, np.ones((dels.shape[0], 1), np.uint32)], axis=1)
+    none2, none3 = np.zeros((0, 2), np.uint32), np.zeros((0, 3), np.uint32)
+    G = _graph(lm, g)
+    C0 = G.static().membership.copy()
+    r1 = G.update(dels, none3, mode="df")
+    r2 = G.update(none2, ins, mode="df")
+    oC0, _, _ = orc.static(g)
+    st = orc.initial_state(g, oC0)
+    g1, dw = orc.apply_batch(g, dels, none3)
+    oC1, st, _, _ = orc.update(g1, dw, none3, st, "df")
+    g2, _ = orc.apply_batch(g1, none2, ins)
+    oC2, st, _, _ = orc.update(g2, np.zeros((0, 3), np.uint32), ins, st, "df")
+    assert np.array_equal(C0, oC0) and np.array_equal(r1.membership, oC1) and np.array_equal(r2.membership, oC2)
+    assert np.array_equal(g2.offs, g.offs) and np.array_equal(g2.cols, g.cols)  # G^2 = G^0
+    match = float(np.mean(r2.membership == C0))
+    assert 0.0 < match <= 1.0
