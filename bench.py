@@ -384,8 +384,8 @@ def run_ablation(args, binding, inputs):
 
 
 def run_serving(args, binding, inputs):
-    """Serving form: eight tenant R-MAT graphs (scales 20, 20, 21, 21, 22, 22,
-    23, 23; edge factor 16; unit weights; made on the GPU) in a server with
+    """Serving form: tenant R-MAT graphs (by default scales 20, 20, 21, 21, 22,
+    22, 23, 23; edge factor 16; unit weights; made on the GPU) in a server with
     args.streams workers.  Admission: a budget that holds seven of the eight
     estimated footprints refuses the eighth; the measured server admits all.
     Requests: target graph uniform, B = round(exp(U[ln 1e2, ln 1e6]))
@@ -399,7 +399,7 @@ def run_serving(args, binding, inputs):
     import numpy as np
     import torch
     dev = torch.device("cuda:0")
-    scales = [20, 20, 21, 21, 22, 22, 23, 23]
+    scales = [int(x) for x in args.tenant_scales.split(",")]
     loads = [float(x) for x in args.loads.split(",")]
     nreq = args.requests
     nwarm = args.warm_requests
@@ -535,6 +535,7 @@ def main():
     ap.add_argument("--requests", type=int, default=500, help="serving: measured requests per load")
     ap.add_argument("--warm-requests", type=int, default=50, help="serving: back-to-back warm-up requests")
     ap.add_argument("--loads", default="0.3,0.5,0.7,0.9", help="serving: offered loads (fractions of capacity)")
+    ap.add_argument("--tenant-scales", default="20,20,21,21,22,22,23,23", help="serving: R-MAT scales of the tenants")
     ap.add_argument("--marker", type=int, default=0,
                     help="launch a spin kernel right before and after the timed steps (profile windowing)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
