@@ -537,7 +537,8 @@ def main():
     ap.add_argument("--loads", default="0.3,0.5,0.7,0.9", help="serving: offered loads (fractions of capacity)")
     ap.add_argument("--tenant-scales", default="20,20,21,21,22,22,23,23", help="serving: R-MAT scales of the tenants")
     ap.add_argument("--marker", type=int, default=0,
-                    help="launch a spin kernel right before and after the timed steps (profile windowing)")
+                    help="launch a spin kernel right before and after the timed static run and the timed "
+                         "update steps (profile windows 0 and 1)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (reference for rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -594,10 +595,15 @@ def main():
     # static Leiden (twice: the first run also allocates the workspace)
     G.static(out=out, **opts)
     torch.cuda.synchronize()
+    if args.marker:
+        torch.cuda._sleep(1000)
     t = time.perf_counter()
     rs = G.static(out=out, **opts)
     torch.cuda.synchronize()
     t_static = time.perf_counter() - t
+    if args.marker:
+        torch.cuda._sleep(1000)
+        torch.cuda.synchronize()
     q_static = G.modularity(out)
     log("static: %.2f ms, passes %d, iters %s, q=%.5f" % (t_static * 1e3, rs.stats["passes"], rs.stats["iters"],
                                                           q_static))
@@ -620,11 +626,13 @@ def main():
         torch.cuda._sleep(1000)
     ev0.record(stream)
     tw = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         dt, r = run_update(args.mode, timed_kernel=args.timed_kernel)
         lat.append(dt)
         edges += r.stats["nnz"]
         stats.append(r.stats)
+        if args.marker and (k + 1) % 5 == 0:  # progress under a profiler (slow, serialised dispatches)
+            log("step %d done" % (k + 1))
     ev1.record(stream)
     if args.marker:
         torch.cuda._sleep(1000)

@@ -1,19 +1,21 @@
 #!/usr/bin/env python3
 """Summaries of rocprofv3 CSV output for the Leiden library.
 
-kernels DIR [--between REGEX] [--top N]
+kernels DIR [--between REGEX] [--window K] [--top N]
     Per-kernel dispatch count, total and average duration from the kernel
-    trace under DIR.  With --between, only the dispatches strictly between the
-    first two dispatches whose name matches REGEX are counted (bench.py
-    launches a marker kernel right before and right after its timed steps).
+    trace under DIR.  With --between, only the dispatches strictly between
+    marker dispatches 2K and 2K + 1 (those whose name matches REGEX) are
+    counted: bench.py --marker launches a marker kernel right before and
+    right after its timed static run (window 0) and its timed update steps
+    (window 1).
 
-counters FETCH_DIR WRITE_DIR --kernel NAME --calib-bytes B [--between REGEX] [--steps K]
+counters FETCH_DIR WRITE_DIR --kernel NAME --calib-bytes B [--between REGEX] [--window K] [--steps S]
     Average FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the kernel whose
     name starts with NAME, each scaled by what the same counter reads for the
     first device copy of the run (bench.py's calibration copy of B bytes,
     which reads and writes B bytes), and the resulting HBM bytes per launch
     as JSON.  NAME '*' sums every dispatch of the window instead and reports
-    the HBM bytes per step (the window holding K steps).
+    the HBM bytes per step (the window holding S steps).
 
 Reads only rocprofv3's CSV files (--output-format csv).
 """
@@ -45,16 +47,19 @@ def _short(name):
     return re.sub(r"\(.*", "", name).strip()
 
 
+WINDOW = 0  # which pair of marker dispatches bounds the window (--window)
+
+
 def _window(names, between):
-    """Index range (lo, hi) of the dispatches between the first two marker
-    dispatches, or the whole list."""
+    """Index range (lo, hi) of the dispatches between marker dispatches
+    2K and 2K + 1 (K = --window), or the whole list."""
     if not between:
         return 0, len(names)
     rx = re.compile(between)
     marks = [i for i, nm in enumerate(names) if rx.search(nm)]
-    if len(marks) < 2:
-        sys.exit("fewer than two dispatches match %r" % between)
-    return marks[0] + 1, marks[1]
+    if len(marks) < 2 * WINDOW + 2:
+        sys.exit("fewer than %d dispatches match %r" % (2 * WINDOW + 2, between))
+    return marks[2 * WINDOW] + 1, marks[2 * WINDOW + 1]
 
 
 def kernels(args):
@@ -156,7 +161,13 @@ def main():
     c.add_argument("--steps", type=int, default=1)
     c.add_argument("--calib-bytes", type=float, required=True)
     c.add_argument("--between", default="")
+    for p in (k, c):
+        p.add_argument("--window", type=int, default=0,
+                       help="marker pair bounding the window (bench.py --marker: 0 = the timed static run, "
+                            "1 = the timed update steps)")
     a = ap.parse_args()
+    global WINDOW
+    WINDOW = a.window
     (kernels if a.cmd == "kernels" else counters)(a)
 
 
