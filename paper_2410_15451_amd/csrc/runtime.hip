@@ -190,16 +190,9 @@ struct leiden_graph {
   bool rowcnt_ready = false;
   Ctl* hctl = nullptr;  // pinned mirror
   KTimer kt;
-  DecideStreams dstreams{};  // side streams of the decide kernels (created with the handle)
-  bool dstreams_ready = false;
   ForestState* forest = nullptr;  // a forest of independent graphs, or null
   ~leiden_graph() {
     delete forest;
-    if (dstreams_ready) {
-      for (hipStream_t& x : dstreams.aux) (void)hipStreamDestroy(x);
-      (void)hipEventDestroy(dstreams.fork);
-      for (hipEvent_t& e : dstreams.join) (void)hipEventDestroy(e);
-    }
     if (kt.ready)
       for (hipEvent_t& e : kt.ev) (void)hipEventDestroy(e);
     if (hctl) (void)hipHostFree(hctl);
@@ -586,8 +579,7 @@ leiden_status local_move(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
       launch_subround_reset(s, ctl);
       launch_bin(s, G->cls_lists.as<uint32_t>() + (size_t)k * nl, &ctl->cls_count[k], nl, g.len, in_range,
                  G->bin_lists.as<uint32_t>(), (size_t)nl, G->bincfg, G->hub_items.as<unsigned long long>(), ctl);
-      launch_decide_all<W, false>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, maxdeg,
-                                  &G->dstreams);
+      launch_decide_all<W, false>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, maxdeg);
       ApplyParams ap{};
       ap.start = g.start;
       ap.len = g.len;
@@ -660,8 +652,7 @@ leiden_status refine(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, Lev
     launch_bin(s, G->cls_lists.as<uint32_t>() + (size_t)r * nl, &ctl->cls_count[r], nl, g.len, nullptr,
                G->bin_lists.as<uint32_t>(), (size_t)nl, G->bincfg, G->hub_items.as<unsigned long long>(), ctl);
     dp.colour = r;
-    launch_decide_all<W, true>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, maxdeg,
-                               &G->dstreams);
+    launch_decide_all<W, true>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, maxdeg);
     launch_apply_refine(s, L.C, L.S, L.K, L.size, G->movers.as<Mover>(), ctl, nl);
   }
   return LEIDEN_OK;
@@ -1068,8 +1059,7 @@ leiden_status probe_decide(leiden_graph* G, hipStream_t s, const leiden_opts& o,
     launch_subround_reset(s, ctl);
     launch_bin(s, G->cls_lists.as<uint32_t>() + (size_t)k * n, &ctl->cls_count[k], n, G->g.len, nullptr,
                G->bin_lists.as<uint32_t>(), (size_t)n, G->bincfg, G->hub_items.as<unsigned long long>(), ctl);
-    launch_decide_all<uint32_t, false>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)n, ctl->bin_count, bins, maxdeg,
-                                       &G->dstreams);
+    launch_decide_all<uint32_t, false>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)n, ctl->bin_count, bins, maxdeg);
   }
   HIPCHK(hipEventRecord(e1, s));
   HIPCHK(hipEventSynchronize(e1));
@@ -1307,15 +1297,6 @@ leiden_status leiden_graph_create(int device, uint32_t n, uint64_t nnz, const in
     return bail(fail(LEIDEN_EDEVICE, "stream creation failed"));
   if (hipHostMalloc((void**)&G->hctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess)
     return bail(fail(LEIDEN_EDEVICE, "pinned allocation failed"));
-  {
-    DecideStreams& d = G->dstreams;
-    bool ok = hipEventCreateWithFlags(&d.fork, hipEventDisableTiming) == hipSuccess;
-    for (int k = 0; k < 3 && ok; ++k)
-      ok = hipStreamCreateWithFlags(&d.aux[k], hipStreamNonBlocking) == hipSuccess &&
-           hipEventCreateWithFlags(&d.join[k], hipEventDisableTiming) == hipSuccess;
-    if (!ok) return bail(fail(LEIDEN_EDEVICE, "stream creation failed"));
-    G->dstreams_ready = true;
-  }
   hipStream_t s = G->own;
   AllocScope alloc_scope(s);
   leiden_status st;
