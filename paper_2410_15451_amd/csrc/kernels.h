@@ -142,10 +142,21 @@ inline uint32_t hub_pick_segs(uint32_t maxdeg) {
 void launch_bin(hipStream_t s, const uint32_t* list, const unsigned int* count, uint32_t n_upper, const uint32_t* len,
                 const uint8_t* in_range, uint32_t* bin_lists, size_t stride, const BinCfg& cfg,
                 unsigned long long* hub_items, Ctl* ctl);
-// maxdeg: largest degree of the level (sizes the hub kernels)
+// Side streams of a sub-round's decide kernels: the degree bins read the same
+// state and only append movers, so their kernels can run side by side
+// (forked from and joined back into the call's stream by events).  Only used
+// while no other call of the process is running: the streams then outnumber
+// the hardware queues, and event waits that several threads submit into
+// shared in-order queues can wait on each other in a cycle.
+struct DecideStreams {
+  hipStream_t aux[3];
+  hipEvent_t fork, join[3];
+};
+// maxdeg: largest degree of the level (sizes the hub kernels); ds may be null
+// (everything on s)
 template <typename W, bool REFINE>
 void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, size_t stride, unsigned int* bin_counts,
-                       const uint64_t* bin_upper, uint32_t maxdeg);
+                       const uint64_t* bin_upper, uint32_t maxdeg, const DecideStreams* ds);
 // long_rows: the level has rows longer than the wavefront path handles
 // items_upper: upper bound of the marking work items (entries / 64 + vertices)
 void launch_apply_moves(hipStream_t s, const ApplyParams& p, uint32_t n_upper, uint64_t items_upper);

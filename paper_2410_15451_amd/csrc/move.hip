@@ -995,10 +995,21 @@ void launch_bin(hipStream_t s, const uint32_t* list, const unsigned int* count, 
 
 template <typename W, bool REFINE>
 void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, size_t stride, unsigned int* bin_counts,
-                       const uint64_t* bin_upper, uint32_t maxdeg) {
+                       const uint64_t* bin_upper, uint32_t maxdeg, const DecideStreams* ds) {
   // bin 0: 8 lanes / 16 slots, bin 1: 32 / 64, bin 2: 64 / 256 (in one
-  // launch); bin 3: block / 1024, bin 4: block / 4096, bin 5: hubs (all
-  // blocks per hub); all on the call's stream
+  // launch on s); bin 3: block / 1024, bin 4: block / 4096, bin 5: hubs (all
+  // blocks per hub), each on its own side stream when ds is given
+  bool forked = false;
+  auto side = [&](int k) -> hipStream_t {
+    if (!ds) return s;
+    if (!forked) {
+      (void)hipEventRecord(ds->fork, s);
+      forked = true;
+    }
+    (void)hipStreamWaitEvent(ds->aux[k], ds->fork, 0);
+    return ds->aux[k];
+  };
+  bool used[3] = {false, false, false};
   {
     SmallBins sb{};
     uint32_t* nb[3] = {&sb.n0, &sb.n1, &sb.n2};
@@ -1016,7 +1027,8 @@ void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, si
     DecideParams<W> q = p;
     q.list = bin_lists + (size_t)b * stride;
     q.count = bin_counts + b;
-    const hipStream_t t = s;
+    const hipStream_t t = side(b - 3);
+    used[b - 3] = true;
     switch (b) {
       case 3:
         hipLaunchKernelGGL((k_decide_block<1024, W, REFINE>), dim3(grid_for(bin_upper[b], 1, 2048)), dim3(kBlock), 0,
@@ -1037,16 +1049,22 @@ void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, si
       }
     }
   }
+  if (ds)
+    for (int k = 0; k < 3; ++k)
+      if (used[k]) {
+        (void)hipEventRecord(ds->join[k], ds->aux[k]);
+        (void)hipStreamWaitEvent(s, ds->join[k], 0);
+      }
 }
 
 template void launch_decide_all<uint32_t, false>(hipStream_t, DecideParams<uint32_t>, uint32_t*, size_t,
-                                                 unsigned int*, const uint64_t*, uint32_t);
+                                                 unsigned int*, const uint64_t*, uint32_t, const DecideStreams*);
 template void launch_decide_all<uint32_t, true>(hipStream_t, DecideParams<uint32_t>, uint32_t*, size_t,
-                                                unsigned int*, const uint64_t*, uint32_t);
+                                                unsigned int*, const uint64_t*, uint32_t, const DecideStreams*);
 template void launch_decide_all<int64_t, false>(hipStream_t, DecideParams<int64_t>, uint32_t*, size_t,
-                                                unsigned int*, const uint64_t*, uint32_t);
+                                                unsigned int*, const uint64_t*, uint32_t, const DecideStreams*);
 template void launch_decide_all<int64_t, true>(hipStream_t, DecideParams<int64_t>, uint32_t*, size_t, unsigned int*,
-                                               const uint64_t*, uint32_t);
+                                               const uint64_t*, uint32_t, const DecideStreams*);
 
 void launch_apply_moves(hipStream_t s, const ApplyParams& p, uint32_t n_upper, uint64_t items_upper) {
   hipLaunchKernelGGL(k_apply_moves, dim3(grid_for(n_upper, kBlock, 1024)), dim3(kBlock), 0, s, p);

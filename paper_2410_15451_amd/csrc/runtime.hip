@@ -1,6 +1,7 @@
 // Host runtime and C-ABI of the gfx950 Leiden library: the graph handle, its
 // device workspace, and the pass loop of Alg. 4 driving the kernels.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -41,6 +42,19 @@ leiden_status fail(leiden_status st, const char* fmt, ...) {
     leiden_status s_ = (expr);                 \
     if (s_ != LEIDEN_OK) return s_;            \
   } while (0)
+
+// Calls of the library running in the process right now (static and update
+// runs, autotuning): the decide kernels use the handle's side streams only
+// while a call runs alone.
+std::atomic<int> g_in_flight{0};
+struct InFlight {
+  InFlight() { g_in_flight.fetch_add(1); }
+  ~InFlight() { g_in_flight.fetch_sub(1); }
+};
+
+// Side streams for a level of nl vertices: levels large enough to fill the
+// GPU with several bins at once, and no other call running.
+const DecideStreams* side_streams(leiden_graph* G, uint32_t nl);
 
 // The stream of the current API call on this thread (null outside calls).
 // Every kernel that reads a handle's buffers runs on that stream or on a side
@@ -190,15 +204,30 @@ struct leiden_graph {
   bool rowcnt_ready = false;
   Ctl* hctl = nullptr;  // pinned mirror
   KTimer kt;
+  DecideStreams dstreams{};  // side streams of the decide kernels (created with the handle)
+  bool dstreams_ready = false;
   ForestState* forest = nullptr;  // a forest of independent graphs, or null
   ~leiden_graph() {
     delete forest;
+    if (dstreams_ready) {
+      for (hipStream_t& x : dstreams.aux) (void)hipStreamDestroy(x);
+      (void)hipEventDestroy(dstreams.fork);
+      for (hipEvent_t& e : dstreams.join) (void)hipEventDestroy(e);
+    }
     if (kt.ready)
       for (hipEvent_t& e : kt.ev) (void)hipEventDestroy(e);
     if (hctl) (void)hipHostFree(hctl);
     if (own) (void)hipStreamDestroy(own);
   }
 };
+
+namespace {
+const DecideStreams* side_streams(leiden_graph* G, uint32_t nl) {
+  constexpr uint32_t kSideMinVertices = 1u << 20;
+  if (!G->dstreams_ready || nl < kSideMinVertices || g_in_flight.load() != 1) return nullptr;
+  return &G->dstreams;
+}
+}  // namespace
 
 namespace lm {
 thread_local KTimer* tl_ktimer = nullptr;
@@ -579,7 +608,8 @@ leiden_status local_move(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
       launch_subround_reset(s, ctl);
       launch_bin(s, G->cls_lists.as<uint32_t>() + (size_t)k * nl, &ctl->cls_count[k], nl, g.len, in_range,
                  G->bin_lists.as<uint32_t>(), (size_t)nl, G->bincfg, G->hub_items.as<unsigned long long>(), ctl);
-      launch_decide_all<W, false>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, maxdeg);
+      launch_decide_all<W, false>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, maxdeg,
+                                  side_streams(G, nl));
       ApplyParams ap{};
       ap.start = g.start;
       ap.len = g.len;
@@ -652,7 +682,8 @@ leiden_status refine(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, Lev
     launch_bin(s, G->cls_lists.as<uint32_t>() + (size_t)r * nl, &ctl->cls_count[r], nl, g.len, nullptr,
                G->bin_lists.as<uint32_t>(), (size_t)nl, G->bincfg, G->hub_items.as<unsigned long long>(), ctl);
     dp.colour = r;
-    launch_decide_all<W, true>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, maxdeg);
+    launch_decide_all<W, true>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, maxdeg,
+                               side_streams(G, nl));
     launch_apply_refine(s, L.C, L.S, L.K, L.size, G->movers.as<Mover>(), ctl, nl);
   }
   return LEIDEN_OK;
@@ -1059,7 +1090,8 @@ leiden_status probe_decide(leiden_graph* G, hipStream_t s, const leiden_opts& o,
     launch_subround_reset(s, ctl);
     launch_bin(s, G->cls_lists.as<uint32_t>() + (size_t)k * n, &ctl->cls_count[k], n, G->g.len, nullptr,
                G->bin_lists.as<uint32_t>(), (size_t)n, G->bincfg, G->hub_items.as<unsigned long long>(), ctl);
-    launch_decide_all<uint32_t, false>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)n, ctl->bin_count, bins, maxdeg);
+    launch_decide_all<uint32_t, false>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)n, ctl->bin_count, bins, maxdeg,
+                                       side_streams(G, n));
   }
   HIPCHK(hipEventRecord(e1, s));
   HIPCHK(hipEventSynchronize(e1));
@@ -1200,6 +1232,7 @@ leiden_status leiden_set_tuning(leiden_graph* G, const leiden_tuning* t) {
 
 leiden_status leiden_autotune(leiden_graph* G, const leiden_opts* opts, leiden_tuning* out) {
   g_err.clear();
+  InFlight in_flight;
   if (!G) return fail(LEIDEN_EINVAL, "null handle");
   leiden_opts o;
   leiden_default_opts(&o);
@@ -1297,6 +1330,15 @@ leiden_status leiden_graph_create(int device, uint32_t n, uint64_t nnz, const in
     return bail(fail(LEIDEN_EDEVICE, "stream creation failed"));
   if (hipHostMalloc((void**)&G->hctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess)
     return bail(fail(LEIDEN_EDEVICE, "pinned allocation failed"));
+  {
+    DecideStreams& d = G->dstreams;
+    bool ok = hipEventCreateWithFlags(&d.fork, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; k < 3 && ok; ++k)
+      ok = hipStreamCreateWithFlags(&d.aux[k], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&d.join[k], hipEventDisableTiming) == hipSuccess;
+    if (!ok) return bail(fail(LEIDEN_EDEVICE, "stream creation failed"));
+    G->dstreams_ready = true;
+  }
   hipStream_t s = G->own;
   AllocScope alloc_scope(s);
   leiden_status st;
@@ -1449,6 +1491,7 @@ leiden_status leiden_graph_nnz(leiden_graph* g, uint64_t* nnz) {
 leiden_status leiden_static(leiden_graph* G, const leiden_opts* opts, uint32_t* membership_out, int out_on_device,
                             double* q_out, leiden_stats* stats) {
   g_err.clear();
+  InFlight in_flight;
   if (!G) return fail(LEIDEN_EINVAL, "null handle");
   leiden_opts o;
   leiden_default_opts(&o);
@@ -1539,6 +1582,7 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
                             leiden_mode mode, const leiden_opts* opts, uint32_t* membership_out, int out_on_device,
                             double* q_out, leiden_stats* stats) {
   g_err.clear();
+  InFlight in_flight;
   if (!G) return fail(LEIDEN_EINVAL, "null handle");
   if (mode != LEIDEN_ND && mode != LEIDEN_DS && mode != LEIDEN_DF) return fail(LEIDEN_EINVAL, "unknown mode");
   if ((n_del && !del) || (n_ins && !ins)) return fail(LEIDEN_EINVAL, "null batch arrays");
