@@ -166,8 +166,8 @@ __device__ inline long long gain_fixed(double dq) {
 //    of lanes reading one hot word (the flag of a large community) then queue
 //    at one memory channel.
 //  ld_sys / st_sys: system-scope relaxed accesses, for values a loop acts on
-//    (union-find parents, hash-table keys, live state of the asynchronous
-//    schedule, partial results of other blocks).  Device-scope loads may be
+//    (hash-table keys, live state of the asynchronous schedule, partial
+//    results of other blocks).  Device-scope loads may be
 //    served by the issuing XCD's own L2, which does not see the other XCDs'
 //    writes during the launch; a retry loop can then read the same stale
 //    value forever.
@@ -182,6 +182,18 @@ __device__ inline T ld_sys(const T* p) {
 template <typename T>
 __device__ inline void st_sys(T* p, T v) {
   __atomic_store_n(p, v, __ATOMIC_RELAXED);
+}
+//  ld_near / st_near: workgroup-scope relaxed accesses, served by the nearest
+//    cache.  For loops whose progress does not rest on fresh values: each
+//    retry is driven by the value an atomic returned (atomics act at memory
+//    and are coherent across XCDs), and a stale value only costs a retry.
+template <typename T>
+__device__ inline T ld_near(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <typename T>
+__device__ inline void st_near(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Raise a flag that many threads may raise at once (e.g. one per member of a

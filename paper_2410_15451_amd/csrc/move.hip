@@ -998,14 +998,17 @@ void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, si
                        const uint64_t* bin_upper, uint32_t maxdeg, const DecideStreams* ds) {
   // bin 0: 8 lanes / 16 slots, bin 1: 32 / 64, bin 2: 64 / 256 (in one
   // launch on s); bin 3: block / 1024, bin 4: block / 4096, bin 5: hubs (all
-  // blocks per hub), each on its own side stream when ds is given
+  // blocks per hub), each on its own side stream when ds is given.  The side
+  // streams fork before the small bins' launch, so all of them run together.
   bool forked = false;
+  if (ds)
+    for (int b = 3; b < kBins && !forked; ++b)
+      if (bin_upper[b]) {
+        (void)hipEventRecord(ds->fork, s);
+        forked = true;
+      }
   auto side = [&](int k) -> hipStream_t {
     if (!ds) return s;
-    if (!forked) {
-      (void)hipEventRecord(ds->fork, s);
-      forked = true;
-    }
     (void)hipStreamWaitEvent(ds->aux[k], ds->fork, 0);
     return ds->aux[k];
   };

@@ -224,14 +224,22 @@ __global__ __launch_bounds__(kBlock) void k_split_init(uint32_t n, const uint32_
   if (threadIdx.x == 0) add_units(parts, kWSplit, entries);
 }
 
+// Every parent is below its child, and a parent pointer only ever moves to
+// another ancestor, so a read of p[x], however stale, names an ancestor of x:
+// a find ends (each step goes to a smaller ID) and returns an ancestor of x,
+// which was a root when written.  Reads may therefore come from the nearest
+// cache.  During the union launches a stale root only makes the union's
+// compare-and-swap fail, and the union goes on from the parent the atomic
+// returned; after them (compress, finish: separate launches) nothing links
+// roots any more and every find reaches the true root.
 __device__ inline uint32_t uf_find(uint32_t* p, uint32_t x) {
   // path halving: every pointer written is an ancestor of the node
-  uint32_t px = ld_sys(&p[x]);
+  uint32_t px = ld_near(&p[x]);
   while (px != x) {
-    const uint32_t gp = ld_sys(&p[px]);
-    if (gp != px) st_sys(&p[x], gp);
+    const uint32_t gp = ld_near(&p[px]);
+    if (gp != px) st_near(&p[x], gp);
     x = gp;
-    px = ld_sys(&p[x]);
+    px = ld_near(&p[x]);
   }
   return x;
 }
@@ -248,7 +256,7 @@ __device__ inline void uf_union(uint32_t* p, uint32_t a, uint32_t b) {
     }
     // hang root b under the smaller root a; if b stopped being a root, go on
     // from the parent the compare-and-swap found (a smaller ID), so that
-    // every retry makes progress whatever the loads above returned
+    // every retry lowers max(a, b) whatever the loads above returned
     const uint32_t o = atomicCAS(&p[b], b, a);
     if (o == b) return;
     b = o;
