@@ -243,6 +243,7 @@ struct AggBufs {
   uint32_t* comm_count;   // members per community
   uint64_t* comm_off;     // member offsets (n + 1)
   uint32_t* comm_fill;
+  uint32_t* comm_fill_long; // members with long rows per community (placed at the back of its range)
   uint32_t* members;
   uint64_t* comm_deg;     // total degree per community
   uint64_t* cap_off;      // super-row capacity offsets (n + 1)
@@ -253,17 +254,20 @@ struct AggBufs {
   void* bigc;             // per-round descriptors of big communities (32 B each, n)
   void* items;            // per-round work items (24 B each, item_cap)
   uint64_t item_cap;
-  unsigned int* stage_cnt;       // per-round stage columns used (n)
+  unsigned long long* stage_ctr; // per-round stage columns and staging slots used (n)
   unsigned long long* self_acc;  // per-round own-key sums (n)
   uint32_t* skeys;               // staging slots (scap)
   unsigned long long* svals;
   uint16_t* smat;                // bucket-start matrices (mcap entries)
   size_t scap, mcap;
   uint32_t emit_cap;             // slots of the emit kernel's LDS table (power of two, 16..4096)
+  unsigned int* slice_ctl;       // 9 words: offsets of the stage-item lists
 };
+// sorted_rows: every row of g is sorted by column (then large communities are
+// staged by XCD slices of the column range)
 template <typename W>
 int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t nc, AggBufs& b, int64_t* out_start,
-              uint32_t* out_len, uint32_t* out_cols, int64_t* out_w, int64_t* Kout, Ctl* ctl);
+              uint32_t* out_len, uint32_t* out_cols, int64_t* out_w, int64_t* Kout, Ctl* ctl, bool sorted_rows);
 
 void launch_static_relabel(hipStream_t s, const uint32_t* C, uint32_t n, uint32_t* minv, uint32_t* flag,
                            uint64_t* rank, uint32_t* out, void* scan_tmp, uint64_t* total, const uint32_t* fgid = nullptr,

@@ -547,42 +547,53 @@ void launch_lookup(hipStream_t s, uint32_t* Ctop, const uint32_t* C, uint32_t n)
 // vertices of one community reserve their range with a single atomic (ranks
 // inside the tile come from the LDS counter), so large communities do not
 // serialise on one global counter.
+// Members of each community, short rows from the front of its range and rows
+// of at least long_min entries from the back (fill_long counts them).
 __global__ __launch_bounds__(kBlock) void k_comm_scatter(const uint32_t* C, uint32_t n, const uint64_t* off,
-                                                         uint32_t* fill, uint32_t* members) {
+                                                         uint32_t* fill, uint32_t* members, const uint32_t* len,
+                                                         uint32_t long_min, uint32_t* fill_long) {
   constexpr int kTile = 1024, kSlots = 2048, kPer = kTile / kBlock;
-  __shared__ uint32_t hk[kSlots];
+  constexpr unsigned long long kEmpty = ~0ull;
+  __shared__ unsigned long long hk[kSlots];
   __shared__ uint32_t hc[kSlots];
   __shared__ uint32_t hb[kSlots];
   for (uint64_t base = (uint64_t)blockIdx.x * kTile; base < n; base += (uint64_t)gridDim.x * kTile) {
     for (int s = threadIdx.x; s < kSlots; s += kBlock) {
-      hk[s] = kNone;
+      hk[s] = kEmpty;
       hc[s] = 0;
     }
     __syncthreads();
-    uint32_t slot[kPer], rank[kPer], key[kPer];
+    uint32_t slot[kPer], rank[kPer];
+    unsigned long long key[kPer];
 #pragma unroll
     for (int t = 0; t < kPer; ++t) {
       const uint64_t i = base + t * kBlock + threadIdx.x;
       if (i >= n) continue;
       const uint32_t c = C[i];
+      const unsigned long long k = (unsigned long long)c | ((unsigned long long)(len[i] >= long_min) << 32);
       uint32_t h = slot_hash(c, kSlots - 1);
       while (true) {
-        const uint32_t o = atomicCAS(&hk[h], kNone, c);
-        if (o == kNone || o == c) break;
+        const unsigned long long o = atomicCAS(&hk[h], kEmpty, k);
+        if (o == kEmpty || o == k) break;
         h = (h + 1) & (kSlots - 1);
       }
-      key[t] = c;
+      key[t] = k;
       slot[t] = h;
       rank[t] = atomicAdd(&hc[h], 1u);
     }
     __syncthreads();
-    for (int s = threadIdx.x; s < kSlots; s += kBlock)
-      if (hk[s] != kNone) hb[s] = atomicAdd(&fill[hk[s]], hc[s]);
+    for (int s = threadIdx.x; s < kSlots; s += kBlock) {
+      const unsigned long long k = hk[s];
+      if (k == kEmpty) continue;
+      const uint32_t c = (uint32_t)k;
+      hb[s] = (k >> 32) ? (uint32_t)(off[c + 1] - off[c]) - atomicAdd(&fill_long[c], hc[s]) - hc[s]
+                        : atomicAdd(&fill[c], hc[s]);
+    }
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < kPer; ++t) {
       const uint64_t i = base + t * kBlock + threadIdx.x;
-      if (i < n) members[off[key[t]] + hb[slot[t]] + rank[t]] = (uint32_t)i;
+      if (i < n) members[off[(uint32_t)key[t]] + hb[slot[t]] + rank[t]] = (uint32_t)i;
     }
     __syncthreads();
   }
@@ -625,13 +636,13 @@ __global__ __launch_bounds__(kBlock) void k_comm_classify(uint32_t nc, const uin
 // host planning).
 __global__ __launch_bounds__(kBlock) void k_big_info(const uint32_t* big, const unsigned int* nbig,
                                                      const uint64_t* moff, const uint64_t* cap, const uint64_t* deg,
-                                                     uint64_t* info) {
+                                                     const uint32_t* nlong, uint64_t* info) {
   const uint32_t cnt = *nbig;
   GRID_STRIDE(k, cnt) {
     const uint32_t c = big[k];
     info[4 * k] = moff[c];
     info[4 * k + 1] = moff[c + 1];
-    info[4 * k + 2] = cap[c];
+    info[4 * k + 2] = cap[c] | ((uint64_t)nlong[c] << 32);  // cap <= community count < 2^32
     info[4 * k + 3] = deg[c];
   }
 }
@@ -761,42 +772,75 @@ __global__ __launch_bounds__(kBlock) void k_agg_lds(Rows<W> g, const uint32_t* C
 
 // Big communities: a group-by of each community's entries with no global
 // hash table (global atomics are slow, those on one address slowest).  Work
-// items are runs of at most kBigMembers members of one community; an item's
-// entries are taken kBigStage at a time.  Each stage is summed by key in an
+// items are runs of members of one community; an item's entries are summed
+// into stages of at most kBigStage entries.  Each stage is summed by key in an
 // LDS table (the community's own key is summed in registers: most entries of
 // a large community stay inside it), and its distinct keys are sorted by
-// bucket (top bits of the salted mixing) into a stage column of the
-// community's staging area, with the bucket starts in column col of the
-// community's (R + 1) x smax matrix.  The emit kernel then sums each group of
+// bucket (top bits of the salted mixing) into a stage column: the next nd
+// slots of the community's staging area (nd distinct keys), with the bucket
+// starts (and nd in row R) in column col of the community's (R + 1) x smax
+// matrix.  The staging area thus needs one slot per entry at most.  The emit kernel then sums each group of
 // buckets over all columns in an LDS table and writes the distinct keys into
 // the super row.  At most 256 buckets (2^kBigMaxRbits): each stage column is
 // R + 1 scattered 16-bit stores, and the counters' LDS then leaves room for
 // three blocks per CU.
+//
+// XCD slices.  Workgroups are handed to the eight XCDs in turn (block b runs
+// on XCD b mod 8), and each XCD has its own L2.  On a level whose rows are
+// sorted by column (the input graph), the vertex IDs are cut into eight
+// slices, and the long rows (kSliceMinLen entries or more, placed at the
+// back of each community's member range) of a community of at least
+// kSliceMinDeg entries are taken in runs of kSliceMembers members, one item
+// per slice: it takes the part of each row whose columns lie in its slice,
+// found by binary search.  The items of slice x are queued in list x, which
+// the blocks of XCD x take in turn, so the C[j] gathers of the long rows hit
+// the 1/8 of C that stays in that XCD's L2 instead of missing to memory.
+// Other items (whole rows, runs of kBigMembers) are dealt over the lists in
+// turn.  (Blocks taking items from shared counters instead were slower: the
+// counters' atomics queue on one memory channel.)
 constexpr uint32_t kBigMembers = 256, kBigStage = 2048, kBigSlots = 4096;
 constexpr uint32_t kBigBucketBits = 10, kBigMaxRbits = 8, kEmitWin = 2048, kEmitSlices = 256;
+constexpr uint32_t kSlices = 8, kSliceMembers = 128, kSliceMinLen = 128, kWhole = 0xFFFFFFFFu;
+constexpr uint64_t kSliceMinDeg = 1u << 16;
+// a community's stage counter: columns used << kColShift | staging slots used
+constexpr uint32_t kColShift = 40;
 
 struct BigComm {
   uint32_t c;      // community
   uint32_t rbits;  // log2 of its bucket count
   uint32_t smax;   // stage columns reserved
   uint32_t pad;
-  uint64_t soff;   // first staging slot (smax * kBigStage slots)
+  uint64_t soff;   // first staging slot (one per entry of the community)
   uint64_t moff;   // first matrix entry ((R + 1) * smax entries)
 };
 struct AggItem {
   uint32_t big;
-  uint32_t pad;
+  uint32_t pad;   // stage items: the slice, or kWhole; emit items: the slice of the community's groups
   uint64_t a, b;  // member range
 };
 
 __device__ inline uint32_t big_mix(uint32_t c) { return fmix32(c ^ kRowSalt); }
 
+// first position of a sorted row holding a column >= key
+__device__ inline uint32_t row_lower_bound(const uint32_t* a, uint32_t L, uint32_t key) {
+  uint32_t lo = 0, hi = L;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (a[mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// sl: the kSlices + 1 list offsets into items; gridDim.x a multiple of kSlices
 template <typename W>
 __global__ __launch_bounds__(kBlock) void k_agg_stage(Rows<W> g, const uint32_t* C, const uint32_t* members,
-                                                      const BigComm* bc, const AggItem* items, uint32_t nitems,
-                                                      uint32_t* skeys, unsigned long long* svals, uint16_t* smat,
-                                                      unsigned int* stage_cnt, unsigned long long* self_acc,
-                                                      unsigned long long* units) {
+                                                      const BigComm* bc, const AggItem* items, unsigned int* sl,
+                                                      uint32_t slice_w, uint32_t* skeys, unsigned long long* svals,
+                                                      uint16_t* smat, unsigned long long* stage_ctr,
+                                                      unsigned long long* self_acc, unsigned long long* units) {
   constexpr uint32_t kNB = 1u << kBigMaxRbits;
   __shared__ int64_t sstart[kBlock];
   __shared__ uint32_t spre[kBlock];
@@ -806,18 +850,55 @@ __global__ __launch_bounds__(kBlock) void k_agg_stage(Rows<W> g, const uint32_t*
   __shared__ unsigned int wsum[kBlock / kWave];
   __shared__ unsigned long long red[kBlock / kWave];
   __shared__ unsigned int scol;
-  for (uint32_t sl = threadIdx.x; sl < kBigSlots; sl += kBlock) {
-    lk[sl] = kNone;
-    lv[sl] = 0;
+  __shared__ unsigned long long sbase;
+  for (uint32_t q = threadIdx.x; q < kBigSlots; q += kBlock) {
+    lk[q] = kNone;
+    lv[q] = 0;
   }
   for (uint32_t q = threadIdx.x; q <= kNB; q += kBlock) lcnt[q] = 0;
   __syncthreads();
   unsigned long long entries = 0;
-  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const AggItem x = items[it];
+  auto run_item = [&](const AggItem x) {
     const BigComm b = bc[x.big];
     const uint32_t rb = b.rbits, R = 1u << rb;
+    const uint32_t sx = x.pad;
     unsigned long long self = 0;
+    // the stage's distinct keys per bucket, their starts, and a column
+    auto flush = [&]() {
+      for (uint32_t q = threadIdx.x; q < kBigSlots; q += kBlock) {
+        const uint32_t c = lk[q];
+        if (c != kNone) atomicAdd(&lcnt[rb ? big_mix(c) >> (32 - rb) : 0u], 1u);
+      }
+      __syncthreads();
+      const uint32_t nd = block_exclusive_scan<kNB / kBlock>(lcnt, R, wsum);
+      if (threadIdx.x == 0) {
+        lcnt[R] = nd;
+        // the next column and its nd slots, taken together: the columns'
+        // slots follow one another in column order
+        const unsigned long long o = atomicAdd(&stage_ctr[x.big], (1ull << kColShift) + nd);
+        scol = (unsigned int)(o >> kColShift);
+        sbase = o & ((1ull << kColShift) - 1);
+      }
+      __syncthreads();
+      const uint32_t col = scol;
+      for (uint32_t q = threadIdx.x; q <= R; q += kBlock) smat[b.moff + (size_t)q * b.smax + col] = (uint16_t)lcnt[q];
+      __syncthreads();
+      uint32_t* tk = skeys + b.soff + sbase;
+      unsigned long long* tv = svals + b.soff + sbase;
+      for (uint32_t q = threadIdx.x; q < kBigSlots; q += kBlock) {
+        const uint32_t c = lk[q];
+        if (c == kNone) continue;
+        const unsigned int pos = atomicAdd(&lcnt[rb ? big_mix(c) >> (32 - rb) : 0u], 1u);
+        tk[pos] = c;
+        tv[pos] = lv[q];
+        lk[q] = kNone;
+        lv[q] = 0;
+      }
+      __syncthreads();
+      for (uint32_t q = threadIdx.x; q <= R; q += kBlock) lcnt[q] = 0;
+      __syncthreads();
+    };
+    uint32_t fill = 0;  // entries summed into the table since the last stage column
     for (uint64_t mb = x.a; mb < x.b; mb += kBlock) {
       const uint64_t mi = mb + threadIdx.x;
       uint32_t L = 0;
@@ -826,6 +907,13 @@ __global__ __launch_bounds__(kBlock) void k_agg_stage(Rows<W> g, const uint32_t*
         const uint32_t v = members[mi];
         L = g.len[v];
         st = g.start[v];
+        if (sx != kWhole) {
+          const uint32_t* row = g.cols + st;
+          const uint32_t e0 = sx == 0 ? 0u : row_lower_bound(row, L, sx * slice_w);
+          const uint32_t e1 = sx == kSlices - 1 ? L : row_lower_bound(row, L, (sx + 1) * slice_w);
+          st += e0;
+          L = e1 - e0;
+        }
       }
       sstart[threadIdx.x] = st;
       // inclusive block scan of the row lengths (wavefront scans, then wavefront totals)
@@ -845,8 +933,8 @@ __global__ __launch_bounds__(kBlock) void k_agg_stage(Rows<W> g, const uint32_t*
       __syncthreads();
       const uint32_t total = spre[kBlock - 1];
       entries += total;
-      for (uint32_t xb = 0; xb < total; xb += kBigStage) {
-        const uint32_t xe = min(total, xb + kBigStage);
+      for (uint32_t xb = 0; xb < total;) {
+        const uint32_t xe = xb + min(total - xb, kBigStage - fill);
         table_accumulate(lk, lv, kBigSlots - 1, xb + threadIdx.x, xe, kBlock,
                          [&](uint32_t xx, uint32_t& key, unsigned long long& w) {
                            int lo = 0, hi = kBlock - 1;
@@ -867,40 +955,21 @@ __global__ __launch_bounds__(kBlock) void k_agg_stage(Rows<W> g, const uint32_t*
                              key = c;
                          });
         __syncthreads();
-        // the stage's distinct keys per bucket, their starts, and a column
-        for (uint32_t sl = threadIdx.x; sl < kBigSlots; sl += kBlock) {
-          const uint32_t c = lk[sl];
-          if (c != kNone) atomicAdd(&lcnt[rb ? big_mix(c) >> (32 - rb) : 0u], 1u);
+        fill += xe - xb;
+        xb = xe;
+        if (fill == kBigStage) {
+          flush();
+          fill = 0;
         }
-        __syncthreads();
-        const uint32_t nd = block_exclusive_scan<kNB / kBlock>(lcnt, R, wsum);
-        if (threadIdx.x == 0) {
-          lcnt[R] = nd;
-          scol = atomicAdd(&stage_cnt[x.big], 1u);
-        }
-        __syncthreads();
-        const uint32_t col = scol;
-        for (uint32_t q = threadIdx.x; q <= R; q += kBlock) smat[b.moff + (size_t)q * b.smax + col] = (uint16_t)lcnt[q];
-        __syncthreads();
-        uint32_t* tk = skeys + b.soff + (size_t)col * kBigStage;
-        unsigned long long* tv = svals + b.soff + (size_t)col * kBigStage;
-        for (uint32_t sl = threadIdx.x; sl < kBigSlots; sl += kBlock) {
-          const uint32_t c = lk[sl];
-          if (c == kNone) continue;
-          const unsigned int pos = atomicAdd(&lcnt[rb ? big_mix(c) >> (32 - rb) : 0u], 1u);
-          tk[pos] = c;
-          tv[pos] = lv[sl];
-          lk[sl] = kNone;
-          lv[sl] = 0;
-        }
-        __syncthreads();
-        for (uint32_t q = threadIdx.x; q <= R; q += kBlock) lcnt[q] = 0;
-        __syncthreads();
       }
     }
+    if (fill) flush();
     self = block_sum(self, red);
     if (threadIdx.x == 0 && self) atomicAdd(&self_acc[x.big], self);
-  }
+  };
+  // the blocks of XCD x (a multiple of kSlices blocks) share list x
+  const uint32_t li = blockIdx.x % kSlices, lo = sl[li], cnt = sl[li + 1] - lo;
+  for (uint32_t k = blockIdx.x / kSlices; k < cnt; k += gridDim.x / kSlices) run_item(items[lo + k]);
   if (threadIdx.x == 0 && units && entries) atomicAdd(units, entries);
 }
 
@@ -918,13 +987,14 @@ __global__ __launch_bounds__(kBlock) void k_agg_stage(Rows<W> g, const uint32_t*
 __global__ __launch_bounds__(kBlock) void k_agg_emit(const BigComm* bc, const AggItem* items, uint32_t nitems,
                                                      const uint32_t* skeys,
                                                      const unsigned long long* svals, const uint16_t* smat,
-                                                     const unsigned int* stage_cnt,
+                                                     const unsigned long long* stage_ctr,
                                                      const unsigned long long* self_acc, const uint64_t* cap_off,
                                                      uint32_t* out_len, uint32_t* out_cols, int64_t* out_w,
                                                      int64_t* Kout, uint32_t cap) {
   __shared__ uint32_t tk[kBigSlots];
   __shared__ unsigned long long tv[kBigSlots];
   __shared__ unsigned int rpre[kEmitWin];
+  __shared__ unsigned int cbase[kEmitWin];
   __shared__ uint16_t rst[kEmitWin];
   __shared__ unsigned int wsum[kBlock / kWave];
   __shared__ unsigned long long red[kBlock / kWave];
@@ -935,7 +1005,7 @@ __global__ __launch_bounds__(kBlock) void k_agg_emit(const BigComm* bc, const Ag
     const uint32_t r = x.big, y = x.pad, nslice = (uint32_t)x.a;
     const BigComm b = bc[r];
     const uint32_t rb = b.rbits, R = 1u << rb;
-    const uint32_t nst = stage_cnt[r];
+    const uint32_t nst = (uint32_t)(stage_ctr[r] >> kColShift);
     const uint16_t* mat = smat + b.moff;
     const uint64_t o = cap_off[b.c];
     if (y == 0 && threadIdx.x == 0) {
@@ -974,15 +1044,18 @@ __global__ __launch_bounds__(kBlock) void k_agg_emit(const BigComm* bc, const Ag
           full = 0;
           nout = 0;
         }
+        uint64_t wbase = 0;  // staging slots of the columns before the window
         for (uint32_t c0 = 0; c0 < nst; c0 += kEmitWin) {
           const uint32_t cw = min(kEmitWin, nst - c0);
           for (uint32_t i = threadIdx.x; i < cw; i += kBlock) {
             const uint32_t s0 = mat[(size_t)b0 * b.smax + c0 + i], s1 = mat[(size_t)b1 * b.smax + c0 + i];
             rst[i] = (uint16_t)s0;
             rpre[i] = s1 - s0;
+            cbase[i] = mat[(size_t)R * b.smax + c0 + i];
           }
           __syncthreads();
           const uint32_t n = block_exclusive_scan<kEmitWin / kBlock>(rpre, cw, wsum);
+          const uint32_t wslots = block_exclusive_scan<kEmitWin / kBlock>(cbase, cw, wsum);
           if (nst <= kEmitWin) mask = min(cap, pow2_at_least(2 * n)) - 1;
           for (uint32_t xx = threadIdx.x; xx < n; xx += kBlock) {
             uint32_t lo = 0, hi = cw - 1;
@@ -993,12 +1066,13 @@ __global__ __launch_bounds__(kBlock) void k_agg_emit(const BigComm* bc, const Ag
               else
                 hi = mid - 1;
             }
-            const size_t pos = b.soff + (size_t)(c0 + lo) * kBigStage + rst[lo] + (xx - rpre[lo]);
+            const size_t pos = b.soff + wbase + cbase[lo] + rst[lo] + (xx - rpre[lo]);
             const uint32_t c = skeys[pos];
             if (q && ((big_mix(c) << gb) >> (32 - q)) != sub) continue;
             if (!table_add_bounded(tk, tv, mask, c, svals[pos], kRowSalt)) full = 1;
           }
           __syncthreads();
+          wbase += wslots;
         }
         const bool fits = full == 0;
         unsigned long long ksum = 0;
@@ -1051,7 +1125,7 @@ __global__ void k_zero_misc_agg(Ctl* ctl) {
 
 template <typename W>
 int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t nc, AggBufs& b, int64_t* out_start,
-              uint32_t* out_len, uint32_t* out_cols, int64_t* out_w, int64_t* Kout, Ctl* ctl) {
+              uint32_t* out_len, uint32_t* out_cols, int64_t* out_w, int64_t* Kout, Ctl* ctl, bool sorted_rows) {
   fill_u32(s, b.comm_count, 0, nc);
   fill_u64(s, b.comm_deg, 0, nc);
   scatter_count(s, C, n, b.comm_count, n);
@@ -1059,8 +1133,9 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
   exclusive_scan_u32(s, b.comm_count, b.comm_off, nc, b.total, b.scan_tmp);
   (void)hipMemcpyAsync(b.comm_off + nc, b.total, sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
   fill_u32(s, b.comm_fill, 0, nc);
+  fill_u32(s, b.comm_fill_long, 0, nc);
   hipLaunchKernelGGL(k_comm_scatter, dim3(grid_n(n, 1024, 4096)), dim3(kBlock), 0, s, C, n, b.comm_off, b.comm_fill,
-                     b.members);
+                     b.members, g.len, sorted_rows ? kSliceMinLen : kNone, b.comm_fill_long);
   hipLaunchKernelGGL(k_zero_misc_agg, dim3(1), dim3(64), 0, s, ctl);
   // capacity per community -> super-row starts
   hipLaunchKernelGGL(k_comm_classify, dim3(grid_n(nc, kBlock * kTileU)), dim3(kBlock), 0, s, nc, b.comm_deg, b.cap_off,
@@ -1082,7 +1157,7 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
   if (nbig == 0) return 0;
   const uint32_t* big = b.small_lists + 2 * (size_t)nc;
   hipLaunchKernelGGL(k_big_info, dim3(grid_n(nbig)), dim3(kBlock), 0, s, big, &ctl->misc[4], b.comm_off, b.cap_off,
-                     b.comm_deg, b.big_info);
+                     b.comm_deg, b.comm_fill_long, b.big_info);
   const size_t ib = sizeof(uint64_t) * 4 * nbig, idb = sizeof(uint32_t) * nbig;
   char* st = (char*)pinned_stage(ib + idb);
   if (!st) return -1;
@@ -1096,31 +1171,51 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
     // a round: as many communities as their staging areas, matrices and
     // work items fit
     std::vector<BigComm> rc;
-    std::vector<AggItem> ins;
-    uint64_t used = 0, mused = 0, nemitted = 0;
+    std::vector<AggItem> lists[kSlices];
+    uint64_t used = 0, mused = 0, nemitted = 0, nstage = 0, spread = 0;
     uint32_t last = first;
     while (last < nbig) {
-      const uint64_t m0 = info[4 * last], m1 = info[4 * last + 1], cap = info[4 * last + 2], deg = info[4 * last + 3];
-      const uint64_t nitems = (m1 - m0 + kBigMembers - 1) / kBigMembers;
-      // every item's stages hold at most kBigStage entries: deg / kBigStage + one partial stage per item
+      const uint64_t m0 = info[4 * last], m1 = info[4 * last + 1], deg = info[4 * last + 3];
+      const uint64_t cap = info[4 * last + 2] & 0xFFFFFFFFull, nlong = info[4 * last + 2] >> 32;
+      // long rows (at the back of the member range) by slices, the others whole
+      const bool sliced = sorted_rows && deg >= kSliceMinDeg && nlong > 0;
+      const uint64_t ml = sliced ? m1 - nlong : m1;
+      const uint64_t nitems = (ml - m0 + kBigMembers - 1) / kBigMembers +
+                              (m1 - ml + kSliceMembers - 1) / kSliceMembers * kSlices;
+      // stage columns: every item's stages hold at most kBigStage entries, so
+      // deg / kBigStage + one partial stage per item
       const uint64_t smax = deg / kBigStage + nitems + 1;
       uint32_t rb = 0;
       while (rb < kBigMaxRbits && ((uint64_t)1 << (kBigBucketBits + rb)) < std::min(cap, deg)) ++rb;
-      const uint64_t slots = smax * kBigStage, ment = (((uint64_t)1 << rb) + 1) * smax;
+      const uint64_t slots = deg, ment = (((uint64_t)1 << rb) + 1) * smax;
       const uint64_t nemit = std::min<uint64_t>(kEmitSlices, (uint64_t)1 << rb);
       if (slots > b.scap || ment > b.mcap || nitems + nemit > b.item_cap) return -2;
       if (last > first &&
-          (used + slots > b.scap || mused + ment > b.mcap || ins.size() + nemitted + nitems + nemit > b.item_cap))
+          (used + slots > b.scap || mused + ment > b.mcap || nstage + nemitted + nitems + nemit > b.item_cap))
         break;
       const uint32_t r = (uint32_t)rc.size();
       rc.push_back(BigComm{ids[last], rb, (uint32_t)smax, 0, used, mused});
-      for (uint64_t a = m0; a < m1; a += kBigMembers) ins.push_back(AggItem{r, 0, a, std::min(m1, a + kBigMembers)});
+      for (uint64_t a = m0; a < ml; a += kBigMembers)
+        lists[spread++ % kSlices].push_back(AggItem{r, kWhole, a, std::min(ml, a + kBigMembers)});
+      for (uint64_t a = ml; a < m1; a += kSliceMembers)
+        for (uint32_t x = 0; x < kSlices; ++x) lists[x].push_back(AggItem{r, x, a, std::min(m1, a + kSliceMembers)});
       used += slots;
       mused += ment;
       nemitted += nemit;
+      nstage += nitems;
       ++last;
     }
     const uint32_t nr = (uint32_t)rc.size();
+    // stage items list by list (list offsets in sl)
+    std::vector<AggItem> ins;
+    unsigned int sl[kSlices + 1] = {};
+    size_t longest = 0;
+    for (uint32_t x = 0; x < kSlices; ++x) {
+      sl[x] = (unsigned int)ins.size();
+      ins.insert(ins.end(), lists[x].begin(), lists[x].end());
+      longest = std::max(longest, lists[x].size());
+    }
+    sl[kSlices] = (unsigned int)ins.size();
     const size_t nins = ins.size();
     // emit items: (community, slice of up to kEmitSlices) after the stage items
     for (uint32_t r = 0; r < nr; ++r) {
@@ -1131,25 +1226,27 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
     // through pinned memory: the copies queue behind the kernels instead of
     // each waiting for the stream (the round ends with a synchronisation)
     const size_t rb_bytes = sizeof(BigComm) * nr, ib2 = sizeof(AggItem) * ins.size();
-    char* hs = (char*)pinned_stage(rb_bytes + ib2);
+    char* hs = (char*)pinned_stage(rb_bytes + ib2 + sizeof(sl));
     if (!hs) return -1;
     std::memcpy(hs, rc.data(), rb_bytes);
     std::memcpy(hs + rb_bytes, ins.data(), ib2);
+    std::memcpy(hs + rb_bytes + ib2, sl, sizeof(sl));
     (void)hipMemcpyAsync(b.bigc, hs, rb_bytes, hipMemcpyHostToDevice, s);
     (void)hipMemcpyAsync(di, hs + rb_bytes, ib2, hipMemcpyHostToDevice, s);
-    fill_u32(s, b.stage_cnt, 0, nr);
+    (void)hipMemcpyAsync(b.slice_ctl, hs + rb_bytes + ib2, sizeof(sl), hipMemcpyHostToDevice, s);
+    fill_u64(s, (uint64_t*)b.stage_ctr, 0, nr);
     fill_u64(s, (uint64_t*)b.self_acc, 0, nr);
     // the input graph's big communities are timed as LEIDEN_KT_AGG_BIG
     const bool timed = sizeof(W) == 4;
     if (timed) kt_mark(LEIDEN_KT_AGG_BIG, s);
-    hipLaunchKernelGGL(k_agg_stage<W>, dim3(std::min<size_t>(nins, 4096)), dim3(kBlock), 0, s, g, C, b.members,
-                       (const BigComm*)b.bigc, di, (uint32_t)nins, b.skeys, b.svals, b.smat, b.stage_cnt,
-                       b.self_acc, timed ? &ctl->kt_units[LEIDEN_KT_AGG_BIG] : nullptr);
+    hipLaunchKernelGGL(k_agg_stage<W>, dim3(kSlices * std::min<size_t>(longest, 512)), dim3(kBlock), 0, s, g, C, b.members,
+                       (const BigComm*)b.bigc, di, b.slice_ctl, (n + kSlices - 1) / kSlices, b.skeys, b.svals, b.smat,
+                       b.stage_ctr, b.self_acc, timed ? &ctl->kt_units[LEIDEN_KT_AGG_BIG] : nullptr);
     if (timed) kt_mark(LEIDEN_KT_AGG_BIG, s);
     const size_t nemit = ins.size() - nins;
     const uint32_t ecap = (b.emit_cap >= 16 && b.emit_cap <= kBigSlots) ? b.emit_cap : kBigSlots;
     hipLaunchKernelGGL(k_agg_emit, dim3(std::min<size_t>(nemit, 8192)), dim3(kBlock), 0, s, (const BigComm*)b.bigc,
-                       di + nins, (uint32_t)nemit, b.skeys, b.svals, b.smat, b.stage_cnt, b.self_acc,
+                       di + nins, (uint32_t)nemit, b.skeys, b.svals, b.smat, b.stage_ctr, b.self_acc,
                        (const uint64_t*)out_start, out_len, out_cols, out_w, Kout, ecap);
     if (hipStreamSynchronize(s) != hipSuccess) return -1;  // host vectors must outlive the copies
     first = last;
@@ -1158,9 +1255,9 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
 }
 
 template int aggregate<uint32_t>(hipStream_t, Rows<uint32_t>, uint32_t, const uint32_t*, uint32_t, AggBufs&, int64_t*,
-                                 uint32_t*, uint32_t*, int64_t*, int64_t*, Ctl*);
+                                 uint32_t*, uint32_t*, int64_t*, int64_t*, Ctl*, bool);
 template int aggregate<int64_t>(hipStream_t, Rows<int64_t>, uint32_t, const uint32_t*, uint32_t, AggBufs&, int64_t*,
-                                uint32_t*, uint32_t*, int64_t*, int64_t*, Ctl*);
+                                uint32_t*, uint32_t*, int64_t*, int64_t*, Ctl*, bool);
 
 // ---------------------------------------------------------------------------
 // Static output labels: dense, ordered by each community's minimum vertex.

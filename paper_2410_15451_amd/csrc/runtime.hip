@@ -8,6 +8,7 @@
 #include <cstring>
 #include <limits>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/leiden.h"
@@ -186,7 +187,7 @@ struct leiden_graph {
   Buf cls_lists, bin_lists, iter_list, next_list, movers, split_list, split_rest, split_key, split_wide, lab;
   Buf flag, newid, scan_tmp, ctl, small;
   Buf lvA_start, lvA_len, lvA_cols, lvA_w, lvB_start, lvB_len, lvB_cols, lvB_w;
-  Buf agg_count, agg_off, agg_fill, agg_members, agg_deg, agg_cap, agg_lists, agg_bigcap, agg_tbl, agg_keys, agg_vals,
+  Buf agg_count, agg_off, agg_fill, agg_fill2, agg_members, agg_deg, agg_cap, agg_lists, agg_bigcap, agg_tbl, agg_keys, agg_vals,
       agg_mat, agg_items, mark_items;
   Buf hub_keys, hub_vals, hub_list, hub_idx, hub_off, hub_moff, hub_rbits, hub_size, hub_msize, hub_kid;
   Buf hub_items, hub_mat, hub_live, hub_pdq, hub_pc, hub_done;
@@ -365,6 +366,7 @@ leiden_status ensure_workspace(leiden_graph* G, hipStream_t s, uint32_t classes)
   CHK(G->agg_count.reserve(n * u32));
   CHK(G->agg_off.reserve((n + 1) * u64));
   CHK(G->agg_fill.reserve(n * u32));
+  CHK(G->agg_fill2.reserve(n * u32));
   CHK(G->agg_members.reserve(n * u32));
   CHK(G->agg_deg.reserve(n * u64));
   CHK(G->agg_cap.reserve((n + 1) * u64));
@@ -373,12 +375,12 @@ leiden_status ensure_workspace(leiden_graph* G, hipStream_t s, uint32_t classes)
   CHK(G->agg_tbl.reserve(n * 48));  // per-round descriptors (32 B) and counters (4 + 8 B) of big communities
   CHK(G->agg_items.reserve(kAggItems * 24));
   CHK(G->mark_items.reserve((nnz / 64 + n + 1) * 8));
-  // staging for the big communities of an aggregation: every entry once, plus
-  // one partial stage per work item of 256 members and per community
-  const uint64_t scap = nnz + 8 * (uint64_t)n + (1 << 16);
+  // staging for the big communities of an aggregation: one slot per entry;
+  // bucket-start matrices: (R + 1) 16-bit starts per stage column
+  const uint64_t scap = nnz + (1 << 16), mcap = nnz + 8 * (uint64_t)n + (1 << 16);
   CHK(G->agg_keys.reserve(scap * u32));
   CHK(G->agg_vals.reserve(scap * u64));
-  CHK(G->agg_mat.reserve((scap + scap / 1024 + 4096) * 2));
+  CHK(G->agg_mat.reserve((mcap + mcap / 1024 + 4096) * 2));
   const uint64_t hslots = next_pow2(2 * n);
   CHK(G->tr_minv.reserve(n * u32));
   const size_t hk_bytes = G->tr_hk.bytes;
@@ -748,6 +750,7 @@ AggBufs agg_bufs(leiden_graph* G, uint64_t* total) {
   ab.comm_count = G->agg_count.as<uint32_t>();
   ab.comm_off = G->agg_off.as<uint64_t>();
   ab.comm_fill = G->agg_fill.as<uint32_t>();
+  ab.comm_fill_long = G->agg_fill2.as<uint32_t>();
   ab.members = G->agg_members.as<uint32_t>();
   ab.comm_deg = G->agg_deg.as<uint64_t>();
   ab.cap_off = G->agg_cap.as<uint64_t>();
@@ -758,7 +761,7 @@ AggBufs agg_bufs(leiden_graph* G, uint64_t* total) {
   ab.bigc = G->agg_tbl.p;
   ab.items = G->agg_items.p;
   ab.item_cap = kAggItems;
-  ab.stage_cnt = (unsigned int*)((char*)G->agg_tbl.p + 32 * (size_t)G->n);
+  ab.stage_ctr = (unsigned long long*)((char*)G->agg_tbl.p + 32 * (size_t)G->n);
   ab.self_acc = (unsigned long long*)((char*)G->agg_tbl.p + 40 * (size_t)G->n);
   ab.skeys = G->agg_keys.as<uint32_t>();
   ab.svals = G->agg_vals.as<unsigned long long>();
@@ -766,6 +769,7 @@ AggBufs agg_bufs(leiden_graph* G, uint64_t* total) {
   ab.scap = G->agg_keys.bytes / 4;
   ab.mcap = G->agg_mat.bytes / 2;
   ab.emit_cap = G->emit_slots;
+  ab.slice_ctl = (unsigned int*)(G->small.as<uint64_t>() + 400);
   return ab;
 }
 
@@ -799,8 +803,10 @@ leiden_status next_level(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
   // K of the next level goes to whichever of the two K buffers is not current
   int64_t* Kn = L.K == G->K.as<int64_t>() ? G->Kb.as<int64_t>() : G->K.as<int64_t>();
   count_units(s, g.len, nullptr, nl, G->edge_parts.as<unsigned long long>(), kWAggIn);
+  // the input graph's rows are sorted by column (required of the input and
+  // kept by the batch merge); aggregated levels are not
   int rc = aggregate<W>(s, g, nl, L.C, (uint32_t)nc, ab, bs.as<int64_t>(), bl.as<uint32_t>(), bc.as<uint32_t>(),
-                        bw.as<int64_t>(), Kn, dctl(G));
+                        bw.as<int64_t>(), Kn, dctl(G), std::is_same<W, uint32_t>::value);
   if (rc != 0) return fail(LEIDEN_EDEVICE, "aggregation failed (%d)", rc);
   count_units(s, bl.as<uint32_t>(), nullptr, nc, G->edge_parts.as<unsigned long long>(), kWAggOut);
   // dense renumbering, C <- C'[C] over the input vertices, next-level set-up
@@ -1142,7 +1148,7 @@ leiden_status probe_aggregate(leiden_graph* G, hipStream_t s, uint32_t slots, fl
   HIPCHK(hipEventRecord(e0, s));
   const int rc = aggregate<uint32_t>(s, rows0(G), n, C, (uint32_t)nc, ab, G->lvA_start.as<int64_t>(),
                                      G->lvA_len.as<uint32_t>(), G->lvA_cols.as<uint32_t>(), G->lvA_w.as<int64_t>(),
-                                     G->Kb.as<int64_t>(), dctl(G));
+                                     G->Kb.as<int64_t>(), dctl(G), true);
   HIPCHK(hipEventRecord(e1, s));
   HIPCHK(hipEventSynchronize(e1));
   float ms = 0;
