@@ -148,9 +148,10 @@ void launch_bin(hipStream_t s, const uint32_t* list, const unsigned int* count, 
 // while no other call of the process is running: the streams then outnumber
 // the hardware queues, and event waits that several threads submit into
 // shared in-order queues can wait on each other in a cycle.
+constexpr int kDecideSide = 2;
 struct DecideStreams {
-  hipStream_t aux[3];
-  hipEvent_t fork, join[3];
+  hipStream_t aux[kDecideSide];
+  hipEvent_t fork, join[kDecideSide];
 };
 // maxdeg: largest degree of the level (sizes the hub kernels); ds may be null
 // (everything on s)

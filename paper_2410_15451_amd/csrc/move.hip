@@ -381,14 +381,26 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(DecideParams<W> p) {
     nused = 0;
   }
   __syncthreads();
+  // the next vertex's community and row bounds are fetched while the current
+  // one is summed (only the block deciding a vertex moves it, so its C entry
+  // is the same when its turn comes)
+  uint32_t nv = 0, nd = 0, nL = 0;
+  int64_t ns0 = 0;
+  if (blockIdx.x < cnt) {
+    nv = p.list[blockIdx.x];
+    nd = p.C[nv];
+    ns0 = p.g.start[nv];
+    nL = p.g.len[nv];
+  }
   for (uint32_t item = blockIdx.x; item < cnt; item += gridDim.x) {
-    const uint32_t v = p.list[item];
-    const uint32_t d = p.C[v];
+    const uint32_t v = nv, d = nd;
+    const int64_t s0 = ns0;
+    const uint32_t L = nL;
+    const uint32_t nx = item + gridDim.x;
+    const uint32_t nv2 = nx < cnt ? p.list[nx] : 0u;
     const bool valid = !(REFINE && p.size[d] != 1);
     unsigned long long kid = 0;
     if (valid) {
-      const int64_t s0 = p.g.start[v];
-      const uint32_t L = p.g.len[v];
       const uint32_t bnd = REFINE ? p.CB[v] : 0;
       if (threadIdx.x == 0) {
         edges += L;
@@ -407,6 +419,12 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(DecideParams<W> p) {
                               });
     }
     __syncthreads();
+    if (nx < cnt) {
+      nv = nv2;
+      nd = p.C[nv];
+      ns0 = p.g.start[nv];
+      nL = p.g.len[nv];
+    }
     kid = block_sum(kid, red);
     double bdq = -INFINITY;
     uint32_t bc = kNone;
@@ -997,22 +1015,24 @@ template <typename W, bool REFINE>
 void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, size_t stride, unsigned int* bin_counts,
                        const uint64_t* bin_upper, uint32_t maxdeg, const DecideStreams* ds) {
   // bin 0: 8 lanes / 16 slots, bin 1: 32 / 64, bin 2: 64 / 256 (in one
-  // launch on s); bin 3: block / 1024, bin 4: block / 4096, bin 5: hubs (all
-  // blocks per hub), each on its own side stream when ds is given.  The side
-  // streams fork before the small bins' launch, so all of them run together.
+  // launch on s); bin 3: block / 1024, bin 4: block / 4096, each on its own
+  // side stream when ds is given; bin 5: hubs (all blocks per hub), on s
+  // after the small bins.  The side streams fork before the small bins'
+  // launch, so the three streams run together.  (With four hardware queues
+  // per process a third side stream shared a queue with another one, and
+  // the hubs then waited for the 4096 bin instead of the small bins, which
+  // finish first.)
   bool forked = false;
-  if (ds)
-    for (int b = 3; b < kBins && !forked; ++b)
-      if (bin_upper[b]) {
-        (void)hipEventRecord(ds->fork, s);
-        forked = true;
-      }
+  if (ds && (bin_upper[3] || bin_upper[4])) {
+    (void)hipEventRecord(ds->fork, s);
+    forked = true;
+  }
   auto side = [&](int k) -> hipStream_t {
-    if (!ds) return s;
+    if (!forked) return s;
     (void)hipStreamWaitEvent(ds->aux[k], ds->fork, 0);
     return ds->aux[k];
   };
-  bool used[3] = {false, false, false};
+  bool used[kDecideSide] = {false, false};
   {
     SmallBins sb{};
     uint32_t* nb[3] = {&sb.n0, &sb.n1, &sb.n2};
@@ -1030,8 +1050,8 @@ void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, si
     DecideParams<W> q = p;
     q.list = bin_lists + (size_t)b * stride;
     q.count = bin_counts + b;
-    const hipStream_t t = side(b - 3);
-    used[b - 3] = true;
+    const hipStream_t t = b < 5 ? side(b - 3) : s;
+    if (b < 5) used[b - 3] = forked;
     switch (b) {
       case 3:
         hipLaunchKernelGGL((k_decide_block<1024, W, REFINE>), dim3(grid_for(bin_upper[b], 1, 2048)), dim3(kBlock), 0,
@@ -1052,8 +1072,8 @@ void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, si
       }
     }
   }
-  if (ds)
-    for (int k = 0; k < 3; ++k)
+  if (forked)
+    for (int k = 0; k < kDecideSide; ++k)
       if (used[k]) {
         (void)hipEventRecord(ds->join[k], ds->aux[k]);
         (void)hipStreamWaitEvent(s, ds->join[k], 0);

@@ -1339,7 +1339,7 @@ leiden_status leiden_graph_create(int device, uint32_t n, uint64_t nnz, const in
   {
     DecideStreams& d = G->dstreams;
     bool ok = hipEventCreateWithFlags(&d.fork, hipEventDisableTiming) == hipSuccess;
-    for (int k = 0; k < 3 && ok; ++k)
+    for (int k = 0; k < kDecideSide && ok; ++k)
       ok = hipStreamCreateWithFlags(&d.aux[k], hipStreamNonBlocking) == hipSuccess &&
            hipEventCreateWithFlags(&d.join[k], hipEventDisableTiming) == hipSuccess;
     if (!ok) return bail(fail(LEIDEN_EDEVICE, "stream creation failed"));
