@@ -166,8 +166,8 @@ __device__ inline long long gain_fixed(double dq) {
 //    of lanes reading one hot word (the flag of a large community) then queue
 //    at one memory channel.
 //  ld_sys / st_sys: system-scope relaxed accesses, for values a loop acts on
-//    (hash-table keys, live state of the asynchronous schedule, partial
-//    results of other blocks).  Device-scope loads may be
+//    (live state of the asynchronous schedule, partial results of other
+//    blocks).  Device-scope loads may be
 //    served by the issuing XCD's own L2, which does not see the other XCDs'
 //    writes during the launch; a retry loop can then read the same stale
 //    value forever.
@@ -186,7 +186,10 @@ __device__ inline void st_sys(T* p, T v) {
 //  ld_near / st_near: workgroup-scope relaxed accesses, served by the nearest
 //    cache.  For loops whose progress does not rest on fresh values: each
 //    retry is driven by the value an atomic returned (atomics act at memory
-//    and are coherent across XCDs), and a stale value only costs a retry.
+//    and are coherent across XCDs), and a stale value only costs a retry
+//    (union-find parents; keys of a hash table, written once per launch, so a
+//    stale read shows a taken slot empty and the compare-and-swap that follows
+//    returns its key).
 template <typename T>
 __device__ inline T ld_near(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);

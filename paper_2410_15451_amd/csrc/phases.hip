@@ -1381,7 +1381,7 @@ __device__ inline uint64_t pair_slot(unsigned long long key, uint64_t mask) {
 __device__ inline uint64_t pair_insert(unsigned long long* hk, uint64_t mask, unsigned long long key) {
   uint64_t h = pair_slot(key, mask);
   while (true) {
-    const unsigned long long k = ld_sys(&hk[h]);
+    const unsigned long long k = ld_near(&hk[h]);
     if (k == key) return h;
     if (k == kNone64) {
       const unsigned long long o = atomicCAS(&hk[h], kNone64, key);
@@ -1451,7 +1451,7 @@ __global__ __launch_bounds__(kBlock) void k_track_split(uint32_t n, const uint32
         if (key != kNone64) {
           uint64_t h = pair_slot(key, mask);
           while (true) {
-            const unsigned long long k = ld_sys(&hk[h]);
+            const unsigned long long k = ld_near(&hk[h]);
             if (k == key) break;
             if (k == kNone64) {
               const unsigned long long o = atomicCAS(&hk[h], kNone64, key);
