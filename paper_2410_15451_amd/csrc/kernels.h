@@ -245,6 +245,7 @@ struct AggBufs {
   uint64_t* comm_off;     // member offsets (n + 1)
   uint32_t* comm_fill;
   uint32_t* comm_fill_long; // members with long rows per community (placed at the back of its range)
+  uint64_t* member_eoff;    // entry offsets of the members in member order (n + 1)
   uint32_t* members;
   uint64_t* comm_deg;     // total degree per community
   uint64_t* cap_off;      // super-row capacity offsets (n + 1)

@@ -647,6 +647,11 @@ __global__ __launch_bounds__(kBlock) void k_big_info(const uint32_t* big, const 
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_member_len(const uint32_t* members, uint32_t n, const uint32_t* len,
+                                                       uint32_t* mlen) {
+  GRID_STRIDE(m, n) mlen[m] = len[members[m]];
+}
+
 // Accumulate all entries of the members of community c into table (tk, tv).
 // G lanes cooperate; members are taken G at a time and their entries are
 // flattened so every lane has work whatever the member degrees.
@@ -715,11 +720,14 @@ __device__ inline void agg_accumulate(Rows<W> g, const uint32_t* C, const uint32
   }
 }
 
+// The table of a community takes min(T, 2 deg) slots (a power of two; at
+// most deg distinct keys), so a community of a few hundred entries does not
+// clear and scan all T.
 template <int G, int T, typename W>
 __global__ __launch_bounds__(kBlock) void k_agg_lds(Rows<W> g, const uint32_t* C, const uint32_t* members,
                                                     const uint64_t* moff, const uint32_t* list, const unsigned int* count,
-                                                    const uint64_t* cap_off, uint32_t* out_len, uint32_t* out_cols,
-                                                    int64_t* out_w, int64_t* Kout) {
+                                                    const uint64_t* deg, const uint64_t* cap_off, uint32_t* out_len,
+                                                    uint32_t* out_cols, int64_t* out_w, int64_t* Kout) {
   constexpr int GPB = kBlock / G;
   __shared__ uint32_t keys[GPB * T];
   __shared__ unsigned long long vals[GPB * T];
@@ -733,21 +741,22 @@ __global__ __launch_bounds__(kBlock) void k_agg_lds(Rows<W> g, const uint32_t* C
   const uint32_t cnt = *count;
   for (uint32_t base = blockIdx.x * GPB; base < cnt; base += gridDim.x * GPB) {
     const uint32_t item = base + grp;
-    for (int s = lane; s < T; s += G) {
+    const bool valid = item < cnt;
+    const uint32_t c = valid ? list[item] : 0;
+    const uint32_t tn = valid ? min((uint32_t)T, pow2_at_least((uint32_t)min<uint64_t>(2 * deg[c], T))) : 1u;
+    for (uint32_t s = lane; s < tn; s += G) {
       tk[s] = kNone;
       tv[s] = 0;
     }
     if (lane == 0) wpos[grp] = 0;
     __syncthreads();
-    const bool valid = item < cnt;
-    const uint32_t c = valid ? list[item] : 0;
     const uint64_t m0 = valid ? moff[c] : 0, m1 = valid ? moff[c + 1] : 0;
-    agg_accumulate<G, W>(g, C, members, m0, m1, tk, tv, T - 1, lane, sstart + grp * G, spre + grp * G);
+    agg_accumulate<G, W>(g, C, members, m0, m1, tk, tv, tn - 1, lane, sstart + grp * G, spre + grp * G);
     __syncthreads();
     unsigned long long ksum = 0;
     if (valid) {
       const uint64_t o = cap_off[c];
-      for (int sl = lane; sl < T; sl += G) {
+      for (uint32_t sl = lane; sl < tn; sl += G) {
         const uint32_t d = tk[sl];
         if (d == kNone) continue;
         const unsigned long long w = tv[sl];
@@ -772,7 +781,7 @@ __global__ __launch_bounds__(kBlock) void k_agg_lds(Rows<W> g, const uint32_t* C
 
 // Big communities: a group-by of each community's entries with no global
 // hash table (global atomics are slow, those on one address slowest).  Work
-// items are runs of members of one community; an item's entries are summed
+// items are parts of one community's entries; an item's entries are summed
 // into stages of at most kBigStage entries.  Each stage is summed by key in an
 // LDS table (the community's own key is summed in registers: most entries of
 // a large community stay inside it), and its distinct keys are sorted by
@@ -795,12 +804,17 @@ __global__ __launch_bounds__(kBlock) void k_agg_lds(Rows<W> g, const uint32_t* C
 // found by binary search.  The items of slice x are queued in list x, which
 // the blocks of XCD x take in turn, so the C[j] gathers of the long rows hit
 // the 1/8 of C that stays in that XCD's L2 instead of missing to memory.
-// Other items (whole rows, runs of kBigMembers) are dealt over the lists in
-// turn.  (Blocks taking items from shared counters instead were slower: the
-// counters' atomics queue on one memory channel.)
-constexpr uint32_t kBigMembers = 256, kBigStage = 2048, kBigSlots = 4096;
+// Items of whole rows are dealt over the lists in turn.  (Blocks taking items
+// from shared counters instead were slower: the counters' atomics queue on
+// one memory channel.)
+constexpr uint32_t kBigStage = 2048, kBigSlots = 4096;
 constexpr uint32_t kBigBucketBits = 10, kBigMaxRbits = 8, kEmitWin = 2048, kEmitSlices = 256;
-constexpr uint32_t kSlices = 8, kSliceMembers = 128, kSliceMinLen = 128, kWhole = 0xFFFFFFFFu;
+constexpr uint32_t kSlices = 8, kSliceMembers = 128, kSliceMinLen = 128;
+// Items of whole rows are ranges of kRangeEntries entries of the community's
+// whole-row members in member order (found through the members' entry
+// offsets), so that every item has the same work however long the rows are.
+constexpr uint32_t kRange = 0xFFFFFFFEu;
+constexpr uint64_t kRangeEntries = 8192;
 constexpr uint64_t kSliceMinDeg = 1u << 16;
 // a community's stage counter: columns used << kColShift | staging slots used
 constexpr uint32_t kColShift = 40;
@@ -809,14 +823,14 @@ struct BigComm {
   uint32_t c;      // community
   uint32_t rbits;  // log2 of its bucket count
   uint32_t smax;   // stage columns reserved
-  uint32_t pad;
+  uint32_t pad;    // whole-row members (the first ones of its member range)
   uint64_t soff;   // first staging slot (one per entry of the community)
   uint64_t moff;   // first matrix entry ((R + 1) * smax entries)
 };
 struct AggItem {
   uint32_t big;
-  uint32_t pad;   // stage items: the slice, or kWhole; emit items: the slice of the community's groups
-  uint64_t a, b;  // member range
+  uint32_t pad;   // stage items: the slice, or kRange; emit items: the slice of the community's groups
+  uint64_t a, b;  // member range, or for kRange the entry range relative to the community's first entry
 };
 
 __device__ inline uint32_t big_mix(uint32_t c) { return fmix32(c ^ kRowSalt); }
@@ -837,6 +851,7 @@ __device__ inline uint32_t row_lower_bound(const uint32_t* a, uint32_t L, uint32
 // sl: the kSlices + 1 list offsets into items; gridDim.x a multiple of kSlices
 template <typename W>
 __global__ __launch_bounds__(kBlock) void k_agg_stage(Rows<W> g, const uint32_t* C, const uint32_t* members,
+                                                      const uint64_t* moff, const uint64_t* eoff,
                                                       const BigComm* bc, const AggItem* items, unsigned int* sl,
                                                       uint32_t slice_w, uint32_t* skeys, unsigned long long* svals,
                                                       uint16_t* smat, unsigned long long* stage_ctr,
@@ -899,15 +914,40 @@ __global__ __launch_bounds__(kBlock) void k_agg_stage(Rows<W> g, const uint32_t*
       __syncthreads();
     };
     uint32_t fill = 0;  // entries summed into the table since the last stage column
-    for (uint64_t mb = x.a; mb < x.b; mb += kBlock) {
+    // members [mfirst, mend); a range item takes the entries [lo, hi) of the
+    // community's whole-row members in member order (eoff: entry offsets)
+    uint64_t mfirst = x.a, mend = x.b, lo = 0, hi = 0;
+    if (sx == kRange) {
+      const uint64_t m0 = moff[b.c];
+      mend = m0 + b.pad;
+      const uint64_t e0 = eoff[m0];
+      lo = e0 + x.a;
+      hi = min(e0 + x.b, eoff[mend]);
+      if (lo >= hi) return;  // block-uniform: past the members' entries
+      // the member holding entry lo: the last m with eoff[m] <= lo
+      uint64_t a = m0, z = mend - 1;
+      while (a < z) {
+        const uint64_t mid = (a + z + 1) >> 1;
+        if (eoff[mid] <= lo)
+          a = mid;
+        else
+          z = mid - 1;
+      }
+      mfirst = a;
+    }
+    for (uint64_t mb = mfirst; mb < mend; mb += kBlock) {
       const uint64_t mi = mb + threadIdx.x;
       uint32_t L = 0;
       int64_t st = 0;
-      if (mi < x.b) {
+      if (mi < mend) {
         const uint32_t v = members[mi];
         L = g.len[v];
         st = g.start[v];
-        if (sx != kWhole) {
+        if (sx == kRange) {
+          const uint64_t em = eoff[mi], a = max(em, lo), z = min(em + L, hi);
+          st += (int64_t)(a - em);
+          L = z > a ? (uint32_t)(z - a) : 0u;
+        } else {  // the part of a long row in slice sx
           const uint32_t* row = g.cols + st;
           const uint32_t e0 = sx == 0 ? 0u : row_lower_bound(row, L, sx * slice_w);
           const uint32_t e1 = sx == kSlices - 1 ? L : row_lower_bound(row, L, (sx + 1) * slice_w);
@@ -962,6 +1002,7 @@ __global__ __launch_bounds__(kBlock) void k_agg_stage(Rows<W> g, const uint32_t*
           fill = 0;
         }
       }
+      if (sx == kRange && eoff[min(mb + kBlock, mend)] >= hi) break;  // block-uniform
     }
     if (fill) flush();
     self = block_sum(self, red);
@@ -1143,11 +1184,11 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
   exclusive_scan_u64(s, b.cap_off, (uint64_t*)out_start, nc, b.total, b.scan_tmp);
   // kernel launches for small / medium communities read their counts on device
   hipLaunchKernelGGL((k_agg_lds<64, 256, W>), dim3(grid_n(nc, kBlock / 64, 2048)), dim3(kBlock), 0, s, g, C, b.members,
-                     b.comm_off, b.small_lists, &ctl->misc[2], (const uint64_t*)out_start, out_len, out_cols, out_w,
-                     Kout);
-  hipLaunchKernelGGL((k_agg_lds<kBlock, 4096, W>), dim3(grid_n(nc, 1, 2048)), dim3(kBlock), 0, s, g, C, b.members,
-                     b.comm_off, b.small_lists + (size_t)nc, &ctl->misc[3], (const uint64_t*)out_start, out_len,
+                     b.comm_off, b.small_lists, &ctl->misc[2], b.comm_deg, (const uint64_t*)out_start, out_len,
                      out_cols, out_w, Kout);
+  hipLaunchKernelGGL((k_agg_lds<kBlock, 4096, W>), dim3(grid_n(nc, 1, 2048)), dim3(kBlock), 0, s, g, C, b.members,
+                     b.comm_off, b.small_lists + (size_t)nc, &ctl->misc[3], b.comm_deg, (const uint64_t*)out_start,
+                     out_len, out_cols, out_w, Kout);
   // big communities: plan staging areas on the host
   unsigned int* pn = (unsigned int*)pinned_stage(4);
   if (!pn) return -1;
@@ -1155,6 +1196,9 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
   if (hipStreamSynchronize(s) != hipSuccess) return -1;
   const unsigned int nbig = *pn;
   if (nbig == 0) return 0;
+  // entry offsets of the members in member order (lengths in comm_fill, free after the scatter)
+  hipLaunchKernelGGL(k_member_len, dim3(grid_n(n)), dim3(kBlock), 0, s, b.members, n, g.len, b.comm_fill);
+  exclusive_scan_u32(s, b.comm_fill, b.member_eoff, n, b.member_eoff + n, b.scan_tmp);
   const uint32_t* big = b.small_lists + 2 * (size_t)nc;
   hipLaunchKernelGGL(k_big_info, dim3(grid_n(nbig)), dim3(kBlock), 0, s, big, &ctl->misc[4], b.comm_off, b.cap_off,
                      b.comm_deg, b.comm_fill_long, b.big_info);
@@ -1180,8 +1224,9 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
       // long rows (at the back of the member range) by slices, the others whole
       const bool sliced = sorted_rows && deg >= kSliceMinDeg && nlong > 0;
       const uint64_t ml = sliced ? m1 - nlong : m1;
-      const uint64_t nitems = (ml - m0 + kBigMembers - 1) / kBigMembers +
-                              (m1 - ml + kSliceMembers - 1) / kSliceMembers * kSlices;
+      // ranges over [0, deg), clipped on the device to the whole-row members' entries
+      const uint64_t nrange = ml > m0 ? (deg + kRangeEntries - 1) / kRangeEntries : 0;
+      const uint64_t nitems = nrange + (m1 - ml + kSliceMembers - 1) / kSliceMembers * kSlices;
       // stage columns: every item's stages hold at most kBigStage entries, so
       // deg / kBigStage + one partial stage per item
       const uint64_t smax = deg / kBigStage + nitems + 1;
@@ -1194,9 +1239,10 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
           (used + slots > b.scap || mused + ment > b.mcap || nstage + nemitted + nitems + nemit > b.item_cap))
         break;
       const uint32_t r = (uint32_t)rc.size();
-      rc.push_back(BigComm{ids[last], rb, (uint32_t)smax, 0, used, mused});
-      for (uint64_t a = m0; a < ml; a += kBigMembers)
-        lists[spread++ % kSlices].push_back(AggItem{r, kWhole, a, std::min(ml, a + kBigMembers)});
+      rc.push_back(BigComm{ids[last], rb, (uint32_t)smax, (uint32_t)(ml - m0), used, mused});
+      for (uint64_t j = 0; j < nrange; ++j)
+        lists[spread++ % kSlices].push_back(
+            AggItem{r, kRange, j * kRangeEntries, std::min(deg, (j + 1) * kRangeEntries)});
       for (uint64_t a = ml; a < m1; a += kSliceMembers)
         for (uint32_t x = 0; x < kSlices; ++x) lists[x].push_back(AggItem{r, x, a, std::min(m1, a + kSliceMembers)});
       used += slots;
@@ -1240,7 +1286,7 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
     const bool timed = sizeof(W) == 4;
     if (timed) kt_mark(LEIDEN_KT_AGG_BIG, s);
     hipLaunchKernelGGL(k_agg_stage<W>, dim3(kSlices * std::min<size_t>(longest, 512)), dim3(kBlock), 0, s, g, C, b.members,
-                       (const BigComm*)b.bigc, di, b.slice_ctl, (n + kSlices - 1) / kSlices, b.skeys, b.svals, b.smat,
+                       (const uint64_t*)b.comm_off, (const uint64_t*)b.member_eoff, (const BigComm*)b.bigc, di, b.slice_ctl, (n + kSlices - 1) / kSlices, b.skeys, b.svals, b.smat,
                        b.stage_ctr, b.self_acc, timed ? &ctl->kt_units[LEIDEN_KT_AGG_BIG] : nullptr);
     if (timed) kt_mark(LEIDEN_KT_AGG_BIG, s);
     const size_t nemit = ins.size() - nins;

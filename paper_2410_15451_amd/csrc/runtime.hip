@@ -187,7 +187,7 @@ struct leiden_graph {
   Buf cls_lists, bin_lists, iter_list, next_list, movers, split_list, split_rest, split_key, split_wide, lab;
   Buf flag, newid, scan_tmp, ctl, small;
   Buf lvA_start, lvA_len, lvA_cols, lvA_w, lvB_start, lvB_len, lvB_cols, lvB_w;
-  Buf agg_count, agg_off, agg_fill, agg_fill2, agg_members, agg_deg, agg_cap, agg_lists, agg_bigcap, agg_tbl, agg_keys, agg_vals,
+  Buf agg_count, agg_off, agg_fill, agg_fill2, agg_eoff, agg_members, agg_deg, agg_cap, agg_lists, agg_bigcap, agg_tbl, agg_keys, agg_vals,
       agg_mat, agg_items, mark_items;
   Buf hub_keys, hub_vals, hub_list, hub_idx, hub_off, hub_moff, hub_rbits, hub_size, hub_msize, hub_kid;
   Buf hub_items, hub_mat, hub_live, hub_pdq, hub_pc, hub_done;
@@ -367,6 +367,7 @@ leiden_status ensure_workspace(leiden_graph* G, hipStream_t s, uint32_t classes)
   CHK(G->agg_off.reserve((n + 1) * u64));
   CHK(G->agg_fill.reserve(n * u32));
   CHK(G->agg_fill2.reserve(n * u32));
+  CHK(G->agg_eoff.reserve((n + 1) * u64));
   CHK(G->agg_members.reserve(n * u32));
   CHK(G->agg_deg.reserve(n * u64));
   CHK(G->agg_cap.reserve((n + 1) * u64));
@@ -751,6 +752,7 @@ AggBufs agg_bufs(leiden_graph* G, uint64_t* total) {
   ab.comm_off = G->agg_off.as<uint64_t>();
   ab.comm_fill = G->agg_fill.as<uint32_t>();
   ab.comm_fill_long = G->agg_fill2.as<uint32_t>();
+  ab.member_eoff = G->agg_eoff.as<uint64_t>();
   ab.members = G->agg_members.as<uint32_t>();
   ab.comm_deg = G->agg_deg.as<uint64_t>();
   ab.cap_off = G->agg_cap.as<uint64_t>();
