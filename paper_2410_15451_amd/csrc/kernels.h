@@ -251,7 +251,7 @@ struct AggBufs {
   uint64_t* cap_off;      // super-row capacity offsets (n + 1)
   uint64_t* total;        // device scalars
   void* scan_tmp;
-  uint32_t* small_lists;  // communities per bin (small, medium, big), n each
+  uint32_t* small_lists;  // communities per class (small, large medium, big, medium), n each
   uint64_t* big_info;     // (member begin, member end, capacity, entries) of each big community, 4 n
   void* bigc;             // per-round descriptors of big communities (32 B each, n)
   void* items;            // per-round work items (24 B each, item_cap)

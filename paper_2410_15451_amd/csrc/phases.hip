@@ -599,15 +599,18 @@ __global__ __launch_bounds__(kBlock) void k_comm_scatter(const uint32_t* C, uint
   }
 }
 
-// Row capacities and classification: 0 = small (LDS, 64 lanes, 256 slots),
-// 1 = medium (LDS, block, 4096 slots), 2 = big (global table).
-constexpr uint64_t kAggSmall = 128, kAggMedium = 2048;
+// Row capacities and classification by entries: 0 = small (LDS, 64 lanes,
+// 256 slots), 3 = medium (LDS, block, 1024 slots), 1 = large medium (LDS,
+// block, 4096 slots), 2 = big (staging).  One block per community decides
+// one community at a time, so the 1024-slot class (12 KB of LDS: eight
+// blocks per CU instead of three) keeps more communities in flight.
+constexpr uint64_t kAggSmall = 128, kAggMid = 512, kAggMedium = 2048;
 
 __global__ __launch_bounds__(kBlock) void k_comm_classify(uint32_t nc, const uint64_t* deg, uint64_t* cap,
                                                           uint32_t* out_len, int64_t* Kout, uint32_t* lists,
                                                           size_t stride, Ctl* ctl) {
-  __shared__ unsigned int scnt[3], sbase[3];
-  if (threadIdx.x < 3) scnt[threadIdx.x] = 0;
+  __shared__ unsigned int scnt[4], sbase[4];
+  if (threadIdx.x < 4) scnt[threadIdx.x] = 0;
   __syncthreads();
   constexpr uint32_t tile = kBlock * kTileU;
   for (uint64_t base = (uint64_t)blockIdx.x * tile; base < nc; base += (uint64_t)gridDim.x * tile) {
@@ -622,10 +625,10 @@ __global__ __launch_bounds__(kBlock) void k_comm_classify(uint32_t nc, const uin
         cap[c] = d < nc ? d : nc;
         out_len[c] = 0;
         Kout[c] = 0;
-        if (d > 0) key[u] = d <= kAggSmall ? 0u : (d <= kAggMedium ? 1u : 2u);
+        if (d > 0) key[u] = d <= kAggSmall ? 0u : (d <= kAggMid ? 3u : (d <= kAggMedium ? 1u : 2u));
       }
     }
-    tile_append<kTileU>(key, val, 3, scnt, sbase, [&](uint32_t b, uint32_t*& l, unsigned int*& cn) {
+    tile_append<kTileU>(key, val, 4, scnt, sbase, [&](uint32_t b, uint32_t*& l, unsigned int*& cn) {
       l = lists + (size_t)b * stride;
       cn = &ctl->misc[2 + b];
     });
@@ -1161,7 +1164,7 @@ __global__ __launch_bounds__(kBlock) void k_agg_emit(const BigComm* bc, const Ag
 }
 
 __global__ void k_zero_misc_agg(Ctl* ctl) {
-  if (threadIdx.x < 3) ctl->misc[2 + threadIdx.x] = 0;
+  if (threadIdx.x < 4) ctl->misc[2 + threadIdx.x] = 0;
 }
 
 template <typename W>
@@ -1186,6 +1189,9 @@ int aggregate(hipStream_t s, Rows<W> g, uint32_t n, const uint32_t* C, uint32_t 
   hipLaunchKernelGGL((k_agg_lds<64, 256, W>), dim3(grid_n(nc, kBlock / 64, 2048)), dim3(kBlock), 0, s, g, C, b.members,
                      b.comm_off, b.small_lists, &ctl->misc[2], b.comm_deg, (const uint64_t*)out_start, out_len,
                      out_cols, out_w, Kout);
+  hipLaunchKernelGGL((k_agg_lds<kBlock, 1024, W>), dim3(grid_n(nc, 1, 2048)), dim3(kBlock), 0, s, g, C, b.members,
+                     b.comm_off, b.small_lists + 3 * (size_t)nc, &ctl->misc[5], b.comm_deg,
+                     (const uint64_t*)out_start, out_len, out_cols, out_w, Kout);
   hipLaunchKernelGGL((k_agg_lds<kBlock, 4096, W>), dim3(grid_n(nc, 1, 2048)), dim3(kBlock), 0, s, g, C, b.members,
                      b.comm_off, b.small_lists + (size_t)nc, &ctl->misc[3], b.comm_deg, (const uint64_t*)out_start,
                      out_len, out_cols, out_w, Kout);

@@ -371,7 +371,7 @@ leiden_status ensure_workspace(leiden_graph* G, hipStream_t s, uint32_t classes)
   CHK(G->agg_members.reserve(n * u32));
   CHK(G->agg_deg.reserve(n * u64));
   CHK(G->agg_cap.reserve((n + 1) * u64));
-  CHK(G->agg_lists.reserve(3 * n * u32));
+  CHK(G->agg_lists.reserve(4 * n * u32));
   CHK(G->agg_bigcap.reserve(4 * n * u64));
   CHK(G->agg_tbl.reserve(n * 48));  // per-round descriptors (32 B) and counters (4 + 8 B) of big communities
   CHK(G->agg_items.reserve(kAggItems * 24));
