@@ -67,6 +67,12 @@ __global__ __launch_bounds__(kBlock) void k_bin(const uint32_t* list, const unsi
                                                 Ctl* ctl) {
   __shared__ unsigned int scnt[kBins], sbase[kBins];
   if (threadIdx.x < kBins) scnt[threadIdx.x] = 0;
+  // the previous sub-round's mover and marking counts (their readers, the
+  // apply and marking kernels, have finished; nothing here reads them)
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->mover_count = 0;
+    ctl->mark_items = 0;
+  }
   __syncthreads();
   const uint32_t cnt = *count;
   constexpr uint32_t tile = kBlock * kBinU;
@@ -836,7 +842,17 @@ __device__ inline void apply_delta(uint32_t* tk, unsigned long long* ts, unsigne
   atomicAdd(&tn[h], (unsigned int)dn);
 }
 
+// The sub-round's bin counts and hub items, cleared for the next sub-round
+// by the apply kernel (its decide kernels, their only readers, have finished).
+__device__ inline void clear_bins(Ctl* ctl) {
+  if (blockIdx.x == 0) {
+    if (threadIdx.x < kBins) ctl->bin_count[threadIdx.x] = 0;
+    if (threadIdx.x == 0) ctl->hub_items = 0;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_apply_moves(ApplyParams p) {
+  clear_bins(p.ctl);
   __shared__ unsigned int wtot[kBlock / kWave];
   __shared__ unsigned int sbase;
   __shared__ unsigned long long red[kBlock / kWave];
@@ -953,6 +969,7 @@ __global__ __launch_bounds__(kBlock) void k_mark_items(ApplyParams p) {
 // Refinement moves: an isolated vertex joins its chosen sub-community.
 __global__ __launch_bounds__(kBlock) void k_apply_refine(uint32_t* C, int64_t* S, const int64_t* K, uint32_t* size,
                                                          const Mover* movers, Ctl* ctl) {
+  clear_bins(ctl);
   const uint32_t cnt = ctl->mover_count;
   for (uint32_t m = blockIdx.x * kBlock + threadIdx.x; m < cnt; m += gridDim.x * kBlock) {
     const Mover mv = movers[m];
@@ -977,8 +994,16 @@ __global__ void k_subround_reset(Ctl* ctl) {
 }
 
 // Start of an iteration: the vertices queued as unprocessed become this
-// iteration's input (the host swaps the two list buffers to match).
+// iteration's input (the host swaps the two list buffers to match); the first
+// sub-round's counters start at zero (later sub-rounds: the bin and apply
+// kernels of the one before clear them).
 __global__ void k_iteration_reset(Ctl* ctl, uint32_t P) {
+  if (threadIdx.x < kBins) ctl->bin_count[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    ctl->mover_count = 0;
+    ctl->mark_items = 0;
+    ctl->hub_items = 0;
+  }
   if (threadIdx.x < kMaxClasses) ctl->cls_count[threadIdx.x] = 0;
   if (threadIdx.x == 0) {
     ctl->dq_fixed = 0;
@@ -1110,6 +1135,12 @@ void launch_iteration_reset(hipStream_t s, Ctl* ctl, uint32_t P) {
 }
 
 __global__ void k_cls_reset(Ctl* ctl) {
+  if (threadIdx.x < kBins) ctl->bin_count[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    ctl->mover_count = 0;
+    ctl->mark_items = 0;
+    ctl->hub_items = 0;
+  }
   if (threadIdx.x < kMaxClasses) ctl->cls_count[threadIdx.x] = 0;
 }
 

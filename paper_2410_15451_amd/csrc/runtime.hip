@@ -607,8 +607,9 @@ leiden_status local_move(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
     const bool all = li == 0 && (!first_pass || ro.init_all);
     launch_distribute(s, all ? nullptr : iter_list, all ? nullptr : &ctl->iter_count, nl, li, P, stamp,
                       G->pend.as<uint32_t>(), G->cls_lists.as<uint32_t>(), (size_t)nl, ctl);
+    // each sub-round's counters are cleared by the iteration reset, or by
+    // the previous sub-round's bin (movers, marks) and apply (bins, hubs)
     for (uint32_t k = 0; k < P; ++k) {
-      launch_subround_reset(s, ctl);
       launch_bin(s, G->cls_lists.as<uint32_t>() + (size_t)k * nl, &ctl->cls_count[k], nl, g.len, in_range,
                  G->bin_lists.as<uint32_t>(), (size_t)nl, G->bincfg, G->hub_items.as<unsigned long long>(), ctl);
       launch_decide_all<W, false>(s, dp, G->bin_lists.as<uint32_t>(), (size_t)nl, ctl->bin_count, bins, maxdeg,
@@ -680,8 +681,9 @@ leiden_status refine(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, Lev
   dp.async = async ? 1 : 0;
   bind_hubs(G, dp);
   dp.pick_segs = hub_pick_segs(maxdeg);
+  // each colour round's counters are cleared by the class reset above, or by
+  // the previous round's bin (movers) and apply (bins, hubs)
   for (uint32_t r = 0; r < R; ++r) {
-    launch_subround_reset(s, ctl);
     launch_bin(s, G->cls_lists.as<uint32_t>() + (size_t)r * nl, &ctl->cls_count[r], nl, g.len, nullptr,
                G->bin_lists.as<uint32_t>(), (size_t)nl, G->bincfg, G->hub_items.as<unsigned long long>(), ctl);
     dp.colour = r;
