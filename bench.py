@@ -314,6 +314,99 @@ def run_stability(args, binding, inputs):
             "paper_context": "the paper reports DF Leiden with tracking keeping 84% to 44% for 1e-7 to 0.1 |E|"}
 
 
+def chunglu_modularity(offs, cols, w, C, n):
+    """Eq. 1 of membership C recomputed with torch on the device, rows taken
+    in chunks (an independent check of the library's value)."""
+    import torch
+    C = C.to(torch.int64)
+    deg = offs[1:] - offs[:-1]
+    K = torch.zeros(n, dtype=torch.int64, device=offs.device)
+    intra = 0
+    step = 1 << 22
+    for r0 in range(0, n, step):
+        r1 = min(n, r0 + step)
+        a, b = int(offs[r0]), int(offs[r1])
+        src = torch.repeat_interleave(torch.arange(r0, r1, device=offs.device), deg[r0:r1])
+        ww = w[a:b].to(torch.int64)
+        K[r0:r1] = torch.zeros(r1 - r0, dtype=torch.int64, device=offs.device).index_add_(0, src - r0, ww)
+        same = C[src] == C[cols[a:b].to(torch.int64)]
+        intra += int(ww[same].sum())
+    S = torch.zeros(n, dtype=torch.int64, device=offs.device).index_add_(0, C, K)
+    m2 = int(K.sum())
+    ssq = float((S.to(torch.float64) ** 2).sum())
+    return intra / m2 - ssq / float(m2) ** 2
+
+
+def run_chunglu(args, binding, inputs):
+    """The large single graph: a Chung-Lu graph (exponent 2.1, largest
+    expected degree 10^6, mean degree 40, weights 1..16) of --cl-vertices
+    vertices made on the device; static Leiden, then DF Leiden over batch
+    sizes 1e-7 .. 1e-1 |E| (80% insertions / 20% deletions), each size once
+    in the deterministic and once in the asynchronous mode, on the evolving
+    graph.  Reports time and modularity per (fraction, mode); the static
+    result's modularity is checked against a recomputation with torch."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    n = args.cl_vertices
+    t0 = time.time()
+    offs, cols, w = inputs.chung_lu_torch(n, inputs.BASE_SEED + 60, dev)
+    torch.cuda.synchronize()
+    nnz = cols.numel()
+    maxdeg = int((offs[1:] - offs[:-1]).max())
+    log("chung-lu: n=%d nnz=%d maxdeg=%d (%.1f s)" % (n, nnz, maxdeg, time.time() - t0))
+    # the update pool first, while the library holds no memory yet
+    fracs = (1e-7, 1e-6, 1e-5, 1e-4, 1e-3, 1e-2, 1e-1)
+    E = nnz // 2
+    sizes = [max(1, int(round(f * E))) for f in fracs]
+    n_ins = [int(round(0.8 * b)) for b in sizes]
+    n_del = [b - i for b, i in zip(sizes, n_ins)]
+    t = time.time()
+    dels, ins = inputs.update_pool_torch(offs, cols, 2 * sum(n_del), 2 * sum(n_ins), inputs.BASE_SEED + 61,
+                                         w_range=(1, 16))
+    log("update pool: %d deletions, %d insertions (%.1f s)" % (dels.shape[0], ins.shape[0], time.time() - t))
+    torch.cuda.empty_cache()
+    G = binding.Graph(offs, cols, w)
+    out = torch.zeros(n, dtype=torch.int32, device=dev)
+    G.static(out=out)  # the first run also allocates the workspace
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rs = G.static(out=out)
+    torch.cuda.synchronize()
+    t_static = time.perf_counter() - t
+    log("static: %.1f ms, passes %d, q=%.6f" % (t_static * 1e3, rs.stats["passes"], rs.q))
+    q_check = chunglu_modularity(offs, cols, w, out, n)
+    log("static modularity recomputed with torch: %.9f (library %.9f)" % (q_check, rs.q))
+    assert int(out.min()) >= 0 and int(out.max()) < n
+    assert abs(q_check - rs.q) < 1e-9, (q_check, rs.q)
+    del offs, cols, w
+    torch.cuda.empty_cache()
+    pd = pi = 0
+    rows = {}
+    for f, nd, ni in zip(fracs, n_del, n_ins):
+        for mode, det in (("deterministic", 1), ("asynchronous", 0)):
+            d = torch.from_numpy(dels[pd:pd + nd].view(np.int32)).to(dev)
+            i = torch.from_numpy(ins[pi:pi + ni].view(np.int32)).to(dev)
+            pd += nd
+            pi += ni
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = G.update(d, i, mode="df", out=out, deterministic=det)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            rows.setdefault("%g" % f, {})[mode] = {"ms": dt * 1e3, "q": r.q, "passes": r.stats["passes"],
+                                                  "affected": r.stats["affected"], "updates": nd + ni}
+            log("df %s f=%g (%d updates): %.1f ms, q=%.6f, affected %d" % (mode, f, nd + ni, dt * 1e3, r.q,
+                                                                        r.stats["affected"]))
+            del d, i
+    G.close()
+    return {"metric": "large single graph: DF Leiden update time over batch sizes", "value": rows["0.001"]["deterministic"]["ms"],
+            "unit": "ms", "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "int64+f64",
+            "config": {"workload": "chunglu_df_sweep", "n": n, "nnz": nnz, "max_degree": maxdeg, "gamma": 2.1,
+                       "weights": "1..16", "value_is": "deterministic DF update at 1e-3 |E|"},
+            "static_ms": t_static * 1e3, "static_q": rs.q, "static_q_torch": q_check, "by_fraction": rows}
+
+
 def run_temporal(args, binding, inputs):
     """Temporal replay (the paper's real-world dynamic experiment with a
     synthetic stream): 90% of the edges preloaded, static Leiden, then 100
@@ -524,10 +617,11 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=24)
     ap.add_argument("--timed-kernel", default="agg_big", help="kernel timed with HIP events for the roofline")
     ap.add_argument("--workload", default="rmat",
-                    choices=["rmat", "forest", "serving", "stability", "temporal", "ablation"],
+                    choices=["rmat", "forest", "serving", "stability", "temporal", "ablation", "chunglu"],
                     help="rmat: the 4M-vertex R-MAT DF stream (default); forest: 4,096 kNN graphs as "
                          "block-diagonal forests; "
-                         "serving: tenant R-MAT graphs under a Poisson stream of update requests")
+                         "serving: tenant R-MAT graphs under a Poisson stream of update requests; chunglu: the "
+                         "large single Chung-Lu graph, DF over batch sizes 1e-7..1e-1 |E|")
     ap.add_argument("--graphs", type=int, default=4096, help="forest: number of kNN graphs")
     ap.add_argument("--forest-entries", type=float, default=1.2e9, help="forest: most entries of one forest")
     ap.add_argument("--single-sample", type=int, default=128, help="forest: graphs also run one at a time")
@@ -536,6 +630,7 @@ def main():
     ap.add_argument("--warm-requests", type=int, default=50, help="serving: back-to-back warm-up requests")
     ap.add_argument("--loads", default="0.3,0.5,0.7,0.9", help="serving: offered loads (fractions of capacity)")
     ap.add_argument("--tenant-scales", default="20,20,21,21,22,22,23,23", help="serving: R-MAT scales of the tenants")
+    ap.add_argument("--cl-vertices", type=int, default=50_000_000, help="chunglu: vertices of the large graph")
     ap.add_argument("--marker", type=int, default=0,
                     help="launch a spin kernel right before and after the timed static run and the timed "
                          "update steps (profile windows 0 and 1)")
@@ -565,6 +660,9 @@ def main():
         return
     if args.workload == "ablation":
         print(json.dumps(run_ablation(args, binding, inputs)), flush=True)
+        return
+    if args.workload == "chunglu":
+        print(json.dumps(run_chunglu(args, binding, inputs)), flush=True)
         return
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()

@@ -42,6 +42,9 @@ stand in for them):
     64 points around it in the order of (bucket, a random projection) rather
     than among its whole bucket, and the weight is 1 + floor(99 D / (D + d^2))
     (integer arithmetic);
+  * Chung-Lu at full size (the large single graph: 5*10^7 vertices, about
+    2*10^9 entries) is made on the device by ``chung_lu_torch`` with the same
+    recipe (endpoint pairs drawn in chunks);
   * serving tenants: R-MAT graphs by the recipe above made on the device by
     ``rmat_torch`` (torch random streams), and per tenant one pool of distinct
     edges to delete and distinct absent pairs to insert whose prefixes make
@@ -452,6 +455,58 @@ def rmat_torch(scale: int, seed: int, device, edge_factor: int = 16, a: float = 
     offs = torch.zeros(n + 1, dtype=torch.int64, device=device)
     offs[1:] = torch.cumsum(torch.bincount(s2, minlength=n), 0)
     return offs, d2.to(torch.int32), torch.ones_like(d2, dtype=torch.int32)
+
+
+def chung_lu_torch(n: int, seed: int, device, avg_degree: float = 40.0, max_degree: float = 1e6,
+                   gamma: float = 2.1, wmax: int = 16, chunk: int = 1 << 26):
+    """Chung-Lu graph by the recipe of ``chung_lu`` made with torch on
+    ``device`` (its own random streams, so not the same graph as
+    ``chung_lu`` with the same seed): round(avg_degree * n / 2) endpoint
+    pairs drawn in chunks, self-loops and repeated pairs dropped, weights
+    uniform in 1..wmax per undirected edge, a seeded vertex permutation.
+    Returns (offs int64[n+1], cols int32[nnz], w int32[nnz]) tensors."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    wt = torch.from_numpy(chung_lu_weights(n, avg_degree, max_degree, gamma)).to(device)
+    cdf = torch.cumsum(wt, 0)
+    cdf /= cdf[-1].clone()
+    del wt
+    m = int(round(avg_degree * n / 2))
+    keys = []
+    for a in range(0, m, chunk):
+        c = min(chunk, m - a)
+        u = torch.searchsorted(cdf, torch.rand(c, generator=g, device=device, dtype=torch.float64), right=True)
+        v = torch.searchsorted(cdf, torch.rand(c, generator=g, device=device, dtype=torch.float64), right=True)
+        u.clamp_(max=n - 1)
+        v.clamp_(max=n - 1)
+        keep = u != v
+        lo, hi = torch.minimum(u, v)[keep], torch.maximum(u, v)[keep]
+        del u, v, keep
+        keys.append(torch.unique(lo * n + hi))
+        del lo, hi
+    del cdf
+    key = torch.unique(torch.cat(keys))
+    del keys
+    ww = torch.randint(1, wmax + 1, (key.numel(),), generator=g, device=device, dtype=torch.int32)
+    perm = torch.randperm(n, generator=g, device=device)
+    a, b = perm[key // n], perm[key % n]
+    del key, perm
+    # both directions, sorted by (row, column)
+    rk = torch.cat([a * n + b, b * n + a])
+    del a, b
+    ww = torch.cat([ww, ww])
+    rk, order = torch.sort(rk)
+    ww = ww[order]
+    del order
+    src = rk // n
+    offs = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    offs[1:] = torch.cumsum(torch.bincount(src, minlength=n), 0)
+    del src
+    cols = (rk % n).to(torch.int32)
+    del rk
+    return offs, cols, ww
 
 
 def update_pool_torch(offs, cols, n_del: int, n_ins: int, seed: int, w_range=(1, 1)):

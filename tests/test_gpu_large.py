@@ -1,0 +1,61 @@
+"""The large single graph at its full size: a Chung-Lu graph of 5*10^7
+vertices and about 1.9*10^9 entries (exponent 2.1, largest expected degree
+10^6, weights 1..16), made on the device.
+
+The oracle cannot run at this size, so the results are checked by
+properties that hold at any size: every label is a vertex ID, the reported
+modularity equals Eq. 1 of the returned membership recomputed here with
+torch from the graph (exact integer sums, one FP64 formula), and a DF update
+returns a valid membership whose reported modularity equals the library's
+own Eq. 1 of it.  Parity with the oracle on the same recipe is tested at
+2^20 vertices (test_chung_lu_power_law).
+"""
+import sys
+import os
+
+import numpy as np
+import pytest
+
+from paper_2410_15451_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+
+def test_chung_lu_full_size_properties():
+    import torch
+
+    import bench
+    from paper_2410_15451_amd import binding
+    binding.lib()
+    n = 50_000_000
+    dev = torch.device("cuda:0")
+    offs, cols, w = inputs.chung_lu_torch(n, inputs.BASE_SEED + 60, dev)
+    nnz = cols.numel()
+    print("chung-lu: n=%d nnz=%d" % (n, nnz), flush=True)
+    assert nnz > 1_500_000_000 and int((offs[1:] - offs[:-1]).max()) > 500_000
+    E = nnz // 2
+    nb = int(round(1e-3 * E))
+    dels, ins = inputs.update_pool_torch(offs, cols, nb - int(round(0.8 * nb)), int(round(0.8 * nb)),
+                                         inputs.BASE_SEED + 61, w_range=(1, 16))
+    torch.cuda.empty_cache()
+    G = binding.Graph(offs, cols, w)
+    try:
+        out = torch.zeros(n, dtype=torch.int32, device=dev)
+        rs = G.static(out=out)
+        assert int(out.min()) >= 0 and int(out.max()) < n
+        q = bench.chunglu_modularity(offs, cols, w, out, n)
+        print("static q %.9f, recomputed %.9f" % (rs.q, q), flush=True)
+        assert abs(q - rs.q) < 1e-9, (q, rs.q)
+        del offs, cols, w
+        torch.cuda.empty_cache()
+        r = G.update(torch.from_numpy(dels.view(np.int32)).to(dev), torch.from_numpy(ins.view(np.int32)).to(dev),
+                     mode="df", out=out)
+        assert int(out.min()) >= 0 and int(out.max()) < n
+        assert r.stats["nnz"] == nnz + 2 * (ins.shape[0] - dels.shape[0])
+        assert G.modularity(out) == r.q
+        print("df update q %.9f" % r.q, flush=True)
+    finally:
+        G.close()
+        torch.cuda.empty_cache()
