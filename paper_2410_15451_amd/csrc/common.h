@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <type_traits>
 
 namespace lm {
 
@@ -340,7 +341,7 @@ __device__ inline void table_accumulate_listed(KeyPtr keys, ValPtr vals, uint32_
       }
       const uint32_t k = __atomic_load_n(&keys[h], __ATOMIC_RELAXED);
       if (k == key) {
-        atomicAdd(&vals[h], w);
+        atomicAdd(&vals[h], (std::remove_cv_t<std::remove_pointer_t<ValPtr>>)w);
         key = kNone;
         continue;
       }
@@ -351,7 +352,7 @@ __device__ inline void table_accumulate_listed(KeyPtr keys, ValPtr vals, uint32_
           if (x < cap) list[x] = (uint16_t)h;
         }
         if (o == kNone || o == key) {
-          atomicAdd(&vals[h], w);
+          atomicAdd(&vals[h], (std::remove_cv_t<std::remove_pointer_t<ValPtr>>)w);
           key = kNone;
           continue;
         }

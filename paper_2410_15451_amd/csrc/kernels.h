@@ -23,6 +23,7 @@ struct DecideParams {
   Ctl* ctl;
   unsigned long long* edge_parts;  // edge scans, kEdgeParts counters kEdgeStride apart
   int async;             // 1: moves are applied at once against the live state
+  int narrow;            // 1: 2m < 2^32, so every K_{i->c} fits 32 bits (narrower LDS tables)
   uint8_t* dS;           // split flags for asynchronous local moves (dynamic runs) or null
   // hub bin: a hub of degree L has nch = ceil(L / kHubChunk) chunks; chunk k
   // owns staging slots [k * kHubChunk, (k + 1) * kHubChunk) of the hub's

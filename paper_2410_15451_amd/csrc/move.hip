@@ -361,13 +361,16 @@ __global__ __launch_bounds__(kBlock) void k_decide_small(DecideParams<W> p, Smal
 // One block (kBlock lanes) per vertex, T-slot table in LDS.  The table
 // starts empty and lists the slots it takes: a vertex reads and clears only
 // those (its distinct communities are usually far fewer than the slots).
-template <int T, typename W, bool REFINE>
+// V: the table's sums, 64-bit, or 32-bit when 2m < 2^32 (a 4096-slot table
+// then takes 32 KB of LDS instead of 48 KB: four blocks per CU instead of
+// three, and a block decides one vertex at a time)
+template <int T, typename W, bool REFINE, typename V = unsigned long long>
 __global__ __launch_bounds__(kBlock) void k_decide_block(DecideParams<W> p) {
   // slot list of at most LC entries (a vertex with more distinct communities
   // reads and clears the whole table); 512 keeps three 4096-slot blocks per CU
   constexpr uint32_t LC = T < 512 ? T : 512;
   __shared__ uint32_t tk[T];
-  __shared__ unsigned long long tv[T];
+  __shared__ V tv[T];
   __shared__ uint16_t used[LC];
   __shared__ unsigned int nused;
   __shared__ unsigned long long red[kBlock / kWave];
@@ -1083,8 +1086,12 @@ void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, si
                            t, q);
         break;
       case 4:
-        hipLaunchKernelGGL((k_decide_block<4096, W, REFINE>), dim3(grid_for(bin_upper[b], 1, 1024)), dim3(kBlock), 0,
-                           t, q);
+        if (p.narrow)
+          hipLaunchKernelGGL((k_decide_block<4096, W, REFINE, unsigned int>), dim3(grid_for(bin_upper[b], 1, 1024)),
+                             dim3(kBlock), 0, t, q);
+        else
+          hipLaunchKernelGGL((k_decide_block<4096, W, REFINE>), dim3(grid_for(bin_upper[b], 1, 1024)), dim3(kBlock),
+                             0, t, q);
         break;
       default: {
         if (sizeof(W) == 4 && !REFINE) kt_mark(LEIDEN_KT_HUB_INSERT, t);

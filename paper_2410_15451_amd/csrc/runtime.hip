@@ -116,9 +116,11 @@ uint64_t next_pow2(uint64_t x) {
 // Eq. 2 constants from 2m, computed once per run on the host.
 struct QConst {
   double inv_m = 0, inv_2m2 = 0;
+  bool narrow = false;  // 2m < 2^32: every K_{i->c} fits 32 bits
 };
 QConst make_qconst(uint64_t M2) {
   QConst q;
+  q.narrow = M2 < (1ull << 32);
   const double m = 0.5 * (double)M2;
   q.inv_m = 1.0 / m;
   q.inv_2m2 = 1.0 / ((2.0 * m) * m);
@@ -596,6 +598,7 @@ leiden_status local_move(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl,
   dp.movers = G->movers.as<Mover>();
   dp.ctl = ctl;
   dp.async = async ? 1 : 0;
+  dp.narrow = qc.narrow ? 1 : 0;
   dp.dS = ro.dynamic ? L.dS : nullptr;
   bind_hubs(G, dp);
   dp.pick_segs = hub_pick_segs(maxdeg);
@@ -679,6 +682,7 @@ leiden_status refine(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, Lev
   dp.movers = G->movers.as<Mover>();
   dp.ctl = ctl;
   dp.async = async ? 1 : 0;
+  dp.narrow = qc.narrow ? 1 : 0;
   bind_hubs(G, dp);
   dp.pick_segs = hub_pick_segs(maxdeg);
   // each colour round's counters are cleared by the class reset above, or by
