@@ -175,7 +175,9 @@ leiden_status leiden_set_tuning(leiden_graph* g, const leiden_tuning* t);
  * it in *out (may be NULL).  The handle's graph and state are unchanged. */
 leiden_status leiden_autotune(leiden_graph* g, const leiden_opts* opts, leiden_tuning* out);
 
-/* Symbol of a leiden_kernel as profilers list it (NULL for an unknown value). */
+/* Symbol of a leiden_kernel as profilers list it (NULL for an unknown value).
+ * For LEIDEN_KT_HUB_INSERT it is the prefix common to the kernel's two
+ * instantiations (32-bit table sums when 2m < 2^32, else 64-bit). */
 const char* leiden_kernel_name(int32_t kernel);
 
 /* Fill *opts with the defaults above. */

@@ -289,14 +289,14 @@ __device__ inline void table_accumulate(KeyPtr keys, ValPtr vals, uint32_t mask,
       }
       const uint32_t k = __atomic_load_n(&keys[h], __ATOMIC_RELAXED);
       if (k == key) {
-        atomicAdd(&vals[h], w);
+        atomicAdd(&vals[h], (std::remove_cv_t<std::remove_pointer_t<ValPtr>>)w);
         key = kNone;
         continue;
       }
       if (k == kNone) {
         const uint32_t o = atomicCAS(&keys[h], kNone, key);
         if (o == kNone || o == key) {
-          atomicAdd(&vals[h], w);
+          atomicAdd(&vals[h], (std::remove_cv_t<std::remove_pointer_t<ValPtr>>)w);
           key = kNone;
           continue;
         }

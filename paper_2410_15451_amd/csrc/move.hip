@@ -489,11 +489,12 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(DecideParams<W> p) {
 // ---------------------------------------------------------------------------
 __device__ inline uint32_t hub_bucket(uint32_t c, uint32_t rb) { return rb ? fmix32(c) >> (32 - rb) : 0u; }
 
-template <typename W, bool REFINE>
+// V: the chunk table's sums (32-bit when 2m < 2^32, as in the block decide)
+template <typename W, bool REFINE, typename V = unsigned long long>
 __global__ __launch_bounds__(kBlock) void k_hub_chunk(DecideParams<W> p) {
   constexpr uint32_t kNB = 1u << kHubMaxRbits;
   __shared__ uint32_t lk[kHubSlots];
-  __shared__ unsigned long long lv[kHubSlots];
+  __shared__ V lv[kHubSlots];
   __shared__ unsigned int lcnt[kNB + 1];
   __shared__ unsigned int wsum[kBlock / kWave];
   __shared__ unsigned long long red[kBlock / kWave];
@@ -1095,8 +1096,12 @@ void launch_decide_all(hipStream_t s, DecideParams<W> p, uint32_t* bin_lists, si
         break;
       default: {
         if (sizeof(W) == 4 && !REFINE) kt_mark(LEIDEN_KT_HUB_INSERT, t);
-        hipLaunchKernelGGL((k_hub_chunk<W, REFINE>), dim3(grid_for(bin_upper[b] * (maxdeg / kHubChunk + 1), 1, 1536)),
-                           dim3(kBlock), 0, t, q);
+        if (p.narrow)
+          hipLaunchKernelGGL((k_hub_chunk<W, REFINE, unsigned int>),
+                             dim3(grid_for(bin_upper[b] * (maxdeg / kHubChunk + 1), 1, 1536)), dim3(kBlock), 0, t, q);
+        else
+          hipLaunchKernelGGL((k_hub_chunk<W, REFINE>), dim3(grid_for(bin_upper[b] * (maxdeg / kHubChunk + 1), 1, 1536)),
+                             dim3(kBlock), 0, t, q);
         if (sizeof(W) == 4 && !REFINE) kt_mark(LEIDEN_KT_HUB_INSERT, t);
         hipLaunchKernelGGL((k_hub_pick<W, REFINE>), dim3(grid_for(bin_upper[b], 1, 512), p.pick_segs),
                            dim3(kBlock), 0, t, q);

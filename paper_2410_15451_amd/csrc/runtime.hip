@@ -1206,8 +1206,8 @@ const char* leiden_kernel_name(int32_t kernel) {
   switch (kernel) {
     case LEIDEN_KT_NONE:
       return "";
-    case LEIDEN_KT_HUB_INSERT:
-      return "lm::k_hub_chunk<unsigned int, false>";
+    case LEIDEN_KT_HUB_INSERT:  // two instantiations (32- or 64-bit table sums): their common prefix
+      return "lm::k_hub_chunk<unsigned int, false";
     case LEIDEN_KT_AGG_BIG:
       return "lm::k_agg_stage<unsigned int>";
     default:
