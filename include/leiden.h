@@ -22,8 +22,11 @@
  *     needs before returning.  The handle owns all device memory it allocates.
  *   - Every call returns a leiden_status; leiden_last_error() gives a message
  *     for the calling thread.  A failed call leaves the handle's graph and
- *     state as they were (updates are transactional).
- *   - Calls on one handle must not overlap; different handles are independent.
+ *     state as they were, except an update that fails after its batch is in
+ *     the graph (see leiden_update).
+ *   - One call at a time per handle: a call that finds the handle in use by
+ *     another thread returns LEIDEN_EBUSY and does nothing.  Different
+ *     handles are independent.
  */
 #ifndef LEIDEN_MI355X_H
 #define LEIDEN_MI355X_H
@@ -39,7 +42,8 @@ typedef enum {
   LEIDEN_EINVAL = -1,  /* invalid argument or batch */
   LEIDEN_ENOMEM = -2,  /* device memory exhausted */
   LEIDEN_EDEVICE = -3, /* HIP runtime error */
-  LEIDEN_ESTATE = -4   /* handle has no state for the request (e.g. update before any run) */
+  LEIDEN_ESTATE = -4,  /* handle has no state for the request (e.g. update before any run) */
+  LEIDEN_EBUSY = -5    /* another call is using the handle (one call at a time per handle) */
 } leiden_status;
 
 typedef enum {
@@ -201,6 +205,15 @@ void leiden_graph_destroy(leiden_graph* g);
 /* Number of directed entries currently held. */
 leiden_status leiden_graph_nnz(leiden_graph* g, uint64_t* nnz);
 
+/* Device memory of a handle: the graph, its auxiliary state and the working
+ * buffers that calls grow on demand (they are kept for later calls).
+ * leiden_memory_used gives the bytes held now.  A budget above 0 bounds
+ * them: a call that would grow the handle past it returns LEIDEN_ENOMEM
+ * (with the batch rules of leiden_update below); 0, the default, means no
+ * bound.  Lowering the budget frees nothing. */
+leiden_status leiden_set_memory_budget(leiden_graph* g, uint64_t budget_bytes);
+leiden_status leiden_memory_used(leiden_graph* g, uint64_t* used_bytes);
+
 /* Static Leiden (Alg. 4 with every vertex affected and every community
  * marked for refinement).  membership_out: uint32[n], dense labels ordered
  * by each community's minimum vertex.  Sets the handle's state (C, K, Sigma,
@@ -213,7 +226,11 @@ leiden_status leiden_static(leiden_graph* g, const leiden_opts* opts, uint32_t* 
  * each an existing edge; ins: n_ins undirected (u, v, w) as uint32[3 * n_ins],
  * each an absent pair, w > 0.  A self-loop, an ID >= n, a repeated pair, a
  * deletion of an absent edge or an insertion of a present one gives
- * LEIDEN_EINVAL and changes nothing.  prev_membership: uint32[n] C^{t-1} with
+ * LEIDEN_EINVAL and changes nothing.  A failure after the batch is in the
+ * graph (device memory, the memory budget, a HIP error) keeps the updated
+ * graph and drops the auxiliary state: the next update then returns
+ * LEIDEN_ESTATE unless it passes prev_membership, and leiden_static or
+ * leiden_state_import restore the state.  prev_membership: uint32[n] C^{t-1} with
  * labels < n, or NULL for the handle's last result; a membership that differs
  * from the last result restarts Sigma from K and DeltaSigma from zero.
  * membership_out: uint32[n] C^t with tracked labels. */

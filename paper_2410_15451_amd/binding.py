@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libleiden_mi355x.so")
 
-LEIDEN_OK, LEIDEN_EINVAL, LEIDEN_ENOMEM, LEIDEN_EDEVICE, LEIDEN_ESTATE = 0, -1, -2, -3, -4
+LEIDEN_OK, LEIDEN_EINVAL, LEIDEN_ENOMEM, LEIDEN_EDEVICE, LEIDEN_ESTATE, LEIDEN_EBUSY = 0, -1, -2, -3, -4, -5
 MODES = {"nd": 0, "ds": 1, "df": 2}
 
 # Every symbol include/leiden.h declares.
@@ -27,7 +27,8 @@ EXPORTS = ("leiden_default_opts", "leiden_graph_create", "leiden_graph_destroy",
            "leiden_set_tuning", "leiden_autotune", "leiden_batch_run", "leiden_server_create",
            "leiden_server_destroy", "leiden_server_add_graph", "leiden_server_remove_graph", "leiden_server_submit",
            "leiden_server_wait", "leiden_server_get_stats", "leiden_modularity_noalloc", "leiden_forest_create",
-           "leiden_forest_results", "leiden_forest_info", "leiden_server_footprint")
+           "leiden_forest_results", "leiden_forest_info", "leiden_server_footprint", "leiden_set_memory_budget",
+           "leiden_memory_used")
 
 FOREST_ITER_HIST = 16  # passes whose iteration counts leiden_forest_results returns
 
@@ -138,6 +139,10 @@ def lib():
         L.leiden_graph_destroy.restype = None
         L.leiden_graph_nnz.argtypes = [P, ctypes.POINTER(u64)]
         L.leiden_graph_nnz.restype = i32
+        L.leiden_set_memory_budget.argtypes = [P, u64]
+        L.leiden_set_memory_budget.restype = i32
+        L.leiden_memory_used.argtypes = [P, ctypes.POINTER(u64)]
+        L.leiden_memory_used.restype = i32
         L.leiden_static.argtypes = [P, P, P, i32, P, P]
         L.leiden_static.restype = i32
         L.leiden_update.argtypes = [P, P, u64, P, u64, i32, P, i32, i32, P, P, i32, P, P]
@@ -274,6 +279,15 @@ class Graph:
     def nnz(self) -> int:
         x = ctypes.c_uint64()
         _check(lib().leiden_graph_nnz(self._h, ctypes.byref(x)))
+        return int(x.value)
+
+    def set_memory_budget(self, budget_bytes: int):
+        """Bound the handle's device memory (0: no bound)."""
+        _check(lib().leiden_set_memory_budget(self._h, ctypes.c_uint64(int(budget_bytes))))
+
+    def memory_used(self) -> int:
+        x = ctypes.c_uint64()
+        _check(lib().leiden_memory_used(self._h, ctypes.byref(x)))
         return int(x.value)
 
     def _out(self, out):

@@ -65,10 +65,24 @@ const DecideStreams* side_streams(leiden_graph* G, uint32_t nl);
 // device (other handles' calls on other streams keep running).
 thread_local hipStream_t tl_alloc_stream = nullptr;
 
+// Device bytes a handle holds, and its budget (0: none).  The handle of the
+// current API call on this thread is charged for its buffers' growth.
+struct MemAccount {
+  uint64_t budget = 0, used = 0;
+};
+thread_local MemAccount* tl_account = nullptr;
+
 struct AllocScope {
   hipStream_t prev;
-  explicit AllocScope(hipStream_t s) : prev(tl_alloc_stream) { tl_alloc_stream = s; }
-  ~AllocScope() { tl_alloc_stream = prev; }
+  MemAccount* prev_account;
+  explicit AllocScope(hipStream_t s, MemAccount* a = nullptr) : prev(tl_alloc_stream), prev_account(tl_account) {
+    tl_alloc_stream = s;
+    tl_account = a;
+  }
+  ~AllocScope() {
+    tl_alloc_stream = prev;
+    tl_account = prev_account;
+  }
 };
 
 // Device allocation owned by the handle; grows on demand, never shrinks.
@@ -80,6 +94,11 @@ struct Buf {
   }
   leiden_status reserve(size_t b) {
     if (b <= bytes) return LEIDEN_OK;
+    const size_t want = std::max<size_t>(b, 256);
+    MemAccount* acct = tl_account;
+    if (acct && acct->budget && acct->used - bytes + want > acct->budget)
+      return fail(LEIDEN_ENOMEM, "the handle's device memory budget of %llu bytes would be exceeded (%llu held, "
+                  "%zu more wanted)", (unsigned long long)acct->budget, (unsigned long long)acct->used, want - bytes);
     if (p) {
       // kernels queued earlier may still read the old block
       if (tl_alloc_stream)
@@ -87,16 +106,17 @@ struct Buf {
       else
         (void)hipDeviceSynchronize();
       (void)hipFree(p);
+      if (acct) acct->used -= bytes;
     }
     p = nullptr;
     bytes = 0;
-    size_t want = std::max<size_t>(b, 256);
     if (hipMalloc(&p, want) != hipSuccess) {
       (void)hipGetLastError();
       p = nullptr;
       return fail(LEIDEN_ENOMEM, "device allocation of %zu bytes failed", want);
     }
     bytes = want;
+    if (acct) acct->used += want;
     return LEIDEN_OK;
   }
   template <typename T>
@@ -160,6 +180,8 @@ struct ForestState {
 struct leiden_graph {
   int device = 0;
   hipStream_t own = nullptr;
+  MemAccount mem;                 // device bytes held and the budget
+  std::atomic<bool> busy{false};  // a call is using the handle
   uint32_t n = 0;
   float slack = 0.2f;
   SlackCsr g;
@@ -223,6 +245,39 @@ struct leiden_graph {
     if (own) (void)hipStreamDestroy(own);
   }
 };
+
+// One call at a time per handle: a second call that finds the handle in use
+// returns LEIDEN_EBUSY instead of racing on its buffers.
+struct BusyGuard {
+  std::atomic<bool>* f = nullptr;
+  explicit BusyGuard(leiden_graph* G) {
+    if (G && !G->busy.exchange(true)) f = &G->busy;
+  }
+  ~BusyGuard() {
+    if (f) f->store(false);
+  }
+  bool ok() const { return f != nullptr; }
+};
+// Once a batch is merged into the graph, a call that fails must not leave the
+// previous graph's auxiliary state behind as if it described the new one: the
+// state is dropped unless the call completes (leiden_static or
+// leiden_state_import restores it).
+struct StateDrop {
+  leiden_graph* G;
+  bool armed = true;
+  explicit StateDrop(leiden_graph* g) : G(g) {}
+  void keep() { armed = false; }
+  ~StateDrop() {
+    if (armed) {
+      G->has_state = false;
+      G->heads_valid = false;
+    }
+  }
+};
+
+#define BUSY_GUARD(G)          \
+  BusyGuard busy_guard_(G);    \
+  if (!busy_guard_.ok()) return fail(LEIDEN_EBUSY, "the handle is in use by another call")
 
 namespace {
 const DecideStreams* side_streams(leiden_graph* G, uint32_t nl) {
@@ -1171,7 +1226,7 @@ leiden_status probe_aggregate(leiden_graph* G, hipStream_t s, uint32_t slots, fl
 // Level-0 degree bins after a change of thresholds.
 leiden_status refresh_bins0(leiden_graph* G) {
   hipStream_t s = G->own;
-  AllocScope alloc_scope(s);
+  AllocScope alloc_scope(s, &G->mem);
   CHK(level_bins(G, s, G->g.len, G->n, G->bins0, &G->maxdeg0));
   HIPCHK(hipStreamSynchronize(s));
   return LEIDEN_OK;
@@ -1216,20 +1271,26 @@ const char* leiden_kernel_name(int32_t kernel) {
 }
 
 
-leiden_status leiden_get_tuning(leiden_graph* G, leiden_tuning* out) {
-  g_err.clear();
-  if (!G || !out) return fail(LEIDEN_EINVAL, "null argument");
+static void tuning_of(const leiden_graph* G, leiden_tuning* out) {
   std::memset(out, 0, sizeof(*out));
   for (int b = 0; b < kBins - 1; ++b) out->bin_max_degree[b] = G->bincfg.max_deg[b];
   out->agg_emit_slots = G->emit_slots;
   out->probe_ms = G->tune_ms;
   out->agg_probe_ms = G->tune_agg_ms;
+}
+
+leiden_status leiden_get_tuning(leiden_graph* G, leiden_tuning* out) {
+  g_err.clear();
+  if (!G || !out) return fail(LEIDEN_EINVAL, "null argument");
+  BUSY_GUARD(G);
+  tuning_of(G, out);
   return LEIDEN_OK;
 }
 
 leiden_status leiden_set_tuning(leiden_graph* G, const leiden_tuning* t) {
   g_err.clear();
   if (!G || !t) return fail(LEIDEN_EINVAL, "null argument");
+  BUSY_GUARD(G);
   BinCfg c = kDefaultBins;
   for (int b = 0; b < kBins - 1; ++b) c.max_deg[b] = t->bin_max_degree[b];
   if (!bins_valid(c))
@@ -1248,13 +1309,14 @@ leiden_status leiden_autotune(leiden_graph* G, const leiden_opts* opts, leiden_t
   g_err.clear();
   InFlight in_flight;
   if (!G) return fail(LEIDEN_EINVAL, "null handle");
+  BUSY_GUARD(G);
   leiden_opts o;
   leiden_default_opts(&o);
   if (opts) o = *opts;
   CHK(check_opts(o));
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = stream_of(G, opts);
-  AllocScope alloc_scope(s);
+  AllocScope alloc_scope(s, &G->mem);
   CHK(ensure_workspace(G, s, std::max(o.move_classes, o.refine_rounds)));
   const uint32_t n = G->n;
   // singleton start on the input graph
@@ -1313,7 +1375,7 @@ leiden_status leiden_autotune(leiden_graph* G, const leiden_opts* opts, leiden_t
   }
   G->emit_slots = best_slots;
   G->tune_agg_ms = best_agg;
-  if (out) CHK(leiden_get_tuning(G, out));
+  if (out) tuning_of(G, out);
   return LEIDEN_OK;
 }
 
@@ -1354,7 +1416,7 @@ leiden_status leiden_graph_create(int device, uint32_t n, uint64_t nnz, const in
     G->dstreams_ready = true;
   }
   hipStream_t s = G->own;
-  AllocScope alloc_scope(s);
+  AllocScope alloc_scope(s, &G->mem);
   leiden_status st;
   // upload the input CSR
   Buf in_offs, in_cols, in_w;
@@ -1447,7 +1509,7 @@ leiden_status leiden_forest_create(int device, uint32_t n_graphs, const uint32_t
       (st = FS->out_local.reserve(nn * 4)) || (st = FS->live_len.reserve(nn * 4)))
     return bail(st);
   hipStream_t s = G->own;
-  AllocScope alloc_scope(s);
+  AllocScope alloc_scope(s, &G->mem);
   if (hipMemcpyAsync(FS->base0.p, first.data(), nb * 4, hipMemcpyHostToDevice, s) != hipSuccess)
     return bail(fail(LEIDEN_EDEVICE, "copy"));
   forest_gid(s, (uint32_t)n, n_graphs, FS->base0.as<uint32_t>(), FS->gid0.as<uint32_t>());
@@ -1465,6 +1527,7 @@ leiden_status leiden_forest_create(int device, uint32_t n_graphs, const uint32_t
 leiden_status leiden_forest_results(leiden_graph* G, double* q, uint32_t* passes, uint32_t* iters) {
   g_err.clear();
   if (!G) return fail(LEIDEN_EINVAL, "null handle");
+  BUSY_GUARD(G);
   ForestState* FS = G->forest;
   if (!FS) return fail(LEIDEN_EINVAL, "not a forest");
   const uint32_t nq = FS->nq;
@@ -1487,12 +1550,29 @@ leiden_status leiden_forest_results(leiden_graph* G, double* q, uint32_t* passes
 leiden_status leiden_forest_info(leiden_graph* G, uint32_t* n_graphs, uint32_t* first_vertex) {
   g_err.clear();
   if (!G || !n_graphs) return fail(LEIDEN_EINVAL, "null argument");
+  BUSY_GUARD(G);
   if (!G->forest) {
     *n_graphs = 0;
     return LEIDEN_OK;
   }
   *n_graphs = G->forest->nq;
   if (first_vertex) std::memcpy(first_vertex, G->forest->first.data(), 4 * ((size_t)G->forest->nq + 1));
+  return LEIDEN_OK;
+}
+
+leiden_status leiden_set_memory_budget(leiden_graph* G, uint64_t budget_bytes) {
+  g_err.clear();
+  if (!G) return fail(LEIDEN_EINVAL, "null handle");
+  BUSY_GUARD(G);
+  G->mem.budget = budget_bytes;
+  return LEIDEN_OK;
+}
+
+leiden_status leiden_memory_used(leiden_graph* G, uint64_t* used_bytes) {
+  g_err.clear();
+  if (!G || !used_bytes) return fail(LEIDEN_EINVAL, "null argument");
+  BUSY_GUARD(G);
+  *used_bytes = G->mem.used;
   return LEIDEN_OK;
 }
 
@@ -1507,13 +1587,14 @@ leiden_status leiden_static(leiden_graph* G, const leiden_opts* opts, uint32_t* 
   g_err.clear();
   InFlight in_flight;
   if (!G) return fail(LEIDEN_EINVAL, "null handle");
+  BUSY_GUARD(G);
   leiden_opts o;
   leiden_default_opts(&o);
   if (opts) o = *opts;
   CHK(check_opts(o));
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = stream_of(G, opts);
-  AllocScope alloc_scope(s);
+  AllocScope alloc_scope(s, &G->mem);
   if (stats) std::memset(stats, 0, sizeof(*stats));
   KtScope kts(G, o.timed_kernel);
   CHK(ensure_workspace(G, s, std::max(o.move_classes, o.refine_rounds)));
@@ -1598,6 +1679,7 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   g_err.clear();
   InFlight in_flight;
   if (!G) return fail(LEIDEN_EINVAL, "null handle");
+  BUSY_GUARD(G);
   if (mode != LEIDEN_ND && mode != LEIDEN_DS && mode != LEIDEN_DF) return fail(LEIDEN_EINVAL, "unknown mode");
   if ((n_del && !del) || (n_ins && !ins)) return fail(LEIDEN_EINVAL, "null batch arrays");
   leiden_opts o;
@@ -1608,7 +1690,7 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
     return fail(LEIDEN_ESTATE, "no previous memberships: run leiden_static or pass prev_membership");
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = stream_of(G, opts);
-  AllocScope alloc_scope(s);
+  AllocScope alloc_scope(s, &G->mem);
   if (stats) std::memset(stats, 0, sizeof(*stats));
   KtScope kts(G, o.timed_kernel);
   const uint32_t n = G->n;
@@ -1747,6 +1829,7 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
     }
     if (rc != 0) return fail(LEIDEN_ENOMEM, "could not make room for the batch");
   }
+  StateDrop drop(G);  // the graph holds the batch from here on
   count_units(s, G->g.len, bb.touched, nt, G->edge_parts.as<unsigned long long>(), kWMerge);
   // level-0 degree bins after the batch
   CHK(level_bins(G, s, G->g.len, n, G->bins0, &G->maxdeg0));
@@ -1867,6 +1950,7 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   dsig_out(s, n, tb.matched, dSig, G->st_dS.as<int64_t>());
   HIPCHK(hipMemcpyAsync(G->st_C.p, out, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
   G->has_state = true;
+  drop.keep();
   HIPCHK(hipEventRecord(e2, s));
   double q = std::numeric_limits<double>::quiet_NaN();
   if (FS)
@@ -1911,9 +1995,10 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
 leiden_status leiden_modularity(leiden_graph* G, const uint32_t* membership, int on_device, double* q_out) {
   g_err.clear();
   if (!G || !membership || !q_out) return fail(LEIDEN_EINVAL, "null argument");
+  BUSY_GUARD(G);
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = G->own;
-  AllocScope alloc_scope(s);
+  AllocScope alloc_scope(s, &G->mem);
   CHK(ensure_workspace(G, s, 8));
   const uint32_t n = G->n;
   uint32_t* C = G->C.as<uint32_t>();
@@ -1942,12 +2027,13 @@ leiden_status leiden_modularity(leiden_graph* G, const uint32_t* membership, int
 leiden_status leiden_modularity_noalloc(leiden_graph* G, const uint32_t* membership, void* stream, double* q_out) {
   g_err.clear();
   if (!G || !membership || !q_out) return fail(LEIDEN_EINVAL, "null argument");
+  BUSY_GUARD(G);
   if (G->forest) return fail(LEIDEN_EINVAL, "forests report modularity per graph (leiden_modularity)");
   if (G->n > kNoAllocMaxN)
     return fail(LEIDEN_EINVAL, "n = %u exceeds the %u vertices of the scratch array", G->n, kNoAllocMaxN);
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = stream ? (hipStream_t)stream : G->own;
-  AllocScope alloc_scope(s);
+  AllocScope alloc_scope(s, &G->mem);
   const int rc = noalloc_modularity(s, G->device, rows0(G), G->n, membership, q_out);
   if (rc == 2) return fail(LEIDEN_EINVAL, "membership has a label >= n");
   if (rc != 0) return fail(LEIDEN_EDEVICE, "modularity without allocation failed");
@@ -1957,9 +2043,10 @@ leiden_status leiden_modularity_noalloc(leiden_graph* G, const uint32_t* members
 leiden_status leiden_graph_export(leiden_graph* G, int64_t* offsets_out, uint32_t* cols_out, uint32_t* w_out) {
   g_err.clear();
   if (!G || !offsets_out) return fail(LEIDEN_EINVAL, "null argument");
+  BUSY_GUARD(G);
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = G->own;
-  AllocScope alloc_scope(s);
+  AllocScope alloc_scope(s, &G->mem);
   const uint32_t n = G->n;
   std::vector<int64_t> start(n);
   std::vector<uint32_t> len(n);
@@ -1987,11 +2074,12 @@ leiden_status leiden_graph_export(leiden_graph* G, int64_t* offsets_out, uint32_
 leiden_status leiden_state_export(leiden_graph* G, uint32_t* C, int64_t* K, int64_t* Sigma, int64_t* dSigma) {
   g_err.clear();
   if (!G) return fail(LEIDEN_EINVAL, "null handle");
+  BUSY_GUARD(G);
   if (G->forest) return fail(LEIDEN_EINVAL, "state export is for single graphs");
   if (!G->has_state) return fail(LEIDEN_ESTATE, "no state yet");
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = G->own;
-  AllocScope alloc_scope(s);
+  AllocScope alloc_scope(s, &G->mem);
   const uint32_t n = G->n;
   CHK(copy_out(s, C, G->st_C.p, sizeof(uint32_t) * n, 0));
   CHK(copy_out(s, K, G->st_K.p, sizeof(int64_t) * n, 0));
@@ -2005,10 +2093,11 @@ leiden_status leiden_state_import(leiden_graph* G, const uint32_t* C, const int6
                                   const int64_t* dSigma) {
   g_err.clear();
   if (!G || !C || !K || !Sigma || !dSigma) return fail(LEIDEN_EINVAL, "null argument");
+  BUSY_GUARD(G);
   if (G->forest) return fail(LEIDEN_EINVAL, "state import is for single graphs");
   HIPCHK(hipSetDevice(G->device));
   hipStream_t s = G->own;
-  AllocScope alloc_scope(s);
+  AllocScope alloc_scope(s, &G->mem);
   const uint32_t n = G->n;
   CHK(ensure_workspace(G, s, 8));
   for (Buf* b : {&G->st_C}) CHK(b->reserve((size_t)std::max<uint32_t>(n, 1) * 4));
