@@ -1736,8 +1736,9 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   // previous memberships: validate and compare with the handle's state
   uint32_t* Cprev = G->st_C.as<uint32_t>();
   bool restart = !G->has_state;
+  uint32_t* pm = nullptr;  // the caller's C^{t-1}, taken into the state once the batch is in
   if (prev_membership) {
-    uint32_t* pm = G->tr_label.as<uint32_t>();
+    pm = G->tr_label.as<uint32_t>();
     CHK(copy_in(s, pm, prev_membership, sizeof(uint32_t) * n, prev_on_device));
     unsigned int* fl = (unsigned int*)(G->small.as<uint64_t>() + 300);
     if (G->forest) {  // labels inside each graph -> forest labels
@@ -1752,7 +1753,6 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
     CHK(read_dev(s, &f, fl));
     if (f & 1) return fail(LEIDEN_EINVAL, "prev_membership has a label >= n");
     if (f & 2) restart = true;
-    if (restart) HIPCHK(hipMemcpyAsync(Cprev, pm, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
   }
   // batch: copy, group, sort, validate (nothing changes before this passes)
   uint32_t* din = G->bt_in.as<uint32_t>();
@@ -1830,6 +1830,7 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
     if (rc != 0) return fail(LEIDEN_ENOMEM, "could not make room for the batch");
   }
   StateDrop drop(G);  // the graph holds the batch from here on
+  if (restart && pm) HIPCHK(hipMemcpyAsync(Cprev, pm, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
   count_units(s, G->g.len, bb.touched, nt, G->edge_parts.as<unsigned long long>(), kWMerge);
   // level-0 degree bins after the batch
   CHK(level_bins(G, s, G->g.len, n, G->bins0, &G->maxdeg0));
@@ -1838,6 +1839,12 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   HIPCHK(hipEventRecord(e1, s));
   // auxiliary state: restart or continue
   LevelState L = level_state(G);
+  // the input level works on the handle's K and Sigma in place: K^t is kept
+  // by the run (aggregated levels write the two other K buffers in turn) and
+  // Sigma^t is recomputed under the tracked labels at the end; a failure from
+  // here on drops the state (the batch is in the graph)
+  L.K = G->st_K.as<int64_t>();
+  L.S = G->st_S.as<int64_t>();
   if (restart) {
     launch_row_sums_u32(s, rows0(G), n, L.K);  // K^t directly
     launch_sigma_from(s, Cprev, L.K, n, L.S);   // Sigma^t by C^{t-1}
@@ -1851,8 +1858,6 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
     fill_i64(s, Sdummy, 0, n);
     launch_aux_update(s, bb, ne, Cprev, Kdummy, Sdummy, dSig);
   } else {
-    HIPCHK(hipMemcpyAsync(L.K, G->st_K.p, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(L.S, G->st_S.p, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(G->sig.p, G->st_dS.p, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s));
     launch_aux_update(s, bb, ne, Cprev, L.K, L.S, G->sig.as<int64_t>());
   }
@@ -1901,8 +1906,7 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
     (void)cnt;
   }
   // K^t of the input graph survives the run in its own buffer (levels reuse K)
-  int64_t* Kt = G->Kt.as<int64_t>();
-  HIPCHK(hipMemcpyAsync(Kt, L.K, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s));
+  int64_t* const Kt = L.K;  // K^t of the input graph (the handle's K)
   CHK(run_leiden(G, s, L, ro, M2, stats));
   // tracking (Alg. 12) and the new state
   TrackBufs tb{};
@@ -1946,7 +1950,6 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   track(s, n, G->Ctop.as<uint32_t>(), Cprev, Kt, out, G->st_S.as<int64_t>(), labels_are_min, tb);
   G->heads_valid = true;
   // new state: C^t, K^t, Sigma^t by C^t, DeltaSigma^t kept for continued labels
-  HIPCHK(hipMemcpyAsync(G->st_K.p, Kt, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s));
   dsig_out(s, n, tb.matched, dSig, G->st_dS.as<int64_t>());
   HIPCHK(hipMemcpyAsync(G->st_C.p, out, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
   G->has_state = true;

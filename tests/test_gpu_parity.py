@@ -198,13 +198,15 @@ def test_invalid_batches_leave_state(lm, orc):
         (np.array([[u, v], [v, u]]), np.zeros((0, 3))),
         (np.array([[u, v]]), np.array([[v, u, 2]])),
     ]
+    other = (np.arange(g.n) // 50).astype(np.uint32)  # previous memberships that differ from the state
     for dels, ins in bad:
-        with pytest.raises(lm.LeidenError) as ei:
-            G.update(np.asarray(dels, np.uint32), np.asarray(ins, np.uint32), mode="df")
-        assert ei.value.code == lm.LEIDEN_EINVAL
-        after = G.export(), G.state()
-        for a, b in zip(before[0] + before[1], after[0] + after[1]):
-            assert np.array_equal(a, b)
+        for prev in (None, other):
+            with pytest.raises(lm.LeidenError) as ei:
+                G.update(np.asarray(dels, np.uint32), np.asarray(ins, np.uint32), mode="df", prev=prev)
+            assert ei.value.code == lm.LEIDEN_EINVAL
+            after = G.export(), G.state()
+            for a, b in zip(before[0] + before[1], after[0] + after[1]):
+                assert np.array_equal(a, b)
     # still usable afterwards
     _ = G.update(np.zeros((0, 2), np.uint32), np.zeros((0, 3), np.uint32), mode="df")
 
