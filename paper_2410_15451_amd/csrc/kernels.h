@@ -220,17 +220,20 @@ struct RenumberBufs {
 void subset_renumber(hipStream_t s, uint32_t n, uint32_t* C, int64_t*& S, uint32_t*& size, uint8_t*& dS,
                      uint8_t*& dR, RenumberBufs& b, Ctl* ctl);
 
+// lab: one 64-bit union-find word per vertex (community << 32 | parent)
 void launch_split_init(hipStream_t s, uint32_t n, const uint32_t* C, const uint8_t* dS, const uint8_t* dR,
-                       uint32_t* lab, uint32_t* list, uint32_t* wide, unsigned long long* main_key, Ctl* ctl,
-                       const uint32_t* len, unsigned long long* parts);
+                       unsigned long long* lab, uint32_t* list, uint32_t* wide, unsigned long long* main_key,
+                       Ctl* ctl, const uint32_t* len, unsigned long long* parts);
 template <typename W>
-void launch_split_sample(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* lab, const uint32_t* list,
+void launch_split_sample(hipStream_t s, Rows<W> g, const uint32_t* C, unsigned long long* lab, const uint32_t* list,
                          const uint32_t* wide, unsigned long long* main_key, uint32_t* rest, Ctl* ctl,
                          uint32_t n_upper);
 template <typename W>
-void launch_split_union(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* lab, const uint32_t* bin_lists,
-                        size_t stride, const unsigned int* bin_counts, const uint64_t* bin_upper);
-void launch_split_finish(hipStream_t s, uint32_t* C, uint32_t* lab, const uint32_t* list, Ctl* ctl, uint32_t n_upper);
+void launch_split_union(hipStream_t s, Rows<W> g, const uint32_t* C, unsigned long long* lab,
+                        const uint32_t* bin_lists, size_t stride, const unsigned int* bin_counts,
+                        const uint64_t* bin_upper);
+void launch_split_finish(hipStream_t s, uint32_t* C, unsigned long long* lab, const uint32_t* list, Ctl* ctl,
+                         uint32_t n_upper);
 
 void launch_refine_reset(hipStream_t s, uint32_t n, uint32_t* C, uint32_t* CB, int64_t* S, const int64_t* K,
                          uint32_t* size, const uint8_t* dR, uint32_t R, uint32_t* col_lists, size_t stride,

@@ -177,9 +177,12 @@ void subset_renumber(hipStream_t s, uint32_t n, uint32_t* C, int64_t*& S, uint32
 //   4. compress: the root of each vertex is its component's minimum vertex.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kSplitSample = 4, kSplitWideMin = 64;
+using UfNode = unsigned long long;
+constexpr UfNode kUfComm = 0xFFFFFFFF00000000ull;
+__device__ inline UfNode uf_node(uint32_t comm, uint32_t parent) { return ((UfNode)comm << 32) | parent; }
 
 __global__ __launch_bounds__(kBlock) void k_split_init(uint32_t n, const uint32_t* C, const uint8_t* dS,
-                                                       const uint8_t* dR, uint32_t* lab, uint32_t* list,
+                                                       const uint8_t* dR, UfNode* lab, uint32_t* list,
                                                        uint32_t* wide, unsigned long long* main_key, Ctl* ctl,
                                                        const uint32_t* len, unsigned long long* parts) {
   __shared__ unsigned int scnt[2], sbase[2];
@@ -197,7 +200,7 @@ __global__ __launch_bounds__(kBlock) void k_split_init(uint32_t n, const uint32_
       val[u] = (uint32_t)i;
       if (i < n) {
         const uint32_t c = C[i];
-        lab[i] = (uint32_t)i;
+        lab[i] = uf_node(c, (uint32_t)i);
         const bool in = dS[c] && !dR[c];
         // the label of a community is its minimum member: one writer per community
         if (in && c == (uint32_t)i) main_key[c] = 0;
@@ -224,6 +227,12 @@ __global__ __launch_bounds__(kBlock) void k_split_init(uint32_t n, const uint32_
   if (threadIdx.x == 0) add_units(parts, kWSplit, entries);
 }
 
+// A union-find node is one 64-bit word: the parent in the low half and the
+// vertex's community, which stays fixed during the split, in the high half,
+// so that one load gives both (the same-community test and the first step of
+// a find read one line instead of two).  A tree only ever holds vertices of
+// one community, so every word written into it carries that community.
+//
 // Every parent is below its child, and a parent pointer only ever moves to
 // another ancestor, so a read of p[x], however stale, names an ancestor of x:
 // a find ends (each step goes to a smaller ID) and returns an ancestor of x,
@@ -232,22 +241,26 @@ __global__ __launch_bounds__(kBlock) void k_split_init(uint32_t n, const uint32_
 // compare-and-swap fail, and the union goes on from the parent the atomic
 // returned; after them (compress, finish: separate launches) nothing links
 // roots any more and every find reaches the true root.
-__device__ inline uint32_t uf_find(uint32_t* p, uint32_t x) {
+// root of x, whose word wx was read before (the high half is its community)
+__device__ inline uint32_t uf_find(UfNode* p, uint32_t x, UfNode wx) {
   // path halving: every pointer written is an ancestor of the node
-  uint32_t px = ld_near(&p[x]);
+  const UfNode comm = wx & kUfComm;
+  uint32_t px = (uint32_t)wx;
   while (px != x) {
-    const uint32_t gp = ld_near(&p[px]);
-    if (gp != px) st_near(&p[x], gp);
+    const uint32_t gp = (uint32_t)ld_near(&p[px]);
+    if (gp != px) st_near(&p[x], comm | gp);
     x = gp;
-    px = ld_near(&p[x]);
+    px = (uint32_t)ld_near(&p[x]);
   }
   return x;
 }
 
-__device__ inline void uf_union(uint32_t* p, uint32_t a, uint32_t b) {
+// a and b of one community, with their words wa and wb as read
+__device__ inline void uf_union(UfNode* p, uint32_t a, UfNode wa, uint32_t b, UfNode wb) {
+  const UfNode comm = wa & kUfComm;
   while (true) {
-    a = uf_find(p, a);
-    b = uf_find(p, b);
+    a = uf_find(p, a, wa);
+    b = uf_find(p, b, wb);
     if (a == b) return;
     if (a > b) {
       const uint32_t t = a;
@@ -257,15 +270,25 @@ __device__ inline void uf_union(uint32_t* p, uint32_t a, uint32_t b) {
     // hang root b under the smaller root a; if b stopped being a root, go on
     // from the parent the compare-and-swap found (a smaller ID), so that
     // every retry lowers max(a, b) whatever the loads above returned
-    const uint32_t o = atomicCAS(&p[b], b, a);
-    if (o == b) return;
-    b = o;
+    const UfNode o = atomicCAS(&p[b], comm | b, comm | a);
+    if (o == (comm | b)) return;
+    b = (uint32_t)o;
+    wa = ld_near(&p[a]);
+    wb = ld_near(&p[b]);
   }
 }
 
+// the union of u with its neighbour j when both are in one community
+__device__ inline void uf_link(UfNode* lab, uint32_t u, uint32_t j) {
+  if (j == u) return;
+  const UfNode wj = ld_near(&lab[j]), wu = ld_near(&lab[u]);
+  if ((wj ^ wu) & kUfComm) return;
+  uf_union(lab, u, wu, j, wj);
+}
+
 template <typename W>
-__global__ __launch_bounds__(kBlock) void k_split_sample(Rows<W> g, const uint32_t* C, uint32_t* lab,
-                                                         const uint32_t* list, const Ctl* ctl) {
+__global__ __launch_bounds__(kBlock) void k_split_sample(Rows<W> g, UfNode* lab, const uint32_t* list,
+                                                         const Ctl* ctl) {
   // one thread per (vertex, sampled entry): the unions of a vertex run side
   // by side instead of one after another
   const uint64_t cnt = (uint64_t)ctl->split_count * kSplitSample;
@@ -273,8 +296,7 @@ __global__ __launch_bounds__(kBlock) void k_split_sample(Rows<W> g, const uint32
     const uint32_t u = list[q / kSplitSample];
     const uint32_t e = (uint32_t)(q % kSplitSample);
     if (e >= g.len[u]) continue;
-    const uint32_t j = g.cols[g.start[u] + e];
-    if (j != u && C[j] == C[u]) uf_union(lab, u, j);
+    uf_link(lab, u, g.cols[g.start[u] + e]);
   }
 }
 
@@ -283,23 +305,23 @@ __global__ __launch_bounds__(kBlock) void k_split_sample(Rows<W> g, const uint32
 // per (long-row vertex, extra entry), like the first sample.
 constexpr uint32_t kSplitWide = 64;
 template <typename W>
-__global__ __launch_bounds__(kBlock) void k_split_sample_wide(Rows<W> g, const uint32_t* C, uint32_t* lab,
-                                                              const uint32_t* wide, const Ctl* ctl) {
+__global__ __launch_bounds__(kBlock) void k_split_sample_wide(Rows<W> g, UfNode* lab, const uint32_t* wide,
+                                                              const Ctl* ctl) {
   const uint64_t cnt = (uint64_t)ctl->split_wide * kSplitWide;
   GRID_STRIDE(q, cnt) {
     const uint32_t u = wide[q / kSplitWide];
     const uint32_t e = kSplitSample + (uint32_t)(q % kSplitWide);
     if (e >= g.len[u]) continue;
-    const uint32_t j = g.cols[g.start[u] + e];
-    if (j != u && C[j] == C[u]) uf_union(lab, u, j);
+    uf_link(lab, u, g.cols[g.start[u] + e]);
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_split_compress(uint32_t* lab, const uint32_t* list, const Ctl* ctl) {
+__global__ __launch_bounds__(kBlock) void k_split_compress(UfNode* lab, const uint32_t* list, const Ctl* ctl) {
   const uint32_t cnt = ctl->split_count;
   GRID_STRIDE(it, cnt) {
     const uint32_t i = list[it];
-    lab[i] = uf_find(lab, i);
+    const UfNode w = ld_near(&lab[i]);
+    lab[i] = (w & kUfComm) | uf_find(lab, i, w);
   }
 }
 
@@ -325,7 +347,7 @@ __global__ __launch_bounds__(kBlock) void k_split_main(const uint32_t* len, cons
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_split_rest(uint32_t n, const uint32_t* C, const uint32_t* lab,
+__global__ __launch_bounds__(kBlock) void k_split_rest(uint32_t n, const uint32_t* C, const UfNode* lab,
                                                        const uint32_t* list, const unsigned long long* main_key,
                                                        uint32_t* rest, Ctl* ctl) {
   __shared__ unsigned int scnt[1], sbase[1];
@@ -346,7 +368,7 @@ __global__ __launch_bounds__(kBlock) void k_split_rest(uint32_t n, const uint32_
         const unsigned long long key = main_key[c];
         uint32_t m = key ? 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull) : c;
         if (m >= n || C[m] != c) m = c;  // any choice is correct; this one is always in range
-        if (lab[u] != lab[m]) kk[q] = 0;  // both are roots after compression
+        if (lab[u] != lab[m]) kk[q] = 0;  // both are roots after compression (same community half)
         val[q] = u;
       }
     }
@@ -359,7 +381,7 @@ __global__ __launch_bounds__(kBlock) void k_split_rest(uint32_t n, const uint32_
 
 // G lanes per vertex (G <= 64 inside a wavefront, G = kBlock for a block)
 template <int G, typename W>
-__global__ __launch_bounds__(kBlock) void k_split_union(Rows<W> g, const uint32_t* C, uint32_t* lab,
+__global__ __launch_bounds__(kBlock) void k_split_union(Rows<W> g, const uint32_t* C, UfNode* lab,
                                                         const uint32_t* list, const unsigned int* count) {
   const uint32_t grp = threadIdx.x / G, lane = threadIdx.x % G;
   constexpr uint32_t GPB = kBlock / G;
@@ -368,21 +390,23 @@ __global__ __launch_bounds__(kBlock) void k_split_union(Rows<W> g, const uint32_
     const uint32_t it = base + grp;
     if (it >= cnt) continue;
     const uint32_t u = list[it];
-    const uint32_t c = C[u];
+    const UfNode comm = (UfNode)C[u] << 32;
     const int64_t s0 = g.start[u];
     const uint32_t L = g.len[u];
     for (uint32_t e = lane; e < L; e += G) {
       const uint32_t j = g.cols[s0 + e];
-      if (j != u && C[j] == c) uf_union(lab, u, j);
+      if (j == u) continue;
+      const UfNode wj = ld_near(&lab[j]);
+      if ((wj & kUfComm) == comm) uf_union(lab, u, ld_near(&lab[u]), j, wj);
     }
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_split_finish(uint32_t* C, uint32_t* lab, const uint32_t* list, Ctl* ctl) {
+__global__ __launch_bounds__(kBlock) void k_split_finish(uint32_t* C, UfNode* lab, const uint32_t* list, Ctl* ctl) {
   const uint32_t cnt = ctl->split_count;
   GRID_STRIDE(it, cnt) {
     const uint32_t i = list[it];
-    C[i] = uf_find(lab, i);
+    C[i] = uf_find(lab, i, ld_near(&lab[i]));
   }
 }
 
@@ -395,7 +419,7 @@ __global__ void k_split_reset(Ctl* ctl) {
 }
 
 void launch_split_init(hipStream_t s, uint32_t n, const uint32_t* C, const uint8_t* dS, const uint8_t* dR,
-                       uint32_t* lab, uint32_t* list, uint32_t* wide, unsigned long long* main_key, Ctl* ctl,
+                       UfNode* lab, uint32_t* list, uint32_t* wide, unsigned long long* main_key, Ctl* ctl,
                        const uint32_t* len, unsigned long long* parts) {
   hipLaunchKernelGGL(k_split_reset, dim3(1), dim3(1), 0, s, ctl);
   if (n)
@@ -404,13 +428,13 @@ void launch_split_init(hipStream_t s, uint32_t n, const uint32_t* C, const uint8
 }
 
 template <typename W>
-void launch_split_sample(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* lab, const uint32_t* list,
+void launch_split_sample(hipStream_t s, Rows<W> g, const uint32_t* C, UfNode* lab, const uint32_t* list,
                          const uint32_t* wide, unsigned long long* main_key, uint32_t* rest, Ctl* ctl,
                          uint32_t n_upper) {
-  hipLaunchKernelGGL((k_split_sample<W>), dim3(grid_n((uint64_t)n_upper * kSplitSample)), dim3(kBlock), 0, s, g, C,
-                     lab, list, ctl);
+  hipLaunchKernelGGL((k_split_sample<W>), dim3(grid_n((uint64_t)n_upper * kSplitSample)), dim3(kBlock), 0, s, g, lab,
+                     list, ctl);
   hipLaunchKernelGGL((k_split_sample_wide<W>), dim3(grid_n((uint64_t)n_upper * kSplitWide, kBlock, 4096)),
-                     dim3(kBlock), 0, s, g, C, lab, wide, ctl);
+                     dim3(kBlock), 0, s, g, lab, wide, ctl);
   hipLaunchKernelGGL(k_split_compress, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, lab, list, ctl);
   uint32_t hi = 0xFFFFFFFFu;
   for (const uint32_t lo : kSplitMainBands) {
@@ -424,7 +448,7 @@ void launch_split_sample(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* 
 // Full rows of the vertices outside their community's main tree, by degree
 // bin (bins as in the local-moving kernels).
 template <typename W>
-void launch_split_union(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* lab, const uint32_t* bin_lists,
+void launch_split_union(hipStream_t s, Rows<W> g, const uint32_t* C, UfNode* lab, const uint32_t* bin_lists,
                         size_t stride, const unsigned int* bin_counts, const uint64_t* bin_upper) {
   for (int b = 0; b < kBins; ++b) {
     if (!bin_upper[b]) continue;
@@ -445,18 +469,18 @@ void launch_split_union(hipStream_t s, Rows<W> g, const uint32_t* C, uint32_t* l
   }
 }
 
-void launch_split_finish(hipStream_t s, uint32_t* C, uint32_t* lab, const uint32_t* list, Ctl* ctl, uint32_t n_upper) {
+void launch_split_finish(hipStream_t s, uint32_t* C, UfNode* lab, const uint32_t* list, Ctl* ctl, uint32_t n_upper) {
   hipLaunchKernelGGL(k_split_finish, dim3(grid_n(n_upper)), dim3(kBlock), 0, s, C, lab, list, ctl);
 }
 
-template void launch_split_sample<uint32_t>(hipStream_t, Rows<uint32_t>, const uint32_t*, uint32_t*,
+template void launch_split_sample<uint32_t>(hipStream_t, Rows<uint32_t>, const uint32_t*, UfNode*,
                                             const uint32_t*, const uint32_t*, unsigned long long*, uint32_t*, Ctl*,
                                             uint32_t);
-template void launch_split_sample<int64_t>(hipStream_t, Rows<int64_t>, const uint32_t*, uint32_t*, const uint32_t*,
+template void launch_split_sample<int64_t>(hipStream_t, Rows<int64_t>, const uint32_t*, UfNode*, const uint32_t*,
                                            const uint32_t*, unsigned long long*, uint32_t*, Ctl*, uint32_t);
-template void launch_split_union<uint32_t>(hipStream_t, Rows<uint32_t>, const uint32_t*, uint32_t*, const uint32_t*,
+template void launch_split_union<uint32_t>(hipStream_t, Rows<uint32_t>, const uint32_t*, UfNode*, const uint32_t*,
                                            size_t, const unsigned int*, const uint64_t*);
-template void launch_split_union<int64_t>(hipStream_t, Rows<int64_t>, const uint32_t*, uint32_t*, const uint32_t*,
+template void launch_split_union<int64_t>(hipStream_t, Rows<int64_t>, const uint32_t*, UfNode*, const uint32_t*,
                                           size_t, const unsigned int*, const uint64_t*);
 
 // ---------------------------------------------------------------------------

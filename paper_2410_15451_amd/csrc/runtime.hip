@@ -409,7 +409,7 @@ leiden_status ensure_workspace(leiden_graph* G, hipStream_t s, uint32_t classes)
   CHK(G->split_rest.reserve(n * u32));
   CHK(G->split_wide.reserve(n * u32));
   CHK(G->split_key.reserve(n * u64));
-  CHK(G->lab.reserve(n * u32));
+  CHK(G->lab.reserve(n * u64));  // union-find words of the split
   CHK(G->flag.reserve(n * u32));
   CHK(G->newid.reserve((n + 1) * u64));
   CHK(G->scan_tmp.reserve(scan_tmp_bytes(std::max<uint64_t>(n, 2 * nnz)) + 64));
@@ -757,7 +757,7 @@ template <typename W>
 leiden_status split(leiden_graph* G, hipStream_t s, Rows<W> g, uint32_t nl, LevelState& L,
                     const uint64_t bins[kBins]) {
   Ctl* ctl = dctl(G);
-  uint32_t* lab = G->lab.as<uint32_t>();
+  unsigned long long* lab = G->lab.as<unsigned long long>();
   uint32_t* list = G->split_list.as<uint32_t>();
   uint32_t* rest = G->split_rest.as<uint32_t>();
   unsigned long long* key = G->split_key.as<unsigned long long>();
