@@ -206,7 +206,13 @@ void fill_u64(hipStream_t s, uint64_t* p, uint64_t v, size_t n);
 // bins_out / maxdeg_out are added to; parts: 64 x 16 u64 of scratch
 void launch_degree_hist(hipStream_t s, const uint32_t* len, uint32_t n, const BinCfg& cfg, unsigned long long* bins_out,
                         unsigned int* maxdeg_out, unsigned long long* parts);
-void launch_row_sums_u32(hipStream_t s, Rows<uint32_t> g, uint32_t n, int64_t* K);
+// Rows of more than kWaveRowMax entries are summed in chunks of kRowChunk
+// entries by whole blocks (kLongGrid of them); items holds the chunk list:
+// long_items_bytes(nnz) bytes for a graph of nnz entries.
+constexpr uint32_t kWaveRowMax = 1024, kRowChunk = 4096;
+constexpr int kLongGrid = 1024;
+inline size_t long_items_bytes(uint64_t nnz) { return (size_t)(nnz / kRowChunk + nnz / kWaveRowMax + 2) * 8; }
+void launch_row_sums_u32(hipStream_t s, Rows<uint32_t> g, uint32_t n, int64_t* K, unsigned long long* items);
 void launch_count_members(hipStream_t s, const uint32_t* C, uint32_t n, uint32_t* size);
 void launch_sigma_from(hipStream_t s, const uint32_t* C, const int64_t* K, uint32_t n, int64_t* S);
 
@@ -283,8 +289,9 @@ struct ModParts {
   unsigned long long sigma;
   unsigned long long T_hi, T_lo;
 };
+// partials: 4 * nblocks words; items: the long-row chunk list (as for the row sums)
 void modularity_parts(hipStream_t s, Rows<uint32_t> g, uint32_t n, const uint32_t* C, const int64_t* K, int64_t* Sig,
-                      unsigned long long* partials, int nblocks, ModParts* out_dev);
+                      unsigned long long* partials, int nblocks, ModParts* out_dev, unsigned long long* items);
 
 struct TrackBufs {
   uint32_t* head;             // in: minimum vertex of every old label (kNone: not a label); out: those of the new labels

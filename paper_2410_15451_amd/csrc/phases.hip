@@ -68,14 +68,34 @@ void launch_degree_hist(hipStream_t s, const uint32_t* len, uint32_t n, const Bi
   hipLaunchKernelGGL(k_hist_fold, dim3(1), dim3(kWave), 0, s, parts, bins_out, maxdeg_out);
 }
 
-// Weighted degree of every row, one wavefront per row.
-__global__ __launch_bounds__(kBlock) void k_row_sums(Rows<uint32_t> g, uint32_t n, int64_t* K) {
+// Row sweeps (weighted degrees, Eq. 1's intra-community sums) take one
+// wavefront per row; a row of more than kWaveRowMax entries would hold its
+// wavefront for a long serial chain of gathers (a hub of 10^5..10^6 entries
+// for milliseconds), so the wavefront that meets one lists its chunks of
+// kRowChunk entries instead (items[0] counts them, items[1 + q] = row << 32 |
+// chunk) and a second launch sums every chunk with a whole block.
+__device__ inline void list_row_chunks(unsigned long long* items, uint32_t i, uint32_t L, uint32_t lane) {
+  const uint32_t nc = (L + kRowChunk - 1) / kRowChunk;
+  unsigned int base = 0;
+  if (lane == 0) base = (unsigned int)atomicAdd(&items[0], (unsigned long long)nc);
+  base = __shfl(base, 0);
+  for (uint32_t k = lane; k < nc; k += kWave) items[1 + (uint64_t)base + k] = ((unsigned long long)i << 32) | k;
+}
+
+// Weighted degree of every row.
+__global__ __launch_bounds__(kBlock) void k_row_sums(Rows<uint32_t> g, uint32_t n, int64_t* K,
+                                                     unsigned long long* items) {
   const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
   const uint32_t lane = threadIdx.x % kWave;
   const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
   for (uint64_t i = wave; i < n; i += nwaves) {
     const int64_t s0 = g.start[i];
     const uint32_t L = g.len[i];
+    if (L > kWaveRowMax) {  // wavefront-uniform
+      if (lane == 0) K[i] = 0;
+      list_row_chunks(items, (uint32_t)i, L, lane);
+      continue;
+    }
     unsigned long long k = 0;
     for (uint32_t e = lane; e < L; e += kWave) k += g.w[s0 + e];
     k = group_sum<kWave>(k);
@@ -83,8 +103,28 @@ __global__ __launch_bounds__(kBlock) void k_row_sums(Rows<uint32_t> g, uint32_t 
   }
 }
 
-void launch_row_sums_u32(hipStream_t s, Rows<uint32_t> g, uint32_t n, int64_t* K) {
-  if (n) hipLaunchKernelGGL(k_row_sums, dim3(grid_n(n, kBlock / kWave, 16384)), dim3(kBlock), 0, s, g, n, K);
+// the listed chunks, one block each
+__global__ __launch_bounds__(kBlock) void k_row_sums_long(Rows<uint32_t> g, int64_t* K,
+                                                          const unsigned long long* items) {
+  __shared__ unsigned long long red[kBlock / kWave];
+  const unsigned long long cnt = items[0];
+  for (unsigned long long q = blockIdx.x; q < cnt; q += gridDim.x) {
+    const unsigned long long it = items[1 + q];
+    const uint32_t i = (uint32_t)(it >> 32), e0 = (uint32_t)it * kRowChunk;
+    const uint32_t e1 = min(g.len[i], e0 + kRowChunk);
+    const int64_t s0 = g.start[i];
+    unsigned long long k = 0;
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += kBlock) k += g.w[s0 + e];
+    k = block_sum(k, red);
+    if (threadIdx.x == 0) atomicAdd((unsigned long long*)&K[i], k);
+  }
+}
+
+void launch_row_sums_u32(hipStream_t s, Rows<uint32_t> g, uint32_t n, int64_t* K, unsigned long long* items) {
+  if (n == 0) return;
+  fill_u64(s, (uint64_t*)items, 0, 1);
+  hipLaunchKernelGGL(k_row_sums, dim3(grid_n(n, kBlock / kWave, 16384)), dim3(kBlock), 0, s, g, n, K, items);
+  hipLaunchKernelGGL(k_row_sums_long, dim3(kLongGrid), dim3(kBlock), 0, s, g, K, items);
 }
 
 void launch_count_members(hipStream_t s, const uint32_t* C, uint32_t n, uint32_t* size) {
@@ -1375,9 +1415,9 @@ void launch_static_relabel(hipStream_t s, const uint32_t* C, uint32_t n, uint32_
 // T = sum Sigma_c^2 as a 128-bit integer.  The host forms
 // Q = sigma / 2m - T / (2m)^2.
 // ---------------------------------------------------------------------------
-// sigma partial sums, one wavefront per row
+// sigma partial sums, one wavefront per row (long rows: listed chunks)
 __global__ __launch_bounds__(kBlock) void k_mod_sigma(Rows<uint32_t> g, uint32_t n, const uint32_t* C,
-                                                      unsigned long long* partials) {
+                                                      unsigned long long* partials, unsigned long long* items) {
   __shared__ unsigned long long red[kBlock / kWave];
   const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
   const uint32_t lane = threadIdx.x % kWave;
@@ -1387,7 +1427,31 @@ __global__ __launch_bounds__(kBlock) void k_mod_sigma(Rows<uint32_t> g, uint32_t
     const uint32_t c = C[i];
     const int64_t s0 = g.start[i];
     const uint32_t L = g.len[i];
+    if (L > kWaveRowMax) {  // wavefront-uniform
+      list_row_chunks(items, (uint32_t)i, L, lane);
+      continue;
+    }
     for (uint32_t e = lane; e < L; e += kWave)
+      if (C[g.cols[s0 + e]] == c) sig += g.w[s0 + e];
+  }
+  sig = block_sum(sig, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = sig;
+}
+
+// the listed chunks, one block each; one partial sum per block
+__global__ __launch_bounds__(kBlock) void k_mod_sigma_long(Rows<uint32_t> g, const uint32_t* C,
+                                                           const unsigned long long* items,
+                                                           unsigned long long* partials) {
+  __shared__ unsigned long long red[kBlock / kWave];
+  const unsigned long long cnt = items[0];
+  unsigned long long sig = 0;
+  for (unsigned long long q = blockIdx.x; q < cnt; q += gridDim.x) {
+    const unsigned long long it = items[1 + q];
+    const uint32_t i = (uint32_t)(it >> 32), e0 = (uint32_t)it * kRowChunk;
+    const uint32_t e1 = min(g.len[i], e0 + kRowChunk);
+    const int64_t s0 = g.start[i];
+    const uint32_t c = C[i];
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += kBlock)
       if (C[g.cols[s0 + e]] == c) sig += g.w[s0 + e];
   }
   sig = block_sum(sig, red);
@@ -1418,27 +1482,46 @@ __global__ __launch_bounds__(kBlock) void k_mod_square(uint32_t n, const int64_t
   }
 }
 
-__global__ void k_mod_final(const unsigned long long* sig_part, const unsigned long long* sq_part, int nblocks,
-                            ModParts* out) {
-  if (threadIdx.x != 0) return;
+// Totals of the per-block parts: sigma of both sigma launches (nblocks each),
+// and the 128-bit sum of squares with its carries.
+__global__ __launch_bounds__(kBlock) void k_mod_final(const unsigned long long* sig_part,
+                                                      const unsigned long long* sq_part,
+                                                      const unsigned long long* long_part, int nblocks,
+                                                      ModParts* out) {
+  __shared__ unsigned long long rs[kBlock], rh[kBlock], rl[kBlock];
   unsigned long long sig = 0, H = 0, L = 0;
-  for (int b = 0; b < nblocks; ++b) {
-    sig += sig_part[b];
+  for (int b = threadIdx.x; b < nblocks; b += kBlock) {
+    sig += sig_part[b] + long_part[b];
     L += sq_part[2 * b + 1];
     H += sq_part[2 * b] + (L < sq_part[2 * b + 1] ? 1ull : 0ull);
   }
-  out->sigma = sig;
-  out->T_hi = H;
-  out->T_lo = L;
+  rs[threadIdx.x] = sig;
+  rh[threadIdx.x] = H;
+  rl[threadIdx.x] = L;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    sig = H = L = 0;
+    for (int t = 0; t < kBlock; ++t) {
+      sig += rs[t];
+      L += rl[t];
+      H += rh[t] + (L < rl[t] ? 1ull : 0ull);
+    }
+    out->sigma = sig;
+    out->T_hi = H;
+    out->T_lo = L;
+  }
 }
 
 void modularity_parts(hipStream_t s, Rows<uint32_t> g, uint32_t n, const uint32_t* C, const int64_t* K, int64_t* Sig,
-                      unsigned long long* partials, int nblocks, ModParts* out_dev) {
+                      unsigned long long* partials, int nblocks, ModParts* out_dev, unsigned long long* items) {
   fill_i64(s, Sig, 0, n);
   scatter_add_i64(s, C, K, n, Sig, n);
-  hipLaunchKernelGGL(k_mod_sigma, dim3(nblocks), dim3(kBlock), 0, s, g, n, C, partials);
+  fill_u64(s, (uint64_t*)items, 0, 1);
+  hipLaunchKernelGGL(k_mod_sigma, dim3(nblocks), dim3(kBlock), 0, s, g, n, C, partials, items);
+  hipLaunchKernelGGL(k_mod_sigma_long, dim3(nblocks), dim3(kBlock), 0, s, g, C, items, partials + 3 * nblocks);
   hipLaunchKernelGGL(k_mod_square, dim3(nblocks), dim3(kBlock), 0, s, n, Sig, partials + nblocks);
-  hipLaunchKernelGGL(k_mod_final, dim3(1), dim3(1), 0, s, partials, partials + nblocks, nblocks, out_dev);
+  hipLaunchKernelGGL(k_mod_final, dim3(1), dim3(kBlock), 0, s, partials, partials + nblocks, partials + 3 * nblocks,
+                     nblocks, out_dev);
 }
 
 // ---------------------------------------------------------------------------

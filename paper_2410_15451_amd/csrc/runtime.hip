@@ -209,6 +209,7 @@ struct leiden_graph {
   // workspace
   Buf C, K, Kb, Kt, S, S2, size, size2, dS, dS2, dR, dR2, CB, rep, Ctop, pend, unproc;
   Buf cls_lists, bin_lists, iter_list, next_list, movers, split_list, split_rest, split_key, split_wide, lab;
+  Buf long_items;  // chunk list of the long rows of the input graph
   Buf flag, newid, scan_tmp, ctl, small;
   Buf lvA_start, lvA_len, lvA_cols, lvA_w, lvB_start, lvB_len, lvB_cols, lvB_w;
   Buf agg_count, agg_off, agg_fill, agg_fill2, agg_eoff, agg_members, agg_deg, agg_cap, agg_lists, agg_bigcap, agg_tbl, agg_keys, agg_vals,
@@ -369,6 +370,18 @@ void bind_graph(leiden_graph* G) {
 
 Rows<uint32_t> rows0(leiden_graph* G) { return Rows<uint32_t>{G->g.start, G->g.len, G->g.cols, G->g.w}; }
 
+// The chunk list of the input graph's long rows, sized for its entries.
+leiden_status reserve_long_items(leiden_graph* G) {
+  return G->long_items.reserve(long_items_bytes(std::max<uint64_t>(G->nnz, 1)));
+}
+
+// K[i] = weighted degree of row i of the input graph
+leiden_status row_sums(leiden_graph* G, hipStream_t s, int64_t* K) {
+  CHK(reserve_long_items(G));
+  launch_row_sums_u32(s, rows0(G), G->n, K, G->long_items.as<unsigned long long>());
+  return LEIDEN_OK;
+}
+
 // Allocate every n- and nnz-sized array a run needs.  Arrays that must start
 // zeroed are cleared on the call's stream s: a hipMemset on the null stream
 // is asynchronous to the host and not ordered with the non-blocking streams
@@ -463,7 +476,7 @@ leiden_status ensure_workspace(leiden_graph* G, hipStream_t s, uint32_t classes)
   CHK(G->dE.reserve(n));
   CHK(G->dC.reserve(n));
   CHK(G->sig.reserve(n * u64));
-  CHK(G->partials.reserve(3 * 1024 * u64));
+  CHK(G->partials.reserve(4 * 1024 * u64));
   CHK(G->modparts.reserve(sizeof(ModParts)));
   CHK(G->rb_reserve.reserve(n * u32));
   CHK(G->scatter_ws.reserve(scatter_ws_bytes(n, n)));
@@ -977,7 +990,9 @@ leiden_status check_opts(const leiden_opts& o) {
 leiden_status modularity_of(leiden_graph* G, hipStream_t s, const uint32_t* C, const int64_t* K, double* q) {
   const int nb = 1024;
   ModParts* mp = G->modparts.as<ModParts>();
-  modularity_parts(s, rows0(G), G->n, C, K, G->sig.as<int64_t>(), G->partials.as<unsigned long long>(), nb, mp);
+  CHK(reserve_long_items(G));
+  modularity_parts(s, rows0(G), G->n, C, K, G->sig.as<int64_t>(), G->partials.as<unsigned long long>(), nb, mp,
+                   G->long_items.as<unsigned long long>());
   unsigned long long* m2d = G->small.as<unsigned long long>() + 128;
   sum_i64(s, K, G->n, m2d);
   char* st = (char*)pinned_stage(sizeof(ModParts) + 8);
@@ -1322,7 +1337,7 @@ leiden_status leiden_autotune(leiden_graph* G, const leiden_opts* opts, leiden_t
   // singleton start on the input graph
   zero_ctl(G, s);
   LevelState L = level_state(G);
-  launch_row_sums_u32(s, rows0(G), n, L.K);
+  CHK(row_sums(G, s, L.K));
   HIPCHK(hipMemcpyAsync(L.S, L.K, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s));
   iota_u32(s, L.C, n);
   fill_u32(s, L.size, 1, n);
@@ -1608,7 +1623,7 @@ leiden_status leiden_static(leiden_graph* G, const leiden_opts* opts, uint32_t* 
   zero_ctl(G, s);
   G->sweeps = 2 * (uint64_t)n;  // set-up of C', K, Sigma and the flags; dense output labels
   LevelState L = level_state(G);
-  launch_row_sums_u32(s, rows0(G), n, L.K);
+  CHK(row_sums(G, s, L.K));
   HIPCHK(hipMemcpyAsync(L.S, L.K, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s));
   iota_u32(s, L.C, n);
   fill_u8(s, L.dR, 1, n);
@@ -1633,7 +1648,7 @@ leiden_status leiden_static(leiden_graph* G, const leiden_opts* opts, uint32_t* 
   CHK(G->st_head.reserve((size_t)std::max<uint32_t>(n, 1) * 4));
   static_heads(s, n, G->flag.as<uint32_t>(), out, G->st_head.as<uint32_t>());
   G->heads_valid = true;
-  launch_row_sums_u32(s, rows0(G), n, G->st_K.as<int64_t>());
+  CHK(row_sums(G, s, G->st_K.as<int64_t>()));
   launch_sigma_from(s, out, G->st_K.as<int64_t>(), n, G->st_S.as<int64_t>());
   fill_i64(s, G->st_dS.as<int64_t>(), 0, n);
   G->has_state = true;
@@ -1846,7 +1861,7 @@ leiden_status leiden_update(leiden_graph* G, const uint32_t* del, uint64_t n_del
   L.K = G->st_K.as<int64_t>();
   L.S = G->st_S.as<int64_t>();
   if (restart) {
-    launch_row_sums_u32(s, rows0(G), n, L.K);  // K^t directly
+    CHK(row_sums(G, s, L.K));  // K^t directly
     launch_sigma_from(s, Cprev, L.K, n, L.S);   // Sigma^t by C^{t-1}
     fill_i64(s, G->st_dS.as<int64_t>(), 0, n);
     // DeltaSigma^t from zero
@@ -2012,7 +2027,7 @@ leiden_status leiden_modularity(leiden_graph* G, const uint32_t* membership, int
   CHK(read_dev(s, &f, fl));
   if (f & 1) return fail(LEIDEN_EINVAL, "membership has a label >= n");
   int64_t* K = G->K.as<int64_t>();
-  launch_row_sums_u32(s, rows0(G), n, K);
+  CHK(row_sums(G, s, K));
   if (ForestState* FS = G->forest) {
     // labels inside each graph; the per-graph values go to leiden_forest_results
     CHK(copy_in(s, C, membership, sizeof(uint32_t) * n, on_device));
@@ -2108,7 +2123,7 @@ leiden_status leiden_state_import(leiden_graph* G, const uint32_t* C, const int6
   // check on the host: labels < n, K = row sums, Sigma = sums of K by label
   std::vector<int64_t> Kref(n);
   int64_t* Kd = G->K.as<int64_t>();
-  launch_row_sums_u32(s, rows0(G), n, Kd);
+  CHK(row_sums(G, s, Kd));
   HIPCHK(hipMemcpyAsync(Kref.data(), Kd, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   std::vector<int64_t> Sref(n, 0);

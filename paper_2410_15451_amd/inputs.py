@@ -464,15 +464,19 @@ def chung_lu_torch(n: int, seed: int, device, avg_degree: float = 40.0, max_degr
     ``chung_lu`` with the same seed): round(avg_degree * n / 2) endpoint
     pairs drawn in chunks, self-loops and repeated pairs dropped, weights
     uniform in 1..wmax per undirected edge, a seeded vertex permutation.
+    The endpoint distribution and the permutation are made on the host (a
+    floating-point prefix sum on the device need not repeat bit for bit from
+    one process to the next), so the same seed gives the same graph in every
+    process.
     Returns (offs int64[n+1], cols int32[nnz], w int32[nnz]) tensors."""
     import torch
 
     g = torch.Generator(device=device)
     g.manual_seed(int(seed))
-    wt = torch.from_numpy(chung_lu_weights(n, avg_degree, max_degree, gamma)).to(device)
-    cdf = torch.cumsum(wt, 0)
-    cdf /= cdf[-1].clone()
-    del wt
+    cdf_h = np.cumsum(chung_lu_weights(n, avg_degree, max_degree, gamma))
+    cdf_h /= cdf_h[-1]
+    cdf = torch.from_numpy(cdf_h).to(device)
+    del cdf_h
     m = int(round(avg_degree * n / 2))
     keys = []
     for a in range(0, m, chunk):
@@ -490,7 +494,7 @@ def chung_lu_torch(n: int, seed: int, device, avg_degree: float = 40.0, max_degr
     key = torch.unique(torch.cat(keys))
     del keys
     ww = torch.randint(1, wmax + 1, (key.numel(),), generator=g, device=device, dtype=torch.int32)
-    perm = torch.randperm(n, generator=g, device=device)
+    perm = torch.from_numpy(np.random.default_rng(int(seed)).permutation(n)).to(device)
     a, b = perm[key // n], perm[key % n]
     del key, perm
     # both directions, sorted by (row, column)
