@@ -637,6 +637,26 @@ def test_knn_inputs_are_valid_graphs():
     assert np.diff(g.offs).min() >= 1
 
 
+def test_chung_lu_device_generator_repeatable_and_valid():
+    """The torch Chung-Lu generator (the large single graph) gives the same
+    graph on every call with one seed, and a simple symmetric graph with
+    sorted rows and weights in 1..16 (run here with torch on the CPU)."""
+    import torch
+    a = inputs.chung_lu_torch(50_000, 11, torch.device("cpu"))
+    b = inputs.chung_lu_torch(50_000, 11, torch.device("cpu"))
+    assert all(torch.equal(x, y) for x, y in zip(a, b))
+    offs, cols, w = (t.numpy() for t in a)
+    n = offs.size - 1
+    rows = np.repeat(np.arange(n), np.diff(offs))
+    assert cols.size > 10 * n and not np.any(rows == cols)
+    assert int(w.min()) >= 1 and int(w.max()) <= 16
+    key = rows.astype(np.int64) * n + cols
+    assert np.all(np.diff(key) > 0)  # sorted rows, no repeated pair
+    rev = cols.astype(np.int64) * n + rows
+    order = np.argsort(rev)
+    assert np.array_equal(rev[order], key) and np.array_equal(w[order], w)
+
+
 def test_split_all_splits_untouched_disconnected_communities(orc):
     """Section 4.3 compares selective splitting with splitting every community
     not marked for refinement.  A community that is already disconnected and
